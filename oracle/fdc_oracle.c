@@ -1,0 +1,518 @@
+/*
+ * CPU oracle for track-repeating proton dose calculation.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+ * benchmark's CPU-baseline leg may load this file's library.  It shares no
+ * code with the HIP path (no headers, tables or helpers); both read the same
+ * seeded inputs.
+ *
+ * Plain and slow on purpose: FP64 geometry, absolute positions, one history at
+ * a time, integer fixed-point tallies (1 LSB = 2^-24 MeV).  It follows the two
+ * tasks of the GPU kernel in Section 2.3 of the paper:
+ *   task 1 - find the database history, select the trajectory and the start step;
+ *   task 2 - re-trace the stored water steps through the voxel phantom, scaling
+ *            each step's length and scattering angle by the local material
+ *            (Section 2.2), and tally the deposited energy (Section 2.3).
+ * Where the paper is silent the readings below fix the behaviour:
+ *   - a step keeps its energy loss; its water-equivalent length (WEL) is
+ *     consumed voxel by voxel, geometric length = WEL / RSP;
+ *   - energy is deposited uniformly in WEL along a step, split with a
+ *     telescoping round-to-nearest-even so the pieces sum exactly;
+ *   - the deflection is applied at the end of a step (condensed history,
+ *     Section 2.1) with angle theta * sqrt(sum(w_v * G_v) / WEL), G = RScP/RSP;
+ *   - the direction lives in the beam frame and is rotated with the textbook
+ *     polar/azimuth formula, then mapped by the field matrix M = [e1 e2 d];
+ *   - histories of one spot come in chunks of R consecutive indices sharing one
+ *     database track (the paper feeds one history to a whole thread group,
+ *     Section 4); every random number is Philox4x32-10 keyed by the run seed
+ *     with a counter made of the history identity;
+ *   - voxels with HU below the vacuum threshold are free flight;
+ *   - leaving the phantom box ends the history; its undeposited energy is
+ *     counted as escaped.
+ *   - per-history per-voxel-visit deposits are squared for the sum-of-squares
+ *     tally used by the history-by-history uncertainty, Eq. (2).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define FP_SCALE 16777216.0 /* 2^24 LSB per MeV */
+#define TAG_TRACK 2u
+#define TAG_SRC 3u
+#define FLAG_VARIANCE 1u
+#define FLAG_ROTATE 2u
+
+/* ---------------------------------------------------------------------- */
+/* Philox4x32-10, Salmon, Moraes, Dror and Shaw, "Parallel random numbers:
+ * as easy as 1, 2, 3", SC'11.  Ten rounds of the 4x32 S-box with key bump. */
+void oracle_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
+{
+    uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int round = 0; round < 10; ++round) {
+        if (round > 0) {
+            k0 += 0x9E3779B9u; /* golden ratio */
+            k1 += 0xBB67AE85u; /* sqrt(3) - 1 */
+        }
+        uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c0;
+        uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
+        uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        uint32_t n0 = hi1 ^ c1 ^ k0;
+        uint32_t n1 = lo1;
+        uint32_t n2 = hi0 ^ c3 ^ k1;
+        uint32_t n3 = lo0;
+        c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/* uniform in the open interval (0,1): 24 high bits plus half an LSB */
+double oracle_uniform(uint32_t x)
+{
+    return (double)(x >> 8) * (1.0 / 16777216.0) + (1.0 / 33554432.0);
+}
+
+/* ---------------------------------------------------------------------- */
+/* HU -> material, piecewise linear over the table points, clamped at the ends */
+typedef struct {
+    const double *hu, *rho, *rsp, *rscp;
+    int n;
+    double vacuum_below_hu;
+} hu_table;
+
+static double interp(const hu_table *t, const double *val, double h)
+{
+    if (h <= t->hu[0]) return val[0];
+    if (h >= t->hu[t->n - 1]) return val[t->n - 1];
+    int j = 0;
+    while (!(h < t->hu[j + 1])) ++j;
+    return val[j] + (val[j + 1] - val[j]) * (h - t->hu[j]) / (t->hu[j + 1] - t->hu[j]);
+}
+
+/* HU value after clamping to the CT range [-1024, 3071] */
+static double clamp_hu(int16_t v)
+{
+    int h = v;
+    if (h < -1024) h = -1024;
+    if (h > 3071) h = 3071;
+    return (double)h;
+}
+
+/* material of a voxel: is it vacuum, its RSP and G = RScP/RSP */
+static int material(const hu_table *t, int16_t v, double *rsp, double *g)
+{
+    double h = clamp_hu(v);
+    if (h < t->vacuum_below_hu) { *rsp = 0.0; *g = 0.0; return 1; }
+    double s = interp(t, t->rsp, h);
+    double c = interp(t, t->rscp, h);
+    *rsp = s;
+    *g = s > 0.0 ? c / s : 0.0;
+    return s <= 0.0;
+}
+
+void oracle_material(const double *hu_pts, const double *rho, const double *rsp, const double *rscp,
+                     int n_pts, double vacuum_below_hu, const int16_t *hu_in, int n,
+                     double *rho_out, double *rsp_out, double *g_out, uint8_t *vac_out)
+{
+    hu_table t = {hu_pts, rho, rsp, rscp, n_pts, vacuum_below_hu};
+    for (int i = 0; i < n; ++i) {
+        double s, g;
+        vac_out[i] = (uint8_t)material(&t, hu_in[i], &s, &g);
+        rsp_out[i] = s;
+        g_out[i] = g;
+        rho_out[i] = interp(&t, t.rho, clamp_hu(hu_in[i]));
+    }
+}
+
+/* ---------------------------------------------------------------------- */
+typedef struct {
+    /* track database */
+    const float *steps; /* 4 floats per step: dx (WEL cm), dE (MeV), theta, phi */
+    const uint64_t *track_off;
+    uint32_t n_tracks;
+    const float *bin_E;
+    const uint32_t *bin_first;
+    uint32_t n_bins;
+    /* phantom */
+    const int16_t *hu;
+    int n[3];
+    double vox[3], org[3];
+    hu_table tab;
+    /* spots */
+    const float *spot_pos, *spot_dir, *spot_E, *spot_sigma;
+    /* run */
+    uint32_t plan;
+    uint64_t seed;
+    uint32_t R;
+    uint32_t flags;
+} oracle_problem;
+
+typedef struct {
+    int64_t *E;
+    uint64_t *E2;
+    int64_t incident, escaped;
+    uint64_t steps, visits, vacuum_visits, flushes;
+} oracle_tally;
+
+static int64_t fp_energy(double e) { return (int64_t)nearbyint(e * FP_SCALE); }
+
+/* right-handed lateral axes of a beam direction: d = +z gives (x, y) */
+static void field_frame(const double d[3], double e1[3], double e2[3])
+{
+    double a[3] = {0.0, 0.0, 1.0};
+    if (fabs(d[2]) >= 0.9) { a[0] = 1.0; a[2] = 0.0; }
+    e2[0] = d[1] * a[2] - d[2] * a[1];
+    e2[1] = d[2] * a[0] - d[0] * a[2];
+    e2[2] = d[0] * a[1] - d[1] * a[0];
+    double l = sqrt(e2[0] * e2[0] + e2[1] * e2[1] + e2[2] * e2[2]);
+    e2[0] /= l; e2[1] /= l; e2[2] /= l;
+    e1[0] = e2[1] * d[2] - e2[2] * d[1];
+    e1[1] = e2[2] * d[0] - e2[0] * d[2];
+    e1[2] = e2[0] * d[1] - e2[1] * d[0];
+}
+
+/* polar/azimuth rotation of a unit direction (u,v,w) by (theta, phi) */
+static void rotate(double dir[3], double theta, double phi)
+{
+    double u = dir[0], v = dir[1], w = dir[2];
+    double ct = cos(theta), st = sin(theta), cp = cos(phi), sp = sin(phi);
+    double rho = hypot(u, v);
+    double nu, nv, nw;
+    if (rho < 1e-20) {
+        nu = st * cp;
+        nv = st * sp;
+        nw = (w < 0.0 ? -1.0 : 1.0) * ct;
+    } else {
+        nu = u * ct + st * (u * w * cp - v * sp) / rho;
+        nv = v * ct + st * (v * w * cp + u * sp) / rho;
+        nw = w * ct - rho * st * cp;
+    }
+    double l = sqrt(nu * nu + nv * nv + nw * nw);
+    dir[0] = nu / l; dir[1] = nv / l; dir[2] = nw / l;
+}
+
+void oracle_rotate(double dir[3], double theta, double phi) { rotate(dir, theta, phi); }
+
+static void flush(const oracle_problem *P, oracle_tally *T, size_t v, int64_t *acc)
+{
+    if (*acc == 0) return;
+    T->E[v] += *acc;
+    if ((P->flags & FLAG_VARIANCE) && T->E2) {
+        uint64_t q = (uint64_t)((*acc + 2048) >> 12);
+        T->E2[v] += q * q;
+    }
+    T->flushes++;
+    *acc = 0;
+}
+
+enum { END_STOP = 0, END_ESCAPE = 1, END_MISS = 2 };
+
+/* One history (plan, spot s, index h).  Returns the end reason; the end point
+ * is written to endpoint[3].  Tallies go to T (may be NULL for endpoints only). */
+static int replay_history(const oracle_problem *P, uint32_t s, uint64_t h, oracle_tally *T,
+                          double endpoint[3])
+{
+    const uint32_t key[2] = {(uint32_t)P->seed, (uint32_t)(P->seed >> 32)};
+
+    /* ---- task 1: database history, trajectory and start step ---------- */
+    double E_spot = P->spot_E[s];
+    uint32_t b = 0;
+    while (b < P->n_bins && (double)P->bin_E[b] < E_spot) ++b;
+    uint32_t n_b = P->bin_first[b + 1] - P->bin_first[b];
+
+    uint64_t c = h / P->R; /* chunk of R histories sharing one track */
+    uint32_t ctr[4] = {(uint32_t)c, (uint32_t)(c >> 32), s, (P->plan << 4) | TAG_TRACK};
+    uint32_t x[4];
+    oracle_philox4x32_10(ctr, key, x);
+    uint32_t t = P->bin_first[b] + (uint32_t)(((uint64_t)x[0] * n_b) >> 32);
+
+    const float *st = P->steps + 4 * P->track_off[t];
+    uint64_t n_steps = P->track_off[t + 1] - P->track_off[t];
+
+    /* energy skip of a spot below its bin energy, and the start step */
+    int64_t skip = fp_energy(P->bin_E[b]) - fp_energy(E_spot);
+    int64_t T_fp = 0;
+    for (uint64_t k = 0; k < n_steps; ++k) T_fp += fp_energy(st[4 * k + 1]);
+    uint64_t k0 = 0;
+    int64_t cum = 0;
+    while (k0 < n_steps && cum + fp_energy(st[4 * k0 + 1]) <= skip) {
+        cum += fp_energy(st[4 * k0 + 1]);
+        ++k0;
+    }
+    int64_t I_h = T_fp - skip;
+    if (I_h < 0) I_h = 0;
+
+    /* source: Gaussian lateral position, beam direction, optional track rotation */
+    ctr[0] = (uint32_t)h; ctr[1] = (uint32_t)(h >> 32); ctr[2] = s;
+    ctr[3] = (P->plan << 4) | TAG_SRC;
+    oracle_philox4x32_10(ctr, key, x);
+    double r = sqrt(-2.0 * log(oracle_uniform(x[0])));
+    double ang = 2.0 * M_PI * oracle_uniform(x[1]);
+    double n1 = r * cos(ang), n2 = r * sin(ang);
+    double phi0 = (P->flags & FLAG_ROTATE) ? 2.0 * M_PI * oracle_uniform(x[2]) : 0.0;
+
+    double d[3] = {P->spot_dir[3 * s], P->spot_dir[3 * s + 1], P->spot_dir[3 * s + 2]};
+    double dl = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+    d[0] /= dl; d[1] /= dl; d[2] /= dl;
+    double e1[3], e2[3];
+    field_frame(d, e1, e2);
+    double M[3][3]; /* columns e1, e2, d */
+    for (int a = 0; a < 3; ++a) { M[a][0] = e1[a]; M[a][1] = e2[a]; M[a][2] = d[a]; }
+    double sig = P->spot_sigma[s];
+    double pos[3];
+    for (int a = 0; a < 3; ++a)
+        pos[a] = (double)P->spot_pos[3 * s + a] + sig * (n1 * e1[a] + n2 * e2[a]);
+
+    if (T) T->incident += I_h;
+
+    /* ray-box entry; the region outside the box is vacuum */
+    double tin = -INFINITY, tout = INFINITY;
+    int ax_in = -1;
+    for (int a = 0; a < 3; ++a) {
+        double lo = P->org[a], hi = P->org[a] + P->n[a] * P->vox[a];
+        if (d[a] == 0.0) {
+            if (pos[a] < lo || pos[a] >= hi) { tin = INFINITY; break; }
+        } else {
+            double t1 = (lo - pos[a]) / d[a], t2 = (hi - pos[a]) / d[a];
+            if (t1 > t2) { double tt = t1; t1 = t2; t2 = tt; }
+            if (t1 > tin) { tin = t1; ax_in = a; }
+            if (t2 < tout) tout = t2;
+        }
+    }
+    if (!(tin < tout) || tout <= 0.0 || I_h == 0) {
+        memcpy(endpoint, pos, sizeof(double) * 3);
+        if (T) T->escaped += I_h;
+        return I_h == 0 ? END_STOP : END_MISS;
+    }
+    if (tin > 0.0) {
+        for (int a = 0; a < 3; ++a) pos[a] += tin * d[a];
+        /* the entry point lies exactly on the entry face */
+        pos[ax_in] = P->org[ax_in] + (d[ax_in] > 0.0 ? 0.0 : P->n[ax_in] * P->vox[ax_in]);
+    }
+
+    /* voxel of the entry point: a point on a boundary belongs to the voxel
+     * entered in the direction of travel */
+    int iv[3];
+    for (int a = 0; a < 3; ++a) {
+        double u = (pos[a] - P->org[a]) / P->vox[a];
+        double f = floor(u);
+        int i = (int)f;
+        if (u == f && d[a] < 0.0) i -= 1;
+        if (i < 0) i = 0;
+        if (i >= P->n[a]) i = P->n[a] - 1;
+        iv[a] = i;
+    }
+
+    /* ---- task 2: re-trace the steps ------------------------------------ */
+    double db[3] = {0.0, 0.0, 1.0}; /* beam-frame direction */
+    int64_t acc = 0, hist_dep = 0;
+    int reason = END_STOP;
+    int alive = 1;
+    for (uint64_t k = k0; k < n_steps && alive; ++k) {
+        double dx = st[4 * k + 0], theta = st[4 * k + 2], phi = st[4 * k + 3];
+        int64_t e = fp_energy(st[4 * k + 1]);
+        double w_tot = dx;
+        if (k == k0) { /* partial first step */
+            int64_t e_first = cum + e - skip;
+            double f = (double)e_first / (double)e;
+            e = e_first;
+            w_tot = f * dx;
+            theta *= sqrt(f);
+            phi += phi0;
+        }
+        if (T) T->steps++;
+        double tau = 0.0, g2 = 0.0;
+        int64_t dep = 0;
+        while (tau < w_tot) {
+            size_t v = ((size_t)iv[2] * P->n[1] + iv[1]) * P->n[0] + iv[0];
+            double rsp, g;
+            int vac = material(&P->tab, P->hu[v], &rsp, &g);
+            /* distance to the voxel exit, ties resolved x -> y -> z */
+            double lexit = INFINITY;
+            int ax = -1;
+            for (int a = 0; a < 3; ++a) {
+                double ta;
+                if (d[a] > 0.0) ta = (P->org[a] + (iv[a] + 1) * P->vox[a] - pos[a]) / d[a];
+                else if (d[a] < 0.0) ta = (P->org[a] + iv[a] * P->vox[a] - pos[a]) / d[a];
+                else continue;
+                if (ta < 0.0) ta = 0.0;
+                if (ta < lexit) { lexit = ta; ax = a; }
+            }
+            int cross = 1;
+            double move = lexit;
+            if (vac) {
+                if (T) T->vacuum_visits++;
+            } else {
+                if (T) T->visits++;
+                double rem = w_tot - tau;
+                double wb = lexit * rsp;
+                double w_v, tau_n;
+                if (rem <= wb) { /* the step ends in this voxel (or on its exit face) */
+                    w_v = rem;
+                    tau_n = w_tot;
+                    move = rem / rsp;
+                    cross = (rem == wb);
+                } else {
+                    w_v = wb;
+                    tau_n = tau + wb;
+                }
+                int64_t cumk = (int64_t)nearbyint((double)e * (tau_n / w_tot));
+                if (tau_n >= w_tot) cumk = e;
+                int64_t piece = cumk - dep;
+                dep = cumk;
+                acc += piece;
+                hist_dep += piece;
+                g2 += w_v * g;
+                tau = tau_n;
+            }
+            if (cross) {
+                for (int a = 0; a < 3; ++a) pos[a] += move * d[a];
+                pos[ax] = P->org[ax] + (iv[ax] + (d[ax] > 0.0 ? 1 : 0)) * P->vox[ax];
+                if (T) flush(P, T, v, &acc);
+                iv[ax] += d[ax] > 0.0 ? 1 : -1;
+                if (iv[ax] < 0 || iv[ax] >= P->n[ax]) {
+                    if (T) T->escaped += I_h - hist_dep;
+                    reason = END_ESCAPE;
+                    alive = 0;
+                    break;
+                }
+            } else {
+                for (int a = 0; a < 3; ++a) pos[a] += move * d[a];
+            }
+        }
+        if (!alive) break;
+        /* deflection at the end of the step, scaled by the traversed material */
+        double th = theta * sqrt(g2 / w_tot);
+        rotate(db, th, phi);
+        for (int a = 0; a < 3; ++a) d[a] = M[a][0] * db[0] + M[a][1] * db[1] + M[a][2] * db[2];
+    }
+    if (alive && T) {
+        size_t v = ((size_t)iv[2] * P->n[1] + iv[1]) * P->n[0] + iv[0];
+        flush(P, T, v, &acc);
+    }
+    memcpy(endpoint, pos, sizeof(double) * 3);
+    if (alive && hist_dep != I_h) return -1; /* energy not conserved: oracle bug */
+    return reason;
+}
+
+/* ---------------------------------------------------------------------- */
+typedef struct {
+    const float *steps; const uint64_t *track_off; uint32_t n_tracks;
+    const float *bin_E; const uint32_t *bin_first; uint32_t n_bins;
+} oracle_db_args;
+
+static void setup(oracle_problem *P, const float *steps, const uint64_t *track_off, uint32_t n_tracks,
+                  const float *bin_E, const uint32_t *bin_first, uint32_t n_bins,
+                  const int16_t *hu, const int dims[3], const double vox[3], const double org[3],
+                  const double *hu_pts, const double *rho, const double *rsp, const double *rscp,
+                  int n_pts, double vacuum_below_hu,
+                  const float *spot_pos, const float *spot_dir, const float *spot_E, const float *spot_sigma,
+                  uint32_t plan, uint64_t seed, uint32_t R, uint32_t flags)
+{
+    P->steps = steps; P->track_off = track_off; P->n_tracks = n_tracks;
+    P->bin_E = bin_E; P->bin_first = bin_first; P->n_bins = n_bins;
+    P->hu = hu;
+    for (int a = 0; a < 3; ++a) { P->n[a] = dims[a]; P->vox[a] = vox[a]; P->org[a] = org[a]; }
+    P->tab.hu = hu_pts; P->tab.rho = rho; P->tab.rsp = rsp; P->tab.rscp = rscp;
+    P->tab.n = n_pts; P->tab.vacuum_below_hu = vacuum_below_hu;
+    P->spot_pos = spot_pos; P->spot_dir = spot_dir; P->spot_E = spot_E; P->spot_sigma = spot_sigma;
+    P->plan = plan; P->seed = seed; P->R = R; P->flags = flags;
+}
+
+/*
+ * Replay histories [h_begin[i], h_begin[i] + h_count[i]) of every spot i and
+ * add them to the tallies E (int64) and E2 (uint64, may be NULL), plus
+ * stats[0..5] = incident, escaped, steps, visits, vacuum visits, flushes
+ * (int64 / uint64 bit patterns).  Threads split the flattened history range;
+ * each thread tallies privately and the integer sums are added at the end,
+ * which is exact.  Returns 0, or -1 if a history failed to conserve energy.
+ */
+int oracle_replay(const float *steps, const uint64_t *track_off, uint32_t n_tracks,
+                  const float *bin_E, const uint32_t *bin_first, uint32_t n_bins,
+                  const int16_t *hu, const int dims[3], const double vox[3], const double org[3],
+                  const double *hu_pts, const double *rho, const double *rsp, const double *rscp,
+                  int n_pts, double vacuum_below_hu,
+                  const float *spot_pos, const float *spot_dir, const float *spot_E,
+                  const float *spot_sigma, uint32_t n_spots,
+                  const uint64_t *h_begin, const uint64_t *h_count,
+                  uint32_t plan, uint64_t seed, uint32_t R, uint32_t flags, int n_threads,
+                  int64_t *E, uint64_t *E2, int64_t *stats)
+{
+    oracle_problem P;
+    setup(&P, steps, track_off, n_tracks, bin_E, bin_first, n_bins, hu, dims, vox, org,
+          hu_pts, rho, rsp, rscp, n_pts, vacuum_below_hu, spot_pos, spot_dir, spot_E, spot_sigma,
+          plan, seed, R, flags);
+    size_t nvox = (size_t)dims[0] * dims[1] * dims[2];
+    uint64_t *prefix = (uint64_t *)malloc(sizeof(uint64_t) * (n_spots + 1));
+    prefix[0] = 0;
+    for (uint32_t i = 0; i < n_spots; ++i) prefix[i + 1] = prefix[i] + h_count[i];
+    uint64_t total = prefix[n_spots];
+    int err = 0;
+    int nt = n_threads > 0 ? n_threads : 1;
+#ifdef _OPENMP
+    #pragma omp parallel num_threads(nt) reduction(|:err)
+#endif
+    {
+        int tid = 0, nth = 1;
+#ifdef _OPENMP
+        tid = omp_get_thread_num();
+        nth = omp_get_num_threads();
+#endif
+        oracle_tally T;
+        memset(&T, 0, sizeof T);
+        T.E = (int64_t *)calloc(nvox, sizeof(int64_t));
+        T.E2 = E2 ? (uint64_t *)calloc(nvox, sizeof(uint64_t)) : NULL;
+        uint64_t lo = total * (uint64_t)tid / (uint64_t)nth;
+        uint64_t hi = total * (uint64_t)(tid + 1) / (uint64_t)nth;
+        uint32_t s = 0;
+        for (uint64_t g = lo; g < hi; ++g) {
+            while (prefix[s + 1] <= g) ++s;
+            double ep[3];
+            if (replay_history(&P, s, h_begin[s] + (g - prefix[s]), &T, ep) < 0) err |= 1;
+        }
+#ifdef _OPENMP
+        #pragma omp critical
+#endif
+        {
+            for (size_t v = 0; v < nvox; ++v) E[v] += T.E[v];
+            if (E2)
+                for (size_t v = 0; v < nvox; ++v) E2[v] += T.E2[v];
+            stats[0] += T.incident;
+            stats[1] += T.escaped;
+            stats[2] += (int64_t)T.steps;
+            stats[3] += (int64_t)T.visits;
+            stats[4] += (int64_t)T.vacuum_visits;
+            stats[5] += (int64_t)T.flushes;
+        }
+        free(T.E);
+        free(T.E2);
+    }
+    free(prefix);
+    return err ? -1 : 0;
+}
+
+/* End point (cm) and end reason (0 stop, 1 escape, 2 miss) of histories
+ * h0 .. h0+n-1 of spot s.  No tallies are touched. */
+int oracle_endpoints(const float *steps, const uint64_t *track_off, uint32_t n_tracks,
+                     const float *bin_E, const uint32_t *bin_first, uint32_t n_bins,
+                     const int16_t *hu, const int dims[3], const double vox[3], const double org[3],
+                     const double *hu_pts, const double *rho, const double *rsp, const double *rscp,
+                     int n_pts, double vacuum_below_hu,
+                     const float *spot_pos, const float *spot_dir, const float *spot_E,
+                     const float *spot_sigma, uint32_t s, uint64_t h0, uint32_t n,
+                     uint32_t plan, uint64_t seed, uint32_t R, uint32_t flags,
+                     double *xyz, int32_t *reason)
+{
+    oracle_problem P;
+    setup(&P, steps, track_off, n_tracks, bin_E, bin_first, n_bins, hu, dims, vox, org,
+          hu_pts, rho, rsp, rscp, n_pts, vacuum_below_hu, spot_pos, spot_dir, spot_E, spot_sigma,
+          plan, seed, R, flags);
+    for (uint32_t i = 0; i < n; ++i)
+        reason[i] = replay_history(&P, s, h0 + i, NULL, xyz + 3 * i);
+    return 0;
+}

@@ -1,0 +1,212 @@
+"""Python side of the CPU oracle (test infrastructure only).
+
+Only the test suite, the smoke check and the benchmark's CPU-baseline leg may
+import this module.  It wraps the plain-C replay in `fdc_oracle.c` and adds the
+FP64 numpy definitions of the quantities computed from the tallies:
+
+  * dose = deposited energy / voxel mass (Section 2.3), in Gy per primary;
+  * the history-by-history uncertainty of Eq. (2), summed over all N histories
+    of the plan (the upper index of the sum in Eq. (2) is read as N);
+  * the batch uncertainty of Eq. (1);
+  * the mean dose uncertainty: mean of sigma_D / D over voxels with
+    D > Dmax / 2 (Section 2.4);
+  * the gamma index (Low et al. 1998) with a global dose criterion.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liboracle.so")
+SRC_PATH = os.path.join(HERE, "fdc_oracle.c")
+
+MEV_J = 1.602176634e-13          # J per MeV
+FP_LSB_MEV = 2.0 ** -24          # fixed-point energy unit
+FLAG_VARIANCE = 1
+FLAG_ROTATE = 2
+END_STOP, END_ESCAPE, END_MISS = 0, 1, 2
+
+
+def build(force=True):
+    """Compile the oracle with gcc (plain C, -O2, OpenMP)."""
+    if not force and os.path.exists(LIB_PATH) and os.path.getmtime(LIB_PATH) >= os.path.getmtime(SRC_PATH):
+        return LIB_PATH
+    tmp = LIB_PATH + ".tmp"
+    subprocess.run(["gcc", "-O2", "-std=gnu11", "-fopenmp", "-fPIC", "-shared", "-Wall",
+                    "-o", tmp, SRC_PATH, "-lm"], check=True)
+    os.replace(tmp, LIB_PATH)
+    return LIB_PATH
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            build()
+        _lib = C.CDLL(LIB_PATH)
+    return _lib
+
+
+def _p(a, t):
+    return a.ctypes.data_as(C.POINTER(t))
+
+
+def default_table():
+    from paper_1011_2188_amd.inputs import HU_TABLE_DEFAULT
+    return HU_TABLE_DEFAULT
+
+
+# --------------------------------------------------------------------------
+def philox(ctr, key):
+    """Philox4x32-10 of counter ctr[4] (uint32) under key[2]."""
+    c = np.ascontiguousarray(ctr, np.uint32)
+    k = np.ascontiguousarray(key, np.uint32)
+    out = np.zeros(4, np.uint32)
+    lib().oracle_philox4x32_10(_p(c, C.c_uint32), _p(k, C.c_uint32), _p(out, C.c_uint32))
+    return out
+
+
+def rotate(d, theta, phi):
+    """The polar/azimuth direction rotation used at the end of every step."""
+    v = np.ascontiguousarray(d, np.float64).copy()
+    lib().oracle_rotate(_p(v, C.c_double), C.c_double(theta), C.c_double(phi))
+    return v
+
+
+def uniform(x):
+    f = lib().oracle_uniform
+    f.restype = C.c_double
+    return f(C.c_uint32(int(x)))
+
+
+def material(hu, table=None):
+    """(rho, rsp, G, vacuum) for an int16 HU array, by the piecewise-linear table."""
+    t = table or default_table()
+    hu = np.ascontiguousarray(hu, np.int16).ravel()
+    n = hu.size
+    rho, rsp, g = (np.zeros(n) for _ in range(3))
+    vac = np.zeros(n, np.uint8)
+    pts = [np.ascontiguousarray(t[k], np.float64) for k in ("hu", "rho", "rsp", "rscp")]
+    lib().oracle_material(*[_p(a, C.c_double) for a in pts], C.c_int(pts[0].size),
+                          C.c_double(t["vacuum_below_hu"]), _p(hu, C.c_int16), C.c_int(n),
+                          _p(rho, C.c_double), _p(rsp, C.c_double), _p(g, C.c_double),
+                          _p(vac, C.c_uint8))
+    return rho, rsp, g, vac.astype(bool)
+
+
+def _common(db, ph, sp, table):
+    t = table or default_table()
+    spots = np.ascontiguousarray(sp)
+    arrs = dict(
+        steps=np.ascontiguousarray(db.steps, np.float32),
+        track_off=np.ascontiguousarray(db.track_off, np.uint64),
+        bin_E=np.ascontiguousarray(db.bin_E, np.float32),
+        bin_first=np.ascontiguousarray(db.bin_first, np.uint32),
+        hu=np.ascontiguousarray(ph.hu, np.int16),
+        dims=np.array(ph.shape_xyz, np.int32),
+        vox=np.asarray(ph.voxel_cm, np.float64),
+        org=np.asarray(ph.origin_cm, np.float64),
+        tab=[np.ascontiguousarray(t[k], np.float64) for k in ("hu", "rho", "rsp", "rscp")],
+        pos=np.ascontiguousarray(spots["pos_cm"], np.float32),
+        dir=np.ascontiguousarray(spots["dir"], np.float32),
+        E=np.ascontiguousarray(spots["energy_MeV"], np.float32),
+        sig=np.ascontiguousarray(spots["sigma_cm"], np.float32),
+    )
+    args = [_p(arrs["steps"], C.c_float), _p(arrs["track_off"], C.c_uint64), C.c_uint32(db.n_tracks),
+            _p(arrs["bin_E"], C.c_float), _p(arrs["bin_first"], C.c_uint32), C.c_uint32(db.n_bins),
+            _p(arrs["hu"], C.c_int16), _p(arrs["dims"], C.c_int), _p(arrs["vox"], C.c_double),
+            _p(arrs["org"], C.c_double)]
+    args += [_p(a, C.c_double) for a in arrs["tab"]]
+    args += [C.c_int(arrs["tab"][0].size), C.c_double(t["vacuum_below_hu"]),
+             _p(arrs["pos"], C.c_float), _p(arrs["dir"], C.c_float), _p(arrs["E"], C.c_float),
+             _p(arrs["sig"], C.c_float)]
+    return arrs, args
+
+
+def replay(db, ph, sp, h_begin=None, h_count=None, plan=0, seed=1, R=64, flags=FLAG_VARIANCE,
+           threads=None, table=None):
+    """Replay histories h_begin[i] .. h_begin[i]+h_count[i]-1 of every spot i.
+
+    Returns a dict with the int64 energy tally E, the uint64 sum-of-squares tally
+    E2 (x-fastest, shape [nz,ny,nx]), incident/escaped energy (fixed point) and
+    the work counters (steps, visits, vacuum_visits, flushes)."""
+    arrs, args = _common(db, ph, sp, table)
+    ns = len(sp)
+    hb = np.zeros(ns, np.uint64) if h_begin is None else np.ascontiguousarray(h_begin, np.uint64)
+    hc = (np.ascontiguousarray(sp["n_histories"], np.uint64) if h_count is None
+          else np.ascontiguousarray(h_count, np.uint64))
+    nx, ny, nz = ph.shape_xyz
+    E = np.zeros(nx * ny * nz, np.int64)
+    E2 = np.zeros(nx * ny * nz, np.uint64)
+    stats = np.zeros(6, np.int64)
+    nthreads = threads or int(os.environ.get("ORACLE_THREADS", os.cpu_count() or 1))
+    rc = lib().oracle_replay(*args, C.c_uint32(ns), _p(hb, C.c_uint64), _p(hc, C.c_uint64),
+                             C.c_uint32(plan), C.c_uint64(seed), C.c_uint32(R), C.c_uint32(flags),
+                             C.c_int(nthreads), _p(E, C.c_int64), _p(E2, C.c_uint64),
+                             _p(stats, C.c_int64))
+    if rc != 0:
+        raise RuntimeError("oracle replay failed to conserve energy")
+    return dict(E=E.reshape(nz, ny, nx), E2=E2.reshape(nz, ny, nx), incident=int(stats[0]),
+                escaped=int(stats[1]), steps=int(stats[2]), visits=int(stats[3]),
+                vacuum_visits=int(stats[4]), flushes=int(stats[5]),
+                n_histories=int(hc.sum()), threads=nthreads)
+
+
+def endpoints(db, ph, sp, spot, h0, n, plan=0, seed=1, R=64, flags=0, table=None):
+    """End point (cm, float64 [n,3]) and end reason of histories h0..h0+n-1 of a spot."""
+    arrs, args = _common(db, ph, sp, table)
+    xyz = np.zeros((n, 3), np.float64)
+    reason = np.zeros(n, np.int32)
+    lib().oracle_endpoints(*args, C.c_uint32(spot), C.c_uint64(h0), C.c_uint32(n), C.c_uint32(plan),
+                           C.c_uint64(seed), C.c_uint32(R), C.c_uint32(flags),
+                           _p(xyz, C.c_double), _p(reason, C.c_int32))
+    if np.any(reason < 0):
+        raise RuntimeError("oracle replay failed to conserve energy")
+    return xyz, reason
+
+
+# --------------------------------------------------------------------------
+# quantities derived from the tallies (FP64)
+# --------------------------------------------------------------------------
+def voxel_mass_kg(ph, table=None):
+    rho, _, _, vac = material(ph.hu, table)
+    vol = float(np.prod(np.asarray(ph.voxel_cm, np.float64)))
+    return (rho * vol * 1e-3).reshape(ph.hu.shape), vac.reshape(ph.hu.shape)
+
+
+def dose_and_variance(E, E2, n_histories, ph, table=None):
+    """Dose per primary (Gy) = E / m / N, and the Eq. (2) variance of that mean.
+
+    S1 = sum_i D_i and S2 = sum_i D_i^2 over all N histories (zeros included):
+    var = (S2/N - (S1/N)^2) / (N - 1).  E2 is in units of 2^-24 MeV^2."""
+    m, vac = voxel_mass_kg(ph, table)
+    N = float(n_histories)
+    c = FP_LSB_MEV * MEV_J / np.where(vac, 1.0, m)
+    S1 = E.astype(np.float64) * c
+    S2 = E2.astype(np.float64) * FP_LSB_MEV * (MEV_J / np.where(vac, 1.0, m)) ** 2
+    dose = np.where(vac, 0.0, S1 / N)
+    var = np.where(vac, 0.0, (S2 / N - (S1 / N) ** 2) / max(N - 1.0, 1.0))
+    return dose, var
+
+
+def mean_uncertainty(dose, sigma, vacuum=None):
+    """Mean of sigma/D over voxels with D > Dmax/2 (vacuum voxels excluded)."""
+    d = dose if vacuum is None else np.where(vacuum, 0.0, dose)
+    dmax = d.max()
+    sel = d > 0.5 * dmax
+    return float(np.mean(sigma[sel] / d[sel]))
+
+
+def batch_uncertainty(doses):
+    """Eq. (1): sqrt(sum_i (D_i - mean)^2 / (n (n-1))) over n independent batches."""
+    D = np.stack([np.asarray(d, np.float64) for d in doses])
+    n = D.shape[0]
+    mean = D.mean(axis=0)
+    return mean, np.sqrt(((D - mean) ** 2).sum(axis=0) / (n * (n - 1)))

@@ -1,0 +1,270 @@
+"""Seeded synthetic inputs for track-repeating dose calculation.
+
+This module builds the *inputs* of the method and nothing else: voxel phantoms
+(int16 Hounsfield units), pencil-beam spot lists, and the synthetic water track
+database that stands in for the GEANT4 water database of Section 2.2 (the
+paper's database itself is not available).  It holds none of the replay
+arithmetic (scaling, voxel walk, deflection, tallying, dose): both the HIP path
+and the CPU oracle read what this module produces and nothing else.
+
+Water track database (stand-in for Section 2.1/2.2):
+  * mean energy loss per step from the Bragg-Kleeman range-energy relation
+    R(E) = ALPHA * E**P_BK (cm, MeV);
+  * Gaussian energy straggling with Bohr's variance (the variance model named
+    in Section 2.1);
+  * Highland multiple-scattering angle, sampled once per step (condensed
+    history: the angular effect of a segment applied at its end, Section 2.1).
+  Each step record is (dx [cm of water], dE [MeV], theta [rad], phi [rad]) as
+  float32, contiguous per track, tracks grouped by energy bin.
+
+Units: cm, MeV, rad, g/cm^3.  Arrays are x-fastest: hu[z, y, x].
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import numpy as np
+
+# --- physics constants of the synthetic water database ---------------------
+ALPHA = 0.0022          # Bragg-Kleeman prefactor, cm / MeV**P_BK
+P_BK = 1.77             # Bragg-Kleeman exponent
+K_BOHR = 0.1569         # 4*pi*N_A*r_e^2*(m_e c^2)^2, MeV^2 cm^2 / g
+Z_OVER_A_WATER = 0.5551
+X0_WATER = 36.08        # radiation length of water, cm
+M_PROTON = 938.272      # MeV
+STEP_CM = 0.1           # database step length (about the 1 mm depth segmentation of Section 2.2)
+
+# numpy structured dtype matching the C struct fdc_spot (40 bytes)
+SPOT_DTYPE = np.dtype([("pos_cm", "<f4", (3,)), ("dir", "<f4", (3,)),
+                       ("energy_MeV", "<f4"), ("sigma_cm", "<f4"),
+                       ("n_histories", "<u8")])
+assert SPOT_DTYPE.itemsize == 40
+
+# Default HU -> (density, relative stopping power, relative scattering power)
+# table: synthetic constants (not clinical data), piecewise linear.
+HU_TABLE_DEFAULT = {
+    "hu":   np.array([-1000.0, 0.0, 1000.0, 3071.0]),
+    "rho":  np.array([0.0012, 1.0, 1.6, 2.84]),
+    "rsp":  np.array([0.0011, 1.0, 1.5, 2.64]),
+    "rscp": np.array([0.0012, 1.0, 2.16, 3.834]),
+    "vacuum_below_hu": -990.0,
+}
+
+
+@dataclasses.dataclass
+class Phantom:
+    hu: np.ndarray            # int16 [nz, ny, nx]
+    voxel_cm: np.ndarray      # float32 [3] (x, y, z)
+    origin_cm: np.ndarray     # float32 [3] corner of voxel (0,0,0)
+
+    @property
+    def shape_xyz(self):
+        nz, ny, nx = self.hu.shape
+        return nx, ny, nz
+
+
+@dataclasses.dataclass
+class TrackDB:
+    steps: np.ndarray         # float32 [n_steps, 4] = (dx, dE, theta, phi)
+    track_off: np.ndarray     # uint64 [n_tracks + 1]
+    bin_E: np.ndarray         # float32 [n_bins]
+    bin_first: np.ndarray     # uint32 [n_bins + 1]
+
+    @property
+    def n_tracks(self):
+        return int(self.track_off.size - 1)
+
+    @property
+    def n_bins(self):
+        return int(self.bin_E.size)
+
+
+# --------------------------------------------------------------------------
+# water track database
+# --------------------------------------------------------------------------
+def _beta2(E):
+    g = (E + M_PROTON) / M_PROTON
+    return 1.0 - 1.0 / (g * g)
+
+
+def highland_theta0(E, x_cm):
+    """Highland width (rad) for a proton of kinetic energy E (MeV) over x_cm of water."""
+    b2 = _beta2(E)
+    bcp = b2 * (E + M_PROTON)                 # beta * c * p = beta^2 * total energy
+    arg = np.maximum(x_cm, 1e-30) / (X0_WATER * b2)
+    th = 13.6 / bcp * np.sqrt(x_cm / X0_WATER) * (1.0 + 0.038 * np.log(arg))
+    return np.maximum(th, 0.0)
+
+
+def bohr_sigma(E, x_cm):
+    """Bohr straggling width (MeV) in water over x_cm at kinetic energy E."""
+    b2 = _beta2(E)
+    return np.sqrt(K_BOHR * Z_OVER_A_WATER * x_cm * (1.0 - 0.5 * b2) / (1.0 - b2))
+
+
+def csda_range(E):
+    return ALPHA * np.power(E, P_BK)
+
+
+def energy_at_range(R):
+    return np.power(np.maximum(R, 0.0) / ALPHA, 1.0 / P_BK)
+
+
+def _gen_bin(Eb, n_tracks, rng, step_cm):
+    """All tracks of one energy bin; returns (records [n_steps,4] f32, steps per track)."""
+    E = np.full(n_tracks, float(Eb))
+    alive = np.ones(n_tracks, bool)
+    cols = []     # per step: (n_tracks, 4) float32, valid where mask
+    masks = []
+    while alive.any():
+        z = rng.standard_normal((n_tracks, 3))
+        R = csda_range(E)
+        final = alive & (R <= step_cm)
+        normal = alive & ~final
+        rec = np.zeros((n_tracks, 4))
+        # regular step of length step_cm
+        Rn = np.where(normal, R, 2.0 * step_cm)
+        E_mid = energy_at_range(Rn - 0.5 * step_cm)
+        dE_mean = E - energy_at_range(Rn - step_cm)
+        sig = bohr_sigma(E_mid, step_cm)
+        dE = np.clip(dE_mean + sig * z[:, 0], 0.0, E)
+        th0 = highland_theta0(E_mid, step_cm)
+        # final step: the residual range, all residual energy, angle at E/2
+        Ef = np.where(final, E, 1.0)
+        th0f = highland_theta0(0.5 * Ef, np.where(final, R, step_cm))
+        th0 = np.where(final, th0f, th0)
+        dx = np.where(final, R, step_cm)
+        dE = np.where(final, E, dE)
+        tx = th0 * z[:, 1]
+        ty = th0 * z[:, 2]
+        rec[:, 0] = dx
+        rec[:, 1] = dE
+        rec[:, 2] = np.hypot(tx, ty)
+        rec[:, 3] = np.arctan2(ty, tx)
+        cols.append(rec.astype(np.float32))
+        masks.append(alive.copy())
+        E = np.where(alive, E - dE, E)
+        alive = normal & (E > 0.0)
+    recs = np.stack(cols, axis=1)            # [n_tracks, n_steps_max, 4]
+    mask = np.stack(masks, axis=1)           # [n_tracks, n_steps_max]
+    return recs[mask], mask.sum(axis=1)
+
+
+def make_water_track_db(bin_energies_MeV, n_tracks_per_bin, seed, step_cm=STEP_CM):
+    """Synthetic water track database: `n_tracks_per_bin` tracks at each bin energy.
+
+    Deterministic in (seed, bin index).  Bins must be strictly increasing."""
+    bins = np.asarray(bin_energies_MeV, np.float32)
+    if bins.ndim != 1 or bins.size == 0 or np.any(np.diff(bins) <= 0):
+        raise ValueError("bin energies must be a non-empty increasing list")
+    recs, counts = [], []
+    for b, Eb in enumerate(bins):
+        rng = np.random.default_rng([int(seed), b])
+        r, c = _gen_bin(float(Eb), int(n_tracks_per_bin), rng, step_cm)
+        recs.append(r)
+        counts.append(c)
+    counts = np.concatenate(counts).astype(np.uint64)
+    track_off = np.zeros(counts.size + 1, np.uint64)
+    np.cumsum(counts, out=track_off[1:])
+    bin_first = (np.arange(bins.size + 1, dtype=np.uint64) * int(n_tracks_per_bin)).astype(np.uint32)
+    return TrackDB(np.ascontiguousarray(np.concatenate(recs, axis=0), np.float32),
+                   track_off, bins, bin_first)
+
+
+# --------------------------------------------------------------------------
+# phantoms
+# --------------------------------------------------------------------------
+def water_phantom(n=(64, 64, 64), voxel_cm=0.2, origin=None):
+    nx, ny, nz = n
+    hu = np.zeros((nz, ny, nx), np.int16)
+    vox = np.full(3, voxel_cm, np.float32)
+    if origin is None:
+        origin = (-0.5 * nx * voxel_cm, -0.5 * ny * voxel_cm, 0.0)
+    return Phantom(hu, vox, np.asarray(origin, np.float32))
+
+
+def slab_phantom(n=128, voxel_cm=0.1):
+    """Water with a bone slab (HU +1000) at z in [4,6) cm and a lung slab
+    (HU -800) at z in [8,12) cm, slabs perpendicular to the beam (+z)."""
+    ph = water_phantom((n, n, n), voxel_cm)
+    zc = (np.arange(n) + 0.5) * voxel_cm
+    ph.hu[(zc >= 4.0) & (zc < 6.0)] = 1000
+    ph.hu[(zc >= 8.0) & (zc < 12.0)] = -800
+    return ph
+
+
+def thorax_phantom(n=(256, 256, 128), voxel_cm=0.2, seed=2188, scale=(1.0, 1.0, 1.0),
+                   body_axes=(17.0, 11.0), lung_centre_x=7.0, lung_centre_y=-1.0,
+                   lung_axes=(5.0, 7.0, 10.0), spine_centre_y=-8.0, spine_radius=1.5):
+    """Synthetic thorax: air (-1000) around an elliptic body cylinder along z
+    (HU ~ N(40,20)), two lung ellipsoids (HU ~ N(-800,50)) and a spine cylinder
+    (HU ~ N(1000,100)); i.i.d. HU per voxel, rounded to int16.  Centred on 0."""
+    nx, ny, nz = n
+    sx, sy, sz = scale
+    rng = np.random.default_rng(int(seed))
+    x = (np.arange(nx) + 0.5) * voxel_cm - 0.5 * nx * voxel_cm
+    y = (np.arange(ny) + 0.5) * voxel_cm - 0.5 * ny * voxel_cm
+    z = (np.arange(nz) + 0.5) * voxel_cm - 0.5 * nz * voxel_cm
+    Z, Y, X = np.meshgrid(z, y, x, indexing="ij")
+    hu = np.full((nz, ny, nx), -1000.0)
+    body = (X / (body_axes[0] * sx)) ** 2 + (Y / (body_axes[1] * sy)) ** 2 <= 1.0
+    hu[body] = rng.normal(40.0, 20.0, int(body.sum()))
+    lungs = np.zeros_like(body)
+    for cx in (-lung_centre_x, lung_centre_x):
+        lungs |= (((X - cx * sx) / (lung_axes[0] * sx)) ** 2
+                  + ((Y - lung_centre_y * sy) / (lung_axes[1] * sy)) ** 2
+                  + (Z / (lung_axes[2] * sz)) ** 2) <= 1.0
+    hu[lungs] = rng.normal(-800.0, 50.0, int(lungs.sum()))
+    spine = X ** 2 + (Y - spine_centre_y * sy) ** 2 <= (spine_radius * min(sx, sy)) ** 2
+    hu[spine] = rng.normal(1000.0, 100.0, int(spine.sum()))
+    hu = np.clip(np.rint(hu), -32768, 32767).astype(np.int16)
+    vox = np.full(3, voxel_cm, np.float32)
+    origin = np.array([-0.5 * nx * voxel_cm, -0.5 * ny * voxel_cm, -0.5 * nz * voxel_cm], np.float32)
+    return Phantom(hu, vox, origin)
+
+
+# --------------------------------------------------------------------------
+# beam spots
+# --------------------------------------------------------------------------
+def spots(pos, dirs, energies, sigmas, n_histories):
+    k = len(energies)
+    s = np.zeros(k, SPOT_DTYPE)
+    s["pos_cm"] = np.asarray(pos, np.float32).reshape(k, 3)
+    s["dir"] = np.asarray(dirs, np.float32).reshape(k, 3)
+    s["energy_MeV"] = np.asarray(energies, np.float32)
+    s["sigma_cm"] = np.broadcast_to(np.asarray(sigmas, np.float32), (k,))
+    s["n_histories"] = np.broadcast_to(np.asarray(n_histories, np.uint64), (k,))
+    return s
+
+
+def gantry_direction(gantry_deg):
+    """Beam direction in the x-y plane for a coplanar gantry angle:
+    0 deg points along -y, 90 deg along -x, 180 deg along +y."""
+    g = math.radians(gantry_deg)
+    return np.array([-math.sin(g), -math.cos(g), 0.0])
+
+
+def field_frame(d):
+    """Lateral unit vectors (e1, e2) of a beam with unit direction d, such that
+    (e1, e2, d) is right-handed and d = +z gives (x, y)."""
+    d = np.asarray(d, np.float64)
+    a = np.array([1.0, 0.0, 0.0]) if abs(d[2]) >= 0.9 else np.array([0.0, 0.0, 1.0])
+    e2 = np.cross(d, a)
+    e2 /= np.linalg.norm(e2)
+    e1 = np.cross(e2, d)
+    return e1, e2
+
+
+def field_spots(iso, gantry_deg, n_spots, rng, half_width_cm=4.0, e_range=(70.0, 230.0),
+                sigma_cm=0.3, source_distance_cm=30.0, histories=None):
+    d = gantry_direction(gantry_deg)
+    e1, e2 = field_frame(d)
+    a = rng.uniform(-half_width_cm, half_width_cm, n_spots)
+    b = rng.uniform(-half_width_cm, half_width_cm, n_spots)
+    E = rng.uniform(e_range[0], e_range[1], n_spots)
+    pos = (np.asarray(iso, np.float64)[None, :] - source_distance_cm * d[None, :]
+           + a[:, None] * e1[None, :] + b[:, None] * e2[None, :])
+    dirs = np.broadcast_to(d, (n_spots, 3))
+    n = np.zeros(n_spots, np.uint64) if histories is None else histories
+    return spots(pos, dirs, E, sigma_cm, n)
