@@ -1,0 +1,176 @@
+"""Benchmark: proton histories/s of the track-repeating dose engine on one MI355X.
+
+One step = one complete dose calculation of the slab workload (128^3 voxels of
+1 mm with a bone and a lung slab, 25 pencil-beam spots at 70..230 MeV, 4e5
+histories each = 1e7 histories, database of 33 energy bins x 1e4 synthetic
+water tracks): clear the tallies, re-trace every history with the energy and
+squared-energy tallies, and convert to dose and Eq. (2) variance on the device.
+Inputs (database, phantom, spots) are resident in HBM before timing starts.
+
+Prints ONE JSON line.  Also reported: seconds to 2% mean dose uncertainty
+(Eq. (2), voxels above half the maximum dose), the transport kernel against the
+HBM roofline, and the CPU oracle timed on this host on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "proton histories/sec and seconds to 2% dose uncertainty, plain vs denoised, 1 MI355X"
+HBM_PEAK_GBS = 8000.0
+
+# Algorithmic work per history of the slab workload, counted exactly by
+# replaying a 25 x 2000-history sample: steps S = 95.03, voxel-walk iterations
+# C = 205.38 (no vacuum), flushes G = 111.71.  Bytes per history =
+# 16 B per step record / 64 histories sharing it + 2 B voxel index per walk
+# iteration + 8 B per tally atomic (G, doubled with the squared-energy tally).
+SLAB_S, SLAB_C, SLAB_G = 95.03, 205.38, 111.71
+
+
+def slab_bytes_per_history(variance: bool) -> float:
+    return 16.0 * SLAB_S / 64.0 + 2.0 * SLAB_C + 8.0 * SLAB_G * (2.0 if variance else 1.0)
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(ph, sp, db, target_s=15.0):
+    """The oracle as it stands, all host threads, on a bounded sample of the
+    same workload (every spot, fewer histories), scaled to histories/s."""
+    import numpy as np
+    from oracle import oracle as O
+    threads = int(os.environ.get("ORACLE_THREADS", min(os.cpu_count() or 1, 16)))
+    probe = 400
+    t = time.perf_counter()
+    O.replay(db, ph, sp, h_count=np.full(len(sp), probe, np.uint64), threads=threads)
+    rate = probe * len(sp) / (time.perf_counter() - t)
+    per_spot = int(max(probe, min(400_000, rate * target_s / len(sp))))
+    t = time.perf_counter()
+    O.replay(db, ph, sp, h_count=np.full(len(sp), per_spot, np.uint64), threads=threads)
+    dt = time.perf_counter() - t
+    n = per_spot * len(sp)
+    return {"value": n / dt, "unit": "histories/s", "cores": threads, "kind": "oracle",
+            "sample": f"{len(sp)} spots x {per_spot} histories of the same workload ({n} histories, {dt:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-variance", action="store_true", help="energy tally only")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--waves-per-block", type=int, default=4)
+    ap.add_argument("--blocks-per-cu", type=int, default=0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
+              "(histories are independent: more GPUs would take disjoint history ranges and "
+              "sum the int64 tallies once)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1011_2188_amd import fdc as F
+    from paper_1011_2188_amd import inputs as I
+    from paper_1011_2188_amd import workloads as W
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.init()
+    dev = torch.device("cuda", 0)
+    stream = torch.cuda.current_stream()
+    variance = not args.no_variance
+    flags = F.FDC_RUN_VARIANCE if variance else 0
+
+    t = time.perf_counter()
+    ph, sp, db = W.slab()
+    log(f"inputs generated in {time.perf_counter() - t:.1f} s: DB {db.steps.shape[0]} steps, "
+        f"{db.n_tracks} tracks, {db.n_bins} bins")
+    c = F.Context(device=0, seed=1, table=I.HU_TABLE_DEFAULT)
+    c.set_launch_config(args.waves_per_block, args.blocks_per_cu)
+    t = time.perf_counter()
+    c.load_track_db(db, stream)
+    plan = c.load_phantom(ph, stream)
+    c.add_beam_spots(plan, sp)
+    torch.cuda.synchronize()
+    log(f"loaded into HBM in {time.perf_counter() - t:.2f} s")
+    nvox = ph.hu.size
+    hist_per_step = int(sp["n_histories"].sum())
+    dose = torch.empty(nvox, dtype=torch.float64, device=dev)
+    var = torch.empty(nvox, dtype=torch.float64, device=dev) if variance else None
+
+    ev = []
+
+    def step(timed):
+        c.reset_plan(plan, stream=stream)
+        if timed:
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+        c.run_histories([plan], flags, stream=stream)
+        if timed:
+            e1.record(stream)
+            ev.append((e0, e1))
+        c.compute_dose(plan, dose, var, stream=stream)
+
+    for _ in range(args.warmup):
+        step(False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step(True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    wall = t1 - t0
+    value = hist_per_step * args.steps / wall
+    kern_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+    log(f"{args.steps} steps in {wall:.3f} s: {value:.4g} histories/s; transport {kern_ms:.3f} ms per launch")
+
+    # seconds to 2% mean uncertainty (Eq. (2), voxels above Dmax/2), from the last step
+    out = {}
+    if variance:
+        r = c.read_dose_and_variance(plan, raw=False, stream=stream)
+        d, v = r["dose"], r["var"]
+        sel = d > 0.5 * d.max()
+        u0 = float(np.mean(np.sqrt(np.maximum(v[sel], 0)) / d[sel]))
+        n2 = hist_per_step * (u0 / 0.02) ** 2
+        out["mean_uncertainty_at_1e7"] = u0
+        out["histories_to_2pct"] = n2
+        out["seconds_to_2pct"] = n2 / value
+        assert r["deposited"] + r["escaped"] == r["incident"], "energy identity violated"
+        log(f"mean uncertainty {u0:.4%} at {hist_per_step} histories -> 2% at {n2:.3g} histories, "
+            f"{n2 / value:.3g} s")
+
+    bph = slab_bytes_per_history(variance)
+    achieved = bph * hist_per_step / (kern_ms * 1e-3) / 1e9
+    atomics = SLAB_G * (2.0 if variance else 1.0) * hist_per_step / (kern_ms * 1e-3)
+    result = {
+        "metric": METRIC, "value": value, "unit": "histories/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "slab phantom 128^3 x 1 mm (bone z 4-6 cm, lung z 8-12 cm), 25 spots "
+                               "70-230 MeV, 1e7 histories per step, DB 33 bins x 1e4 tracks, int64 "
+                               "fixed-point tallies" + (" + squared-energy tally" if variance else ""),
+                   "histories_per_step": hist_per_step, "variance": variance,
+                   "waves_per_block": args.waves_per_block, "blocks_per_cu": args.blocks_per_cu},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "transport_kernel", "kernel_ms": kern_ms,
+                     "bytes_per_history": bph, "tally_atomics_per_s": atomics},
+        **out,
+    }
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle on a bounded sample ...")
+        result["cpu_baseline"] = cpu_baseline(ph, sp, db)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,230 @@
+/*
+ * fdc.h - C ABI of the MI355X track-repeating proton dose engine (libfdc.so).
+ *
+ * The method (Yepes, Mirkovic, Taddei, "A GPU implementation of a
+ * track-repeating algorithm for proton radiotherapy dose calculations"):
+ * proton tracks pre-computed in water are re-traced through a voxelised CT
+ * phantom, each step's length and scattering angle scaled by the local
+ * material, and the deposited energy tallied on a voxel grid (Sections 2.2,
+ * 2.3); the tally becomes dose by dividing by voxel mass, and a second tally of
+ * squared deposits gives the history-by-history uncertainty of Eq. (2)
+ * (Sections 2.3, 2.4).
+ *
+ * Conventions shared by every call
+ *   - Every call returns an int status (FDC_OK or a negative FDC_E_* code); no
+ *     call aborts or throws.  fdc_last_error() holds the message of the last
+ *     failure on that context.
+ *   - All arguments are validated before any HIP call.  Loaders are
+ *     all-or-nothing: on error the previous state is unchanged.
+ *   - Host arrays passed in are borrowed for the duration of the call only.
+ *     Device memory belongs to the context (allocated through the allocator
+ *     hook, else hipMalloc) unless a call says the caller owns it.
+ *   - hip_stream is the caller's hipStream_t (NULL = the null stream).  Work is
+ *     enqueued on it; fdc_run_histories and fdc_compute_dose return without
+ *     waiting; calls that fill host memory synchronise the stream first.
+ *   - Units: cm, MeV, rad, Gy.  Energies in the tallies are integers in units
+ *     of 2^-24 MeV (fixed point), so tallies are independent of the order in
+ *     which histories finish.
+ *   - Arrays are x-fastest: element (ix, iy, iz) is at (iz*ny + iy)*nx + ix.
+ *   - A context is used by one host thread at a time.
+ */
+#ifndef FDC_H
+#define FDC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fdc_ctx fdc_ctx;
+
+enum {
+    FDC_OK = 0,
+    FDC_E_ARG = -1,      /* null pointer, bad size, NaN, unsorted table ...          */
+    FDC_E_STATE = -2,    /* call out of order (e.g. run before a database is loaded) */
+    FDC_E_NOMEM = -3,    /* device or host allocation failed; state unchanged        */
+    FDC_E_HIP = -4,      /* a HIP runtime call failed (message has the HIP error)    */
+    FDC_E_RANGE = -5,    /* spot energy outside the database's bin energies          */
+    FDC_E_FORMAT = -6,   /* malformed track database                                 */
+    FDC_E_OVERFLOW = -7  /* requested histories could overflow the int64 tally       */
+};
+
+/* fdc_create's hip_device value for a context without a GPU: every argument
+ * check and all host-side bookkeeping run, nothing is sent to a device, and
+ * calls that must produce device results return FDC_E_STATE. */
+#define FDC_NO_DEVICE (-1)
+
+/* run flags */
+enum {
+    FDC_RUN_VARIANCE = 1u,      /* also tally squared per-visit deposits (Section 2.3)  */
+    FDC_RUN_ROTATE_TRACKS = 2u  /* rotate each re-traced track by a random azimuth      */
+};
+
+/* One stored water step (Section 2.2: direction change, length and energy loss
+ * of each step): water-equivalent length, energy loss, polar and azimuthal
+ * deflection applied at the end of the step.  16 bytes. */
+typedef struct { float dx_cm, dE_MeV, theta_rad, phi_rad; } fdc_step;
+
+/* A pencil-beam spot: histories start at pos + sigma*(n1*e1 + n2*e2) moving
+ * along dir (unit), where (n1, n2) are standard normal and (e1, e2) the lateral
+ * axes of dir: e2 = normalize(dir x a), e1 = e2 x dir, with a = +x if
+ * |dir.z| >= 0.9 else +z.  The source region outside the phantom is vacuum. */
+typedef struct {
+    float pos_cm[3];
+    float dir[3];
+    float energy_MeV;
+    float sigma_cm;
+    uint64_t n_histories; /* histories per fdc_run_histories call */
+} fdc_spot;
+
+typedef struct {
+    uint64_t n_histories;  /* histories run on the plan since its last reset          */
+    int64_t incident_fp;   /* sum of incident energies, 2^-24 MeV                      */
+    int64_t deposited_fp;  /* sum of the energy tally                                  */
+    int64_t escaped_fp;    /* energy carried out of the phantom box; deposited+escaped
+                              equals incident exactly                                 */
+} fdc_summary;
+
+/* launch knobs; none of them changes any result bit */
+typedef struct {
+    uint32_t waves_per_block;   /* 1..16, default 4                                    */
+    uint32_t blocks_per_cu;     /* persistent grid size = blocks_per_cu * CUs; 0 = one
+                                   block per work unit (non-persistent)                */
+    uint32_t reserved[6];
+} fdc_launch_config;
+
+typedef void *(*fdc_alloc_fn)(size_t bytes, void *user);
+typedef void (*fdc_free_fn)(void *ptr, void *user);
+
+/* Create a context on HIP device hip_device.  seed keys every random number
+ * (Philox4x32-10); reuse_R is the number of consecutive histories of a spot
+ * that re-trace one database track (the paper feeds a single stored history to
+ * a whole thread group, Section 4, and re-uses it for many incident protons,
+ * Section 2.3); 64 matches one wavefront.  *out receives the context.
+ * hip_device == FDC_NO_DEVICE creates a validation-only context.
+ * Errors: FDC_E_ARG (out NULL, reuse_R == 0), FDC_E_HIP (no such device),
+ * FDC_E_NOMEM. */
+int fdc_create(fdc_ctx **out, int hip_device, uint64_t seed, uint32_t reuse_R);
+
+/* Free all device memory owned by the context and the context itself. */
+int fdc_destroy(fdc_ctx *ctx);
+
+/* Message of the last failed call on ctx ("" if none).  Valid until the next call. */
+const char *fdc_last_error(const fdc_ctx *ctx);
+
+/* Route the context's device allocations through alloc/free (e.g. a framework's
+ * caching allocator).  Must be called before any loader.  Errors: FDC_E_STATE
+ * if device memory was already allocated, FDC_E_ARG if only one hook is given. */
+int fdc_set_allocator(fdc_ctx *ctx, fdc_alloc_fn alloc, fdc_free_fn free_fn, void *user);
+
+/* Material table (Section 2.5: each voxel gets a material and mass density from
+ * its CT number; Section 2.3: the material table holds the step-length and
+ * scattering-angle scaling parameters).  Piecewise linear in HU over n_pts
+ * increasing points hu_pts[]: mass density rho (g/cm^3), relative stopping power
+ * rsp and relative scattering power rscp; clamped beyond the ends.  HU are
+ * clamped to [-1024, 3071]; HU < vacuum_below_hu is vacuum (free flight, no
+ * deposit).  Optional: the default table is used otherwise.  Applies to plans
+ * loaded afterwards and to the dose of every plan.
+ * Errors: FDC_E_ARG (NULL, n_pts < 2 or > 64, not increasing, negative or NaN
+ * values). */
+int fdc_set_hu_table(fdc_ctx *ctx, const float *hu_pts, const float *rho, const float *rsp,
+                     const float *rscp, int n_pts, float vacuum_below_hu);
+
+/* Load the water track database into device memory (Section 2.2: particle
+ * trajectories stored as steps; Section 2.3: kept in GPU global memory).
+ * steps[n_steps] hold the tracks back to back; track t is
+ * steps[track_off[t] .. track_off[t+1]); tracks of energy bin b are
+ * bin_first[b] .. bin_first[b+1]-1, bin energies bin_E_MeV[b] strictly
+ * increasing.  Replaces a previously loaded database.
+ * Errors: FDC_E_ARG (NULL, zero counts), FDC_E_FORMAT (offsets not monotone or
+ * not ending at n_steps, empty track or bin, bins not increasing, dx <= 0, dE <
+ * 0 or any non-finite value), FDC_E_NOMEM, FDC_E_HIP. */
+int fdc_load_track_db(fdc_ctx *ctx, const fdc_step *steps, uint64_t n_steps,
+                      const uint64_t *track_off, uint32_t n_tracks, const float *bin_E_MeV,
+                      const uint32_t *bin_first, uint32_t n_bins, void *hip_stream);
+
+/* Add a plan: a phantom of nx*ny*nz voxels of size voxel_cm (x, y, z) whose
+ * voxel (0,0,0) starts at origin_cm, with CT numbers hu[] (host, x-fastest;
+ * Section 2.3: a three-dimensional array with a material index per voxel).
+ * Allocates its energy and squared-energy tallies (Section 2.3: a tally grid
+ * with the phantom's voxel count, stored as a one-dimensional array), zeroed.
+ * *plan_out receives the plan id.  Errors: FDC_E_ARG (NULL, non-positive or
+ * non-finite sizes, more than 2^31 voxels), FDC_E_NOMEM, FDC_E_HIP. */
+int fdc_load_phantom(fdc_ctx *ctx, int32_t *plan_out, const int16_t *hu, int nx, int ny, int nz,
+                     const float voxel_cm[3], const float origin_cm[3], void *hip_stream);
+
+/* Append n spots to a plan (Section 2.5: the incident field; Section 2.3: the
+ * phase space of incident protons).  Each spot re-traces tracks of the smallest
+ * bin energy >= its energy, starting inside the track where the remaining
+ * energy equals the spot energy (Section 2.3, task 1).  Errors: FDC_E_ARG (bad
+ * plan, NULL, non-finite values, zero direction, negative sigma), FDC_E_RANGE
+ * (energy below the first or above the last bin energy), FDC_E_STATE (no
+ * database loaded). */
+int fdc_add_beam_spots(fdc_ctx *ctx, int32_t plan, const fdc_spot *spots, uint32_t n);
+
+/* One pass of the method over n_plans plans in a single launch (Section 2.3:
+ * every incident proton is an independent thread re-tracing a stored
+ * history): every spot of every listed plan runs its n_histories more
+ * histories.  A history is identified by (plan, spot, h) where h continues
+ * across calls; that identity keys every random number, so tallies do not
+ * depend on launch configuration, batching or call splitting.  flags:
+ * FDC_RUN_*.  Asynchronous on hip_stream.  Errors: FDC_E_ARG (bad or repeated
+ * plan id), FDC_E_STATE (no database), FDC_E_OVERFLOW (the plan's histories
+ * times the largest bin energy could exceed the int64 tally), FDC_E_NOMEM,
+ * FDC_E_HIP. */
+int fdc_run_histories(fdc_ctx *ctx, const int32_t *plans, uint32_t n_plans, uint32_t flags,
+                      void *hip_stream);
+
+/* Zero a plan's tallies and summary (asynchronous).  The history counters keep
+ * running unless rewind is non-zero, in which case the next run repeats the
+ * same histories from h = 0.  Errors: FDC_E_ARG. */
+int fdc_reset_plan(fdc_ctx *ctx, int32_t plan, int rewind, void *hip_stream);
+
+/* Dose per primary and its Eq. (2) variance into caller-owned DEVICE arrays of
+ * nx*ny*nz doubles (either may be NULL), asynchronously.  Dose = deposited
+ * energy / voxel mass / N (Section 2.3), N the plan's histories; variance =
+ * (S2/N - (S1/N)^2)/(N-1) with S1, S2 the sums of per-history dose and squared
+ * dose (Eq. (2), summed over all N histories).  Vacuum voxels get 0.
+ * Errors: FDC_E_ARG, FDC_E_STATE (variance asked but a run without
+ * FDC_RUN_VARIANCE touched the plan, or no history run), FDC_E_HIP. */
+int fdc_compute_dose(fdc_ctx *ctx, int32_t plan, double *dose_dev, double *var_dev,
+                     void *hip_stream);
+
+/* As fdc_compute_dose, into HOST arrays, plus the raw tallies (raw_E int64,
+ * raw_E2 uint64, nx*ny*nz each) and the summary; any pointer may be NULL.
+ * Synchronises hip_stream.  Errors as fdc_compute_dose. */
+int fdc_read_dose_and_variance(fdc_ctx *ctx, int32_t plan, double *dose_gy_per_primary,
+                               double *var_gy2, int64_t *raw_E, uint64_t *raw_E2,
+                               fdc_summary *sum, void *hip_stream);
+
+/* Replay histories h0 .. h0+n-1 of spot `spot` of a plan without tallying and
+ * return their end points (host xyz_out[3n], cm) and end reasons (host
+ * reason_out[n]: 0 stopped, 1 escaped the phantom, 2 missed it).  Uses the
+ * same kernel code as fdc_run_histories.  Synchronises hip_stream.
+ * Errors: FDC_E_ARG, FDC_E_STATE, FDC_E_HIP. */
+int fdc_debug_endpoints(fdc_ctx *ctx, int32_t plan, uint32_t spot, uint64_t h0, uint32_t n,
+                        uint32_t flags, float *xyz_out, int32_t *reason_out, void *hip_stream);
+
+/* Device Philox4x32-10 (Salmon et al., SC'11) of n counters ctr[4n] under the
+ * context seed, into out[4n] (host arrays).  For testing the generator.
+ * Synchronises hip_stream.  Errors: FDC_E_ARG, FDC_E_HIP. */
+int fdc_debug_philox(fdc_ctx *ctx, const uint32_t *ctr, uint32_t *out, uint32_t n, void *hip_stream);
+
+/* The material table as staged on the device: for HU index i = HU + 1024,
+ * i in 0..4095, rsp_out[i], g_out[i] = rscp/rsp and rho_out[i] (host arrays of
+ * 4096 floats; vacuum entries have rsp = g = 0).  Synchronises hip_stream. */
+int fdc_debug_material(fdc_ctx *ctx, float *rsp_out, float *g_out, float *rho_out, void *hip_stream);
+
+/* Launch knobs for fdc_run_histories (see fdc_launch_config).  Results are
+ * bitwise identical for every valid setting.  Errors: FDC_E_ARG. */
+int fdc_set_launch_config(fdc_ctx *ctx, const fdc_launch_config *cfg);
+
+/* Number of compute units of the context's device (for launch sizing). */
+int fdc_device_cus(fdc_ctx *ctx, int *cus);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FDC_H */

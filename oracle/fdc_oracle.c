@@ -71,6 +71,12 @@ void oracle_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t
     out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
 }
 
+/* n counters ctr[4n] under one key, into out[4n] */
+void oracle_philox_batch(const uint32_t *ctr, const uint32_t key[2], uint32_t *out, uint64_t n)
+{
+    for (uint64_t i = 0; i < n; ++i) oracle_philox4x32_10(ctr + 4 * i, key, out + 4 * i);
+}
+
 /* uniform in the open interval (0,1): 24 high bits plus half an LSB */
 double oracle_uniform(uint32_t x)
 {

@@ -73,6 +73,16 @@ def philox(ctr, key):
     return out
 
 
+def philox_batch(ctr, key):
+    """Philox4x32-10 of counters ctr[n,4] under one key."""
+    c = np.ascontiguousarray(ctr, np.uint32).reshape(-1, 4)
+    k = np.ascontiguousarray(key, np.uint32)
+    out = np.zeros_like(c)
+    lib().oracle_philox_batch(_p(c, C.c_uint32), _p(k, C.c_uint32), _p(out, C.c_uint32),
+                              C.c_uint64(c.shape[0]))
+    return out
+
+
 def rotate(d, theta, phi):
     """The polar/azimuth direction rotation used at the end of every step."""
     v = np.ascontiguousarray(d, np.float64).copy()
@@ -146,7 +156,7 @@ def replay(db, ph, sp, h_begin=None, h_count=None, plan=0, seed=1, R=64, flags=F
     E = np.zeros(nx * ny * nz, np.int64)
     E2 = np.zeros(nx * ny * nz, np.uint64)
     stats = np.zeros(6, np.int64)
-    nthreads = threads or int(os.environ.get("ORACLE_THREADS", os.cpu_count() or 1))
+    nthreads = threads or int(os.environ.get("ORACLE_THREADS", min(os.cpu_count() or 1, 16)))
     rc = lib().oracle_replay(*args, C.c_uint32(ns), _p(hb, C.c_uint64), _p(hc, C.c_uint64),
                              C.c_uint32(plan), C.c_uint64(seed), C.c_uint32(R), C.c_uint32(flags),
                              C.c_int(nthreads), _p(E, C.c_int64), _p(E2, C.c_uint64),

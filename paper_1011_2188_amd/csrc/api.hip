@@ -1,0 +1,864 @@
+// Host runtime of libfdc.so: the C ABI declared in include/fdc.h.
+//
+// Owns the device state (track database, material table, plans with their
+// tallies and spots), validates every argument before touching the GPU, builds
+// the per-run work table (spot history ranges cut into 64-history wave units)
+// and enqueues the kernels on the caller's stream.
+#include "fdc.h"
+#include "fdc_device.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <limits>
+#include <new>
+#include <string>
+#include <vector>
+
+using namespace fdc;
+
+namespace {
+
+struct PlanHost {
+    int n[3] = {0, 0, 0};
+    float vox[3] = {0, 0, 0};
+    float org[3] = {0, 0, 0};
+    size_t nvox = 0;
+    uint16_t *idx = nullptr;
+    unsigned long long *E = nullptr;
+    unsigned long long *E2 = nullptr;
+    unsigned long long *acc = nullptr;      // incident, escaped, deposited scratch
+    std::vector<fdc_spot> spots;
+    std::vector<uint64_t> h_next;
+    uint64_t n_hist = 0;
+    bool var_complete = true;
+};
+
+// the default material table: synthetic piecewise-linear constants
+const double kDefaultTable[4][4] = {
+    // hu, rho, rsp, rscp
+    {-1000.0, 0.0012, 0.0011, 0.0012},
+    {0.0, 1.0, 1.0, 1.0},
+    {1000.0, 1.6, 1.5, 2.16},
+    {3071.0, 2.84, 2.64, 3.834},
+};
+
+} // namespace
+
+struct fdc_ctx {
+    int device = 0;
+    bool dry = false;                // no device: validation and host bookkeeping only
+    uint64_t seed = 0;
+    uint32_t R = 64;
+    int cus = 256;
+    std::string err;
+
+    fdc_alloc_fn alloc = nullptr;
+    fdc_free_fn freef = nullptr;
+    void *user = nullptr;
+    size_t live_allocs = 0;
+
+    // track database
+    float4 *steps = nullptr;
+    unsigned long long *track_off = nullptr;
+    long long *track_T = nullptr;
+    uint32_t *bin_first = nullptr;
+    std::vector<float> bin_E;
+    std::vector<uint32_t> bin_first_h;
+    uint32_t n_tracks = 0, n_bins = 0;
+
+    // material table
+    std::vector<double> table;   // rows of (hu, rho, rsp, rscp)
+    double vacuum_below = -990.0;
+    float2 *lut = nullptr;
+    float *rho_lut = nullptr;
+
+    // plans and spots
+    std::vector<PlanHost> plans;
+    DevPlan *d_plans = nullptr;
+    size_t d_plans_cap = 0;
+    bool plans_dirty = true;
+    DevSpot *d_spots = nullptr;
+    size_t d_spots_cap = 0;
+    std::vector<uint32_t> spot_base;
+    bool spots_dirty = true;
+
+    // per-run work table
+    WorkItem *d_items = nullptr;
+    WorkItem *h_items = nullptr;     // pinned staging
+    size_t items_cap = 0;
+    hipEvent_t items_ev = nullptr;
+    bool items_ev_pending = false;
+    unsigned long long *d_queue = nullptr;
+
+    // read-back scratch
+    double *d_dose = nullptr, *d_var = nullptr;
+    size_t dose_cap = 0;
+
+    fdc_launch_config cfg{};
+};
+
+namespace {
+
+int fail(fdc_ctx *c, int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (c) c->err = buf;
+    return code;
+}
+
+#define HIPCHK(expr)                                                                      \
+    do {                                                                                  \
+        hipError_t e_ = (expr);                                                           \
+        if (e_ != hipSuccess) return fail(ctx, FDC_E_HIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+void *dalloc(fdc_ctx *ctx, size_t bytes)
+{
+    if (bytes == 0) bytes = 256;
+    void *p = nullptr;
+    if (ctx->alloc) {
+        p = ctx->alloc(bytes, ctx->user);
+    } else if (hipMalloc(&p, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        p = nullptr;
+    }
+    if (p) ctx->live_allocs++;
+    return p;
+}
+
+void dfree(fdc_ctx *ctx, void *p)
+{
+    if (!p) return;
+    if (ctx->freef) ctx->freef(p, ctx->user);
+    else (void)hipFree(p);
+    ctx->live_allocs--;
+}
+
+template <class T> T *dalloc_n(fdc_ctx *ctx, size_t n) { return (T *)dalloc(ctx, n * sizeof(T)); }
+
+hipStream_t S(void *s) { return (hipStream_t)s; }
+
+bool finite3(const float v[3]) { return std::isfinite(v[0]) && std::isfinite(v[1]) && std::isfinite(v[2]); }
+
+int rebuild_lut(fdc_ctx *ctx)
+{
+    const int n = (int)(ctx->table.size() / 4);
+    double *dt = dalloc_n<double>(ctx, ctx->table.size());
+    if (!dt) return fail(ctx, FDC_E_NOMEM, "material table: device allocation failed");
+    hipError_t e = hipMemcpy(dt, ctx->table.data(), ctx->table.size() * sizeof(double), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = launch_build_lut(dt, n, ctx->vacuum_below, ctx->lut, ctx->rho_lut, nullptr);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    dfree(ctx, dt);
+    if (e != hipSuccess) return fail(ctx, FDC_E_HIP, "material table: %s", hipGetErrorString(e));
+    return FDC_OK;
+}
+
+// right-handed lateral axes (e1, e2) of a unit direction d; d = +z gives (x, y)
+void field_frame(const double d[3], double e1[3], double e2[3])
+{
+    double a[3] = {0.0, 0.0, 1.0};
+    if (std::fabs(d[2]) >= 0.9) { a[0] = 1.0; a[2] = 0.0; }
+    e2[0] = d[1] * a[2] - d[2] * a[1];
+    e2[1] = d[2] * a[0] - d[0] * a[2];
+    e2[2] = d[0] * a[1] - d[1] * a[0];
+    const double l = std::sqrt(e2[0] * e2[0] + e2[1] * e2[1] + e2[2] * e2[2]);
+    for (int q = 0; q < 3; ++q) e2[q] /= l;
+    e1[0] = e2[1] * d[2] - e2[2] * d[1];
+    e1[1] = e2[2] * d[0] - e2[0] * d[2];
+    e1[2] = e2[0] * d[1] - e2[1] * d[0];
+}
+
+// spot -> bin (smallest bin energy >= spot energy); -1 if out of range
+int spot_bin(const fdc_ctx *ctx, float E)
+{
+    if (ctx->n_bins == 0 || !(E >= ctx->bin_E.front()) || !(E <= ctx->bin_E.back())) return -1;
+    int b = 0;
+    while (ctx->bin_E[b] < E) ++b;
+    return b;
+}
+
+int check_spot(fdc_ctx *ctx, const fdc_spot &s)
+{
+    if (!finite3(s.pos_cm) || !finite3(s.dir) || !std::isfinite(s.energy_MeV) || !std::isfinite(s.sigma_cm))
+        return fail(ctx, FDC_E_ARG, "spot has a non-finite field");
+    if (s.sigma_cm < 0.f) return fail(ctx, FDC_E_ARG, "spot sigma is negative");
+    const double l = std::sqrt((double)s.dir[0] * s.dir[0] + (double)s.dir[1] * s.dir[1] + (double)s.dir[2] * s.dir[2]);
+    if (!(l > 1e-6)) return fail(ctx, FDC_E_ARG, "spot direction is zero");
+    if (spot_bin(ctx, s.energy_MeV) < 0)
+        return fail(ctx, FDC_E_RANGE, "spot energy %g MeV outside the database bins [%g, %g]", s.energy_MeV,
+                    ctx->n_bins ? ctx->bin_E.front() : 0.f, ctx->n_bins ? ctx->bin_E.back() : 0.f);
+    return FDC_OK;
+}
+
+DevSpot make_dev_spot(const fdc_ctx *ctx, const fdc_spot &s, uint32_t plan, uint32_t idx)
+{
+    DevSpot d{};
+    double dir[3] = {s.dir[0], s.dir[1], s.dir[2]};
+    const double l = std::sqrt(dir[0] * dir[0] + dir[1] * dir[1] + dir[2] * dir[2]);
+    for (int q = 0; q < 3; ++q) dir[q] /= l;
+    double e1[3], e2[3];
+    field_frame(dir, e1, e2);
+    for (int q = 0; q < 3; ++q) {
+        d.pos[q] = s.pos_cm[q];
+        d.e1[q] = e1[q];
+        d.e2[q] = e2[q];
+        d.d[q] = dir[q];
+        d.m[3 * q + 0] = (float)e1[q];
+        d.m[3 * q + 1] = (float)e2[q];
+        d.m[3 * q + 2] = (float)dir[q];
+    }
+    d.sigma = s.sigma_cm;
+    const int b = spot_bin(ctx, s.energy_MeV);
+    d.bin = (uint32_t)b;
+    d.plan = plan;
+    d.spot = idx;
+    d.skip = to_fp(ctx->bin_E[b]) - to_fp(s.energy_MeV);
+    return d;
+}
+
+int ensure_spots(fdc_ctx *ctx)
+{
+    if (!ctx->spots_dirty) return FDC_OK;
+    std::vector<DevSpot> all;
+    ctx->spot_base.assign(ctx->plans.size() + 1, 0);
+    for (size_t p = 0; p < ctx->plans.size(); ++p) {
+        ctx->spot_base[p] = (uint32_t)all.size();
+        for (size_t j = 0; j < ctx->plans[p].spots.size(); ++j) {
+            const fdc_spot &s = ctx->plans[p].spots[j];
+            int rc = check_spot(ctx, s);
+            if (rc) return rc;
+            all.push_back(make_dev_spot(ctx, s, (uint32_t)p, (uint32_t)j));
+        }
+    }
+    ctx->spot_base[ctx->plans.size()] = (uint32_t)all.size();
+    if (all.size() > ctx->d_spots_cap) {
+        DevSpot *n = dalloc_n<DevSpot>(ctx, all.size());
+        if (!n) return fail(ctx, FDC_E_NOMEM, "spot table: device allocation failed");
+        HIPCHK(hipDeviceSynchronize());
+        dfree(ctx, ctx->d_spots);
+        ctx->d_spots = n;
+        ctx->d_spots_cap = all.size();
+    }
+    if (!all.empty()) {
+        HIPCHK(hipDeviceSynchronize());
+        HIPCHK(hipMemcpy(ctx->d_spots, all.data(), all.size() * sizeof(DevSpot), hipMemcpyHostToDevice));
+    }
+    ctx->spots_dirty = false;
+    return FDC_OK;
+}
+
+int ensure_plans(fdc_ctx *ctx)
+{
+    if (!ctx->plans_dirty) return FDC_OK;
+    std::vector<DevPlan> all(ctx->plans.size());
+    for (size_t p = 0; p < ctx->plans.size(); ++p) {
+        const PlanHost &P = ctx->plans[p];
+        DevPlan &d = all[p];
+        d.idx = P.idx;
+        d.E = P.E;
+        d.E2 = P.E2;
+        d.acc = P.acc;
+        for (int q = 0; q < 3; ++q) {
+            d.n[q] = P.n[q];
+            d.vox[q] = P.vox[q];
+            d.org[q] = P.org[q];
+            d.vox_d[q] = P.vox[q];
+            d.org_d[q] = P.org[q];
+        }
+    }
+    if (all.size() > ctx->d_plans_cap) {
+        const size_t cap = std::max<size_t>(all.size(), 2 * ctx->d_plans_cap);
+        DevPlan *n = dalloc_n<DevPlan>(ctx, cap);
+        if (!n) return fail(ctx, FDC_E_NOMEM, "plan table: device allocation failed");
+        HIPCHK(hipDeviceSynchronize());
+        dfree(ctx, ctx->d_plans);
+        ctx->d_plans = n;
+        ctx->d_plans_cap = cap;
+    }
+    HIPCHK(hipDeviceSynchronize());
+    HIPCHK(hipMemcpy(ctx->d_plans, all.data(), all.size() * sizeof(DevPlan), hipMemcpyHostToDevice));
+    ctx->plans_dirty = false;
+    return FDC_OK;
+}
+
+int ensure_items(fdc_ctx *ctx, size_t n, hipStream_t s)
+{
+    if (ctx->items_ev_pending) {
+        HIPCHK(hipEventSynchronize(ctx->items_ev));
+        ctx->items_ev_pending = false;
+    }
+    if (n <= ctx->items_cap) return FDC_OK;
+    const size_t cap = std::max<size_t>(n, 2 * ctx->items_cap);
+    WorkItem *d = dalloc_n<WorkItem>(ctx, cap);
+    if (!d) return fail(ctx, FDC_E_NOMEM, "work table: device allocation failed");
+    WorkItem *h = nullptr;
+    if (hipHostMalloc((void **)&h, cap * sizeof(WorkItem), hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        dfree(ctx, d);
+        return fail(ctx, FDC_E_NOMEM, "work table: pinned host allocation failed");
+    }
+    HIPCHK(hipStreamSynchronize(s));      // the old table may still be read by a kernel
+    dfree(ctx, ctx->d_items);
+    if (ctx->h_items) (void)hipHostFree(ctx->h_items);
+    ctx->d_items = d;
+    ctx->h_items = h;
+    ctx->items_cap = cap;
+    return FDC_OK;
+}
+
+bool valid_plan(const fdc_ctx *ctx, int32_t plan) { return plan >= 0 && (size_t)plan < ctx->plans.size(); }
+
+TransportArgs base_args(const fdc_ctx *ctx)
+{
+    TransportArgs a{};
+    a.steps = ctx->steps;
+    a.track_off = ctx->track_off;
+    a.track_T = ctx->track_T;
+    a.bin_first = ctx->bin_first;
+    a.plans = ctx->d_plans;
+    a.spots = ctx->d_spots;
+    a.items = ctx->d_items;
+    a.lut = ctx->lut;
+    a.seed_lo = (uint32_t)ctx->seed;
+    a.seed_hi = (uint32_t)(ctx->seed >> 32);
+    a.R = ctx->R;
+    return a;
+}
+
+} // namespace
+
+extern "C" {
+
+int fdc_create(fdc_ctx **out, int hip_device, uint64_t seed, uint32_t reuse_R)
+{
+    if (!out) return FDC_E_ARG;
+    *out = nullptr;
+    if (reuse_R == 0) return FDC_E_ARG;
+    if (hip_device == FDC_NO_DEVICE) {
+        fdc_ctx *dry = new (std::nothrow) fdc_ctx();
+        if (!dry) return FDC_E_NOMEM;
+        dry->dry = true;
+        dry->device = -1;
+        dry->seed = seed;
+        dry->R = reuse_R;
+        dry->cfg.waves_per_block = 4;
+        *out = dry;
+        return FDC_OK;
+    }
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || hip_device < 0 || hip_device >= ndev) {
+        (void)hipGetLastError();
+        return FDC_E_HIP;
+    }
+    fdc_ctx *ctx = new (std::nothrow) fdc_ctx();
+    if (!ctx) return FDC_E_NOMEM;
+    ctx->device = hip_device;
+    ctx->seed = seed;
+    ctx->R = reuse_R;
+    ctx->cfg.waves_per_block = 4;
+    ctx->cfg.blocks_per_cu = 0;
+    if (hipSetDevice(hip_device) != hipSuccess) { delete ctx; return FDC_E_HIP; }
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, hip_device) == hipSuccess) ctx->cus = prop.multiProcessorCount;
+    if (hipEventCreateWithFlags(&ctx->items_ev, hipEventDisableTiming) != hipSuccess) { delete ctx; return FDC_E_HIP; }
+    *out = ctx;
+    return FDC_OK;
+}
+
+int fdc_destroy(fdc_ctx *ctx)
+{
+    if (!ctx) return FDC_E_ARG;
+    if (ctx->dry) { delete ctx; return FDC_OK; }
+    (void)hipSetDevice(ctx->device);
+    (void)hipDeviceSynchronize();
+    for (PlanHost &P : ctx->plans) {
+        dfree(ctx, P.idx); dfree(ctx, P.E); dfree(ctx, P.E2); dfree(ctx, P.acc);
+    }
+    dfree(ctx, ctx->steps); dfree(ctx, ctx->track_off); dfree(ctx, ctx->track_T); dfree(ctx, ctx->bin_first);
+    dfree(ctx, ctx->lut); dfree(ctx, ctx->rho_lut);
+    dfree(ctx, ctx->d_plans); dfree(ctx, ctx->d_spots); dfree(ctx, ctx->d_items); dfree(ctx, ctx->d_queue);
+    dfree(ctx, ctx->d_dose); dfree(ctx, ctx->d_var);
+    if (ctx->h_items) (void)hipHostFree(ctx->h_items);
+    if (ctx->items_ev) (void)hipEventDestroy(ctx->items_ev);
+    delete ctx;
+    return FDC_OK;
+}
+
+const char *fdc_last_error(const fdc_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+int fdc_set_allocator(fdc_ctx *ctx, fdc_alloc_fn alloc, fdc_free_fn free_fn, void *user)
+{
+    if (!ctx) return FDC_E_ARG;
+    if ((alloc == nullptr) != (free_fn == nullptr)) return fail(ctx, FDC_E_ARG, "give both allocator hooks or none");
+    if (ctx->live_allocs) return fail(ctx, FDC_E_STATE, "device memory already allocated");
+    ctx->alloc = alloc;
+    ctx->freef = free_fn;
+    ctx->user = user;
+    return FDC_OK;
+}
+
+static int ensure_table(fdc_ctx *ctx)
+{
+    if (ctx->lut) return FDC_OK;
+    if (ctx->table.empty()) {
+        for (auto &row : kDefaultTable) ctx->table.insert(ctx->table.end(), row, row + 4);
+        ctx->vacuum_below = -990.0;
+    }
+    ctx->lut = dalloc_n<float2>(ctx, kLutSize);
+    ctx->rho_lut = dalloc_n<float>(ctx, kLutSize);
+    if (!ctx->lut || !ctx->rho_lut) {
+        dfree(ctx, ctx->lut); dfree(ctx, ctx->rho_lut);
+        ctx->lut = nullptr; ctx->rho_lut = nullptr;
+        return fail(ctx, FDC_E_NOMEM, "material table: device allocation failed");
+    }
+    return rebuild_lut(ctx);
+}
+
+int fdc_set_hu_table(fdc_ctx *ctx, const float *hu_pts, const float *rho, const float *rsp, const float *rscp,
+                     int n_pts, float vacuum_below_hu)
+{
+    if (!ctx) return FDC_E_ARG;
+    if (!hu_pts || !rho || !rsp || !rscp) return fail(ctx, FDC_E_ARG, "material table: NULL array");
+    if (n_pts < 2 || n_pts > kMaxTablePts) return fail(ctx, FDC_E_ARG, "material table: n_pts must be 2..%d", kMaxTablePts);
+    if (!std::isfinite(vacuum_below_hu)) return fail(ctx, FDC_E_ARG, "material table: vacuum threshold not finite");
+    for (int i = 0; i < n_pts; ++i) {
+        if (!std::isfinite(hu_pts[i]) || !std::isfinite(rho[i]) || !std::isfinite(rsp[i]) || !std::isfinite(rscp[i]))
+            return fail(ctx, FDC_E_ARG, "material table: non-finite value at point %d", i);
+        if (rho[i] < 0.f || rsp[i] < 0.f || rscp[i] < 0.f)
+            return fail(ctx, FDC_E_ARG, "material table: negative value at point %d", i);
+        if (i && !(hu_pts[i] > hu_pts[i - 1])) return fail(ctx, FDC_E_ARG, "material table: HU not increasing");
+    }
+    if (ctx->dry) {
+        ctx->table.clear();
+        for (int i = 0; i < n_pts; ++i) {
+            ctx->table.push_back(hu_pts[i]); ctx->table.push_back(rho[i]);
+            ctx->table.push_back(rsp[i]); ctx->table.push_back(rscp[i]);
+        }
+        ctx->vacuum_below = vacuum_below_hu;
+        return FDC_OK;
+    }
+    HIPCHK(hipSetDevice(ctx->device));
+    std::vector<double> old = ctx->table;
+    const double old_vac = ctx->vacuum_below;
+    ctx->table.clear();
+    for (int i = 0; i < n_pts; ++i) {
+        ctx->table.push_back(hu_pts[i]); ctx->table.push_back(rho[i]);
+        ctx->table.push_back(rsp[i]); ctx->table.push_back(rscp[i]);
+    }
+    ctx->vacuum_below = vacuum_below_hu;
+    int rc = ctx->lut ? rebuild_lut(ctx) : ensure_table(ctx);
+    if (rc) { ctx->table = old; ctx->vacuum_below = old_vac; }
+    return rc;
+}
+
+int fdc_load_track_db(fdc_ctx *ctx, const fdc_step *steps, uint64_t n_steps, const uint64_t *track_off,
+                      uint32_t n_tracks, const float *bin_E, const uint32_t *bin_first, uint32_t n_bins,
+                      void *hip_stream)
+{
+    if (!ctx) return FDC_E_ARG;
+    if (!steps || !track_off || !bin_E || !bin_first) return fail(ctx, FDC_E_ARG, "track database: NULL array");
+    if (n_steps == 0 || n_tracks == 0 || n_bins == 0) return fail(ctx, FDC_E_ARG, "track database: zero count");
+    if (track_off[0] != 0 || track_off[n_tracks] != n_steps)
+        return fail(ctx, FDC_E_FORMAT, "track database: offsets must start at 0 and end at n_steps");
+    for (uint32_t t = 0; t < n_tracks; ++t)
+        if (!(track_off[t + 1] > track_off[t])) return fail(ctx, FDC_E_FORMAT, "track database: track %u empty or offsets not increasing", t);
+    if (bin_first[0] != 0 || bin_first[n_bins] != n_tracks)
+        return fail(ctx, FDC_E_FORMAT, "track database: bin_first must start at 0 and end at n_tracks");
+    for (uint32_t b = 0; b < n_bins; ++b) {
+        if (!(bin_first[b + 1] > bin_first[b])) return fail(ctx, FDC_E_FORMAT, "track database: bin %u empty", b);
+        if (!std::isfinite(bin_E[b]) || !(bin_E[b] > 0.f)) return fail(ctx, FDC_E_FORMAT, "track database: bad bin energy");
+        if (b && !(bin_E[b] > bin_E[b - 1])) return fail(ctx, FDC_E_FORMAT, "track database: bin energies not increasing");
+    }
+    for (uint64_t k = 0; k < n_steps; ++k) {
+        const fdc_step &s = steps[k];
+        if (!std::isfinite(s.dx_cm) || !std::isfinite(s.dE_MeV) || !std::isfinite(s.theta_rad) || !std::isfinite(s.phi_rad))
+            return fail(ctx, FDC_E_FORMAT, "track database: non-finite value in step %llu", (unsigned long long)k);
+        if (!(s.dx_cm > 0.f) || s.dE_MeV < 0.f || s.theta_rad < 0.f)
+            return fail(ctx, FDC_E_FORMAT, "track database: step %llu needs dx > 0, dE >= 0, theta >= 0", (unsigned long long)k);
+    }
+    if (ctx->dry) {
+        ctx->bin_E.assign(bin_E, bin_E + n_bins);
+        ctx->bin_first_h.assign(bin_first, bin_first + n_bins + 1);
+        ctx->n_tracks = n_tracks;
+        ctx->n_bins = n_bins;
+        ctx->spots_dirty = true;
+        return FDC_OK;
+    }
+    HIPCHK(hipSetDevice(ctx->device));
+    int rc = ensure_table(ctx);
+    if (rc) return rc;
+    float4 *d_steps = dalloc_n<float4>(ctx, n_steps);
+    unsigned long long *d_off = dalloc_n<unsigned long long>(ctx, (size_t)n_tracks + 1);
+    long long *d_T = dalloc_n<long long>(ctx, n_tracks);
+    uint32_t *d_bf = dalloc_n<uint32_t>(ctx, (size_t)n_bins + 1);
+    if (!d_steps || !d_off || !d_T || !d_bf) {
+        dfree(ctx, d_steps); dfree(ctx, d_off); dfree(ctx, d_T); dfree(ctx, d_bf);
+        return fail(ctx, FDC_E_NOMEM, "track database: device allocation of %llu bytes failed",
+                    (unsigned long long)(n_steps * sizeof(float4)));
+    }
+    hipStream_t s = S(hip_stream);
+    hipError_t e = hipMemcpyAsync(d_steps, steps, n_steps * sizeof(float4), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(d_off, track_off, ((size_t)n_tracks + 1) * 8, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(d_bf, bin_first, ((size_t)n_bins + 1) * 4, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = launch_track_energy(d_steps, d_off, d_T, n_tracks, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        dfree(ctx, d_steps); dfree(ctx, d_off); dfree(ctx, d_T); dfree(ctx, d_bf);
+        return fail(ctx, FDC_E_HIP, "track database upload: %s", hipGetErrorString(e));
+    }
+    HIPCHK(hipDeviceSynchronize());
+    dfree(ctx, ctx->steps); dfree(ctx, ctx->track_off); dfree(ctx, ctx->track_T); dfree(ctx, ctx->bin_first);
+    ctx->steps = d_steps;
+    ctx->track_off = d_off;
+    ctx->track_T = d_T;
+    ctx->bin_first = d_bf;
+    ctx->bin_E.assign(bin_E, bin_E + n_bins);
+    ctx->bin_first_h.assign(bin_first, bin_first + n_bins + 1);
+    ctx->n_tracks = n_tracks;
+    ctx->n_bins = n_bins;
+    ctx->spots_dirty = true;
+    return FDC_OK;
+}
+
+int fdc_load_phantom(fdc_ctx *ctx, int32_t *plan_out, const int16_t *hu, int nx, int ny, int nz,
+                     const float voxel_cm[3], const float origin_cm[3], void *hip_stream)
+{
+    if (!ctx) return FDC_E_ARG;
+    if (!plan_out || !hu || !voxel_cm || !origin_cm) return fail(ctx, FDC_E_ARG, "phantom: NULL argument");
+    if (nx <= 0 || ny <= 0 || nz <= 0) return fail(ctx, FDC_E_ARG, "phantom: dimensions must be positive");
+    const size_t nvox = (size_t)nx * ny * nz;
+    if (nvox >= (size_t(1) << 31)) return fail(ctx, FDC_E_ARG, "phantom: more than 2^31 voxels");
+    if (!finite3(voxel_cm) || !finite3(origin_cm) || !(voxel_cm[0] > 0.f) || !(voxel_cm[1] > 0.f) || !(voxel_cm[2] > 0.f))
+        return fail(ctx, FDC_E_ARG, "phantom: voxel sizes must be positive and finite");
+    if (ctx->plans.size() >= (1u << 27)) return fail(ctx, FDC_E_ARG, "phantom: too many plans");
+    PlanHost P;
+    P.n[0] = nx; P.n[1] = ny; P.n[2] = nz;
+    for (int q = 0; q < 3; ++q) { P.vox[q] = voxel_cm[q]; P.org[q] = origin_cm[q]; }
+    P.nvox = nvox;
+    if (ctx->dry) {
+        ctx->plans.push_back(std::move(P));
+        *plan_out = (int32_t)(ctx->plans.size() - 1);
+        return FDC_OK;
+    }
+    HIPCHK(hipSetDevice(ctx->device));
+    int rc = ensure_table(ctx);
+    if (rc) return rc;
+    int16_t *d_hu = dalloc_n<int16_t>(ctx, nvox);
+    P.idx = dalloc_n<uint16_t>(ctx, nvox);
+    P.E = dalloc_n<unsigned long long>(ctx, nvox);
+    P.E2 = dalloc_n<unsigned long long>(ctx, nvox);
+    P.acc = dalloc_n<unsigned long long>(ctx, 4);
+    if (!d_hu || !P.idx || !P.E || !P.E2 || !P.acc) {
+        dfree(ctx, d_hu); dfree(ctx, P.idx); dfree(ctx, P.E); dfree(ctx, P.E2); dfree(ctx, P.acc);
+        return fail(ctx, FDC_E_NOMEM, "phantom: device allocation failed (%zu voxels)", nvox);
+    }
+    hipStream_t s = S(hip_stream);
+    hipError_t e = hipMemcpyAsync(d_hu, hu, nvox * sizeof(int16_t), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = launch_hu_to_index(d_hu, P.idx, nvox, s);
+    if (e == hipSuccess) e = hipMemsetAsync(P.E, 0, nvox * 8, s);
+    if (e == hipSuccess) e = hipMemsetAsync(P.E2, 0, nvox * 8, s);
+    if (e == hipSuccess) e = hipMemsetAsync(P.acc, 0, 32, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    dfree(ctx, d_hu);
+    if (e != hipSuccess) {
+        dfree(ctx, P.idx); dfree(ctx, P.E); dfree(ctx, P.E2); dfree(ctx, P.acc);
+        return fail(ctx, FDC_E_HIP, "phantom upload: %s", hipGetErrorString(e));
+    }
+    ctx->plans.push_back(std::move(P));
+    ctx->plans_dirty = true;
+    ctx->spots_dirty = true;
+    *plan_out = (int32_t)(ctx->plans.size() - 1);
+    return FDC_OK;
+}
+
+int fdc_add_beam_spots(fdc_ctx *ctx, int32_t plan, const fdc_spot *spots, uint32_t n)
+{
+    if (!ctx) return FDC_E_ARG;
+    if (!valid_plan(ctx, plan)) return fail(ctx, FDC_E_ARG, "spots: no plan %d", plan);
+    if (n && !spots) return fail(ctx, FDC_E_ARG, "spots: NULL array");
+    if (ctx->n_bins == 0) return fail(ctx, FDC_E_STATE, "spots: load a track database first");
+    for (uint32_t i = 0; i < n; ++i) {
+        int rc = check_spot(ctx, spots[i]);
+        if (rc) return rc;
+    }
+    PlanHost &P = ctx->plans[plan];
+    P.spots.insert(P.spots.end(), spots, spots + n);
+    P.h_next.resize(P.spots.size(), 0);
+    ctx->spots_dirty = true;
+    return FDC_OK;
+}
+
+int fdc_run_histories(fdc_ctx *ctx, const int32_t *plans, uint32_t n_plans, uint32_t flags, void *hip_stream)
+{
+    if (!ctx) return FDC_E_ARG;
+    if (n_plans && !plans) return fail(ctx, FDC_E_ARG, "run: NULL plan list");
+    if (flags & ~(uint32_t)(FDC_RUN_VARIANCE | FDC_RUN_ROTATE_TRACKS)) return fail(ctx, FDC_E_ARG, "run: unknown flag");
+    if (ctx->n_bins == 0) return fail(ctx, FDC_E_STATE, "run: no track database loaded");
+    std::vector<char> seen(ctx->plans.size(), 0);
+    for (uint32_t i = 0; i < n_plans; ++i) {
+        if (!valid_plan(ctx, plans[i])) return fail(ctx, FDC_E_ARG, "run: no plan %d", plans[i]);
+        if (seen[plans[i]]++) return fail(ctx, FDC_E_ARG, "run: plan %d listed twice", plans[i]);
+    }
+    // overflow guard: every history deposits at most the largest bin energy
+    const double emax = (double)to_fp(ctx->bin_E.back());
+    for (uint32_t i = 0; i < n_plans; ++i) {
+        const PlanHost &P = ctx->plans[plans[i]];
+        double nh = (double)P.n_hist;
+        for (const fdc_spot &s : P.spots) nh += (double)s.n_histories;
+        if (nh * emax >= 9.2e18) return fail(ctx, FDC_E_OVERFLOW, "run: plan %d would exceed the int64 tally", plans[i]);
+    }
+    if (ctx->dry) {
+        for (uint32_t i = 0; i < n_plans; ++i) {
+            PlanHost &P = ctx->plans[plans[i]];
+            for (size_t j = 0; j < P.spots.size(); ++j) {
+                P.h_next[j] += P.spots[j].n_histories;
+                P.n_hist += P.spots[j].n_histories;
+                if (P.spots[j].n_histories && !(flags & FDC_RUN_VARIANCE)) P.var_complete = false;
+            }
+        }
+        return FDC_OK;
+    }
+    HIPCHK(hipSetDevice(ctx->device));
+    int rc = ensure_plans(ctx);
+    if (!rc) rc = ensure_spots(ctx);
+    if (rc) return rc;
+    hipStream_t s = S(hip_stream);
+    size_t n_items = 0;
+    for (uint32_t i = 0; i < n_plans; ++i)
+        for (const fdc_spot &sp : ctx->plans[plans[i]].spots) n_items += sp.n_histories > 0;
+    if (n_items == 0) return FDC_OK;
+    rc = ensure_items(ctx, n_items, s);
+    if (rc) return rc;
+    unsigned long long units = 0;
+    size_t k = 0;
+    for (uint32_t i = 0; i < n_plans; ++i) {
+        const PlanHost &P = ctx->plans[plans[i]];
+        for (size_t j = 0; j < P.spots.size(); ++j) {
+            const uint64_t n = P.spots[j].n_histories;
+            if (!n) continue;
+            WorkItem &w = ctx->h_items[k++];
+            w.h0 = P.h_next[j];
+            w.h_end = P.h_next[j] + n;
+            w.unit0 = units;
+            w.gspot = ctx->spot_base[plans[i]] + (uint32_t)j;
+            w.pad = 0;
+            units += (w.h_end - 1) / kWave - w.h0 / kWave + 1;
+        }
+    }
+    HIPCHK(hipMemcpyAsync(ctx->d_items, ctx->h_items, n_items * sizeof(WorkItem), hipMemcpyHostToDevice, s));
+    HIPCHK(hipEventRecord(ctx->items_ev, s));
+    ctx->items_ev_pending = true;
+
+    TransportArgs a = base_args(ctx);
+    a.n_items = (uint32_t)n_items;
+    a.n_units = units;
+    a.flags = flags;
+    const uint32_t wpb = ctx->cfg.waves_per_block;
+    uint32_t grid;
+    if (ctx->cfg.blocks_per_cu) {
+        if (!ctx->d_queue) {
+            ctx->d_queue = dalloc_n<unsigned long long>(ctx, 1);
+            if (!ctx->d_queue) return fail(ctx, FDC_E_NOMEM, "run: queue allocation failed");
+        }
+        HIPCHK(hipMemsetAsync(ctx->d_queue, 0, 8, s));
+        a.queue = ctx->d_queue;
+        grid = ctx->cfg.blocks_per_cu * (uint32_t)ctx->cus;
+    } else {
+        const unsigned long long g = (units + wpb - 1) / wpb;
+        if (g > 0x7fffffffull) return fail(ctx, FDC_E_ARG, "run: too many work units for one launch");
+        grid = (uint32_t)g;
+    }
+    HIPCHK(launch_transport(a, wpb, grid, (flags & FDC_RUN_VARIANCE) != 0, false, s));
+    for (uint32_t i = 0; i < n_plans; ++i) {
+        PlanHost &P = ctx->plans[plans[i]];
+        for (size_t j = 0; j < P.spots.size(); ++j) {
+            P.h_next[j] += P.spots[j].n_histories;
+            P.n_hist += P.spots[j].n_histories;
+            if (P.spots[j].n_histories && !(flags & FDC_RUN_VARIANCE)) P.var_complete = false;
+        }
+    }
+    return FDC_OK;
+}
+
+int fdc_reset_plan(fdc_ctx *ctx, int32_t plan, int rewind, void *hip_stream)
+{
+    if (!ctx) return FDC_E_ARG;
+    if (!valid_plan(ctx, plan)) return fail(ctx, FDC_E_ARG, "reset: no plan %d", plan);
+    PlanHost &P = ctx->plans[plan];
+    if (!ctx->dry) {
+        HIPCHK(hipSetDevice(ctx->device));
+        hipStream_t s = S(hip_stream);
+        HIPCHK(hipMemsetAsync(P.E, 0, P.nvox * 8, s));
+        HIPCHK(hipMemsetAsync(P.E2, 0, P.nvox * 8, s));
+        HIPCHK(hipMemsetAsync(P.acc, 0, 32, s));
+    }
+    P.n_hist = 0;
+    P.var_complete = true;
+    if (rewind) std::fill(P.h_next.begin(), P.h_next.end(), 0);
+    return FDC_OK;
+}
+
+int fdc_compute_dose(fdc_ctx *ctx, int32_t plan, double *dose_dev, double *var_dev, void *hip_stream)
+{
+    if (!ctx) return FDC_E_ARG;
+    if (!valid_plan(ctx, plan)) return fail(ctx, FDC_E_ARG, "dose: no plan %d", plan);
+    const PlanHost &P = ctx->plans[plan];
+    if (P.n_hist == 0) return fail(ctx, FDC_E_STATE, "dose: no histories run on plan %d", plan);
+    if (var_dev && !P.var_complete)
+        return fail(ctx, FDC_E_STATE, "dose: variance asked but a run without FDC_RUN_VARIANCE touched plan %d", plan);
+    if (!dose_dev && !var_dev) return FDC_OK;
+    if (ctx->dry) return fail(ctx, FDC_E_STATE, "dose: context has no device");
+    HIPCHK(hipSetDevice(ctx->device));
+    const double vol = (double)P.vox[0] * (double)P.vox[1] * (double)P.vox[2];
+    HIPCHK(launch_dose(nullptr, P.idx, P.E, P.E2, ctx->lut, ctx->rho_lut, P.nvox, vol, (double)P.n_hist,
+                       dose_dev, var_dev, S(hip_stream)));
+    return FDC_OK;
+}
+
+int fdc_read_dose_and_variance(fdc_ctx *ctx, int32_t plan, double *dose, double *var, int64_t *raw_E,
+                               uint64_t *raw_E2, fdc_summary *sum, void *hip_stream)
+{
+    if (!ctx) return FDC_E_ARG;
+    if (!valid_plan(ctx, plan)) return fail(ctx, FDC_E_ARG, "read: no plan %d", plan);
+    PlanHost &P = ctx->plans[plan];
+    if ((dose || var) && P.n_hist == 0) return fail(ctx, FDC_E_STATE, "read: no histories run on plan %d", plan);
+    if (var && !P.var_complete)
+        return fail(ctx, FDC_E_STATE, "read: variance asked but a run without FDC_RUN_VARIANCE touched plan %d", plan);
+    if (ctx->dry) return fail(ctx, FDC_E_STATE, "read: context has no device");
+    HIPCHK(hipSetDevice(ctx->device));
+    hipStream_t s = S(hip_stream);
+    if (dose || var) {
+        if (P.nvox > ctx->dose_cap) {
+            double *d1 = dalloc_n<double>(ctx, P.nvox), *d2 = dalloc_n<double>(ctx, P.nvox);
+            if (!d1 || !d2) { dfree(ctx, d1); dfree(ctx, d2); return fail(ctx, FDC_E_NOMEM, "read: scratch allocation failed"); }
+            HIPCHK(hipStreamSynchronize(s));
+            dfree(ctx, ctx->d_dose); dfree(ctx, ctx->d_var);
+            ctx->d_dose = d1; ctx->d_var = d2; ctx->dose_cap = P.nvox;
+        }
+        int rc = fdc_compute_dose(ctx, plan, dose ? ctx->d_dose : nullptr, var ? ctx->d_var : nullptr, hip_stream);
+        if (rc) return rc;
+        if (dose) HIPCHK(hipMemcpyAsync(dose, ctx->d_dose, P.nvox * 8, hipMemcpyDeviceToHost, s));
+        if (var) HIPCHK(hipMemcpyAsync(var, ctx->d_var, P.nvox * 8, hipMemcpyDeviceToHost, s));
+    }
+    if (raw_E) HIPCHK(hipMemcpyAsync(raw_E, P.E, P.nvox * 8, hipMemcpyDeviceToHost, s));
+    if (raw_E2) HIPCHK(hipMemcpyAsync(raw_E2, P.E2, P.nvox * 8, hipMemcpyDeviceToHost, s));
+    unsigned long long acc[3] = {0, 0, 0};
+    if (sum) {
+        HIPCHK(hipMemsetAsync(P.acc + 2, 0, 8, s));
+        HIPCHK(launch_sum_i64(P.E, P.nvox, P.acc + 2, s));
+        HIPCHK(hipMemcpyAsync(acc, P.acc, 24, hipMemcpyDeviceToHost, s));
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    if (sum) {
+        sum->n_histories = P.n_hist;
+        sum->incident_fp = (int64_t)acc[0];
+        sum->escaped_fp = (int64_t)acc[1];
+        sum->deposited_fp = (int64_t)acc[2];
+    }
+    return FDC_OK;
+}
+
+int fdc_debug_endpoints(fdc_ctx *ctx, int32_t plan, uint32_t spot, uint64_t h0, uint32_t n, uint32_t flags,
+                        float *xyz_out, int32_t *reason_out, void *hip_stream)
+{
+    if (!ctx) return FDC_E_ARG;
+    if (!valid_plan(ctx, plan)) return fail(ctx, FDC_E_ARG, "endpoints: no plan %d", plan);
+    if (spot >= ctx->plans[plan].spots.size()) return fail(ctx, FDC_E_ARG, "endpoints: no spot %u", spot);
+    if (n == 0) return FDC_OK;
+    if (!xyz_out || !reason_out) return fail(ctx, FDC_E_ARG, "endpoints: NULL output");
+    if (flags & ~(uint32_t)(FDC_RUN_VARIANCE | FDC_RUN_ROTATE_TRACKS)) return fail(ctx, FDC_E_ARG, "endpoints: unknown flag");
+    if (ctx->n_bins == 0) return fail(ctx, FDC_E_STATE, "endpoints: no track database loaded");
+    if (ctx->dry) return fail(ctx, FDC_E_STATE, "endpoints: context has no device");
+    HIPCHK(hipSetDevice(ctx->device));
+    int rc = ensure_plans(ctx);
+    if (!rc) rc = ensure_spots(ctx);
+    if (rc) return rc;
+    hipStream_t s = S(hip_stream);
+    float *d_xyz = dalloc_n<float>(ctx, 3 * (size_t)n);
+    int *d_reason = dalloc_n<int>(ctx, n);
+    WorkItem *d_item = dalloc_n<WorkItem>(ctx, 1);
+    if (!d_xyz || !d_reason || !d_item) {
+        dfree(ctx, d_xyz); dfree(ctx, d_reason); dfree(ctx, d_item);
+        return fail(ctx, FDC_E_NOMEM, "endpoints: allocation failed");
+    }
+    WorkItem w{h0, h0 + n, 0, ctx->spot_base[plan] + spot, 0};
+    const unsigned long long units = (w.h_end - 1) / kWave - w.h0 / kWave + 1;
+    TransportArgs a = base_args(ctx);
+    a.items = d_item;
+    a.n_items = 1;
+    a.n_units = units;
+    a.flags = flags;
+    a.ep_xyz = d_xyz;
+    a.ep_reason = d_reason;
+    hipError_t e = hipMemcpyAsync(d_item, &w, sizeof w, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = launch_transport(a, 4, (uint32_t)((units + 3) / 4), false, true, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(xyz_out, d_xyz, 12 * (size_t)n, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(reason_out, d_reason, 4 * (size_t)n, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    dfree(ctx, d_xyz); dfree(ctx, d_reason); dfree(ctx, d_item);
+    if (e != hipSuccess) return fail(ctx, FDC_E_HIP, "endpoints: %s", hipGetErrorString(e));
+    return FDC_OK;
+}
+
+int fdc_debug_philox(fdc_ctx *ctx, const uint32_t *ctr, uint32_t *out, uint32_t n, void *hip_stream)
+{
+    if (!ctx) return FDC_E_ARG;
+    if (n == 0) return FDC_OK;
+    if (!ctr || !out) return fail(ctx, FDC_E_ARG, "philox: NULL array");
+    if (ctx->dry) return fail(ctx, FDC_E_STATE, "philox: context has no device");
+    HIPCHK(hipSetDevice(ctx->device));
+    hipStream_t s = S(hip_stream);
+    uint4 *d_c = dalloc_n<uint4>(ctx, n), *d_o = dalloc_n<uint4>(ctx, n);
+    if (!d_c || !d_o) { dfree(ctx, d_c); dfree(ctx, d_o); return fail(ctx, FDC_E_NOMEM, "philox: allocation failed"); }
+    hipError_t e = hipMemcpyAsync(d_c, ctr, 16 * (size_t)n, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = launch_philox_test(d_c, d_o, n, (uint32_t)ctx->seed, (uint32_t)(ctx->seed >> 32), s);
+    if (e == hipSuccess) e = hipMemcpyAsync(out, d_o, 16 * (size_t)n, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    dfree(ctx, d_c); dfree(ctx, d_o);
+    if (e != hipSuccess) return fail(ctx, FDC_E_HIP, "philox: %s", hipGetErrorString(e));
+    return FDC_OK;
+}
+
+int fdc_debug_material(fdc_ctx *ctx, float *rsp_out, float *g_out, float *rho_out, void *hip_stream)
+{
+    if (!ctx) return FDC_E_ARG;
+    if (!rsp_out || !g_out || !rho_out) return fail(ctx, FDC_E_ARG, "material: NULL output");
+    if (ctx->dry) return fail(ctx, FDC_E_STATE, "material: context has no device");
+    HIPCHK(hipSetDevice(ctx->device));
+    int rc = ensure_table(ctx);
+    if (rc) return rc;
+    std::vector<float2> l(kLutSize);
+    hipStream_t s = S(hip_stream);
+    HIPCHK(hipMemcpyAsync(l.data(), ctx->lut, sizeof(float2) * kLutSize, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(rho_out, ctx->rho_lut, sizeof(float) * kLutSize, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    for (int i = 0; i < kLutSize; ++i) { rsp_out[i] = l[i].x; g_out[i] = l[i].y; }
+    return FDC_OK;
+}
+
+int fdc_set_launch_config(fdc_ctx *ctx, const fdc_launch_config *cfg)
+{
+    if (!ctx) return FDC_E_ARG;
+    if (!cfg) return fail(ctx, FDC_E_ARG, "launch config: NULL");
+    if (cfg->waves_per_block < 1 || cfg->waves_per_block > 16)
+        return fail(ctx, FDC_E_ARG, "launch config: waves_per_block must be 1..16");
+    if (cfg->blocks_per_cu > 64) return fail(ctx, FDC_E_ARG, "launch config: blocks_per_cu must be 0..64");
+    ctx->cfg = *cfg;
+    return FDC_OK;
+}
+
+int fdc_device_cus(fdc_ctx *ctx, int *cus)
+{
+    if (!ctx || !cus) return FDC_E_ARG;
+    *cus = ctx->cus;
+    return FDC_OK;
+}
+
+} // extern "C"

@@ -1,0 +1,149 @@
+// Set-up and finishing kernels: material table, HU -> table index, track
+// energies, dose and Eq. (2) variance, integer reductions, Philox test.
+#include "fdc_device.h"
+
+namespace fdc {
+
+namespace {
+
+// pts: n_pts rows of (hu, rho, rsp, rscp); piecewise linear, clamped at the ends
+__device__ double table_value(const double *pts, int n_pts, int col, double h)
+{
+    if (h <= pts[0]) return pts[col];
+    if (h >= pts[4 * (n_pts - 1)]) return pts[4 * (n_pts - 1) + col];
+    int j = 0;
+    while (!(h < pts[4 * (j + 1)])) ++j;
+    const double h0 = pts[4 * j], h1 = pts[4 * (j + 1)];
+    const double v0 = pts[4 * j + col], v1 = pts[4 * (j + 1) + col];
+    return v0 + (v1 - v0) * (h - h0) / (h1 - h0);
+}
+
+__global__ void build_lut_kernel(const double *pts, int n_pts, double vacuum_below, float2 *lut,
+                                 float *rho)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= kLutSize) return;
+    const double h = (double)(i + kHuMin);
+    rho[i] = (float)table_value(pts, n_pts, 1, h);
+    if (h < vacuum_below) {
+        lut[i] = make_float2(0.f, 0.f);
+        return;
+    }
+    const double s = table_value(pts, n_pts, 2, h);
+    const double c = table_value(pts, n_pts, 3, h);
+    lut[i] = s > 0.0 ? make_float2((float)s, (float)(c / s)) : make_float2(0.f, 0.f);
+}
+
+__global__ void hu_to_index_kernel(const int16_t *__restrict__ hu, uint16_t *__restrict__ idx, size_t n)
+{
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        const int h = min(max((int)hu[i], kHuMin), kHuMin + kLutSize - 1);
+        idx[i] = (uint16_t)(h - kHuMin);
+    }
+}
+
+__global__ void track_energy_kernel(const float4 *__restrict__ steps, const unsigned long long *__restrict__ off,
+                                    long long *__restrict__ T, uint32_t n_tracks)
+{
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n_tracks) return;
+    long long s = 0;
+    for (unsigned long long k = off[t]; k < off[t + 1]; ++k) s += to_fp(steps[k].y);
+    T[t] = s;
+}
+
+// dose per primary = E / (rho V) / N and Eq. (2) variance of that mean
+__global__ void dose_kernel(const uint16_t *__restrict__ idx, const unsigned long long *__restrict__ E,
+                            const unsigned long long *__restrict__ E2, const float2 *__restrict__ lut,
+                            const float *__restrict__ rho_lut, size_t nvox, double vol_cm3, double N,
+                            double *__restrict__ dose, double *__restrict__ var)
+{
+    for (size_t v = blockIdx.x * (size_t)blockDim.x + threadIdx.x; v < nvox; v += (size_t)gridDim.x * blockDim.x) {
+        const uint16_t m = idx[v];
+        const bool vac = lut[m].x == 0.f;
+        const double mass_kg = (double)rho_lut[m] * vol_cm3 * 1e-3;
+        const double per = kMeVToJ / mass_kg;                // Gy per MeV in this voxel
+        const double s1 = vac ? 0.0 : (double)(long long)E[v] * kFpMeV * per;
+        if (dose) dose[v] = s1 / N;
+        if (var) {
+            const double s2 = vac || !E2 ? 0.0 : (double)E2[v] * kFpMeV * per * per;
+            const double mean = s1 / N;
+            var[v] = N > 1.0 ? (s2 / N - mean * mean) / (N - 1.0) : 0.0;
+        }
+    }
+}
+
+__global__ void sum_i64_kernel(const unsigned long long *__restrict__ x, size_t n, unsigned long long *out)
+{
+    __shared__ unsigned long long part[16];
+    unsigned long long s = 0;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        s += x[i];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, kWave);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long t = 0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += part[w];
+        atomicAdd(out, t);
+    }
+}
+
+__global__ void philox_test_kernel(const uint4 *ctr, uint4 *out, uint32_t n, uint32_t k0, uint32_t k1)
+{
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = philox4x32_10(ctr[i], k0, k1);
+}
+
+uint32_t grid_for(size_t n, uint32_t block, uint32_t cap = 65536)
+{
+    size_t g = (n + block - 1) / block;
+    if (g < 1) g = 1;
+    return (uint32_t)(g > cap ? cap : g);
+}
+
+} // namespace
+
+hipError_t launch_build_lut(const double *pts, int n_pts, double vacuum_below, float2 *lut, float *rho,
+                            hipStream_t s)
+{
+    hipLaunchKernelGGL(build_lut_kernel, dim3(kLutSize / 256), dim3(256), 0, s, pts, n_pts, vacuum_below, lut, rho);
+    return hipGetLastError();
+}
+
+hipError_t launch_hu_to_index(const int16_t *hu, uint16_t *idx, size_t n, hipStream_t s)
+{
+    hipLaunchKernelGGL(hu_to_index_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, hu, idx, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_track_energy(const float4 *steps, const unsigned long long *off, long long *T,
+                               uint32_t n_tracks, hipStream_t s)
+{
+    hipLaunchKernelGGL(track_energy_kernel, dim3((n_tracks + 255) / 256), dim3(256), 0, s, steps, off, T, n_tracks);
+    return hipGetLastError();
+}
+
+hipError_t launch_dose(const DevPlan *, const uint16_t *idx, const unsigned long long *E,
+                       const unsigned long long *E2, const float2 *lut, const float *rho_lut,
+                       size_t nvox, double vol, double n_hist, double *dose, double *var, hipStream_t s)
+{
+    hipLaunchKernelGGL(dose_kernel, dim3(grid_for(nvox, 256, 8192)), dim3(256), 0, s, idx, E, E2, lut, rho_lut,
+                       nvox, vol, n_hist, dose, var);
+    return hipGetLastError();
+}
+
+hipError_t launch_sum_i64(const unsigned long long *x, size_t n, unsigned long long *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(sum_i64_kernel, dim3(grid_for(n, 256, 2048)), dim3(256), 0, s, x, n, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_philox_test(const uint4 *ctr, uint4 *out, uint32_t n, uint32_t k0, uint32_t k1, hipStream_t s)
+{
+    hipLaunchKernelGGL(philox_test_kernel, dim3((n + 255) / 256), dim3(256), 0, s, ctr, out, n, k0, k1);
+    return hipGetLastError();
+}
+
+} // namespace fdc

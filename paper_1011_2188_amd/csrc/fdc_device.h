@@ -1,0 +1,127 @@
+// Internal layout shared by the library's host runtime and its kernels.
+// Not part of the public ABI (include/fdc.h).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fdc {
+
+constexpr int kLutSize = 4096;        // HU index = clamp(HU, -1024, 3071) + 1024
+constexpr int kHuMin = -1024;
+constexpr int kWave = 64;             // CDNA wavefront
+constexpr uint32_t kTagTrack = 2u;    // Philox counter tags (word 3, low 4 bits)
+constexpr uint32_t kTagSource = 3u;
+constexpr uint32_t kFlagVariance = 1u;
+constexpr uint32_t kFlagRotate = 2u;
+constexpr int kMaxTablePts = 64;
+constexpr double kMeVToJ = 1.602176634e-13;
+constexpr double kFpMeV = 1.0 / 16777216.0;   // one fixed-point unit in MeV
+
+// one phantom + its tallies, as seen by the kernels
+struct DevPlan {
+    const uint16_t *idx;             // HU index per voxel, x-fastest
+    unsigned long long *E;           // int64 energy tally (two's complement in u64 adds)
+    unsigned long long *E2;          // uint64 sum of squared per-visit deposits
+    unsigned long long *acc;         // [0] incident, [1] escaped (fixed point)
+    int n[3];
+    float vox[3];
+    float org[3];
+    double vox_d[3];
+    double org_d[3];
+};
+
+// one spot with everything task 1 needs that does not depend on the history
+struct DevSpot {
+    double pos[3];
+    double e1[3], e2[3], d[3];      // lateral axes and direction (double, for the source)
+    float m[9];                     // field matrix, columns e1 e2 d (row-major m[r*3+c])
+    float sigma;
+    uint32_t bin;
+    uint32_t plan;                  // plan id (Philox counter word 3)
+    uint32_t spot;                  // spot index inside its plan (counter word 2)
+    long long skip;                 // fp(E_bin) - fp(E_spot)
+};
+
+// a contiguous range of histories of one spot, split in wave units of 64
+// histories aligned to multiples of 64
+struct WorkItem {
+    unsigned long long h0, h_end;   // histories [h0, h_end)
+    unsigned long long unit0;       // index of this item's first wave unit
+    uint32_t gspot;                 // index into the DevSpot array
+    uint32_t pad;
+};
+
+struct TransportArgs {
+    const float4 *steps;                 // (dx, dE, theta, phi)
+    const unsigned long long *track_off; // n_tracks + 1
+    const long long *track_T;            // sum of fp(dE) per track
+    const uint32_t *bin_first;           // n_bins + 1
+    const DevPlan *plans;
+    const DevSpot *spots;
+    const WorkItem *items;
+    const float2 *lut;                   // (rsp, g) per HU index; rsp == 0 is vacuum
+    unsigned long long n_units;
+    unsigned long long *queue;           // persistent mode: next unit counter
+    uint32_t n_items;
+    uint32_t seed_lo, seed_hi;
+    uint32_t R;
+    uint32_t flags;
+    float *ep_xyz;                       // endpoint mode outputs (else null)
+    int *ep_reason;
+};
+
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two 32x32
+// multiplies with a Weyl key schedule.
+__host__ __device__ inline void philox_round(uint32_t &c0, uint32_t &c1, uint32_t &c2, uint32_t &c3,
+                                             uint32_t k0, uint32_t k1)
+{
+    const uint64_t a = (uint64_t)0xD2511F53u * c0;
+    const uint64_t b = (uint64_t)0xCD9E8D57u * c2;
+    const uint32_t n0 = (uint32_t)(b >> 32) ^ c1 ^ k0;
+    const uint32_t n2 = (uint32_t)(a >> 32) ^ c3 ^ k1;
+    c1 = (uint32_t)b;
+    c3 = (uint32_t)a;
+    c0 = n0;
+    c2 = n2;
+}
+
+__host__ __device__ inline uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        philox_round(c.x, c.y, c.z, c.w, k0, k1);
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return c;
+}
+
+// 24 random bits mapped to the open interval (0, 1)
+__host__ __device__ inline double u01(uint32_t x)
+{
+    return (double)(x >> 8) * 0x1p-24 + 0x1p-25;
+}
+
+// energy in MeV (float) -> fixed point; exact for every float input
+__host__ __device__ inline long long to_fp(float mev)
+{
+    return (long long)rintf(mev * 16777216.0f);
+}
+
+// kernels' host-side launchers (implemented next to their kernels)
+hipError_t launch_transport(const TransportArgs &a, uint32_t waves_per_block, uint32_t grid_blocks,
+                            bool variance, bool endpoints, hipStream_t s);
+hipError_t launch_build_lut(const double *pts, int n_pts, double vacuum_below, float2 *lut, float *rho,
+                            hipStream_t s);
+hipError_t launch_hu_to_index(const int16_t *hu, uint16_t *idx, size_t n, hipStream_t s);
+hipError_t launch_track_energy(const float4 *steps, const unsigned long long *off, long long *T,
+                               uint32_t n_tracks, hipStream_t s);
+hipError_t launch_dose(const DevPlan *plan_dev, const uint16_t *idx, const unsigned long long *E,
+                       const unsigned long long *E2, const float2 *lut, const float *rho_lut,
+                       size_t nvox, double voxel_volume_cm3, double n_hist, double *dose, double *var,
+                       hipStream_t s);
+hipError_t launch_sum_i64(const unsigned long long *x, size_t n, unsigned long long *out, hipStream_t s);
+hipError_t launch_philox_test(const uint4 *ctr, uint4 *out, uint32_t n, uint32_t k0, uint32_t k1,
+                              hipStream_t s);
+
+} // namespace fdc

@@ -1,0 +1,351 @@
+// Transport kernel: re-traces stored water tracks through a voxel phantom and
+// tallies deposited energy (Sections 2.2 and 2.3 of the paper).
+//
+// Work decomposition: a wave unit is 64 consecutive histories of one spot
+// (aligned to multiples of 64), one history per lane.  Consecutive histories
+// of a spot share a database track in chunks of R (R = 64 by default), so the
+// lanes of a wave read the same step record each step: the record loads are
+// broadcast loads, and lanes only diverge in the voxel walk - the paper's
+// choice of feeding one stored history to a whole thread group (Section 4).
+//
+// Per history (task 1, Section 2.3): pick the track of the chunk with Philox,
+// find the start step where the remaining energy equals the spot energy,
+// sample the lateral source position, and enter the phantom box.  Then (task
+// 2) each step's water-equivalent length (WEL) is consumed voxel by voxel at
+// geometric length WEL / RSP, its energy split over the voxels in proportion
+// to the WEL consumed (telescoping rounding to integers), and at the step end
+// the direction is deflected by theta * sqrt(sum(w_v * G_v) / WEL) with
+// G = RScP / RSP.  Deposits accumulate in a register while the proton stays
+// in one voxel and are flushed with a 64-bit integer atomic when it leaves.
+//
+// Geometry is FP32 with the position kept as (integer voxel, fraction in the
+// voxel), so precision does not degrade with the distance from the origin.
+// The source sample and the box entry are computed in FP64 once per history.
+#include "fdc_device.h"
+
+namespace fdc {
+
+namespace {
+
+constexpr float kInf = __builtin_huge_valf();
+
+struct Lane {
+    int i[3];           // voxel
+    float f[3];         // position inside the voxel, voxel units, [0, 1]
+    float d[3];         // direction (CT frame, unit)
+    float b[3];         // direction in the beam frame
+    uint32_t v;         // linear voxel index
+};
+
+__host__ __device__ inline void set_direction_terms(const float d[3], const float vox[3], float step_inv[3],
+                                           float dv[3])
+{
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        dv[a] = d[a] / vox[a];                                  // voxel units per cm
+        step_inv[a] = d[a] != 0.f ? vox[a] / fabsf(d[a]) : kInf; // cm per voxel
+    }
+}
+
+template <bool VAR, bool EP>
+__host__ __device__ inline void flush(const DevPlan &pl, uint32_t v, long long &acc)
+{
+    if (acc == 0) return;
+    if constexpr (!EP) {
+        atomicAdd(pl.E + v, (unsigned long long)acc);
+        if (VAR) {
+            const unsigned long long q = (unsigned long long)((acc + 2048) >> 12);
+            atomicAdd(pl.E2 + v, q * q);
+        }
+    }
+    acc = 0;
+}
+
+template <bool VAR, bool EP>
+__host__ __device__ void replay_history(const TransportArgs &a, const DevSpot &sp, const DevPlan &pl,
+                               const float2 *__restrict__ lut, unsigned long long h, uint32_t slot,
+                               long long &inc, long long &esc)
+{
+    // ---- task 1: track, start step, source ---------------------------------
+    const uint32_t first = a.bin_first[sp.bin];
+    const uint32_t nb = a.bin_first[sp.bin + 1] - first;
+    const unsigned long long c = h / a.R;
+    const uint4 xt = philox4x32_10(make_uint4((uint32_t)c, (uint32_t)(c >> 32), sp.spot,
+                                              (sp.plan << 4) | kTagTrack), a.seed_lo, a.seed_hi);
+    const uint32_t t = first + (uint32_t)(((uint64_t)xt.x * nb) >> 32);
+    unsigned long long k = a.track_off[t];
+    const unsigned long long kend = a.track_off[t + 1];
+    const long long skip = sp.skip;
+    long long cum = 0;
+    long long e = 0;
+    for (; k < kend; ++k) {
+        e = to_fp(a.steps[k].y);
+        if (cum + e > skip) break;
+        cum += e;
+    }
+    long long I_h = a.track_T[t] - skip;
+    if (I_h < 0) I_h = 0;
+    inc = I_h;
+
+    const uint4 xs = philox4x32_10(make_uint4((uint32_t)h, (uint32_t)(h >> 32), sp.spot,
+                                              (sp.plan << 4) | kTagSource), a.seed_lo, a.seed_hi);
+    const double r = sqrt(-2.0 * log(u01(xs.x)));
+    double sa, ca;
+    sincos(2.0 * M_PI * u01(xs.y), &sa, &ca);
+    const double n1 = r * ca, n2 = r * sa;
+    const float phi0 = (a.flags & kFlagRotate) ? (float)(2.0 * M_PI * u01(xs.z)) : 0.f;
+    double p[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) p[q] = sp.pos[q] + (double)sp.sigma * (n1 * sp.e1[q] + n2 * sp.e2[q]);
+
+    // ray-box entry (FP64); outside the box is vacuum
+    double tin = -__builtin_huge_val(), tout = __builtin_huge_val();
+    int ax_in = 0;
+    bool miss = false;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        const double lo = pl.org_d[q], hi = pl.org_d[q] + pl.n[q] * pl.vox_d[q];
+        if (sp.d[q] == 0.0) {
+            miss |= (p[q] < lo || p[q] >= hi);
+        } else {
+            double t1 = (lo - p[q]) / sp.d[q], t2 = (hi - p[q]) / sp.d[q];
+            if (t1 > t2) { const double tt = t1; t1 = t2; t2 = tt; }
+            if (t1 > tin) { tin = t1; ax_in = q; }
+            tout = fmin(tout, t2);
+        }
+    }
+    miss = miss || !(tin < tout) || tout <= 0.0;
+    if (miss || I_h == 0 || k == kend) {
+        esc = I_h;
+        if (EP) {
+            a.ep_xyz[3 * slot + 0] = (float)p[0];
+            a.ep_xyz[3 * slot + 1] = (float)p[1];
+            a.ep_xyz[3 * slot + 2] = (float)p[2];
+            a.ep_reason[slot] = (I_h == 0 || k == kend) ? 0 : 2;
+        }
+        return;
+    }
+    if (tin > 0.0) {
+#pragma unroll
+        for (int q = 0; q < 3; ++q) p[q] += tin * sp.d[q];
+    }
+    Lane L;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        double u = (p[q] - pl.org_d[q]) / pl.vox_d[q];
+        if (tin > 0.0 && q == ax_in) u = sp.d[q] > 0.0 ? 0.0 : (double)pl.n[q];  // on the entry face
+        double fl = floor(u);
+        int i = (int)fl;
+        if (u == fl && sp.d[q] < 0.0) i -= 1;     // a boundary point belongs to the voxel entered
+        i = min(max(i, 0), pl.n[q] - 1);
+        L.i[q] = i;
+        L.f[q] = (float)fmin(fmax(u - (double)i, 0.0), 1.0);
+        L.d[q] = (float)sp.d[q];
+    }
+    L.b[0] = 0.f; L.b[1] = 0.f; L.b[2] = 1.f;
+    L.v = ((uint32_t)L.i[2] * (uint32_t)pl.n[1] + (uint32_t)L.i[1]) * (uint32_t)pl.n[0] + (uint32_t)L.i[0];
+    const uint32_t stride[3] = {1u, (uint32_t)pl.n[0], (uint32_t)pl.n[0] * (uint32_t)pl.n[1]};
+
+    float sinv[3], dv[3];
+    set_direction_terms(L.d, pl.vox, sinv, dv);
+
+    // ---- task 2: re-trace the steps -----------------------------------------
+    long long acc = 0, hdep = 0;
+    bool escaped = false;
+    bool first_step = true;
+    for (; k < kend; ++k) {
+        const float4 rec = a.steps[k];
+        float w_tot = rec.x, th = rec.z, ph = rec.w;
+        e = to_fp(rec.y);
+        if (first_step) {                          // partial first step
+            const long long e_first = cum + e - skip;
+            const float f = (float)e_first / (float)e;
+            e = e_first;
+            w_tot = f * rec.x;
+            th *= sqrtf(f);
+            ph += phi0;
+            first_step = false;
+        }
+        const float inv_w = 1.f / w_tot;
+        const float ef = (float)e;
+        float tau = 0.f, g2 = 0.f;
+        long long dep = 0;
+        while (tau < w_tot) {
+            const float2 m = lut[pl.idx[L.v]];
+            // distance (cm) to the exit face along each axis; ties go x -> y -> z
+            float tx = (L.d[0] > 0.f ? 1.f - L.f[0] : L.f[0]) * sinv[0];
+            float ty = (L.d[1] > 0.f ? 1.f - L.f[1] : L.f[1]) * sinv[1];
+            float tz = (L.d[2] > 0.f ? 1.f - L.f[2] : L.f[2]) * sinv[2];
+            tx = L.d[0] != 0.f ? tx : kInf;
+            ty = L.d[1] != 0.f ? ty : kInf;
+            tz = L.d[2] != 0.f ? tz : kInf;
+            float tmin = tx;
+            int ax = 0;
+            if (ty < tmin) { tmin = ty; ax = 1; }
+            if (tz < tmin) { tmin = tz; ax = 2; }
+            float move = tmin;
+            bool cross = true;
+            if (m.x != 0.f) {                      // material: consume WEL
+                const float rem = w_tot - tau;
+                const float wb = tmin * m.x;
+                float w_v, tau_n;
+                if (rem <= wb) {
+                    w_v = rem;
+                    tau_n = w_tot;
+                    move = rem / m.x;
+                    cross = (rem == wb);
+                } else {
+                    w_v = wb;
+                    tau_n = tau + wb;
+                }
+                long long cumk = e;
+                if (tau_n < w_tot) cumk = min(e, (long long)rintf(ef * (tau_n * inv_w)));
+                const long long piece = cumk - dep;
+                dep = cumk;
+                acc += piece;
+                hdep += piece;
+                g2 += w_v * m.y;
+                tau = tau_n;
+            }
+#pragma unroll
+            for (int q = 0; q < 3; ++q) L.f[q] = fminf(fmaxf(L.f[q] + move * dv[q], 0.f), 1.f);
+            if (cross) {
+                flush<VAR, EP>(pl, L.v, acc);
+                bool out = false;
+#pragma unroll
+                for (int q = 0; q < 3; ++q) {
+                    if (q == ax) {
+                        const int s = L.d[q] > 0.f ? 1 : -1;
+                        const int ni = L.i[q] + s;
+                        out = (unsigned)ni >= (unsigned)pl.n[q];
+                        if (out) {
+                            L.f[q] = s > 0 ? 1.f : 0.f;    // end point on the exit face
+                        } else {
+                            L.i[q] = ni;
+                            L.f[q] = s > 0 ? 0.f : 1.f;
+                            L.v += s > 0 ? stride[q] : (uint32_t)(-(int)stride[q]);
+                        }
+                    }
+                }
+                if (out) {
+                    escaped = true;
+                    break;
+                }
+            }
+        }
+        if (escaped) break;
+        // deflection at the end of the step, scaled by the traversed material
+        const float th2 = th * sqrtf(g2 * inv_w);
+        float st, ct, sph, cph;
+        sincosf(th2, &st, &ct);
+        sincosf(ph, &sph, &cph);
+        const float u = L.b[0], vv = L.b[1], w = L.b[2];
+        const float rho = hypotf(u, vv);
+        float nu, nv, nw;
+        if (rho < 1e-20f) {
+            nu = st * cph;
+            nv = st * sph;
+            nw = (w < 0.f ? -ct : ct);
+        } else {
+            const float ir = 1.f / rho;
+            nu = u * ct + st * (u * w * cph - vv * sph) * ir;
+            nv = vv * ct + st * (vv * w * cph + u * sph) * ir;
+            nw = w * ct - rho * st * cph;
+        }
+        const float nrm = 1.f / sqrtf(nu * nu + nv * nv + nw * nw);
+        L.b[0] = nu * nrm; L.b[1] = nv * nrm; L.b[2] = nw * nrm;
+#pragma unroll
+        for (int q = 0; q < 3; ++q)
+            L.d[q] = sp.m[3 * q + 0] * L.b[0] + sp.m[3 * q + 1] * L.b[1] + sp.m[3 * q + 2] * L.b[2];
+        set_direction_terms(L.d, pl.vox, sinv, dv);
+    }
+    if (!escaped) flush<VAR, EP>(pl, L.v, acc);
+    esc = escaped ? I_h - hdep : 0;
+    if (EP) {
+#pragma unroll
+        for (int q = 0; q < 3; ++q)
+            a.ep_xyz[3 * slot + q] = (float)(pl.org_d[q] + ((double)L.i[q] + (double)L.f[q]) * pl.vox_d[q]);
+        a.ep_reason[slot] = escaped ? 1 : 0;
+    }
+}
+
+__device__ inline long long wave_sum(long long x)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, kWave);
+    return x;
+}
+
+template <bool VAR, bool EP>
+__device__ void process_unit(const TransportArgs &a, const float2 *lut, unsigned long long unit,
+                             uint32_t lane)
+{
+    // the work item holding this unit: largest i with items[i].unit0 <= unit
+    uint32_t lo = 0, hi = a.n_items;
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (a.items[mid].unit0 <= unit) lo = mid; else hi = mid;
+    }
+    const WorkItem it = a.items[lo];
+    const DevSpot &sp = a.spots[it.gspot];
+    const DevPlan &pl = a.plans[sp.plan];
+    const unsigned long long h = (it.h0 / kWave + (unit - it.unit0)) * kWave + lane;
+    long long inc = 0, esc = 0;
+    if (h >= it.h0 && h < it.h_end)
+        replay_history<VAR, EP>(a, sp, pl, lut, h, (uint32_t)(h - it.h0), inc, esc);
+    if (!EP) {
+        inc = wave_sum(inc);
+        esc = wave_sum(esc);
+        if (lane == 0) {
+            if (inc) atomicAdd(pl.acc + 0, (unsigned long long)inc);
+            if (esc) atomicAdd(pl.acc + 1, (unsigned long long)esc);
+        }
+    }
+}
+
+template <bool VAR, bool EP>
+__global__ void __launch_bounds__(1024) transport_kernel(TransportArgs a)
+{
+    __shared__ float2 s_lut[kLutSize];
+    for (int i = threadIdx.x; i < kLutSize; i += blockDim.x) s_lut[i] = a.lut[i];
+    __syncthreads();
+    const uint32_t lane = threadIdx.x & (kWave - 1);
+    const uint32_t wave = threadIdx.x / kWave;
+    const uint32_t wpb = blockDim.x / kWave;
+    if (a.queue == nullptr) {
+        const unsigned long long unit = (unsigned long long)blockIdx.x * wpb + wave;
+        if (unit < a.n_units) process_unit<VAR, EP>(a, s_lut, unit, lane);
+        return;
+    }
+    // persistent: each wave pulls units from a global counter until none are
+    // left.  Every lane executes the atomic (lane 0 adds 1, the others 0), so
+    // there is no divergent branch around it, and lane 0's old value - a unique
+    // ticket - is read back with readfirstlane as a scalar: the loop exit is a
+    // uniform branch and no cross-lane read sits in divergent control flow.
+    for (;;) {
+        const unsigned long long got = atomicAdd(a.queue, lane == 0 ? 1ull : 0ull);
+        const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)got);
+        const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(got >> 32));
+        const unsigned long long unit = ((unsigned long long)hi << 32) | lo;
+        if (unit >= a.n_units) break;
+        process_unit<VAR, EP>(a, s_lut, unit, lane);
+    }
+}
+
+} // namespace
+
+hipError_t launch_transport(const TransportArgs &a, uint32_t waves_per_block, uint32_t grid_blocks,
+                            bool variance, bool endpoints, hipStream_t s)
+{
+    const dim3 block(waves_per_block * kWave);
+    const dim3 grid(grid_blocks);
+    if (endpoints)
+        hipLaunchKernelGGL((transport_kernel<false, true>), grid, block, 0, s, a);
+    else if (variance)
+        hipLaunchKernelGGL((transport_kernel<true, false>), grid, block, 0, s, a);
+    else
+        hipLaunchKernelGGL((transport_kernel<false, false>), grid, block, 0, s, a);
+    return hipGetLastError();
+}
+
+} // namespace fdc

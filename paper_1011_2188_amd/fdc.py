@@ -1,0 +1,274 @@
+"""Thin Python binding of libfdc.so (include/fdc.h).
+
+Argument marshalling only: every step of the dose calculation runs in the
+library's HIP kernels.  The library must have been built (`build.build()` or
+`__graft_entry__.build()`); importing this module without it raises - there is
+no fallback path.
+
+The module-level functions carry the C names (`fdc_create`, `fdc_run_histories`
+...) and take/return plain ctypes values; `Context` wraps them for numpy inputs
+and torch device tensors.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libfdc.so")
+
+FDC_OK, FDC_E_ARG, FDC_E_STATE, FDC_E_NOMEM, FDC_E_HIP, FDC_E_RANGE, FDC_E_FORMAT, FDC_E_OVERFLOW = \
+    0, -1, -2, -3, -4, -5, -6, -7
+FDC_NO_DEVICE = -1
+FDC_RUN_VARIANCE = 1
+FDC_RUN_ROTATE_TRACKS = 2
+ERROR_NAMES = {0: "FDC_OK", -1: "FDC_E_ARG", -2: "FDC_E_STATE", -3: "FDC_E_NOMEM", -4: "FDC_E_HIP",
+               -5: "FDC_E_RANGE", -6: "FDC_E_FORMAT", -7: "FDC_E_OVERFLOW"}
+
+# every entry point declared in include/fdc.h
+EXPORTS = ["fdc_create", "fdc_destroy", "fdc_last_error", "fdc_set_allocator", "fdc_set_hu_table",
+           "fdc_load_track_db", "fdc_load_phantom", "fdc_add_beam_spots", "fdc_run_histories",
+           "fdc_reset_plan", "fdc_compute_dose", "fdc_read_dose_and_variance", "fdc_debug_endpoints",
+           "fdc_debug_philox", "fdc_debug_material", "fdc_set_launch_config", "fdc_device_cus"]
+
+
+class fdc_summary(C.Structure):
+    _fields_ = [("n_histories", C.c_uint64), ("incident_fp", C.c_int64),
+                ("deposited_fp", C.c_int64), ("escaped_fp", C.c_int64)]
+
+
+class fdc_launch_config(C.Structure):
+    _fields_ = [("waves_per_block", C.c_uint32), ("blocks_per_cu", C.c_uint32),
+                ("reserved", C.c_uint32 * 6)]
+
+
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+
+
+class FdcError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{ERROR_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+_lib = None
+_P = C.c_void_p
+
+
+def lib():
+    """Load libfdc.so; raises if it was not built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it first (paper_1011_2188_amd.build.build())")
+    L = C.CDLL(LIB_PATH)
+    sig = {
+        "fdc_create": (C.c_int, [C.POINTER(_P), C.c_int, C.c_uint64, C.c_uint32]),
+        "fdc_destroy": (C.c_int, [_P]),
+        "fdc_last_error": (C.c_char_p, [_P]),
+        "fdc_set_allocator": (C.c_int, [_P, ALLOC_FN, FREE_FN, _P]),
+        "fdc_set_hu_table": (C.c_int, [_P, _P, _P, _P, _P, C.c_int, C.c_float]),
+        "fdc_load_track_db": (C.c_int, [_P, _P, C.c_uint64, _P, C.c_uint32, _P, _P, C.c_uint32, _P]),
+        "fdc_load_phantom": (C.c_int, [_P, C.POINTER(C.c_int32), _P, C.c_int, C.c_int, C.c_int, _P, _P, _P]),
+        "fdc_add_beam_spots": (C.c_int, [_P, C.c_int32, _P, C.c_uint32]),
+        "fdc_run_histories": (C.c_int, [_P, _P, C.c_uint32, C.c_uint32, _P]),
+        "fdc_reset_plan": (C.c_int, [_P, C.c_int32, C.c_int, _P]),
+        "fdc_compute_dose": (C.c_int, [_P, C.c_int32, _P, _P, _P]),
+        "fdc_read_dose_and_variance": (C.c_int, [_P, C.c_int32, _P, _P, _P, _P, C.POINTER(fdc_summary), _P]),
+        "fdc_debug_endpoints": (C.c_int, [_P, C.c_int32, C.c_uint32, C.c_uint64, C.c_uint32, C.c_uint32,
+                                          _P, _P, _P]),
+        "fdc_debug_philox": (C.c_int, [_P, _P, _P, C.c_uint32, _P]),
+        "fdc_debug_material": (C.c_int, [_P, _P, _P, _P, _P]),
+        "fdc_set_launch_config": (C.c_int, [_P, C.POINTER(fdc_launch_config)]),
+        "fdc_device_cus": (C.c_int, [_P, C.POINTER(C.c_int)]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+def _ptr(a):
+    if a is None:
+        return None
+    if isinstance(a, np.ndarray):
+        return a.ctypes.data
+    return a.data_ptr()      # torch tensor
+
+
+def _stream(stream):
+    if stream is None:
+        try:
+            import torch
+            if torch.cuda.is_available() and torch.cuda.is_initialized():
+                return torch.cuda.current_stream().cuda_stream
+        except ImportError:
+            pass
+        return None
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+# ---- C-named wrappers (argument marshalling only) -------------------------
+def fdc_create(hip_device, seed, reuse_R):
+    h = _P()
+    rc = lib().fdc_create(C.byref(h), hip_device, seed, reuse_R)
+    return rc, h
+
+
+def fdc_last_error(ctx):
+    m = lib().fdc_last_error(ctx)
+    return m.decode() if m else ""
+
+
+def _check(ctx, rc):
+    if rc != FDC_OK:
+        raise FdcError(rc, fdc_last_error(ctx))
+
+
+class Context:
+    """One libfdc context (one device).  Inputs are numpy arrays on the host
+    (copied by the loaders); dose outputs are numpy or torch device tensors."""
+
+    def __init__(self, device=0, seed=1, reuse_R=64, torch_allocator=False, table=None):
+        rc, h = fdc_create(device, seed, reuse_R)
+        if rc != FDC_OK:
+            raise FdcError(rc, f"fdc_create(device={device}) failed")
+        self.h = h
+        self.device = device
+        self.plans = {}           # plan id -> shape (nz, ny, nx)
+        self._keep = []
+        if torch_allocator:
+            self._use_torch_allocator()
+        if table is not None:
+            self.set_hu_table(table)
+
+    # -- lifetime
+    def close(self):
+        if self.h:
+            lib().fdc_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def _use_torch_allocator(self):
+        import torch
+        live = {}
+        dev = torch.device("cuda", self.device)
+
+        def _alloc(n, user):
+            try:
+                t = torch.empty(int(n), dtype=torch.uint8, device=dev)
+            except RuntimeError:
+                return None
+            live[t.data_ptr()] = t
+            return t.data_ptr()
+
+        def _free(p, user):
+            live.pop(p, None)
+
+        fa, ff = ALLOC_FN(_alloc), FREE_FN(_free)
+        self._keep += [fa, ff, live]
+        _check(self.h, lib().fdc_set_allocator(self.h, fa, ff, None))
+
+    # -- inputs
+    def set_hu_table(self, t):
+        cols = [np.ascontiguousarray(t[k], np.float32) for k in ("hu", "rho", "rsp", "rscp")]
+        _check(self.h, lib().fdc_set_hu_table(self.h, *[c.ctypes.data for c in cols], cols[0].size,
+                                              float(t["vacuum_below_hu"])))
+
+    def load_track_db(self, db, stream=None):
+        steps = np.ascontiguousarray(db.steps, np.float32)
+        off = np.ascontiguousarray(db.track_off, np.uint64)
+        be = np.ascontiguousarray(db.bin_E, np.float32)
+        bf = np.ascontiguousarray(db.bin_first, np.uint32)
+        _check(self.h, lib().fdc_load_track_db(self.h, steps.ctypes.data, steps.shape[0], off.ctypes.data,
+                                               off.size - 1, be.ctypes.data, bf.ctypes.data, be.size,
+                                               _stream(stream)))
+
+    def load_phantom(self, ph, stream=None):
+        hu = np.ascontiguousarray(ph.hu, np.int16)
+        nz, ny, nx = hu.shape
+        vox = np.ascontiguousarray(ph.voxel_cm, np.float32)
+        org = np.ascontiguousarray(ph.origin_cm, np.float32)
+        plan = C.c_int32()
+        _check(self.h, lib().fdc_load_phantom(self.h, C.byref(plan), hu.ctypes.data, nx, ny, nz,
+                                              vox.ctypes.data, org.ctypes.data, _stream(stream)))
+        self.plans[plan.value] = (nz, ny, nx)
+        return plan.value
+
+    def add_beam_spots(self, plan, spots):
+        from .inputs import SPOT_DTYPE
+        s = np.ascontiguousarray(spots, SPOT_DTYPE)
+        _check(self.h, lib().fdc_add_beam_spots(self.h, plan, s.ctypes.data, s.size))
+
+    # -- the method
+    def run_histories(self, plans, flags=FDC_RUN_VARIANCE, stream=None):
+        p = np.ascontiguousarray(np.atleast_1d(plans), np.int32)
+        _check(self.h, lib().fdc_run_histories(self.h, p.ctypes.data, p.size, flags, _stream(stream)))
+
+    def reset_plan(self, plan, rewind=False, stream=None):
+        _check(self.h, lib().fdc_reset_plan(self.h, plan, int(bool(rewind)), _stream(stream)))
+
+    def compute_dose(self, plan, dose=None, var=None, stream=None):
+        """Into torch float64 device tensors (either may be None)."""
+        _check(self.h, lib().fdc_compute_dose(self.h, plan, _ptr(dose), _ptr(var), _stream(stream)))
+
+    def read_dose_and_variance(self, plan, dose=True, var=True, raw=False, stream=None):
+        shape = self.plans[plan]
+        out = {}
+        d = np.empty(shape, np.float64) if dose else None
+        v = np.empty(shape, np.float64) if var else None
+        e = np.empty(shape, np.int64) if raw else None
+        e2 = np.empty(shape, np.uint64) if raw else None
+        s = fdc_summary()
+        _check(self.h, lib().fdc_read_dose_and_variance(self.h, plan, _ptr(d), _ptr(v), _ptr(e), _ptr(e2),
+                                                        C.byref(s), _stream(stream)))
+        out.update(dose=d, var=v, E=e, E2=e2, n_histories=s.n_histories, incident=s.incident_fp,
+                   deposited=s.deposited_fp, escaped=s.escaped_fp)
+        return out
+
+    # -- testing aids
+    def debug_endpoints(self, plan, spot, h0, n, flags=0, stream=None):
+        xyz = np.empty((n, 3), np.float32)
+        why = np.empty(n, np.int32)
+        _check(self.h, lib().fdc_debug_endpoints(self.h, plan, spot, h0, n, flags, xyz.ctypes.data,
+                                                 why.ctypes.data, _stream(stream)))
+        return xyz, why
+
+    def debug_philox(self, ctr, stream=None):
+        c = np.ascontiguousarray(ctr, np.uint32).reshape(-1, 4)
+        out = np.empty_like(c)
+        _check(self.h, lib().fdc_debug_philox(self.h, c.ctypes.data, out.ctypes.data, c.shape[0], _stream(stream)))
+        return out
+
+    def debug_material(self, stream=None):
+        rsp, g, rho = (np.empty(4096, np.float32) for _ in range(3))
+        _check(self.h, lib().fdc_debug_material(self.h, rsp.ctypes.data, g.ctypes.data, rho.ctypes.data,
+                                                _stream(stream)))
+        return rsp, g, rho
+
+    def set_launch_config(self, waves_per_block=4, blocks_per_cu=0):
+        cfg = fdc_launch_config(waves_per_block, blocks_per_cu)
+        _check(self.h, lib().fdc_set_launch_config(self.h, C.byref(cfg)))
+
+    def device_cus(self):
+        n = C.c_int()
+        _check(self.h, lib().fdc_device_cus(self.h, C.byref(n)))
+        return n.value

@@ -1,0 +1,269 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Criteria (floating point decides only continuous quantities here; integers
+that depend on integers alone must match exactly):
+  * dose within 0.5% of Dmax in every voxel above 10% of Dmax;
+  * at least 99.9% of sampled histories end within 1e-4 cm of the oracle's
+    end point, with the same end reason;
+  * deposited + escaped == incident exactly, and the incident energy (which
+    depends only on the Philox track choice and integer energies) equals the
+    oracle's exactly;
+  * tallies bitwise identical across launch configurations and batching.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from oracle import oracle as O  # noqa: E402
+from paper_1011_2188_amd import fdc as F  # noqa: E402
+from paper_1011_2188_amd import inputs as I  # noqa: E402
+from paper_1011_2188_amd import workloads as W  # noqa: E402
+
+SEED = 1
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    O.build(force=False)
+    torch.cuda.init()
+
+
+def ctx_for(db, R=64, seed=SEED, **cfg):
+    c = F.Context(device=0, seed=seed, reuse_R=R, table=I.HU_TABLE_DEFAULT)
+    c.load_track_db(db)
+    if cfg:
+        c.set_launch_config(**cfg)
+    return c
+
+
+def gpu_run(c, ph, sp, flags=F.FDC_RUN_VARIANCE):
+    p = c.load_phantom(ph)
+    c.add_beam_spots(p, sp)
+    c.run_histories([p], flags)
+    r = c.read_dose_and_variance(p, var=bool(flags & F.FDC_RUN_VARIANCE), raw=True)
+    r["plan"] = p
+    return r
+
+
+def check_dose(g, o, ph, n):
+    dose_o, var_o = O.dose_and_variance(o["E"], o["E2"], n, ph)
+    dmax = dose_o.max()
+    sel = dose_o > 0.1 * dmax
+    err = np.abs(g["dose"] - dose_o)[sel].max() / dmax
+    assert err <= 0.005, f"dose differs by {err:.4%} of Dmax"
+    return dose_o, var_o
+
+
+def check_energy(g, o):
+    assert g["deposited"] + g["escaped"] == g["incident"]
+    assert int(g["E"].sum()) == g["deposited"]
+    assert g["incident"] == o["incident"]
+
+
+def check_endpoints(c, plan, db, ph, sp, spot, h0, n, flags=0, R=64):
+    xg, rg = c.debug_endpoints(plan, spot, h0, n, flags)
+    xo, ro = O.endpoints(db, ph, sp, spot, h0, n, seed=SEED, R=R, flags=flags)
+    same = rg == ro
+    close = np.linalg.norm(xg.astype(np.float64) - xo, axis=1) <= 1e-4
+    ok = same & close
+    return int(ok.sum()), n
+
+
+# ---------------------------------------------------------------- units -----
+def test_device_philox_bitwise():
+    c = F.Context(device=0, seed=0x1234_5678_9ABC_DEF0)
+    rng = np.random.default_rng(3)
+    ctr = rng.integers(0, 2 ** 32, size=(1_000_000, 4), dtype=np.uint64).astype(np.uint32)
+    ctr[:1000, 1:] = 0
+    g = c.debug_philox(ctr)
+    o = O.philox_batch(ctr, [0x9ABCDEF0, 0x12345678])
+    assert np.array_equal(g, o)
+
+
+def test_device_material_table():
+    c = F.Context(device=0, table=I.HU_TABLE_DEFAULT)
+    rsp, g, rho = c.debug_material()
+    hu = (np.arange(4096) - 1024).astype(np.int16)
+    rho_o, rsp_o, g_o, vac = O.material(hu)
+    assert np.array_equal(rsp == 0, vac)
+    assert np.allclose(rsp, rsp_o, rtol=1e-6, atol=0)
+    assert np.allclose(g, g_o, rtol=1e-6, atol=0)
+    assert np.allclose(rho, rho_o, rtol=1e-6, atol=0)
+
+
+# ---------------------------------------------------------------- parity ----
+def test_water_pencil_full_parity():
+    """64^3 water, one 150 MeV pencil beam, 1e5 histories (all of them)."""
+    ph, sp, db = W.water_pencil()
+    c = ctx_for(db)
+    g = gpu_run(c, ph, sp)
+    o = O.replay(db, ph, sp, seed=SEED)
+    check_energy(g, o)
+    _, var_o = check_dose(g, o, ph, 100_000)
+    assert abs(g["escaped"] - o["escaped"]) <= 1e-6 * o["incident"]
+    sel = g["dose"] > 0.5 * g["dose"].max()
+    ug = np.mean(np.sqrt(g["var"][sel]) / g["dose"][sel])
+    uo = np.mean(np.sqrt(var_o[sel]) / g["dose"][sel])
+    assert abs(ug / uo - 1) < 0.01
+    ok, n = check_endpoints(c, g["plan"], db, ph, sp, 0, 0, 4096)
+    assert ok >= 0.999 * n
+
+
+def test_slab_parity():
+    """Bone/lung slab phantom, 25 spots from 70 to 230 MeV, 4e4 histories each."""
+    ph = I.slab_phantom(128, 0.1)
+    sp = W.slab_spots(40_000)
+    db = W.multi_bin_db(2000)
+    c = ctx_for(db)
+    g = gpu_run(c, ph, sp)
+    o = O.replay(db, ph, sp, seed=SEED)
+    check_energy(g, o)
+    check_dose(g, o, ph, int(sp["n_histories"].sum()))
+    tot = good = 0
+    for s in range(25):
+        ok, n = check_endpoints(c, g["plan"], db, ph, sp, s, 1000, 200)
+        good += ok
+        tot += n
+    assert good >= 0.999 * tot
+
+
+def test_thorax_subset_parity():
+    """Synthetic thorax, 3 fields x 60 spots, 3000 histories each, rotation on."""
+    ph = I.thorax_phantom((256, 256, 128), 0.2, seed=2188)
+    sp_all = W.thorax_spots(total=6000 * 3000)
+    sp = np.concatenate([sp_all[f * 2000:f * 2000 + 60] for f in range(3)])
+    db = W.multi_bin_db(2000)
+    c = ctx_for(db)
+    flags = F.FDC_RUN_VARIANCE | F.FDC_RUN_ROTATE_TRACKS
+    g = gpu_run(c, ph, sp, flags)
+    o = O.replay(db, ph, sp, seed=SEED, flags=flags)
+    check_energy(g, o)
+    check_dose(g, o, ph, int(sp["n_histories"].sum()))
+    tot = good = 0
+    for s in range(0, 180, 6):
+        ok, n = check_endpoints(c, g["plan"], db, ph, sp, s, 0, 128, flags)
+        good += ok
+        tot += n
+    assert good >= 0.999 * tot
+
+
+@pytest.mark.parametrize("R", [1, 320])
+def test_reuse_factor_parity(R):
+    ph = I.thorax_phantom((64, 64, 48), 0.4, seed=5)
+    rng = np.random.default_rng(7)
+    sp = I.field_spots((3.0, -1.0, 0.0), 90.0, 12, rng, histories=np.full(12, 777, np.uint64))
+    db = W.multi_bin_db(2000)
+    c = ctx_for(db, R=R)
+    g = gpu_run(c, ph, sp)
+    o = O.replay(db, ph, sp, seed=SEED, R=R)
+    check_energy(g, o)
+    check_dose(g, o, ph, 12 * 777)
+    ok, n = check_endpoints(c, g["plan"], db, ph, sp, 3, 5, 300, R=R)
+    assert ok >= 0.999 * n
+
+
+# ------------------------------------------------------ order independence --
+def _tallies(db, ph, sp, **cfg):
+    c = ctx_for(db, **cfg)
+    g = gpu_run(c, ph, sp)
+    return g["E"], g["E2"], g["escaped"]
+
+
+def test_launch_configs_bitwise():
+    ph = I.thorax_phantom((96, 96, 64), 0.3, seed=11)
+    rng = np.random.default_rng(1)
+    sp = I.field_spots((3.0, -1.0, 0.0), 0.0, 40, rng, histories=np.full(40, 1500, np.uint64))
+    db = W.multi_bin_db(2000)
+    ref = _tallies(db, ph, sp)
+    for cfg in [dict(waves_per_block=1), dict(waves_per_block=16), dict(waves_per_block=4, blocks_per_cu=2),
+                dict(waves_per_block=8, blocks_per_cu=8)]:
+        got = _tallies(db, ph, sp, **cfg)
+        assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1]) and got[2] == ref[2], cfg
+
+
+def test_split_runs_and_batching_bitwise():
+    """run(n) twice == run(2n) (history counters continue, unaligned h0), and
+    plans launched together == plans launched one by one."""
+    db = W.multi_bin_db(2000)
+    ph1 = I.thorax_phantom((80, 80, 40), 0.3, seed=1)
+    ph2 = I.slab_phantom(64, 0.2)
+    rng = np.random.default_rng(2)
+    sp1 = I.field_spots((2.0, 0.0, 0.0), 180.0, 9, rng, histories=np.full(9, 100, np.uint64))
+    sp2 = W.slab_spots(150)[::3]
+    c = ctx_for(db)
+    a1, a2 = c.load_phantom(ph1), c.load_phantom(ph2)
+    c.add_beam_spots(a1, sp1)
+    c.add_beam_spots(a2, sp2)
+    c.run_histories([a1, a2])
+    c.run_histories([a2, a1])
+    ra1 = c.read_dose_and_variance(a1, raw=True)
+    ra2 = c.read_dose_and_variance(a2, raw=True)
+    c2 = ctx_for(db)
+    b1 = c2.load_phantom(ph1)
+    sp1b = sp1.copy()
+    sp1b["n_histories"] = 200
+    c2.add_beam_spots(b1, sp1b)
+    c2.run_histories([b1])
+    b2 = c2.load_phantom(ph2)
+    sp2b = sp2.copy()
+    sp2b["n_histories"] = 300
+    c2.add_beam_spots(b2, sp2b)
+    c2.run_histories([b2])
+    rb1 = c2.read_dose_and_variance(b1, raw=True)
+    rb2 = c2.read_dose_and_variance(b2, raw=True)
+    assert np.array_equal(ra1["E"], rb1["E"]) and np.array_equal(ra1["E2"], rb1["E2"])
+    assert np.array_equal(ra2["E"], rb2["E"]) and np.array_equal(ra2["E2"], rb2["E2"])
+    o = O.replay(db, ph1, sp1b, seed=SEED, plan=0)
+    assert ra1["incident"] == o["incident"]
+
+
+# ------------------------------------------------------------ edge cases ----
+def test_edge_cases():
+    db = W.multi_bin_db(2000)
+    ph = I.water_phantom((20, 20, 20), 0.5)
+    c = ctx_for(db)
+    p = c.load_phantom(ph)
+    # a spot aimed away from the box: every history misses, all energy escapes
+    c.add_beam_spots(p, I.spots([[0, 0, -2.0]], [[0, 0, -1.0]], [150.0], 0.3, 65))
+    c.run_histories([p])
+    r = c.read_dose_and_variance(p, raw=True)
+    assert r["E"].sum() == 0 and r["escaped"] == r["incident"] > 0
+    _, why = c.debug_endpoints(p, 0, 0, 65)
+    assert np.all(why == 2)
+    # a run with no histories is a no-op; reading a plan that never ran is an error
+    q = c.load_phantom(ph)
+    c.add_beam_spots(q, I.spots([[0, 0, -1.0]], [[0, 0, 1.0]], [100.0], 0.3, 0))
+    c.run_histories([q])
+    with pytest.raises(F.FdcError):
+        c.read_dose_and_variance(q)
+    # ragged history counts and spot energies exactly on / between bins
+    for n in (1, 63, 64, 65, 129):
+        sp = I.spots([[0.3, 0, -1.0], [0, 0.2, -1.0]], [[0, 0, 1.0], [0, 0, 1.0]], [70.0, 71.3], 0.4, n)
+        pl = c.load_phantom(ph)
+        c.add_beam_spots(pl, sp)
+        c.run_histories([pl])
+        g = c.read_dose_and_variance(pl, raw=True)
+        o = O.replay(db, ph, sp, seed=SEED, plan=pl)
+        assert g["incident"] == o["incident"] and g["deposited"] + g["escaped"] == g["incident"]
+        assert np.abs(g["E"] - o["E"]).sum() <= 1e-5 * o["incident"]
+
+
+# ------------------------------------------------------ full-size checks ----
+def test_full_size_slab_sampled():
+    """The 1e7-history slab workload in the benchmark's launch configuration:
+    energy identity exactly, sampled end points against the oracle."""
+    ph, sp, db = W.slab()
+    c = ctx_for(db, waves_per_block=4, blocks_per_cu=0)
+    g = gpu_run(c, ph, sp, flags=0)
+    assert g["n_histories"] == 10_000_000
+    assert g["deposited"] + g["escaped"] == g["incident"]
+    tot = good = 0
+    for s in range(0, 25, 2):
+        ok, n = check_endpoints(c, g["plan"], db, ph, sp, s, 400_000 - 96, 96)
+        good += ok
+        tot += n
+    assert good >= 0.999 * tot
