@@ -51,6 +51,13 @@ def build(verbose=False):
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stderr}")
     os.replace(tmp, LIB)
+    # stand-alone microbenchmarks of the HBM / atomic ceilings
+    mb = os.path.join(PKG, "fdc_microbench")
+    r = subprocess.run([cc, *FLAGS, os.path.join(CSRC, "microbench.hip"), "-o", mb + ".tmp"],
+                       capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"hipcc failed on microbench.hip:\n{r.stderr}")
+    os.replace(mb + ".tmp", mb)
     return LIB
 
 

@@ -1,0 +1,145 @@
+"""The C-ABI library on the CPU: it loads, exports every entry point declared
+in include/fdc.h, and its argument checks and host bookkeeping behave as
+documented (through a context created with FDC_NO_DEVICE; nothing here
+launches a kernel)."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1011_2188_amd import fdc as F
+from paper_1011_2188_amd import inputs as I
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    txt = open(os.path.join(ROOT, "include", "fdc.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(fdc_[a-z_0-9]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = F.lib()
+    names = _declared()
+    assert len(names) >= 17
+    for n in names:
+        assert hasattr(lib, n), n
+    assert sorted(F.EXPORTS) == names
+
+
+def test_create_arguments():
+    rc, h = F.fdc_create(F.FDC_NO_DEVICE, 1, 0)
+    assert rc == F.FDC_E_ARG
+    assert F.lib().fdc_create(None, F.FDC_NO_DEVICE, 1, 64) == F.FDC_E_ARG
+    rc, h = F.fdc_create(12345, 1, 64)          # no such device (or no GPU at all)
+    assert rc == F.FDC_E_HIP
+
+
+@pytest.fixture
+def ctx():
+    c = F.Context(device=F.FDC_NO_DEVICE)
+    yield c
+    c.close()
+
+
+def _db(n_tracks=3):
+    return I.make_water_track_db([100.0, 105.0], n_tracks, seed=1)
+
+
+def _expect(code, fn, *a, **k):
+    with pytest.raises(F.FdcError) as e:
+        fn(*a, **k)
+    assert e.value.code == code, str(e.value)
+    return str(e.value)
+
+
+def test_track_db_validation(ctx):
+    db = _db()
+    ctx.load_track_db(db)
+
+    def bad(mut):
+        d = I.TrackDB(db.steps.copy(), db.track_off.copy(), db.bin_E.copy(), db.bin_first.copy())
+        mut(d)
+        return d
+    _expect(F.FDC_E_FORMAT, ctx.load_track_db, bad(lambda d: d.steps.__setitem__((5, 0), 0.0)))
+    _expect(F.FDC_E_FORMAT, ctx.load_track_db, bad(lambda d: d.steps.__setitem__((5, 1), -1.0)))
+    _expect(F.FDC_E_FORMAT, ctx.load_track_db, bad(lambda d: d.steps.__setitem__((2, 2), np.nan)))
+    _expect(F.FDC_E_FORMAT, ctx.load_track_db, bad(lambda d: d.track_off.__setitem__(2, d.track_off[1])))
+    _expect(F.FDC_E_FORMAT, ctx.load_track_db, bad(lambda d: d.track_off.__setitem__(-1, d.track_off[-1] - 1)))
+    _expect(F.FDC_E_FORMAT, ctx.load_track_db, bad(lambda d: d.bin_E.__setitem__(1, 99.0)))
+    _expect(F.FDC_E_FORMAT, ctx.load_track_db, bad(lambda d: d.bin_first.__setitem__(1, 0)))
+    lib = F.lib()
+    assert lib.fdc_load_track_db(ctx.h, None, 1, None, 1, None, None, 1, None) == F.FDC_E_ARG
+    assert "NULL" in F.fdc_last_error(ctx.h)
+
+
+def test_phantom_and_table_validation(ctx):
+    ph = I.water_phantom((4, 4, 4), 0.5)
+    p = ctx.load_phantom(ph)
+    assert p == 0
+    bad = I.Phantom(ph.hu, np.array([0.5, -0.5, 0.5], np.float32), ph.origin_cm)
+    _expect(F.FDC_E_ARG, ctx.load_phantom, bad)
+    bad = I.Phantom(ph.hu, ph.voxel_cm, np.array([np.inf, 0, 0], np.float32))
+    _expect(F.FDC_E_ARG, ctx.load_phantom, bad)
+    t = dict(I.HU_TABLE_DEFAULT)
+    ctx.set_hu_table(t)
+    t2 = dict(t, hu=np.array([-1000.0, 0.0, 0.0, 3071.0]))
+    _expect(F.FDC_E_ARG, ctx.set_hu_table, t2)
+    t3 = dict(t, rsp=np.array([0.1, -1.0, 1.5, 2.6]))
+    _expect(F.FDC_E_ARG, ctx.set_hu_table, t3)
+
+
+def test_spots_and_run_validation(ctx):
+    ph = I.water_phantom((4, 4, 4), 0.5)
+    p = ctx.load_phantom(ph)
+    sp = I.spots([[0, 0, -1]], [[0, 0, 1]], [101.0], 0.3, 100)
+    _expect(F.FDC_E_STATE, ctx.add_beam_spots, p, sp)        # no database yet
+    _expect(F.FDC_E_STATE, ctx.run_histories, [p])
+    ctx.load_track_db(_db())
+    ctx.add_beam_spots(p, sp)
+    _expect(F.FDC_E_RANGE, ctx.add_beam_spots, p, I.spots([[0, 0, -1]], [[0, 0, 1]], [99.9], 0.3, 1))
+    _expect(F.FDC_E_RANGE, ctx.add_beam_spots, p, I.spots([[0, 0, -1]], [[0, 0, 1]], [105.1], 0.3, 1))
+    _expect(F.FDC_E_ARG, ctx.add_beam_spots, p, I.spots([[0, 0, -1]], [[0, 0, 0]], [101.0], 0.3, 1))
+    _expect(F.FDC_E_ARG, ctx.add_beam_spots, p, I.spots([[0, 0, -1]], [[0, 0, 1]], [101.0], -0.3, 1))
+    _expect(F.FDC_E_ARG, ctx.add_beam_spots, p, I.spots([[np.nan, 0, -1]], [[0, 0, 1]], [101.0], 0.3, 1))
+    _expect(F.FDC_E_ARG, ctx.add_beam_spots, 7, sp)
+    _expect(F.FDC_E_ARG, ctx.run_histories, [p, p])
+    _expect(F.FDC_E_ARG, ctx.run_histories, [3])
+    _expect(F.FDC_E_ARG, ctx.run_histories, [p], 1 << 5)
+    ctx.run_histories([p], 0)
+    # reading needs a device; a variance read after a run without the flag is refused first
+    _expect(F.FDC_E_STATE, ctx.read_dose_and_variance, p, True, True)
+    _expect(F.FDC_E_STATE, ctx.read_dose_and_variance, p, True, False)
+    _expect(F.FDC_E_STATE, ctx.debug_endpoints, p, 0, 0, 4)
+
+
+def test_overflow_guard(ctx):
+    ctx.load_track_db(_db())
+    p = ctx.load_phantom(I.water_phantom((2, 2, 2), 1.0))
+    # 105 MeV = 1.76e9 fixed-point units; 6e9 histories would pass 2^63
+    ctx.add_beam_spots(p, I.spots([[0, 0, -1]], [[0, 0, 1]], [101.0], 0.3, 6_000_000_000))
+    _expect(F.FDC_E_OVERFLOW, ctx.run_histories, [p])
+    q = ctx.load_phantom(I.water_phantom((2, 2, 2), 1.0))
+    ctx.add_beam_spots(q, I.spots([[0, 0, -1]], [[0, 0, 1]], [101.0], 0.3, 2_000_000_000))
+    ctx.run_histories([q])
+    ctx.run_histories([q])
+    _expect(F.FDC_E_OVERFLOW, ctx.run_histories, [q])      # cumulative count is guarded
+    ctx.reset_plan(q)
+    ctx.run_histories([q])
+
+
+def test_launch_config_validation(ctx):
+    ctx.set_launch_config(8, 4)
+    _expect(F.FDC_E_ARG, ctx.set_launch_config, 0, 0)
+    _expect(F.FDC_E_ARG, ctx.set_launch_config, 17, 0)
+    _expect(F.FDC_E_ARG, ctx.set_launch_config, 4, 65)
+    assert ctx.device_cus() > 0
+
+
+def test_allocator_hooks_rules(ctx):
+    lib = F.lib()
+    keep = F.ALLOC_FN(lambda n, u: None)
+    assert lib.fdc_set_allocator(ctx.h, keep, F.FREE_FN(), None) == F.FDC_E_ARG
