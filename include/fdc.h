@@ -39,6 +39,7 @@ extern "C" {
 #endif
 
 typedef struct fdc_ctx fdc_ctx;
+typedef struct fdc_graph fdc_graph;
 
 enum {
     FDC_OK = 0,
@@ -55,6 +56,12 @@ enum {
  * check and all host-side bookkeeping run, nothing is sent to a device, and
  * calls that must produce device results return FDC_E_STATE. */
 #define FDC_NO_DEVICE (-1)
+
+/* fdc_graph_create options */
+enum {
+    FDC_GRAPH_RESET_TALLIES = 1u,   /* clear the plans' tallies at the start of each launch  */
+    FDC_GRAPH_DOSE = 2u             /* end each launch with dose (and variance) per plan       */
+};
 
 /* run flags */
 enum {
@@ -92,7 +99,13 @@ typedef struct {
     uint32_t waves_per_block;   /* 1..16, default 4                                    */
     uint32_t blocks_per_cu;     /* persistent grid size = blocks_per_cu * CUs; 0 = one
                                    block per work unit (non-persistent)                */
-    uint32_t reserved[6];
+    uint32_t tally_slots;       /* 0: flush visits with global atomics; else a power of
+                                   two 256..8192: per-workgroup LDS sub-tally with that
+                                   many slots (persistent rounds; blocks_per_cu 0 is
+                                   taken as 1)                                        */
+    uint32_t units_per_wave;    /* with tally_slots: 64-history units per wave per
+                                   round, 1..64 (0 is taken as 1)                      */
+    uint32_t reserved[4];
 } fdc_launch_config;
 
 typedef void *(*fdc_alloc_fn)(size_t bytes, void *user);
@@ -177,6 +190,30 @@ int fdc_add_beam_spots(fdc_ctx *ctx, int32_t plan, const fdc_spot *spots, uint32
 int fdc_run_histories(fdc_ctx *ctx, const int32_t *plans, uint32_t n_plans, uint32_t flags,
                       void *hip_stream);
 
+/* Capture one fdc_run_histories pass over n_plans plans (plus, with options,
+ * clearing the tallies first and computing dose and variance after) as a HIP
+ * graph, for repeated launches with one call each.  The plans' spots, the
+ * launch configuration and the outputs are fixed at capture; every launch runs
+ * each spot's n_histories NEXT histories (the history counters live on the
+ * device and advance inside the graph), so replays are new work with the same
+ * random-number identity as eager runs.  dose_dev / var_dev: arrays of
+ * n_plans DEVICE pointers (nx*ny*nz doubles each, either array may be NULL)
+ * used with FDC_GRAPH_DOSE.  No memory is allocated by a launch.  A graph
+ * becomes stale when a phantom, spots or a database is loaded afterwards
+ * (launch then returns FDC_E_STATE).  Errors: as fdc_run_histories, plus
+ * FDC_E_ARG (bad options), FDC_E_STATE (no device; variance output without
+ * FDC_RUN_VARIANCE history), FDC_E_HIP. */
+int fdc_graph_create(fdc_ctx *ctx, const int32_t *plans, uint32_t n_plans, uint32_t flags, uint32_t options,
+                     double *const *dose_dev, double *const *var_dev, fdc_graph **out);
+
+/* Launch a captured graph on hip_stream (asynchronous).  Errors: FDC_E_ARG,
+ * FDC_E_STATE (stale graph), FDC_E_OVERFLOW (without FDC_GRAPH_RESET_TALLIES,
+ * as fdc_run_histories), FDC_E_HIP. */
+int fdc_graph_launch(fdc_graph *graph, void *hip_stream);
+
+/* Wait for the device, then free the graph and its work table. */
+int fdc_graph_destroy(fdc_graph *graph);
+
 /* Zero a plan's tallies and summary (asynchronous).  The history counters keep
  * running unless rewind is non-zero, in which case the next run repeats the
  * same histories from h = 0.  Errors: FDC_E_ARG. */
@@ -218,8 +255,44 @@ int fdc_debug_philox(fdc_ctx *ctx, const uint32_t *ctr, uint32_t *out, uint32_t 
 int fdc_debug_material(fdc_ctx *ctx, float *rsp_out, float *g_out, float *rho_out, void *hip_stream);
 
 /* Launch knobs for fdc_run_histories (see fdc_launch_config).  Results are
- * bitwise identical for every valid setting.  Errors: FDC_E_ARG. */
+ * bitwise identical for every valid setting.  Errors: FDC_E_ARG (out of range,
+ * or an LDS sub-tally that does not fit next to the 32 KB material table:
+ * 12 B per slot, 20 B with the squared-energy tally, at most 160 KB in all). */
 int fdc_set_launch_config(fdc_ctx *ctx, const fdc_launch_config *cfg);
+
+/* Mean dose uncertainty (Section 2.4): the mean of sqrt(var)/dose over the
+ * plan's non-vacuum voxels whose dose exceeds frac * Dmax (frac = 0.5 in the
+ * paper), Dmax taken over non-vacuum voxels.  dose_dev / var_dev: DEVICE
+ * arrays of the plan's voxel count (e.g. from fdc_compute_dose).  Host
+ * outputs: *mean_out, and optionally the number of voxels averaged and Dmax.
+ * Reductions run in a fixed order (reproducible).  Synchronises hip_stream.
+ * Errors: FDC_E_ARG, FDC_E_STATE (no device), FDC_E_NOMEM, FDC_E_HIP. */
+int fdc_mean_uncertainty(fdc_ctx *ctx, int32_t plan, const double *dose_dev, const double *var_dev, double frac,
+                         double *mean_out, uint64_t *n_out, double *dmax_out, void *hip_stream);
+
+/* Batch uncertainty, Eq. (1): for n_batches >= 2 dose arrays stored back to
+ * back in doses_dev (DEVICE, n_batches * n_vox doubles), per voxel the mean
+ * and sqrt(sum_i (D_i - mean)^2 / (n (n - 1))) into DEVICE arrays mean_dev /
+ * sigma_dev (either may be NULL).  Asynchronous.  Errors: FDC_E_ARG,
+ * FDC_E_STATE (no device), FDC_E_HIP. */
+int fdc_batch_uncertainty(fdc_ctx *ctx, const double *doses_dev, uint32_t n_batches, uint64_t n_vox,
+                          double *mean_dev, double *sigma_dev, void *hip_stream);
+
+/* Gamma index (Low et al. 1998; Section 2.4 uses 3%/3 mm, pass when gamma <=
+ * 1) of the evaluated dose eval_dev against the reference ref_dev (DEVICE
+ * arrays on the plan's grid).  Global dose criterion dose_frac * Dmax(ref),
+ * distance criterion dta_cm; reference voxels that are vacuum or below
+ * cutoff_frac * Dmax are not evaluated.  For each evaluated voxel, gamma is the
+ * minimum over points of the evaluated dose upsampled twice per axis by
+ * trilinear interpolation within search_cm of
+ * sqrt(r^2 / dta^2 + (D_e - D_r)^2 / (dose_frac * Dmax)^2).  gamma_dev
+ * (DEVICE floats, may be NULL) receives gamma per voxel (-1 where not
+ * evaluated); *pass_rate_out the fraction of evaluated voxels with gamma <= 1.
+ * Synchronises hip_stream.  Errors: FDC_E_ARG, FDC_E_STATE, FDC_E_NOMEM,
+ * FDC_E_HIP. */
+int fdc_gamma_index(fdc_ctx *ctx, int32_t plan, const double *ref_dev, const double *eval_dev, double dose_frac,
+                    double dta_cm, double cutoff_frac, double search_cm, float *gamma_dev, double *pass_rate_out,
+                    uint64_t *n_eval_out, void *hip_stream);
 
 /* Number of compute units of the context's device (for launch sizing). */
 int fdc_device_cus(fdc_ctx *ctx, int *cus);

@@ -220,3 +220,53 @@ def batch_uncertainty(doses):
     n = D.shape[0]
     mean = D.mean(axis=0)
     return mean, np.sqrt(((D - mean) ** 2).sum(axis=0) / (n * (n - 1)))
+
+
+def _upsample2(a):
+    """Trilinear interpolation at half-voxel spacing: along each axis the new
+    points are the voxel values and the midpoints between neighbours."""
+    for ax in range(3):
+        a = np.moveaxis(a, ax, 0)
+        n = a.shape[0]
+        u = np.empty((2 * n - 1,) + a.shape[1:])
+        u[0::2] = a
+        u[1::2] = 0.5 * (a[:-1] + a[1:])
+        a = np.moveaxis(u, 0, ax)
+    return a
+
+
+def gamma_index(ref, ev, ph, dose_frac=0.02, dta_cm=0.2, cutoff_frac=0.1, search_cm=0.6, table=None):
+    """Gamma index (Low et al. 1998), global dose criterion dose_frac * Dmax(ref).
+
+    Evaluated voxels: non-vacuum reference voxels with D >= cutoff_frac * Dmax.
+    gamma = min over points p of the evaluated dose upsampled twice per axis
+    (trilinear) within search_cm of sqrt(|r - p|^2 / dta^2 + (D_e(p) - D_r)^2 /
+    (dose_frac * Dmax)^2).  Returns (gamma array with -1 where not evaluated,
+    pass rate = fraction of evaluated voxels with gamma <= 1)."""
+    ref = np.asarray(ref, np.float64)
+    ev = np.asarray(ev, np.float64)
+    _, vac = voxel_mass_kg(ph, table)
+    dmax = ref[~vac].max()
+    sel = (~vac) & (ref >= cutoff_frac * dmax)
+    U = _upsample2(ev)
+    nz, ny, nx = ref.shape
+    vx, vy, vz = (float(v) for v in ph.voxel_cm)
+    z, y, x = np.nonzero(sel)
+    dr = ref[sel]
+    best = np.full(dr.shape, np.inf)
+    rx, ry, rz = (int(np.floor(search_cm / (0.5 * v) + 1e-9)) for v in (vx, vy, vz))
+    for c in range(-rz, rz + 1):
+        for b in range(-ry, ry + 1):
+            for a in range(-rx, rx + 1):
+                d2 = (a * 0.5 * vx) ** 2 + (b * 0.5 * vy) ** 2 + (c * 0.5 * vz) ** 2
+                if d2 > search_cm ** 2 * (1 + 1e-12):
+                    continue
+                pz, py, px = 2 * z + c, 2 * y + b, 2 * x + a
+                ok = (pz >= 0) & (py >= 0) & (px >= 0) & (pz <= 2 * nz - 2) & (py <= 2 * ny - 2) & (px <= 2 * nx - 2)
+                e = np.zeros_like(dr)
+                e[ok] = U[pz[ok], py[ok], px[ok]]
+                g2 = d2 / dta_cm ** 2 + (e - dr) ** 2 / (dose_frac * dmax) ** 2
+                best = np.where(ok, np.minimum(best, g2), best)
+    g = np.full(ref.shape, -1.0)
+    g[sel] = np.sqrt(best)
+    return g, float(np.mean(g[sel] <= 1.0)) if sel.any() else 0.0

@@ -82,6 +82,8 @@ struct fdc_ctx {
     bool plans_dirty = true;
     DevSpot *d_spots = nullptr;
     size_t d_spots_cap = 0;
+    unsigned long long *d_hnext = nullptr;   // per DevSpot: next history index
+    uint64_t gen = 1;                        // bumped whenever device tables move
     std::vector<uint32_t> spot_base;
     bool spots_dirty = true;
 
@@ -98,6 +100,18 @@ struct fdc_ctx {
     size_t dose_cap = 0;
 
     fdc_launch_config cfg{};
+    hipStream_t cap_stream = nullptr;        // for graph capture
+};
+
+struct fdc_graph {
+    fdc_ctx *ctx = nullptr;
+    uint64_t gen = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    WorkItem *d_items = nullptr;
+    std::vector<int32_t> plans;
+    uint32_t flags = 0;
+    bool reset = false;
 };
 
 namespace {
@@ -238,19 +252,29 @@ int ensure_spots(fdc_ctx *ctx)
         }
     }
     ctx->spot_base[ctx->plans.size()] = (uint32_t)all.size();
+    std::vector<unsigned long long> hn;
+    for (const PlanHost &P : ctx->plans) hn.insert(hn.end(), P.h_next.begin(), P.h_next.end());
     if (all.size() > ctx->d_spots_cap) {
         DevSpot *n = dalloc_n<DevSpot>(ctx, all.size());
-        if (!n) return fail(ctx, FDC_E_NOMEM, "spot table: device allocation failed");
+        unsigned long long *h = dalloc_n<unsigned long long>(ctx, all.size());
+        if (!n || !h) {
+            dfree(ctx, n); dfree(ctx, h);
+            return fail(ctx, FDC_E_NOMEM, "spot table: device allocation failed");
+        }
         HIPCHK(hipDeviceSynchronize());
         dfree(ctx, ctx->d_spots);
+        dfree(ctx, ctx->d_hnext);
         ctx->d_spots = n;
+        ctx->d_hnext = h;
         ctx->d_spots_cap = all.size();
     }
     if (!all.empty()) {
         HIPCHK(hipDeviceSynchronize());
         HIPCHK(hipMemcpy(ctx->d_spots, all.data(), all.size() * sizeof(DevSpot), hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(ctx->d_hnext, hn.data(), hn.size() * 8, hipMemcpyHostToDevice));
     }
     ctx->spots_dirty = false;
+    ctx->gen++;
     return FDC_OK;
 }
 
@@ -285,6 +309,7 @@ int ensure_plans(fdc_ctx *ctx)
     HIPCHK(hipDeviceSynchronize());
     HIPCHK(hipMemcpy(ctx->d_plans, all.data(), all.size() * sizeof(DevPlan), hipMemcpyHostToDevice));
     ctx->plans_dirty = false;
+    ctx->gen++;
     return FDC_OK;
 }
 
@@ -325,6 +350,7 @@ TransportArgs base_args(const fdc_ctx *ctx)
     a.plans = ctx->d_plans;
     a.spots = ctx->d_spots;
     a.items = ctx->d_items;
+    a.hnext = ctx->d_hnext;
     a.lut = ctx->lut;
     a.seed_lo = (uint32_t)ctx->seed;
     a.seed_hi = (uint32_t)(ctx->seed >> 32);
@@ -368,6 +394,7 @@ int fdc_create(fdc_ctx **out, int hip_device, uint64_t seed, uint32_t reuse_R)
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, hip_device) == hipSuccess) ctx->cus = prop.multiProcessorCount;
     if (hipEventCreateWithFlags(&ctx->items_ev, hipEventDisableTiming) != hipSuccess) { delete ctx; return FDC_E_HIP; }
+    if (prepare_lds_kernels() != hipSuccess) { (void)hipEventDestroy(ctx->items_ev); delete ctx; return FDC_E_HIP; }
     *out = ctx;
     return FDC_OK;
 }
@@ -384,6 +411,8 @@ int fdc_destroy(fdc_ctx *ctx)
     dfree(ctx, ctx->steps); dfree(ctx, ctx->track_off); dfree(ctx, ctx->track_T); dfree(ctx, ctx->bin_first);
     dfree(ctx, ctx->lut); dfree(ctx, ctx->rho_lut);
     dfree(ctx, ctx->d_plans); dfree(ctx, ctx->d_spots); dfree(ctx, ctx->d_items); dfree(ctx, ctx->d_queue);
+    dfree(ctx, ctx->d_hnext);
+    if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
     dfree(ctx, ctx->d_dose); dfree(ctx, ctx->d_var);
     if (ctx->h_items) (void)hipHostFree(ctx->h_items);
     if (ctx->items_ev) (void)hipEventDestroy(ctx->items_ev);
@@ -524,6 +553,7 @@ int fdc_load_track_db(fdc_ctx *ctx, const fdc_step *steps, uint64_t n_steps, con
     ctx->n_tracks = n_tracks;
     ctx->n_bins = n_bins;
     ctx->spots_dirty = true;
+    ctx->gen++;
     return FDC_OK;
 }
 
@@ -595,9 +625,8 @@ int fdc_add_beam_spots(fdc_ctx *ctx, int32_t plan, const fdc_spot *spots, uint32
     return FDC_OK;
 }
 
-int fdc_run_histories(fdc_ctx *ctx, const int32_t *plans, uint32_t n_plans, uint32_t flags, void *hip_stream)
+static int validate_run(fdc_ctx *ctx, const int32_t *plans, uint32_t n_plans, uint32_t flags, uint64_t launches)
 {
-    if (!ctx) return FDC_E_ARG;
     if (n_plans && !plans) return fail(ctx, FDC_E_ARG, "run: NULL plan list");
     if (flags & ~(uint32_t)(FDC_RUN_VARIANCE | FDC_RUN_ROTATE_TRACKS)) return fail(ctx, FDC_E_ARG, "run: unknown flag");
     if (ctx->n_bins == 0) return fail(ctx, FDC_E_STATE, "run: no track database loaded");
@@ -611,79 +640,227 @@ int fdc_run_histories(fdc_ctx *ctx, const int32_t *plans, uint32_t n_plans, uint
     for (uint32_t i = 0; i < n_plans; ++i) {
         const PlanHost &P = ctx->plans[plans[i]];
         double nh = (double)P.n_hist;
-        for (const fdc_spot &s : P.spots) nh += (double)s.n_histories;
+        for (const fdc_spot &s : P.spots) nh += (double)s.n_histories * (double)launches;
         if (nh * emax >= 9.2e18) return fail(ctx, FDC_E_OVERFLOW, "run: plan %d would exceed the int64 tally", plans[i]);
     }
-    if (ctx->dry) {
-        for (uint32_t i = 0; i < n_plans; ++i) {
-            PlanHost &P = ctx->plans[plans[i]];
-            for (size_t j = 0; j < P.spots.size(); ++j) {
-                P.h_next[j] += P.spots[j].n_histories;
-                P.n_hist += P.spots[j].n_histories;
-                if (P.spots[j].n_histories && !(flags & FDC_RUN_VARIANCE)) P.var_complete = false;
-            }
-        }
-        return FDC_OK;
-    }
-    HIPCHK(hipSetDevice(ctx->device));
-    int rc = ensure_plans(ctx);
-    if (!rc) rc = ensure_spots(ctx);
-    if (rc) return rc;
-    hipStream_t s = S(hip_stream);
-    size_t n_items = 0;
-    for (uint32_t i = 0; i < n_plans; ++i)
-        for (const fdc_spot &sp : ctx->plans[plans[i]].spots) n_items += sp.n_histories > 0;
-    if (n_items == 0) return FDC_OK;
-    rc = ensure_items(ctx, n_items, s);
-    if (rc) return rc;
-    unsigned long long units = 0;
-    size_t k = 0;
-    for (uint32_t i = 0; i < n_plans; ++i) {
-        const PlanHost &P = ctx->plans[plans[i]];
-        for (size_t j = 0; j < P.spots.size(); ++j) {
-            const uint64_t n = P.spots[j].n_histories;
-            if (!n) continue;
-            WorkItem &w = ctx->h_items[k++];
-            w.h0 = P.h_next[j];
-            w.h_end = P.h_next[j] + n;
-            w.unit0 = units;
-            w.gspot = ctx->spot_base[plans[i]] + (uint32_t)j;
-            w.pad = 0;
-            units += (w.h_end - 1) / kWave - w.h0 / kWave + 1;
-        }
-    }
-    HIPCHK(hipMemcpyAsync(ctx->d_items, ctx->h_items, n_items * sizeof(WorkItem), hipMemcpyHostToDevice, s));
-    HIPCHK(hipEventRecord(ctx->items_ev, s));
-    ctx->items_ev_pending = true;
+    return FDC_OK;
+}
 
-    TransportArgs a = base_args(ctx);
-    a.n_items = (uint32_t)n_items;
-    a.n_units = units;
-    a.flags = flags;
-    const uint32_t wpb = ctx->cfg.waves_per_block;
-    uint32_t grid;
-    if (ctx->cfg.blocks_per_cu) {
-        if (!ctx->d_queue) {
-            ctx->d_queue = dalloc_n<unsigned long long>(ctx, 1);
-            if (!ctx->d_queue) return fail(ctx, FDC_E_NOMEM, "run: queue allocation failed");
-        }
-        HIPCHK(hipMemsetAsync(ctx->d_queue, 0, 8, s));
-        a.queue = ctx->d_queue;
-        grid = ctx->cfg.blocks_per_cu * (uint32_t)ctx->cus;
-    } else {
-        const unsigned long long g = (units + wpb - 1) / wpb;
-        if (g > 0x7fffffffull) return fail(ctx, FDC_E_ARG, "run: too many work units for one launch");
-        grid = (uint32_t)g;
-    }
-    HIPCHK(launch_transport(a, wpb, grid, (flags & FDC_RUN_VARIANCE) != 0, false, s));
+// host bookkeeping of a launched run (the device counters advance by themselves)
+static void account_run(fdc_ctx *ctx, const int32_t *plans, uint32_t n_plans, uint32_t flags, bool reset)
+{
     for (uint32_t i = 0; i < n_plans; ++i) {
         PlanHost &P = ctx->plans[plans[i]];
+        if (reset) {
+            P.n_hist = 0;
+            P.var_complete = true;
+        }
         for (size_t j = 0; j < P.spots.size(); ++j) {
             P.h_next[j] += P.spots[j].n_histories;
             P.n_hist += P.spots[j].n_histories;
             if (P.spots[j].n_histories && !(flags & FDC_RUN_VARIANCE)) P.var_complete = false;
         }
     }
+}
+
+static unsigned long long build_items(const fdc_ctx *ctx, const int32_t *plans, uint32_t n_plans,
+                                      std::vector<WorkItem> &items)
+{
+    unsigned long long units = 0;
+    items.clear();
+    for (uint32_t i = 0; i < n_plans; ++i) {
+        const PlanHost &P = ctx->plans[plans[i]];
+        for (size_t j = 0; j < P.spots.size(); ++j) {
+            const uint64_t n = P.spots[j].n_histories;
+            if (!n) continue;
+            WorkItem w{};
+            w.h0 = 0;                              // the spot's device counter is added
+            w.n = n;
+            w.unit0 = units;
+            w.gspot = ctx->spot_base[plans[i]] + (uint32_t)j;
+            items.push_back(w);
+            units += units_for(n);
+        }
+    }
+    return units;
+}
+
+// transport launch for a work table already on the device; the queue counter
+// is cleared with a kernel so that the sequence can be captured in a graph
+static int enqueue_transport(fdc_ctx *ctx, TransportArgs a, uint32_t flags, hipStream_t s)
+{
+    const uint32_t wpb = ctx->cfg.waves_per_block;
+    const bool variance = (flags & FDC_RUN_VARIANCE) != 0;
+    if (ctx->cfg.tally_slots &&
+        kLutSize * sizeof(float2) + 64 + lds_tally_bytes(ctx->cfg.tally_slots, variance) > kMaxLdsBytes)
+        return fail(ctx, FDC_E_ARG, "run: LDS sub-tally of %u slots with the squared-energy tally does not fit",
+                    ctx->cfg.tally_slots);
+    const bool persistent = ctx->cfg.tally_slots || ctx->cfg.blocks_per_cu;
+    if (persistent) {
+        if (!ctx->d_queue) {
+            ctx->d_queue = dalloc_n<unsigned long long>(ctx, 1);
+            if (!ctx->d_queue) return fail(ctx, FDC_E_NOMEM, "run: queue allocation failed");
+        }
+        HIPCHK(launch_fill_u64(ctx->d_queue, 1, 0, s));
+        a.queue = ctx->d_queue;
+    }
+    if (ctx->cfg.tally_slots) {
+        const uint32_t grid = std::max<uint32_t>(1, ctx->cfg.blocks_per_cu) * (uint32_t)ctx->cus;
+        HIPCHK(launch_transport_lds(a, wpb, grid, ctx->cfg.tally_slots, std::max<uint32_t>(1, ctx->cfg.units_per_wave),
+                                    variance, s));
+    } else if (ctx->cfg.blocks_per_cu) {
+        HIPCHK(launch_transport(a, wpb, ctx->cfg.blocks_per_cu * (uint32_t)ctx->cus, variance, false, s));
+    } else {
+        const unsigned long long g = (a.n_units + wpb - 1) / wpb;
+        if (g > 0x7fffffffull) return fail(ctx, FDC_E_ARG, "run: too many work units for one launch");
+        HIPCHK(launch_transport(a, wpb, (uint32_t)g, variance, false, s));
+    }
+    return FDC_OK;
+}
+
+int fdc_run_histories(fdc_ctx *ctx, const int32_t *plans, uint32_t n_plans, uint32_t flags, void *hip_stream)
+{
+    if (!ctx) return FDC_E_ARG;
+    int rc = validate_run(ctx, plans, n_plans, flags, 1);
+    if (rc) return rc;
+    if (ctx->dry) {
+        account_run(ctx, plans, n_plans, flags, false);
+        return FDC_OK;
+    }
+    HIPCHK(hipSetDevice(ctx->device));
+    rc = ensure_plans(ctx);
+    if (!rc) rc = ensure_spots(ctx);
+    if (rc) return rc;
+    hipStream_t s = S(hip_stream);
+    std::vector<WorkItem> items;
+    const unsigned long long units = build_items(ctx, plans, n_plans, items);
+    if (items.empty()) return FDC_OK;
+    rc = ensure_items(ctx, items.size(), s);
+    if (rc) return rc;
+    std::copy(items.begin(), items.end(), ctx->h_items);
+    HIPCHK(hipMemcpyAsync(ctx->d_items, ctx->h_items, items.size() * sizeof(WorkItem), hipMemcpyHostToDevice, s));
+    HIPCHK(hipEventRecord(ctx->items_ev, s));
+    ctx->items_ev_pending = true;
+    TransportArgs a = base_args(ctx);
+    a.n_items = (uint32_t)items.size();
+    a.n_units = units;
+    a.flags = flags;
+    rc = enqueue_transport(ctx, a, flags, s);
+    if (rc) return rc;
+    HIPCHK(launch_advance(ctx->d_items, (uint32_t)items.size(), ctx->d_hnext, ctx->d_spots, ctx->d_plans, s));
+    account_run(ctx, plans, n_plans, flags, false);
+    return FDC_OK;
+}
+
+int fdc_graph_create(fdc_ctx *ctx, const int32_t *plans, uint32_t n_plans, uint32_t flags, uint32_t options,
+                     double *const *dose_dev, double *const *var_dev, fdc_graph **out)
+{
+    if (!ctx) return FDC_E_ARG;
+    if (!out) return fail(ctx, FDC_E_ARG, "graph: NULL output");
+    *out = nullptr;
+    if (options & ~(uint32_t)(FDC_GRAPH_RESET_TALLIES | FDC_GRAPH_DOSE)) return fail(ctx, FDC_E_ARG, "graph: unknown option");
+    if ((options & FDC_GRAPH_DOSE) && !dose_dev && !var_dev) return fail(ctx, FDC_E_ARG, "graph: dose option without outputs");
+    if ((options & FDC_GRAPH_DOSE) && var_dev && !(flags & FDC_RUN_VARIANCE))
+        return fail(ctx, FDC_E_ARG, "graph: variance output needs FDC_RUN_VARIANCE");
+    if ((options & FDC_GRAPH_DOSE) && var_dev && !(options & FDC_GRAPH_RESET_TALLIES))
+        for (uint32_t i = 0; i < n_plans; ++i)
+            if (valid_plan(ctx, plans[i]) && !ctx->plans[plans[i]].var_complete)
+                return fail(ctx, FDC_E_STATE, "graph: variance output but plan %d has runs without it", plans[i]);
+    int rc = validate_run(ctx, plans, n_plans, flags, 1);
+    if (rc) return rc;
+    if (ctx->dry) return fail(ctx, FDC_E_STATE, "graph: context has no device");
+    HIPCHK(hipSetDevice(ctx->device));
+    rc = ensure_plans(ctx);
+    if (!rc) rc = ensure_spots(ctx);
+    if (rc) return rc;
+    std::vector<WorkItem> items;
+    const unsigned long long units = build_items(ctx, plans, n_plans, items);
+    fdc_graph *g = new (std::nothrow) fdc_graph();
+    if (!g) return fail(ctx, FDC_E_NOMEM, "graph: host allocation failed");
+    g->ctx = ctx;
+    g->plans.assign(plans, plans + n_plans);
+    g->flags = flags;
+    g->reset = (options & FDC_GRAPH_RESET_TALLIES) != 0;
+    g->d_items = dalloc_n<WorkItem>(ctx, std::max<size_t>(items.size(), 1));
+    if (!g->d_items) { delete g; return fail(ctx, FDC_E_NOMEM, "graph: work table allocation failed"); }
+    auto cleanup = [&](int code, const char *what, hipError_t e) {
+        if (g->exec) (void)hipGraphExecDestroy(g->exec);
+        if (g->graph) (void)hipGraphDestroy(g->graph);
+        dfree(ctx, g->d_items);
+        delete g;
+        return fail(ctx, code, "graph: %s: %s", what, hipGetErrorString(e));
+    };
+    hipError_t e = hipSuccess;
+    if (!items.empty()) e = hipMemcpy(g->d_items, items.data(), items.size() * sizeof(WorkItem), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return cleanup(FDC_E_HIP, "work table upload", e);
+    if (!ctx->cap_stream) {
+        e = hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking);
+        if (e != hipSuccess) return cleanup(FDC_E_HIP, "stream", e);
+    }
+    if ((ctx->cfg.tally_slots || ctx->cfg.blocks_per_cu) && !ctx->d_queue) {
+        ctx->d_queue = dalloc_n<unsigned long long>(ctx, 1);     // no allocation inside the capture
+        if (!ctx->d_queue) return cleanup(FDC_E_NOMEM, "queue allocation", hipErrorOutOfMemory);
+    }
+    hipStream_t s = ctx->cap_stream;
+    e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return cleanup(FDC_E_HIP, "begin capture", e);
+    rc = FDC_OK;
+    for (uint32_t i = 0; i < n_plans && g->reset && e == hipSuccess; ++i) {
+        PlanHost &P = ctx->plans[plans[i]];
+        e = launch_fill_u64(P.E, P.nvox, 0, s);
+        if (e == hipSuccess) e = launch_fill_u64(P.E2, P.nvox, 0, s);
+        if (e == hipSuccess) e = launch_fill_u64(P.acc, 4, 0, s);
+    }
+    if (e == hipSuccess && !items.empty()) {
+        TransportArgs a = base_args(ctx);
+        a.items = g->d_items;
+        a.n_items = (uint32_t)items.size();
+        a.n_units = units;
+        a.flags = flags;
+        rc = enqueue_transport(ctx, a, flags, s);
+        if (!rc) e = launch_advance(g->d_items, (uint32_t)items.size(), ctx->d_hnext, ctx->d_spots, ctx->d_plans, s);
+    }
+    for (uint32_t i = 0; i < n_plans && (options & FDC_GRAPH_DOSE) && e == hipSuccess && !rc; ++i) {
+        PlanHost &P = ctx->plans[plans[i]];
+        const double vol = (double)P.vox[0] * (double)P.vox[1] * (double)P.vox[2];
+        e = launch_dose(P.idx, P.E, P.E2, ctx->lut, ctx->rho_lut, P.nvox, vol, P.acc + 3,
+                        dose_dev ? dose_dev[i] : nullptr, var_dev ? var_dev[i] : nullptr, s);
+    }
+    hipError_t e2 = hipStreamEndCapture(s, &g->graph);
+    if (rc) { std::string m = ctx->err; cleanup(rc, "capture", hipSuccess); ctx->err = m; return rc; }
+    if (e != hipSuccess) return cleanup(FDC_E_HIP, "captured launch", e);
+    if (e2 != hipSuccess) return cleanup(FDC_E_HIP, "end capture", e2);
+    e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) return cleanup(FDC_E_HIP, "instantiate", e);
+    g->gen = ctx->gen;
+    *out = g;
+    return FDC_OK;
+}
+
+int fdc_graph_launch(fdc_graph *g, void *hip_stream)
+{
+    if (!g) return FDC_E_ARG;
+    fdc_ctx *ctx = g->ctx;
+    if (g->gen != ctx->gen || ctx->spots_dirty || ctx->plans_dirty)
+        return fail(ctx, FDC_E_STATE, "graph: plans, spots or database changed since capture; capture again");
+    int rc = validate_run(ctx, g->plans.data(), (uint32_t)g->plans.size(), g->flags, 1);
+    if (rc && !(rc == FDC_E_OVERFLOW && g->reset)) return rc;
+    HIPCHK(hipSetDevice(ctx->device));
+    HIPCHK(hipGraphLaunch(g->exec, S(hip_stream)));
+    account_run(ctx, g->plans.data(), (uint32_t)g->plans.size(), g->flags, g->reset);
+    return FDC_OK;
+}
+
+int fdc_graph_destroy(fdc_graph *g)
+{
+    if (!g) return FDC_E_ARG;
+    fdc_ctx *ctx = g->ctx;
+    (void)hipSetDevice(ctx->device);
+    (void)hipDeviceSynchronize();
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    dfree(ctx, g->d_items);
+    delete g;
     return FDC_OK;
 }
 
@@ -695,9 +872,11 @@ int fdc_reset_plan(fdc_ctx *ctx, int32_t plan, int rewind, void *hip_stream)
     if (!ctx->dry) {
         HIPCHK(hipSetDevice(ctx->device));
         hipStream_t s = S(hip_stream);
-        HIPCHK(hipMemsetAsync(P.E, 0, P.nvox * 8, s));
-        HIPCHK(hipMemsetAsync(P.E2, 0, P.nvox * 8, s));
-        HIPCHK(hipMemsetAsync(P.acc, 0, 32, s));
+        HIPCHK(launch_fill_u64(P.E, P.nvox, 0, s));
+        HIPCHK(launch_fill_u64(P.E2, P.nvox, 0, s));
+        HIPCHK(launch_fill_u64(P.acc, 4, 0, s));
+        if (rewind && !ctx->spots_dirty && !P.spots.empty())
+            HIPCHK(launch_fill_u64(ctx->d_hnext + ctx->spot_base[plan], P.spots.size(), 0, s));
     }
     P.n_hist = 0;
     P.var_complete = true;
@@ -717,8 +896,8 @@ int fdc_compute_dose(fdc_ctx *ctx, int32_t plan, double *dose_dev, double *var_d
     if (ctx->dry) return fail(ctx, FDC_E_STATE, "dose: context has no device");
     HIPCHK(hipSetDevice(ctx->device));
     const double vol = (double)P.vox[0] * (double)P.vox[1] * (double)P.vox[2];
-    HIPCHK(launch_dose(nullptr, P.idx, P.E, P.E2, ctx->lut, ctx->rho_lut, P.nvox, vol, (double)P.n_hist,
-                       dose_dev, var_dev, S(hip_stream)));
+    HIPCHK(launch_dose(P.idx, P.E, P.E2, ctx->lut, ctx->rho_lut, P.nvox, vol, P.acc + 3, dose_dev, var_dev,
+                       S(hip_stream)));
     return FDC_OK;
 }
 
@@ -749,15 +928,15 @@ int fdc_read_dose_and_variance(fdc_ctx *ctx, int32_t plan, double *dose, double 
     }
     if (raw_E) HIPCHK(hipMemcpyAsync(raw_E, P.E, P.nvox * 8, hipMemcpyDeviceToHost, s));
     if (raw_E2) HIPCHK(hipMemcpyAsync(raw_E2, P.E2, P.nvox * 8, hipMemcpyDeviceToHost, s));
-    unsigned long long acc[3] = {0, 0, 0};
+    unsigned long long acc[4] = {0, 0, 0, 0};
     if (sum) {
-        HIPCHK(hipMemsetAsync(P.acc + 2, 0, 8, s));
+        HIPCHK(launch_fill_u64(P.acc + 2, 1, 0, s));
         HIPCHK(launch_sum_i64(P.E, P.nvox, P.acc + 2, s));
-        HIPCHK(hipMemcpyAsync(acc, P.acc, 24, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(acc, P.acc, 32, hipMemcpyDeviceToHost, s));
     }
     HIPCHK(hipStreamSynchronize(s));
     if (sum) {
-        sum->n_histories = P.n_hist;
+        sum->n_histories = acc[3];
         sum->incident_fp = (int64_t)acc[0];
         sum->escaped_fp = (int64_t)acc[1];
         sum->deposited_fp = (int64_t)acc[2];
@@ -788,10 +967,11 @@ int fdc_debug_endpoints(fdc_ctx *ctx, int32_t plan, uint32_t spot, uint64_t h0, 
         dfree(ctx, d_xyz); dfree(ctx, d_reason); dfree(ctx, d_item);
         return fail(ctx, FDC_E_NOMEM, "endpoints: allocation failed");
     }
-    WorkItem w{h0, h0 + n, 0, ctx->spot_base[plan] + spot, 0};
-    const unsigned long long units = (w.h_end - 1) / kWave - w.h0 / kWave + 1;
+    WorkItem w{h0, n, 0, ctx->spot_base[plan] + spot, 0};
+    const unsigned long long units = units_for(n);
     TransportArgs a = base_args(ctx);
     a.items = d_item;
+    a.hnext = nullptr;                       // h0 is absolute here
     a.n_items = 1;
     a.n_units = units;
     a.flags = flags;
@@ -850,7 +1030,108 @@ int fdc_set_launch_config(fdc_ctx *ctx, const fdc_launch_config *cfg)
     if (cfg->waves_per_block < 1 || cfg->waves_per_block > 16)
         return fail(ctx, FDC_E_ARG, "launch config: waves_per_block must be 1..16");
     if (cfg->blocks_per_cu > 64) return fail(ctx, FDC_E_ARG, "launch config: blocks_per_cu must be 0..64");
+    if (cfg->tally_slots) {
+        const uint32_t t = cfg->tally_slots;
+        if (t < 256 || t > 8192 || (t & (t - 1)))
+            return fail(ctx, FDC_E_ARG, "launch config: tally_slots must be 0 or a power of two 256..8192");
+        if (kLutSize * sizeof(float2) + 64 + lds_tally_bytes(t, false) > kMaxLdsBytes)
+            return fail(ctx, FDC_E_ARG, "launch config: LDS sub-tally of %u slots does not fit", t);
+    }
+    if (cfg->units_per_wave > 64) return fail(ctx, FDC_E_ARG, "launch config: units_per_wave must be 0..64");
     ctx->cfg = *cfg;
+    return FDC_OK;
+}
+
+int fdc_mean_uncertainty(fdc_ctx *ctx, int32_t plan, const double *dose_dev, const double *var_dev, double frac,
+                         double *mean_out, uint64_t *n_out, double *dmax_out, void *hip_stream)
+{
+    if (!ctx) return FDC_E_ARG;
+    if (!valid_plan(ctx, plan)) return fail(ctx, FDC_E_ARG, "mean uncertainty: no plan %d", plan);
+    if (!dose_dev || !var_dev || !mean_out) return fail(ctx, FDC_E_ARG, "mean uncertainty: NULL argument");
+    if (!(frac >= 0.0 && frac < 1.0)) return fail(ctx, FDC_E_ARG, "mean uncertainty: frac must be in [0, 1)");
+    if (ctx->dry) return fail(ctx, FDC_E_STATE, "mean uncertainty: context has no device");
+    HIPCHK(hipSetDevice(ctx->device));
+    const PlanHost &P = ctx->plans[plan];
+    hipStream_t s = S(hip_stream);
+    double *scr = dalloc_n<double>(ctx, metrics_scratch_doubles());
+    if (!scr) return fail(ctx, FDC_E_NOMEM, "mean uncertainty: scratch allocation failed");
+    double out[3] = {0, 0, 0};
+    double *d_out = scr + metrics_scratch_doubles() - 4;
+    hipError_t e = launch_mean_uncertainty(dose_dev, var_dev, P.idx, ctx->lut, P.nvox, frac, scr, d_out, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(out, d_out, sizeof out, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    dfree(ctx, scr);
+    if (e != hipSuccess) return fail(ctx, FDC_E_HIP, "mean uncertainty: %s", hipGetErrorString(e));
+    *mean_out = out[2] > 0 ? out[1] / out[2] : 0.0;
+    if (n_out) *n_out = (uint64_t)out[2];
+    if (dmax_out) *dmax_out = out[0];
+    return FDC_OK;
+}
+
+int fdc_batch_uncertainty(fdc_ctx *ctx, const double *doses_dev, uint32_t n_batches, uint64_t n_vox,
+                          double *mean_dev, double *sigma_dev, void *hip_stream)
+{
+    if (!ctx) return FDC_E_ARG;
+    if (!doses_dev || (!mean_dev && !sigma_dev)) return fail(ctx, FDC_E_ARG, "batch uncertainty: NULL argument");
+    if (n_batches < 2 || n_vox == 0) return fail(ctx, FDC_E_ARG, "batch uncertainty: need n_batches >= 2 and voxels");
+    if (ctx->dry) return fail(ctx, FDC_E_STATE, "batch uncertainty: context has no device");
+    HIPCHK(hipSetDevice(ctx->device));
+    HIPCHK(launch_batch_uncertainty(doses_dev, n_batches, n_vox, mean_dev, sigma_dev, S(hip_stream)));
+    return FDC_OK;
+}
+
+int fdc_gamma_index(fdc_ctx *ctx, int32_t plan, const double *ref_dev, const double *eval_dev, double dose_frac,
+                    double dta_cm, double cutoff_frac, double search_cm, float *gamma_dev, double *pass_rate_out,
+                    uint64_t *n_eval_out, void *hip_stream)
+{
+    if (!ctx) return FDC_E_ARG;
+    if (!valid_plan(ctx, plan)) return fail(ctx, FDC_E_ARG, "gamma: no plan %d", plan);
+    if (!ref_dev || !eval_dev) return fail(ctx, FDC_E_ARG, "gamma: NULL dose array");
+    if (!(dose_frac > 0.0) || !(dta_cm > 0.0) || !(cutoff_frac >= 0.0) || !(search_cm >= dta_cm) ||
+        !std::isfinite(search_cm))
+        return fail(ctx, FDC_E_ARG, "gamma: need dose_frac > 0, dta > 0, cutoff >= 0, search >= dta");
+    const PlanHost &P = ctx->plans[plan];
+    // candidate offsets on the twice-upsampled grid, sorted by distance
+    std::vector<int4> offs;
+    std::vector<double> d2;
+    int r[3];
+    for (int q = 0; q < 3; ++q) r[q] = (int)std::floor(search_cm / (0.5 * P.vox[q]) + 1e-9);
+    if ((double)(2 * r[0] + 1) * (2 * r[1] + 1) * (2 * r[2] + 1) > 4e6)
+        return fail(ctx, FDC_E_ARG, "gamma: search radius too large for the voxel size");
+    std::vector<std::pair<double, int4>> cand;
+    for (int c = -r[2]; c <= r[2]; ++c)
+        for (int b = -r[1]; b <= r[1]; ++b)
+            for (int a = -r[0]; a <= r[0]; ++a) {
+                const double dx = a * 0.5 * P.vox[0], dy = b * 0.5 * P.vox[1], dz = c * 0.5 * P.vox[2];
+                const double dist2 = dx * dx + dy * dy + dz * dz;
+                if (dist2 <= search_cm * search_cm * (1.0 + 1e-12)) cand.push_back({dist2 / (dta_cm * dta_cm), int4{a, b, c, 0}});
+            }
+    std::stable_sort(cand.begin(), cand.end(), [](const auto &x, const auto &y) { return x.first < y.first; });
+    for (auto &p : cand) { d2.push_back(p.first); offs.push_back(p.second); }
+    if (ctx->dry) return fail(ctx, FDC_E_STATE, "gamma: context has no device");
+    HIPCHK(hipSetDevice(ctx->device));
+    hipStream_t s = S(hip_stream);
+    const size_t ns = metrics_scratch_doubles();
+    double *scr = dalloc_n<double>(ctx, ns + 2 * offs.size() + 4);
+    if (!scr) return fail(ctx, FDC_E_NOMEM, "gamma: scratch allocation failed");
+    double *d_out = scr + ns - 4;
+    double *d_d2 = scr + ns;
+    int4 *d_offs = (int4 *)(scr + ns + offs.size());
+    unsigned long long *d_cnt = (unsigned long long *)(scr + ns + 2 * offs.size());
+    unsigned long long cnt[2] = {0, 0};
+    hipError_t e = hipMemcpyAsync(d_d2, d2.data(), d2.size() * 8, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(d_offs, offs.data(), offs.size() * 16, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemsetAsync(d_cnt, 0, 16, s);
+    if (e == hipSuccess) e = launch_dmax(ref_dev, P.idx, ctx->lut, P.nvox, scr, d_out, s);
+    if (e == hipSuccess)
+        e = launch_gamma(ref_dev, eval_dev, P.idx, ctx->lut, P.n[0], P.n[1], P.n[2], d_offs, d_d2, (int)offs.size(),
+                         d_out, dose_frac, cutoff_frac, gamma_dev, d_cnt, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(cnt, d_cnt, 16, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    dfree(ctx, scr);
+    if (e != hipSuccess) return fail(ctx, FDC_E_HIP, "gamma: %s", hipGetErrorString(e));
+    if (pass_rate_out) *pass_rate_out = cnt[0] ? (double)cnt[1] / (double)cnt[0] : 0.0;
+    if (n_eval_out) *n_eval_out = cnt[0];
     return FDC_OK;
 }
 

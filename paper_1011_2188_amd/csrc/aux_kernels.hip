@@ -52,25 +52,47 @@ __global__ void track_energy_kernel(const float4 *__restrict__ steps, const unsi
     T[t] = s;
 }
 
-// dose per primary = E / (rho V) / N and Eq. (2) variance of that mean
+// dose per primary = E / (rho V) / N and Eq. (2) variance of that mean; N is
+// the plan's device history count
 __global__ void dose_kernel(const uint16_t *__restrict__ idx, const unsigned long long *__restrict__ E,
                             const unsigned long long *__restrict__ E2, const float2 *__restrict__ lut,
-                            const float *__restrict__ rho_lut, size_t nvox, double vol_cm3, double N,
-                            double *__restrict__ dose, double *__restrict__ var)
+                            const float *__restrict__ rho_lut, size_t nvox, double vol_cm3,
+                            const unsigned long long *__restrict__ n_hist, double *__restrict__ dose,
+                            double *__restrict__ var)
 {
+    const double N = (double)n_hist[0];
     for (size_t v = blockIdx.x * (size_t)blockDim.x + threadIdx.x; v < nvox; v += (size_t)gridDim.x * blockDim.x) {
         const uint16_t m = idx[v];
-        const bool vac = lut[m].x == 0.f;
+        const bool vac = lut[m].x == 0.f || N <= 0.0;
         const double mass_kg = (double)rho_lut[m] * vol_cm3 * 1e-3;
         const double per = kMeVToJ / mass_kg;                // Gy per MeV in this voxel
         const double s1 = vac ? 0.0 : (double)(long long)E[v] * kFpMeV * per;
-        if (dose) dose[v] = s1 / N;
+        if (dose) dose[v] = vac ? 0.0 : s1 / N;
         if (var) {
             const double s2 = vac || !E2 ? 0.0 : (double)E2[v] * kFpMeV * per * per;
-            const double mean = s1 / N;
+            const double mean = vac ? 0.0 : s1 / N;
             var[v] = N > 1.0 ? (s2 / N - mean * mean) / (N - 1.0) : 0.0;
         }
     }
+}
+
+// after a transport launch: every item's spot counter moves past its histories
+// and its plan's history count grows
+__global__ void advance_kernel(const WorkItem *__restrict__ items, uint32_t n_items,
+                               unsigned long long *__restrict__ hnext, const DevSpot *__restrict__ spots,
+                               const DevPlan *__restrict__ plans)
+{
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_items) return;
+    const WorkItem it = items[i];
+    hnext[it.gspot] += it.n;                 // one item per spot and launch: no race
+    atomicAdd(plans[spots[it.gspot].plan].acc + 3, it.n);
+}
+
+__global__ void fill_u64_kernel(unsigned long long *__restrict__ p, size_t n, unsigned long long value)
+{
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        p[i] = value;
 }
 
 __global__ void sum_i64_kernel(const unsigned long long *__restrict__ x, size_t n, unsigned long long *out)
@@ -125,12 +147,26 @@ hipError_t launch_track_energy(const float4 *steps, const unsigned long long *of
     return hipGetLastError();
 }
 
-hipError_t launch_dose(const DevPlan *, const uint16_t *idx, const unsigned long long *E,
-                       const unsigned long long *E2, const float2 *lut, const float *rho_lut,
-                       size_t nvox, double vol, double n_hist, double *dose, double *var, hipStream_t s)
+hipError_t launch_dose(const uint16_t *idx, const unsigned long long *E, const unsigned long long *E2,
+                       const float2 *lut, const float *rho_lut, size_t nvox, double vol,
+                       const unsigned long long *n_hist, double *dose, double *var, hipStream_t s)
 {
     hipLaunchKernelGGL(dose_kernel, dim3(grid_for(nvox, 256, 8192)), dim3(256), 0, s, idx, E, E2, lut, rho_lut,
                        nvox, vol, n_hist, dose, var);
+    return hipGetLastError();
+}
+
+hipError_t launch_advance(const WorkItem *items, uint32_t n_items, unsigned long long *hnext, const DevSpot *spots,
+                          const DevPlan *plans, hipStream_t s)
+{
+    hipLaunchKernelGGL(advance_kernel, dim3((n_items + 255) / 256), dim3(256), 0, s, items, n_items, hnext, spots,
+                       plans);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_u64(unsigned long long *p, size_t n, unsigned long long value, hipStream_t s)
+{
+    hipLaunchKernelGGL(fill_u64_kernel, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, p, n, value);
     return hipGetLastError();
 }
 

@@ -14,6 +14,7 @@ constexpr uint32_t kTagSource = 3u;
 constexpr uint32_t kFlagVariance = 1u;
 constexpr uint32_t kFlagRotate = 2u;
 constexpr int kMaxTablePts = 64;
+constexpr size_t kMaxLdsBytes = 160 * 1024;   // LDS per workgroup on gfx950
 constexpr double kMeVToJ = 1.602176634e-13;
 constexpr double kFpMeV = 1.0 / 16777216.0;   // one fixed-point unit in MeV
 
@@ -22,7 +23,8 @@ struct DevPlan {
     const uint16_t *idx;             // HU index per voxel, x-fastest
     unsigned long long *E;           // int64 energy tally (two's complement in u64 adds)
     unsigned long long *E2;          // uint64 sum of squared per-visit deposits
-    unsigned long long *acc;         // [0] incident, [1] escaped (fixed point)
+    unsigned long long *acc;         // [0] incident, [1] escaped (fixed point), [2] scratch,
+                                     // [3] histories run since the last reset
     int n[3];
     float vox[3];
     float org[3];
@@ -42,14 +44,24 @@ struct DevSpot {
     long long skip;                 // fp(E_bin) - fp(E_spot)
 };
 
-// a contiguous range of histories of one spot, split in wave units of 64
-// histories aligned to multiples of 64
+// a contiguous range of histories of one spot, cut in wave units of 64
+// histories aligned to multiples of 64.  The range starts at h0, plus the
+// spot's device history counter hnext[gspot] when the launch has one (runs;
+// debug end-point replays give h0 explicitly).  An item owns units_for(n)
+// units, enough for any alignment of its start, so a captured launch stays
+// valid while the counters advance.
 struct WorkItem {
-    unsigned long long h0, h_end;   // histories [h0, h_end)
+    unsigned long long h0;
+    unsigned long long n;
     unsigned long long unit0;       // index of this item's first wave unit
     uint32_t gspot;                 // index into the DevSpot array
     uint32_t pad;
 };
+
+__host__ __device__ inline unsigned long long units_for(unsigned long long n)
+{
+    return n ? (n + 62) / 64 + 1 : 0;
+}
 
 struct TransportArgs {
     const float4 *steps;                 // (dx, dE, theta, phi)
@@ -59,6 +71,7 @@ struct TransportArgs {
     const DevPlan *plans;
     const DevSpot *spots;
     const WorkItem *items;
+    const unsigned long long *hnext;     // per DevSpot: next history index (null: h0 is absolute)
     const float2 *lut;                   // (rsp, g) per HU index; rsp == 0 is vacuum
     unsigned long long n_units;
     unsigned long long *queue;           // persistent mode: next unit counter
@@ -111,16 +124,33 @@ __host__ __device__ inline long long to_fp(float mev)
 // kernels' host-side launchers (implemented next to their kernels)
 hipError_t launch_transport(const TransportArgs &a, uint32_t waves_per_block, uint32_t grid_blocks,
                             bool variance, bool endpoints, hipStream_t s);
+hipError_t launch_transport_lds(const TransportArgs &a, uint32_t waves_per_block, uint32_t grid_blocks,
+                                uint32_t slots, uint32_t units_per_wave, bool variance, hipStream_t s);
+size_t lds_tally_bytes(uint32_t slots, bool variance);
+hipError_t prepare_lds_kernels();
 hipError_t launch_build_lut(const double *pts, int n_pts, double vacuum_below, float2 *lut, float *rho,
                             hipStream_t s);
 hipError_t launch_hu_to_index(const int16_t *hu, uint16_t *idx, size_t n, hipStream_t s);
 hipError_t launch_track_energy(const float4 *steps, const unsigned long long *off, long long *T,
                                uint32_t n_tracks, hipStream_t s);
-hipError_t launch_dose(const DevPlan *plan_dev, const uint16_t *idx, const unsigned long long *E,
-                       const unsigned long long *E2, const float2 *lut, const float *rho_lut,
-                       size_t nvox, double voxel_volume_cm3, double n_hist, double *dose, double *var,
-                       hipStream_t s);
+hipError_t launch_dose(const uint16_t *idx, const unsigned long long *E, const unsigned long long *E2,
+                       const float2 *lut, const float *rho_lut, size_t nvox, double voxel_volume_cm3,
+                       const unsigned long long *n_hist, double *dose, double *var, hipStream_t s);
+hipError_t launch_advance(const WorkItem *items, uint32_t n_items, unsigned long long *hnext, const DevSpot *spots,
+                          const DevPlan *plans, hipStream_t s);
+hipError_t launch_fill_u64(unsigned long long *p, size_t n, unsigned long long value, hipStream_t s);
 hipError_t launch_sum_i64(const unsigned long long *x, size_t n, unsigned long long *out, hipStream_t s);
+hipError_t launch_dmax(const double *d, const uint16_t *idx, const float2 *lut, size_t n, double *part,
+                       double *out3, hipStream_t s);
+hipError_t launch_mean_uncertainty(const double *d, const double *var, const uint16_t *idx, const float2 *lut,
+                                   size_t n, double frac, double *scratch, double *out3, hipStream_t s);
+size_t metrics_scratch_doubles();
+hipError_t launch_batch_uncertainty(const double *doses, uint32_t nb, size_t n, double *mean, double *sigma,
+                                    hipStream_t s);
+hipError_t launch_gamma(const double *ref, const double *ev, const uint16_t *idx, const float2 *lut, int nx, int ny,
+                        int nz, const int4 *offs, const double *offd2, int n_offs, const double *dmax_out,
+                        double dose_frac, double cutoff_frac, float *gamma, unsigned long long *counts,
+                        hipStream_t s);
 hipError_t launch_philox_test(const uint4 *ctr, uint4 *out, uint32_t n, uint32_t k0, uint32_t k1,
                               hipStream_t s);
 

@@ -2,7 +2,8 @@
 // tallies deposited energy (Sections 2.2 and 2.3 of the paper).
 //
 // Work decomposition: a wave unit is 64 consecutive histories of one spot
-// (aligned to multiples of 64), one history per lane.  Consecutive histories
+// (aligned to multiples of 64), one history per lane; a spot's run starts at
+// its device history counter, which a small kernel advances after the launch.  Consecutive histories
 // of a spot share a database track in chunks of R (R = 64 by default), so the
 // lanes of a wave read the same step record each step: the record loads are
 // broadcast loads, and lanes only diverge in the voxel walk - the paper's
@@ -47,24 +48,76 @@ __host__ __device__ inline void set_direction_terms(const float d[3], const floa
     }
 }
 
-template <bool VAR, bool EP>
-__host__ __device__ inline void flush(const DevPlan &pl, uint32_t v, long long &acc)
-{
-    if (acc == 0) return;
-    if constexpr (!EP) {
-        atomicAdd(pl.E + v, (unsigned long long)acc);
+// Where a voxel visit's deposit goes.  Every sink adds the integer deposit
+// `acc` to E[v] and, with the squared-energy tally, q^2 to E2[v] with
+// q = (acc + 2^11) >> 12 (the deposit rounded to 2^-12 MeV).
+template <bool VAR>
+struct GlobalSink {            // 64-bit device atomics straight into the plan's tallies
+    const DevPlan *pl;
+    __device__ void add(uint32_t v, uint32_t, long long acc) const
+    {
+        atomicAdd(pl->E + v, (unsigned long long)acc);
         if (VAR) {
             const unsigned long long q = (unsigned long long)((acc + 2048) >> 12);
-            atomicAdd(pl.E2 + v, q * q);
+            atomicAdd(pl->E2 + v, q * q);
         }
     }
-    acc = 0;
-}
+};
 
-template <bool VAR, bool EP>
+struct NullSink {              // end-point replays: nothing is tallied
+    __host__ __device__ void add(uint32_t, uint32_t, long long) const {}
+};
+
+constexpr uint32_t kEmpty = 0xFFFFFFFFu;
+constexpr int kProbes = 8;
+
+// Per-workgroup sub-tally in LDS: an open-addressed table of `mask + 1` slots
+// (voxel key, energy, squared energy).  A visit adds into the slot holding its
+// voxel, claiming an empty one with a compare-and-swap; after kProbes occupied
+// slots it falls back to the global atomics.  Voxels consecutive in x land in
+// consecutive slots, so the end-of-round flush partly coalesces.  The table
+// holds voxels of one plan per round; visits of another plan go straight to
+// the global atomics.
+template <bool VAR>
+struct LdsSink {
+    const DevPlan *pl;          // plan of the unit being replayed
+    const DevPlan *tab_pl;      // plan whose voxels the table holds this round
+    uint32_t *keys;
+    unsigned long long *e, *e2;
+    uint32_t mask;
+    __device__ void add(uint32_t v, uint32_t ix, long long acc) const
+    {
+        const unsigned long long q = (unsigned long long)((acc + 2048) >> 12);
+        if (pl != tab_pl) {                        // a round straddling two plans
+            atomicAdd(pl->E + v, (unsigned long long)acc);
+            if (VAR) atomicAdd(pl->E2 + v, q * q);
+            return;
+        }
+        uint32_t row = v - ix;                     // start of the x row
+        row ^= row >> 15;
+        row *= 0x2c1b3c6du;
+        row ^= row >> 12;
+        uint32_t s = (row + ix) & mask;
+#pragma unroll 1
+        for (int p = 0; p < kProbes; ++p) {
+            uint32_t k = keys[s];
+            if (k == kEmpty) k = atomicCAS(keys + s, kEmpty, v);
+            if (k == kEmpty || k == v) {
+                atomicAdd(e + s, (unsigned long long)acc);
+                if (VAR) atomicAdd(e2 + s, q * q);
+                return;
+            }
+            s = (s + 1) & mask;
+        }
+        atomicAdd(pl->E + v, (unsigned long long)acc);
+        if (VAR) atomicAdd(pl->E2 + v, q * q);
+    }
+};
+
+template <bool EP, class Sink>
 __host__ __device__ void replay_history(const TransportArgs &a, const DevSpot &sp, const DevPlan &pl,
                                const float2 *__restrict__ lut, unsigned long long h, uint32_t slot,
-                               long long &inc, long long &esc)
+                               long long &inc, long long &esc, const Sink &sink)
 {
     // ---- task 1: track, start step, source ---------------------------------
     const uint32_t first = a.bin_first[sp.bin];
@@ -210,7 +263,10 @@ __host__ __device__ void replay_history(const TransportArgs &a, const DevSpot &s
 #pragma unroll
             for (int q = 0; q < 3; ++q) L.f[q] = fminf(fmaxf(L.f[q] + move * dv[q], 0.f), 1.f);
             if (cross) {
-                flush<VAR, EP>(pl, L.v, acc);
+                if (acc != 0) {
+                    sink.add(L.v, (uint32_t)L.i[0], acc);
+                    acc = 0;
+                }
                 bool out = false;
 #pragma unroll
                 for (int q = 0; q < 3; ++q) {
@@ -259,7 +315,7 @@ __host__ __device__ void replay_history(const TransportArgs &a, const DevSpot &s
             L.d[q] = sp.m[3 * q + 0] * L.b[0] + sp.m[3 * q + 1] * L.b[1] + sp.m[3 * q + 2] * L.b[2];
         set_direction_terms(L.d, pl.vox, sinv, dv);
     }
-    if (!escaped) flush<VAR, EP>(pl, L.v, acc);
+    if (!escaped && acc != 0) sink.add(L.v, (uint32_t)L.i[0], acc);
     esc = escaped ? I_h - hdep : 0;
     if (EP) {
 #pragma unroll
@@ -276,9 +332,9 @@ __device__ inline long long wave_sum(long long x)
     return x;
 }
 
-template <bool VAR, bool EP>
+template <bool EP, class Sink>
 __device__ void process_unit(const TransportArgs &a, const float2 *lut, unsigned long long unit,
-                             uint32_t lane)
+                             uint32_t lane, const Sink &sink)
 {
     // the work item holding this unit: largest i with items[i].unit0 <= unit
     uint32_t lo = 0, hi = a.n_items;
@@ -289,10 +345,11 @@ __device__ void process_unit(const TransportArgs &a, const float2 *lut, unsigned
     const WorkItem it = a.items[lo];
     const DevSpot &sp = a.spots[it.gspot];
     const DevPlan &pl = a.plans[sp.plan];
-    const unsigned long long h = (it.h0 / kWave + (unit - it.unit0)) * kWave + lane;
+    const unsigned long long h0 = it.h0 + (a.hnext ? a.hnext[it.gspot] : 0ull);
+    const unsigned long long h = (h0 / kWave + (unit - it.unit0)) * kWave + lane;
     long long inc = 0, esc = 0;
-    if (h >= it.h0 && h < it.h_end)
-        replay_history<VAR, EP>(a, sp, pl, lut, h, (uint32_t)(h - it.h0), inc, esc);
+    if (h >= h0 && h < h0 + it.n)
+        replay_history<EP>(a, sp, pl, lut, h, (uint32_t)(h - h0), inc, esc, sink);
     if (!EP) {
         inc = wave_sum(inc);
         esc = wave_sum(esc);
@@ -303,6 +360,25 @@ __device__ void process_unit(const TransportArgs &a, const float2 *lut, unsigned
     }
 }
 
+// the plan whose tallies a unit deposits into (the LDS sink needs it for its
+// fallback and its flush)
+__device__ inline const DevPlan *plan_of_unit(const TransportArgs &a, unsigned long long unit)
+{
+    uint32_t lo = 0, hi = a.n_items;
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (a.items[mid].unit0 <= unit) lo = mid; else hi = mid;
+    }
+    return a.plans + a.spots[a.items[lo].gspot].plan;
+}
+
+__device__ inline unsigned long long scalar_u64(unsigned long long x)
+{
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)x);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(x >> 32));
+    return ((unsigned long long)hi << 32) | lo;
+}
+
 template <bool VAR, bool EP>
 __global__ void __launch_bounds__(1024) transport_kernel(TransportArgs a)
 {
@@ -310,11 +386,14 @@ __global__ void __launch_bounds__(1024) transport_kernel(TransportArgs a)
     for (int i = threadIdx.x; i < kLutSize; i += blockDim.x) s_lut[i] = a.lut[i];
     __syncthreads();
     const uint32_t lane = threadIdx.x & (kWave - 1);
-    const uint32_t wave = threadIdx.x / kWave;
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);   // scalar
     const uint32_t wpb = blockDim.x / kWave;
     if (a.queue == nullptr) {
         const unsigned long long unit = (unsigned long long)blockIdx.x * wpb + wave;
-        if (unit < a.n_units) process_unit<VAR, EP>(a, s_lut, unit, lane);
+        if (unit < a.n_units) {
+            if (EP) process_unit<EP>(a, s_lut, unit, lane, NullSink{});
+            else process_unit<EP>(a, s_lut, unit, lane, GlobalSink<VAR>{plan_of_unit(a, unit)});
+        }
         return;
     }
     // persistent: each wave pulls units from a global counter until none are
@@ -323,12 +402,72 @@ __global__ void __launch_bounds__(1024) transport_kernel(TransportArgs a)
     // ticket - is read back with readfirstlane as a scalar: the loop exit is a
     // uniform branch and no cross-lane read sits in divergent control flow.
     for (;;) {
-        const unsigned long long got = atomicAdd(a.queue, lane == 0 ? 1ull : 0ull);
-        const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)got);
-        const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(got >> 32));
-        const unsigned long long unit = ((unsigned long long)hi << 32) | lo;
+        const unsigned long long unit = scalar_u64(atomicAdd(a.queue, lane == 0 ? 1ull : 0ull));
         if (unit >= a.n_units) break;
-        process_unit<VAR, EP>(a, s_lut, unit, lane);
+        if (EP) process_unit<EP>(a, s_lut, unit, lane, NullSink{});
+        else process_unit<EP>(a, s_lut, unit, lane, GlobalSink<VAR>{plan_of_unit(a, unit)});
+    }
+}
+
+// Persistent kernel with a per-workgroup LDS sub-tally.  The workgroup works in
+// rounds: it claims wpb * upw consecutive units (wave w takes upw of them),
+// every visit deposits into the LDS table, then after a barrier the table is
+// flushed into the plans' tallies with one global atomic per occupied slot and
+// cleared.  Units of one round come from the same spot or a neighbouring one,
+// whose histories overlap in space, so most visits of a round merge in LDS.
+template <bool VAR>
+__global__ void __launch_bounds__(1024) transport_lds_kernel(TransportArgs a, uint32_t slots, uint32_t upw)
+{
+    __shared__ float2 s_lut[kLutSize];
+    __shared__ unsigned long long s_claim;
+    extern __shared__ unsigned long long s_dyn[];
+    unsigned long long *s_e = s_dyn;
+    unsigned long long *s_e2 = s_dyn + slots;
+    uint32_t *s_key = (uint32_t *)(s_dyn + (VAR ? 2 : 1) * slots);
+    for (int i = threadIdx.x; i < kLutSize; i += blockDim.x) s_lut[i] = a.lut[i];
+    for (uint32_t i = threadIdx.x; i < slots; i += blockDim.x) {
+        s_key[i] = kEmpty;
+        s_e[i] = 0;
+        if (VAR) s_e2[i] = 0;
+    }
+    const uint32_t lane = threadIdx.x & (kWave - 1);
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);   // scalar
+    const uint32_t wpb = blockDim.x / kWave;
+    const unsigned long long per_round = (unsigned long long)wpb * upw;
+    for (;;) {
+        // one ticket per round for the whole workgroup, taken by thread 0's
+        // lane of the atomic (every lane executes it, the others add 0)
+        const unsigned long long got = atomicAdd(a.queue, threadIdx.x == 0 ? per_round : 0ull);
+        if (threadIdx.x == 0) s_claim = got;
+        __syncthreads();
+        const unsigned long long base = scalar_u64(s_claim);
+        if (base >= a.n_units) break;
+        const DevPlan *tab_pl = plan_of_unit(a, base);
+        for (uint32_t j = 0; j < upw; ++j) {
+            const unsigned long long unit = base + (unsigned long long)wave * upw + j;
+            if (unit >= a.n_units) break;
+            const DevPlan *pl = plan_of_unit(a, unit);
+            process_unit<false>(a, s_lut, unit, lane, LdsSink<VAR>{pl, tab_pl, s_key, s_e, s_e2, slots - 1});
+        }
+        __syncthreads();
+        // flush: one atomic per occupied slot; consecutive slots often hold
+        // consecutive voxels, so neighbouring lanes' atomics share lines
+        const DevPlan *pl = tab_pl;
+        for (uint32_t i = threadIdx.x; i < slots; i += blockDim.x) {
+            const uint32_t k = s_key[i];
+            if (k != kEmpty) {
+                const unsigned long long ev = s_e[i];
+                if (ev) atomicAdd(pl->E + k, ev);
+                if (VAR) {
+                    const unsigned long long e2v = s_e2[i];
+                    if (e2v) atomicAdd(pl->E2 + k, e2v);
+                    s_e2[i] = 0;
+                }
+                s_e[i] = 0;
+                s_key[i] = kEmpty;
+            }
+        }
+        __syncthreads();
     }
 }
 
@@ -345,6 +484,35 @@ hipError_t launch_transport(const TransportArgs &a, uint32_t waves_per_block, ui
         hipLaunchKernelGGL((transport_kernel<true, false>), grid, block, 0, s, a);
     else
         hipLaunchKernelGGL((transport_kernel<false, false>), grid, block, 0, s, a);
+    return hipGetLastError();
+}
+
+size_t lds_tally_bytes(uint32_t slots, bool variance)
+{
+    return (size_t)slots * ((variance ? 16 : 8) + 4);
+}
+
+hipError_t prepare_lds_kernels()
+{
+    const int dyn = (int)(kMaxLdsBytes - kLutSize * sizeof(float2) - 64);
+    hipError_t e = hipFuncSetAttribute((const void *)transport_lds_kernel<true>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute((const void *)transport_lds_kernel<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                dyn);
+    return e;
+}
+
+hipError_t launch_transport_lds(const TransportArgs &a, uint32_t waves_per_block, uint32_t grid_blocks,
+                                uint32_t slots, uint32_t units_per_wave, bool variance, hipStream_t s)
+{
+    const dim3 block(waves_per_block * kWave);
+    const dim3 grid(grid_blocks);
+    const size_t dyn = lds_tally_bytes(slots, variance);
+    if (variance)
+        hipLaunchKernelGGL((transport_lds_kernel<true>), grid, block, dyn, s, a, slots, units_per_wave);
+    else
+        hipLaunchKernelGGL((transport_lds_kernel<false>), grid, block, dyn, s, a, slots, units_per_wave);
     return hipGetLastError();
 }
 

@@ -30,7 +30,11 @@ ERROR_NAMES = {0: "FDC_OK", -1: "FDC_E_ARG", -2: "FDC_E_STATE", -3: "FDC_E_NOMEM
 EXPORTS = ["fdc_create", "fdc_destroy", "fdc_last_error", "fdc_set_allocator", "fdc_set_hu_table",
            "fdc_load_track_db", "fdc_load_phantom", "fdc_add_beam_spots", "fdc_run_histories",
            "fdc_reset_plan", "fdc_compute_dose", "fdc_read_dose_and_variance", "fdc_debug_endpoints",
-           "fdc_debug_philox", "fdc_debug_material", "fdc_set_launch_config", "fdc_device_cus"]
+           "fdc_debug_philox", "fdc_debug_material", "fdc_set_launch_config", "fdc_device_cus",
+           "fdc_mean_uncertainty", "fdc_batch_uncertainty", "fdc_gamma_index",
+           "fdc_graph_create", "fdc_graph_launch", "fdc_graph_destroy"]
+FDC_GRAPH_RESET_TALLIES = 1
+FDC_GRAPH_DOSE = 2
 
 
 class fdc_summary(C.Structure):
@@ -40,7 +44,8 @@ class fdc_summary(C.Structure):
 
 class fdc_launch_config(C.Structure):
     _fields_ = [("waves_per_block", C.c_uint32), ("blocks_per_cu", C.c_uint32),
-                ("reserved", C.c_uint32 * 6)]
+                ("tally_slots", C.c_uint32), ("units_per_wave", C.c_uint32),
+                ("reserved", C.c_uint32 * 4)]
 
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
@@ -84,6 +89,14 @@ def lib():
         "fdc_debug_material": (C.c_int, [_P, _P, _P, _P, _P]),
         "fdc_set_launch_config": (C.c_int, [_P, C.POINTER(fdc_launch_config)]),
         "fdc_device_cus": (C.c_int, [_P, C.POINTER(C.c_int)]),
+        "fdc_mean_uncertainty": (C.c_int, [_P, C.c_int32, _P, _P, C.c_double, C.POINTER(C.c_double),
+                                           C.POINTER(C.c_uint64), C.POINTER(C.c_double), _P]),
+        "fdc_batch_uncertainty": (C.c_int, [_P, _P, C.c_uint32, C.c_uint64, _P, _P, _P]),
+        "fdc_graph_create": (C.c_int, [_P, _P, C.c_uint32, C.c_uint32, C.c_uint32, _P, _P, C.POINTER(_P)]),
+        "fdc_graph_launch": (C.c_int, [_P, _P]),
+        "fdc_graph_destroy": (C.c_int, [_P]),
+        "fdc_gamma_index": (C.c_int, [_P, C.c_int32, _P, _P, C.c_double, C.c_double, C.c_double, C.c_double,
+                                      _P, C.POINTER(C.c_double), C.POINTER(C.c_uint64), _P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -132,6 +145,27 @@ def _check(ctx, rc):
         raise FdcError(rc, fdc_last_error(ctx))
 
 
+class Graph:
+    """A captured run (fdc_graph_*); launch() enqueues one replay."""
+
+    def __init__(self, ctx, handle, keep):
+        self.ctx, self.h, self._keep = ctx, handle, keep
+
+    def launch(self, stream=None):
+        _check(self.ctx.h, lib().fdc_graph_launch(self.h, _stream(stream)))
+
+    def close(self):
+        if self.h:
+            lib().fdc_graph_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class Context:
     """One libfdc context (one device).  Inputs are numpy arrays on the host
     (copied by the loaders); dose outputs are numpy or torch device tensors."""
@@ -144,6 +178,7 @@ class Context:
         self.device = device
         self.plans = {}           # plan id -> shape (nz, ny, nx)
         self._keep = []
+        self._graphs = []
         if torch_allocator:
             self._use_torch_allocator()
         if table is not None:
@@ -152,6 +187,8 @@ class Context:
     # -- lifetime
     def close(self):
         if self.h:
+            for g in self._graphs:
+                g.close()
             lib().fdc_destroy(self.h)
             self.h = None
 
@@ -264,9 +301,44 @@ class Context:
                                                 _stream(stream)))
         return rsp, g, rho
 
-    def set_launch_config(self, waves_per_block=4, blocks_per_cu=0):
-        cfg = fdc_launch_config(waves_per_block, blocks_per_cu)
+    def set_launch_config(self, waves_per_block=4, blocks_per_cu=0, tally_slots=0, units_per_wave=0):
+        cfg = fdc_launch_config(waves_per_block, blocks_per_cu, tally_slots, units_per_wave)
         _check(self.h, lib().fdc_set_launch_config(self.h, C.byref(cfg)))
+
+    # -- graphs
+    def graph_create(self, plans, flags=FDC_RUN_VARIANCE, reset=True, doses=None, variances=None):
+        """Capture a run over `plans` (optionally clearing tallies first and
+        writing dose/variance into the given torch device tensors after)."""
+        p = np.ascontiguousarray(np.atleast_1d(plans), np.int32)
+        opts = (FDC_GRAPH_RESET_TALLIES if reset else 0) | (FDC_GRAPH_DOSE if (doses or variances) else 0)
+        dp = (C.c_void_p * p.size)(*[_ptr(d) for d in doses]) if doses else None
+        vp = (C.c_void_p * p.size)(*[_ptr(v) for v in variances]) if variances else None
+        g = _P()
+        _check(self.h, lib().fdc_graph_create(self.h, p.ctypes.data, p.size, flags, opts,
+                                              C.cast(dp, _P) if dp is not None else None,
+                                              C.cast(vp, _P) if vp is not None else None, C.byref(g)))
+        gr = Graph(self, g, (doses, variances))
+        self._graphs.append(gr)
+        return gr
+
+    # -- metrics (device arrays in, host scalars out)
+    def mean_uncertainty(self, plan, dose, var, frac=0.5, stream=None):
+        m, n, dmax = C.c_double(), C.c_uint64(), C.c_double()
+        _check(self.h, lib().fdc_mean_uncertainty(self.h, plan, _ptr(dose), _ptr(var), frac, C.byref(m),
+                                                  C.byref(n), C.byref(dmax), _stream(stream)))
+        return m.value, n.value, dmax.value
+
+    def batch_uncertainty(self, doses, mean=None, sigma=None, stream=None):
+        """doses: torch float64 device tensor [n_batches, n_vox]."""
+        _check(self.h, lib().fdc_batch_uncertainty(self.h, _ptr(doses), doses.shape[0], doses[0].numel(),
+                                                   _ptr(mean), _ptr(sigma), _stream(stream)))
+
+    def gamma_index(self, plan, ref, ev, dose_frac=0.02, dta_cm=0.2, cutoff_frac=0.1, search_cm=0.6,
+                    gamma=None, stream=None):
+        rate, n = C.c_double(), C.c_uint64()
+        _check(self.h, lib().fdc_gamma_index(self.h, plan, _ptr(ref), _ptr(ev), dose_frac, dta_cm, cutoff_frac,
+                                             search_cm, _ptr(gamma), C.byref(rate), C.byref(n), _stream(stream)))
+        return rate.value, n.value
 
     def device_cus(self):
         n = C.c_int()

@@ -180,21 +180,26 @@ def test_launch_configs_bitwise():
     db = W.multi_bin_db(2000)
     ref = _tallies(db, ph, sp)
     for cfg in [dict(waves_per_block=1), dict(waves_per_block=16), dict(waves_per_block=4, blocks_per_cu=2),
-                dict(waves_per_block=8, blocks_per_cu=8)]:
+                dict(waves_per_block=8, blocks_per_cu=8),
+                dict(waves_per_block=16, blocks_per_cu=1, tally_slots=4096),
+                dict(waves_per_block=8, blocks_per_cu=2, tally_slots=1024, units_per_wave=3),
+                dict(waves_per_block=4, blocks_per_cu=1, tally_slots=256, units_per_wave=1)]:
         got = _tallies(db, ph, sp, **cfg)
         assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1]) and got[2] == ref[2], cfg
 
 
-def test_split_runs_and_batching_bitwise():
+@pytest.mark.parametrize("cfg", [{}, dict(waves_per_block=8, blocks_per_cu=1, tally_slots=2048, units_per_wave=2)])
+def test_split_runs_and_batching_bitwise(cfg):
     """run(n) twice == run(2n) (history counters continue, unaligned h0), and
-    plans launched together == plans launched one by one."""
+    plans launched together == plans launched one by one (also with the LDS
+    sub-tally, whose rounds then straddle the two plans)."""
     db = W.multi_bin_db(2000)
     ph1 = I.thorax_phantom((80, 80, 40), 0.3, seed=1)
     ph2 = I.slab_phantom(64, 0.2)
     rng = np.random.default_rng(2)
     sp1 = I.field_spots((2.0, 0.0, 0.0), 180.0, 9, rng, histories=np.full(9, 100, np.uint64))
     sp2 = W.slab_spots(150)[::3]
-    c = ctx_for(db)
+    c = ctx_for(db, **cfg)
     a1, a2 = c.load_phantom(ph1), c.load_phantom(ph2)
     c.add_beam_spots(a1, sp1)
     c.add_beam_spots(a2, sp2)
@@ -267,3 +272,44 @@ def test_full_size_slab_sampled():
         good += ok
         tot += n
     assert good >= 0.999 * tot
+
+
+# ---------------------------------------------------------------- graphs ----
+@pytest.mark.parametrize("cfg", [{}, dict(waves_per_block=16, blocks_per_cu=1, tally_slots=4096, units_per_wave=2)])
+def test_graph_replays_match_eager(cfg):
+    """A captured run (clear tallies -> transport -> advance counters -> dose)
+    replayed four times, with eager work and synchronisation in between,
+    equals four eager passes bitwise, replay by replay."""
+    db = W.multi_bin_db(2000)
+    ph = I.thorax_phantom((64, 56, 40), 0.3, seed=21)
+    rng = np.random.default_rng(4)
+    sp = I.field_spots((2.0, -1.0, 0.0), 180.0, 15, rng, histories=np.full(15, 1000, np.uint64))
+    n = ph.hu.size
+    ce = ctx_for(db, **cfg)
+    pe = ce.load_phantom(ph)
+    ce.add_beam_spots(pe, sp)
+    de = torch.empty(n, dtype=torch.float64, device="cuda")
+    ve = torch.empty(n, dtype=torch.float64, device="cuda")
+    eager = []
+    for _ in range(4):
+        ce.reset_plan(pe)
+        ce.run_histories([pe], F.FDC_RUN_VARIANCE)
+        ce.compute_dose(pe, de, ve)
+        r = ce.read_dose_and_variance(pe, dose=False, var=False, raw=True)
+        eager.append((r["E"], r["E2"], de.cpu().numpy(), ve.cpu().numpy(), r["incident"]))
+    cg = ctx_for(db, **cfg)
+    pg = cg.load_phantom(ph)
+    cg.add_beam_spots(pg, sp)
+    dg = torch.empty(n, dtype=torch.float64, device="cuda")
+    vg = torch.empty(n, dtype=torch.float64, device="cuda")
+    g = cg.graph_create([pg], F.FDC_RUN_VARIANCE, reset=True, doses=[dg], variances=[vg])
+    for k in range(4):
+        g.launch()
+        torch.cuda.synchronize()
+        cg.debug_philox(np.arange(64, dtype=np.uint32).reshape(16, 4))     # eager work in between
+        r = cg.read_dose_and_variance(pg, dose=False, var=False, raw=True)
+        E, E2, d, v, inc = eager[k]
+        assert np.array_equal(r["E"], E) and np.array_equal(r["E2"], E2), k
+        assert r["incident"] == inc and r["n_histories"] == 15000
+        assert np.array_equal(dg.cpu().numpy(), d) and np.array_equal(vg.cpu().numpy(), v), k
+    g.close()
