@@ -40,6 +40,7 @@ extern "C" {
 
 typedef struct fdc_ctx fdc_ctx;
 typedef struct fdc_graph fdc_graph;
+typedef struct fdc_unet fdc_unet;
 
 enum {
     FDC_OK = 0,
@@ -296,6 +297,61 @@ int fdc_gamma_index(fdc_ctx *ctx, int32_t plan, const double *ref_dev, const dou
 
 /* Number of compute units of the context's device (for launch sizing). */
 int fdc_device_cus(fdc_ctx *ctx, int *cus);
+
+/* ---------------------------------------------------------------------------
+ * Dose denoiser: a 3-level 3D U-Net mapping (low-history dose, density) to a
+ * high-history dose, trained and run with BF16 MFMA kernels accumulating in
+ * FP32.  Layers (channels-first notation): conv3 2->16, 16->16 | avg-pool 2 |
+ * conv3 16->32, 32->32 | pool | conv3 32->64, 64->64 | transposed conv 2x2x2
+ * stride 2 64->32, concat with the 32-channel encoder output | conv3 64->32,
+ * 32->32 | transposed conv 32->16, concat | conv3 32->16, 16->16 | conv1 16->1,
+ * plus the input dose (residual).  conv3 = 3x3x3 cross-correlation, zero
+ * padding 1, ReLU after every conv3.  Loss: mean squared error.
+ * Parameters: one flat FP32 vector of fdc_unet_num_params() values, per layer
+ * in the order above: weights in C order of [cout][cin][3][3][3] (conv3),
+ * [cin][cout][2][2][2] (transposed) or [cout][cin] (conv1), then biases.
+ * ------------------------------------------------------------------------- */
+
+/* Number of parameters of the network (339 681). */
+int64_t fdc_unet_num_params(void);
+
+/* A network instance for volumes of nx*ny*nz voxels (each a multiple of 4),
+ * with its activation, gradient and Adam buffers.  Parameters start at zero:
+ * set them with fdc_unet_set_params.  Errors: FDC_E_ARG, FDC_E_HIP, FDC_E_NOMEM. */
+int fdc_unet_create(fdc_unet **out, int hip_device, int nx, int ny, int nz);
+int fdc_unet_destroy(fdc_unet *u);
+const char *fdc_unet_last_error(const fdc_unet *u);
+
+/* Copy the flat parameter vector in (host, FP32), clear the Adam moments and
+ * pack the bf16 operands.  Synchronises hip_stream.  FDC_E_ARG on NULL/NaN. */
+int fdc_unet_set_params(fdc_unet *u, const float *host_params, void *hip_stream);
+/* Copy the parameters / the gradients of the last fdc_unet_backward out to
+ * host arrays of fdc_unet_num_params() floats.  Synchronise hip_stream. */
+int fdc_unet_get_params(fdc_unet *u, float *host_params, void *hip_stream);
+int fdc_unet_get_grads(fdc_unet *u, float *host_grads, void *hip_stream);
+
+/* Inference: in_dev = DEVICE FP32 [2][nz][ny][nx] (channel 0 the dose, 1 the
+ * density input), out_dev = DEVICE FP32 [nz][ny][nx].  Asynchronous. */
+int fdc_unet_forward(fdc_unet *u, const float *in_dev, float *out_dev, void *hip_stream);
+
+/* Forward, mean-squared-error loss against target_dev (DEVICE FP32
+ * [nz][ny][nx]) and backward: the gradient of the loss with respect to every
+ * parameter is left in the instance (FP32).  out_dev (may be NULL) receives
+ * the prediction; loss_host (may be NULL; then the call is asynchronous)
+ * the loss, after synchronising hip_stream.  Errors: FDC_E_ARG, FDC_E_HIP. */
+int fdc_unet_backward(fdc_unet *u, const float *in_dev, const float *target_dev, float *out_dev,
+                      double *loss_host, void *hip_stream);
+
+/* One Adam step (Kingma and Ba 2015, bias-corrected) on the FP32 parameters
+ * with the last gradients, then re-pack the bf16 operands.  Asynchronous. */
+int fdc_unet_adam(fdc_unet *u, float lr, float beta1, float beta2, float eps, void *hip_stream);
+
+/* Testing aid: copy internal bf16 buffer `index` (0..26: x, e1a, c1, p1, e2a,
+ * c2, p2, ma, m, d2a, d2, d1a, d1, then the gradients gd1, gd1a, gc1, gd2,
+ * gd2a, gc2, gm, gma, gp2, ge2, ge2a, gp1, ge1, ge1a; channels-last,
+ * *pitch values per voxel) to host_out (NULL: sizes only).  Synchronises. */
+int fdc_unet_debug_buffer(fdc_unet *u, int index, uint16_t *host_out, int64_t *n_voxels, int32_t *pitch,
+                          void *hip_stream);
 
 #ifdef __cplusplus
 }

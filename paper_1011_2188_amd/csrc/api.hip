@@ -1112,12 +1112,15 @@ int fdc_gamma_index(fdc_ctx *ctx, int32_t plan, const double *ref_dev, const dou
     HIPCHK(hipSetDevice(ctx->device));
     hipStream_t s = S(hip_stream);
     const size_t ns = metrics_scratch_doubles();
-    double *scr = dalloc_n<double>(ctx, ns + 2 * offs.size() + 4);
+    // scratch: reduction area (ns doubles), squared distances (n doubles),
+    // offsets (n int4 = 2n doubles), two counters
+    const size_t no = offs.size();
+    double *scr = dalloc_n<double>(ctx, ns + 3 * no + 4);
     if (!scr) return fail(ctx, FDC_E_NOMEM, "gamma: scratch allocation failed");
     double *d_out = scr + ns - 4;
     double *d_d2 = scr + ns;
-    int4 *d_offs = (int4 *)(scr + ns + offs.size());
-    unsigned long long *d_cnt = (unsigned long long *)(scr + ns + 2 * offs.size());
+    int4 *d_offs = (int4 *)(scr + ns + no);
+    unsigned long long *d_cnt = (unsigned long long *)(scr + ns + 3 * no);
     unsigned long long cnt[2] = {0, 0};
     hipError_t e = hipMemcpyAsync(d_d2, d2.data(), d2.size() * 8, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipMemcpyAsync(d_offs, offs.data(), offs.size() * 16, hipMemcpyHostToDevice, s);

@@ -1,0 +1,1008 @@
+// Dose denoiser: a 3-level 3D U-Net (16/32/64 channels) trained and run with
+// hand-written BF16 MFMA kernels accumulating in FP32 (CDNA4
+// v_mfma_f32_16x16x32_bf16).
+//
+// Activations are bfloat16, channels-last: element (voxel v, channel c) of a
+// view is p[v * pitch + c], channel counts padded to multiples of 8 so that a
+// lane loads 8 channels (16 bytes) at once.  Concatenations are views into one
+// buffer (no copies).  Weights live as FP32 master copies in the canonical
+// layout of the network description (per layer: weights, then biases) and are
+// packed to bfloat16 GEMM operands after every update.
+//
+// Kernels:
+//   igemm    implicit GEMM, rows = voxels, cols = output channels, K = kernel
+//            offsets x input channels.  Operand gathers: 3x3x3 neighbours with
+//            zero padding, 1x1, or the 8 fine voxels of a coarse voxel.
+//            Epilogues: bias, ReLU, a 0/1 mask (ReLU backward), bf16 store, or
+//            a depth-to-space store (transposed convolution).
+//   wgrad    weight gradient sum_v P[v][i] * Q[map(v, o)][j] over voxels, tiles
+//            transposed through LDS, per-slab partials summed in a fixed order.
+//   small kernels: input packing, 2x2x2 average pool and its adjoint, the 1x1
+//            head with residual and MSE loss, bias gradients, Adam.
+#include "fdc.h"
+#include "fdc_device.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+namespace fdc {
+namespace nn {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned short u16;
+
+enum { A_CONV3 = 0, A_CONV1 = 1, A_S2D = 2 };
+enum { E_STORE = 0, E_D2S = 1 };
+
+struct Grid {
+    int nx, ny, nz;
+};
+
+__device__ inline u16 f2bf(float f)
+{
+    uint32_t u = __builtin_bit_cast(uint32_t, f);
+    u += 0x7FFFu + ((u >> 16) & 1u);            // round to nearest even
+    return (u16)(u >> 16);
+}
+
+__device__ inline float bf2f(u16 b) { return __builtin_bit_cast(float, (uint32_t)b << 16); }
+
+__device__ inline bf16x8 load8(const u16 *p)
+{
+    const uint4 q = *(const uint4 *)p;
+    return __builtin_bit_cast(bf16x8, q);
+}
+
+__device__ inline bf16x8 zero8() { return __builtin_bit_cast(bf16x8, make_uint4(0, 0, 0, 0)); }
+
+// ---------------------------------------------------------------------------
+// implicit GEMM.  One wave computes 16*MT consecutive rows x 16*NT columns.
+// Rows index the row grid g (output voxels; coarse voxels for D2S and S2D).
+// Operand A[row][k], k = o * cpad + c (o: kernel offset, c: source channel):
+//   A_CONV3: source voxel = row voxel + (dz-1, dy-1, dx-1), o = (dz*3+dy)*3+dx
+//   A_CONV1: source voxel = row voxel
+//   A_S2D  : source grid is 2x finer, source voxel = 2*row + (a>>2, (a>>1)&1, a&1), o = a
+// Operand B[k][n] = wpk[n * kpad + k] (packed weights, zero padded).
+// v_mfma_f32_16x16x32_bf16 lane layout: A[i][k] in lane i + 16*(k/8), element
+// k%8; B[k][j] in lane j + 16*(k/8), element k%8; D[i][j] in lane j +
+// 16*(i/4), element i%4.
+// Columns are split over blockIdx.y in blocks of 16*NT.
+template <int AM, int EM, int MT, int NT>
+__global__ void __launch_bounds__(256) igemm_kernel(const u16 *__restrict__ src, int src_pitch, int cpad, Grid g,
+                                                    const u16 *__restrict__ wpk, int kpad, int n_cols,
+                                                    const float *__restrict__ bias, int relu,
+                                                    const u16 *__restrict__ mask, int mask_pitch,
+                                                    u16 *__restrict__ dst, int dst_pitch, int d2s_cout)
+{
+    const int n_base = blockIdx.y * 16 * NT;
+    const int lane = threadIdx.x & 63;
+    const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const long n_rows = (long)g.nx * g.ny * g.nz;
+    const long row0 = (long)wave * (16 * MT);
+    if (row0 >= n_rows) return;
+    const int li = lane & 15, lg = lane >> 4;
+    const int n_off = AM == A_CONV3 ? 27 : AM == A_S2D ? 8 : 1;
+    const int kvalid = n_off * cpad;
+    const int fx = 2 * g.nx, fy = 2 * g.ny;     // fine grid (A_S2D sources)
+
+    int rz[MT], ry[MT], rx[MT];
+    bool rok[MT];
+#pragma unroll
+    for (int m = 0; m < MT; ++m) {
+        const long r = row0 + 16 * m + li;
+        rok[m] = r < n_rows;
+        const long rr = rok[m] ? r : 0;
+        rx[m] = (int)(rr % g.nx);
+        ry[m] = (int)((rr / g.nx) % g.ny);
+        rz[m] = (int)(rr / ((long)g.nx * g.ny));
+    }
+    f32x4 acc[MT][NT];
+#pragma unroll
+    for (int m = 0; m < MT; ++m)
+#pragma unroll
+        for (int t = 0; t < NT; ++t) acc[m][t] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+    for (int k0 = 0; k0 < kpad; k0 += 32) {
+        const int k = k0 + 8 * lg;
+        const int o = k / cpad, c = k - o * cpad;
+        bf16x8 a[MT];
+#pragma unroll
+        for (int m = 0; m < MT; ++m) {
+            a[m] = zero8();
+            if (k < kvalid && rok[m]) {
+                long sv = -1;
+                if (AM == A_CONV3) {
+                    const int z = rz[m] + o / 9 - 1, y = ry[m] + (o / 3) % 3 - 1, x = rx[m] + o % 3 - 1;
+                    if (z >= 0 && z < g.nz && y >= 0 && y < g.ny && x >= 0 && x < g.nx)
+                        sv = ((long)z * g.ny + y) * g.nx + x;
+                } else if (AM == A_CONV1) {
+                    sv = ((long)rz[m] * g.ny + ry[m]) * g.nx + rx[m];
+                } else {
+                    const int z = 2 * rz[m] + (o >> 2), y = 2 * ry[m] + ((o >> 1) & 1), x = 2 * rx[m] + (o & 1);
+                    sv = ((long)z * fy + y) * fx + x;
+                }
+                if (sv >= 0) a[m] = load8(src + sv * src_pitch + c);
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            const int n = n_base + 16 * t + li;
+            const bf16x8 b = n < n_cols ? load8(wpk + (long)n * kpad + k) : zero8();
+#pragma unroll
+            for (int m = 0; m < MT; ++m) acc[m][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[m], b, acc[m][t], 0, 0, 0);
+        }
+    }
+    // epilogue: lane holds D[4*lg + e][li] of every (m, t) tile
+#pragma unroll
+    for (int m = 0; m < MT; ++m)
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            const int n = n_base + 16 * t + li;
+            if (n >= n_cols) continue;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const long r = row0 + 16 * m + 4 * lg + e;
+                if (r >= n_rows) continue;
+                float v = acc[m][t][e];
+                if (EM == E_STORE) {
+                    if (bias) v += bias[n];
+                    if (relu) v = fmaxf(v, 0.f);
+                    if (mask && !(bf2f(mask[r * mask_pitch + n]) > 0.f)) v = 0.f;
+                    dst[r * dst_pitch + n] = f2bf(v);
+                } else {
+                    const int a8 = n / d2s_cout, co = n - a8 * d2s_cout;
+                    if (bias) v += bias[co];
+                    const int x = (int)(r % g.nx), y = (int)((r / g.nx) % g.ny), z = (int)(r / ((long)g.nx * g.ny));
+                    const long fv = ((long)(2 * z + (a8 >> 2)) * fy + (2 * y + ((a8 >> 1) & 1))) * fx + 2 * x + (a8 & 1);
+                    dst[fv * dst_pitch + co] = f2bf(v);
+                }
+            }
+        }
+}
+
+// ---------------------------------------------------------------------------
+// weight gradient: part[slab][o][i][j] = sum over the slab's rows v of
+// P[v][i] * Q[src(v, o)][j], with src as in the igemm gathers:
+//   A_CONV3: Q on the row grid, neighbour o (zero outside);  A_S2D: Q on the
+//   2x finer grid, sub-voxel o.  i < pc, j < qc (multiples of 16, zero padded).
+// 32 rows at a time are staged in LDS transposed ([channel][row]) so that a
+// lane's 8 consecutive rows of one channel are one 16-byte read.
+template <int AM>
+__global__ void __launch_bounds__(256) wgrad_kernel(const u16 *__restrict__ P, int p_pitch, int p_ch,
+                                                    const u16 *__restrict__ Q, int q_pitch, int q_ch, Grid g,
+                                                    long rows_per_slab, float *__restrict__ part, int pc, int qc)
+{
+    __shared__ __attribute__((aligned(16))) u16 sP[64 * 32];
+    __shared__ __attribute__((aligned(16))) u16 sQ[64 * 32];
+    const int o = blockIdx.x;
+    const int slab = blockIdx.y;
+    const int n_off = gridDim.x;
+    const long n_rows = (long)g.nx * g.ny * g.nz;
+    const long r_begin = (long)slab * rows_per_slab;
+    const long r_end = std::min<long>(n_rows, r_begin + rows_per_slab);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int li = lane & 15, lg = lane >> 4;
+    const int tiles_i = pc / 16, tiles_j = qc / 16, n_tiles = tiles_i * tiles_j;
+    const int fx = 2 * g.nx, fy = 2 * g.ny;
+    f32x4 acc[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc[q] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+    for (long r0 = r_begin; r0 < r_end; r0 += 32) {
+        // stage: thread -> (row 0..31, channel group of 8)
+        for (int s = threadIdx.x; s < 32 * 8; s += blockDim.x) {
+            const int rr = s & 31, cg = s >> 5;            // cg 0..7 -> channels 8cg..8cg+7
+            const long r = r0 + rr;
+            uint4 vp = make_uint4(0, 0, 0, 0), vq = make_uint4(0, 0, 0, 0);
+            if (r < r_end) {
+                if (8 * cg < p_ch) vp = *(const uint4 *)(P + r * p_pitch + 8 * cg);
+                if (8 * cg < q_ch) {
+                    const int x = (int)(r % g.nx), y = (int)((r / g.nx) % g.ny), z = (int)(r / ((long)g.nx * g.ny));
+                    long sv = -1;
+                    if (AM == A_CONV3) {
+                        const int zz = z + o / 9 - 1, yy = y + (o / 3) % 3 - 1, xx = x + o % 3 - 1;
+                        if (zz >= 0 && zz < g.nz && yy >= 0 && yy < g.ny && xx >= 0 && xx < g.nx)
+                            sv = ((long)zz * g.ny + yy) * g.nx + xx;
+                    } else {
+                        sv = ((long)(2 * z + (o >> 2)) * fy + (2 * y + ((o >> 1) & 1))) * fx + 2 * x + (o & 1);
+                    }
+                    if (sv >= 0) vq = *(const uint4 *)(Q + sv * q_pitch + 8 * cg);
+                }
+            }
+            const u16 *hp = (const u16 *)&vp, *hq = (const u16 *)&vq;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                sP[(8 * cg + e) * 32 + rr] = hp[e];
+                sQ[(8 * cg + e) * 32 + rr] = hq[e];
+            }
+        }
+        __syncthreads();
+        // MFMA over the 32 staged rows: K = rows
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int tile = wave + 4 * q;
+            if (tile < n_tiles) {
+                const int ti = tile / tiles_j, tj = tile % tiles_j;
+                const bf16x8 a = load8(sP + (16 * ti + li) * 32 + 8 * lg);
+                const bf16x8 b = load8(sQ + (16 * tj + li) * 32 + 8 * lg);
+                acc[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[q], 0, 0, 0);
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int tile = wave + 4 * q;
+        if (tile >= n_tiles) continue;
+        const int ti = tile / tiles_j, tj = tile % tiles_j;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int i = 16 * ti + 4 * lg + e, j = 16 * tj + li;
+            part[(((long)slab * n_off + o) * pc + i) * qc + j] = acc[q][e];
+        }
+    }
+}
+
+// sum the slabs in a fixed order: out[(o, i, j)] = sum_s part[s][o][i][j]
+__global__ void slab_sum_kernel(const float *__restrict__ part, int slabs, long per_slab, float *__restrict__ out)
+{
+    for (long x = blockIdx.x * (long)blockDim.x + threadIdx.x; x < per_slab; x += (long)gridDim.x * blockDim.x) {
+        float s = 0.f;
+        for (int k = 0; k < slabs; ++k) s += part[k * per_slab + x];
+        out[x] = s;
+    }
+}
+
+// bias gradient partials: part[block][c] = sum over the block's voxels of G[v][c]
+__global__ void bias_part_kernel(const u16 *__restrict__ G, int pitch, int C, long n, long per_block,
+                                 float *__restrict__ part)
+{
+    const long v0 = blockIdx.x * per_block, v1 = std::min<long>(n, v0 + per_block);
+    for (int c = threadIdx.y; c < C; c += blockDim.y) {
+        float s = 0.f;
+        for (long v = v0 + threadIdx.x; v < v1; v += blockDim.x) s += bf2f(G[v * pitch + c]);
+        for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+        if (threadIdx.x == 0) part[(long)blockIdx.x * C + c] = s;
+    }
+}
+
+// FP32 [2][n] channels-first input -> bf16 channels-last, pitch 8 (zeros beyond 2)
+__global__ void pack_input_kernel(const float *__restrict__ in, long n, u16 *__restrict__ x)
+{
+    for (long v = blockIdx.x * (long)blockDim.x + threadIdx.x; v < n; v += (long)gridDim.x * blockDim.x) {
+        uint4 q = make_uint4(0, 0, 0, 0);
+        u16 *h = (u16 *)&q;
+        h[0] = f2bf(in[v]);
+        h[1] = f2bf(in[n + v]);
+        *(uint4 *)(x + v * 8) = q;
+    }
+}
+
+// 2x2x2 average pool: coarse grid g, fine grid 2g
+__global__ void pool_kernel(const u16 *__restrict__ src, int s_pitch, int C, Grid g, u16 *__restrict__ dst, int d_pitch)
+{
+    const long n = (long)g.nx * g.ny * g.nz;
+    const int fx = 2 * g.nx, fy = 2 * g.ny;
+    for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < n * C; t += (long)gridDim.x * blockDim.x) {
+        const long v = t / C;
+        const int c = (int)(t - v * C);
+        const int x = (int)(v % g.nx), y = (int)((v / g.nx) % g.ny), z = (int)(v / ((long)g.nx * g.ny));
+        float s = 0.f;
+        for (int a = 0; a < 8; ++a) {
+            const long fv = ((long)(2 * z + (a >> 2)) * fy + (2 * y + ((a >> 1) & 1))) * fx + 2 * x + (a & 1);
+            s += bf2f(src[fv * s_pitch + c]);
+        }
+        dst[v * d_pitch + c] = f2bf(s * 0.125f);
+    }
+}
+
+// adjoint of the pool plus the skip-connection gradient, masked by ReLU:
+// ge[fine v][c] = bf16( (bf16(gp[coarse(v)][c] / 8) + skip[v][c]) * (e[v][c] > 0) )
+__global__ void pool_back_kernel(const u16 *__restrict__ gp, int gp_pitch, const u16 *__restrict__ skip,
+                                 int skip_pitch, const u16 *__restrict__ e, int e_pitch, int C, Grid fine,
+                                 u16 *__restrict__ ge, int ge_pitch)
+{
+    const long n = (long)fine.nx * fine.ny * fine.nz;
+    const int cx = fine.nx / 2, cy = fine.ny / 2;
+    for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < n * C; t += (long)gridDim.x * blockDim.x) {
+        const long v = t / C;
+        const int c = (int)(t - v * C);
+        const int x = (int)(v % fine.nx), y = (int)((v / fine.nx) % fine.ny), z = (int)(v / ((long)fine.nx * fine.ny));
+        const long cv = ((long)(z / 2) * cy + y / 2) * cx + x / 2;
+        const float up = bf2f(f2bf(bf2f(gp[cv * gp_pitch + c]) * 0.125f));
+        const float s = bf2f(skip[v * skip_pitch + c]) + up;
+        ge[v * ge_pitch + c] = f2bf(bf2f(e[v * e_pitch + c]) > 0.f ? s : 0.f);
+    }
+}
+
+// head: y = w . d1 + b + dose; loss partials; gy = 2 (y - t) / N; the head's
+// input gradient w * gy masked by d1 > 0 (bf16) and its weight/bias partials
+__global__ void head_kernel(const u16 *__restrict__ d1, int pitch, const float *__restrict__ in, long n,
+                            const float *__restrict__ w, const float *__restrict__ target, float *__restrict__ y_out,
+                            u16 *__restrict__ gd1, double *__restrict__ loss_part, float *__restrict__ gw_part,
+                            long per_block)
+{
+    __shared__ double s_loss[256];
+    __shared__ float s_g[256][17];
+    const long v0 = blockIdx.x * per_block, v1 = std::min<long>(n, v0 + per_block);
+    double l = 0.0;
+    float gwl[17];
+    for (int c = 0; c < 17; ++c) gwl[c] = 0.f;
+    const double inv_n = 1.0 / (double)n;
+    for (long v = v0 + threadIdx.x; v < v1; v += blockDim.x) {
+        float h[16];
+        float y = w[16];
+        for (int c = 0; c < 16; ++c) {
+            h[c] = bf2f(d1[v * pitch + c]);
+            y += w[c] * h[c];
+        }
+        y += in[v];
+        if (y_out) y_out[v] = y;
+        if (target) {
+            const float d = y - target[v];
+            l += (double)d * d;
+            const float gy = (float)(2.0 * d * inv_n);
+            for (int c = 0; c < 16; ++c) {
+                gwl[c] += gy * h[c];
+                gd1[v * pitch + c] = f2bf(h[c] > 0.f ? w[c] * gy : 0.f);
+            }
+            gwl[16] += gy;
+        }
+    }
+    if (!target) return;
+    s_loss[threadIdx.x] = l;
+    for (int c = 0; c < 17; ++c) s_g[threadIdx.x][c] = gwl[c];
+    __syncthreads();
+    for (int wdt = blockDim.x / 2; wdt > 0; wdt >>= 1) {
+        if ((int)threadIdx.x < wdt) {
+            s_loss[threadIdx.x] += s_loss[threadIdx.x + wdt];
+            for (int c = 0; c < 17; ++c) s_g[threadIdx.x][c] += s_g[threadIdx.x + wdt][c];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        loss_part[blockIdx.x] = s_loss[0] * inv_n;
+        for (int c = 0; c < 17; ++c) gw_part[blockIdx.x * 17 + c] = s_g[0][c];
+    }
+}
+
+__global__ void head_finish_kernel(const double *__restrict__ loss_part, const float *__restrict__ gw_part, int nb,
+                                   double *__restrict__ loss, float *__restrict__ grad_head)
+{
+    const int c = threadIdx.x;
+    if (c < 17) {
+        float s = 0.f;
+        for (int b = 0; b < nb; ++b) s += gw_part[b * 17 + c];
+        grad_head[c] = s;
+    }
+    if (c == 0) {
+        double l = 0.0;
+        for (int b = 0; b < nb; ++b) l += loss_part[b];
+        *loss = l;
+    }
+}
+
+// Adam with bias correction (Kingma and Ba 2015) on the FP32 master copy
+__global__ void adam_kernel(float *__restrict__ p, const float *__restrict__ g, float *__restrict__ m,
+                            float *__restrict__ s, long n, float lr, float b1, float b2, float eps, float c1, float c2)
+{
+    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+        const float gi = g[i];
+        const float mi = b1 * m[i] + (1.f - b1) * gi;
+        const float si = b2 * s[i] + (1.f - b2) * gi * gi;
+        m[i] = mi;
+        s[i] = si;
+        p[i] -= lr * (mi / c1) / (sqrtf(si / c2) + eps);
+    }
+}
+
+// Pack FP32 canonical weights into bf16 GEMM operands wpk[n * kpad + k].
+//   mode 0: conv3 forward   n = co,            k = o * cpad_in + ci,   w[co][ci][o]
+//   mode 1: conv3 backward  n = ci,            k = o * cpad_out + co,  w[co][ci][26 - o]
+//   mode 2: tconv forward   n = a * cout + co, k = ci,                 w[ci][co][a]
+//   mode 3: tconv backward  n = ci,            k = a * cpad_out + co,  w[ci][co][a]
+__global__ void pack_kernel(const float *__restrict__ w, int mode, int cin, int cout, int cpad, int n_cols, int kpad,
+                            u16 *__restrict__ wpk)
+{
+    const long total = (long)n_cols * kpad;
+    for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < total; t += (long)gridDim.x * blockDim.x) {
+        const int n = (int)(t / kpad), k = (int)(t - (long)n * kpad);
+        float v = 0.f;
+        if (mode == 0) {
+            const int o = k / cpad, ci = k % cpad;
+            if (o < 27 && ci < cin) v = w[((long)n * cin + ci) * 27 + o];
+        } else if (mode == 1) {
+            const int o = k / cpad, co = k % cpad;
+            if (o < 27 && co < cout) v = w[((long)co * cin + n) * 27 + (26 - o)];
+        } else if (mode == 2) {
+            const int a = n / cout, co = n % cout;
+            if (k < cin) v = w[((long)k * cout + co) * 8 + a];
+        } else {
+            const int a = k / cpad, co = k % cpad;
+            if (a < 8 && co < cout) v = w[((long)n * cout + co) * 8 + a];
+        }
+        wpk[t] = f2bf(v);
+    }
+}
+
+// canonical weight gradient from the summed wgrad output s[o][i][j]
+//   conv3: i = co, j = ci  -> g[co][ci][o];   tconv: i = ci, j = co -> g[ci][co][o]
+__global__ void scatter_wgrad_kernel(const float *__restrict__ s, int n_off, int pc, int qc, int ni, int nj,
+                                     float *__restrict__ gw)
+{
+    const long total = (long)n_off * ni * nj;
+    for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < total; t += (long)gridDim.x * blockDim.x) {
+        const int o = (int)(t % n_off);
+        const long ij = t / n_off;
+        const int j = (int)(ij % nj), i = (int)(ij / nj);
+        gw[((long)i * nj + j) * n_off + o] = s[((long)o * pc + i) * qc + j];
+    }
+}
+
+// head parameters as the head kernel reads them: bf16-rounded weights, FP32 bias
+__global__ void head_weights_kernel(const float *__restrict__ p, float *__restrict__ out)
+{
+    const int c = threadIdx.x;
+    if (c < 16) out[c] = bf2f(f2bf(p[c]));
+    if (c == 16) out[16] = p[16];
+}
+
+__global__ void bias_finish_kernel(const float *__restrict__ part, int nb, int C, float *__restrict__ gb)
+{
+    const int c = threadIdx.x;
+    if (c >= C) return;
+    float s = 0.f;
+    for (int b = 0; b < nb; ++b) s += part[b * C + c];
+    gb[c] = s;
+}
+
+// ------------------------------------------------------------------ host --
+enum { K_CONV3 = 0, K_TCONV = 1, K_CONV1 = 2 };
+
+struct LayerDesc {
+    const char *name;
+    int kind, cin, cout;
+};
+
+// the network, in the canonical parameter order (weights then biases per layer)
+const LayerDesc kLayers[] = {
+    {"enc1a", K_CONV3, 2, 16}, {"enc1b", K_CONV3, 16, 16}, {"enc2a", K_CONV3, 16, 32}, {"enc2b", K_CONV3, 32, 32},
+    {"mida", K_CONV3, 32, 64}, {"midb", K_CONV3, 64, 64},  {"up2", K_TCONV, 64, 32},   {"dec2a", K_CONV3, 64, 32},
+    {"dec2b", K_CONV3, 32, 32}, {"up1", K_TCONV, 32, 16},  {"dec1a", K_CONV3, 32, 16}, {"dec1b", K_CONV3, 16, 16},
+    {"head", K_CONV1, 16, 1}};
+constexpr int kNumLayers = 13;
+enum { L_E1A, L_E1B, L_E2A, L_E2B, L_MA, L_MB, L_UP2, L_D2A, L_D2B, L_UP1, L_D1A, L_D1B, L_HEAD };
+
+inline int pad8(int c) { return (c + 7) & ~7; }
+inline int pad16(int c) { return (c + 15) & ~15; }
+inline int pad32(int k) { return (k + 31) & ~31; }
+
+long weight_count(const LayerDesc &L)
+{
+    return (long)L.cin * L.cout * (L.kind == K_CONV3 ? 27 : L.kind == K_TCONV ? 8 : 1);
+}
+
+long total_params()
+{
+    long n = 0;
+    for (const LayerDesc &L : kLayers) n += weight_count(L) + L.cout;
+    return n;
+}
+
+struct View {
+    u16 *p;
+    int pitch;
+    int ch;
+};
+
+} // namespace nn
+} // namespace fdc
+
+using namespace fdc;
+using namespace fdc::nn;
+
+struct fdc_unet {
+    int device = 0;
+    Grid g[3];                      // full, half, quarter resolution
+    long nv[3];
+    std::string err;
+    long n_params = 0;
+    long w_off[kNumLayers], b_off[kNumLayers];
+    float *params = nullptr, *grads = nullptr, *adam_m = nullptr, *adam_s = nullptr;
+    int step = 0;
+    u16 *wpk_f[kNumLayers] = {}, *wpk_b[kNumLayers] = {};
+    int kpad_f[kNumLayers] = {}, ncol_f[kNumLayers] = {}, kpad_b[kNumLayers] = {}, ncol_b[kNumLayers] = {};
+    std::vector<void *> allocs;
+    // activations (bf16, channels-last)
+    u16 *x, *e1a, *c1, *p1, *e2a, *c2, *p2, *ma, *m, *d2a, *d2, *d1a, *d1;
+    // activation gradients
+    u16 *gd1, *gd1a, *gc1, *gd2, *gd2a, *gc2, *gm, *gma, *gp2, *ge2, *ge2a, *gp1, *ge1, *ge1a;
+    float *wpart = nullptr, *wsum = nullptr, *bpart = nullptr, *hpart = nullptr, *hw = nullptr;
+    double *lpart = nullptr, *loss = nullptr;
+    size_t wpart_n = 0;
+};
+
+namespace {
+
+int ufail(fdc_unet *u, int code, const char *msg, hipError_t e = hipSuccess)
+{
+    if (u) u->err = std::string(msg) + (e != hipSuccess ? std::string(": ") + hipGetErrorString(e) : "");
+    return code;
+}
+
+template <class T> T *ualloc(fdc_unet *u, size_t n)
+{
+    void *p = nullptr;
+    if (hipMalloc(&p, std::max<size_t>(n, 1) * sizeof(T)) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    u->allocs.push_back(p);
+    return (T *)p;
+}
+
+uint32_t blocks_for(long n, int per = 256, long cap = 16384) { return (uint32_t)std::max<long>(1, std::min<long>(cap, (n + per - 1) / per)); }
+
+// one implicit-GEMM launch: rows on grid g, n_cols output columns
+hipError_t igemm(int am, int em, const View &src, int cpad, const Grid &g, const u16 *wpk, int kpad, int n_cols,
+                 const float *bias, bool relu, const View *mask, const View &dst, int d2s_cout, hipStream_t s)
+{
+    const long rows = (long)g.nx * g.ny * g.nz;
+    const long waves = (rows + 31) / 32;                  // MT = 2: 32 rows per wave
+    const int nt = n_cols >= 64 ? 4 : n_cols >= 32 ? 2 : 1;
+    const dim3 grid((uint32_t)((waves + 3) / 4), (uint32_t)((n_cols + 16 * nt - 1) / (16 * nt)));
+    const u16 *mp = mask ? mask->p : nullptr;
+    const int mpitch = mask ? mask->pitch : 0;
+#define IG(AM_, EM_, NT_) hipLaunchKernelGGL((igemm_kernel<AM_, EM_, 2, NT_>), grid, dim3(256), 0, s, src.p, src.pitch, \
+                                             cpad, g, wpk, kpad, n_cols, bias, (int)relu, mp, mpitch, dst.p, dst.pitch, d2s_cout)
+#define IGN(AM_, EM_) do { if (nt == 4) IG(AM_, EM_, 4); else if (nt == 2) IG(AM_, EM_, 2); else IG(AM_, EM_, 1); } while (0)
+    if (em == E_D2S) {
+        if (am != A_CONV1) return hipErrorInvalidValue;
+        IGN(A_CONV1, E_D2S);
+    } else if (am == A_CONV3) {
+        IGN(A_CONV3, E_STORE);
+    } else if (am == A_S2D) {
+        IGN(A_S2D, E_STORE);
+    } else {
+        IGN(A_CONV1, E_STORE);
+    }
+#undef IGN
+#undef IG
+    return hipGetLastError();
+}
+
+} // namespace
+
+namespace {
+
+hipError_t wgrad(int am, const View &P, int p_ch, const View &Q, int q_ch, const Grid &g, int n_off, fdc_unet *u,
+                 bool transposed_layer, int ni, int nj, float *gw_out, hipStream_t s)
+{
+    const long rows = (long)g.nx * g.ny * g.nz;
+    const int pc = pad16(p_ch), qc = pad16(q_ch);
+    long slabs = std::min<long>(64, std::max<long>(1, rows / 2048));
+    long per = (rows + slabs - 1) / slabs;
+    per = (per + 31) & ~31L;
+    slabs = (rows + per - 1) / per;
+    const size_t need = (size_t)slabs * n_off * pc * qc;
+    if (need > u->wpart_n) return hipErrorInvalidValue;
+    if (am == A_CONV3)
+        hipLaunchKernelGGL((wgrad_kernel<A_CONV3>), dim3(n_off, (uint32_t)slabs), dim3(256), 0, s, P.p, P.pitch, p_ch,
+                           Q.p, Q.pitch, q_ch, g, per, u->wpart, pc, qc);
+    else
+        hipLaunchKernelGGL((wgrad_kernel<A_S2D>), dim3(n_off, (uint32_t)slabs), dim3(256), 0, s, P.p, P.pitch, p_ch,
+                           Q.p, Q.pitch, q_ch, g, per, u->wpart, pc, qc);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const long per_slab = (long)n_off * pc * qc;
+    hipLaunchKernelGGL(slab_sum_kernel, dim3(blocks_for(per_slab)), dim3(256), 0, s, u->wpart, (int)slabs, per_slab,
+                       u->wsum);
+    hipLaunchKernelGGL(scatter_wgrad_kernel, dim3(blocks_for((long)n_off * ni * nj)), dim3(256), 0, s, u->wsum, n_off,
+                       pc, qc, ni, nj, gw_out);
+    (void)transposed_layer;
+    return hipGetLastError();
+}
+
+hipError_t bias_grad(const View &G, int C, long n, fdc_unet *u, float *gb, hipStream_t s)
+{
+    const long per = 4096;
+    const int nb = (int)((n + per - 1) / per);
+    hipLaunchKernelGGL(bias_part_kernel, dim3(nb), dim3(64, 4), 0, s, G.p, G.pitch, C, n, per, u->bpart);
+    hipLaunchKernelGGL(bias_finish_kernel, dim3(1), dim3(64), 0, s, u->bpart, nb, C, gb);
+    return hipGetLastError();
+}
+
+hipError_t pack_all(fdc_unet *u, hipStream_t s)
+{
+    for (int l = 0; l < kNumLayers; ++l) {
+        const LayerDesc &L = kLayers[l];
+        const float *w = u->params + u->w_off[l];
+        if (L.kind == K_CONV3) {
+            hipLaunchKernelGGL(pack_kernel, dim3(blocks_for((long)u->ncol_f[l] * u->kpad_f[l])), dim3(256), 0, s, w, 0,
+                               L.cin, L.cout, pad8(L.cin), u->ncol_f[l], u->kpad_f[l], u->wpk_f[l]);
+            if (u->wpk_b[l])
+                hipLaunchKernelGGL(pack_kernel, dim3(blocks_for((long)u->ncol_b[l] * u->kpad_b[l])), dim3(256), 0, s, w,
+                                   1, L.cin, L.cout, pad8(L.cout), u->ncol_b[l], u->kpad_b[l], u->wpk_b[l]);
+        } else if (L.kind == K_TCONV) {
+            hipLaunchKernelGGL(pack_kernel, dim3(blocks_for((long)u->ncol_f[l] * u->kpad_f[l])), dim3(256), 0, s, w, 2,
+                               L.cin, L.cout, pad8(L.cin), u->ncol_f[l], u->kpad_f[l], u->wpk_f[l]);
+            hipLaunchKernelGGL(pack_kernel, dim3(blocks_for((long)u->ncol_b[l] * u->kpad_b[l])), dim3(256), 0, s, w, 3,
+                               L.cin, L.cout, pad8(L.cout), u->ncol_b[l], u->kpad_b[l], u->wpk_b[l]);
+        }
+    }
+    return hipGetLastError();
+}
+
+// views of the activation buffers (concatenations share one buffer)
+struct Views {
+    View x, e1a, u1, e1, c1, p1, e2a, u2, e2, c2, p2, ma, m, d2a, d2, d1a, d1;
+    View gd1, gd1a, gc1, gu1, ge1s, gd2, gd2a, gc2, gu2, ge2s, gm, gma, gp2, ge2, ge2a, gp1, ge1, ge1a;
+};
+
+Views views(const fdc_unet *u)
+{
+    Views v;
+    v.x = {u->x, 8, 2};
+    v.e1a = {u->e1a, 16, 16};
+    v.c1 = {u->c1, 32, 32};
+    v.u1 = {u->c1, 32, 16};
+    v.e1 = {u->c1 + 16, 32, 16};
+    v.p1 = {u->p1, 16, 16};
+    v.e2a = {u->e2a, 32, 32};
+    v.c2 = {u->c2, 64, 64};
+    v.u2 = {u->c2, 64, 32};
+    v.e2 = {u->c2 + 32, 64, 32};
+    v.p2 = {u->p2, 32, 32};
+    v.ma = {u->ma, 64, 64};
+    v.m = {u->m, 64, 64};
+    v.d2a = {u->d2a, 32, 32};
+    v.d2 = {u->d2, 32, 32};
+    v.d1a = {u->d1a, 16, 16};
+    v.d1 = {u->d1, 16, 16};
+    v.gd1 = {u->gd1, 16, 16};
+    v.gd1a = {u->gd1a, 16, 16};
+    v.gc1 = {u->gc1, 32, 32};
+    v.gu1 = {u->gc1, 32, 16};
+    v.ge1s = {u->gc1 + 16, 32, 16};
+    v.gd2 = {u->gd2, 32, 32};
+    v.gd2a = {u->gd2a, 32, 32};
+    v.gc2 = {u->gc2, 64, 64};
+    v.gu2 = {u->gc2, 64, 32};
+    v.ge2s = {u->gc2 + 32, 64, 32};
+    v.gm = {u->gm, 64, 64};
+    v.gma = {u->gma, 64, 64};
+    v.gp2 = {u->gp2, 32, 32};
+    v.ge2 = {u->ge2, 32, 32};
+    v.ge2a = {u->ge2a, 32, 32};
+    v.gp1 = {u->gp1, 16, 16};
+    v.ge1 = {u->ge1, 16, 16};
+    v.ge1a = {u->ge1a, 16, 16};
+    return v;
+}
+
+hipError_t conv_fwd(fdc_unet *u, int l, const View &src, const Grid &g, const View &dst, hipStream_t s)
+{
+    const LayerDesc &L = kLayers[l];
+    return igemm(A_CONV3, E_STORE, src, pad8(L.cin), g, u->wpk_f[l], u->kpad_f[l], L.cout, u->params + u->b_off[l],
+                 true, nullptr, dst, 0, s);
+}
+
+hipError_t forward_pass(fdc_unet *u, const float *in, hipStream_t s)
+{
+    const Views v = views(u);
+    const Grid *g = u->g;
+    hipLaunchKernelGGL(pack_input_kernel, dim3(blocks_for(u->nv[0])), dim3(256), 0, s, in, u->nv[0], u->x);
+    hipError_t e = hipGetLastError();
+    if (!e) e = conv_fwd(u, L_E1A, v.x, g[0], v.e1a, s);
+    if (!e) e = conv_fwd(u, L_E1B, v.e1a, g[0], v.e1, s);
+    if (!e) {
+        hipLaunchKernelGGL(pool_kernel, dim3(blocks_for(u->nv[1] * 16)), dim3(256), 0, s, v.e1.p, v.e1.pitch, 16, g[1],
+                           v.p1.p, v.p1.pitch);
+        e = hipGetLastError();
+    }
+    if (!e) e = conv_fwd(u, L_E2A, v.p1, g[1], v.e2a, s);
+    if (!e) e = conv_fwd(u, L_E2B, v.e2a, g[1], v.e2, s);
+    if (!e) {
+        hipLaunchKernelGGL(pool_kernel, dim3(blocks_for(u->nv[2] * 32)), dim3(256), 0, s, v.e2.p, v.e2.pitch, 32, g[2],
+                           v.p2.p, v.p2.pitch);
+        e = hipGetLastError();
+    }
+    if (!e) e = conv_fwd(u, L_MA, v.p2, g[2], v.ma, s);
+    if (!e) e = conv_fwd(u, L_MB, v.ma, g[2], v.m, s);
+    if (!e) e = igemm(A_CONV1, E_D2S, v.m, 64, g[2], u->wpk_f[L_UP2], u->kpad_f[L_UP2], u->ncol_f[L_UP2],
+                      u->params + u->b_off[L_UP2], false, nullptr, v.u2, 32, s);
+    if (!e) e = conv_fwd(u, L_D2A, v.c2, g[1], v.d2a, s);
+    if (!e) e = conv_fwd(u, L_D2B, v.d2a, g[1], v.d2, s);
+    if (!e) e = igemm(A_CONV1, E_D2S, v.d2, 32, g[1], u->wpk_f[L_UP1], u->kpad_f[L_UP1], u->ncol_f[L_UP1],
+                      u->params + u->b_off[L_UP1], false, nullptr, v.u1, 16, s);
+    if (!e) e = conv_fwd(u, L_D1A, v.c1, g[0], v.d1a, s);
+    if (!e) e = conv_fwd(u, L_D1B, v.d1a, g[0], v.d1, s);
+    return e;
+}
+
+hipError_t backward_pass(fdc_unet *u, const float *in, hipStream_t s)
+{
+    const Views v = views(u);
+    const Grid *g = u->g;
+    float *G = u->grads;
+    auto gw = [&](int l) { return G + u->w_off[l]; };
+    auto gb = [&](int l) { return G + u->b_off[l]; };
+    auto bwd = [&](int l, const View &gout, const Grid &gr, const View *mask, const View &gin) {
+        const LayerDesc &L = kLayers[l];
+        return igemm(A_CONV3, E_STORE, gout, pad8(L.cout), gr, u->wpk_b[l], u->kpad_b[l], L.cin, nullptr, false, mask,
+                     gin, 0, s);
+    };
+    auto wg3 = [&](int l, const View &gout, const View &in_v, const Grid &gr) {
+        const LayerDesc &L = kLayers[l];
+        hipError_t e = wgrad(A_CONV3, gout, L.cout, in_v, L.cin, gr, 27, u, false, L.cout, L.cin, gw(l), s);
+        if (!e) e = bias_grad(gout, L.cout, (long)gr.nx * gr.ny * gr.nz, u, gb(l), s);
+        return e;
+    };
+    (void)in;
+    hipError_t e = hipSuccess;
+    // dec1b, dec1a
+    if (!e) e = bwd(L_D1B, v.gd1, g[0], &v.d1a, v.gd1a);
+    if (!e) e = wg3(L_D1B, v.gd1, v.d1a, g[0]);
+    if (!e) e = bwd(L_D1A, v.gd1a, g[0], nullptr, v.gc1);
+    if (!e) e = wg3(L_D1A, v.gd1a, v.c1, g[0]);
+    // up1: transposed conv 32 -> 16 (coarse rows on g[1])
+    if (!e) e = igemm(A_S2D, E_STORE, v.gu1, 16, g[1], u->wpk_b[L_UP1], u->kpad_b[L_UP1], 32, nullptr, false, &v.d2,
+                      v.gd2, 0, s);
+    if (!e) e = wgrad(A_S2D, v.d2, 32, v.gu1, 16, g[1], 8, u, true, 32, 16, gw(L_UP1), s);
+    if (!e) e = bias_grad(v.gu1, 16, u->nv[0], u, gb(L_UP1), s);
+    // dec2b, dec2a
+    if (!e) e = bwd(L_D2B, v.gd2, g[1], &v.d2a, v.gd2a);
+    if (!e) e = wg3(L_D2B, v.gd2, v.d2a, g[1]);
+    if (!e) e = bwd(L_D2A, v.gd2a, g[1], nullptr, v.gc2);
+    if (!e) e = wg3(L_D2A, v.gd2a, v.c2, g[1]);
+    // up2: transposed conv 64 -> 32 (coarse rows on g[2])
+    if (!e) e = igemm(A_S2D, E_STORE, v.gu2, 32, g[2], u->wpk_b[L_UP2], u->kpad_b[L_UP2], 64, nullptr, false, &v.m,
+                      v.gm, 0, s);
+    if (!e) e = wgrad(A_S2D, v.m, 64, v.gu2, 32, g[2], 8, u, true, 64, 32, gw(L_UP2), s);
+    if (!e) e = bias_grad(v.gu2, 32, u->nv[1], u, gb(L_UP2), s);
+    // mid
+    if (!e) e = bwd(L_MB, v.gm, g[2], &v.ma, v.gma);
+    if (!e) e = wg3(L_MB, v.gm, v.ma, g[2]);
+    if (!e) e = bwd(L_MA, v.gma, g[2], nullptr, v.gp2);
+    if (!e) e = wg3(L_MA, v.gma, v.p2, g[2]);
+    // pool 2 adjoint + skip, enc2
+    if (!e) {
+        hipLaunchKernelGGL(pool_back_kernel, dim3(blocks_for(u->nv[1] * 32)), dim3(256), 0, s, v.gp2.p, v.gp2.pitch,
+                           v.ge2s.p, v.ge2s.pitch, v.e2.p, v.e2.pitch, 32, g[1], v.ge2.p, v.ge2.pitch);
+        e = hipGetLastError();
+    }
+    if (!e) e = bwd(L_E2B, v.ge2, g[1], &v.e2a, v.ge2a);
+    if (!e) e = wg3(L_E2B, v.ge2, v.e2a, g[1]);
+    if (!e) e = bwd(L_E2A, v.ge2a, g[1], nullptr, v.gp1);
+    if (!e) e = wg3(L_E2A, v.ge2a, v.p1, g[1]);
+    // pool 1 adjoint + skip, enc1
+    if (!e) {
+        hipLaunchKernelGGL(pool_back_kernel, dim3(blocks_for(u->nv[0] * 16)), dim3(256), 0, s, v.gp1.p, v.gp1.pitch,
+                           v.ge1s.p, v.ge1s.pitch, v.e1.p, v.e1.pitch, 16, g[0], v.ge1.p, v.ge1.pitch);
+        e = hipGetLastError();
+    }
+    if (!e) e = bwd(L_E1B, v.ge1, g[0], &v.e1a, v.ge1a);
+    if (!e) e = wg3(L_E1B, v.ge1, v.e1a, g[0]);
+    if (!e) e = wg3(L_E1A, v.ge1a, v.x, g[0]);
+    return e;
+}
+
+hipError_t head(fdc_unet *u, const float *in, const float *target, float *out, hipStream_t s)
+{
+    const long per = 8192;
+    const int nb = (int)((u->nv[0] + per - 1) / per);
+    // the head reads bf16-rounded weights like every other layer (its bias stays FP32)
+    hipLaunchKernelGGL(head_weights_kernel, dim3(1), dim3(64), 0, s, u->params + u->w_off[L_HEAD], u->hw);
+    hipLaunchKernelGGL(head_kernel, dim3(nb), dim3(256), 0, s, u->d1, 16, in, u->nv[0], u->hw, target, out, u->gd1,
+                       u->lpart, u->hpart, per);
+    hipError_t e = hipGetLastError();
+    if (!e && target) {
+        hipLaunchKernelGGL(head_finish_kernel, dim3(1), dim3(64), 0, s, u->lpart, u->hpart, nb, u->loss,
+                           u->grads + u->w_off[L_HEAD]);
+        e = hipGetLastError();
+    }
+    return e;
+}
+
+} // namespace
+
+extern "C" {
+
+int64_t fdc_unet_num_params(void) { return total_params(); }
+
+const char *fdc_unet_last_error(const fdc_unet *u) { return u ? u->err.c_str() : "null"; }
+
+int fdc_unet_destroy(fdc_unet *u)
+{
+    if (!u) return FDC_E_ARG;
+    (void)hipSetDevice(u->device);
+    (void)hipDeviceSynchronize();
+    for (void *p : u->allocs) (void)hipFree(p);
+    delete u;
+    return FDC_OK;
+}
+
+int fdc_unet_create(fdc_unet **out, int hip_device, int nx, int ny, int nz)
+{
+    if (!out) return FDC_E_ARG;
+    *out = nullptr;
+    if (nx <= 0 || ny <= 0 || nz <= 0 || nx % 4 || ny % 4 || nz % 4) return FDC_E_ARG;
+    if ((long)nx * ny * nz >= (1L << 31)) return FDC_E_ARG;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || hip_device < 0 || hip_device >= ndev) {
+        (void)hipGetLastError();
+        return FDC_E_HIP;
+    }
+    fdc_unet *u = new (std::nothrow) fdc_unet();
+    if (!u) return FDC_E_NOMEM;
+    u->device = hip_device;
+    if (hipSetDevice(hip_device) != hipSuccess) { delete u; return FDC_E_HIP; }
+    for (int r = 0; r < 3; ++r) {
+        u->g[r] = Grid{nx >> r, ny >> r, nz >> r};
+        u->nv[r] = (long)u->g[r].nx * u->g[r].ny * u->g[r].nz;
+    }
+    long o = 0;
+    for (int l = 0; l < kNumLayers; ++l) {
+        u->w_off[l] = o;
+        o += weight_count(kLayers[l]);
+        u->b_off[l] = o;
+        o += kLayers[l].cout;
+    }
+    u->n_params = o;
+    bool ok = true;
+    auto A16 = [&](long n) { u16 *p = ualloc<u16>(u, (size_t)n); ok = ok && p; return p; };
+    u->params = ualloc<float>(u, o);
+    u->grads = ualloc<float>(u, o);
+    u->adam_m = ualloc<float>(u, o);
+    u->adam_s = ualloc<float>(u, o);
+    ok = u->params && u->grads && u->adam_m && u->adam_s;
+    for (int l = 0; l < kNumLayers; ++l) {
+        const LayerDesc &L = kLayers[l];
+        if (L.kind == K_CONV3) {
+            u->ncol_f[l] = L.cout; u->kpad_f[l] = pad32(27 * pad8(L.cin));
+            u->ncol_b[l] = L.cin;  u->kpad_b[l] = pad32(27 * pad8(L.cout));
+            u->wpk_f[l] = A16((long)u->ncol_f[l] * u->kpad_f[l]);
+            if (l != L_E1A) u->wpk_b[l] = A16((long)u->ncol_b[l] * u->kpad_b[l]);
+        } else if (L.kind == K_TCONV) {
+            u->ncol_f[l] = 8 * L.cout; u->kpad_f[l] = pad32(pad8(L.cin));
+            u->ncol_b[l] = L.cin;      u->kpad_b[l] = pad32(8 * pad8(L.cout));
+            u->wpk_f[l] = A16((long)u->ncol_f[l] * u->kpad_f[l]);
+            u->wpk_b[l] = A16((long)u->ncol_b[l] * u->kpad_b[l]);
+        }
+    }
+    const long n0 = u->nv[0], n1 = u->nv[1], n2 = u->nv[2];
+    u->x = A16(n0 * 8); u->e1a = A16(n0 * 16); u->c1 = A16(n0 * 32); u->p1 = A16(n1 * 16); u->e2a = A16(n1 * 32);
+    u->c2 = A16(n1 * 64); u->p2 = A16(n2 * 32); u->ma = A16(n2 * 64); u->m = A16(n2 * 64); u->d2a = A16(n1 * 32);
+    u->d2 = A16(n1 * 32); u->d1a = A16(n0 * 16); u->d1 = A16(n0 * 16);
+    u->gd1 = A16(n0 * 16); u->gd1a = A16(n0 * 16); u->gc1 = A16(n0 * 32); u->gd2 = A16(n1 * 32);
+    u->gd2a = A16(n1 * 32); u->gc2 = A16(n1 * 64); u->gm = A16(n2 * 64); u->gma = A16(n2 * 64);
+    u->gp2 = A16(n2 * 32); u->ge2 = A16(n1 * 32); u->ge2a = A16(n1 * 32); u->gp1 = A16(n1 * 16);
+    u->ge1 = A16(n0 * 16); u->ge1a = A16(n0 * 16);
+    u->wpart_n = (size_t)64 * 27 * 64 * 64;
+    u->wpart = ualloc<float>(u, u->wpart_n);
+    u->wsum = ualloc<float>(u, 27 * 64 * 64 + 256);
+    u->bpart = ualloc<float>(u, (size_t)((n0 + 4095) / 4096) * 64);
+    u->hpart = ualloc<float>(u, (size_t)((n0 + 8191) / 8192) * 17);
+    u->lpart = ualloc<double>(u, (size_t)((n0 + 8191) / 8192));
+    u->loss = ualloc<double>(u, 1);
+    u->hw = ualloc<float>(u, 32);
+    ok = ok && u->hw && u->wpart && u->wsum && u->bpart && u->hpart && u->lpart && u->loss;
+    if (!ok) { fdc_unet_destroy(u); return FDC_E_NOMEM; }
+    if (hipMemset(u->params, 0, o * 4) != hipSuccess || hipMemset(u->grads, 0, o * 4) != hipSuccess ||
+        hipMemset(u->adam_m, 0, o * 4) != hipSuccess || hipMemset(u->adam_s, 0, o * 4) != hipSuccess) {
+        fdc_unet_destroy(u);
+        return FDC_E_HIP;
+    }
+    *out = u;
+    return FDC_OK;
+}
+
+int fdc_unet_set_params(fdc_unet *u, const float *host, void *hip_stream)
+{
+    if (!u) return FDC_E_ARG;
+    if (!host) return ufail(u, FDC_E_ARG, "set_params: NULL");
+    for (long i = 0; i < u->n_params; ++i)
+        if (!std::isfinite(host[i])) return ufail(u, FDC_E_ARG, "set_params: non-finite value");
+    hipStream_t s = (hipStream_t)hip_stream;
+    hipError_t e = hipSetDevice(u->device);
+    if (!e) e = hipMemcpyAsync(u->params, host, u->n_params * 4, hipMemcpyHostToDevice, s);
+    if (!e) e = hipMemsetAsync(u->adam_m, 0, u->n_params * 4, s);
+    if (!e) e = hipMemsetAsync(u->adam_s, 0, u->n_params * 4, s);
+    if (!e) e = pack_all(u, s);
+    if (!e) e = hipStreamSynchronize(s);
+    if (e) return ufail(u, FDC_E_HIP, "set_params", e);
+    u->step = 0;
+    return FDC_OK;
+}
+
+static int copy_out(fdc_unet *u, const float *src, float *host, void *hip_stream, const char *what)
+{
+    if (!u) return FDC_E_ARG;
+    if (!host) return ufail(u, FDC_E_ARG, what);
+    hipStream_t s = (hipStream_t)hip_stream;
+    hipError_t e = hipSetDevice(u->device);
+    if (!e) e = hipMemcpyAsync(host, src, u->n_params * 4, hipMemcpyDeviceToHost, s);
+    if (!e) e = hipStreamSynchronize(s);
+    if (e) return ufail(u, FDC_E_HIP, what, e);
+    return FDC_OK;
+}
+
+int fdc_unet_get_params(fdc_unet *u, float *host, void *s) { return copy_out(u, u ? u->params : nullptr, host, s, "get_params"); }
+int fdc_unet_get_grads(fdc_unet *u, float *host, void *s) { return copy_out(u, u ? u->grads : nullptr, host, s, "get_grads"); }
+
+int fdc_unet_forward(fdc_unet *u, const float *in_dev, float *out_dev, void *hip_stream)
+{
+    if (!u) return FDC_E_ARG;
+    if (!in_dev || !out_dev) return ufail(u, FDC_E_ARG, "forward: NULL");
+    hipStream_t s = (hipStream_t)hip_stream;
+    hipError_t e = hipSetDevice(u->device);
+    if (!e) e = forward_pass(u, in_dev, s);
+    if (!e) e = head(u, in_dev, nullptr, out_dev, s);
+    if (e) return ufail(u, FDC_E_HIP, "forward", e);
+    return FDC_OK;
+}
+
+int fdc_unet_backward(fdc_unet *u, const float *in_dev, const float *target_dev, float *out_dev, double *loss_host,
+                      void *hip_stream)
+{
+    if (!u) return FDC_E_ARG;
+    if (!in_dev || !target_dev) return ufail(u, FDC_E_ARG, "backward: NULL");
+    hipStream_t s = (hipStream_t)hip_stream;
+    hipError_t e = hipSetDevice(u->device);
+    if (!e) e = forward_pass(u, in_dev, s);
+    if (!e) e = head(u, in_dev, target_dev, out_dev, s);
+    if (!e) e = backward_pass(u, in_dev, s);
+    if (!e && loss_host) e = hipMemcpyAsync(loss_host, u->loss, 8, hipMemcpyDeviceToHost, s);
+    if (!e && loss_host) e = hipStreamSynchronize(s);
+    if (e) return ufail(u, FDC_E_HIP, "backward", e);
+    return FDC_OK;
+}
+
+int fdc_unet_debug_buffer(fdc_unet *u, int index, uint16_t *host_out, int64_t *n_voxels, int32_t *pitch,
+                          void *hip_stream)
+{
+    if (!u) return FDC_E_ARG;
+    u16 *const bufs[] = {u->x, u->e1a, u->c1, u->p1, u->e2a, u->c2, u->p2, u->ma, u->m, u->d2a, u->d2, u->d1a, u->d1,
+                         u->gd1, u->gd1a, u->gc1, u->gd2, u->gd2a, u->gc2, u->gm, u->gma, u->gp2, u->ge2, u->ge2a,
+                         u->gp1, u->ge1, u->ge1a};
+    const int lvl[] = {0, 0, 0, 1, 1, 1, 2, 2, 2, 1, 1, 0, 0, 0, 0, 0, 1, 1, 1, 2, 2, 2, 1, 1, 1, 0, 0};
+    const int pit[] = {8, 16, 32, 16, 32, 64, 32, 64, 64, 32, 32, 16, 16, 16, 16, 32, 32, 32, 64, 64, 64, 32, 32, 32,
+                       16, 16, 16};
+    if (index < 0 || index >= (int)(sizeof(lvl) / sizeof(int))) return ufail(u, FDC_E_ARG, "debug_buffer: index");
+    const long n = u->nv[lvl[index]];
+    if (n_voxels) *n_voxels = n;
+    if (pitch) *pitch = pit[index];
+    if (!host_out) return FDC_OK;
+    hipStream_t s = (hipStream_t)hip_stream;
+    hipError_t e = hipSetDevice(u->device);
+    if (!e) e = hipMemcpyAsync(host_out, bufs[index], (size_t)n * pit[index] * 2, hipMemcpyDeviceToHost, s);
+    if (!e) e = hipStreamSynchronize(s);
+    if (e) return ufail(u, FDC_E_HIP, "debug_buffer", e);
+    return FDC_OK;
+}
+
+int fdc_unet_adam(fdc_unet *u, float lr, float beta1, float beta2, float eps, void *hip_stream)
+{
+    if (!u) return FDC_E_ARG;
+    if (!(lr > 0.f) || !(beta1 >= 0.f && beta1 < 1.f) || !(beta2 >= 0.f && beta2 < 1.f) || !(eps > 0.f))
+        return ufail(u, FDC_E_ARG, "adam: bad hyper-parameters");
+    hipStream_t s = (hipStream_t)hip_stream;
+    u->step++;
+    const float c1 = 1.f - std::pow(beta1, (float)u->step), c2 = 1.f - std::pow(beta2, (float)u->step);
+    hipError_t e = hipSetDevice(u->device);
+    if (!e) {
+        hipLaunchKernelGGL(adam_kernel, dim3(blocks_for(u->n_params)), dim3(256), 0, s, u->params, u->grads, u->adam_m,
+                           u->adam_s, u->n_params, lr, beta1, beta2, eps, c1, c2);
+        e = hipGetLastError();
+    }
+    if (!e) e = pack_all(u, s);
+    if (e) return ufail(u, FDC_E_HIP, "adam", e);
+    return FDC_OK;
+}
+
+} // extern "C"

@@ -32,7 +32,10 @@ EXPORTS = ["fdc_create", "fdc_destroy", "fdc_last_error", "fdc_set_allocator", "
            "fdc_reset_plan", "fdc_compute_dose", "fdc_read_dose_and_variance", "fdc_debug_endpoints",
            "fdc_debug_philox", "fdc_debug_material", "fdc_set_launch_config", "fdc_device_cus",
            "fdc_mean_uncertainty", "fdc_batch_uncertainty", "fdc_gamma_index",
-           "fdc_graph_create", "fdc_graph_launch", "fdc_graph_destroy"]
+           "fdc_graph_create", "fdc_graph_launch", "fdc_graph_destroy",
+           "fdc_unet_num_params", "fdc_unet_create", "fdc_unet_destroy", "fdc_unet_last_error",
+           "fdc_unet_set_params", "fdc_unet_get_params", "fdc_unet_get_grads", "fdc_unet_forward",
+           "fdc_unet_backward", "fdc_unet_adam", "fdc_unet_debug_buffer"]
 FDC_GRAPH_RESET_TALLIES = 1
 FDC_GRAPH_DOSE = 2
 
@@ -95,6 +98,17 @@ def lib():
         "fdc_graph_create": (C.c_int, [_P, _P, C.c_uint32, C.c_uint32, C.c_uint32, _P, _P, C.POINTER(_P)]),
         "fdc_graph_launch": (C.c_int, [_P, _P]),
         "fdc_graph_destroy": (C.c_int, [_P]),
+        "fdc_unet_num_params": (C.c_int64, []),
+        "fdc_unet_create": (C.c_int, [C.POINTER(_P), C.c_int, C.c_int, C.c_int, C.c_int]),
+        "fdc_unet_destroy": (C.c_int, [_P]),
+        "fdc_unet_last_error": (C.c_char_p, [_P]),
+        "fdc_unet_set_params": (C.c_int, [_P, _P, _P]),
+        "fdc_unet_get_params": (C.c_int, [_P, _P, _P]),
+        "fdc_unet_get_grads": (C.c_int, [_P, _P, _P]),
+        "fdc_unet_forward": (C.c_int, [_P, _P, _P, _P]),
+        "fdc_unet_backward": (C.c_int, [_P, _P, _P, _P, C.POINTER(C.c_double), _P]),
+        "fdc_unet_adam": (C.c_int, [_P, C.c_float, C.c_float, C.c_float, C.c_float, _P]),
+        "fdc_unet_debug_buffer": (C.c_int, [_P, C.c_int, _P, C.POINTER(C.c_int64), C.POINTER(C.c_int32), _P]),
         "fdc_gamma_index": (C.c_int, [_P, C.c_int32, _P, _P, C.c_double, C.c_double, C.c_double, C.c_double,
                                       _P, C.POINTER(C.c_double), C.POINTER(C.c_uint64), _P]),
     }
@@ -344,3 +358,74 @@ class Context:
         n = C.c_int()
         _check(self.h, lib().fdc_device_cus(self.h, C.byref(n)))
         return n.value
+
+
+UNET_BUFFERS = ["x", "e1a", "c1", "p1", "e2a", "c2", "p2", "ma", "m", "d2a", "d2", "d1a", "d1",
+                "gd1", "gd1a", "gc1", "gd2", "gd2a", "gc2", "gm", "gma", "gp2", "ge2", "ge2a", "gp1", "ge1", "ge1a"]
+
+
+class UNet:
+    """The dose denoiser (fdc_unet_*): volumes of nz x ny x nx voxels."""
+
+    def __init__(self, shape_zyx, device=0):
+        nz, ny, nx = shape_zyx
+        h = _P()
+        rc = lib().fdc_unet_create(C.byref(h), device, nx, ny, nz)
+        if rc != FDC_OK:
+            raise FdcError(rc, f"fdc_unet_create({nx}, {ny}, {nz}) failed")
+        self.h, self.shape = h, (nz, ny, nx)
+        self.n_params = int(lib().fdc_unet_num_params())
+
+    def _check(self, rc):
+        if rc != FDC_OK:
+            m = lib().fdc_unet_last_error(self.h)
+            raise FdcError(rc, m.decode() if m else "")
+
+    def close(self):
+        if self.h:
+            lib().fdc_unet_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, flat, stream=None):
+        v = np.ascontiguousarray(flat, np.float32)
+        assert v.size == self.n_params
+        self._check(lib().fdc_unet_set_params(self.h, v.ctypes.data, _stream(stream)))
+
+    def get_params(self, stream=None):
+        v = np.empty(self.n_params, np.float32)
+        self._check(lib().fdc_unet_get_params(self.h, v.ctypes.data, _stream(stream)))
+        return v
+
+    def get_grads(self, stream=None):
+        v = np.empty(self.n_params, np.float32)
+        self._check(lib().fdc_unet_get_grads(self.h, v.ctypes.data, _stream(stream)))
+        return v
+
+    def forward(self, inp, out, stream=None):
+        """inp: torch float32 [2, nz, ny, nx] on the device; out: [nz, ny, nx]."""
+        self._check(lib().fdc_unet_forward(self.h, _ptr(inp), _ptr(out), _stream(stream)))
+
+    def backward(self, inp, target, out=None, want_loss=True, stream=None):
+        loss = C.c_double()
+        self._check(lib().fdc_unet_backward(self.h, _ptr(inp), _ptr(target), _ptr(out),
+                                            C.byref(loss) if want_loss else None, _stream(stream)))
+        return loss.value if want_loss else None
+
+    def adam(self, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+        self._check(lib().fdc_unet_adam(self.h, lr, beta1, beta2, eps, _stream(stream)))
+
+    def debug_buffer(self, name, stream=None):
+        """Internal bf16 buffer as float32 [voxels, pitch] (channels-last)."""
+        i = UNET_BUFFERS.index(name)
+        n, pitch = C.c_int64(), C.c_int32()
+        self._check(lib().fdc_unet_debug_buffer(self.h, i, None, C.byref(n), C.byref(pitch), None))
+        raw = np.empty(n.value * pitch.value, np.uint16)
+        self._check(lib().fdc_unet_debug_buffer(self.h, i, raw.ctypes.data, C.byref(n), C.byref(pitch),
+                                                _stream(stream)))
+        return (raw.astype(np.uint32) << 16).view(np.float32).reshape(n.value, pitch.value)

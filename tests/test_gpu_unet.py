@@ -1,0 +1,115 @@
+"""The BF16-MFMA denoiser kernels (through the C ABI) against the FP64 oracle
+that rounds to bfloat16 at the same storage points.  Criteria: prediction and
+per-layer parameter gradients within 1e-2 (2e-2 for gradients) of the oracle's
+RMS; Adam exact to FP32 rounding; a single crop can be over-fitted."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from oracle import unet_ref as U  # noqa: E402
+from paper_1011_2188_amd import fdc as F  # noqa: E402
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.init()
+
+
+def _case(shape, seed):
+    rng = np.random.default_rng(seed)
+    P = U.init_params(seed)
+    for n in P:
+        P[n] = (P[n][0], 0.05 * rng.standard_normal(P[n][1].shape))
+    nz, ny, nx = shape
+    x = np.stack([rng.random(shape) * 2.0, 0.5 + rng.random(shape)])
+    t = x[0] + 0.1 * rng.standard_normal(shape)
+    return P, x, t
+
+
+def _rms(a):
+    return float(np.sqrt(np.mean(np.square(a))))
+
+
+def test_unet_parameter_count():
+    assert F.lib().fdc_unet_num_params() == U.n_params() == 339_681
+
+
+@pytest.mark.parametrize("shape", [(8, 8, 16), (16, 12, 8)])
+def test_unet_forward_matches_oracle(shape):
+    P, x, _ = _case(shape, 1)
+    net = F.UNet(shape)
+    flat = U.flatten(P).astype(np.float32)
+    net.set_params(flat)
+    xin = torch.tensor(x, dtype=torch.float32, device="cuda")
+    y = torch.empty(shape, dtype=torch.float32, device="cuda")
+    net.forward(xin, y)
+    torch.cuda.synchronize()
+    yo, cache = U.forward(U.unflatten(flat.astype(np.float64)), x.astype(np.float32).astype(np.float64), bf16=True)
+    # layer by layer (channels-last buffers vs channels-first oracle)
+    for name, key, ch in [("e1a", "e1a", 16), ("d1", "d1", 16), ("m", "m", 64)]:
+        g = net.debug_buffer(name)[:, :ch]
+        o = cache[key].reshape(ch, -1).T
+        assert _rms(g - o) <= 1e-2 * _rms(o), name
+    h_g = y.cpu().numpy() - x[0]
+    h_o = yo - x[0]
+    assert _rms(h_g - h_o) <= 1e-2 * _rms(h_o)
+
+
+def test_unet_gradients_match_oracle():
+    shape = (8, 8, 8)
+    P, x, t = _case(shape, 2)
+    net = F.UNet(shape)
+    flat = U.flatten(P).astype(np.float32)
+    net.set_params(flat)
+    xin = torch.tensor(x, dtype=torch.float32, device="cuda")
+    tt = torch.tensor(t, dtype=torch.float32, device="cuda")
+    loss = net.backward(xin, tt)
+    gg = net.get_grads()
+    lo, G, _ = U.loss_and_grad(U.unflatten(flat.astype(np.float64)), x.astype(np.float32).astype(np.float64),
+                               t.astype(np.float32).astype(np.float64), bf16=True)
+    assert abs(loss / lo - 1) < 1e-3
+    go = U.flatten(G)
+    off = 0
+    for name, kind, ci, co in U.LAYERS:
+        nw = int(np.prod(U.weight_shape(kind, ci, co)))
+        for a, b, what in [(off, off + nw, "w"), (off + nw, off + nw + co, "b")]:
+            assert _rms(gg[a:b] - go[a:b]) <= 2e-2 * _rms(go[a:b]) + 1e-12, (name, what)
+        off += nw + co
+
+
+def test_unet_adam_matches_oracle():
+    shape = (8, 8, 8)
+    P, x, t = _case(shape, 3)
+    net = F.UNet(shape)
+    flat = U.flatten(P).astype(np.float32)
+    net.set_params(flat)
+    xin = torch.tensor(x, dtype=torch.float32, device="cuda")
+    tt = torch.tensor(t, dtype=torch.float32, device="cuda")
+    v, m, s = flat.astype(np.float64), np.zeros(flat.size), np.zeros(flat.size)
+    for step in (1, 2):
+        net.backward(xin, tt, want_loss=False)
+        g = net.get_grads().astype(np.float64)
+        net.adam(1e-3)
+        v, m, s = U.adam(v, g, m, s, step, lr=1e-3)
+        got = net.get_params()
+        assert np.max(np.abs(got - v)) <= 1e-6 * max(1.0, np.max(np.abs(v)))
+
+
+def test_unet_overfits_one_crop():
+    shape = (16, 16, 16)
+    P, x, t = _case(shape, 4)
+    net = F.UNet(shape)
+    net.set_params(U.flatten(P).astype(np.float32))
+    xin = torch.tensor(x, dtype=torch.float32, device="cuda")
+    tt = torch.tensor(t, dtype=torch.float32, device="cuda")
+    first = net.backward(xin, tt)
+    net.adam(3e-3)
+    for _ in range(150):
+        net.backward(xin, tt, want_loss=False)
+        net.adam(3e-3)
+    last = net.backward(xin, tt)
+    assert last < 0.2 * first
