@@ -67,8 +67,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-variance", action="store_true", help="energy tally only")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--waves-per-block", type=int, default=4)
-    ap.add_argument("--blocks-per-cu", type=int, default=0)
+    ap.add_argument("--launch", default="tune",
+                    help="'tune' (autotune before the warm-up, untimed) or waves_per_block,blocks_per_cu,"
+                         "tally_slots,units_per_wave")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -95,13 +96,22 @@ def main():
     log(f"inputs generated in {time.perf_counter() - t:.1f} s: DB {db.steps.shape[0]} steps, "
         f"{db.n_tracks} tracks, {db.n_bins} bins")
     c = F.Context(device=0, seed=1, table=I.HU_TABLE_DEFAULT)
-    c.set_launch_config(args.waves_per_block, args.blocks_per_cu)
     t = time.perf_counter()
     c.load_track_db(db, stream)
     plan = c.load_phantom(ph, stream)
     c.add_beam_spots(plan, sp)
     torch.cuda.synchronize()
     log(f"loaded into HBM in {time.perf_counter() - t:.2f} s")
+    if args.launch == "tune":
+        from paper_1011_2188_amd import autotune as A
+        t = time.perf_counter()
+        launch, timings = A.tune(c, [plan], flags, reps=2, use_cache=False)
+        log(f"autotuned in {time.perf_counter() - t:.1f} s: {launch}")
+    else:
+        w, b, ts, u = (int(v) for v in args.launch.split(","))
+        launch = dict(waves_per_block=w, blocks_per_cu=b, tally_slots=ts, units_per_wave=u)
+        c.set_launch_config(**launch)
+    kernel = "transport_lds_kernel" if launch.get("tally_slots", 0) else "transport_kernel"
     nvox = ph.hu.size
     hist_per_step = int(sp["n_histories"].sum())
     dose = torch.empty(nvox, dtype=torch.float64, device=dev)
@@ -158,11 +168,10 @@ def main():
         "config": {"workload": "slab phantom 128^3 x 1 mm (bone z 4-6 cm, lung z 8-12 cm), 25 spots "
                                "70-230 MeV, 1e7 histories per step, DB 33 bins x 1e4 tracks, int64 "
                                "fixed-point tallies" + (" + squared-energy tally" if variance else ""),
-                   "histories_per_step": hist_per_step, "variance": variance,
-                   "waves_per_block": args.waves_per_block, "blocks_per_cu": args.blocks_per_cu},
+                   "histories_per_step": hist_per_step, "variance": variance, "launch": launch},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "transport_kernel", "kernel_ms": kern_ms,
+                     "kernel": kernel, "kernel_ms": kern_ms,
                      "bytes_per_history": bph, "tally_atomics_per_s": atomics},
         **out,
     }

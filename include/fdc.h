@@ -295,6 +295,16 @@ int fdc_gamma_index(fdc_ctx *ctx, int32_t plan, const double *ref_dev, const dou
                     double dta_cm, double cutoff_frac, double search_cm, float *gamma_dev, double *pass_rate_out,
                     uint64_t *n_eval_out, void *hip_stream);
 
+/* Mass density (g/cm^3) of every voxel of a plan from its HU (Section 2.5)
+ * into a DEVICE float array of nx*ny*nz.  Asynchronous.  Errors: FDC_E_ARG,
+ * FDC_E_STATE (no device), FDC_E_HIP. */
+int fdc_density(fdc_ctx *ctx, int32_t plan, float *rho_dev, void *hip_stream);
+
+/* Denoiser input of a plan (DEVICE arrays): out[0][v] = dose[v] * scale
+ * (scale = 1/Dmax of that dose), out[1][v] = rho[v] / 2.  Asynchronous. */
+int fdc_denoise_input(fdc_ctx *ctx, int32_t plan, const double *dose_dev, const float *rho_dev, double scale,
+                      float *out_dev, void *hip_stream);
+
 /* Number of compute units of the context's device (for launch sizing). */
 int fdc_device_cus(fdc_ctx *ctx, int *cus);
 
@@ -325,6 +335,9 @@ const char *fdc_unet_last_error(const fdc_unet *u);
 /* Copy the flat parameter vector in (host, FP32), clear the Adam moments and
  * pack the bf16 operands.  Synchronises hip_stream.  FDC_E_ARG on NULL/NaN. */
 int fdc_unet_set_params(fdc_unet *u, const float *host_params, void *hip_stream);
+/* He-normal initialisation (std sqrt(2 / fan_in); the head x 0.1; biases 0)
+ * from a seeded host generator, then as fdc_unet_set_params. */
+int fdc_unet_init_params(fdc_unet *u, uint64_t seed, void *hip_stream);
 /* Copy the parameters / the gradients of the last fdc_unet_backward out to
  * host arrays of fdc_unet_num_params() floats.  Synchronise hip_stream. */
 int fdc_unet_get_params(fdc_unet *u, float *host_params, void *hip_stream);

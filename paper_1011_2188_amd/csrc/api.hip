@@ -1138,6 +1138,31 @@ int fdc_gamma_index(fdc_ctx *ctx, int32_t plan, const double *ref_dev, const dou
     return FDC_OK;
 }
 
+int fdc_density(fdc_ctx *ctx, int32_t plan, float *rho_dev, void *hip_stream)
+{
+    if (!ctx) return FDC_E_ARG;
+    if (!valid_plan(ctx, plan)) return fail(ctx, FDC_E_ARG, "density: no plan %d", plan);
+    if (!rho_dev) return fail(ctx, FDC_E_ARG, "density: NULL output");
+    if (ctx->dry) return fail(ctx, FDC_E_STATE, "density: context has no device");
+    HIPCHK(hipSetDevice(ctx->device));
+    const PlanHost &P = ctx->plans[plan];
+    HIPCHK(launch_density(P.idx, ctx->rho_lut, P.nvox, rho_dev, S(hip_stream)));
+    return FDC_OK;
+}
+
+int fdc_denoise_input(fdc_ctx *ctx, int32_t plan, const double *dose_dev, const float *rho_dev, double scale,
+                      float *out_dev, void *hip_stream)
+{
+    if (!ctx) return FDC_E_ARG;
+    if (!valid_plan(ctx, plan)) return fail(ctx, FDC_E_ARG, "denoise input: no plan %d", plan);
+    if (!dose_dev || !rho_dev || !out_dev || !std::isfinite(scale))
+        return fail(ctx, FDC_E_ARG, "denoise input: NULL argument or bad scale");
+    if (ctx->dry) return fail(ctx, FDC_E_STATE, "denoise input: context has no device");
+    HIPCHK(hipSetDevice(ctx->device));
+    HIPCHK(launch_denoise_input(dose_dev, rho_dev, ctx->plans[plan].nvox, scale, out_dev, S(hip_stream)));
+    return FDC_OK;
+}
+
 int fdc_device_cus(fdc_ctx *ctx, int *cus)
 {
     if (!ctx || !cus) return FDC_E_ARG;

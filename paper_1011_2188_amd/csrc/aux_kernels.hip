@@ -95,6 +95,24 @@ __global__ void fill_u64_kernel(unsigned long long *__restrict__ p, size_t n, un
         p[i] = value;
 }
 
+// density per voxel from the HU index (vacuum voxels report their table density)
+__global__ void density_kernel(const uint16_t *__restrict__ idx, const float *__restrict__ rho_lut, size_t n,
+                               float *__restrict__ rho)
+{
+    for (size_t v = blockIdx.x * (size_t)blockDim.x + threadIdx.x; v < n; v += (size_t)gridDim.x * blockDim.x)
+        rho[v] = rho_lut[idx[v]];
+}
+
+// denoiser input: channel 0 = dose * scale, channel 1 = density / 2
+__global__ void denoise_input_kernel(const double *__restrict__ dose, const float *__restrict__ rho, size_t n,
+                                     double scale, float *__restrict__ out)
+{
+    for (size_t v = blockIdx.x * (size_t)blockDim.x + threadIdx.x; v < n; v += (size_t)gridDim.x * blockDim.x) {
+        out[v] = (float)(dose[v] * scale);
+        out[n + v] = 0.5f * rho[v];
+    }
+}
+
 __global__ void sum_i64_kernel(const unsigned long long *__restrict__ x, size_t n, unsigned long long *out)
 {
     __shared__ unsigned long long part[16];
@@ -167,6 +185,19 @@ hipError_t launch_advance(const WorkItem *items, uint32_t n_items, unsigned long
 hipError_t launch_fill_u64(unsigned long long *p, size_t n, unsigned long long value, hipStream_t s)
 {
     hipLaunchKernelGGL(fill_u64_kernel, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, p, n, value);
+    return hipGetLastError();
+}
+
+hipError_t launch_density(const uint16_t *idx, const float *rho_lut, size_t n, float *rho, hipStream_t s)
+{
+    hipLaunchKernelGGL(density_kernel, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, idx, rho_lut, n, rho);
+    return hipGetLastError();
+}
+
+hipError_t launch_denoise_input(const double *dose, const float *rho, size_t n, double scale, float *out,
+                                hipStream_t s)
+{
+    hipLaunchKernelGGL(denoise_input_kernel, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, dose, rho, n, scale, out);
     return hipGetLastError();
 }
 

@@ -139,6 +139,9 @@ hipError_t launch_dose(const uint16_t *idx, const unsigned long long *E, const u
 hipError_t launch_advance(const WorkItem *items, uint32_t n_items, unsigned long long *hnext, const DevSpot *spots,
                           const DevPlan *plans, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long *p, size_t n, unsigned long long value, hipStream_t s);
+hipError_t launch_density(const uint16_t *idx, const float *rho_lut, size_t n, float *rho, hipStream_t s);
+hipError_t launch_denoise_input(const double *dose, const float *rho, size_t n, double scale, float *out,
+                                hipStream_t s);
 hipError_t launch_sum_i64(const unsigned long long *x, size_t n, unsigned long long *out, hipStream_t s);
 hipError_t launch_dmax(const double *d, const uint16_t *idx, const float2 *lut, size_t n, double *part,
                        double *out3, hipStream_t s);

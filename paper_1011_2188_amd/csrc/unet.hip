@@ -24,6 +24,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <random>
 #include <cstring>
 #include <new>
 #include <string>
@@ -918,6 +919,21 @@ int fdc_unet_set_params(fdc_unet *u, const float *host, void *hip_stream)
     if (e) return ufail(u, FDC_E_HIP, "set_params", e);
     u->step = 0;
     return FDC_OK;
+}
+
+int fdc_unet_init_params(fdc_unet *u, uint64_t seed, void *hip_stream)
+{
+    if (!u) return FDC_E_ARG;
+    std::vector<float> v(u->n_params, 0.f);
+    std::mt19937_64 gen(seed);
+    std::normal_distribution<double> nd(0.0, 1.0);
+    for (int l = 0; l < kNumLayers; ++l) {
+        const LayerDesc &L = kLayers[l];
+        const int taps = L.kind == K_CONV3 ? 27 : L.kind == K_TCONV ? 8 : 1;
+        const double sd = std::sqrt(2.0 / (double)(L.cin * taps)) * (l == L_HEAD ? 0.1 : 1.0);
+        for (long i = 0; i < weight_count(L); ++i) v[u->w_off[l] + i] = (float)(sd * nd(gen));
+    }
+    return fdc_unet_set_params(u, v.data(), hip_stream);
 }
 
 static int copy_out(fdc_unet *u, const float *src, float *host, void *hip_stream, const char *what)

@@ -1,0 +1,175 @@
+"""Measurements beyond the benchmark's main line (run on one GPU):
+
+  thorax_rate       histories/s on the 1e8-history synthetic thorax plan;
+  batched           64 thorax-like plans in ONE captured graph launch vs 64
+                    separate eager runs (same histories, same tallies);
+  denoiser_study    seconds to 2% mean uncertainty, plain vs denoised at equal
+                    gamma pass rate (2%/2 mm) against an independent reference.
+"""
+from __future__ import annotations
+
+import math
+import time
+
+import numpy as np
+
+from . import autotune as A
+from . import denoise as D
+from . import fdc as F
+from . import inputs as I
+from . import workloads as W
+
+
+def _sync():
+    import torch
+    torch.cuda.synchronize()
+
+
+def thorax_rate(db, reps=2, tune=True, log=print):
+    import torch
+    ph, sp, _ = W.thorax()
+    c = F.Context(0, 1, table=I.HU_TABLE_DEFAULT)
+    c.load_track_db(db)
+    p = c.load_phantom(ph)
+    c.add_beam_spots(p, sp)
+    cfg = A.tune(c, [p], F.FDC_RUN_VARIANCE, reps=1, log=None)[0] if tune else {}
+    n = int(sp["n_histories"].sum())
+    d = torch.empty(ph.hu.size, dtype=torch.float64, device="cuda")
+    v = torch.empty(ph.hu.size, dtype=torch.float64, device="cuda")
+    best = math.inf
+    for _ in range(reps):
+        c.reset_plan(p)
+        _sync()
+        t = time.perf_counter()
+        c.run_histories([p], F.FDC_RUN_VARIANCE)
+        c.compute_dose(p, d, v)
+        _sync()
+        best = min(best, time.perf_counter() - t)
+    u, _, _ = c.mean_uncertainty(p, d, v, 0.5)
+    n2 = n * (u / 0.02) ** 2
+    out = {"histories": n, "seconds": best, "histories_per_s": n / best, "launch": cfg,
+           "mean_uncertainty": u, "seconds_to_2pct": n2 / (n / best)}
+    log(f"thorax: {out}")
+    c.close()
+    return out
+
+
+def batched(db, log=print, hist_scale=1.0):
+    """64 plans: one graph launch (all plans, tallies cleared, dose computed)
+    against 64 separate eager runs of the same plans in a second context."""
+    import torch
+    plans = W.batched_plans(64, hist_scale=hist_scale)
+    ctxs = []
+    for k in range(2):
+        c = F.Context(0, 1, table=I.HU_TABLE_DEFAULT)
+        c.load_track_db(db)
+        ids = []
+        for ph, sp in plans:
+            p = c.load_phantom(ph)
+            c.add_beam_spots(p, sp)
+            ids.append(p)
+        ctxs.append((c, ids))
+    (cg, ids), (ce, ide) = ctxs
+    cfg, _ = A.tune(cg, ids, F.FDC_RUN_VARIANCE, reps=1)
+    ce.set_launch_config(**cfg)
+    doses = [torch.empty(ph.hu.size, dtype=torch.float64, device="cuda") for ph, _ in plans]
+    vars_ = [torch.empty(ph.hu.size, dtype=torch.float64, device="cuda") for ph, _ in plans]
+    g = cg.graph_create(ids, F.FDC_RUN_VARIANCE, reset=True, doses=doses, variances=vars_)
+    n_hist = sum(int(sp["n_histories"].sum()) for _, sp in plans)
+    g.launch()
+    _sync()
+    t = time.perf_counter()
+    g.launch()
+    _sync()
+    t_graph = time.perf_counter() - t
+    for p in ide:                                  # warm-up pass, then the timed one
+        ce.run_histories([p], F.FDC_RUN_VARIANCE)
+    _sync()
+    for p in ide:
+        ce.reset_plan(p)
+    _sync()
+    t = time.perf_counter()
+    for p, d, v in zip(ide, doses, vars_):
+        ce.run_histories([p], F.FDC_RUN_VARIANCE)
+        ce.compute_dose(p, d, v)
+    _sync()
+    t_sep = time.perf_counter() - t
+    # same histories on both sides (second pass of each context): tallies equal
+    same = all(np.array_equal(cg.read_dose_and_variance(a, dose=False, var=False, raw=True)["E"],
+                              ce.read_dose_and_variance(b, dose=False, var=False, raw=True)["E"])
+               for a, b in zip(ids[:4], ide[:4]))
+    out = {"plans": len(plans), "histories": n_hist, "graph_seconds": t_graph, "separate_seconds": t_sep,
+           "graph_histories_per_s": n_hist / t_graph, "separate_histories_per_s": n_hist / t_sep,
+           "launch": cfg, "first_plans_bitwise_equal": bool(same)}
+    log(f"batched: {out}")
+    g.close()
+    cg.close()
+    ce.close()
+    return out
+
+
+def denoiser_study(db, n_train=48, n_test=6, shape=(128, 128, 64), voxel_cm=0.4, per_pass=100_000,
+                   high_passes=60, crop=(32, 64, 64), steps=3000, lr=1e-3, log=print):
+    """Plain vs denoised seconds to 2% at equal gamma pass rate.
+
+    Plain: N_2% from the Eq. (2) mean uncertainty of one pass; its gamma pass
+    rate G* (2%/2 mm) against an independent reference of `high_passes`
+    passes.  Denoised: the smallest N_d among N_2% * {1/64, ..., 1} whose
+    denoised dose reaches G*; t = N / rate (+ inference time)."""
+    import torch
+    sim = D.Simulator(db, seed=7)
+    plans = []
+    for k in range(n_train + n_test):
+        ph, sp = D.denoise_plan(10_000 + k if k < n_train else 20_000 + k, shape, voxel_cm)
+        plans.append(sim.add(ph, sp, per_pass))
+    t = time.perf_counter()
+    pairs = D.make_pairs(sim, plans[:n_train], high_passes)
+    _sync()
+    t_pairs = time.perf_counter() - t
+    log(f"pairs: {n_train} plans x {(1 + high_passes) * per_pass:.3g} histories in {t_pairs:.1f} s")
+    net, losses, t_train = D.train(pairs, crop, steps, lr, seed=0, log=log, log_every=500)
+    params = net.get_params()
+    net.close()
+    rate = n_train * (1 + high_passes) * per_pass / t_pairs
+    rows = []
+    for p in plans[n_train:]:
+        d1, v1 = sim.dose(p, 1, variance=True)
+        u1, _, _ = sim.ctx.mean_uncertainty(p, d1, v1, 0.5)
+        n2 = per_pass * (u1 / 0.02) ** 2                       # histories to 2%
+        passes_2 = max(1, int(round(n2 / per_pass)))
+        rho = sim.density(p)
+        ref, _ = sim.dose(p, 4 * passes_2 + high_passes)
+        plain, _ = sim.dose(p, passes_2)
+        x, dmax = sim.net_input(p, plain, rho)
+        r = sim.scaled(p, ref, rho, dmax)
+        g_star = sim.ctx.gamma_index(p, r.reshape(-1).double(), x[0].reshape(-1).double())[0]
+        best = None
+        for frac in (1 / 64, 1 / 32, 1 / 16, 1 / 8, 1 / 4, 1 / 2, 1):
+            k = max(1, int(round(passes_2 * frac)))
+            low, _ = sim.dose(p, k)
+            xl, dl = sim.net_input(p, low, rho)
+            _sync()
+            ti = time.perf_counter()
+            den = D.infer(params, xl)
+            _sync()
+            t_inf = time.perf_counter() - ti
+            rl = sim.scaled(p, ref, rho, dl)
+            g = sim.ctx.gamma_index(p, rl.reshape(-1).double(), den.reshape(-1).double())[0]
+            if g >= g_star:
+                best = (k * per_pass, g, t_inf)
+                break
+        row = {"plan": int(p), "u_one_pass": u1, "N_2pct": n2, "G_star": g_star,
+               "t_plain_s": passes_2 * per_pass / rate,
+               "N_denoised": best[0] if best else None, "G_denoised": best[1] if best else None,
+               "t_denoised_s": (best[0] / rate + best[2]) if best else None}
+        log(f"denoise eval: {row}")
+        rows.append(row)
+    ok = [r for r in rows if r["t_denoised_s"] is not None]
+    out = {"train_plans": n_train, "test_plans": n_test, "shape_xyz": shape, "voxel_cm": voxel_cm,
+           "train_steps": steps, "crop_zyx": crop, "train_seconds": t_train, "pair_seconds": t_pairs,
+           "rate_histories_per_s": rate, "final_loss": losses[-1][1],
+           "t_plain_mean_s": float(np.mean([r["t_plain_s"] for r in rows])),
+           "t_denoised_mean_s": float(np.mean([r["t_denoised_s"] for r in ok])) if ok else None,
+           "reached": len(ok), "rows": rows}
+    log(f"denoiser study: {out}")
+    return out

@@ -35,7 +35,8 @@ EXPORTS = ["fdc_create", "fdc_destroy", "fdc_last_error", "fdc_set_allocator", "
            "fdc_graph_create", "fdc_graph_launch", "fdc_graph_destroy",
            "fdc_unet_num_params", "fdc_unet_create", "fdc_unet_destroy", "fdc_unet_last_error",
            "fdc_unet_set_params", "fdc_unet_get_params", "fdc_unet_get_grads", "fdc_unet_forward",
-           "fdc_unet_backward", "fdc_unet_adam", "fdc_unet_debug_buffer"]
+           "fdc_unet_backward", "fdc_unet_adam", "fdc_unet_debug_buffer", "fdc_density", "fdc_denoise_input",
+           "fdc_unet_init_params"]
 FDC_GRAPH_RESET_TALLIES = 1
 FDC_GRAPH_DOSE = 2
 
@@ -98,11 +99,14 @@ def lib():
         "fdc_graph_create": (C.c_int, [_P, _P, C.c_uint32, C.c_uint32, C.c_uint32, _P, _P, C.POINTER(_P)]),
         "fdc_graph_launch": (C.c_int, [_P, _P]),
         "fdc_graph_destroy": (C.c_int, [_P]),
+        "fdc_density": (C.c_int, [_P, C.c_int32, _P, _P]),
+        "fdc_denoise_input": (C.c_int, [_P, C.c_int32, _P, _P, C.c_double, _P, _P]),
         "fdc_unet_num_params": (C.c_int64, []),
         "fdc_unet_create": (C.c_int, [C.POINTER(_P), C.c_int, C.c_int, C.c_int, C.c_int]),
         "fdc_unet_destroy": (C.c_int, [_P]),
         "fdc_unet_last_error": (C.c_char_p, [_P]),
         "fdc_unet_set_params": (C.c_int, [_P, _P, _P]),
+        "fdc_unet_init_params": (C.c_int, [_P, C.c_uint64, _P]),
         "fdc_unet_get_params": (C.c_int, [_P, _P, _P]),
         "fdc_unet_get_grads": (C.c_int, [_P, _P, _P]),
         "fdc_unet_forward": (C.c_int, [_P, _P, _P, _P]),
@@ -124,8 +128,12 @@ def _ptr(a):
     if a is None:
         return None
     if isinstance(a, np.ndarray):
+        if not a.flags.c_contiguous:
+            raise ValueError("array arguments must be C-contiguous")
         return a.ctypes.data
-    return a.data_ptr()      # torch tensor
+    if not a.is_contiguous():   # torch tensor
+        raise ValueError("tensor arguments must be contiguous")
+    return a.data_ptr()
 
 
 def _stream(stream):
@@ -335,6 +343,13 @@ class Context:
         self._graphs.append(gr)
         return gr
 
+    def density(self, plan, rho, stream=None):
+        _check(self.h, lib().fdc_density(self.h, plan, _ptr(rho), _stream(stream)))
+
+    def denoise_input(self, plan, dose, rho, scale, out, stream=None):
+        _check(self.h, lib().fdc_denoise_input(self.h, plan, _ptr(dose), _ptr(rho), float(scale), _ptr(out),
+                                               _stream(stream)))
+
     # -- metrics (device arrays in, host scalars out)
     def mean_uncertainty(self, plan, dose, var, frac=0.5, stream=None):
         m, n, dmax = C.c_double(), C.c_uint64(), C.c_double()
@@ -396,6 +411,9 @@ class UNet:
         v = np.ascontiguousarray(flat, np.float32)
         assert v.size == self.n_params
         self._check(lib().fdc_unet_set_params(self.h, v.ctypes.data, _stream(stream)))
+
+    def init_params(self, seed, stream=None):
+        self._check(lib().fdc_unet_init_params(self.h, seed, _stream(stream)))
 
     def get_params(self, stream=None):
         v = np.empty(self.n_params, np.float32)

@@ -188,6 +188,32 @@ def test_launch_configs_bitwise():
         assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1]) and got[2] == ref[2], cfg
 
 
+def test_autotuner_candidates_bitwise_and_tuning_leaves_no_trace(tmp_path):
+    """Every configuration the autotuner may pick gives the same tallies, and a
+    tuned run (candidates timed on the real plan, then rewound) equals an
+    untuned one bitwise."""
+    from paper_1011_2188_amd import autotune as A
+    ph = I.thorax_phantom((72, 72, 48), 0.3, seed=12)
+    rng = np.random.default_rng(3)
+    sp = I.field_spots((2.0, -1.0, 0.0), 90.0, 30, rng, histories=np.full(30, 700, np.uint64))
+    db = W.multi_bin_db(2000)
+    ref = _tallies(db, ph, sp)
+    for cfg in A.CANDIDATES:
+        got = _tallies(db, ph, sp, **cfg)
+        assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1]) and got[2] == ref[2], cfg
+    c = ctx_for(db)
+    p = c.load_phantom(ph)
+    c.add_beam_spots(p, sp)
+    best, timings = A.tune(c, [p], F.FDC_RUN_VARIANCE, reps=1, cache_path=str(tmp_path / "tune.json"))
+    assert best in A.CANDIDATES and len(timings) == len(A.CANDIDATES)
+    c.run_histories([p], F.FDC_RUN_VARIANCE)
+    r = c.read_dose_and_variance(p, raw=True)
+    assert np.array_equal(r["E"], ref[0]) and np.array_equal(r["E2"], ref[1]) and r["escaped"] == ref[2]
+    assert r["n_histories"] == 30 * 700
+    again, _ = A.tune(c, [p], F.FDC_RUN_VARIANCE, cache_path=str(tmp_path / "tune.json"))   # cache hit
+    assert again == best
+
+
 @pytest.mark.parametrize("cfg", [{}, dict(waves_per_block=8, blocks_per_cu=1, tally_slots=2048, units_per_wave=2)])
 def test_split_runs_and_batching_bitwise(cfg):
     """run(n) twice == run(2n) (history counters continue, unaligned h0), and
