@@ -115,6 +115,29 @@ __host__ __device__ inline double u01(uint32_t x)
     return (double)(x >> 8) * 0x1p-24 + 0x1p-25;
 }
 
+// Global-memory views of device pointers.  The plan buffers are reached
+// through pointers stored in device memory, which the compiler would otherwise
+// access as generic (flat) pointers; a flat access also counts against the LDS
+// wait counter, so an LDS lookup issued after a flat tally atomic would stall
+// until that atomic completes.  (The qualifier applies to the device pass only;
+// the host pass sees plain pointers.)
+#if defined(__HIP_DEVICE_COMPILE__)
+#define FDC_AS_GLOBAL __attribute__((address_space(1)))
+#else
+#define FDC_AS_GLOBAL
+#endif
+
+__host__ __device__ inline uint16_t load_global(const uint16_t *p, uint32_t i)
+{
+    return ((const FDC_AS_GLOBAL uint16_t *)p)[i];
+}
+
+// relaxed device-scope 64-bit add without a return value
+__device__ inline void add_global(unsigned long long *p, unsigned long long v)
+{
+    __hip_atomic_fetch_add((FDC_AS_GLOBAL unsigned long long *)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // energy in MeV (float) -> fixed point; exact for every float input
 __host__ __device__ inline long long to_fp(float mev)
 {

@@ -56,10 +56,10 @@ struct GlobalSink {            // 64-bit device atomics straight into the plan's
     const DevPlan *pl;
     __device__ void add(uint32_t v, uint32_t, long long acc) const
     {
-        atomicAdd(pl->E + v, (unsigned long long)acc);
+        add_global(pl->E + v, (unsigned long long)acc);
         if (VAR) {
             const unsigned long long q = (unsigned long long)((acc + 2048) >> 12);
-            atomicAdd(pl->E2 + v, q * q);
+            add_global(pl->E2 + v, q * q);
         }
     }
 };
@@ -89,8 +89,8 @@ struct LdsSink {
     {
         const unsigned long long q = (unsigned long long)((acc + 2048) >> 12);
         if (pl != tab_pl) {                        // a round straddling two plans
-            atomicAdd(pl->E + v, (unsigned long long)acc);
-            if (VAR) atomicAdd(pl->E2 + v, q * q);
+            add_global(pl->E + v, (unsigned long long)acc);
+            if (VAR) add_global(pl->E2 + v, q * q);
             return;
         }
         uint32_t row = v - ix;                     // start of the x row
@@ -109,8 +109,8 @@ struct LdsSink {
             }
             s = (s + 1) & mask;
         }
-        atomicAdd(pl->E + v, (unsigned long long)acc);
-        if (VAR) atomicAdd(pl->E2 + v, q * q);
+        add_global(pl->E + v, (unsigned long long)acc);
+        if (VAR) add_global(pl->E2 + v, q * q);
     }
 };
 
@@ -203,11 +203,19 @@ __host__ __device__ void replay_history(const TransportArgs &a, const DevSpot &s
     set_direction_terms(L.d, pl.vox, sinv, dv);
 
     // ---- task 2: re-trace the steps -----------------------------------------
+    // Loads are issued one use ahead: the material of the voxel across the
+    // exit face (it depends on geometry only) before the current voxel's
+    // deposit is flushed, and the next step record one step ahead, so no wait
+    // for a load also waits for the tally atomics issued before it.
+    const uint16_t *__restrict__ vidx = pl.idx;
+    float2 m = lut[load_global(vidx, L.v)];
     long long acc = 0, hdep = 0;
     bool escaped = false;
     bool first_step = true;
+    float4 next_rec = a.steps[k];
     for (; k < kend; ++k) {
-        const float4 rec = a.steps[k];
+        const float4 rec = next_rec;
+        if (k + 1 < kend) next_rec = a.steps[k + 1];
         float w_tot = rec.x, th = rec.z, ph = rec.w;
         e = to_fp(rec.y);
         if (first_step) {                          // partial first step
@@ -224,7 +232,6 @@ __host__ __device__ void replay_history(const TransportArgs &a, const DevSpot &s
         float tau = 0.f, g2 = 0.f;
         long long dep = 0;
         while (tau < w_tot) {
-            const float2 m = lut[pl.idx[L.v]];
             // distance (cm) to the exit face along each axis; ties go x -> y -> z
             float tx = (L.d[0] > 0.f ? 1.f - L.f[0] : L.f[0]) * sinv[0];
             float ty = (L.d[1] > 0.f ? 1.f - L.f[1] : L.f[1]) * sinv[1];
@@ -236,6 +243,15 @@ __host__ __device__ void replay_history(const TransportArgs &a, const DevSpot &s
             int ax = 0;
             if (ty < tmin) { tmin = ty; ax = 1; }
             if (tz < tmin) { tmin = tz; ax = 2; }
+            // the voxel across that face, and its material index (prefetch)
+            const float d_ax = ax == 0 ? L.d[0] : (ax == 1 ? L.d[1] : L.d[2]);
+            const int i_ax = ax == 0 ? L.i[0] : (ax == 1 ? L.i[1] : L.i[2]);
+            const int n_ax = ax == 0 ? pl.n[0] : (ax == 1 ? pl.n[1] : pl.n[2]);
+            const uint32_t st_ax = ax == 0 ? stride[0] : (ax == 1 ? stride[1] : stride[2]);
+            const int ni = i_ax + (d_ax > 0.f ? 1 : -1);
+            const bool out = (unsigned)ni >= (unsigned)n_ax;
+            const uint32_t vn = d_ax > 0.f ? L.v + st_ax : L.v - st_ax;
+            const uint16_t idx_n = load_global(vidx, out ? L.v : vn);
             float move = tmin;
             bool cross = true;
             if (m.x != 0.f) {                      // material: consume WEL
@@ -267,26 +283,20 @@ __host__ __device__ void replay_history(const TransportArgs &a, const DevSpot &s
                     sink.add(L.v, (uint32_t)L.i[0], acc);
                     acc = 0;
                 }
-                bool out = false;
+                const float f_new = (d_ax > 0.f) == out ? 1.f : 0.f;   // exit face when out, else entry face
 #pragma unroll
                 for (int q = 0; q < 3; ++q) {
                     if (q == ax) {
-                        const int s = L.d[q] > 0.f ? 1 : -1;
-                        const int ni = L.i[q] + s;
-                        out = (unsigned)ni >= (unsigned)pl.n[q];
-                        if (out) {
-                            L.f[q] = s > 0 ? 1.f : 0.f;    // end point on the exit face
-                        } else {
-                            L.i[q] = ni;
-                            L.f[q] = s > 0 ? 0.f : 1.f;
-                            L.v += s > 0 ? stride[q] : (uint32_t)(-(int)stride[q]);
-                        }
+                        L.f[q] = f_new;
+                        if (!out) L.i[q] = ni;
                     }
                 }
                 if (out) {
                     escaped = true;
                     break;
                 }
+                L.v = vn;
+                m = lut[idx_n];
             }
         }
         if (escaped) break;
@@ -354,8 +364,8 @@ __device__ void process_unit(const TransportArgs &a, const float2 *lut, unsigned
         inc = wave_sum(inc);
         esc = wave_sum(esc);
         if (lane == 0) {
-            if (inc) atomicAdd(pl.acc + 0, (unsigned long long)inc);
-            if (esc) atomicAdd(pl.acc + 1, (unsigned long long)esc);
+            if (inc) add_global(pl.acc + 0, (unsigned long long)inc);
+            if (esc) add_global(pl.acc + 1, (unsigned long long)esc);
         }
     }
 }
@@ -457,10 +467,10 @@ __global__ void __launch_bounds__(1024) transport_lds_kernel(TransportArgs a, ui
             const uint32_t k = s_key[i];
             if (k != kEmpty) {
                 const unsigned long long ev = s_e[i];
-                if (ev) atomicAdd(pl->E + k, ev);
+                if (ev) add_global(pl->E + k, ev);
                 if (VAR) {
                     const unsigned long long e2v = s_e2[i];
-                    if (e2v) atomicAdd(pl->E2 + k, e2v);
+                    if (e2v) add_global(pl->E2 + k, e2v);
                     s_e2[i] = 0;
                 }
                 s_e[i] = 0;
