@@ -100,13 +100,20 @@ typedef struct {
     uint32_t waves_per_block;   /* 1..16, default 4                                    */
     uint32_t blocks_per_cu;     /* persistent grid size = blocks_per_cu * CUs; 0 = one
                                    block per work unit (non-persistent)                */
-    uint32_t tally_slots;       /* 0: flush visits with global atomics; else a power of
-                                   two 256..8192: per-workgroup LDS sub-tally with that
-                                   many slots (persistent rounds; blocks_per_cu 0 is
-                                   taken as 1)                                        */
+    uint32_t tally_slots;       /* 0: flush visits with global atomics; else the size of
+                                   a per-workgroup LDS sub-tally (persistent rounds;
+                                   blocks_per_cu 0 is taken as 1): with tally_mode 0 a
+                                   power of two 256..8192, with tally_mode 1 a multiple
+                                   of 64 from 256 up to what fits                       */
     uint32_t units_per_wave;    /* with tally_slots: 64-history units per wave per
                                    round, 1..64 (0 is taken as 1)                      */
-    uint32_t reserved[4];
+    uint32_t tally_mode;        /* with tally_slots: 0 = hash table (voxel key, E, E2;
+                                   12 or 20 B per slot) whose visits fall back to global
+                                   atomics once 8 probes find no room; 1 = write-back
+                                   cache of one 64-bit word (voxel | partial sum) per
+                                   slot and tally (8 or 16 B per slot), a conflicting
+                                   voxel evicting the old sum with one global atomic    */
+    uint32_t reserved[3];
 } fdc_launch_config;
 
 typedef void *(*fdc_alloc_fn)(size_t bytes, void *user);
@@ -257,8 +264,9 @@ int fdc_debug_material(fdc_ctx *ctx, float *rsp_out, float *g_out, float *rho_ou
 
 /* Launch knobs for fdc_run_histories (see fdc_launch_config).  Results are
  * bitwise identical for every valid setting.  Errors: FDC_E_ARG (out of range,
- * or an LDS sub-tally that does not fit next to the 32 KB material table:
- * 12 B per slot, 20 B with the squared-energy tally, at most 160 KB in all). */
+ * or an LDS sub-tally that does not fit next to the 32 KB material table in
+ * 160 KB; with the squared-energy tally the size is checked again at run
+ * time). */
 int fdc_set_launch_config(fdc_ctx *ctx, const fdc_launch_config *cfg);
 
 /* Mean dose uncertainty (Section 2.4): the mean of sqrt(var)/dose over the

@@ -1,7 +1,7 @@
 """Autotuner for the launch knobs of fdc_run_histories.
 
 Only knobs that cannot change a result bit are searched: waves per workgroup,
-persistent grid size, the LDS sub-tally size and units per wave per round
+persistent grid size, the LDS sub-tally's kind and size, and units per wave per round
 (integer tallies make every setting bitwise identical; the GPU tests check
 it).  Each candidate is timed on the caller's real plans; the plans are then
 rewound (tallies cleared, history counters back to 0), so tuning leaves no
@@ -23,6 +23,8 @@ CANDIDATES = (
     + [dict(waves_per_block=16, blocks_per_cu=1, tally_slots=4096, units_per_wave=u) for u in (1, 2, 4)]
     + [dict(waves_per_block=8, blocks_per_cu=2, tally_slots=2048, units_per_wave=u) for u in (1, 2, 4)]
     + [dict(waves_per_block=4, blocks_per_cu=4, tally_slots=1024, units_per_wave=u) for u in (2, 4)]
+    + [dict(waves_per_block=16, blocks_per_cu=1, tally_slots=8128, units_per_wave=u, tally_mode=1) for u in (1, 2, 4, 8)]
+    + [dict(waves_per_block=8, blocks_per_cu=2, tally_slots=3008, units_per_wave=u, tally_mode=1) for u in (2, 4)]
 )
 
 

@@ -692,7 +692,8 @@ static int enqueue_transport(fdc_ctx *ctx, TransportArgs a, uint32_t flags, hipS
     const uint32_t wpb = ctx->cfg.waves_per_block;
     const bool variance = (flags & FDC_RUN_VARIANCE) != 0;
     if (ctx->cfg.tally_slots &&
-        kLutSize * sizeof(float2) + 64 + lds_tally_bytes(ctx->cfg.tally_slots, variance) > kMaxLdsBytes)
+        kLutSize * sizeof(float2) + 64 + lds_tally_bytes(ctx->cfg.tally_slots, variance, ctx->cfg.tally_mode) >
+            kMaxLdsBytes)
         return fail(ctx, FDC_E_ARG, "run: LDS sub-tally of %u slots with the squared-energy tally does not fit",
                     ctx->cfg.tally_slots);
     const bool persistent = ctx->cfg.tally_slots || ctx->cfg.blocks_per_cu;
@@ -707,7 +708,7 @@ static int enqueue_transport(fdc_ctx *ctx, TransportArgs a, uint32_t flags, hipS
     if (ctx->cfg.tally_slots) {
         const uint32_t grid = std::max<uint32_t>(1, ctx->cfg.blocks_per_cu) * (uint32_t)ctx->cus;
         HIPCHK(launch_transport_lds(a, wpb, grid, ctx->cfg.tally_slots, std::max<uint32_t>(1, ctx->cfg.units_per_wave),
-                                    variance, s));
+                                    variance, ctx->cfg.tally_mode, s));
     } else if (ctx->cfg.blocks_per_cu) {
         HIPCHK(launch_transport(a, wpb, ctx->cfg.blocks_per_cu * (uint32_t)ctx->cus, variance, false, s));
     } else {
@@ -1030,11 +1031,14 @@ int fdc_set_launch_config(fdc_ctx *ctx, const fdc_launch_config *cfg)
     if (cfg->waves_per_block < 1 || cfg->waves_per_block > 16)
         return fail(ctx, FDC_E_ARG, "launch config: waves_per_block must be 1..16");
     if (cfg->blocks_per_cu > 64) return fail(ctx, FDC_E_ARG, "launch config: blocks_per_cu must be 0..64");
+    if (cfg->tally_mode > 1) return fail(ctx, FDC_E_ARG, "launch config: tally_mode must be 0 or 1");
     if (cfg->tally_slots) {
         const uint32_t t = cfg->tally_slots;
-        if (t < 256 || t > 8192 || (t & (t - 1)))
+        if (cfg->tally_mode == 0 && (t < 256 || t > 8192 || (t & (t - 1))))
             return fail(ctx, FDC_E_ARG, "launch config: tally_slots must be 0 or a power of two 256..8192");
-        if (kLutSize * sizeof(float2) + 64 + lds_tally_bytes(t, false) > kMaxLdsBytes)
+        if (cfg->tally_mode == 1 && (t < 256 || t % 64))
+            return fail(ctx, FDC_E_ARG, "launch config: tally_slots must be 0 or a multiple of 64 from 256");
+        if (kLutSize * sizeof(float2) + 64 + lds_tally_bytes(t, false, cfg->tally_mode) > kMaxLdsBytes)
             return fail(ctx, FDC_E_ARG, "launch config: LDS sub-tally of %u slots does not fit", t);
     }
     if (cfg->units_per_wave > 64) return fail(ctx, FDC_E_ARG, "launch config: units_per_wave must be 0..64");

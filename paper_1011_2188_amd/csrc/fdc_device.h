@@ -148,8 +148,8 @@ __host__ __device__ inline long long to_fp(float mev)
 hipError_t launch_transport(const TransportArgs &a, uint32_t waves_per_block, uint32_t grid_blocks,
                             bool variance, bool endpoints, hipStream_t s);
 hipError_t launch_transport_lds(const TransportArgs &a, uint32_t waves_per_block, uint32_t grid_blocks,
-                                uint32_t slots, uint32_t units_per_wave, bool variance, hipStream_t s);
-size_t lds_tally_bytes(uint32_t slots, bool variance);
+                                uint32_t slots, uint32_t units_per_wave, bool variance, uint32_t mode, hipStream_t s);
+size_t lds_tally_bytes(uint32_t slots, bool variance, uint32_t mode);
 hipError_t prepare_lds_kernels();
 hipError_t launch_build_lut(const double *pts, int n_pts, double vacuum_below, float2 *lut, float *rho,
                             hipStream_t s);

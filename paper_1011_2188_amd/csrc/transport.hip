@@ -114,6 +114,73 @@ struct LdsSink {
     }
 };
 
+// Slot of a voxel in an LDS table of n slots: a hash of the voxel's x row
+// plus its x index, so voxels consecutive in x take consecutive slots (the
+// flush of a table then partly coalesces).
+__device__ inline uint32_t row_slot(uint32_t v, uint32_t ix, uint32_t n)
+{
+    uint32_t row = v - ix;
+    row ^= row >> 15;
+    row *= 0x2c1b3c6du;
+    row ^= row >> 12;
+    uint32_t s = (uint32_t)(((unsigned long long)row * n) >> 32) + ix;
+    return s < n ? s : s % n;
+}
+
+// Per-workgroup write-back cache of the tallies in LDS.  A slot is one 64-bit
+// word per tally: (voxel + 1) in the top 64 - vbits bits, a partial sum in the
+// low vbits bits, 0 = empty.  Every update is a single compare-and-swap: a hit
+// adds to the sum, a miss installs the new voxel and sends the evicted sum to
+// the plan's tally with one global atomic.  The sums stay exact integers (a
+// sum that would overflow its field goes to the global tally instead), so the
+// result is the same as with global atomics alone.  The cache holds voxels of
+// one plan per round; other plans' visits go straight to the global atomics.
+template <bool VAR>
+struct CacheSink {
+    const DevPlan *pl;          // plan of the unit being replayed
+    const DevPlan *tab_pl;      // plan whose voxels the cache holds this round
+    unsigned long long *ce, *ce2;
+    uint32_t n;                 // slots
+    uint32_t vbits;             // value bits of a word
+
+    __device__ static void put(unsigned long long *c, unsigned long long *g, uint32_t s, uint32_t v,
+                               unsigned long long val, uint32_t vbits)
+    {
+        const unsigned long long vmax = (1ull << vbits) - 1;
+        const unsigned long long key = (unsigned long long)(v + 1) << vbits;
+        if (val <= vmax) {
+            unsigned long long w = c[s];
+#pragma unroll 1
+            for (int tries = 0; tries < 16; ++tries) {
+                const bool hit = (w & ~vmax) == key;
+                if (hit && val > vmax - (w & vmax)) break;        // the sum would overflow
+                const unsigned long long nw = hit ? w + val : (key | val);
+                const unsigned long long old = atomicCAS(c + s, w, nw);
+                if (old == w) {
+                    if (!hit && w != 0) add_global(g + ((w >> vbits) - 1), w & vmax);
+                    return;
+                }
+                w = old;
+            }
+        }
+        add_global(g + v, val);
+    }
+
+    __device__ void add(uint32_t v, uint32_t ix, long long acc) const
+    {
+        const unsigned long long q = (unsigned long long)((acc + 2048) >> 12);
+        if (pl != tab_pl) {                        // a round straddling two plans
+            add_global(pl->E + v, (unsigned long long)acc);
+            if (VAR) add_global(pl->E2 + v, q * q);
+            return;
+        }
+        const uint32_t s = row_slot(v, ix, n);
+        if (acc > 0) put(ce, pl->E, s, v, (unsigned long long)acc, vbits);
+        else add_global(pl->E + v, (unsigned long long)acc);   // negative deposits stay out of the cache
+        if (VAR && q) put(ce2, pl->E2, s, v, q * q, vbits);
+    }
+};
+
 template <bool EP, class Sink>
 __host__ __device__ void replay_history(const TransportArgs &a, const DevSpot &sp, const DevPlan &pl,
                                const float2 *__restrict__ lut, unsigned long long h, uint32_t slot,
@@ -425,7 +492,9 @@ __global__ void __launch_bounds__(1024) transport_kernel(TransportArgs a)
 // flushed into the plans' tallies with one global atomic per occupied slot and
 // cleared.  Units of one round come from the same spot or a neighbouring one,
 // whose histories overlap in space, so most visits of a round merge in LDS.
-template <bool VAR>
+// CACHE selects the sub-tally: the hash table with global fallback (LdsSink)
+// or the write-back cache (CacheSink).
+template <bool VAR, bool CACHE>
 __global__ void __launch_bounds__(1024) transport_lds_kernel(TransportArgs a, uint32_t slots, uint32_t upw)
 {
     __shared__ float2 s_lut[kLutSize];
@@ -436,7 +505,7 @@ __global__ void __launch_bounds__(1024) transport_lds_kernel(TransportArgs a, ui
     uint32_t *s_key = (uint32_t *)(s_dyn + (VAR ? 2 : 1) * slots);
     for (int i = threadIdx.x; i < kLutSize; i += blockDim.x) s_lut[i] = a.lut[i];
     for (uint32_t i = threadIdx.x; i < slots; i += blockDim.x) {
-        s_key[i] = kEmpty;
+        if (!CACHE) s_key[i] = kEmpty;
         s_e[i] = 0;
         if (VAR) s_e2[i] = 0;
     }
@@ -453,28 +522,50 @@ __global__ void __launch_bounds__(1024) transport_lds_kernel(TransportArgs a, ui
         const unsigned long long base = scalar_u64(s_claim);
         if (base >= a.n_units) break;
         const DevPlan *tab_pl = plan_of_unit(a, base);
+        // value bits of a cache word: the key needs bit_width(voxel count)
+        const uint32_t nvox = (uint32_t)tab_pl->n[0] * (uint32_t)tab_pl->n[1] * (uint32_t)tab_pl->n[2];
+        const uint32_t vbits = 64u - (32u - (uint32_t)__builtin_clz(nvox | 1u));
         for (uint32_t j = 0; j < upw; ++j) {
             const unsigned long long unit = base + (unsigned long long)wave * upw + j;
             if (unit >= a.n_units) break;
             const DevPlan *pl = plan_of_unit(a, unit);
-            process_unit<false>(a, s_lut, unit, lane, LdsSink<VAR>{pl, tab_pl, s_key, s_e, s_e2, slots - 1});
+            if (CACHE)
+                process_unit<false>(a, s_lut, unit, lane, CacheSink<VAR>{pl, tab_pl, s_e, s_e2, slots, vbits});
+            else
+                process_unit<false>(a, s_lut, unit, lane, LdsSink<VAR>{pl, tab_pl, s_key, s_e, s_e2, slots - 1});
         }
         __syncthreads();
         // flush: one atomic per occupied slot; consecutive slots often hold
         // consecutive voxels, so neighbouring lanes' atomics share lines
         const DevPlan *pl = tab_pl;
         for (uint32_t i = threadIdx.x; i < slots; i += blockDim.x) {
-            const uint32_t k = s_key[i];
-            if (k != kEmpty) {
-                const unsigned long long ev = s_e[i];
-                if (ev) add_global(pl->E + k, ev);
-                if (VAR) {
-                    const unsigned long long e2v = s_e2[i];
-                    if (e2v) add_global(pl->E2 + k, e2v);
-                    s_e2[i] = 0;
+            if (CACHE) {
+                const unsigned long long vmax = (1ull << vbits) - 1;
+                const unsigned long long w = s_e[i];
+                if (w) {
+                    add_global(pl->E + ((w >> vbits) - 1), w & vmax);
+                    s_e[i] = 0;
                 }
-                s_e[i] = 0;
-                s_key[i] = kEmpty;
+                if (VAR) {
+                    const unsigned long long w2 = s_e2[i];
+                    if (w2) {
+                        add_global(pl->E2 + ((w2 >> vbits) - 1), w2 & vmax);
+                        s_e2[i] = 0;
+                    }
+                }
+            } else {
+                const uint32_t k = s_key[i];
+                if (k != kEmpty) {
+                    const unsigned long long ev = s_e[i];
+                    if (ev) add_global(pl->E + k, ev);
+                    if (VAR) {
+                        const unsigned long long e2v = s_e2[i];
+                        if (e2v) add_global(pl->E2 + k, e2v);
+                        s_e2[i] = 0;
+                    }
+                    s_e[i] = 0;
+                    s_key[i] = kEmpty;
+                }
             }
         }
         __syncthreads();
@@ -497,32 +588,36 @@ hipError_t launch_transport(const TransportArgs &a, uint32_t waves_per_block, ui
     return hipGetLastError();
 }
 
-size_t lds_tally_bytes(uint32_t slots, bool variance)
+size_t lds_tally_bytes(uint32_t slots, bool variance, uint32_t mode)
 {
-    return (size_t)slots * ((variance ? 16 : 8) + 4);
+    return (size_t)slots * ((variance ? 16 : 8) + (mode ? 0 : 4));
 }
 
 hipError_t prepare_lds_kernels()
 {
     const int dyn = (int)(kMaxLdsBytes - kLutSize * sizeof(float2) - 64);
-    hipError_t e = hipFuncSetAttribute((const void *)transport_lds_kernel<true>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
-    if (e == hipSuccess)
-        e = hipFuncSetAttribute((const void *)transport_lds_kernel<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                dyn);
+    const void *k[4] = {(const void *)transport_lds_kernel<true, false>, (const void *)transport_lds_kernel<false, false>,
+                        (const void *)transport_lds_kernel<true, true>, (const void *)transport_lds_kernel<false, true>};
+    hipError_t e = hipSuccess;
+    for (int i = 0; i < 4 && e == hipSuccess; ++i)
+        e = hipFuncSetAttribute(k[i], hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
     return e;
 }
 
 hipError_t launch_transport_lds(const TransportArgs &a, uint32_t waves_per_block, uint32_t grid_blocks,
-                                uint32_t slots, uint32_t units_per_wave, bool variance, hipStream_t s)
+                                uint32_t slots, uint32_t units_per_wave, bool variance, uint32_t mode, hipStream_t s)
 {
     const dim3 block(waves_per_block * kWave);
     const dim3 grid(grid_blocks);
-    const size_t dyn = lds_tally_bytes(slots, variance);
-    if (variance)
-        hipLaunchKernelGGL((transport_lds_kernel<true>), grid, block, dyn, s, a, slots, units_per_wave);
+    const size_t dyn = lds_tally_bytes(slots, variance, mode);
+    if (mode && variance)
+        hipLaunchKernelGGL((transport_lds_kernel<true, true>), grid, block, dyn, s, a, slots, units_per_wave);
+    else if (mode)
+        hipLaunchKernelGGL((transport_lds_kernel<false, true>), grid, block, dyn, s, a, slots, units_per_wave);
+    else if (variance)
+        hipLaunchKernelGGL((transport_lds_kernel<true, false>), grid, block, dyn, s, a, slots, units_per_wave);
     else
-        hipLaunchKernelGGL((transport_lds_kernel<false>), grid, block, dyn, s, a, slots, units_per_wave);
+        hipLaunchKernelGGL((transport_lds_kernel<false, false>), grid, block, dyn, s, a, slots, units_per_wave);
     return hipGetLastError();
 }
 

@@ -49,7 +49,7 @@ class fdc_summary(C.Structure):
 class fdc_launch_config(C.Structure):
     _fields_ = [("waves_per_block", C.c_uint32), ("blocks_per_cu", C.c_uint32),
                 ("tally_slots", C.c_uint32), ("units_per_wave", C.c_uint32),
-                ("reserved", C.c_uint32 * 4)]
+                ("tally_mode", C.c_uint32), ("reserved", C.c_uint32 * 3)]
 
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
@@ -323,8 +323,8 @@ class Context:
                                                 _stream(stream)))
         return rsp, g, rho
 
-    def set_launch_config(self, waves_per_block=4, blocks_per_cu=0, tally_slots=0, units_per_wave=0):
-        cfg = fdc_launch_config(waves_per_block, blocks_per_cu, tally_slots, units_per_wave)
+    def set_launch_config(self, waves_per_block=4, blocks_per_cu=0, tally_slots=0, units_per_wave=0, tally_mode=0):
+        cfg = fdc_launch_config(waves_per_block, blocks_per_cu, tally_slots, units_per_wave, tally_mode)
         _check(self.h, lib().fdc_set_launch_config(self.h, C.byref(cfg)))
 
     # -- graphs

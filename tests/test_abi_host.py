@@ -136,6 +136,16 @@ def test_launch_config_validation(ctx):
     _expect(F.FDC_E_ARG, ctx.set_launch_config, 0, 0)
     _expect(F.FDC_E_ARG, ctx.set_launch_config, 17, 0)
     _expect(F.FDC_E_ARG, ctx.set_launch_config, 4, 65)
+    # LDS sub-tally sizes: hash table = power of two 256..8192; cache = multiple of 64 that fits
+    ctx.set_launch_config(16, 1, 4096, 2)
+    _expect(F.FDC_E_ARG, ctx.set_launch_config, 16, 1, 3000, 2)
+    _expect(F.FDC_E_ARG, ctx.set_launch_config, 16, 1, 128, 2)
+    ctx.set_launch_config(16, 1, 8128, 2, 1)
+    ctx.set_launch_config(16, 1, 16320, 2, 1)          # fits with the energy tally alone
+    _expect(F.FDC_E_ARG, ctx.set_launch_config, 16, 1, 16384, 2, 1)
+    _expect(F.FDC_E_ARG, ctx.set_launch_config, 16, 1, 8100, 2, 1)
+    _expect(F.FDC_E_ARG, ctx.set_launch_config, 16, 1, 4096, 2, 2)
+    _expect(F.FDC_E_ARG, ctx.set_launch_config, 4, 0, 0, 65)
     assert ctx.device_cus() > 0
 
 
