@@ -23,7 +23,7 @@ CANDIDATES = (
     + [dict(waves_per_block=16, blocks_per_cu=1, tally_slots=4096, units_per_wave=u) for u in (1, 2, 4)]
     + [dict(waves_per_block=8, blocks_per_cu=2, tally_slots=2048, units_per_wave=u) for u in (1, 2, 4)]
     + [dict(waves_per_block=4, blocks_per_cu=4, tally_slots=1024, units_per_wave=u) for u in (2, 4)]
-    + [dict(waves_per_block=16, blocks_per_cu=1, tally_slots=8128, units_per_wave=u, tally_mode=1) for u in (1, 2, 4, 8)]
+    + [dict(waves_per_block=16, blocks_per_cu=1, tally_slots=8064, units_per_wave=u, tally_mode=1) for u in (1, 2, 4, 8)]
     + [dict(waves_per_block=8, blocks_per_cu=2, tally_slots=3008, units_per_wave=u, tally_mode=1) for u in (2, 4)]
 )
 
@@ -84,6 +84,8 @@ def tune(ctx, plans, flags=F.FDC_RUN_VARIANCE, spots_per_plan=None, histories_pe
     for cfg in candidates:
         try:
             ctx.set_launch_config(**cfg)
+            for p in plans:                            # clear the tallies (histories keep counting), so
+                ctx.reset_plan(p)                      # repeated runs of big plans cannot overflow them
             ctx.run_histories(plans, flags)            # warm-up (and first-touch of the tallies)
             t = _time_run(ctx, plans, flags, reps)
         except F.FdcError as e:                        # e.g. an LDS size that does not fit

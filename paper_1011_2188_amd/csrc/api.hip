@@ -62,6 +62,7 @@ struct fdc_ctx {
 
     // track database
     float4 *steps = nullptr;
+    float4 *step_aux = nullptr;
     unsigned long long *track_off = nullptr;
     long long *track_T = nullptr;
     uint32_t *bin_first = nullptr;
@@ -292,6 +293,7 @@ int ensure_plans(fdc_ctx *ctx)
         for (int q = 0; q < 3; ++q) {
             d.n[q] = P.n[q];
             d.vox[q] = P.vox[q];
+            d.inv_vox[q] = 1.f / P.vox[q];
             d.org[q] = P.org[q];
             d.vox_d[q] = P.vox[q];
             d.org_d[q] = P.org[q];
@@ -344,6 +346,7 @@ TransportArgs base_args(const fdc_ctx *ctx)
 {
     TransportArgs a{};
     a.steps = ctx->steps;
+    a.step_aux = ctx->step_aux;
     a.track_off = ctx->track_off;
     a.track_T = ctx->track_T;
     a.bin_first = ctx->bin_first;
@@ -408,7 +411,8 @@ int fdc_destroy(fdc_ctx *ctx)
     for (PlanHost &P : ctx->plans) {
         dfree(ctx, P.idx); dfree(ctx, P.E); dfree(ctx, P.E2); dfree(ctx, P.acc);
     }
-    dfree(ctx, ctx->steps); dfree(ctx, ctx->track_off); dfree(ctx, ctx->track_T); dfree(ctx, ctx->bin_first);
+    dfree(ctx, ctx->steps); dfree(ctx, ctx->step_aux); dfree(ctx, ctx->track_off); dfree(ctx, ctx->track_T);
+    dfree(ctx, ctx->bin_first);
     dfree(ctx, ctx->lut); dfree(ctx, ctx->rho_lut);
     dfree(ctx, ctx->d_plans); dfree(ctx, ctx->d_spots); dfree(ctx, ctx->d_items); dfree(ctx, ctx->d_queue);
     dfree(ctx, ctx->d_hnext);
@@ -524,27 +528,31 @@ int fdc_load_track_db(fdc_ctx *ctx, const fdc_step *steps, uint64_t n_steps, con
     int rc = ensure_table(ctx);
     if (rc) return rc;
     float4 *d_steps = dalloc_n<float4>(ctx, n_steps);
+    float4 *d_aux = dalloc_n<float4>(ctx, n_steps);
     unsigned long long *d_off = dalloc_n<unsigned long long>(ctx, (size_t)n_tracks + 1);
     long long *d_T = dalloc_n<long long>(ctx, n_tracks);
     uint32_t *d_bf = dalloc_n<uint32_t>(ctx, (size_t)n_bins + 1);
-    if (!d_steps || !d_off || !d_T || !d_bf) {
-        dfree(ctx, d_steps); dfree(ctx, d_off); dfree(ctx, d_T); dfree(ctx, d_bf);
+    if (!d_steps || !d_aux || !d_off || !d_T || !d_bf) {
+        dfree(ctx, d_steps); dfree(ctx, d_aux); dfree(ctx, d_off); dfree(ctx, d_T); dfree(ctx, d_bf);
         return fail(ctx, FDC_E_NOMEM, "track database: device allocation of %llu bytes failed",
-                    (unsigned long long)(n_steps * sizeof(float4)));
+                    (unsigned long long)(2 * n_steps * sizeof(float4)));
     }
     hipStream_t s = S(hip_stream);
     hipError_t e = hipMemcpyAsync(d_steps, steps, n_steps * sizeof(float4), hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipMemcpyAsync(d_off, track_off, ((size_t)n_tracks + 1) * 8, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipMemcpyAsync(d_bf, bin_first, ((size_t)n_bins + 1) * 4, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = launch_track_energy(d_steps, d_off, d_T, n_tracks, s);
+    if (e == hipSuccess) e = launch_step_aux(d_steps, d_aux, n_steps, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
-        dfree(ctx, d_steps); dfree(ctx, d_off); dfree(ctx, d_T); dfree(ctx, d_bf);
+        dfree(ctx, d_steps); dfree(ctx, d_aux); dfree(ctx, d_off); dfree(ctx, d_T); dfree(ctx, d_bf);
         return fail(ctx, FDC_E_HIP, "track database upload: %s", hipGetErrorString(e));
     }
     HIPCHK(hipDeviceSynchronize());
-    dfree(ctx, ctx->steps); dfree(ctx, ctx->track_off); dfree(ctx, ctx->track_T); dfree(ctx, ctx->bin_first);
+    dfree(ctx, ctx->steps); dfree(ctx, ctx->step_aux); dfree(ctx, ctx->track_off); dfree(ctx, ctx->track_T);
+    dfree(ctx, ctx->bin_first);
     ctx->steps = d_steps;
+    ctx->step_aux = d_aux;
     ctx->track_off = d_off;
     ctx->track_T = d_T;
     ctx->bin_first = d_bf;
@@ -692,7 +700,7 @@ static int enqueue_transport(fdc_ctx *ctx, TransportArgs a, uint32_t flags, hipS
     const uint32_t wpb = ctx->cfg.waves_per_block;
     const bool variance = (flags & FDC_RUN_VARIANCE) != 0;
     if (ctx->cfg.tally_slots &&
-        kLutSize * sizeof(float2) + 64 + lds_tally_bytes(ctx->cfg.tally_slots, variance, ctx->cfg.tally_mode) >
+        kLutSize * sizeof(float2) + kLdsFixedBytes + lds_tally_bytes(ctx->cfg.tally_slots, variance, ctx->cfg.tally_mode) >
             kMaxLdsBytes)
         return fail(ctx, FDC_E_ARG, "run: LDS sub-tally of %u slots with the squared-energy tally does not fit",
                     ctx->cfg.tally_slots);
@@ -1038,7 +1046,7 @@ int fdc_set_launch_config(fdc_ctx *ctx, const fdc_launch_config *cfg)
             return fail(ctx, FDC_E_ARG, "launch config: tally_slots must be 0 or a power of two 256..8192");
         if (cfg->tally_mode == 1 && (t < 256 || t % 64))
             return fail(ctx, FDC_E_ARG, "launch config: tally_slots must be 0 or a multiple of 64 from 256");
-        if (kLutSize * sizeof(float2) + 64 + lds_tally_bytes(t, false, cfg->tally_mode) > kMaxLdsBytes)
+        if (kLutSize * sizeof(float2) + kLdsFixedBytes + lds_tally_bytes(t, false, cfg->tally_mode) > kMaxLdsBytes)
             return fail(ctx, FDC_E_ARG, "launch config: LDS sub-tally of %u slots does not fit", t);
     }
     if (cfg->units_per_wave > 64) return fail(ctx, FDC_E_ARG, "launch config: units_per_wave must be 0..64");

@@ -52,6 +52,20 @@ __global__ void track_energy_kernel(const float4 *__restrict__ steps, const unsi
     T[t] = s;
 }
 
+// per-step terms the walk would otherwise compute for every lane: the azimuth's
+// cosine and sine (the same sincosf the walk uses, so the values are
+// identical) and the reciprocal step length
+__global__ void step_aux_kernel(const float4 *__restrict__ steps, float4 *__restrict__ aux, unsigned long long n)
+{
+    for (unsigned long long k = blockIdx.x * (unsigned long long)blockDim.x + threadIdx.x; k < n;
+         k += (unsigned long long)gridDim.x * blockDim.x) {
+        const float4 r = steps[k];
+        float sp, cp;
+        sincosf(r.w, &sp, &cp);
+        aux[k] = make_float4(cp, sp, 1.f / r.x, 0.f);
+    }
+}
+
 // dose per primary = E / (rho V) / N and Eq. (2) variance of that mean; N is
 // the plan's device history count
 __global__ void dose_kernel(const uint16_t *__restrict__ idx, const unsigned long long *__restrict__ E,
@@ -155,6 +169,12 @@ hipError_t launch_build_lut(const double *pts, int n_pts, double vacuum_below, f
 hipError_t launch_hu_to_index(const int16_t *hu, uint16_t *idx, size_t n, hipStream_t s)
 {
     hipLaunchKernelGGL(hu_to_index_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, hu, idx, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_step_aux(const float4 *steps, float4 *aux, unsigned long long n, hipStream_t s)
+{
+    hipLaunchKernelGGL(step_aux_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, steps, aux, n);
     return hipGetLastError();
 }
 

@@ -15,6 +15,8 @@ constexpr uint32_t kFlagVariance = 1u;
 constexpr uint32_t kFlagRotate = 2u;
 constexpr int kMaxTablePts = 64;
 constexpr size_t kMaxLdsBytes = 160 * 1024;   // LDS per workgroup on gfx950
+constexpr int kWaveConst = 16;                 // floats of per-wave constants in LDS
+constexpr size_t kLdsFixedBytes = 64 + 16 * kWaveConst * sizeof(float);   // besides the material table
 constexpr double kMeVToJ = 1.602176634e-13;
 constexpr double kFpMeV = 1.0 / 16777216.0;   // one fixed-point unit in MeV
 
@@ -27,6 +29,7 @@ struct DevPlan {
                                      // [3] histories run since the last reset
     int n[3];
     float vox[3];
+    float inv_vox[3];                // 1 / vox (FP32)
     float org[3];
     double vox_d[3];
     double org_d[3];
@@ -65,6 +68,7 @@ __host__ __device__ inline unsigned long long units_for(unsigned long long n)
 
 struct TransportArgs {
     const float4 *steps;                 // (dx, dE, theta, phi)
+    const float4 *step_aux;              // per step: (cos phi, sin phi, 1 / dx, 0), made at load
     const unsigned long long *track_off; // n_tracks + 1
     const long long *track_T;            // sum of fp(dE) per track
     const uint32_t *bin_first;           // n_bins + 1
@@ -138,10 +142,47 @@ __device__ inline void add_global(unsigned long long *p, unsigned long long v)
     __hip_atomic_fetch_add((FDC_AS_GLOBAL unsigned long long *)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// rintf(x) converted to int64, and int64 -> float; both take the 32-bit
+// conversion when it gives the same result (values below 2^31 in magnitude),
+// which is a few instructions instead of the general 64-bit sequence
+__host__ __device__ inline long long rint_ll(float x)
+{
+    const float r = rintf(x);
+    if (fabsf(r) < 2147483648.f) return (long long)(int)r;
+    return (long long)r;
+}
+
+__host__ __device__ inline float ll_to_f(long long e)
+{
+    if (e == (long long)(int)e) return (float)(int)e;
+    return (float)e;
+}
+
+// Reciprocal and reciprocal square root: the hardware approximations
+// (v_rcp_f32, v_rsq_f32, about 1 ulp) in device code, exact division in the
+// host pass (which only CPU checks of the walk compile).
+__host__ __device__ inline float fast_rcp(float x)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_rcpf(x);
+#else
+    return 1.f / x;
+#endif
+}
+
+__host__ __device__ inline float fast_rsq(float x)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_rsqf(x);
+#else
+    return 1.f / sqrtf(x);
+#endif
+}
+
 // energy in MeV (float) -> fixed point; exact for every float input
 __host__ __device__ inline long long to_fp(float mev)
 {
-    return (long long)rintf(mev * 16777216.0f);
+    return rint_ll(mev * 16777216.0f);
 }
 
 // kernels' host-side launchers (implemented next to their kernels)
@@ -154,6 +195,7 @@ hipError_t prepare_lds_kernels();
 hipError_t launch_build_lut(const double *pts, int n_pts, double vacuum_below, float2 *lut, float *rho,
                             hipStream_t s);
 hipError_t launch_hu_to_index(const int16_t *hu, uint16_t *idx, size_t n, hipStream_t s);
+hipError_t launch_step_aux(const float4 *steps, float4 *aux, unsigned long long n, hipStream_t s);
 hipError_t launch_track_energy(const float4 *steps, const unsigned long long *off, long long *T,
                                uint32_t n_tracks, hipStream_t s);
 hipError_t launch_dose(const uint16_t *idx, const unsigned long long *E, const unsigned long long *E2,

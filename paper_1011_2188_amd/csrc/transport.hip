@@ -38,28 +38,30 @@ struct Lane {
     uint32_t v;         // linear voxel index
 };
 
-__host__ __device__ inline void set_direction_terms(const float d[3], const float vox[3], float step_inv[3],
-                                           float dv[3])
+__host__ __device__ inline void set_direction_terms(const float d[3], const float inv_vox[3], float step_inv[3],
+                                                    float dv[3])
 {
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        dv[a] = d[a] / vox[a];                                  // voxel units per cm
-        step_inv[a] = d[a] != 0.f ? vox[a] / fabsf(d[a]) : kInf; // cm per voxel
+        dv[a] = d[a] * inv_vox[a];                  // voxel units per cm
+        step_inv[a] = fast_rcp(fabsf(dv[a]));       // cm per voxel (infinite along an axis not travelled)
     }
 }
 
 // Where a voxel visit's deposit goes.  Every sink adds the integer deposit
 // `acc` to E[v] and, with the squared-energy tally, q^2 to E2[v] with
 // q = (acc + 2^11) >> 12 (the deposit rounded to 2^-12 MeV).
+// (Sinks hold the tally pointers by value: read once per unit, they stay in
+// registers instead of being re-read from the plan record at every flush.)
 template <bool VAR>
 struct GlobalSink {            // 64-bit device atomics straight into the plan's tallies
-    const DevPlan *pl;
+    unsigned long long *E, *E2;
     __device__ void add(uint32_t v, uint32_t, long long acc) const
     {
-        add_global(pl->E + v, (unsigned long long)acc);
+        add_global(E + v, (unsigned long long)acc);
         if (VAR) {
             const unsigned long long q = (unsigned long long)((acc + 2048) >> 12);
-            add_global(pl->E2 + v, q * q);
+            add_global(E2 + v, q * q);
         }
     }
 };
@@ -80,17 +82,17 @@ constexpr int kProbes = 8;
 // the global atomics.
 template <bool VAR>
 struct LdsSink {
-    const DevPlan *pl;          // plan of the unit being replayed
-    const DevPlan *tab_pl;      // plan whose voxels the table holds this round
+    unsigned long long *E, *E2; // tallies of the unit's plan
+    bool same;                  // the unit's plan is the one whose voxels the table holds
     uint32_t *keys;
     unsigned long long *e, *e2;
     uint32_t mask;
     __device__ void add(uint32_t v, uint32_t ix, long long acc) const
     {
         const unsigned long long q = (unsigned long long)((acc + 2048) >> 12);
-        if (pl != tab_pl) {                        // a round straddling two plans
-            add_global(pl->E + v, (unsigned long long)acc);
-            if (VAR) add_global(pl->E2 + v, q * q);
+        if (!same) {                               // a round straddling two plans
+            add_global(E + v, (unsigned long long)acc);
+            if (VAR) add_global(E2 + v, q * q);
             return;
         }
         uint32_t row = v - ix;                     // start of the x row
@@ -109,8 +111,8 @@ struct LdsSink {
             }
             s = (s + 1) & mask;
         }
-        add_global(pl->E + v, (unsigned long long)acc);
-        if (VAR) add_global(pl->E2 + v, q * q);
+        add_global(E + v, (unsigned long long)acc);
+        if (VAR) add_global(E2 + v, q * q);
     }
 };
 
@@ -137,8 +139,8 @@ __device__ inline uint32_t row_slot(uint32_t v, uint32_t ix, uint32_t n)
 // one plan per round; other plans' visits go straight to the global atomics.
 template <bool VAR>
 struct CacheSink {
-    const DevPlan *pl;          // plan of the unit being replayed
-    const DevPlan *tab_pl;      // plan whose voxels the cache holds this round
+    unsigned long long *E, *E2; // tallies of the unit's plan
+    bool same;                  // the unit's plan is the one whose voxels the cache holds
     unsigned long long *ce, *ce2;
     uint32_t n;                 // slots
     uint32_t vbits;             // value bits of a word
@@ -169,22 +171,26 @@ struct CacheSink {
     __device__ void add(uint32_t v, uint32_t ix, long long acc) const
     {
         const unsigned long long q = (unsigned long long)((acc + 2048) >> 12);
-        if (pl != tab_pl) {                        // a round straddling two plans
-            add_global(pl->E + v, (unsigned long long)acc);
-            if (VAR) add_global(pl->E2 + v, q * q);
+        if (!same) {                               // a round straddling two plans
+            add_global(E + v, (unsigned long long)acc);
+            if (VAR) add_global(E2 + v, q * q);
             return;
         }
         const uint32_t s = row_slot(v, ix, n);
-        if (acc > 0) put(ce, pl->E, s, v, (unsigned long long)acc, vbits);
-        else add_global(pl->E + v, (unsigned long long)acc);   // negative deposits stay out of the cache
-        if (VAR && q) put(ce2, pl->E2, s, v, q * q, vbits);
+        if (acc > 0) put(ce, E, s, v, (unsigned long long)acc, vbits);
+        else add_global(E + v, (unsigned long long)acc);   // negative deposits stay out of the cache
+        if (VAR && q) put(ce2, E2, s, v, q * q, vbits);
     }
 };
 
+// wc: the wave's constants in LDS, written by process_unit: the spot's field
+// matrix (9 floats, row-major) and the plan's 1 / voxel size (3).  They are
+// read where they are used (volatile, so not hoisted into registers that
+// would stay live across the walk).
 template <bool EP, class Sink>
 __host__ __device__ void replay_history(const TransportArgs &a, const DevSpot &sp, const DevPlan &pl,
-                               const float2 *__restrict__ lut, unsigned long long h, uint32_t slot,
-                               long long &inc, long long &esc, const Sink &sink)
+                               const float2 *__restrict__ lut, const volatile float *wc, unsigned long long h,
+                               uint32_t slot, long long &inc, long long &esc, const Sink &sink)
 {
     // ---- task 1: track, start step, source ---------------------------------
     const uint32_t first = a.bin_first[sp.bin];
@@ -263,11 +269,17 @@ __host__ __device__ void replay_history(const TransportArgs &a, const DevSpot &s
         L.d[q] = (float)sp.d[q];
     }
     L.b[0] = 0.f; L.b[1] = 0.f; L.b[2] = 1.f;
-    L.v = ((uint32_t)L.i[2] * (uint32_t)pl.n[1] + (uint32_t)L.i[1]) * (uint32_t)pl.n[0] + (uint32_t)L.i[0];
-    const uint32_t stride[3] = {1u, (uint32_t)pl.n[0], (uint32_t)pl.n[0] * (uint32_t)pl.n[1]};
+    // what the walk reads of the plan and spot, as values (not re-read from
+    // memory inside the loops, where the tally atomics could alias them)
+    const int nx = pl.n[0], ny = pl.n[1], nz = pl.n[2];
+    L.v = ((uint32_t)L.i[2] * (uint32_t)ny + (uint32_t)L.i[1]) * (uint32_t)nx + (uint32_t)L.i[0];
+    const uint32_t stride[3] = {1u, (uint32_t)nx, (uint32_t)nx * (uint32_t)ny};
 
     float sinv[3], dv[3];
-    set_direction_terms(L.d, pl.vox, sinv, dv);
+    {
+        const float iv[3] = {wc[9], wc[10], wc[11]};
+        set_direction_terms(L.d, iv, sinv, dv);
+    }
 
     // ---- task 2: re-trace the steps -----------------------------------------
     // Loads are issued one use ahead: the material of the voxel across the
@@ -278,24 +290,25 @@ __host__ __device__ void replay_history(const TransportArgs &a, const DevSpot &s
     float2 m = lut[load_global(vidx, L.v)];
     long long acc = 0, hdep = 0;
     bool escaped = false;
-    bool first_step = true;
-    float4 next_rec = a.steps[k];
-    for (; k < kend; ++k) {
-        const float4 rec = next_rec;
-        if (k + 1 < kend) next_rec = a.steps[k + 1];
-        float w_tot = rec.x, th = rec.z, ph = rec.w;
-        e = to_fp(rec.y);
-        if (first_step) {                          // partial first step
-            const long long e_first = cum + e - skip;
-            const float f = (float)e_first / (float)e;
-            e = e_first;
-            w_tot = f * rec.x;
-            th *= sqrtf(f);
-            ph += phi0;
-            first_step = false;
-        }
-        const float inv_w = 1.f / w_tot;
-        const float ef = (float)e;
+    // the partial first step (its remaining energy e_first of the stored e):
+    // length f * dx, angle sqrt(f) * theta, azimuth rotated by phi0
+    float4 rec = a.steps[k], aux = a.step_aux[k];
+    e = to_fp(rec.y);
+    const long long e_first = cum + e - skip;
+    const float f = ll_to_f(e_first) / ll_to_f(e);
+    e = e_first;
+    float w_tot = f * rec.x;
+    float th = rec.z * sqrtf(f);
+    float cph = aux.x, sph = aux.y;                 // cos, sin of the azimuth
+    float inv_w = 1.f / w_tot;
+    if (phi0 != 0.f) sincosf(rec.w + phi0, &sph, &cph);
+    float4 next_rec = rec, next_aux = aux;
+    if (k + 1 < kend) {
+        next_rec = a.steps[k + 1];
+        next_aux = a.step_aux[k + 1];
+    }
+    for (;;) {
+        const float ef = ll_to_f(e);
         float tau = 0.f, g2 = 0.f;
         long long dep = 0;
         while (tau < w_tot) {
@@ -313,7 +326,7 @@ __host__ __device__ void replay_history(const TransportArgs &a, const DevSpot &s
             // the voxel across that face, and its material index (prefetch)
             const float d_ax = ax == 0 ? L.d[0] : (ax == 1 ? L.d[1] : L.d[2]);
             const int i_ax = ax == 0 ? L.i[0] : (ax == 1 ? L.i[1] : L.i[2]);
-            const int n_ax = ax == 0 ? pl.n[0] : (ax == 1 ? pl.n[1] : pl.n[2]);
+            const int n_ax = ax == 0 ? nx : (ax == 1 ? ny : nz);
             const uint32_t st_ax = ax == 0 ? stride[0] : (ax == 1 ? stride[1] : stride[2]);
             const int ni = i_ax + (d_ax > 0.f ? 1 : -1);
             const bool out = (unsigned)ni >= (unsigned)n_ax;
@@ -335,7 +348,7 @@ __host__ __device__ void replay_history(const TransportArgs &a, const DevSpot &s
                     tau_n = tau + wb;
                 }
                 long long cumk = e;
-                if (tau_n < w_tot) cumk = min(e, (long long)rintf(ef * (tau_n * inv_w)));
+                if (tau_n < w_tot) cumk = min(e, rint_ll(ef * (tau_n * inv_w)));
                 const long long piece = cumk - dep;
                 dep = cumk;
                 acc += piece;
@@ -369,28 +382,44 @@ __host__ __device__ void replay_history(const TransportArgs &a, const DevSpot &s
         if (escaped) break;
         // deflection at the end of the step, scaled by the traversed material
         const float th2 = th * sqrtf(g2 * inv_w);
-        float st, ct, sph, cph;
+        float st, ct;
         sincosf(th2, &st, &ct);
-        sincosf(ph, &sph, &cph);
         const float u = L.b[0], vv = L.b[1], w = L.b[2];
-        const float rho = hypotf(u, vv);
+        const float rho = sqrtf(u * u + vv * vv);         // |u|, |v| <= 1: no overflow
         float nu, nv, nw;
         if (rho < 1e-20f) {
             nu = st * cph;
             nv = st * sph;
             nw = (w < 0.f ? -ct : ct);
         } else {
-            const float ir = 1.f / rho;
+            const float ir = fast_rcp(rho);
             nu = u * ct + st * (u * w * cph - vv * sph) * ir;
             nv = vv * ct + st * (vv * w * cph + u * sph) * ir;
             nw = w * ct - rho * st * cph;
         }
-        const float nrm = 1.f / sqrtf(nu * nu + nv * nv + nw * nw);
+        const float nrm = fast_rsq(nu * nu + nv * nv + nw * nw);
         L.b[0] = nu * nrm; L.b[1] = nv * nrm; L.b[2] = nw * nrm;
 #pragma unroll
         for (int q = 0; q < 3; ++q)
-            L.d[q] = sp.m[3 * q + 0] * L.b[0] + sp.m[3 * q + 1] * L.b[1] + sp.m[3 * q + 2] * L.b[2];
-        set_direction_terms(L.d, pl.vox, sinv, dv);
+            L.d[q] = wc[3 * q + 0] * L.b[0] + wc[3 * q + 1] * L.b[1] + wc[3 * q + 2] * L.b[2];
+        {
+            const float iv[3] = {wc[9], wc[10], wc[11]};
+            set_direction_terms(L.d, iv, sinv, dv);
+        }
+        // next stored step (its record and terms were loaded one step ahead)
+        if (++k >= kend) break;
+        rec = next_rec;
+        aux = next_aux;
+        if (k + 1 < kend) {
+            next_rec = a.steps[k + 1];
+            next_aux = a.step_aux[k + 1];
+        }
+        w_tot = rec.x;
+        th = rec.z;
+        cph = aux.x;
+        sph = aux.y;
+        inv_w = aux.z;
+        e = to_fp(rec.y);
     }
     if (!escaped && acc != 0) sink.add(L.v, (uint32_t)L.i[0], acc);
     esc = escaped ? I_h - hdep : 0;
@@ -410,7 +439,7 @@ __device__ inline long long wave_sum(long long x)
 }
 
 template <bool EP, class Sink>
-__device__ void process_unit(const TransportArgs &a, const float2 *lut, unsigned long long unit,
+__device__ void process_unit(const TransportArgs &a, const float2 *lut, float *wc, unsigned long long unit,
                              uint32_t lane, const Sink &sink)
 {
     // the work item holding this unit: largest i with items[i].unit0 <= unit
@@ -425,8 +454,13 @@ __device__ void process_unit(const TransportArgs &a, const float2 *lut, unsigned
     const unsigned long long h0 = it.h0 + (a.hnext ? a.hnext[it.gspot] : 0ull);
     const unsigned long long h = (h0 / kWave + (unit - it.unit0)) * kWave + lane;
     long long inc = 0, esc = 0;
+    // the wave's constants, one per lane 0..11 whether or not the lane has a
+    // history (one wave's LDS accesses execute in order, so its later reads
+    // see them)
+    if (lane < 9) wc[lane] = sp.m[lane];
+    else if (lane < 12) wc[lane] = pl.inv_vox[lane - 9];
     if (h >= h0 && h < h0 + it.n)
-        replay_history<EP>(a, sp, pl, lut, h, (uint32_t)(h - h0), inc, esc, sink);
+        replay_history<EP>(a, sp, pl, lut, wc, h, (uint32_t)(h - h0), inc, esc, sink);
     if (!EP) {
         inc = wave_sum(inc);
         esc = wave_sum(esc);
@@ -460,6 +494,7 @@ template <bool VAR, bool EP>
 __global__ void __launch_bounds__(1024) transport_kernel(TransportArgs a)
 {
     __shared__ float2 s_lut[kLutSize];
+    __shared__ float s_wc[16][kWaveConst];
     for (int i = threadIdx.x; i < kLutSize; i += blockDim.x) s_lut[i] = a.lut[i];
     __syncthreads();
     const uint32_t lane = threadIdx.x & (kWave - 1);
@@ -468,8 +503,11 @@ __global__ void __launch_bounds__(1024) transport_kernel(TransportArgs a)
     if (a.queue == nullptr) {
         const unsigned long long unit = (unsigned long long)blockIdx.x * wpb + wave;
         if (unit < a.n_units) {
-            if (EP) process_unit<EP>(a, s_lut, unit, lane, NullSink{});
-            else process_unit<EP>(a, s_lut, unit, lane, GlobalSink<VAR>{plan_of_unit(a, unit)});
+            if (EP) process_unit<EP>(a, s_lut, s_wc[wave], unit, lane, NullSink{});
+            else {
+                const DevPlan *pl = plan_of_unit(a, unit);
+                process_unit<EP>(a, s_lut, s_wc[wave], unit, lane, GlobalSink<VAR>{pl->E, pl->E2});
+            }
         }
         return;
     }
@@ -481,8 +519,11 @@ __global__ void __launch_bounds__(1024) transport_kernel(TransportArgs a)
     for (;;) {
         const unsigned long long unit = scalar_u64(atomicAdd(a.queue, lane == 0 ? 1ull : 0ull));
         if (unit >= a.n_units) break;
-        if (EP) process_unit<EP>(a, s_lut, unit, lane, NullSink{});
-        else process_unit<EP>(a, s_lut, unit, lane, GlobalSink<VAR>{plan_of_unit(a, unit)});
+        if (EP) process_unit<EP>(a, s_lut, s_wc[wave], unit, lane, NullSink{});
+        else {
+            const DevPlan *pl = plan_of_unit(a, unit);
+            process_unit<EP>(a, s_lut, s_wc[wave], unit, lane, GlobalSink<VAR>{pl->E, pl->E2});
+        }
     }
 }
 
@@ -498,6 +539,7 @@ template <bool VAR, bool CACHE>
 __global__ void __launch_bounds__(1024) transport_lds_kernel(TransportArgs a, uint32_t slots, uint32_t upw)
 {
     __shared__ float2 s_lut[kLutSize];
+    __shared__ float s_wc[16][kWaveConst];
     __shared__ unsigned long long s_claim;
     extern __shared__ unsigned long long s_dyn[];
     unsigned long long *s_e = s_dyn;
@@ -530,26 +572,28 @@ __global__ void __launch_bounds__(1024) transport_lds_kernel(TransportArgs a, ui
             if (unit >= a.n_units) break;
             const DevPlan *pl = plan_of_unit(a, unit);
             if (CACHE)
-                process_unit<false>(a, s_lut, unit, lane, CacheSink<VAR>{pl, tab_pl, s_e, s_e2, slots, vbits});
+                process_unit<false>(a, s_lut, s_wc[wave], unit, lane,
+                                    CacheSink<VAR>{pl->E, pl->E2, pl == tab_pl, s_e, s_e2, slots, vbits});
             else
-                process_unit<false>(a, s_lut, unit, lane, LdsSink<VAR>{pl, tab_pl, s_key, s_e, s_e2, slots - 1});
+                process_unit<false>(a, s_lut, s_wc[wave], unit, lane,
+                                    LdsSink<VAR>{pl->E, pl->E2, pl == tab_pl, s_key, s_e, s_e2, slots - 1});
         }
         __syncthreads();
         // flush: one atomic per occupied slot; consecutive slots often hold
         // consecutive voxels, so neighbouring lanes' atomics share lines
-        const DevPlan *pl = tab_pl;
+        unsigned long long *const tE = tab_pl->E, *const tE2 = tab_pl->E2;
         for (uint32_t i = threadIdx.x; i < slots; i += blockDim.x) {
             if (CACHE) {
                 const unsigned long long vmax = (1ull << vbits) - 1;
                 const unsigned long long w = s_e[i];
                 if (w) {
-                    add_global(pl->E + ((w >> vbits) - 1), w & vmax);
+                    add_global(tE + ((w >> vbits) - 1), w & vmax);
                     s_e[i] = 0;
                 }
                 if (VAR) {
                     const unsigned long long w2 = s_e2[i];
                     if (w2) {
-                        add_global(pl->E2 + ((w2 >> vbits) - 1), w2 & vmax);
+                        add_global(tE2 + ((w2 >> vbits) - 1), w2 & vmax);
                         s_e2[i] = 0;
                     }
                 }
@@ -557,10 +601,10 @@ __global__ void __launch_bounds__(1024) transport_lds_kernel(TransportArgs a, ui
                 const uint32_t k = s_key[i];
                 if (k != kEmpty) {
                     const unsigned long long ev = s_e[i];
-                    if (ev) add_global(pl->E + k, ev);
+                    if (ev) add_global(tE + k, ev);
                     if (VAR) {
                         const unsigned long long e2v = s_e2[i];
-                        if (e2v) add_global(pl->E2 + k, e2v);
+                        if (e2v) add_global(tE2 + k, e2v);
                         s_e2[i] = 0;
                     }
                     s_e[i] = 0;
@@ -595,7 +639,7 @@ size_t lds_tally_bytes(uint32_t slots, bool variance, uint32_t mode)
 
 hipError_t prepare_lds_kernels()
 {
-    const int dyn = (int)(kMaxLdsBytes - kLutSize * sizeof(float2) - 64);
+    const int dyn = (int)(kMaxLdsBytes - kLutSize * sizeof(float2) - kLdsFixedBytes);
     const void *k[4] = {(const void *)transport_lds_kernel<true, false>, (const void *)transport_lds_kernel<false, false>,
                         (const void *)transport_lds_kernel<true, true>, (const void *)transport_lds_kernel<false, true>};
     hipError_t e = hipSuccess;

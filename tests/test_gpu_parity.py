@@ -187,7 +187,7 @@ def test_launch_configs_bitwise():
                 # write-back cache: tiny tables force evictions and CAS contention
                 dict(waves_per_block=16, blocks_per_cu=1, tally_slots=256, units_per_wave=4, tally_mode=1),
                 dict(waves_per_block=4, blocks_per_cu=2, tally_slots=320, units_per_wave=1, tally_mode=1),
-                dict(waves_per_block=16, blocks_per_cu=1, tally_slots=8128, units_per_wave=2, tally_mode=1)]:
+                dict(waves_per_block=16, blocks_per_cu=1, tally_slots=8064, units_per_wave=2, tally_mode=1)]:
         got = _tallies(db, ph, sp, **cfg)
         assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1]) and got[2] == ref[2], cfg
 
@@ -308,7 +308,7 @@ def test_full_size_slab_sampled():
 
 # ---------------------------------------------------------------- graphs ----
 @pytest.mark.parametrize("cfg", [{}, dict(waves_per_block=16, blocks_per_cu=1, tally_slots=4096, units_per_wave=2),
-                                 dict(waves_per_block=16, blocks_per_cu=1, tally_slots=8128, units_per_wave=2,
+                                 dict(waves_per_block=16, blocks_per_cu=1, tally_slots=8064, units_per_wave=2,
                                       tally_mode=1)])
 def test_graph_replays_match_eager(cfg):
     """A captured run (clear tallies -> transport -> advance counters -> dose)
