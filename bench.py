@@ -6,10 +6,14 @@ histories each = 1e7 histories, database of 33 energy bins x 1e4 synthetic
 water tracks): clear the tallies, re-trace every history with the energy and
 squared-energy tallies, and convert to dose and Eq. (2) variance on the device.
 Inputs (database, phantom, spots) are resident in HBM before timing starts.
+The launch configuration is autotuned before the warm-up (untimed; only knobs
+that cannot change a result bit), or fixed with --launch.
 
 Prints ONE JSON line.  Also reported: seconds to 2% mean dose uncertainty
 (Eq. (2), voxels above half the maximum dose), the transport kernel against the
-HBM roofline, and the CPU oracle timed on this host on a bounded sample.
+HBM roofline (HIP-event kernel time; HBM traffic from the committed rocprofv3
+counter summary when it matches this kernel and launch), and the CPU oracle
+timed on this host on a bounded sample.
 """
 from __future__ import annotations
 
@@ -35,6 +39,26 @@ SLAB_S, SLAB_C, SLAB_G = 95.03, 205.38, 111.71
 
 def slab_bytes_per_history(variance: bool) -> float:
     return 16.0 * SLAB_S / 64.0 + 2.0 * SLAB_C + 8.0 * SLAB_G * (2.0 if variance else 1.0)
+
+
+def measured_traffic(launch):
+    """HBM bytes per launch of the transport kernel from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE summary, if it was taken for this launch
+    configuration and the kernel sources are unchanged since; else None."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "transport_slab_1e7_pmc.md")
+    try:
+        fields = dict(line.strip().split(": ", 1) for line in open(path) if line.startswith("    ") and ": " in line
+                      and line.strip().split(": ", 1)[0] in ("launch", "traffic_bytes_per_launch", "kernel_source_sha1"))
+        src = b"".join(open(os.path.join(ROOT, "paper_1011_2188_amd", "csrc", f), "rb").read()
+                       for f in ("transport.hip", "fdc_device.h"))
+    except (OSError, ValueError):
+        return None
+    want = ",".join(str(launch.get(k, 0)) for k in ("waves_per_block", "blocks_per_cu", "tally_slots",
+                                                     "units_per_wave", "tally_mode"))
+    if fields.get("kernel_source_sha1") != hashlib.sha1(src).hexdigest() or fields.get("launch") != want:
+        return None
+    return float(fields["traffic_bytes_per_launch"])
 
 
 def log(*a):
@@ -69,7 +93,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--launch", default="tune",
                     help="'tune' (autotune before the warm-up, untimed) or waves_per_block,blocks_per_cu,"
-                         "tally_slots,units_per_wave")
+                         "tally_slots,units_per_wave[,tally_mode]")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -107,9 +131,11 @@ def main():
         t = time.perf_counter()
         launch, timings = A.tune(c, [plan], flags, reps=2, use_cache=False)
         log(f"autotuned in {time.perf_counter() - t:.1f} s: {launch}")
+        for k, v in sorted(timings.items(), key=lambda kv: kv[1]):
+            log(f"  {v * 1e3:8.2f} ms  {k}")
     else:
-        w, b, ts, u = (int(v) for v in args.launch.split(","))
-        launch = dict(waves_per_block=w, blocks_per_cu=b, tally_slots=ts, units_per_wave=u)
+        v = [int(x) for x in args.launch.split(",")]
+        launch = dict(zip(("waves_per_block", "blocks_per_cu", "tally_slots", "units_per_wave", "tally_mode"), v))
         c.set_launch_config(**launch)
     kernel = "transport_lds_kernel" if launch.get("tally_slots", 0) else "transport_kernel"
     nvox = ph.hu.size
@@ -160,7 +186,8 @@ def main():
 
     bph = slab_bytes_per_history(variance)
     achieved = bph * hist_per_step / (kern_ms * 1e-3) / 1e9
-    atomics = SLAB_G * (2.0 if variance else 1.0) * hist_per_step / (kern_ms * 1e-3)
+    updates = SLAB_G * (2.0 if variance else 1.0) * hist_per_step / (kern_ms * 1e-3)
+    traffic = measured_traffic(launch)
     result = {
         "metric": METRIC, "value": value, "unit": "histories/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True,
@@ -170,9 +197,9 @@ def main():
                                "fixed-point tallies" + (" + squared-energy tally" if variance else ""),
                    "histories_per_step": hist_per_step, "variance": variance, "launch": launch},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": kernel, "kernel_ms": kern_ms,
-                     "bytes_per_history": bph, "tally_atomics_per_s": atomics},
+                     "bytes_per_history": bph, "tally_updates_per_s": updates},
         **out,
     }
     if not args.no_cpu_baseline:
