@@ -106,17 +106,18 @@ class Simulator:
         return out[0]
 
 
-def make_pairs(sim, plans, high_passes):
-    """Per plan: (input [2,z,y,x], target [z,y,x]) float32 device tensors; the
-    input from one pass, the target from `high_passes` further passes."""
-    torch = sim.torch
+def make_pairs(sim, plans, high_passes, levels=(1,)):
+    """Per plan and input level k: (input [2,z,y,x], target [z,y,x]) float32
+    device tensors; the input from k passes, the target from `high_passes`
+    further passes, both divided by the input's Dmax (one target per level)."""
     pairs = []
     for p in plans:
-        low, _ = sim.dose(p, 1)
+        lows = [(k, sim.dose(p, k)[0]) for k in levels]
         high, _ = sim.dose(p, high_passes)
         rho = sim.density(p)
-        x, dmax = sim.net_input(p, low, rho)
-        pairs.append((x, sim.scaled(p, high, rho, dmax)))
+        for k, low in lows:
+            x, dmax = sim.net_input(p, low, rho)
+            pairs.append((x, sim.scaled(p, high, rho, dmax)))
     return pairs
 
 

@@ -206,17 +206,18 @@ def thorax_phantom(n=(256, 256, 128), voxel_cm=0.2, seed=2188, scale=(1.0, 1.0, 
     x = (np.arange(nx) + 0.5) * voxel_cm - 0.5 * nx * voxel_cm
     y = (np.arange(ny) + 0.5) * voxel_cm - 0.5 * ny * voxel_cm
     z = (np.arange(nz) + 0.5) * voxel_cm - 0.5 * nz * voxel_cm
-    Z, Y, X = np.meshgrid(z, y, x, indexing="ij")
-    hu = np.full((nz, ny, nx), -1000.0)
-    body = (X / (body_axes[0] * sx)) ** 2 + (Y / (body_axes[1] * sy)) ** 2 <= 1.0
+    X, Y = x[None, :], y[:, None]              # cylinders along z: masks on the (y, x) plane
+    shape = (nz, ny, nx)
+    hu = np.full(shape, -1000.0)
+    body = np.broadcast_to((X / (body_axes[0] * sx)) ** 2 + (Y / (body_axes[1] * sy)) ** 2 <= 1.0, shape)
     hu[body] = rng.normal(40.0, 20.0, int(body.sum()))
-    lungs = np.zeros_like(body)
+    lungs = np.zeros(shape, bool)
+    tz = ((z / (lung_axes[2] * sz)) ** 2)[:, None, None]
     for cx in (-lung_centre_x, lung_centre_x):
-        lungs |= (((X - cx * sx) / (lung_axes[0] * sx)) ** 2
-                  + ((Y - lung_centre_y * sy) / (lung_axes[1] * sy)) ** 2
-                  + (Z / (lung_axes[2] * sz)) ** 2) <= 1.0
+        txy = (((X - cx * sx) / (lung_axes[0] * sx)) ** 2 + ((Y - lung_centre_y * sy) / (lung_axes[1] * sy)) ** 2)
+        lungs |= (txy[None] + tz) <= 1.0
     hu[lungs] = rng.normal(-800.0, 50.0, int(lungs.sum()))
-    spine = X ** 2 + (Y - spine_centre_y * sy) ** 2 <= (spine_radius * min(sx, sy)) ** 2
+    spine = np.broadcast_to(X ** 2 + (Y - spine_centre_y * sy) ** 2 <= (spine_radius * min(sx, sy)) ** 2, shape)
     hu[spine] = rng.normal(1000.0, 100.0, int(spine.sum()))
     hu = np.clip(np.rint(hu), -32768, 32767).astype(np.int16)
     vox = np.full(3, voxel_cm, np.float32)
