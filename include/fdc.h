@@ -159,9 +159,11 @@ int fdc_set_hu_table(fdc_ctx *ctx, const float *hu_pts, const float *rho, const 
  * steps[track_off[t] .. track_off[t+1]); tracks of energy bin b are
  * bin_first[b] .. bin_first[b+1]-1, bin energies bin_E_MeV[b] strictly
  * increasing.  Replaces a previously loaded database.
+ * A step's energy loss must be below 128 MeV (its 2^-24 MeV fixed-point value
+ * then fits 32 bits; stored steps are a few MeV).
  * Errors: FDC_E_ARG (NULL, zero counts), FDC_E_FORMAT (offsets not monotone or
  * not ending at n_steps, empty track or bin, bins not increasing, dx <= 0, dE <
- * 0 or any non-finite value), FDC_E_NOMEM, FDC_E_HIP. */
+ * 0, dE >= 128 MeV or any non-finite value), FDC_E_NOMEM, FDC_E_HIP. */
 int fdc_load_track_db(fdc_ctx *ctx, const fdc_step *steps, uint64_t n_steps,
                       const uint64_t *track_off, uint32_t n_tracks, const float *bin_E_MeV,
                       const uint32_t *bin_first, uint32_t n_bins, void *hip_stream);

@@ -515,6 +515,9 @@ int fdc_load_track_db(fdc_ctx *ctx, const fdc_step *steps, uint64_t n_steps, con
             return fail(ctx, FDC_E_FORMAT, "track database: non-finite value in step %llu", (unsigned long long)k);
         if (!(s.dx_cm > 0.f) || s.dE_MeV < 0.f || s.theta_rad < 0.f)
             return fail(ctx, FDC_E_FORMAT, "track database: step %llu needs dx > 0, dE >= 0, theta >= 0", (unsigned long long)k);
+        if (!(s.dE_MeV < 128.f))       // the walk splits a step's energy in 32-bit fixed point
+            return fail(ctx, FDC_E_FORMAT, "track database: step %llu loses %g MeV (must be below 128)",
+                        (unsigned long long)k, (double)s.dE_MeV);
     }
     if (ctx->dry) {
         ctx->bin_E.assign(bin_E, bin_E + n_bins);

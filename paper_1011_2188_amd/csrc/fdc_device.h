@@ -179,6 +179,29 @@ __host__ __device__ inline float fast_rsq(float x)
 #endif
 }
 
+__host__ __device__ inline float fast_sqrt(float x)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_sqrtf(x);          // v_sqrt_f32
+#else
+    return sqrtf(x);
+#endif
+}
+
+// sin and cos of a small angle: Taylor series to x^9 and x^10 (truncation
+// below 2e-11 for |x| <= 0.5, under FP32 rounding); sincosf beyond.
+__host__ __device__ inline void small_sincos(float x, float *s, float *c)
+{
+    if (fabsf(x) <= 0.5f) {
+        const float x2 = x * x;
+        *s = x * fmaf(x2, fmaf(x2, fmaf(x2, fmaf(x2, 1.f / 362880.f, -1.f / 5040.f), 1.f / 120.f), -1.f / 6.f), 1.f);
+        *c = fmaf(x2, fmaf(x2, fmaf(x2, fmaf(x2, fmaf(x2, -1.f / 3628800.f, 1.f / 40320.f), -1.f / 720.f),
+                                    1.f / 24.f), -0.5f), 1.f);
+    } else {
+        sincosf(x, s, c);
+    }
+}
+
 // energy in MeV (float) -> fixed point; exact for every float input
 __host__ __device__ inline long long to_fp(float mev)
 {

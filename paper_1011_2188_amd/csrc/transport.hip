@@ -38,13 +38,20 @@ struct Lane {
     uint32_t v;         // linear voxel index
 };
 
-__host__ __device__ inline void set_direction_terms(const float d[3], const float inv_vox[3], float step_inv[3],
-                                                    float dv[3])
+// Per-direction terms of the walk: dv = voxel units per cm along each axis,
+// and the coefficients of the distance (cm) to the exit face along an axis as
+// a function of the fraction f inside the voxel: t = ta * f + tb, i.e.
+// (1 - f) / |dv| moving up, f / |dv| moving down, infinite along an axis not
+// travelled.
+__host__ __device__ inline void set_direction_terms(const float d[3], const float inv_vox[3], float ta[3],
+                                                    float tb[3], float dv[3])
 {
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        dv[a] = d[a] * inv_vox[a];                  // voxel units per cm
-        step_inv[a] = fast_rcp(fabsf(dv[a]));       // cm per voxel (infinite along an axis not travelled)
+        dv[a] = d[a] * inv_vox[a];
+        const float s = fast_rcp(fabsf(dv[a]));
+        ta[a] = d[a] > 0.f ? -s : (d[a] < 0.f ? s : 0.f);
+        tb[a] = d[a] > 0.f ? s : (d[a] < 0.f ? 0.f : kInf);
     }
 }
 
@@ -145,27 +152,13 @@ struct CacheSink {
     uint32_t n;                 // slots
     uint32_t vbits;             // value bits of a word
 
-    __device__ static void put(unsigned long long *c, unsigned long long *g, uint32_t s, uint32_t v,
-                               unsigned long long val, uint32_t vbits)
+    // one word's next value: hit -> add (0 when the sum would overflow its
+    // field), miss -> install the voxel with val
+    __device__ static unsigned long long next_word(unsigned long long w, unsigned long long key,
+                                                   unsigned long long val, unsigned long long vmax)
     {
-        const unsigned long long vmax = (1ull << vbits) - 1;
-        const unsigned long long key = (unsigned long long)(v + 1) << vbits;
-        if (val <= vmax) {
-            unsigned long long w = c[s];
-#pragma unroll 1
-            for (int tries = 0; tries < 16; ++tries) {
-                const bool hit = (w & ~vmax) == key;
-                if (hit && val > vmax - (w & vmax)) break;        // the sum would overflow
-                const unsigned long long nw = hit ? w + val : (key | val);
-                const unsigned long long old = atomicCAS(c + s, w, nw);
-                if (old == w) {
-                    if (!hit && w != 0) add_global(g + ((w >> vbits) - 1), w & vmax);
-                    return;
-                }
-                w = old;
-            }
-        }
-        add_global(g + v, val);
+        if ((w & ~vmax) == key) return val > vmax - (w & vmax) ? 0ull : w + val;
+        return key | val;
     }
 
     __device__ void add(uint32_t v, uint32_t ix, long long acc) const
@@ -177,9 +170,44 @@ struct CacheSink {
             return;
         }
         const uint32_t s = row_slot(v, ix, n);
-        if (acc > 0) put(ce, E, s, v, (unsigned long long)acc, vbits);
-        else add_global(E + v, (unsigned long long)acc);   // negative deposits stay out of the cache
-        if (VAR && q) put(ce2, E2, s, v, q * q, vbits);
+        const unsigned long long vmax = (1ull << vbits) - 1;
+        const unsigned long long key = (unsigned long long)(v + 1) << vbits;
+        const unsigned long long v1 = (unsigned long long)acc, v2 = q * q;
+        // deposits are >= 0 (the database has dE >= 0); values wider than a
+        // word's field go straight to the global tally
+        bool todo1 = acc > 0, todo2 = VAR && q != 0;
+        if (todo1 && v1 > vmax) { add_global(E + v, v1); todo1 = false; }
+        if (todo2 && v2 > vmax) { add_global(E2 + v, v2); todo2 = false; }
+        // the two words are updated side by side: both reads, both
+        // compare-and-swaps, then each retries on its own if it lost a race
+        unsigned long long w1 = todo1 ? ce[s] : 0ull, w2 = todo2 ? ce2[s] : 0ull;
+#pragma unroll 1
+        for (int tries = 0; tries < 16 && (todo1 || todo2); ++tries) {
+            const unsigned long long n1 = todo1 ? next_word(w1, key, v1, vmax) : 0ull;
+            const unsigned long long n2 = todo2 ? next_word(w2, key, v2, vmax) : 0ull;
+            if (todo1 && n1 == 0ull) { add_global(E + v, v1); todo1 = false; }     // would overflow
+            if (todo2 && n2 == 0ull) { add_global(E2 + v, v2); todo2 = false; }
+            const unsigned long long o1 = todo1 ? atomicCAS(ce + s, w1, n1) : w1;
+            const unsigned long long o2 = todo2 ? atomicCAS(ce2 + s, w2, n2) : w2;
+            if (todo1) {
+                if (o1 == w1) {
+                    if (w1 != 0 && (w1 & ~vmax) != key) add_global(E + ((w1 >> vbits) - 1), w1 & vmax);   // evicted
+                    todo1 = false;
+                } else {
+                    w1 = o1;
+                }
+            }
+            if (todo2) {
+                if (o2 == w2) {
+                    if (w2 != 0 && (w2 & ~vmax) != key) add_global(E2 + ((w2 >> vbits) - 1), w2 & vmax);
+                    todo2 = false;
+                } else {
+                    w2 = o2;
+                }
+            }
+        }
+        if (todo1) add_global(E + v, v1);
+        if (todo2) add_global(E2 + v, v2);
     }
 };
 
@@ -275,10 +303,10 @@ __host__ __device__ void replay_history(const TransportArgs &a, const DevSpot &s
     L.v = ((uint32_t)L.i[2] * (uint32_t)ny + (uint32_t)L.i[1]) * (uint32_t)nx + (uint32_t)L.i[0];
     const uint32_t stride[3] = {1u, (uint32_t)nx, (uint32_t)nx * (uint32_t)ny};
 
-    float sinv[3], dv[3];
+    float ta[3], tb[3], dv[3];
     {
         const float iv[3] = {wc[9], wc[10], wc[11]};
-        set_direction_terms(L.d, iv, sinv, dv);
+        set_direction_terms(L.d, iv, ta, tb, dv);
     }
 
     // ---- task 2: re-trace the steps -----------------------------------------
@@ -296,7 +324,7 @@ __host__ __device__ void replay_history(const TransportArgs &a, const DevSpot &s
     e = to_fp(rec.y);
     const long long e_first = cum + e - skip;
     const float f = ll_to_f(e_first) / ll_to_f(e);
-    e = e_first;
+    int e32 = (int)e_first;                         // a step's energy fits 32 bits (checked at load)
     float w_tot = f * rec.x;
     float th = rec.z * sqrtf(f);
     float cph = aux.x, sph = aux.y;                 // cos, sin of the azimuth
@@ -308,17 +336,14 @@ __host__ __device__ void replay_history(const TransportArgs &a, const DevSpot &s
         next_aux = a.step_aux[k + 1];
     }
     for (;;) {
-        const float ef = ll_to_f(e);
+        const float ef = (float)e32;
         float tau = 0.f, g2 = 0.f;
-        long long dep = 0;
+        int dep = 0;
         while (tau < w_tot) {
             // distance (cm) to the exit face along each axis; ties go x -> y -> z
-            float tx = (L.d[0] > 0.f ? 1.f - L.f[0] : L.f[0]) * sinv[0];
-            float ty = (L.d[1] > 0.f ? 1.f - L.f[1] : L.f[1]) * sinv[1];
-            float tz = (L.d[2] > 0.f ? 1.f - L.f[2] : L.f[2]) * sinv[2];
-            tx = L.d[0] != 0.f ? tx : kInf;
-            ty = L.d[1] != 0.f ? ty : kInf;
-            tz = L.d[2] != 0.f ? tz : kInf;
+            const float tx = fmaf(ta[0], L.f[0], tb[0]);
+            const float ty = fmaf(ta[1], L.f[1], tb[1]);
+            const float tz = fmaf(ta[2], L.f[2], tb[2]);
             float tmin = tx;
             int ax = 0;
             if (ty < tmin) { tmin = ty; ax = 1; }
@@ -341,15 +366,15 @@ __host__ __device__ void replay_history(const TransportArgs &a, const DevSpot &s
                 if (rem <= wb) {
                     w_v = rem;
                     tau_n = w_tot;
-                    move = rem / m.x;
+                    move = rem * fast_rcp(m.x);
                     cross = (rem == wb);
                 } else {
                     w_v = wb;
                     tau_n = tau + wb;
                 }
-                long long cumk = e;
-                if (tau_n < w_tot) cumk = min(e, rint_ll(ef * (tau_n * inv_w)));
-                const long long piece = cumk - dep;
+                int cumk = e32;
+                if (tau_n < w_tot) cumk = min(e32, (int)rintf(ef * (tau_n * inv_w)));
+                const int piece = cumk - dep;
                 dep = cumk;
                 acc += piece;
                 hdep += piece;
@@ -381,11 +406,11 @@ __host__ __device__ void replay_history(const TransportArgs &a, const DevSpot &s
         }
         if (escaped) break;
         // deflection at the end of the step, scaled by the traversed material
-        const float th2 = th * sqrtf(g2 * inv_w);
+        const float th2 = th * fast_sqrt(g2 * inv_w);
         float st, ct;
-        sincosf(th2, &st, &ct);
+        small_sincos(th2, &st, &ct);
         const float u = L.b[0], vv = L.b[1], w = L.b[2];
-        const float rho = sqrtf(u * u + vv * vv);         // |u|, |v| <= 1: no overflow
+        const float rho = fast_sqrt(u * u + vv * vv);     // |u|, |v| <= 1: no overflow
         float nu, nv, nw;
         if (rho < 1e-20f) {
             nu = st * cph;
@@ -404,7 +429,7 @@ __host__ __device__ void replay_history(const TransportArgs &a, const DevSpot &s
             L.d[q] = wc[3 * q + 0] * L.b[0] + wc[3 * q + 1] * L.b[1] + wc[3 * q + 2] * L.b[2];
         {
             const float iv[3] = {wc[9], wc[10], wc[11]};
-            set_direction_terms(L.d, iv, sinv, dv);
+            set_direction_terms(L.d, iv, ta, tb, dv);
         }
         // next stored step (its record and terms were loaded one step ahead)
         if (++k >= kend) break;
@@ -419,7 +444,7 @@ __host__ __device__ void replay_history(const TransportArgs &a, const DevSpot &s
         cph = aux.x;
         sph = aux.y;
         inv_w = aux.z;
-        e = to_fp(rec.y);
+        e32 = (int)to_fp(rec.y);
     }
     if (!escaped && acc != 0) sink.add(L.v, (uint32_t)L.i[0], acc);
     esc = escaped ? I_h - hdep : 0;

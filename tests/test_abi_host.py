@@ -66,6 +66,7 @@ def test_track_db_validation(ctx):
         return d
     _expect(F.FDC_E_FORMAT, ctx.load_track_db, bad(lambda d: d.steps.__setitem__((5, 0), 0.0)))
     _expect(F.FDC_E_FORMAT, ctx.load_track_db, bad(lambda d: d.steps.__setitem__((5, 1), -1.0)))
+    _expect(F.FDC_E_FORMAT, ctx.load_track_db, bad(lambda d: d.steps.__setitem__((5, 1), 128.0)))  # 32-bit split
     _expect(F.FDC_E_FORMAT, ctx.load_track_db, bad(lambda d: d.steps.__setitem__((2, 2), np.nan)))
     _expect(F.FDC_E_FORMAT, ctx.load_track_db, bad(lambda d: d.track_off.__setitem__(2, d.track_off[1])))
     _expect(F.FDC_E_FORMAT, ctx.load_track_db, bad(lambda d: d.track_off.__setitem__(-1, d.track_off[-1] - 1)))
