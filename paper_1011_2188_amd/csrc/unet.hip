@@ -167,6 +167,94 @@ __global__ void __launch_bounds__(256) igemm_kernel(const u16 *__restrict__ src,
 }
 
 // ---------------------------------------------------------------------------
+// 3x3x3 convolution (forward and backward-data) with the input tile in LDS.
+// A block computes an output tile of 16 (x) x TY (y) x 4 (z) voxels for 16*NT
+// output channels: it stages the tile and a one-voxel halo, (TY+2) x 6 x 18
+// voxels of all input channels, into LDS once (channels-last, 16-byte rows),
+// then every kernel tap is an offset into that copy instead of a new gather
+// through the caches.  Wave w computes the z slice w; its m-th MFMA row tile
+// is the 16 voxels of x at y = m.  K = 27 taps x cpad channels, in steps of 32
+// (lane group lg takes 8 channels of tap (k0 + 8 lg) / cpad).  Weights (the
+// B operand) come from the packed table in global memory, as in igemm.
+template <int NT, int TY>
+__global__ void __launch_bounds__(256) conv3_kernel(const u16 *__restrict__ src, int src_pitch, int cpad, int cshift,
+                                                    Grid g, const u16 *__restrict__ wpk, int kpad, int n_cols,
+                                                    const float *__restrict__ bias, int relu,
+                                                    const u16 *__restrict__ mask, int mask_pitch,
+                                                    u16 *__restrict__ dst, int dst_pitch)
+{
+    constexpr int TX = 16, TZ = 4, HX = TX + 2, HY = TY + 2, HZ = TZ + 2;
+    extern __shared__ __attribute__((aligned(16))) u16 sh[];
+    const int hp = cpad + 8;                               // LDS channel pitch (16-byte rows, skewed banks)
+    const int tiles_x = (g.nx + TX - 1) / TX, tiles_y = (g.ny + TY - 1) / TY;
+    const int bx = blockIdx.x % tiles_x, by = (blockIdx.x / tiles_x) % tiles_y, bz = blockIdx.x / (tiles_x * tiles_y);
+    const int x0 = bx * TX, y0 = by * TY, z0 = bz * TZ;
+    const int n_base = blockIdx.y * 16 * NT;
+    const int cg_n = cpad / 8;
+    for (int t = threadIdx.x; t < HZ * HY * HX * cg_n; t += blockDim.x) {
+        const int h = t / cg_n, cg = t - h * cg_n;
+        const int hx = h % HX, hy = (h / HX) % HY, hz = h / (HX * HY);
+        const int x = x0 - 1 + hx, y = y0 - 1 + hy, z = z0 - 1 + hz;
+        uint4 v = make_uint4(0, 0, 0, 0);
+        if (x >= 0 && x < g.nx && y >= 0 && y < g.ny && z >= 0 && z < g.nz)
+            v = *(const uint4 *)(src + (((long)z * g.ny + y) * g.nx + x) * src_pitch + 8 * cg);
+        *(uint4 *)(sh + h * hp + 8 * cg) = v;
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int li = lane & 15, lg = lane >> 4;
+    const int kvalid = 27 * cpad;
+    f32x4 acc[TY][NT];
+#pragma unroll
+    for (int m = 0; m < TY; ++m)
+#pragma unroll
+        for (int t = 0; t < NT; ++t) acc[m][t] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 0; k0 < kpad; k0 += 32) {
+        const int k = k0 + 8 * lg;
+        const bool kv = k < kvalid;
+        const int o = k >> cshift, c = k - (o << cshift);
+        const int dz = o / 9, dy = (o / 3) % 3, dx = o % 3;   // halo coordinates are shifted by +1
+        bf16x8 b[NT];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            const int n = n_base + 16 * t + li;
+            b[t] = (kv && n < n_cols) ? load8(wpk + (long)n * kpad + k) : zero8();
+        }
+#pragma unroll
+        for (int m = 0; m < TY; ++m) {
+            const int h = ((w + dz) * HY + (m + dy)) * HX + (li + dx);
+            const bf16x8 a = kv ? load8(sh + h * hp + c) : zero8();
+#pragma unroll
+            for (int t = 0; t < NT; ++t) acc[m][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[t], acc[m][t], 0, 0, 0);
+        }
+    }
+    // epilogue: lane holds D[4 lg + e][li] of every (m, t) tile: voxel x = x0 + 4 lg + e
+    const int z = z0 + w;
+    if (z >= g.nz) return;
+#pragma unroll
+    for (int m = 0; m < TY; ++m) {
+        const int y = y0 + m;
+        if (y >= g.ny) continue;
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            const int n = n_base + 16 * t + li;
+            if (n >= n_cols) continue;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int x = x0 + 4 * lg + e;
+                if (x >= g.nx) continue;
+                const long r = ((long)z * g.ny + y) * g.nx + x;
+                float v = acc[m][t][e];
+                if (bias) v += bias[n];
+                if (relu) v = fmaxf(v, 0.f);
+                if (mask && !(bf2f(mask[r * mask_pitch + n]) > 0.f)) v = 0.f;
+                dst[r * dst_pitch + n] = f2bf(v);
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // weight gradient: part[slab][o][i][j] = sum over the slab's rows v of
 // P[v][i] * Q[src(v, o)][j], with src as in the igemm gathers:
 //   A_CONV3: Q on the row grid, neighbour o (zero outside);  A_S2D: Q on the
@@ -387,16 +475,34 @@ __global__ void slab_sum_kernel(const float *__restrict__ part, int slabs, long 
     }
 }
 
-// bias gradient partials: part[block][c] = sum over the block's voxels of G[v][c]
-__global__ void bias_part_kernel(const u16 *__restrict__ G, int pitch, int C, long n, long per_block,
-                                 float *__restrict__ part)
+// bias gradient partials: part[block][c] = sum over the block's voxels of G[v][c].
+// Thread t reads 8 channels (16 bytes) of voxel v0 + t / (C/8) + k * (256 / (C/8)),
+// so consecutive threads read consecutive bytes; the per-thread sums are then
+// added per channel in a fixed order (reproducible).  C: multiple of 8, <= 64.
+__global__ void __launch_bounds__(256) bias_part_kernel(const u16 *__restrict__ G, int pitch, int C, long n,
+                                                        long per_block, float *__restrict__ part)
 {
+    __shared__ float red[256][8];
+    const int cgs = C / 8, per_step = 256 / cgs;
+    const int cg = threadIdx.x % cgs, vo = threadIdx.x / cgs;
     const long v0 = blockIdx.x * per_block, v1 = std::min<long>(n, v0 + per_block);
-    for (int c = threadIdx.y; c < C; c += blockDim.y) {
-        float s = 0.f;
-        for (long v = v0 + threadIdx.x; v < v1; v += blockDim.x) s += bf2f(G[v * pitch + c]);
-        for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
-        if (threadIdx.x == 0) part[(long)blockIdx.x * C + c] = s;
+    float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    if (vo < per_step) {
+        for (long v = v0 + vo; v < v1; v += per_step) {
+            const uint4 q = *(const uint4 *)(G + v * pitch + 8 * cg);
+            const u16 *h = (const u16 *)&q;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) acc[e] += bf2f(h[e]);
+        }
+    }
+#pragma unroll
+    for (int e = 0; e < 8; ++e) red[threadIdx.x][e] = acc[e];
+    __syncthreads();
+    if ((int)threadIdx.x < C) {
+        const int c = threadIdx.x, g8 = c / 8, e = c % 8;
+        float sum = 0.f;
+        for (int k = 0; k < per_step; ++k) sum += red[k * cgs + g8][e];
+        part[(long)blockIdx.x * C + c] = sum;
     }
 }
 
@@ -694,7 +800,22 @@ hipError_t igemm(int am, int em, const View &src, int cpad, const Grid &g, const
         if (am != A_CONV1) return hipErrorInvalidValue;
         IGN(A_CONV1, E_D2S);
     } else if (am == A_CONV3) {
-        IGN(A_CONV3, E_STORE);
+        // LDS-tiled kernel: 16 x TY x 4 output voxels per block (TY = 2 for 64
+        // input channels, so the tile and its halo stay under 64 KB of LDS)
+        const int ty = cpad >= 64 ? 2 : 4;
+        const int cshift = __builtin_ctz((unsigned)cpad);
+        if ((cpad & (cpad - 1)) || cpad < 8 || cpad > 64) return hipErrorInvalidValue;
+        const uint32_t tiles = (uint32_t)(((g.nx + 15) / 16) * ((g.ny + ty - 1) / ty) * ((g.nz + 3) / 4));
+        const dim3 cgrid(tiles, (uint32_t)((n_cols + 16 * nt - 1) / (16 * nt)));
+        const size_t lds = (size_t)6 * (ty + 2) * 18 * (cpad + 8) * sizeof(u16);
+#define CV(NT_, TY_) hipLaunchKernelGGL((conv3_kernel<NT_, TY_>), cgrid, dim3(256), lds, s, src.p, src.pitch, cpad, \
+                                        cshift, g, wpk, kpad, n_cols, bias, (int)relu, mp, mpitch, dst.p, dst.pitch)
+        if (ty == 2) {
+            if (nt == 4) CV(4, 2); else if (nt == 2) CV(2, 2); else CV(1, 2);
+        } else {
+            if (nt == 4) CV(4, 4); else if (nt == 2) CV(2, 4); else CV(1, 4);
+        }
+#undef CV
     } else if (am == A_S2D) {
         IGN(A_S2D, E_STORE);
     } else {
@@ -749,9 +870,10 @@ hipError_t wgrad(int am, const View &P, int p_ch, const View &Q, int q_ch, const
 
 hipError_t bias_grad(const View &G, int C, long n, fdc_unet *u, float *gb, hipStream_t s)
 {
-    const long per = 4096;
+    if (C % 8 || C > 64) return hipErrorInvalidValue;
+    const long per = 16384;                               // few partials: the finish is one small block
     const int nb = (int)((n + per - 1) / per);
-    hipLaunchKernelGGL(bias_part_kernel, dim3(nb), dim3(64, 4), 0, s, G.p, G.pitch, C, n, per, u->bpart);
+    hipLaunchKernelGGL(bias_part_kernel, dim3(nb), dim3(256), 0, s, G.p, G.pitch, C, n, per, u->bpart);
     hipLaunchKernelGGL(bias_finish_kernel, dim3(1), dim3(64), 0, s, u->bpart, nb, C, gb);
     return hipGetLastError();
 }
@@ -1025,7 +1147,7 @@ int fdc_unet_create(fdc_unet **out, int hip_device, int nx, int ny, int nz)
     u->wpart_n = (size_t)64 * 27 * 64 * 64;
     u->wpart = ualloc<float>(u, u->wpart_n);
     u->wsum = ualloc<float>(u, 27 * 64 * 64 + 256);
-    u->bpart = ualloc<float>(u, (size_t)((n0 + 4095) / 4096) * 64);
+    u->bpart = ualloc<float>(u, (size_t)((n0 + 16383) / 16384) * 64);
     u->hpart = ualloc<float>(u, (size_t)((n0 + 8191) / 8192) * 17);
     u->lpart = ualloc<double>(u, (size_t)((n0 + 8191) / 8192));
     u->loss = ualloc<double>(u, 1);
