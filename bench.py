@@ -61,6 +61,70 @@ def measured_traffic(launch):
     return float(fields["traffic_bytes_per_launch"])
 
 
+def extras(c, launch, log):
+    """Other rows of the path, timed live: the 1e8-history thorax plan (both
+    tallies, the slab's launch configuration) and the denoiser's forward pass
+    (256x256x128 volume) and training step (128^3 crop: forward, backward,
+    Adam), each the best of three after a warm-up."""
+    import numpy as np
+    import torch
+    from paper_1011_2188_amd import fdc as F
+    from paper_1011_2188_amd import workloads as W
+
+    def best(f, n=3):
+        f()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(n):
+            t = time.perf_counter()
+            f()
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t)
+        return min(ts)
+
+    out = {}
+    ph, sp, _ = W.thorax()
+    p = c.load_phantom(ph)
+    c.add_beam_spots(p, sp)
+    n = int(sp["n_histories"].sum())
+
+    def thorax_run():
+        c.reset_plan(p)
+        c.run_histories([p], F.FDC_RUN_VARIANCE)
+    t = best(thorax_run)
+    out["thorax_1e8"] = {"seconds": t, "histories_per_s": n / t, "launch": launch,
+                         "workload": "thorax 256x256x128 x 2 mm, 3 fields x 2000 spots, 1e8 histories, both tallies"}
+    log(f"thorax: {n / t:.4g} histories/s")
+    g = torch.Generator(device="cuda").manual_seed(0)
+    vol = (128, 256, 256)
+    net = F.UNet(vol)
+    net.init_params(1)
+    x = torch.rand((2,) + vol, device="cuda", generator=g)
+    y = torch.empty(vol, device="cuda")
+    tf = best(lambda: net.forward(x, y))
+    net.close()
+    crop = (128, 128, 128)
+    net = F.UNet(crop)
+    net.init_params(1)
+    xc = torch.rand((2,) + crop, device="cuda", generator=g)
+    tc = xc[0].clone()
+
+    def step():
+        net.backward(xc, tc, want_loss=False)
+        net.adam(1e-3)
+    ts = best(step)
+    net.close()
+    vox_f, vox_c = float(np.prod(vol)), float(np.prod(crop))
+    out["denoiser"] = {"forward_ms_256x256x128": tf * 1e3, "forward_tflops": 94_880 * vox_f / tf / 1e12,
+                       "train_step_ms_128cube": ts * 1e3, "train_tflops": 3 * 94_880 * vox_c / ts / 1e12,
+                       "peak_tflops_bf16": 2500.0,
+                       "seconds_to_2pct_denoised": None,
+                       "note": "denoised time to 2% at equal gamma pass rate: not reached (the plain method is "
+                               "faster on thorax-like plans; see profiles/denoiser_study_thorax.md)"}
+    log(f"denoiser: forward {tf * 1e3:.2f} ms, training step {ts * 1e3:.2f} ms")
+    return out
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -91,6 +155,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-variance", action="store_true", help="energy tally only")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip the thorax and denoiser timings")
     ap.add_argument("--launch", default="tune",
                     help="'tune' (autotune before the warm-up, untimed) or waves_per_block,blocks_per_cu,"
                          "tally_slots,units_per_wave[,tally_mode]")
@@ -202,6 +267,8 @@ def main():
                      "bytes_per_history": bph, "tally_updates_per_s": updates},
         **out,
     }
+    if not args.no_extras:
+        result["extras"] = extras(c, launch, log)
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample ...")
         result["cpu_baseline"] = cpu_baseline(ph, sp, db)

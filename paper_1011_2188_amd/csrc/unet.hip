@@ -687,13 +687,24 @@ __global__ void head_weights_kernel(const float *__restrict__ p, float *__restri
     if (c == 16) out[16] = p[16];
 }
 
-__global__ void bias_finish_kernel(const float *__restrict__ part, int nb, int C, float *__restrict__ gb)
+// gb[c] = sum over the nb partials; 256 threads: thread t sums channel t % C over
+// partials b = t / C, t / C + 256 / C, ... and the groups are added in a fixed
+// order (reproducible)
+__global__ void __launch_bounds__(256) bias_finish_kernel(const float *__restrict__ part, int nb, int C,
+                                                          float *__restrict__ gb)
 {
-    const int c = threadIdx.x;
-    if (c >= C) return;
+    __shared__ float red[256];
+    const int groups = 256 / C, c = threadIdx.x % C, j = threadIdx.x / C;
     float s = 0.f;
-    for (int b = 0; b < nb; ++b) s += part[b * C + c];
-    gb[c] = s;
+    if (j < groups)
+        for (int b = j; b < nb; b += groups) s += part[(long)b * C + c];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    if ((int)threadIdx.x < C) {
+        float t = 0.f;
+        for (int k = 0; k < groups; ++k) t += red[k * C + threadIdx.x];
+        gb[threadIdx.x] = t;
+    }
 }
 
 // ------------------------------------------------------------------ host --
@@ -871,10 +882,10 @@ hipError_t wgrad(int am, const View &P, int p_ch, const View &Q, int q_ch, const
 hipError_t bias_grad(const View &G, int C, long n, fdc_unet *u, float *gb, hipStream_t s)
 {
     if (C % 8 || C > 64) return hipErrorInvalidValue;
-    const long per = 16384;                               // few partials: the finish is one small block
+    const long per = 4096;
     const int nb = (int)((n + per - 1) / per);
     hipLaunchKernelGGL(bias_part_kernel, dim3(nb), dim3(256), 0, s, G.p, G.pitch, C, n, per, u->bpart);
-    hipLaunchKernelGGL(bias_finish_kernel, dim3(1), dim3(64), 0, s, u->bpart, nb, C, gb);
+    hipLaunchKernelGGL(bias_finish_kernel, dim3(1), dim3(256), 0, s, u->bpart, nb, C, gb);
     return hipGetLastError();
 }
 
@@ -1147,7 +1158,7 @@ int fdc_unet_create(fdc_unet **out, int hip_device, int nx, int ny, int nz)
     u->wpart_n = (size_t)64 * 27 * 64 * 64;
     u->wpart = ualloc<float>(u, u->wpart_n);
     u->wsum = ualloc<float>(u, 27 * 64 * 64 + 256);
-    u->bpart = ualloc<float>(u, (size_t)((n0 + 16383) / 16384) * 64);
+    u->bpart = ualloc<float>(u, (size_t)((n0 + 4095) / 4096) * 64);
     u->hpart = ualloc<float>(u, (size_t)((n0 + 8191) / 8192) * 17);
     u->lpart = ualloc<double>(u, (size_t)((n0 + 8191) / 8192));
     u->loss = ualloc<double>(u, 1);
