@@ -290,20 +290,83 @@ def test_edge_cases():
 
 
 # ------------------------------------------------------ full-size checks ----
-def test_full_size_slab_sampled():
-    """The 1e7-history slab workload in the benchmark's launch configuration:
-    energy identity exactly, sampled end points against the oracle."""
+BENCH_LAUNCH = dict(waves_per_block=16, blocks_per_cu=1, tally_slots=8064, units_per_wave=1, tally_mode=1)
+
+
+def test_full_size_slab_dose_vs_oracle():
+    """The 1e7-history slab workload in the benchmark's launch configuration
+    (LDS write-back cache): dose and Eq. (2) variance against the oracle run
+    on the same 1e7 histories, energy identity exactly, incident energy equal
+    to the oracle's, the tallies bitwise equal to the plain global-atomic
+    launch, and sampled end points."""
     ph, sp, db = W.slab()
-    c = ctx_for(db, waves_per_block=4, blocks_per_cu=0)
-    g = gpu_run(c, ph, sp, flags=0)
+    c = ctx_for(db, **BENCH_LAUNCH)
+    g = gpu_run(c, ph, sp)
     assert g["n_histories"] == 10_000_000
     assert g["deposited"] + g["escaped"] == g["incident"]
+    ref = gpu_run(ctx_for(db, waves_per_block=4), ph, sp)
+    assert np.array_equal(g["E"], ref["E"]) and np.array_equal(g["E2"], ref["E2"])
+    o = O.replay(db, ph, sp, seed=SEED)
+    assert g["incident"] == o["incident"]
+    dose_o, var_o = check_dose(g, o, ph, 10_000_000)
+    sel = dose_o > 0.5 * dose_o.max()
+    rel = np.abs(np.sqrt(g["var"][sel]) - np.sqrt(var_o[sel])) / np.sqrt(var_o[sel])
+    assert np.median(rel) < 0.01
     tot = good = 0
     for s in range(0, 25, 2):
         ok, n = check_endpoints(c, g["plan"], db, ph, sp, s, 400_000 - 96, 96)
         good += ok
         tot += n
     assert good >= 0.999 * tot
+
+
+def test_full_size_thorax_sampled():
+    """The 1e8-history thorax workload in the benchmark's launch configuration:
+    tallies bitwise equal to the global-atomic launch, energy identity, and
+    sampled end points (with track rotation off, as the workload runs)."""
+    ph, sp, db = W.thorax()
+    c = ctx_for(db, **BENCH_LAUNCH)
+    g = gpu_run(c, ph, sp)
+    assert g["n_histories"] == int(sp["n_histories"].sum())
+    assert g["deposited"] + g["escaped"] == g["incident"]
+    ref = gpu_run(ctx_for(db, waves_per_block=4, blocks_per_cu=4), ph, sp)
+    assert np.array_equal(g["E"], ref["E"]) and np.array_equal(g["E2"], ref["E2"])
+    tot = good = 0
+    for s in range(0, len(sp), 500):
+        n0 = int(sp["n_histories"][s])
+        ok, n = check_endpoints(c, g["plan"], db, ph, sp, s, n0 - 64, 64)
+        good += ok
+        tot += n
+    assert good >= 0.999 * tot
+
+
+def test_batched_graph_full_size():
+    """The 64-plan batched workload (1.6e8 histories) as one captured graph
+    launch in the benchmark's launch configuration equals separate eager runs
+    of each plan with global atomics, plan by plan, bitwise; every plan keeps
+    the energy identity."""
+    plans = W.batched_plans(64)
+    db = W.multi_bin_db()
+    cg = ctx_for(db, **BENCH_LAUNCH)
+    ce = ctx_for(db, waves_per_block=4)
+    ig, ie = [], []
+    for ph, sp in plans:
+        for c, ids in ((cg, ig), (ce, ie)):
+            p = c.load_phantom(ph)
+            c.add_beam_spots(p, sp)
+            ids.append(p)
+    gr = cg.graph_create(ig, F.FDC_RUN_VARIANCE, reset=True)
+    gr.launch()
+    torch.cuda.synchronize()
+    for p in ie:
+        ce.run_histories([p], F.FDC_RUN_VARIANCE)
+    for a, b, (ph, sp) in zip(ig, ie, plans):
+        ra = cg.read_dose_and_variance(a, dose=False, var=False, raw=True)
+        rb = ce.read_dose_and_variance(b, dose=False, var=False, raw=True)
+        assert ra["n_histories"] == rb["n_histories"] == int(sp["n_histories"].sum())
+        assert ra["deposited"] + ra["escaped"] == ra["incident"] == rb["incident"]
+        assert np.array_equal(ra["E"], rb["E"]) and np.array_equal(ra["E2"], rb["E2"])
+    gr.close()
 
 
 # ---------------------------------------------------------------- graphs ----
