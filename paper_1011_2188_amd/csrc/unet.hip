@@ -337,20 +337,11 @@ __global__ void __launch_bounds__(256) wgrad_kernel(const u16 *__restrict__ P, i
     }
 }
 
-// Weight gradient of a 3x3x3 convolution with the gfx950 LDS transpose read.
-// part[slab][o][i][j] = sum over the slab's rows r of P[r][i] * Q[src(r, o)][j],
-// o = (dz*3 + dy)*3 + dx, src = the voxel shifted by (dx-1, dy-1, dz-1), zero
-// outside the grid.  A block owns one (dz, dy) pair and a slab of rows; per
-// chunk of kCh rows it stages P rows and the (dz, dy)-shifted Q rows with a
-// one-row halo (row-major, 16-byte copies), then serves all three dx shifts
-// from the same Q window: dx only moves the start row, and the x-row
-// boundary (where a dx shift would wrap into the neighbouring x row) is a
-// per-row zero mask on the P fragment.  MFMA operands are read with
-// ds_read_b64_tr_b16: within a 16-lane group, lane r addresses row R + r/4,
+// MFMA operands from row-major LDS tiles with the gfx950 LDS transpose read
+// (ds_read_b64_tr_b16): within a 16-lane group, lane r addresses row R + r/4,
 // channels c0 + 4 (r%4) .. +3, and lane i receives rows R..R+3 of channel
 // c0 + i - four consecutive contraction elements, as the 16x16x32 bf16 MFMA
 // operands want them (two reads give the lane's eight).
-constexpr int kCh = 128;
 
 typedef short v4s __attribute__((ext_vector_type(4)));
 typedef __attribute__((address_space(3))) v4s lds_v4s;
@@ -368,81 +359,75 @@ __device__ inline bf16x8 tr_frag(const u16 *tile, int pitch, int row, int col)
     return __builtin_bit_cast(bf16x8, c);
 }
 
-__global__ void __launch_bounds__(256) wgrad3_kernel(const u16 *__restrict__ P, int p_pitch, int p_ch,
-                                                     const u16 *__restrict__ Q, int q_pitch, int q_ch, Grid g,
-                                                     long rows_per_slab, float *__restrict__ part, int pc, int qc,
-                                                     int wpb)
+// Weight gradient of a 3x3x3 convolution over 3D tiles.  A block loops over
+// tiles of 16 (x) x TY x TZ voxels (tile t = blockIdx.x + k * gridDim.x) and
+// owns the taps og * G .. og * G + G - 1 (og = blockIdx.y).  Per tile it stages
+// the output gradient P of the tile and the input Q of the tile plus a
+// one-voxel halo (row-major, 16-byte copies); the contraction runs over the
+// tile's voxels in x-fastest order, 32 at a time.  Eight consecutive
+// contraction voxels are 8 consecutive x of one row, and for every tap their
+// shifted neighbours are 8 consecutive halo rows, so both MFMA operands come
+// straight from ds_read_b64_tr_b16 with no boundary masks (the halo holds the
+// zeros).  Accumulators stay in registers across the block's tiles;
+// part[blockIdx.x][o][i][j] receives the block's sums.
+template <int TY, int TZ>
+__global__ void __launch_bounds__(256) wgrad3t_kernel(const u16 *__restrict__ P, int p_pitch, int p_ch,
+                                                      const u16 *__restrict__ Q, int q_pitch, int q_ch, Grid g,
+                                                      float *__restrict__ part, int pc, int qc, int G)
 {
-    // wpb (1, 3 or 9) consecutive (dz, dy) windows per block: narrow layers
-    // take more windows so that a staged P chunk feeds more MFMAs
+    constexpr int TX = 16, HX = TX + 2, HY = TY + 2, HZ = TZ + 2, TV = TX * TY * TZ;
     extern __shared__ __attribute__((aligned(16))) u16 lds[];
-    const int sp_pitch = pc + 8, sq_pitch = qc + 8;      // 16-byte aligned rows, skewed banks
-    const int sq_size = (kCh + 2) * sq_pitch;
+    const int sp_pitch = pc + 8, sq_pitch = qc + 8;
     u16 *sP = lds;
-    u16 *sQ = lds + kCh * sp_pitch;
-    const int win0 = blockIdx.x * wpb;
-    const int slab = blockIdx.y;
-    const long n_rows = (long)g.nx * g.ny * g.nz;
-    const long r_begin = (long)slab * rows_per_slab;
-    const long r_end = std::min<long>(n_rows, r_begin + rows_per_slab);
+    u16 *sQ = lds + TV * sp_pitch;
+    const int tiles_x = (g.nx + TX - 1) / TX, tiles_y = (g.ny + TY - 1) / TY, tiles_z = (g.nz + TZ - 1) / TZ;
+    const int n_tiles_grid = tiles_x * tiles_y * tiles_z;
+    const int o0 = blockIdx.y * G;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int lg = lane >> 4;
-    const int tiles_j = qc / 16, n_tiles = (pc / 16) * tiles_j;
-    const int n_acc = 3 * wpb * n_tiles;                 // <= 48 (the host picks wpb)
+    const int tiles_j = qc / 16, n_ct = (pc / 16) * tiles_j;   // channel tiles
+    const int n_acc = G * n_ct;                                // <= 48 (the host picks G)
     const int pcg = pc / 8, qcg = qc / 8;
-    constexpr int kMaxAcc = 12;                           // 48 tiles / 4 waves
+    constexpr int kMaxAcc = 12;
     f32x4 acc[kMaxAcc];
 #pragma unroll
     for (int q = 0; q < kMaxAcc; ++q) acc[q] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-    for (long r0 = r_begin; r0 < r_end; r0 += kCh) {
-        // stage P rows r0 .. r0+kCh-1 and, per window, the shifted Q rows r0-1 .. r0+kCh
-        for (int t = threadIdx.x; t < kCh * pcg; t += blockDim.x) {
-            const int rr = t / pcg, cg = t % pcg;
-            const long r = r0 + rr;
+    for (int t = blockIdx.x; t < n_tiles_grid; t += gridDim.x) {
+        const int bx = t % tiles_x, by = (t / tiles_x) % tiles_y, bz = t / (tiles_x * tiles_y);
+        const int x0 = bx * TX, y0 = by * TY, z0 = bz * TZ;
+        for (int u = threadIdx.x; u < TV * pcg; u += blockDim.x) {
+            const int k = u / pcg, cg = u - k * pcg;
+            const int x = x0 + k % TX, y = y0 + (k / TX) % TY, z = z0 + k / (TX * TY);
             uint4 v = make_uint4(0, 0, 0, 0);
-            if (r < r_end && 8 * cg < p_ch) v = *(const uint4 *)(P + r * p_pitch + 8 * cg);
-            *(uint4 *)(sP + rr * sp_pitch + 8 * cg) = v;
+            if (x < g.nx && y < g.ny && z < g.nz && 8 * cg < p_ch)
+                v = *(const uint4 *)(P + (((long)z * g.ny + y) * g.nx + x) * p_pitch + 8 * cg);
+            *(uint4 *)(sP + k * sp_pitch + 8 * cg) = v;
         }
-        for (int t = threadIdx.x; t < wpb * (kCh + 2) * qcg; t += blockDim.x) {
-            const int wi = t / ((kCh + 2) * qcg), rem = t % ((kCh + 2) * qcg);
-            const int ss = rem / qcg, cg = rem % qcg;
-            const int win = win0 + wi, dz = win / 3 - 1, dy = win % 3 - 1;
-            const int v = (int)r0 - 1 + ss;               // grids hold < 2^31 voxels
-            uint4 w = make_uint4(0, 0, 0, 0);
-            if (v >= 0 && v < (int)n_rows && 8 * cg < q_ch) {
-                const uint32_t xy = (uint32_t)v / (uint32_t)g.nx;
-                const int x = v - (int)xy * g.nx;
-                const uint32_t z = xy / (uint32_t)g.ny;
-                const int yy = (int)(xy - z * (uint32_t)g.ny) + dy, zz = (int)z + dz;
-                if (yy >= 0 && yy < g.ny && zz >= 0 && zz < g.nz)
-                    w = *(const uint4 *)(Q + ((long)(zz * g.ny + yy) * g.nx + x) * q_pitch + 8 * cg);
-            }
-            *(uint4 *)(sQ + wi * sq_size + ss * sq_pitch + 8 * cg) = w;
+        for (int u = threadIdx.x; u < HZ * HY * HX * qcg; u += blockDim.x) {
+            const int h = u / qcg, cg = u - h * qcg;
+            const int x = x0 - 1 + h % HX, y = y0 - 1 + (h / HX) % HY, z = z0 - 1 + h / (HX * HY);
+            uint4 v = make_uint4(0, 0, 0, 0);
+            if (x >= 0 && x < g.nx && y >= 0 && y < g.ny && z >= 0 && z < g.nz && 8 * cg < q_ch)
+                v = *(const uint4 *)(Q + (((long)z * g.ny + y) * g.nx + x) * q_pitch + 8 * cg);
+            *(uint4 *)(sQ + h * sq_pitch + 8 * cg) = v;
         }
         __syncthreads();
-#pragma unroll
-        for (int kb = 0; kb < kCh / 32; ++kb) {
-            // x of the lane's first contraction row (row r0 + 32 kb + 8 lg)
-            const int x0 = (int)((uint32_t)(r0 + 32 * kb + 8 * lg) % (uint32_t)g.nx);
+#pragma unroll 1
+        for (int kb = 0; kb < TV / 32; ++kb) {
+            // the lane group's 8 contraction voxels: x = 8 (lg % 2) .. +7 of tile row (y, z)
+            const int k0 = 32 * kb + 8 * lg;
+            const int xr = k0 % TX, yr = (k0 / TX) % TY, zr = k0 / (TX * TY);
 #pragma unroll
             for (int q = 0; q < kMaxAcc; ++q) {
                 const int T = wave + 4 * q;
                 if (T < n_acc) {
-                    const int wdx = T / n_tiles, tile = T % n_tiles;   // wdx = 3 * window + dx index
-                    const int wi = wdx / 3, dx = wdx % 3 - 1;
-                    const int ti = tile / tiles_j, tj = tile % tiles_j;
-                    bf16x8 a = tr_frag(sP, sp_pitch, 32 * kb + 8 * lg, 16 * ti);
-                    if (dx != 0) {                        // zero rows whose x + dx leaves the grid
-                        int x = x0;
-#pragma unroll
-                        for (int e = 0; e < 8; ++e) {
-                            const int xs = x + dx;
-                            if (xs < 0 || xs >= g.nx) a[e] = (__bf16)0.f;
-                            x = (x + 1 == g.nx) ? 0 : x + 1;
-                        }
-                    }
-                    const bf16x8 b = tr_frag(sQ + wi * sq_size, sq_pitch, 1 + dx + 32 * kb + 8 * lg, 16 * tj);
+                    const int o = o0 + T / n_ct, ct = T % n_ct;
+                    const int ti = ct / tiles_j, tj = ct % tiles_j;
+                    const int dz = o / 9, dy = (o / 3) % 3, dx = o % 3;     // halo shift = tap
+                    const bf16x8 a = tr_frag(sP, sp_pitch, k0, 16 * ti);
+                    const int hrow = ((zr + dz) * HY + (yr + dy)) * HX + (xr + dx);
+                    const bf16x8 b = tr_frag(sQ, sq_pitch, hrow, 16 * tj);
                     acc[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[q], 0, 0, 0);
                 }
             }
@@ -454,24 +439,35 @@ __global__ void __launch_bounds__(256) wgrad3_kernel(const u16 *__restrict__ P, 
     for (int q = 0; q < kMaxAcc; ++q) {
         const int T = wave + 4 * q;
         if (T >= n_acc) continue;
-        const int wdx = T / n_tiles, tile = T % n_tiles;
-        const int ti = tile / tiles_j, tj = tile % tiles_j;
-        const int o = win0 * 3 + wdx;                     // (dz, dy, dx) offset index
+        const int o = o0 + T / n_ct, ct = T % n_ct;
+        const int ti = ct / tiles_j, tj = ct % tiles_j;
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
             const int i = 16 * ti + 4 * lg + e, j = 16 * tj + li;
-            part[(((long)slab * 27 + o) * pc + i) * qc + j] = acc[q][e];
+            part[(((long)blockIdx.x * 27 + o) * pc + i) * qc + j] = acc[q][e];
         }
     }
 }
 
-// sum the slabs in a fixed order: out[(o, i, j)] = sum_s part[s][o][i][j]
-__global__ void slab_sum_kernel(const float *__restrict__ part, int slabs, long per_slab, float *__restrict__ out)
+// sum the slabs in a fixed order: out[(o, i, j)] = sum_s part[s][o][i][j].
+// Block = 64 elements x 8 waves: wave w adds slabs w, w + 8, ... (coalesced rows),
+// then the 8 partial sums are added in wave order (reproducible).
+__global__ void __launch_bounds__(512) slab_sum_kernel(const float *__restrict__ part, int slabs, long per_slab,
+                                                       float *__restrict__ out)
 {
-    for (long x = blockIdx.x * (long)blockDim.x + threadIdx.x; x < per_slab; x += (long)gridDim.x * blockDim.x) {
-        float s = 0.f;
-        for (int k = 0; k < slabs; ++k) s += part[k * per_slab + x];
-        out[x] = s;
+    __shared__ float red[8][64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const long x = blockIdx.x * 64L + lane;
+    float s = 0.f;
+    if (x < per_slab)
+        for (int k = w; k < slabs; k += 8) s += part[k * per_slab + x];
+    red[w][lane] = s;
+    __syncthreads();
+    if (w == 0 && x < per_slab) {
+        float t = 0.f;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) t += red[k][lane];
+        out[x] = t;
     }
 }
 
@@ -853,26 +849,30 @@ hipError_t wgrad(int am, const View &P, int p_ch, const View &Q, int q_ch, const
     const size_t need = (size_t)slabs * n_off * pc * qc;
     if (need > u->wpart_n) return hipErrorInvalidValue;
     if (am == A_CONV3) {
-        // slabs of whole staging chunks; as many as the partial-sum buffer
-        // holds (small layers get more blocks), at least 4 chunks each
-        const int n_tiles = (pc / 16) * (qc / 16);
-        const int wpb = 3 * 9 * n_tiles <= 48 ? 9 : (3 * 3 * n_tiles <= 48 ? 3 : 1);
-        const long cap = std::min<long>((long)(u->wpart_n / ((size_t)n_off * pc * qc)), 256);
-        slabs = std::max<long>(1, std::min<long>(cap, rows / (4 * kCh)));
-        per = (rows + slabs - 1) / slabs;
-        per = (per + kCh - 1) / kCh * kCh;
-        slabs = (rows + per - 1) / per;
-        const size_t lds = ((size_t)kCh * (pc + 8) + (size_t)wpb * (kCh + 2) * (qc + 8)) * sizeof(u16);
-        hipLaunchKernelGGL(wgrad3_kernel, dim3(9 / wpb, (uint32_t)slabs), dim3(256), lds, s, P.p, P.pitch, p_ch,
-                           Q.p, Q.pitch, q_ch, g, per, u->wpart, pc, qc, wpb);
+        // 3D tiles: 16 x 4 x 4 voxels for 16-channel operands, 16 x 4 x 2 for 32,
+        // 16 x 2 x 2 for 64 (tile and halo under 64 KB of LDS); taps per block G
+        // so that G x channel tiles <= 48 accumulators
+        const int cmax = std::max(pc, qc);
+        const int ty = cmax <= 32 ? 4 : 2, tz = cmax <= 16 ? 4 : 2;
+        const int n_ct = (pc / 16) * (qc / 16);
+        const int G = 27 * n_ct <= 48 ? 27 : (9 * n_ct <= 48 ? 9 : 3);
+        const long tiles = ((g.nx + 15) / 16) * (long)((g.ny + ty - 1) / ty) * ((g.nz + tz - 1) / tz);
+        const long cap = (long)(u->wpart_n / ((size_t)27 * pc * qc));
+        slabs = std::max<long>(1, std::min<long>({tiles, cap, 2048L / (27 / G)}));
+        const size_t lds = ((size_t)16 * ty * tz * (pc + 8) + (size_t)18 * (ty + 2) * (tz + 2) * (qc + 8)) * sizeof(u16);
+        const dim3 grid((uint32_t)slabs, (uint32_t)(27 / G));
+#define WT(TY_, TZ_) hipLaunchKernelGGL((wgrad3t_kernel<TY_, TZ_>), grid, dim3(256), lds, s, P.p, P.pitch, p_ch, \
+                                        Q.p, Q.pitch, q_ch, g, u->wpart, pc, qc, G)
+        if (ty == 4 && tz == 4) WT(4, 4); else if (ty == 4) WT(4, 2); else WT(2, 2);
+#undef WT
     } else
         hipLaunchKernelGGL((wgrad_kernel<A_S2D>), dim3(n_off, (uint32_t)slabs), dim3(256), 0, s, P.p, P.pitch, p_ch,
                            Q.p, Q.pitch, q_ch, g, per, u->wpart, pc, qc);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const long per_slab = (long)n_off * pc * qc;
-    hipLaunchKernelGGL(slab_sum_kernel, dim3(blocks_for(per_slab)), dim3(256), 0, s, u->wpart, (int)slabs, per_slab,
-                       u->wsum);
+    hipLaunchKernelGGL(slab_sum_kernel, dim3((uint32_t)((per_slab + 63) / 64)), dim3(512), 0, s, u->wpart, (int)slabs,
+                       per_slab, u->wsum);
     hipLaunchKernelGGL(scatter_wgrad_kernel, dim3(blocks_for((long)n_off * ni * nj)), dim3(256), 0, s, u->wsum, n_off,
                        pc, qc, ni, nj, gw_out);
     (void)transposed_layer;
