@@ -176,6 +176,29 @@ __global__ void __launch_bounds__(256) igemm_kernel(const u16 *__restrict__ src,
 // is the 16 voxels of x at y = m.  K = 27 taps x cpad channels, in steps of 32
 // (lane group lg takes 8 channels of tap (k0 + 8 lg) / cpad).  Weights (the
 // B operand) come from the packed table in global memory, as in igemm.
+// Copy `total` 16-byte items into LDS, B per thread in flight: all loads of a
+// batch are issued before its stores (a load followed by its own store would
+// serialise the global round trips).  src(t): global address or null (zeros);
+// dst(t): LDS address.
+template <int B, class Src, class Dst>
+__device__ inline void stage16(int total, Src src, Dst dst)
+{
+    for (int t0 = threadIdx.x; t0 < total; t0 += B * (int)blockDim.x) {
+        uint4 v[B];
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            const int t = t0 + b * (int)blockDim.x;
+            const u16 *p = t < total ? src(t) : nullptr;
+            v[b] = p ? *(const uint4 *)p : make_uint4(0, 0, 0, 0);
+        }
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            const int t = t0 + b * (int)blockDim.x;
+            if (t < total) *(uint4 *)dst(t) = v[b];
+        }
+    }
+}
+
 template <int NT, int TY>
 __global__ void __launch_bounds__(256) conv3_kernel(const u16 *__restrict__ src, int src_pitch, int cpad, int cshift,
                                                     Grid g, const u16 *__restrict__ wpk, int kpad, int n_cols,
@@ -185,48 +208,80 @@ __global__ void __launch_bounds__(256) conv3_kernel(const u16 *__restrict__ src,
 {
     constexpr int TX = 16, TZ = 4, HX = TX + 2, HY = TY + 2, HZ = TZ + 2;
     extern __shared__ __attribute__((aligned(16))) u16 sh[];
+    __shared__ int s_tap[27];                              // halo-row offset of each tap
     const int hp = cpad + 8;                               // LDS channel pitch (16-byte rows, skewed banks)
     const int tiles_x = (g.nx + TX - 1) / TX, tiles_y = (g.ny + TY - 1) / TY;
     const int bx = blockIdx.x % tiles_x, by = (blockIdx.x / tiles_x) % tiles_y, bz = blockIdx.x / (tiles_x * tiles_y);
     const int x0 = bx * TX, y0 = by * TY, z0 = bz * TZ;
     const int n_base = blockIdx.y * 16 * NT;
-    const int cg_n = cpad / 8;
-    for (int t = threadIdx.x; t < HZ * HY * HX * cg_n; t += blockDim.x) {
-        const int h = t / cg_n, cg = t - h * cg_n;
-        const int hx = h % HX, hy = (h / HX) % HY, hz = h / (HX * HY);
-        const int x = x0 - 1 + hx, y = y0 - 1 + hy, z = z0 - 1 + hz;
-        uint4 v = make_uint4(0, 0, 0, 0);
-        if (x >= 0 && x < g.nx && y >= 0 && y < g.ny && z >= 0 && z < g.nz)
-            v = *(const uint4 *)(src + (((long)z * g.ny + y) * g.nx + x) * src_pitch + 8 * cg);
-        *(uint4 *)(sh + h * hp + 8 * cg) = v;
+    const int gshift = cshift - 3;                         // cpad / 8 = 1 << gshift channel groups
+    if (threadIdx.x < 27) {
+        const int o = threadIdx.x;
+        s_tap[o] = ((o / 9) * HY + (o / 3) % 3) * HX + o % 3;
     }
+    stage16<8>((HZ * HY * HX) << gshift,
+            [&](int t) -> const u16 * {
+                const int h = t >> gshift, cg = t & ((1 << gshift) - 1);
+                const int x = x0 - 1 + h % HX, y = y0 - 1 + (h / HX) % HY, z = z0 - 1 + h / (HX * HY);
+                if (x < 0 || x >= g.nx || y < 0 || y >= g.ny || z < 0 || z >= g.nz) return nullptr;
+                return src + (((long)z * g.ny + y) * g.nx + x) * src_pitch + 8 * cg;
+            },
+            [&](int t) { return sh + (t >> gshift) * hp + 8 * (t & ((1 << gshift) - 1)); });
     __syncthreads();
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int li = lane & 15, lg = lane >> 4;
     const int kvalid = 27 * cpad;
+    // element offset of this lane's row in each m tile at tap 0
+    int base[TY];
+#pragma unroll
+    for (int m = 0; m < TY; ++m) base[m] = ((w * HY + m) * HX + li) * hp;
     f32x4 acc[TY][NT];
 #pragma unroll
     for (int m = 0; m < TY; ++m)
 #pragma unroll
         for (int t = 0; t < NT; ++t) acc[m][t] = f32x4{0.f, 0.f, 0.f, 0.f};
-    for (int k0 = 0; k0 < kpad; k0 += 32) {
-        const int k = k0 + 8 * lg;
-        const bool kv = k < kvalid;
-        const int o = k >> cshift, c = k - (o << cshift);
-        const int dz = o / 9, dy = (o / 3) % 3, dx = o % 3;   // halo coordinates are shifted by +1
-        bf16x8 b[NT];
+    const u16 *wrow[NT];
+    bool wok[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        const int n = n_base + 16 * t + li;
+        wok[t] = n < n_cols;
+        wrow[t] = wpk + (long)(wok[t] ? n : 0) * kpad;
+    }
+    // weight fragments of K step k (zero past the valid K or columns); loads are
+    // unconditional from a clamped address so that they issue together
+    auto load_w = [&](bf16x8 *b, int k) {
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
-            const int n = n_base + 16 * t + li;
-            b[t] = (kv && n < n_cols) ? load8(wpk + (long)n * kpad + k) : zero8();
+            const bf16x8 v = load8(wrow[t] + min(k, kpad - 8));
+            b[t] = (wok[t] && k < kvalid) ? v : zero8();
         }
+    };
+    // one K step: all A reads first, then the MFMAs
+    auto kstep = [&](const bf16x8 *b, int k) {
+        const bool kv = k < kvalid;
+        const int o = kv ? k >> cshift : 0;
+        const int off = s_tap[o] * hp + (kv ? k - (o << cshift) : 0);
+        bf16x8 a[TY];
+#pragma unroll
+        for (int m = 0; m < TY; ++m) a[m] = load8(sh + base[m] + off);
 #pragma unroll
         for (int m = 0; m < TY; ++m) {
-            const int h = ((w + dz) * HY + (m + dy)) * HX + (li + dx);
-            const bf16x8 a = kv ? load8(sh + h * hp + c) : zero8();
+            const bf16x8 am = kv ? a[m] : zero8();
 #pragma unroll
-            for (int t = 0; t < NT; ++t) acc[m][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[t], acc[m][t], 0, 0, 0);
+            for (int t = 0; t < NT; ++t) acc[m][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am, b[t], acc[m][t], 0, 0, 0);
         }
+    };
+    // K loop, two steps per turn with two weight buffers (the next step's
+    // weights load while this step computes)
+    bf16x8 b0[NT], b1[NT];
+    load_w(b0, 8 * lg);
+    for (int k0 = 0; k0 < kpad; k0 += 64) {
+        load_w(b1, k0 + 32 + 8 * lg);
+        kstep(b0, k0 + 8 * lg);
+        if (k0 + 32 >= kpad) break;
+        load_w(b0, k0 + 64 + 8 * lg);
+        kstep(b1, k0 + 32 + 8 * lg);
     }
     // epilogue: lane holds D[4 lg + e][li] of every (m, t) tile: voxel x = x0 + 4 lg + e
     const int z = z0 + w;
@@ -396,22 +451,22 @@ __global__ void __launch_bounds__(256) wgrad3t_kernel(const u16 *__restrict__ P,
     for (int t = blockIdx.x; t < n_tiles_grid; t += gridDim.x) {
         const int bx = t % tiles_x, by = (t / tiles_x) % tiles_y, bz = t / (tiles_x * tiles_y);
         const int x0 = bx * TX, y0 = by * TY, z0 = bz * TZ;
-        for (int u = threadIdx.x; u < TV * pcg; u += blockDim.x) {
-            const int k = u / pcg, cg = u - k * pcg;
-            const int x = x0 + k % TX, y = y0 + (k / TX) % TY, z = z0 + k / (TX * TY);
-            uint4 v = make_uint4(0, 0, 0, 0);
-            if (x < g.nx && y < g.ny && z < g.nz && 8 * cg < p_ch)
-                v = *(const uint4 *)(P + (((long)z * g.ny + y) * g.nx + x) * p_pitch + 8 * cg);
-            *(uint4 *)(sP + k * sp_pitch + 8 * cg) = v;
-        }
-        for (int u = threadIdx.x; u < HZ * HY * HX * qcg; u += blockDim.x) {
-            const int h = u / qcg, cg = u - h * qcg;
-            const int x = x0 - 1 + h % HX, y = y0 - 1 + (h / HX) % HY, z = z0 - 1 + h / (HX * HY);
-            uint4 v = make_uint4(0, 0, 0, 0);
-            if (x >= 0 && x < g.nx && y >= 0 && y < g.ny && z >= 0 && z < g.nz && 8 * cg < q_ch)
-                v = *(const uint4 *)(Q + (((long)z * g.ny + y) * g.nx + x) * q_pitch + 8 * cg);
-            *(uint4 *)(sQ + h * sq_pitch + 8 * cg) = v;
-        }
+        stage16<4>(TV * pcg,
+                [&](int u) -> const u16 * {
+                    const int k = u / pcg, cg = u - k * pcg;
+                    const int x = x0 + k % TX, y = y0 + (k / TX) % TY, z = z0 + k / (TX * TY);
+                    if (x >= g.nx || y >= g.ny || z >= g.nz || 8 * cg >= p_ch) return nullptr;
+                    return P + (((long)z * g.ny + y) * g.nx + x) * p_pitch + 8 * cg;
+                },
+                [&](int u) { return sP + (u / pcg) * sp_pitch + 8 * (u % pcg); });
+        stage16<4>(HZ * HY * HX * qcg,
+                [&](int u) -> const u16 * {
+                    const int h = u / qcg, cg = u - h * qcg;
+                    const int x = x0 - 1 + h % HX, y = y0 - 1 + (h / HX) % HY, z = z0 - 1 + h / (HX * HY);
+                    if (x < 0 || x >= g.nx || y < 0 || y >= g.ny || z < 0 || z >= g.nz || 8 * cg >= q_ch) return nullptr;
+                    return Q + (((long)z * g.ny + y) * g.nx + x) * q_pitch + 8 * cg;
+                },
+                [&](int u) { return sQ + (u / qcg) * sq_pitch + 8 * (u % qcg); });
         __syncthreads();
 #pragma unroll 1
         for (int kb = 0; kb < TV / 32; ++kb) {
