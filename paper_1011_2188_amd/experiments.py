@@ -110,7 +110,8 @@ def batched(db, log=print, hist_scale=1.0):
 
 def denoiser_study(db, n_train=128, n_test=6, shape=(256, 256, 128), voxel_cm=0.2, per_pass=1_000_000,
                    high_passes=100, crop=(128, 128, 128), steps=6000, lr=1e-3, log=print, levels=(1, 2, 4),
-                   launch=dict(waves_per_block=16, blocks_per_cu=1, tally_slots=8064, units_per_wave=1, tally_mode=1)):
+                   launch=dict(waves_per_block=16, blocks_per_cu=1, tally_slots=8064, units_per_wave=1, tally_mode=1),
+                   step_passes=2):
     """Plain vs denoised seconds to 2% at equal gamma pass rate (2%/2 mm).
 
     Training pairs: k passes (per_pass histories each, k in `levels`) as input,
@@ -118,7 +119,8 @@ def denoiser_study(db, n_train=128, n_test=6, shape=(256, 256, 128), voxel_cm=0.
     the Eq. (2) mean uncertainty of one pass; the plain dose at N_2% and its
     gamma pass rate G* against an independent reference of
     4 * N_2% + high_passes * per_pass histories; the denoised dose at k passes,
-    k = 1, 2, 4, ... up to the passes of N_2%, until its pass rate reaches G*.
+    k = 1, 2, 4, ... (or 1, 2, 3, ... with step_passes=1) up to the passes of
+    N_2%, until its pass rate reaches G*.
     Times = histories / the measured transport rate (+ inference)."""
     import torch
     sim = D.Simulator(db, seed=7, rotate=True, launch=launch)
@@ -173,7 +175,7 @@ def denoiser_study(db, n_train=128, n_test=6, shape=(256, 256, 128), voxel_cm=0.
             if g >= g_star:
                 best = (k * per_pass, g, t_inf)
                 break
-            k *= 2
+            k = k + 1 if step_passes == 1 else k * 2
         row = {"plan": int(p), "u_one_pass": u1, "N_2pct": n2, "passes_2pct": passes_2, "G_star": g_star,
                "t_plain_s": passes_2 * per_pass / rate, "tried_passes_gamma_denoised_plain": tried,
                "N_denoised": best[0] if best else None, "G_denoised": best[1] if best else None,
