@@ -357,30 +357,23 @@ __host__ __device__ void replay_history(const TransportArgs &a, const DevSpot &s
             const bool out = (unsigned)ni >= (unsigned)n_ax;
             const uint32_t vn = d_ax > 0.f ? L.v + st_ax : L.v - st_ax;
             const uint16_t idx_n = load_global(vidx, out ? L.v : vn);
-            float move = tmin;
-            bool cross = true;
-            if (m.x != 0.f) {                      // material: consume WEL
-                const float rem = w_tot - tau;
-                const float wb = tmin * m.x;
-                float w_v, tau_n;
-                if (rem <= wb) {
-                    w_v = rem;
-                    tau_n = w_tot;
-                    move = rem * fast_rcp(m.x);
-                    cross = (rem == wb);
-                } else {
-                    w_v = wb;
-                    tau_n = tau + wb;
-                }
-                int cumk = e32;
-                if (tau_n < w_tot) cumk = min(e32, (int)rintf(ef * (tau_n * inv_w)));
-                const int piece = cumk - dep;
-                dep = cumk;
-                acc += piece;
-                hdep += piece;
-                g2 += w_v * m.y;
-                tau = tau_n;
-            }
+            // consume WEL in this voxel: up to the face (wb) or the step's end
+            // (rem), whichever comes first.  Written without branches; a vacuum
+            // voxel (RSP 0) gives wb = 0: no WEL, no deposit, a full crossing.
+            const float rem = w_tot - tau;
+            const float wb = tmin * m.x;
+            const bool ends = rem <= wb;                 // the step ends in this voxel
+            const float w_v = ends ? rem : wb;
+            const float tau_n = ends ? w_tot : tau + wb;
+            const float move = ends ? rem * fast_rcp(m.x) : tmin;
+            const bool cross = ends ? (rem == wb) : true;
+            const int cumk = tau_n < w_tot ? min(e32, (int)rintf(ef * (tau_n * inv_w))) : e32;
+            const int piece = cumk - dep;
+            dep = cumk;
+            acc += piece;
+            hdep += piece;
+            g2 += w_v * m.y;
+            tau = tau_n;
 #pragma unroll
             for (int q = 0; q < 3; ++q) L.f[q] = fminf(fmaxf(L.f[q] + move * dv[q], 0.f), 1.f);
             if (cross) {
