@@ -24,6 +24,11 @@
 // The source sample and the box entry are computed in FP64 once per history.
 #include "fdc_device.h"
 
+// Floating-point contraction only within one source expression (explicit fmaf
+// stays fused): the walk's rounding is then fixed by the source text, the same
+// in every kernel that inlines it, so all launch variants give identical tallies.
+#pragma clang fp contract(on)
+
 namespace fdc {
 
 namespace {
