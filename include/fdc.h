@@ -103,8 +103,8 @@ typedef struct {
     uint32_t tally_slots;       /* 0: flush visits with global atomics; else the size of
                                    a per-workgroup LDS sub-tally (persistent rounds;
                                    blocks_per_cu 0 is taken as 1): with tally_mode 0 a
-                                   power of two 256..8192, with tally_mode 1 a multiple
-                                   of 64 from 256 up to what fits                       */
+                                   power of two 256..8192, with tally_mode 1 or 2 a
+                                   multiple of 64 from 256 up to what fits              */
     uint32_t units_per_wave;    /* with tally_slots: 64-history units per wave per
                                    round, 1..64 (0 is taken as 1)                      */
     uint32_t tally_mode;        /* with tally_slots: 0 = hash table (voxel key, E, E2;
@@ -112,7 +112,11 @@ typedef struct {
                                    atomics once 8 probes find no room; 1 = write-back
                                    cache of one 64-bit word (voxel | partial sum) per
                                    slot and tally (8 or 16 B per slot), a conflicting
-                                   voxel evicting the old sum with one global atomic    */
+                                   voxel evicting the old sum with one global atomic,
+                                   flushed after every round; 2 = the same cache kept
+                                   for the whole launch when it covers one plan (waves
+                                   take units independently, one flush at the end;
+                                   launches of several plans run as mode 1)            */
     uint32_t reserved[3];
 } fdc_launch_config;
 

@@ -24,6 +24,8 @@ CANDIDATES = (
     + [dict(waves_per_block=8, blocks_per_cu=2, tally_slots=2048, units_per_wave=u) for u in (1, 2, 4)]
     + [dict(waves_per_block=4, blocks_per_cu=4, tally_slots=1024, units_per_wave=u) for u in (2, 4)]
     + [dict(waves_per_block=16, blocks_per_cu=1, tally_slots=8064, units_per_wave=u, tally_mode=1) for u in (1, 2, 4, 8)]
+    + [dict(waves_per_block=16, blocks_per_cu=1, tally_slots=8064, units_per_wave=1, tally_mode=2),
+       dict(waves_per_block=8, blocks_per_cu=1, tally_slots=8064, units_per_wave=1, tally_mode=2)]
     + [dict(waves_per_block=8, blocks_per_cu=2, tally_slots=3008, units_per_wave=u, tally_mode=1) for u in (2, 4)]
 )
 

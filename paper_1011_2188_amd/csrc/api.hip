@@ -696,9 +696,16 @@ static unsigned long long build_items(const fdc_ctx *ctx, const int32_t *plans, 
     return units;
 }
 
+static bool one_plan(const int32_t *plans, uint32_t n_plans)
+{
+    for (uint32_t i = 1; i < n_plans; ++i)
+        if (plans[i] != plans[0]) return false;
+    return true;
+}
+
 // transport launch for a work table already on the device; the queue counter
 // is cleared with a kernel so that the sequence can be captured in a graph
-static int enqueue_transport(fdc_ctx *ctx, TransportArgs a, uint32_t flags, hipStream_t s)
+static int enqueue_transport(fdc_ctx *ctx, TransportArgs a, uint32_t flags, hipStream_t s, bool one_plan)
 {
     const uint32_t wpb = ctx->cfg.waves_per_block;
     const bool variance = (flags & FDC_RUN_VARIANCE) != 0;
@@ -718,8 +725,10 @@ static int enqueue_transport(fdc_ctx *ctx, TransportArgs a, uint32_t flags, hipS
     }
     if (ctx->cfg.tally_slots) {
         const uint32_t grid = std::max<uint32_t>(1, ctx->cfg.blocks_per_cu) * (uint32_t)ctx->cus;
+        // the whole-launch cache (mode 2) needs a launch of one plan; otherwise the rounds cache
+        const uint32_t mode = ctx->cfg.tally_mode == 2 && !one_plan ? 1u : ctx->cfg.tally_mode;
         HIPCHK(launch_transport_lds(a, wpb, grid, ctx->cfg.tally_slots, std::max<uint32_t>(1, ctx->cfg.units_per_wave),
-                                    variance, ctx->cfg.tally_mode, s));
+                                    variance, mode, s));
     } else if (ctx->cfg.blocks_per_cu) {
         HIPCHK(launch_transport(a, wpb, ctx->cfg.blocks_per_cu * (uint32_t)ctx->cus, variance, false, s));
     } else {
@@ -757,7 +766,7 @@ int fdc_run_histories(fdc_ctx *ctx, const int32_t *plans, uint32_t n_plans, uint
     a.n_items = (uint32_t)items.size();
     a.n_units = units;
     a.flags = flags;
-    rc = enqueue_transport(ctx, a, flags, s);
+    rc = enqueue_transport(ctx, a, flags, s, one_plan(plans, n_plans));
     if (rc) return rc;
     HIPCHK(launch_advance(ctx->d_items, (uint32_t)items.size(), ctx->d_hnext, ctx->d_spots, ctx->d_plans, s));
     account_run(ctx, plans, n_plans, flags, false);
@@ -829,7 +838,7 @@ int fdc_graph_create(fdc_ctx *ctx, const int32_t *plans, uint32_t n_plans, uint3
         a.n_items = (uint32_t)items.size();
         a.n_units = units;
         a.flags = flags;
-        rc = enqueue_transport(ctx, a, flags, s);
+        rc = enqueue_transport(ctx, a, flags, s, one_plan(plans, n_plans));
         if (!rc) e = launch_advance(g->d_items, (uint32_t)items.size(), ctx->d_hnext, ctx->d_spots, ctx->d_plans, s);
     }
     for (uint32_t i = 0; i < n_plans && (options & FDC_GRAPH_DOSE) && e == hipSuccess && !rc; ++i) {
@@ -1042,12 +1051,12 @@ int fdc_set_launch_config(fdc_ctx *ctx, const fdc_launch_config *cfg)
     if (cfg->waves_per_block < 1 || cfg->waves_per_block > 16)
         return fail(ctx, FDC_E_ARG, "launch config: waves_per_block must be 1..16");
     if (cfg->blocks_per_cu > 64) return fail(ctx, FDC_E_ARG, "launch config: blocks_per_cu must be 0..64");
-    if (cfg->tally_mode > 1) return fail(ctx, FDC_E_ARG, "launch config: tally_mode must be 0 or 1");
+    if (cfg->tally_mode > 2) return fail(ctx, FDC_E_ARG, "launch config: tally_mode must be 0, 1 or 2");
     if (cfg->tally_slots) {
         const uint32_t t = cfg->tally_slots;
         if (cfg->tally_mode == 0 && (t < 256 || t > 8192 || (t & (t - 1))))
             return fail(ctx, FDC_E_ARG, "launch config: tally_slots must be 0 or a power of two 256..8192");
-        if (cfg->tally_mode == 1 && (t < 256 || t % 64))
+        if (cfg->tally_mode >= 1 && (t < 256 || t % 64))
             return fail(ctx, FDC_E_ARG, "launch config: tally_slots must be 0 or a multiple of 64 from 256");
         if (kLutSize * sizeof(float2) + kLdsFixedBytes + lds_tally_bytes(t, false, cfg->tally_mode) > kMaxLdsBytes)
             return fail(ctx, FDC_E_ARG, "launch config: LDS sub-tally of %u slots does not fit", t);

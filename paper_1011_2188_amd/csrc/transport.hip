@@ -639,6 +639,48 @@ __global__ void __launch_bounds__(1024) transport_lds_kernel(TransportArgs a, ui
     }
 }
 
+// Persistent kernel with a whole-launch LDS write-back cache, for launches of
+// one plan: waves pull units from the queue independently (no rounds and no
+// barriers between units), evictions reach HBM as they happen, and the
+// workgroup flushes the cache once when the queue is empty.
+template <bool VAR>
+__global__ void __launch_bounds__(1024) transport_cache_kernel(TransportArgs a, uint32_t slots)
+{
+    __shared__ float2 s_lut[kLutSize];
+    __shared__ float s_wc[16][kWaveConst];
+    extern __shared__ unsigned long long s_dyn[];
+    unsigned long long *s_e = s_dyn;
+    unsigned long long *s_e2 = s_dyn + slots;
+    for (int i = threadIdx.x; i < kLutSize; i += blockDim.x) s_lut[i] = a.lut[i];
+    for (uint32_t i = threadIdx.x; i < slots; i += blockDim.x) {
+        s_e[i] = 0;
+        if (VAR) s_e2[i] = 0;
+    }
+    __syncthreads();
+    const uint32_t lane = threadIdx.x & (kWave - 1);
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);   // scalar
+    const DevPlan *pl = plan_of_unit(a, 0);                   // the launch's one plan
+    const uint32_t nvox = (uint32_t)pl->n[0] * (uint32_t)pl->n[1] * (uint32_t)pl->n[2];
+    const uint32_t vbits = 64u - (32u - (uint32_t)__builtin_clz(nvox | 1u));
+    unsigned long long *const E = pl->E, *const E2 = pl->E2;
+    // same ticket scheme as the persistent global-atomic kernel
+    for (;;) {
+        const unsigned long long unit = scalar_u64(atomicAdd(a.queue, lane == 0 ? 1ull : 0ull));
+        if (unit >= a.n_units) break;
+        process_unit<false>(a, s_lut, s_wc[wave], unit, lane, CacheSink<VAR>{E, E2, true, s_e, s_e2, slots, vbits});
+    }
+    __syncthreads();
+    const unsigned long long vmax = (1ull << vbits) - 1;
+    for (uint32_t i = threadIdx.x; i < slots; i += blockDim.x) {
+        const unsigned long long w = s_e[i];
+        if (w) add_global(E + ((w >> vbits) - 1), w & vmax);
+        if (VAR) {
+            const unsigned long long w2 = s_e2[i];
+            if (w2) add_global(E2 + ((w2 >> vbits) - 1), w2 & vmax);
+        }
+    }
+}
+
 } // namespace
 
 hipError_t launch_transport(const TransportArgs &a, uint32_t waves_per_block, uint32_t grid_blocks,
@@ -663,10 +705,11 @@ size_t lds_tally_bytes(uint32_t slots, bool variance, uint32_t mode)
 hipError_t prepare_lds_kernels()
 {
     const int dyn = (int)(kMaxLdsBytes - kLutSize * sizeof(float2) - kLdsFixedBytes);
-    const void *k[4] = {(const void *)transport_lds_kernel<true, false>, (const void *)transport_lds_kernel<false, false>,
-                        (const void *)transport_lds_kernel<true, true>, (const void *)transport_lds_kernel<false, true>};
+    const void *k[6] = {(const void *)transport_lds_kernel<true, false>, (const void *)transport_lds_kernel<false, false>,
+                        (const void *)transport_lds_kernel<true, true>, (const void *)transport_lds_kernel<false, true>,
+                        (const void *)transport_cache_kernel<true>, (const void *)transport_cache_kernel<false>};
     hipError_t e = hipSuccess;
-    for (int i = 0; i < 4 && e == hipSuccess; ++i)
+    for (int i = 0; i < 6 && e == hipSuccess; ++i)
         e = hipFuncSetAttribute(k[i], hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
     return e;
 }
@@ -677,7 +720,11 @@ hipError_t launch_transport_lds(const TransportArgs &a, uint32_t waves_per_block
     const dim3 block(waves_per_block * kWave);
     const dim3 grid(grid_blocks);
     const size_t dyn = lds_tally_bytes(slots, variance, mode);
-    if (mode && variance)
+    if (mode == 2 && variance)
+        hipLaunchKernelGGL((transport_cache_kernel<true>), grid, block, dyn, s, a, slots);
+    else if (mode == 2)
+        hipLaunchKernelGGL((transport_cache_kernel<false>), grid, block, dyn, s, a, slots);
+    else if (mode && variance)
         hipLaunchKernelGGL((transport_lds_kernel<true, true>), grid, block, dyn, s, a, slots, units_per_wave);
     else if (mode)
         hipLaunchKernelGGL((transport_lds_kernel<false, true>), grid, block, dyn, s, a, slots, units_per_wave);

@@ -145,7 +145,9 @@ def test_launch_config_validation(ctx):
     ctx.set_launch_config(16, 1, 16192, 2, 1)          # fits with the energy tally alone
     _expect(F.FDC_E_ARG, ctx.set_launch_config, 16, 1, 16256, 2, 1)
     _expect(F.FDC_E_ARG, ctx.set_launch_config, 16, 1, 8100, 2, 1)
-    _expect(F.FDC_E_ARG, ctx.set_launch_config, 16, 1, 4096, 2, 2)
+    ctx.set_launch_config(16, 1, 8064, 1, 2)
+    _expect(F.FDC_E_ARG, ctx.set_launch_config, 16, 1, 4096, 2, 3)
+    _expect(F.FDC_E_ARG, ctx.set_launch_config, 16, 1, 8100, 1, 2)
     _expect(F.FDC_E_ARG, ctx.set_launch_config, 4, 0, 0, 65)
     assert ctx.device_cus() > 0
 

@@ -187,7 +187,10 @@ def test_launch_configs_bitwise():
                 # write-back cache: tiny tables force evictions and CAS contention
                 dict(waves_per_block=16, blocks_per_cu=1, tally_slots=256, units_per_wave=4, tally_mode=1),
                 dict(waves_per_block=4, blocks_per_cu=2, tally_slots=320, units_per_wave=1, tally_mode=1),
-                dict(waves_per_block=16, blocks_per_cu=1, tally_slots=8064, units_per_wave=2, tally_mode=1)]:
+                dict(waves_per_block=16, blocks_per_cu=1, tally_slots=8064, units_per_wave=2, tally_mode=1),
+                # whole-launch cache (one plan), also tiny
+                dict(waves_per_block=16, blocks_per_cu=1, tally_slots=8064, units_per_wave=1, tally_mode=2),
+                dict(waves_per_block=4, blocks_per_cu=2, tally_slots=256, units_per_wave=1, tally_mode=2)]:
         got = _tallies(db, ph, sp, **cfg)
         assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1]) and got[2] == ref[2], cfg
 
@@ -220,7 +223,8 @@ def test_autotuner_candidates_bitwise_and_tuning_leaves_no_trace(tmp_path):
 
 @pytest.mark.parametrize("cfg", [{}, dict(waves_per_block=8, blocks_per_cu=1, tally_slots=2048, units_per_wave=2),
                                  dict(waves_per_block=8, blocks_per_cu=1, tally_slots=512, units_per_wave=3,
-                                      tally_mode=1)])
+                                      tally_mode=1),
+                                 dict(waves_per_block=8, blocks_per_cu=1, tally_slots=512, tally_mode=2)])
 def test_split_runs_and_batching_bitwise(cfg):
     """run(n) twice == run(2n) (history counters continue, unaligned h0), and
     plans launched together == plans launched one by one (also with the LDS
@@ -372,7 +376,8 @@ def test_batched_graph_full_size():
 # ---------------------------------------------------------------- graphs ----
 @pytest.mark.parametrize("cfg", [{}, dict(waves_per_block=16, blocks_per_cu=1, tally_slots=4096, units_per_wave=2),
                                  dict(waves_per_block=16, blocks_per_cu=1, tally_slots=8064, units_per_wave=2,
-                                      tally_mode=1)])
+                                      tally_mode=1),
+                                 dict(waves_per_block=16, blocks_per_cu=1, tally_slots=8064, tally_mode=2)])
 def test_graph_replays_match_eager(cfg):
     """A captured run (clear tallies -> transport -> advance counters -> dose)
     replayed four times, with eager work and synchronisation in between,
