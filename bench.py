@@ -61,11 +61,13 @@ def measured_traffic(launch):
     return float(fields["traffic_bytes_per_launch"])
 
 
-def extras(c, launch, log):
-    """Other rows of the path, timed live: the 1e8-history thorax plan (both
-    tallies, the slab's launch configuration) and the denoiser's forward pass
-    (256x256x128 volume) and training step (128^3 crop: forward, backward,
-    Adam), each the best of three after a warm-up."""
+def extras(c, plan, nvox, hist_per_step, launch, log):
+    """Other rows of the path, timed live: seconds to 2% with the batch
+    estimator of Eq. (1) (six independent batches of the slab workload with the
+    energy tally only, as the paper's batch method); the 1e8-history thorax
+    plan (both tallies, the slab's launch configuration); the denoiser's
+    forward pass (256x256x128 volume) and training step (128^3 crop: forward,
+    backward, Adam), each the best of three after a warm-up."""
     import numpy as np
     import torch
     from paper_1011_2188_amd import fdc as F
@@ -83,6 +85,26 @@ def extras(c, launch, log):
         return min(ts)
 
     out = {}
+    nb = 6
+    doses = torch.empty((nb, nvox), dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for b in range(nb):                       # new histories each batch (counters continue)
+        c.reset_plan(plan)
+        c.run_histories([plan], 0)
+        c.compute_dose(plan, doses[b], None)
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - t
+    mean = torch.empty(nvox, dtype=torch.float64, device="cuda")
+    sigma = torch.empty(nvox, dtype=torch.float64, device="cuda")
+    c.batch_uncertainty(doses, mean, sigma)
+    ub, _, _ = c.mean_uncertainty(plan, mean, sigma.square(), 0.5)
+    n_tot = nb * hist_per_step
+    n2 = n_tot * (ub / 0.02) ** 2
+    out["batch_method_eq1"] = {"batches": nb, "histories": n_tot, "seconds": tb, "histories_per_s": n_tot / tb,
+                               "mean_uncertainty": ub, "histories_to_2pct": n2,
+                               "seconds_to_2pct": n2 / (n_tot / tb)}
+    log(f"batch method: {ub:.4%} at {n_tot} histories -> 2% in {n2 / (n_tot / tb):.4g} s")
     ph, sp, _ = W.thorax()
     p = c.load_phantom(ph)
     c.add_beam_spots(p, sp)
@@ -268,7 +290,7 @@ def main():
         **out,
     }
     if not args.no_extras:
-        result["extras"] = extras(c, launch, log)
+        result["extras"] = extras(c, plan, nvox, hist_per_step, launch, log)
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample ...")
         result["cpu_baseline"] = cpu_baseline(ph, sp, db)
