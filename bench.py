@@ -151,13 +151,14 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(ph, sp, db, target_s=15.0):
+def cpu_baseline(ph, sp, db, target_s=20.0):
     """The oracle as it stands, all host threads, on a bounded sample of the
-    same workload (every spot, fewer histories), scaled to histories/s."""
+    same workload (every spot, up to its full history count, sized for about
+    target_s seconds from a probe run), scaled to histories/s."""
     import numpy as np
     from oracle import oracle as O
     threads = int(os.environ.get("ORACLE_THREADS", min(os.cpu_count() or 1, 16)))
-    probe = 400
+    probe = 4000
     t = time.perf_counter()
     O.replay(db, ph, sp, h_count=np.full(len(sp), probe, np.uint64), threads=threads)
     rate = probe * len(sp) / (time.perf_counter() - t)
