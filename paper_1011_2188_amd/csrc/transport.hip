@@ -143,11 +143,28 @@ __device__ inline uint32_t row_slot(uint32_t v, uint32_t ix, uint32_t n)
 
 // Per-workgroup write-back cache of the tallies in LDS.  A slot is one 64-bit
 // word per tally: (voxel + 1) in the top 64 - vbits bits, a partial sum in the
-// low vbits bits, 0 = empty.  Every update is a single compare-and-swap: a hit
-// adds to the sum, a miss installs the new voxel and sends the evicted sum to
-// the plan's tally with one global atomic.  The sums stay exact integers (a
-// sum that would overflow its field goes to the global tally instead), so the
-// result is the same as with global atomics alone.  The cache holds voxels of
+// low vbits bits, 0 = empty.  No update retries:
+//  - hit (the word read holds the voxel): one atomic add of the deposit;
+//  - miss: one atomic exchange installs (voxel, deposit) and the evicted sum
+//    goes to the plan's tally with one global atomic, unless it is the same
+//    voxel's (another lane installed it first), which is added back in LDS;
+//  - if the word changed voxel between the read and the add, the deposit went
+//    into another voxel's sum: the lane adds it to its own voxel's tally and
+//    subtracts it from the other voxel's (exact in modular integer arithmetic,
+//    whenever that sum is flushed);
+//  - an add that takes a sum to half its field or beyond exchanges the word
+//    with 0 and flushes it.
+// Keys only change by exchange, which carries the whole sum with it, so every
+// unit of deposit reaches exactly one voxel's tally and the result equals that
+// of global atomics alone.  Headroom: a lane whose add took a sum to half the
+// field or beyond exchanges the word before its next LDS access, so at most one
+// add per lane of the workgroup (<= 1024 = 2^10) lands on a word past that mark
+// before it is emptied; every value added in LDS (a deposit or a sum merged
+// back) is below 2^(vbits-12), so a sum stays below
+// 2^(vbits-1) + 1025 * 2^(vbits-12) < 2^vbits and never carries into the key.
+// Larger deposits go straight to the global tally.  A word whose key is 0
+// (an add that landed on a just-emptied word) holds no tally: its sum was also
+// sent to the lane's own voxel, and flushes skip it.  The cache holds voxels of
 // one plan per round; other plans' visits go straight to the global atomics.
 template <bool VAR>
 struct CacheSink {
@@ -156,14 +173,31 @@ struct CacheSink {
     unsigned long long *ce, *ce2;
     uint32_t n;                 // slots
     uint32_t vbits;             // value bits of a word
+    uint32_t nvox;              // voxels of the cached plan (valid keys are 1..nvox)
 
-    // one word's next value: hit -> add (0 when the sum would overflow its
-    // field), miss -> install the voxel with val
-    __device__ static unsigned long long next_word(unsigned long long w, unsigned long long key,
-                                                   unsigned long long val, unsigned long long vmax)
+    __device__ void flush_word(unsigned long long *T, unsigned long long w) const
     {
-        if ((w & ~vmax) == key) return val > vmax - (w & vmax) ? 0ull : w + val;
-        return key | val;
+        const uint32_t kv = (uint32_t)(w >> vbits);
+        const unsigned long long val = w & ((1ull << vbits) - 1);
+        if (kv != 0u && kv <= nvox && val != 0ull) add_global(T + (kv - 1u), val);
+    }
+
+    // after the word's atomic returned o: repair a misdirected add, flush a
+    // full word, or flush the evicted sum
+    __device__ void settle(unsigned long long *c, unsigned long long *T, uint32_t v, unsigned long long key,
+                           unsigned long long val, bool hit, unsigned long long o) const
+    {
+        const unsigned long long vmask = (1ull << vbits) - 1;
+        if (!hit) {
+            flush_word(T, o);
+            return;
+        }
+        if ((o & ~vmask) != key) {
+            add_global(T + v, val);
+            const uint32_t kv = (uint32_t)(o >> vbits);
+            if (kv != 0u && kv <= nvox) add_global(T + (kv - 1u), 0ull - val);
+        }
+        if ((o & vmask) + val >= (1ull << (vbits - 1))) flush_word(T, atomicExch(c, 0ull));
     }
 
     __device__ void add(uint32_t v, uint32_t ix, long long acc) const
@@ -175,44 +209,36 @@ struct CacheSink {
             return;
         }
         const uint32_t s = row_slot(v, ix, n);
-        const unsigned long long vmax = (1ull << vbits) - 1;
+        const unsigned long long vmask = (1ull << vbits) - 1;
+        const unsigned long long lim = 1ull << (vbits - 12);
         const unsigned long long key = (unsigned long long)(v + 1) << vbits;
         const unsigned long long v1 = (unsigned long long)acc, v2 = q * q;
-        // deposits are >= 0 (the database has dE >= 0); values wider than a
-        // word's field go straight to the global tally
-        bool todo1 = acc > 0, todo2 = VAR && q != 0;
-        if (todo1 && v1 > vmax) { add_global(E + v, v1); todo1 = false; }
-        if (todo2 && v2 > vmax) { add_global(E2 + v, v2); todo2 = false; }
-        // the two words are updated side by side: both reads, both
-        // compare-and-swaps, then each retries on its own if it lost a race
-        unsigned long long w1 = todo1 ? ce[s] : 0ull, w2 = todo2 ? ce2[s] : 0ull;
-#pragma unroll 1
-        for (int tries = 0; tries < 16 && (todo1 || todo2); ++tries) {
-            const unsigned long long n1 = todo1 ? next_word(w1, key, v1, vmax) : 0ull;
-            const unsigned long long n2 = todo2 ? next_word(w2, key, v2, vmax) : 0ull;
-            if (todo1 && n1 == 0ull) { add_global(E + v, v1); todo1 = false; }     // would overflow
-            if (todo2 && n2 == 0ull) { add_global(E2 + v, v2); todo2 = false; }
-            const unsigned long long o1 = todo1 ? atomicCAS(ce + s, w1, n1) : w1;
-            const unsigned long long o2 = todo2 ? atomicCAS(ce2 + s, w2, n2) : w2;
-            if (todo1) {
-                if (o1 == w1) {
-                    if (w1 != 0 && (w1 & ~vmax) != key) add_global(E + ((w1 >> vbits) - 1), w1 & vmax);   // evicted
-                    todo1 = false;
-                } else {
-                    w1 = o1;
-                }
-            }
-            if (todo2) {
-                if (o2 == w2) {
-                    if (w2 != 0 && (w2 & ~vmax) != key) add_global(E2 + ((w2 >> vbits) - 1), w2 & vmax);
-                    todo2 = false;
-                } else {
-                    w2 = o2;
-                }
-            }
+        // deposits are >= 0 (the database has dE >= 0)
+        bool do1 = acc > 0, do2 = VAR && q != 0;
+        if (do1 && v1 >= lim) { add_global(E + v, v1); do1 = false; }
+        if (do2 && v2 >= lim) { add_global(E2 + v, v2); do2 = false; }
+        // the two words side by side: both reads, both atomics, then both settles
+        const unsigned long long w1 = do1 ? ce[s] : 0ull, w2 = do2 ? ce2[s] : 0ull;
+        const bool hit1 = (w1 & ~vmask) == key, hit2 = (w2 & ~vmask) == key;
+        unsigned long long o1 = 0ull, o2 = 0ull;
+        if (do1) o1 = hit1 ? atomicAdd(ce + s, v1) : atomicExch(ce + s, key | v1);
+        if (do2) o2 = hit2 ? atomicAdd(ce2 + s, v2) : atomicExch(ce2 + s, key | v2);
+        // a miss that evicted the same voxel (installed an instant earlier by
+        // another lane, typically of the same wave) adds that sum back
+        unsigned long long a1 = v1, a2 = v2;
+        bool h1 = hit1, h2 = hit2;
+        if (do1 && !hit1 && (o1 & ~vmask) == key && (o1 & vmask) < lim) {
+            a1 = o1 & vmask;
+            h1 = true;
+            o1 = atomicAdd(ce + s, a1);
         }
-        if (todo1) add_global(E + v, v1);
-        if (todo2) add_global(E2 + v, v2);
+        if (do2 && !hit2 && (o2 & ~vmask) == key && (o2 & vmask) < lim) {
+            a2 = o2 & vmask;
+            h2 = true;
+            o2 = atomicAdd(ce2 + s, a2);
+        }
+        if (do1) settle(ce + s, E, v, key, a1, h1, o1);
+        if (do2) settle(ce2 + s, E2, v, key, a2, h2, o2);
     }
 };
 
@@ -596,7 +622,7 @@ __global__ void __launch_bounds__(1024) transport_lds_kernel(TransportArgs a, ui
             const DevPlan *pl = plan_of_unit(a, unit);
             if (CACHE)
                 process_unit<false>(a, s_lut, s_wc[wave], unit, lane,
-                                    CacheSink<VAR>{pl->E, pl->E2, pl == tab_pl, s_e, s_e2, slots, vbits});
+                                    CacheSink<VAR>{pl->E, pl->E2, pl == tab_pl, s_e, s_e2, slots, vbits, nvox});
             else
                 process_unit<false>(a, s_lut, s_wc[wave], unit, lane,
                                     LdsSink<VAR>{pl->E, pl->E2, pl == tab_pl, s_key, s_e, s_e2, slots - 1});
@@ -607,16 +633,16 @@ __global__ void __launch_bounds__(1024) transport_lds_kernel(TransportArgs a, ui
         unsigned long long *const tE = tab_pl->E, *const tE2 = tab_pl->E2;
         for (uint32_t i = threadIdx.x; i < slots; i += blockDim.x) {
             if (CACHE) {
-                const unsigned long long vmax = (1ull << vbits) - 1;
+                const CacheSink<VAR> cs{tE, tE2, true, s_e, s_e2, slots, vbits, nvox};
                 const unsigned long long w = s_e[i];
                 if (w) {
-                    add_global(tE + ((w >> vbits) - 1), w & vmax);
+                    cs.flush_word(tE, w);
                     s_e[i] = 0;
                 }
                 if (VAR) {
                     const unsigned long long w2 = s_e2[i];
                     if (w2) {
-                        add_global(tE2 + ((w2 >> vbits) - 1), w2 & vmax);
+                        cs.flush_word(tE2, w2);
                         s_e2[i] = 0;
                     }
                 }
@@ -663,21 +689,17 @@ __global__ void __launch_bounds__(1024) transport_cache_kernel(TransportArgs a, 
     const uint32_t nvox = (uint32_t)pl->n[0] * (uint32_t)pl->n[1] * (uint32_t)pl->n[2];
     const uint32_t vbits = 64u - (32u - (uint32_t)__builtin_clz(nvox | 1u));
     unsigned long long *const E = pl->E, *const E2 = pl->E2;
+    const CacheSink<VAR> cs{E, E2, true, s_e, s_e2, slots, vbits, nvox};
     // same ticket scheme as the persistent global-atomic kernel
     for (;;) {
         const unsigned long long unit = scalar_u64(atomicAdd(a.queue, lane == 0 ? 1ull : 0ull));
         if (unit >= a.n_units) break;
-        process_unit<false>(a, s_lut, s_wc[wave], unit, lane, CacheSink<VAR>{E, E2, true, s_e, s_e2, slots, vbits});
+        process_unit<false>(a, s_lut, s_wc[wave], unit, lane, cs);
     }
     __syncthreads();
-    const unsigned long long vmax = (1ull << vbits) - 1;
     for (uint32_t i = threadIdx.x; i < slots; i += blockDim.x) {
-        const unsigned long long w = s_e[i];
-        if (w) add_global(E + ((w >> vbits) - 1), w & vmax);
-        if (VAR) {
-            const unsigned long long w2 = s_e2[i];
-            if (w2) add_global(E2 + ((w2 >> vbits) - 1), w2 & vmax);
-        }
+        cs.flush_word(E, s_e[i]);
+        if (VAR) cs.flush_word(E2, s_e2[i]);
     }
 }
 
