@@ -106,7 +106,9 @@ typedef struct {
                                    power of two 256..8192, with tally_mode 1 or 2 a
                                    multiple of 64 from 256 up to what fits              */
     uint32_t units_per_wave;    /* with tally_slots: 64-history units per wave per
-                                   round, 1..64 (0 is taken as 1)                      */
+                                   round (mode 2: the workgroup takes chunks of
+                                   waves_per_block * units_per_wave consecutive units),
+                                   1..64 (0 is taken as 1)                             */
     uint32_t tally_mode;        /* with tally_slots: 0 = hash table (voxel key, E, E2;
                                    12 or 20 B per slot) whose visits fall back to global
                                    atomics once 8 probes find no room; 1 = write-back
@@ -115,8 +117,9 @@ typedef struct {
                                    voxel evicting the old sum with one global atomic,
                                    flushed after every round; 2 = the same cache kept
                                    for the whole launch when it covers one plan (waves
-                                   take units independently, one flush at the end;
-                                   launches of several plans run as mode 1)            */
+                                   take units of their workgroup's chunk without
+                                   barriers, one flush at the end; launches of several
+                                   plans run as mode 1)                                */
     uint32_t reserved[3];
 } fdc_launch_config;
 

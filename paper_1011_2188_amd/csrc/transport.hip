@@ -666,14 +666,21 @@ __global__ void __launch_bounds__(1024) transport_lds_kernel(TransportArgs a, ui
 }
 
 // Persistent kernel with a whole-launch LDS write-back cache, for launches of
-// one plan: waves pull units from the queue independently (no rounds and no
-// barriers between units), evictions reach HBM as they happen, and the
-// workgroup flushes the cache once when the queue is empty.
+// one plan: no rounds and no barriers between units, evictions reach HBM as
+// they happen, and the workgroup flushes the cache once when the queue is
+// empty.  The workgroup takes units from the global queue in chunks of
+// `chunk` consecutive units (histories of one spot, which overlap in space)
+// and its waves take units of the current chunk one by one, so the waves
+// sharing the cache work on neighbouring histories.  The chunk word in LDS is
+// (first unit << 16 | units handed out); the wave that draws index `chunk`
+// fetches the next chunk, waves that draw past it wait until the word holds
+// a new chunk (that wave's fetch never waits on anything).
 template <bool VAR>
-__global__ void __launch_bounds__(1024) transport_cache_kernel(TransportArgs a, uint32_t slots)
+__global__ void __launch_bounds__(1024) transport_cache_kernel(TransportArgs a, uint32_t slots, uint32_t chunk)
 {
     __shared__ float2 s_lut[kLutSize];
     __shared__ float s_wc[16][kWaveConst];
+    __shared__ unsigned long long s_chunk;
     extern __shared__ unsigned long long s_dyn[];
     unsigned long long *s_e = s_dyn;
     unsigned long long *s_e2 = s_dyn + slots;
@@ -682,6 +689,10 @@ __global__ void __launch_bounds__(1024) transport_cache_kernel(TransportArgs a, 
         s_e[i] = 0;
         if (VAR) s_e2[i] = 0;
     }
+    const unsigned long long n_units = a.n_units;
+    // the first chunk (a start at or past the end means no work)
+    const unsigned long long first = atomicAdd(a.queue, threadIdx.x == 0 ? (unsigned long long)chunk : 0ull);
+    if (threadIdx.x == 0) s_chunk = (first < n_units ? first : n_units) << 16;
     __syncthreads();
     const uint32_t lane = threadIdx.x & (kWave - 1);
     const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);   // scalar
@@ -690,11 +701,23 @@ __global__ void __launch_bounds__(1024) transport_cache_kernel(TransportArgs a, 
     const uint32_t vbits = 64u - (32u - (uint32_t)__builtin_clz(nvox | 1u));
     unsigned long long *const E = pl->E, *const E2 = pl->E2;
     const CacheSink<VAR> cs{E, E2, true, s_e, s_e2, slots, vbits, nvox};
-    // same ticket scheme as the persistent global-atomic kernel
+    volatile unsigned long long *const chunk_word = &s_chunk;
     for (;;) {
-        const unsigned long long unit = scalar_u64(atomicAdd(a.queue, lane == 0 ? 1ull : 0ull));
-        if (unit >= a.n_units) break;
-        process_unit<false>(a, s_lut, s_wc[wave], unit, lane, cs);
+        // every lane executes the LDS atomic (lane 0 adds 1), lane 0's old value is the ticket
+        const unsigned long long w = scalar_u64(atomicAdd(&s_chunk, lane == 0 ? 1ull : 0ull));
+        const unsigned long long base = w >> 16;
+        const uint32_t idx = (uint32_t)(w & 0xffffu);
+        if (base >= n_units) break;
+        if (idx < chunk) {
+            const unsigned long long unit = base + idx;
+            if (unit < n_units) process_unit<false>(a, s_lut, s_wc[wave], unit, lane, cs);
+        } else if (idx == chunk) {
+            const unsigned long long nb = scalar_u64(atomicAdd(a.queue, lane == 0 ? (unsigned long long)chunk : 0ull));
+            if (lane == 0) atomicExch(&s_chunk, (nb < n_units ? nb : n_units) << 16);
+        } else {
+            // the wave that drew `chunk` replaces the word with a later chunk (or the end)
+            while ((scalar_u64(*chunk_word) >> 16) == base) __builtin_amdgcn_s_sleep(2);
+        }
     }
     __syncthreads();
     for (uint32_t i = threadIdx.x; i < slots; i += blockDim.x) {
@@ -743,9 +766,9 @@ hipError_t launch_transport_lds(const TransportArgs &a, uint32_t waves_per_block
     const dim3 grid(grid_blocks);
     const size_t dyn = lds_tally_bytes(slots, variance, mode);
     if (mode == 2 && variance)
-        hipLaunchKernelGGL((transport_cache_kernel<true>), grid, block, dyn, s, a, slots);
+        hipLaunchKernelGGL((transport_cache_kernel<true>), grid, block, dyn, s, a, slots, waves_per_block * units_per_wave);
     else if (mode == 2)
-        hipLaunchKernelGGL((transport_cache_kernel<false>), grid, block, dyn, s, a, slots);
+        hipLaunchKernelGGL((transport_cache_kernel<false>), grid, block, dyn, s, a, slots, waves_per_block * units_per_wave);
     else if (mode && variance)
         hipLaunchKernelGGL((transport_lds_kernel<true, true>), grid, block, dyn, s, a, slots, units_per_wave);
     else if (mode)

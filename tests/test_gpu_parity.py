@@ -184,13 +184,15 @@ def test_launch_configs_bitwise():
                 dict(waves_per_block=16, blocks_per_cu=1, tally_slots=4096),
                 dict(waves_per_block=8, blocks_per_cu=2, tally_slots=1024, units_per_wave=3),
                 dict(waves_per_block=4, blocks_per_cu=1, tally_slots=256, units_per_wave=1),
-                # write-back cache: tiny tables force evictions and CAS contention
+                # write-back cache: tiny tables force evictions and lanes racing on a word
                 dict(waves_per_block=16, blocks_per_cu=1, tally_slots=256, units_per_wave=4, tally_mode=1),
                 dict(waves_per_block=4, blocks_per_cu=2, tally_slots=320, units_per_wave=1, tally_mode=1),
                 dict(waves_per_block=16, blocks_per_cu=1, tally_slots=8064, units_per_wave=2, tally_mode=1),
-                # whole-launch cache (one plan), also tiny
+                # whole-launch cache (one plan), also tiny; chunks of 16, 8, 15 and 1 units
                 dict(waves_per_block=16, blocks_per_cu=1, tally_slots=8064, units_per_wave=1, tally_mode=2),
-                dict(waves_per_block=4, blocks_per_cu=2, tally_slots=256, units_per_wave=1, tally_mode=2)]:
+                dict(waves_per_block=4, blocks_per_cu=2, tally_slots=256, units_per_wave=2, tally_mode=2),
+                dict(waves_per_block=5, blocks_per_cu=1, tally_slots=512, units_per_wave=3, tally_mode=2),
+                dict(waves_per_block=1, blocks_per_cu=4, tally_slots=256, units_per_wave=1, tally_mode=2)]:
         got = _tallies(db, ph, sp, **cfg)
         assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1]) and got[2] == ref[2], cfg
 
