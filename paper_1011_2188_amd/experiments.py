@@ -4,7 +4,11 @@
   batched           64 thorax-like plans in ONE captured graph launch vs 64
                     separate eager runs (same histories, same tallies);
   denoiser_study    seconds to 2% mean uncertainty, plain vs denoised at equal
-                    gamma pass rate (2%/2 mm) against an independent reference.
+                    gamma pass rate (2%/2 mm) against an independent reference;
+  recycling_study   the database-recycling test of Section 3: mean uncertainty
+                    against N with the history-by-history estimator (Eq. 2)
+                    and with fully independent batches (Eq. 1), for several
+                    track reuse factors R.
 """
 from __future__ import annotations
 
@@ -192,3 +196,117 @@ def denoiser_study(db, n_train=128, n_test=6, shape=(256, 256, 128), voxel_cm=0.
            "reached": len(ok), "rows": rows}
     log(f"denoiser study: {out}")
     return out
+
+
+def _c_over_sqrt(ns, us):
+    """The line C / sqrt(N) through the point of lowest N (as in the paper's
+    recycling figure) and the largest relative deviation of the points from it."""
+    c = us[0] * math.sqrt(ns[0])
+    dev = max(abs(u / (c / math.sqrt(n)) - 1.0) for n, u in zip(ns, us))
+    return c, dev
+
+
+def recycling_study(R_values=(1, 64, 320), db_seeds=(101, 102, 103, 104, 105, 106), hbh_db_seed=2188,
+                    n_min=1_500_000, doublings=5, n_tracks=10_000, log=print,
+                    workload=None):
+    """The recycling test (Section 3): does re-tracing each stored track many
+    times correlate the histories?
+
+    For each reuse factor R (histories of a spot per shared track) and each N in
+    n_min * 2^k (k = 0..doublings) on the slab workload:
+      * history-by-history: one run of N histories (database seed hbh_db_seed,
+        run seed 1), mean over voxels above Dmax/2 of sigma/D from Eq. (2);
+      * batch method: n = len(db_seeds) fully independent batches of N/n
+        histories, each with its own synthetic database (seed db_seeds[i]) and
+        its own run seed, combined with Eq. (1); also with the first half of the
+        batches (their total N/2), and with n batches that share the
+        history-by-history database (different run seeds only).
+    Hidden correlations would show as a departure from 1/sqrt(N) of the
+    history-by-history curve and as history-by-history values below the batch
+    values.  Each curve gets the line C/sqrt(N) through its lowest-N point and
+    the largest relative deviation from it.  Doses of one N are snapshots of
+    one accumulating run (k doubles the passes), so successive points share
+    histories.  `workload` = (phantom, spots) replaces the slab (the spots'
+    n_histories are replaced)."""
+    import torch
+    ph, sp0 = workload if workload is not None else (I.slab_phantom(128, 0.1), W.slab_spots(1))
+    n_b = len(db_seeds)
+    n_spots = len(sp0)
+    if n_min % (n_b * n_spots):
+        raise ValueError("n_min must split evenly over the batches and the spots")
+    ks = [2 ** j for j in range(doublings + 1)]
+    ns = [n_min * k for k in ks]
+    nvox = int(np.prod(ph.hu.shape))
+    t0 = time.perf_counter()
+    bins = list(W.DB_BINS_FULL)
+    dbs = {}
+    for seed in (hbh_db_seed,) + tuple(db_seeds):
+        dbs[seed] = I.make_water_track_db(bins, n_tracks, seed)
+        log(f"recycling: database seed {seed} ready ({time.perf_counter() - t0:.0f} s)")
+
+    def spots(per_pass):
+        sp = sp0.copy()
+        sp["n_histories"] = per_pass // n_spots
+        return sp
+
+    def snapshots(db, run_seed, R, per_pass, variance):
+        """Doses (and Eq. (2) variances) after k passes for every k in ks."""
+        c = F.Context(0, run_seed, reuse_R=R, table=I.HU_TABLE_DEFAULT)
+        c.load_track_db(db)
+        p = c.load_phantom(ph)
+        c.add_beam_spots(p, spots(per_pass))
+        flags = F.FDC_RUN_VARIANCE if variance else 0
+        out, done = [], 0
+        for k in ks:
+            for _ in range(k - done):
+                c.run_histories([p], flags)
+            done = k
+            d = torch.empty(nvox, dtype=torch.float64, device="cuda")
+            v = torch.empty(nvox, dtype=torch.float64, device="cuda") if variance else None
+            c.compute_dose(p, d, v)
+            out.append((d, v))
+        return c, p, out
+
+    result = {"n": ns, "n_min": n_min, "batches": n_b, "db_seeds": list(db_seeds), "hbh_db_seed": hbh_db_seed,
+              "n_tracks_per_bin": n_tracks, "R": {}}
+    for R in R_values:
+        t = time.perf_counter()
+        c, p, hb = snapshots(dbs[hbh_db_seed], 1, R, n_min, True)
+        u_hbh = [c.mean_uncertainty(p, d, v, 0.5)[0] for d, v in hb]
+        c.close()
+        indep = []
+        for i, seed in enumerate(db_seeds):
+            cb, pb, sn = snapshots(dbs[seed], seed, R, n_min // n_b, False)
+            indep.append([d for d, _ in sn])
+            if i < n_b - 1:
+                cb.close()
+        shared = []
+        for i in range(n_b):
+            cs, _, sn = snapshots(dbs[hbh_db_seed], 1000 + i, R, n_min // n_b, False)
+            shared.append([d for d, _ in sn])
+            cs.close()
+
+        def eq1(doses):
+            stack = torch.stack(doses)
+            mean = torch.empty(nvox, dtype=torch.float64, device="cuda")
+            sig = torch.empty(nvox, dtype=torch.float64, device="cuda")
+            cb.batch_uncertainty(stack, mean, sig)
+            return cb.mean_uncertainty(pb, mean, sig.square(), 0.5)[0]
+
+        u_b = [eq1([indep[b][j] for b in range(n_b)]) for j in range(len(ks))]
+        u_half = [eq1([indep[b][j] for b in range(n_b // 2)]) for j in range(len(ks))]
+        u_sh = [eq1([shared[b][j] for b in range(n_b)]) for j in range(len(ks))]
+        cb.close()
+        torch.cuda.synchronize()
+        rec = {"hbh_eq2": u_hbh, "batch_eq1_indep": u_b, "batch_eq1_indep_half": u_half,
+               "n_half": [n // 2 for n in ns], "batch_eq1_shared_db": u_sh,
+               "ratio_hbh_over_batch": [a / b for a, b in zip(u_hbh, u_b)], "seconds": time.perf_counter() - t}
+        for key, xs in (("hbh_eq2", ns), ("batch_eq1_indep", ns), ("batch_eq1_indep_half", rec["n_half"]),
+                        ("batch_eq1_shared_db", ns)):
+            cc, dev = _c_over_sqrt(xs, rec[key])
+            rec[key + "_fit"] = {"C": cc, "max_rel_deviation": dev}
+        result["R"][R] = rec
+        log(f"recycling R={R}: hbh {['%.4f' % u for u in u_hbh]} batch {['%.4f' % u for u in u_b]} "
+            f"({rec['seconds']:.1f} s)")
+        del indep, shared, hb
+    return result
