@@ -253,11 +253,15 @@ static int replay_history(const oracle_problem *P, uint32_t s, uint64_t h, oracl
     int64_t I_h = T_fp - skip;
     if (I_h < 0) I_h = 0;
 
-    /* source: Gaussian lateral position, beam direction, optional track rotation */
+    /* source: lateral position (Gaussian of standard deviation sigma, or for
+     * sigma < 0 uniform over a disk of radius -sigma: the circular field of
+     * Section 2.5), beam direction, optional track rotation */
     ctr[0] = (uint32_t)h; ctr[1] = (uint32_t)(h >> 32); ctr[2] = s;
     ctr[3] = (P->plan << 4) | TAG_SRC;
     oracle_philox4x32_10(ctr, key, x);
-    double r = sqrt(-2.0 * log(oracle_uniform(x[0])));
+    double sig = P->spot_sigma[s];
+    /* Gaussian: Box-Muller radius; disk: the radius whose square is uniform */
+    double r = sig >= 0.0 ? sqrt(-2.0 * log(oracle_uniform(x[0]))) : sqrt(oracle_uniform(x[0]));
     double ang = 2.0 * M_PI * oracle_uniform(x[1]);
     double n1 = r * cos(ang), n2 = r * sin(ang);
     double phi0 = (P->flags & FLAG_ROTATE) ? 2.0 * M_PI * oracle_uniform(x[2]) : 0.0;
@@ -269,10 +273,9 @@ static int replay_history(const oracle_problem *P, uint32_t s, uint64_t h, oracl
     field_frame(d, e1, e2);
     double M[3][3]; /* columns e1, e2, d */
     for (int a = 0; a < 3; ++a) { M[a][0] = e1[a]; M[a][1] = e2[a]; M[a][2] = d[a]; }
-    double sig = P->spot_sigma[s];
     double pos[3];
     for (int a = 0; a < 3; ++a)
-        pos[a] = (double)P->spot_pos[3 * s + a] + sig * (n1 * e1[a] + n2 * e2[a]);
+        pos[a] = (double)P->spot_pos[3 * s + a] + fabs(sig) * (n1 * e1[a] + n2 * e2[a]);
 
     if (T) T->incident += I_h;
 

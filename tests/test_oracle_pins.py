@@ -288,6 +288,30 @@ def test_source_is_gaussian_and_tracks_rotate_rigidly():
     assert not np.allclose((xb - x0)[:64, :2], (xb - x0)[:1, :2], atol=1e-6)
 
 
+def test_disk_field_is_uniform_over_its_disk():
+    """A spot with sigma = -R starts its histories uniformly over the disk of
+    radius R perpendicular to the beam (the circular field of Section 2.5):
+    straight tracks end at the start point's lateral position, so every end
+    point lies within R of the axis, (r / R)^2 and the polar angle are
+    uniform, and the lateral centroid is the axis."""
+    db = I.make_water_track_db([100.0], 3, seed=2)
+    ph = I.water_phantom((60, 60, 50), 0.2, origin=(-6.0, -6.0, 0.0))
+    R = 2.5
+    sp = I.disk_field([0.4, -0.3, -2.0], [0, 0, 1.0], 100.0, R, 4096)
+    assert sp["sigma_cm"][0] == -R
+    x0, r0 = O.endpoints(_straight(db), ph, sp, 0, 0, 4096)
+    assert np.all(r0 == O.END_STOP)
+    dx, dy = x0[:, 0] - 0.4, x0[:, 1] + 0.3
+    rr = np.hypot(dx, dy)
+    assert rr.max() <= R * (1 + 1e-6) and rr.max() > 0.98 * R
+    assert stats.kstest((rr / R) ** 2, "uniform").pvalue > 1e-3
+    assert stats.kstest((np.arctan2(dy, dx) + np.pi) / (2 * np.pi), "uniform").pvalue > 1e-3
+    assert abs(dx.mean()) < 4 * R / 2 / np.sqrt(4096) and abs(dy.mean()) < 4 * R / 2 / np.sqrt(4096)
+    # the same draws with sigma = +R give the Gaussian spot: a different law
+    g, _ = O.endpoints(_straight(db), ph, I.spots([[0.4, -0.3, -2.0]], [[0, 0, 1.0]], [100.0], R, 4096), 0, 0, 4096)
+    assert np.hypot(g[:, 0] - 0.4, g[:, 1] + 0.3).max() > 1.5 * R
+
+
 def test_gantry_direction_straight_tracks():
     db = _straight(I.make_water_track_db([80.0], 1, seed=5))
     ph = I.water_phantom((40, 40, 40), 0.25, origin=(-5.0, -5.0, -5.0))
