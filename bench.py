@@ -63,14 +63,17 @@ def measured_traffic(launch):
 
 def extras(c, plan, nvox, hist_per_step, launch, log):
     """Other rows of the path, timed live: seconds to 2% with the batch
-    estimator of Eq. (1) (six independent batches of the slab workload with the
-    energy tally only, as the paper's batch method); the 1e8-history thorax
-    plan (both tallies, its own tuned launch configuration); the denoiser's
+    estimator of Eq. (1) (six batches of new histories of the slab workload
+    with the energy tally only, as the paper's batch method; the batches share
+    the database, whose own variance the recycling study measures); the 1e8-history thorax
+    plan and the 1e7-history paper-field plan (both tallies, each with its own
+    tuned launch configuration); the denoiser's
     forward pass (256x256x128 volume) and training step (128^3 crop: forward,
     backward, Adam), each the best of three after a warm-up."""
     import numpy as np
     import torch
     from paper_1011_2188_amd import fdc as F
+    from paper_1011_2188_amd import inputs as I
     from paper_1011_2188_amd import workloads as W
 
     def best(f, n=3):
@@ -122,10 +125,35 @@ def extras(c, plan, nvox, hist_per_step, launch, log):
         c.reset_plan(p)
         c.run_histories([p], F.FDC_RUN_VARIANCE)
     t = best(thorax_run)
-    c.set_launch_config(**launch)
     out["thorax_1e8"] = {"seconds": t, "histories_per_s": n / t, "launch": th_launch,
                          "workload": "thorax 256x256x128 x 2 mm, 3 fields x 2000 spots, 1e8 histories, both tallies"}
     log(f"thorax: {n / t:.4g} histories/s")
+    # the paper's kind of test case: 121 MeV disk field (radius 4 cm) on 1 x 1 x 2.5 mm voxels;
+    # its own database (1e5 tracks at 121 MeV) in a second context
+    ph, sp, db_pf = W.paper_field()
+    c2 = F.Context(0, 1, table=I.HU_TABLE_DEFAULT)
+    c2.load_track_db(db_pf)
+    p2 = c2.load_phantom(ph)
+    c2.add_beam_spots(p2, sp)
+    pf_launch, _ = A.tune(c2, [p2], use_cache=False, candidates=th_cands, reps=1)
+    n2 = int(sp["n_histories"].sum())
+    d2 = torch.empty(ph.hu.size, dtype=torch.float64, device="cuda")
+    v2 = torch.empty(ph.hu.size, dtype=torch.float64, device="cuda")
+
+    def pf_run():
+        c2.reset_plan(p2)
+        c2.run_histories([p2], F.FDC_RUN_VARIANCE)
+    t2 = best(pf_run)
+    c2.compute_dose(p2, d2, v2)
+    u2, _, _ = c2.mean_uncertainty(p2, d2, v2, 0.5)
+    c2.close()
+    out["paper_field_1e7"] = {"seconds": t2, "histories_per_s": n2 / t2, "launch": pf_launch,
+                              "mean_uncertainty": u2, "seconds_to_2pct": n2 * (u2 / 0.02) ** 2 / (n2 / t2),
+                              "workload": "thorax 352x240x72 x 1x1x2.5 mm, one 121 MeV field of circular "
+                                          "cross-section (radius 4 cm), 1e7 histories, DB 1e5 tracks at 121 MeV, "
+                                          "both tallies"}
+    log(f"paper field: {n2 / t2:.4g} histories/s, {u2:.4%} at 1e7")
+    c.set_launch_config(**launch)
     g = torch.Generator(device="cuda").manual_seed(0)
     vol = (128, 256, 256)
     net = F.UNet(vol)

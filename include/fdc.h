@@ -75,10 +75,13 @@ enum {
  * deflection applied at the end of the step.  16 bytes. */
 typedef struct { float dx_cm, dE_MeV, theta_rad, phi_rad; } fdc_step;
 
-/* A pencil-beam spot: histories start at pos + sigma*(n1*e1 + n2*e2) moving
- * along dir (unit), where (n1, n2) are standard normal and (e1, e2) the lateral
- * axes of dir: e2 = normalize(dir x a), e1 = e2 x dir, with a = +x if
- * |dir.z| >= 0.9 else +z.  The source region outside the phantom is vacuum. */
+/* A beam spot: histories start at pos + |sigma|*(n1*e1 + n2*e2) moving along
+ * dir (unit), where (e1, e2) are the lateral axes of dir: e2 = normalize(dir x a),
+ * e1 = e2 x dir, with a = +x if |dir.z| >= 0.9 else +z.  sigma >= 0: a pencil
+ * beam, (n1, n2) standard normal; sigma < 0: a field of circular cross-section
+ * (Section 2.5), (n1, n2) uniform over the unit disk, so the start points fill
+ * a disk of radius -sigma uniformly.  The source region outside the phantom is
+ * vacuum. */
 typedef struct {
     float pos_cm[3];
     float dir[3];
@@ -189,7 +192,7 @@ int fdc_load_phantom(fdc_ctx *ctx, int32_t *plan_out, const int16_t *hu, int nx,
  * phase space of incident protons).  Each spot re-traces tracks of the smallest
  * bin energy >= its energy, starting inside the track where the remaining
  * energy equals the spot energy (Section 2.3, task 1).  Errors: FDC_E_ARG (bad
- * plan, NULL, non-finite values, zero direction, negative sigma), FDC_E_RANGE
+ * plan, NULL, non-finite values, zero direction), FDC_E_RANGE
  * (energy below the first or above the last bin energy), FDC_E_STATE (no
  * database loaded). */
 int fdc_add_beam_spots(fdc_ctx *ctx, int32_t plan, const fdc_spot *spots, uint32_t n);

@@ -203,7 +203,6 @@ int check_spot(fdc_ctx *ctx, const fdc_spot &s)
 {
     if (!finite3(s.pos_cm) || !finite3(s.dir) || !std::isfinite(s.energy_MeV) || !std::isfinite(s.sigma_cm))
         return fail(ctx, FDC_E_ARG, "spot has a non-finite field");
-    if (s.sigma_cm < 0.f) return fail(ctx, FDC_E_ARG, "spot sigma is negative");
     const double l = std::sqrt((double)s.dir[0] * s.dir[0] + (double)s.dir[1] * s.dir[1] + (double)s.dir[2] * s.dir[2]);
     if (!(l > 1e-6)) return fail(ctx, FDC_E_ARG, "spot direction is zero");
     if (spot_bin(ctx, s.energy_MeV) < 0)

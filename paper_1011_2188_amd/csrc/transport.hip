@@ -274,14 +274,18 @@ __host__ __device__ void replay_history(const TransportArgs &a, const DevSpot &s
 
     const uint4 xs = philox4x32_10(make_uint4((uint32_t)h, (uint32_t)(h >> 32), sp.spot,
                                               (sp.plan << 4) | kTagSource), a.seed_lo, a.seed_hi);
-    const double r = sqrt(-2.0 * log(u01(xs.x)));
+    // lateral offset: Gaussian of standard deviation sigma (Box-Muller), or for
+    // sigma < 0 uniform over a disk of radius -sigma (radius^2 uniform): the
+    // circular field of Section 2.5
+    const double r = sp.sigma >= 0.f ? sqrt(-2.0 * log(u01(xs.x))) : sqrt(u01(xs.x));
     double sa, ca;
     sincos(2.0 * M_PI * u01(xs.y), &sa, &ca);
     const double n1 = r * ca, n2 = r * sa;
     const float phi0 = (a.flags & kFlagRotate) ? (float)(2.0 * M_PI * u01(xs.z)) : 0.f;
+    const double scale = fabs((double)sp.sigma);
     double p[3];
 #pragma unroll
-    for (int q = 0; q < 3; ++q) p[q] = sp.pos[q] + (double)sp.sigma * (n1 * sp.e1[q] + n2 * sp.e2[q]);
+    for (int q = 0; q < 3; ++q) p[q] = sp.pos[q] + scale * (n1 * sp.e1[q] + n2 * sp.e2[q]);
 
     // ray-box entry (FP64); outside the box is vacuum
     double tin = -__builtin_huge_val(), tout = __builtin_huge_val();

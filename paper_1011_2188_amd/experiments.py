@@ -1,6 +1,8 @@
 """Measurements beyond the benchmark's main line (run on one GPU):
 
   thorax_rate       histories/s on the 1e8-history synthetic thorax plan;
+  paper_field_rate  the same on the paper's own kind of test case (121 MeV
+                    field of circular cross-section, 1 x 1 x 2.5 mm voxels);
   batched           64 thorax-like plans in ONE captured graph launch vs 64
                     separate eager runs (same histories, same tallies);
   denoiser_study    seconds to 2% mean uncertainty, plain vs denoised at equal
@@ -30,8 +32,21 @@ def _sync():
 
 
 def thorax_rate(db, reps=2, tune=True, log=print):
-    import torch
     ph, sp, _ = W.thorax()
+    return workload_rate(ph, sp, db, reps, tune, log, "thorax")
+
+
+def paper_field_rate(reps=2, tune=True, log=print, total=10_000_000):
+    """The paper's test case with synthetic anatomy (Section 2.5): 121 MeV disk
+    field of 4 cm radius on 1 x 1 x 2.5 mm voxels."""
+    ph, sp, db = W.paper_field(total)
+    return workload_rate(ph, sp, db, reps, tune, log, "paper field")
+
+
+def workload_rate(ph, sp, db, reps=2, tune=True, log=print, name="workload"):
+    """Histories/s of one plan (both tallies, dose included), its mean
+    uncertainty and the seconds to 2% it implies (Eq. (2))."""
+    import torch
     c = F.Context(0, 1, table=I.HU_TABLE_DEFAULT)
     c.load_track_db(db)
     p = c.load_phantom(ph)
@@ -53,7 +68,7 @@ def thorax_rate(db, reps=2, tune=True, log=print):
     n2 = n * (u / 0.02) ** 2
     out = {"histories": n, "seconds": best, "histories_per_s": n / best, "launch": cfg,
            "mean_uncertainty": u, "seconds_to_2pct": n2 / (n / best)}
-    log(f"thorax: {out}")
+    log(f"{name}: {out}")
     c.close()
     return out
 

@@ -199,13 +199,15 @@ def thorax_phantom(n=(256, 256, 128), voxel_cm=0.2, seed=2188, scale=(1.0, 1.0, 
                    lung_axes=(5.0, 7.0, 10.0), spine_centre_y=-8.0, spine_radius=1.5):
     """Synthetic thorax: air (-1000) around an elliptic body cylinder along z
     (HU ~ N(40,20)), two lung ellipsoids (HU ~ N(-800,50)) and a spine cylinder
-    (HU ~ N(1000,100)); i.i.d. HU per voxel, rounded to int16.  Centred on 0."""
+    (HU ~ N(1000,100)); i.i.d. HU per voxel, rounded to int16.  Centred on 0.
+    voxel_cm: one size, or (x, y, z) sizes for anisotropic voxels."""
     nx, ny, nz = n
     sx, sy, sz = scale
+    vx, vy, vz = (voxel_cm,) * 3 if np.ndim(voxel_cm) == 0 else tuple(float(v) for v in voxel_cm)
     rng = np.random.default_rng(int(seed))
-    x = (np.arange(nx) + 0.5) * voxel_cm - 0.5 * nx * voxel_cm
-    y = (np.arange(ny) + 0.5) * voxel_cm - 0.5 * ny * voxel_cm
-    z = (np.arange(nz) + 0.5) * voxel_cm - 0.5 * nz * voxel_cm
+    x = (np.arange(nx) + 0.5) * vx - 0.5 * nx * vx
+    y = (np.arange(ny) + 0.5) * vy - 0.5 * ny * vy
+    z = (np.arange(nz) + 0.5) * vz - 0.5 * nz * vz
     X, Y = x[None, :], y[:, None]              # cylinders along z: masks on the (y, x) plane
     shape = (nz, ny, nx)
     hu = np.full(shape, -1000.0)
@@ -220,8 +222,8 @@ def thorax_phantom(n=(256, 256, 128), voxel_cm=0.2, seed=2188, scale=(1.0, 1.0, 
     spine = np.broadcast_to(X ** 2 + (Y - spine_centre_y * sy) ** 2 <= (spine_radius * min(sx, sy)) ** 2, shape)
     hu[spine] = rng.normal(1000.0, 100.0, int(spine.sum()))
     hu = np.clip(np.rint(hu), -32768, 32767).astype(np.int16)
-    vox = np.full(3, voxel_cm, np.float32)
-    origin = np.array([-0.5 * nx * voxel_cm, -0.5 * ny * voxel_cm, -0.5 * nz * voxel_cm], np.float32)
+    vox = np.array([vx, vy, vz], np.float32)
+    origin = np.array([-0.5 * nx * vx, -0.5 * ny * vy, -0.5 * nz * vz], np.float32)
     return Phantom(hu, vox, origin)
 
 
@@ -237,6 +239,13 @@ def spots(pos, dirs, energies, sigmas, n_histories):
     s["sigma_cm"] = np.broadcast_to(np.asarray(sigmas, np.float32), (k,))
     s["n_histories"] = np.broadcast_to(np.asarray(n_histories, np.uint64), (k,))
     return s
+
+
+def disk_field(pos, direction, energy_MeV, radius_cm, n_histories):
+    """One mono-energetic field of circular cross-section: start points uniform
+    over a disk of radius_cm around pos, perpendicular to direction (Section
+    2.5's test field); encoded as a spot with sigma = -radius."""
+    return spots([pos], [direction], [energy_MeV], -float(radius_cm), n_histories)
 
 
 def gantry_direction(gantry_deg):

@@ -91,3 +91,19 @@ def batched_plans(n_plans=64, seed=2188, hist_scale=1.0):
         sp["n_histories"] = h
         plans.append((ph, sp))
     return plans
+
+
+PAPER_ISO = (7.0, -1.0, 0.0)
+
+
+def paper_field(total=10_000_000, n_tracks=100_000, n=(352, 240, 72), voxel_cm=(0.1, 0.1, 0.25)):
+    """The paper's test case (Section 2.5) with synthetic anatomy: a thorax of
+    1 x 1 x 2.5 mm voxels (352 x 240 x 72 = 6.08e6 voxels, against the CT's
+    6.06e6), a mono-energetic 121 MeV field of circular cross-section (radius
+    4 cm, uniform) aimed through the right lung along -y, and a database of
+    1e5 tracks at 121 MeV (the paper's database size)."""
+    ph = I.thorax_phantom(n, voxel_cm, seed=2188)
+    d = I.gantry_direction(0.0)
+    pos = np.asarray(PAPER_ISO) - 30.0 * d
+    sp = I.disk_field(pos, d, 121.0, 4.0, np.uint64(total))
+    return ph, sp, water_db(n_tracks, 2188, 121.0)

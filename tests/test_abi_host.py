@@ -104,7 +104,9 @@ def test_spots_and_run_validation(ctx):
     _expect(F.FDC_E_RANGE, ctx.add_beam_spots, p, I.spots([[0, 0, -1]], [[0, 0, 1]], [99.9], 0.3, 1))
     _expect(F.FDC_E_RANGE, ctx.add_beam_spots, p, I.spots([[0, 0, -1]], [[0, 0, 1]], [105.1], 0.3, 1))
     _expect(F.FDC_E_ARG, ctx.add_beam_spots, p, I.spots([[0, 0, -1]], [[0, 0, 0]], [101.0], 0.3, 1))
-    _expect(F.FDC_E_ARG, ctx.add_beam_spots, p, I.spots([[0, 0, -1]], [[0, 0, 1]], [101.0], -0.3, 1))
+    ctx.add_beam_spots(p, I.spots([[0, 0, -1]], [[0, 0, 1]], [101.0], -0.3, 1))     # a disk field
+    _expect(F.FDC_E_ARG, ctx.add_beam_spots, p, I.spots([[0, 0, -1]], [[0, 0, 1]], [101.0], np.inf, 1))
+    _expect(F.FDC_E_ARG, ctx.add_beam_spots, p, I.spots([[0, 0, -1]], [[0, 0, 1]], [101.0], -np.inf, 1))
     _expect(F.FDC_E_ARG, ctx.add_beam_spots, p, I.spots([[np.nan, 0, -1]], [[0, 0, 1]], [101.0], 0.3, 1))
     _expect(F.FDC_E_ARG, ctx.add_beam_spots, 7, sp)
     _expect(F.FDC_E_ARG, ctx.run_histories, [p, p])

@@ -166,6 +166,23 @@ def test_reuse_factor_parity(R):
     assert ok >= 0.999 * n
 
 
+def test_disk_field_anisotropic_voxels_parity():
+    """The paper's kind of test field (Section 2.5): a mono-energetic field of
+    circular cross-section on a thorax of anisotropic voxels (4 x 4 x 10 mm),
+    against the oracle: energy identity, dose, and end points."""
+    ph = I.thorax_phantom((80, 60, 30), (0.4, 0.4, 1.0), seed=5, scale=(0.8, 0.9, 1.0))
+    db = W.water_db(600, 2188, 121.0)
+    d = I.gantry_direction(0.0)
+    sp = I.disk_field(np.array([5.0, -1.0, 0.0]) - 30.0 * d, d, 121.0, 2.5, 20_000)
+    c = ctx_for(db)
+    g = gpu_run(c, ph, sp)
+    o = O.replay(db, ph, sp, seed=SEED)
+    check_energy(g, o)
+    check_dose(g, o, ph, 20_000)
+    ok, n = check_endpoints(c, g["plan"], db, ph, sp, 0, 1000, 2000)
+    assert ok >= 0.999 * n
+
+
 # ------------------------------------------------------ order independence --
 def _tallies(db, ph, sp, **cfg):
     c = ctx_for(db, **cfg)
@@ -341,6 +358,26 @@ def test_full_size_thorax_sampled():
     for s in range(0, len(sp), 500):
         n0 = int(sp["n_histories"][s])
         ok, n = check_endpoints(c, g["plan"], db, ph, sp, s, n0 - 64, 64)
+        good += ok
+        tot += n
+    assert good >= 0.999 * tot
+
+
+def test_full_size_paper_field_sampled():
+    """The paper-field workload at full size (6.08e6 voxels of 1 x 1 x 2.5 mm,
+    121 MeV disk of 4 cm radius, 1e7 histories) in the benchmark's launch
+    configuration: tallies bitwise equal to the global-atomic launch, energy
+    identity, and sampled end points against the oracle."""
+    ph, sp, db = W.paper_field()
+    c = ctx_for(db, **BENCH_LAUNCH)
+    g = gpu_run(c, ph, sp)
+    assert g["n_histories"] == int(sp["n_histories"].sum())
+    assert g["deposited"] + g["escaped"] == g["incident"]
+    ref = gpu_run(ctx_for(db, waves_per_block=4, blocks_per_cu=4), ph, sp)
+    assert np.array_equal(g["E"], ref["E"]) and np.array_equal(g["E2"], ref["E2"])
+    tot = good = 0
+    for h0 in (0, 4_000_000, 9_999_000):
+        ok, n = check_endpoints(c, g["plan"], db, ph, sp, 0, h0, 1000)
         good += ok
         tot += n
     assert good >= 0.999 * tot
