@@ -32,13 +32,17 @@ HBM_PEAK_GBS = 8000.0
 # Algorithmic work per history of the slab workload, counted exactly by
 # replaying a 25 x 2000-history sample: steps S = 95.03, voxel-walk iterations
 # C = 205.38 (no vacuum), flushes G = 111.71.  Bytes per history =
-# 16 B per step record / 64 histories sharing it + 2 B voxel index per walk
-# iteration + 8 B per tally atomic (G, doubled with the squared-energy tally).
+# 16 B per step record / the histories sharing one read of it (64 when a wave
+# replays one track; 1 when the histories run in start-position order, each
+# lane on its own track) + 2 B voxel index per walk iteration + 8 B per tally
+# update (G, doubled with the squared-energy tally).
 SLAB_S, SLAB_C, SLAB_G = 95.03, 205.38, 111.71
+LAUNCH_KEYS = ("waves_per_block", "blocks_per_cu", "tally_slots", "units_per_wave", "tally_mode", "source_order")
 
 
-def slab_bytes_per_history(variance: bool) -> float:
-    return 16.0 * SLAB_S / 64.0 + 2.0 * SLAB_C + 8.0 * SLAB_G * (2.0 if variance else 1.0)
+def slab_bytes_per_history(variance: bool, source_order: int = 0) -> float:
+    shared = 1.0 if source_order else 64.0
+    return 16.0 * SLAB_S / shared + 2.0 * SLAB_C + 8.0 * SLAB_G * (2.0 if variance else 1.0)
 
 
 def measured_traffic(launch):
@@ -54,8 +58,7 @@ def measured_traffic(launch):
                        for f in ("transport.hip", "fdc_device.h"))
     except (OSError, ValueError):
         return None
-    want = ",".join(str(launch.get(k, 0)) for k in ("waves_per_block", "blocks_per_cu", "tally_slots",
-                                                     "units_per_wave", "tally_mode"))
+    want = ",".join(str(launch.get(k, 0)) for k in LAUNCH_KEYS)
     if fields.get("kernel_source_sha1") != hashlib.sha1(src).hexdigest() or fields.get("launch") != want:
         return None
     return float(fields["traffic_bytes_per_launch"])
@@ -87,9 +90,14 @@ def extras(c, plan, nvox, hist_per_step, launch, log):
             ts.append(time.perf_counter() - t)
         return min(ts)
 
+    from paper_1011_2188_amd import autotune as A
     out = {}
     nb = 6
     doses = torch.empty((nb, nvox), dtype=torch.float64, device="cuda")
+    # the energy-tally-only runs get their own launch configuration (untimed tuning)
+    cache_cands = [dict(waves_per_block=16, blocks_per_cu=1, tally_slots=8064, units_per_wave=1, tally_mode=m,
+                        source_order=o) for m in (1, 2) for o in (0, 1)]
+    eq1_launch, _ = A.tune(c, [plan], 0, use_cache=False, candidates=cache_cands, reps=1)
     torch.cuda.synchronize()
     t = time.perf_counter()
     for b in range(nb):                       # new histories each batch (counters continue)
@@ -104,7 +112,9 @@ def extras(c, plan, nvox, hist_per_step, launch, log):
     ub, _, _ = c.mean_uncertainty(plan, mean, sigma.square(), 0.5)
     n_tot = nb * hist_per_step
     n2 = n_tot * (ub / 0.02) ** 2
+    c.set_launch_config(**launch)
     out["batch_method_eq1"] = {"batches": nb, "histories": n_tot, "seconds": tb, "histories_per_s": n_tot / tb,
+                               "launch": eq1_launch,
                                "mean_uncertainty": ub, "histories_to_2pct": n2,
                                "seconds_to_2pct": n2 / (n_tot / tb)}
     log(f"batch method: {ub:.4%} at {n_tot} histories -> 2% in {n2 / (n_tot / tb):.4g} s")
@@ -115,11 +125,7 @@ def extras(c, plan, nvox, hist_per_step, launch, log):
 
     # the thorax plan gets its own launch configuration (untimed tuning over the
     # LDS-cache candidates), then the slab's is restored
-    from paper_1011_2188_amd import autotune as A
-    th_cands = [dict(waves_per_block=16, blocks_per_cu=1, tally_slots=8064, units_per_wave=1, tally_mode=m)
-                for m in (1, 2)] + [dict(waves_per_block=8, blocks_per_cu=1, tally_slots=8064, units_per_wave=1,
-                                         tally_mode=2)]
-    th_launch, _ = A.tune(c, [p], use_cache=False, candidates=th_cands, reps=1)
+    th_launch, _ = A.tune(c, [p], use_cache=False, candidates=cache_cands, reps=1)
 
     def thorax_run():
         c.reset_plan(p)
@@ -135,7 +141,7 @@ def extras(c, plan, nvox, hist_per_step, launch, log):
     c2.load_track_db(db_pf)
     p2 = c2.load_phantom(ph)
     c2.add_beam_spots(p2, sp)
-    pf_launch, _ = A.tune(c2, [p2], use_cache=False, candidates=th_cands, reps=1)
+    pf_launch, _ = A.tune(c2, [p2], use_cache=False, candidates=cache_cands, reps=1)
     n2 = int(sp["n_histories"].sum())
     d2 = torch.empty(ph.hu.size, dtype=torch.float64, device="cuda")
     v2 = torch.empty(ph.hu.size, dtype=torch.float64, device="cuda")
@@ -260,7 +266,7 @@ def main():
             log(f"  {v * 1e3:8.2f} ms  {k}")
     else:
         v = [int(x) for x in args.launch.split(",")]
-        launch = dict(zip(("waves_per_block", "blocks_per_cu", "tally_slots", "units_per_wave", "tally_mode"), v))
+        launch = dict(zip(LAUNCH_KEYS, v))
         c.set_launch_config(**launch)
     kernel = "transport_lds_kernel" if launch.get("tally_slots", 0) else "transport_kernel"
     nvox = ph.hu.size
@@ -268,30 +274,26 @@ def main():
     dose = torch.empty(nvox, dtype=torch.float64, device=dev)
     var = torch.empty(nvox, dtype=torch.float64, device=dev) if variance else None
 
-    ev = []
-
-    def step(timed):
+    def step():
         c.reset_plan(plan, stream=stream)
-        if timed:
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record(stream)
         c.run_histories([plan], flags, stream=stream)
-        if timed:
-            e1.record(stream)
-            ev.append((e0, e1))
         c.compute_dose(plan, dose, var, stream=stream)
 
     for _ in range(args.warmup):
-        step(False)
+        step()
     torch.cuda.synchronize()
+    # the library brackets each run's transport kernel with HIP events on the
+    # run's stream (read back after the timed region)
+    c.set_timing(True)
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        step(True)
+        step()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     wall = t1 - t0
     value = hist_per_step * args.steps / wall
-    kern_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+    kern_ms = float(np.mean(c.transport_times(min(args.steps, 64))))
+    c.set_timing(False)
     log(f"{args.steps} steps in {wall:.3f} s: {value:.4g} histories/s; transport {kern_ms:.3f} ms per launch")
 
     # seconds to 2% mean uncertainty (Eq. (2), voxels above Dmax/2), from the last step
@@ -309,7 +311,7 @@ def main():
         log(f"mean uncertainty {u0:.4%} at {hist_per_step} histories -> 2% at {n2:.3g} histories, "
             f"{n2 / value:.3g} s")
 
-    bph = slab_bytes_per_history(variance)
+    bph = slab_bytes_per_history(variance, launch.get("source_order", 0))
     achieved = bph * hist_per_step / (kern_ms * 1e-3) / 1e9
     updates = SLAB_G * (2.0 if variance else 1.0) * hist_per_step / (kern_ms * 1e-3)
     traffic = measured_traffic(launch)

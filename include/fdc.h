@@ -123,7 +123,16 @@ typedef struct {
                                    take units of their workgroup's chunk without
                                    barriers, one flush at the end; launches of several
                                    plans run as mode 1)                                */
-    uint32_t reserved[3];
+    uint32_t source_order;      /* 0 = a wave unit takes 64 consecutive histories of a
+                                   spot, which share one database track; 1 = the
+                                   histories of each spot are processed in an order
+                                   sorted by start position (a Morton code on a 0.2 mm
+                                   grid of the lateral offset), each lane on its own
+                                   track: lanes of a wave start close together, which
+                                   lets the LDS cache merge deposits of broad fields.
+                                   Costs a sort per run (device memory about 24 B per
+                                   history); ignored by captured graphs.             */
+    uint32_t reserved[2];
 } fdc_launch_config;
 
 typedef void *(*fdc_alloc_fn)(size_t bytes, void *user);
@@ -327,6 +336,18 @@ int fdc_denoise_input(fdc_ctx *ctx, int32_t plan, const double *dose_dev, const 
 
 /* Number of compute units of the context's device (for launch sizing). */
 int fdc_device_cus(fdc_ctx *ctx, int *cus);
+
+/* Measurement aid: with timing on, every fdc_run_histories records a pair of
+ * HIP events on its stream around the transport kernel alone (not the source
+ * ordering, the queue reset or the history-counter update); the context keeps
+ * the last 64 pairs.  fdc_set_timing(ctx, 1) turns it on and forgets earlier
+ * pairs (0 turns it off).  fdc_transport_times writes the kernel durations
+ * (milliseconds) of the last n timed runs, oldest first, into the host array
+ * ms[n]; it waits for the last one to finish.  Captured graphs are not timed.
+ * Errors: FDC_E_ARG (NULL), FDC_E_STATE (no device; n above the runs timed
+ * and kept), FDC_E_HIP. */
+int fdc_set_timing(fdc_ctx *ctx, int on);
+int fdc_transport_times(fdc_ctx *ctx, float *ms, uint32_t n);
 
 /* ---------------------------------------------------------------------------
  * Dose denoiser: a 3-level 3D U-Net mapping (low-history dose, density) to a

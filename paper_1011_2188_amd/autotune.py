@@ -1,7 +1,8 @@
 """Autotuner for the launch knobs of fdc_run_histories.
 
 Only knobs that cannot change a result bit are searched: waves per workgroup,
-persistent grid size, the LDS sub-tally's kind and size, and units per wave per round
+persistent grid size, the LDS sub-tally's kind and size, units per wave per round
+and the processing order of the histories
 (integer tallies make every setting bitwise identical; the GPU tests check
 it).  Each candidate is timed on the caller's real plans; the plans are then
 rewound (tallies cleared, history counters back to 0), so tuning leaves no
@@ -27,6 +28,9 @@ CANDIDATES = (
     + [dict(waves_per_block=16, blocks_per_cu=1, tally_slots=8064, units_per_wave=1, tally_mode=2),
        dict(waves_per_block=8, blocks_per_cu=1, tally_slots=8064, units_per_wave=1, tally_mode=2)]
     + [dict(waves_per_block=8, blocks_per_cu=2, tally_slots=3008, units_per_wave=u, tally_mode=1) for u in (2, 4)]
+    # histories in start-position order (pays off for broad fields)
+    + [dict(waves_per_block=16, blocks_per_cu=1, tally_slots=8064, units_per_wave=1, tally_mode=m, source_order=1)
+       for m in (1, 2)]
 )
 
 

@@ -11,7 +11,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libfdc.so")
 BUILD = os.path.join(ROOT, "_build")
-SOURCES = ["api.hip", "transport.hip", "aux_kernels.hip", "metrics.hip", "unet.hip"]
+SOURCES = ["api.hip", "transport.hip", "aux_kernels.hip", "order.hip", "metrics.hip", "unet.hip"]
 ARCH = os.environ.get("FDC_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [

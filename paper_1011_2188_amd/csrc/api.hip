@@ -62,7 +62,6 @@ struct fdc_ctx {
 
     // track database
     float4 *steps = nullptr;
-    float4 *step_aux = nullptr;
     unsigned long long *track_off = nullptr;
     long long *track_T = nullptr;
     uint32_t *bin_first = nullptr;
@@ -96,12 +95,28 @@ struct fdc_ctx {
     bool items_ev_pending = false;
     unsigned long long *d_queue = nullptr;
 
+    // processing order by start position (launch config source_order = 1)
+    unsigned long long *d_keys = nullptr;    // 2 x histories
+    size_t keys_cap = 0;
+    uint32_t *d_vals = nullptr;              // 2 x histories
+    size_t vals_cap = 0;
+    uint32_t *d_order = nullptr;             // units x 64
+    size_t order_cap = 0;
+    unsigned char *d_sort_tmp = nullptr;
+    size_t sort_tmp_cap = 0;
+
     // read-back scratch
     double *d_dose = nullptr, *d_var = nullptr;
     size_t dose_cap = 0;
 
     fdc_launch_config cfg{};
     hipStream_t cap_stream = nullptr;        // for graph capture
+
+    // optional timing of the transport kernel: a ring of event pairs
+    static constexpr uint32_t kTimeRing = 64;
+    bool timing = false;
+    hipEvent_t t_start[kTimeRing] = {}, t_end[kTimeRing] = {};
+    uint64_t t_count = 0;
 };
 
 struct fdc_graph {
@@ -345,7 +360,6 @@ TransportArgs base_args(const fdc_ctx *ctx)
 {
     TransportArgs a{};
     a.steps = ctx->steps;
-    a.step_aux = ctx->step_aux;
     a.track_off = ctx->track_off;
     a.track_T = ctx->track_T;
     a.bin_first = ctx->bin_first;
@@ -358,6 +372,25 @@ TransportArgs base_args(const fdc_ctx *ctx)
     a.seed_hi = (uint32_t)(ctx->seed >> 32);
     a.R = ctx->R;
     return a;
+}
+
+// grow a device buffer to at least n elements (contents not kept; a buffer
+// being replaced may still be read by work on s, so s is drained first)
+template <class T>
+bool grow(fdc_ctx *ctx, T *&buf, size_t &cap, size_t n, hipStream_t s)
+{
+    n = std::max<size_t>(n, 1);
+    if (cap >= n && buf) return true;
+    if (buf) {
+        if (hipStreamSynchronize(s) != hipSuccess) return false;
+        dfree(ctx, buf);
+    }
+    buf = nullptr;
+    cap = 0;
+    buf = (T *)dalloc(ctx, n * sizeof(T));
+    if (!buf) return false;
+    cap = n;
+    return true;
 }
 
 } // namespace
@@ -410,15 +443,20 @@ int fdc_destroy(fdc_ctx *ctx)
     for (PlanHost &P : ctx->plans) {
         dfree(ctx, P.idx); dfree(ctx, P.E); dfree(ctx, P.E2); dfree(ctx, P.acc);
     }
-    dfree(ctx, ctx->steps); dfree(ctx, ctx->step_aux); dfree(ctx, ctx->track_off); dfree(ctx, ctx->track_T);
+    dfree(ctx, ctx->steps); dfree(ctx, ctx->track_off); dfree(ctx, ctx->track_T);
     dfree(ctx, ctx->bin_first);
     dfree(ctx, ctx->lut); dfree(ctx, ctx->rho_lut);
     dfree(ctx, ctx->d_plans); dfree(ctx, ctx->d_spots); dfree(ctx, ctx->d_items); dfree(ctx, ctx->d_queue);
+    dfree(ctx, ctx->d_keys); dfree(ctx, ctx->d_vals); dfree(ctx, ctx->d_order); dfree(ctx, ctx->d_sort_tmp);
     dfree(ctx, ctx->d_hnext);
     if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
     dfree(ctx, ctx->d_dose); dfree(ctx, ctx->d_var);
     if (ctx->h_items) (void)hipHostFree(ctx->h_items);
     if (ctx->items_ev) (void)hipEventDestroy(ctx->items_ev);
+    for (uint32_t k = 0; k < fdc_ctx::kTimeRing; ++k) {
+        if (ctx->t_start[k]) (void)hipEventDestroy(ctx->t_start[k]);
+        if (ctx->t_end[k]) (void)hipEventDestroy(ctx->t_end[k]);
+    }
     delete ctx;
     return FDC_OK;
 }
@@ -530,31 +568,29 @@ int fdc_load_track_db(fdc_ctx *ctx, const fdc_step *steps, uint64_t n_steps, con
     int rc = ensure_table(ctx);
     if (rc) return rc;
     float4 *d_steps = dalloc_n<float4>(ctx, n_steps);
-    float4 *d_aux = dalloc_n<float4>(ctx, n_steps);
     unsigned long long *d_off = dalloc_n<unsigned long long>(ctx, (size_t)n_tracks + 1);
     long long *d_T = dalloc_n<long long>(ctx, n_tracks);
     uint32_t *d_bf = dalloc_n<uint32_t>(ctx, (size_t)n_bins + 1);
-    if (!d_steps || !d_aux || !d_off || !d_T || !d_bf) {
-        dfree(ctx, d_steps); dfree(ctx, d_aux); dfree(ctx, d_off); dfree(ctx, d_T); dfree(ctx, d_bf);
+    if (!d_steps || !d_off || !d_T || !d_bf) {
+        dfree(ctx, d_steps); dfree(ctx, d_off); dfree(ctx, d_T); dfree(ctx, d_bf);
         return fail(ctx, FDC_E_NOMEM, "track database: device allocation of %llu bytes failed",
-                    (unsigned long long)(2 * n_steps * sizeof(float4)));
+                    (unsigned long long)(n_steps * sizeof(float4)));
     }
     hipStream_t s = S(hip_stream);
     hipError_t e = hipMemcpyAsync(d_steps, steps, n_steps * sizeof(float4), hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipMemcpyAsync(d_off, track_off, ((size_t)n_tracks + 1) * 8, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipMemcpyAsync(d_bf, bin_first, ((size_t)n_bins + 1) * 4, hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = launch_track_energy(d_steps, d_off, d_T, n_tracks, s);
-    if (e == hipSuccess) e = launch_step_aux(d_steps, d_aux, n_steps, s);
+    if (e == hipSuccess) e = launch_track_energy(d_steps, d_off, d_T, n_tracks, s);   // before the compaction
+    if (e == hipSuccess) e = launch_compact_steps(d_steps, n_steps, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
-        dfree(ctx, d_steps); dfree(ctx, d_aux); dfree(ctx, d_off); dfree(ctx, d_T); dfree(ctx, d_bf);
+        dfree(ctx, d_steps); dfree(ctx, d_off); dfree(ctx, d_T); dfree(ctx, d_bf);
         return fail(ctx, FDC_E_HIP, "track database upload: %s", hipGetErrorString(e));
     }
     HIPCHK(hipDeviceSynchronize());
-    dfree(ctx, ctx->steps); dfree(ctx, ctx->step_aux); dfree(ctx, ctx->track_off); dfree(ctx, ctx->track_T);
+    dfree(ctx, ctx->steps); dfree(ctx, ctx->track_off); dfree(ctx, ctx->track_T);
     dfree(ctx, ctx->bin_first);
     ctx->steps = d_steps;
-    ctx->step_aux = d_aux;
     ctx->track_off = d_off;
     ctx->track_T = d_T;
     ctx->bin_first = d_bf;
@@ -676,7 +712,7 @@ static void account_run(fdc_ctx *ctx, const int32_t *plans, uint32_t n_plans, ui
 static unsigned long long build_items(const fdc_ctx *ctx, const int32_t *plans, uint32_t n_plans,
                                       std::vector<WorkItem> &items)
 {
-    unsigned long long units = 0;
+    unsigned long long units = 0, hist = 0;
     items.clear();
     for (uint32_t i = 0; i < n_plans; ++i) {
         const PlanHost &P = ctx->plans[plans[i]];
@@ -687,12 +723,35 @@ static unsigned long long build_items(const fdc_ctx *ctx, const int32_t *plans, 
             w.h0 = 0;                              // the spot's device counter is added
             w.n = n;
             w.unit0 = units;
+            w.first = hist;
+            hist += n;
             w.gspot = ctx->spot_base[plans[i]] + (uint32_t)j;
             items.push_back(w);
             units += units_for(n);
         }
     }
     return units;
+}
+
+// the run's processing order by start position: keys, sort, per-unit table
+// (enqueued on s after the work table's upload)
+static int enqueue_source_order(fdc_ctx *ctx, const std::vector<WorkItem> &items, unsigned long long units, hipStream_t s)
+{
+    unsigned long long n_total = 0;
+    for (const WorkItem &w : items) {
+        if (w.n >= 0xFFFFFFFFull) return fail(ctx, FDC_E_ARG, "run: source_order needs fewer than 2^32 histories per spot");
+        n_total += w.n;
+    }
+    if (n_total >= 0x7FFFFFFFull) return fail(ctx, FDC_E_ARG, "run: source_order needs fewer than 2^31 histories per run");
+    const size_t tmp = source_order_temp_bytes(n_total, (uint32_t)items.size());
+    if (!grow(ctx, ctx->d_keys, ctx->keys_cap, 2 * n_total, s) || !grow(ctx, ctx->d_vals, ctx->vals_cap, 2 * n_total, s) ||
+        !grow(ctx, ctx->d_order, ctx->order_cap, units * kWave, s) ||
+        !grow(ctx, ctx->d_sort_tmp, ctx->sort_tmp_cap, tmp, s))
+        return fail(ctx, FDC_E_NOMEM, "run: source order buffers");
+    HIPCHK(launch_source_order(ctx->d_items, (uint32_t)items.size(), n_total, units, ctx->d_spots, ctx->d_hnext,
+                               (uint32_t)ctx->seed, (uint32_t)(ctx->seed >> 32), ctx->d_keys, ctx->d_keys + n_total,
+                               ctx->d_vals, ctx->d_vals + n_total, ctx->d_sort_tmp, ctx->sort_tmp_cap, ctx->d_order, s));
+    return FDC_OK;
 }
 
 static bool one_plan(const int32_t *plans, uint32_t n_plans)
@@ -704,7 +763,28 @@ static bool one_plan(const int32_t *plans, uint32_t n_plans)
 
 // transport launch for a work table already on the device; the queue counter
 // is cleared with a kernel so that the sequence can be captured in a graph
-static int enqueue_transport(fdc_ctx *ctx, TransportArgs a, uint32_t flags, hipStream_t s, bool one_plan)
+static int enqueue_transport_kernel(fdc_ctx *ctx, TransportArgs a, uint32_t flags, hipStream_t s, bool one_plan);
+
+// the transport kernel, bracketed by the context's timing events when timing
+// is on (eager runs only)
+static int enqueue_transport(fdc_ctx *ctx, TransportArgs a, uint32_t flags, hipStream_t s, bool one_plan,
+                             bool timed = false)
+{
+    if (!timed || !ctx->timing) return enqueue_transport_kernel(ctx, a, flags, s, one_plan);
+    const uint32_t k = (uint32_t)(ctx->t_count % fdc_ctx::kTimeRing);
+    if (!ctx->t_start[k]) {
+        HIPCHK(hipEventCreate(&ctx->t_start[k]));
+        HIPCHK(hipEventCreate(&ctx->t_end[k]));
+    }
+    HIPCHK(hipEventRecord(ctx->t_start[k], s));
+    const int rc = enqueue_transport_kernel(ctx, a, flags, s, one_plan);
+    if (rc) return rc;
+    HIPCHK(hipEventRecord(ctx->t_end[k], s));
+    ctx->t_count++;
+    return FDC_OK;
+}
+
+static int enqueue_transport_kernel(fdc_ctx *ctx, TransportArgs a, uint32_t flags, hipStream_t s, bool one_plan)
 {
     const uint32_t wpb = ctx->cfg.waves_per_block;
     const bool variance = (flags & FDC_RUN_VARIANCE) != 0;
@@ -765,10 +845,42 @@ int fdc_run_histories(fdc_ctx *ctx, const int32_t *plans, uint32_t n_plans, uint
     a.n_items = (uint32_t)items.size();
     a.n_units = units;
     a.flags = flags;
-    rc = enqueue_transport(ctx, a, flags, s, one_plan(plans, n_plans));
+    if (ctx->cfg.source_order) {
+        rc = enqueue_source_order(ctx, items, units, s);
+        if (rc) return rc;
+        a.order = ctx->d_order;
+    }
+    rc = enqueue_transport(ctx, a, flags, s, one_plan(plans, n_plans), true);
     if (rc) return rc;
     HIPCHK(launch_advance(ctx->d_items, (uint32_t)items.size(), ctx->d_hnext, ctx->d_spots, ctx->d_plans, s));
     account_run(ctx, plans, n_plans, flags, false);
+    return FDC_OK;
+}
+
+int fdc_set_timing(fdc_ctx *ctx, int on)
+{
+    if (!ctx) return FDC_E_ARG;
+    if (ctx->dry && on) return fail(ctx, FDC_E_STATE, "timing: context has no device");
+    ctx->timing = on != 0;
+    ctx->t_count = 0;
+    return FDC_OK;
+}
+
+int fdc_transport_times(fdc_ctx *ctx, float *ms, uint32_t n)
+{
+    if (!ctx) return FDC_E_ARG;
+    if (n && !ms) return fail(ctx, FDC_E_ARG, "timing: NULL output");
+    const uint64_t have = std::min<uint64_t>(ctx->t_count, fdc_ctx::kTimeRing);
+    if (n > have) return fail(ctx, FDC_E_STATE, "timing: %u runs asked, %llu timed and kept", n,
+                             (unsigned long long)have);
+    if (n == 0) return FDC_OK;
+    HIPCHK(hipSetDevice(ctx->device));
+    const uint32_t last = (uint32_t)((ctx->t_count - 1) % fdc_ctx::kTimeRing);
+    HIPCHK(hipEventSynchronize(ctx->t_end[last]));
+    for (uint32_t i = 0; i < n; ++i) {
+        const uint32_t k = (uint32_t)((ctx->t_count - n + i) % fdc_ctx::kTimeRing);
+        HIPCHK(hipEventElapsedTime(&ms[i], ctx->t_start[k], ctx->t_end[k]));
+    }
     return FDC_OK;
 }
 
@@ -987,7 +1099,10 @@ int fdc_debug_endpoints(fdc_ctx *ctx, int32_t plan, uint32_t spot, uint64_t h0, 
         dfree(ctx, d_xyz); dfree(ctx, d_reason); dfree(ctx, d_item);
         return fail(ctx, FDC_E_NOMEM, "endpoints: allocation failed");
     }
-    WorkItem w{h0, n, 0, ctx->spot_base[plan] + spot, 0};
+    WorkItem w{};
+    w.h0 = h0;
+    w.n = n;
+    w.gspot = ctx->spot_base[plan] + spot;
     const unsigned long long units = units_for(n);
     TransportArgs a = base_args(ctx);
     a.items = d_item;
@@ -1061,6 +1176,7 @@ int fdc_set_launch_config(fdc_ctx *ctx, const fdc_launch_config *cfg)
             return fail(ctx, FDC_E_ARG, "launch config: LDS sub-tally of %u slots does not fit", t);
     }
     if (cfg->units_per_wave > 64) return fail(ctx, FDC_E_ARG, "launch config: units_per_wave must be 0..64");
+    if (cfg->source_order > 1) return fail(ctx, FDC_E_ARG, "launch config: source_order must be 0 or 1");
     ctx->cfg = *cfg;
     return FDC_OK;
 }

@@ -52,17 +52,18 @@ __global__ void track_energy_kernel(const float4 *__restrict__ steps, const unsi
     T[t] = s;
 }
 
-// per-step terms the walk would otherwise compute for every lane: the azimuth's
-// cosine and sine (the same sincosf the walk uses, so the values are
-// identical) and the reciprocal step length
-__global__ void step_aux_kernel(const float4 *__restrict__ steps, float4 *__restrict__ aux, unsigned long long n)
+// the stored steps, in place, as the walk reads them: (dx, dE, theta, phi) ->
+// (dx, fixed-point dE as int32 bits, theta cos phi, theta sin phi).  One
+// 16-byte record per step carries everything the walk needs (the energy in
+// the form it is split in, and the deflection without a per-step sincos).
+__global__ void compact_steps_kernel(float4 *__restrict__ steps, unsigned long long n)
 {
     for (unsigned long long k = blockIdx.x * (unsigned long long)blockDim.x + threadIdx.x; k < n;
          k += (unsigned long long)gridDim.x * blockDim.x) {
         const float4 r = steps[k];
         float sp, cp;
         sincosf(r.w, &sp, &cp);
-        aux[k] = make_float4(cp, sp, 1.f / r.x, 0.f);
+        steps[k] = make_float4(r.x, __int_as_float((int)to_fp(r.y)), r.z * cp, r.z * sp);
     }
 }
 
@@ -172,9 +173,9 @@ hipError_t launch_hu_to_index(const int16_t *hu, uint16_t *idx, size_t n, hipStr
     return hipGetLastError();
 }
 
-hipError_t launch_step_aux(const float4 *steps, float4 *aux, unsigned long long n, hipStream_t s)
+hipError_t launch_compact_steps(float4 *steps, unsigned long long n, hipStream_t s)
 {
-    hipLaunchKernelGGL(step_aux_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, steps, aux, n);
+    hipLaunchKernelGGL(compact_steps_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, steps, n);
     return hipGetLastError();
 }
 

@@ -57,6 +57,7 @@ struct WorkItem {
     unsigned long long h0;
     unsigned long long n;
     unsigned long long unit0;       // index of this item's first wave unit
+    unsigned long long first;       // index of this item's first history among the run's
     uint32_t gspot;                 // index into the DevSpot array
     uint32_t pad;
 };
@@ -67,8 +68,8 @@ __host__ __device__ inline unsigned long long units_for(unsigned long long n)
 }
 
 struct TransportArgs {
-    const float4 *steps;                 // (dx, dE, theta, phi)
-    const float4 *step_aux;              // per step: (cos phi, sin phi, 1 / dx, 0), made at load
+    const float4 *steps;                 // per step: (dx, fixed-point dE as int32 bits,
+                                         // theta cos phi, theta sin phi), made at load
     const unsigned long long *track_off; // n_tracks + 1
     const long long *track_T;            // sum of fp(dE) per track
     const uint32_t *bin_first;           // n_bins + 1
@@ -85,6 +86,8 @@ struct TransportArgs {
     uint32_t flags;
     float *ep_xyz;                       // endpoint mode outputs (else null)
     int *ep_reason;
+    const uint32_t *order;               // per unit and lane: offset of the lane's history in its
+                                         // item, 0xFFFFFFFF = none (null: consecutive histories)
 };
 
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two 32x32
@@ -218,12 +221,19 @@ hipError_t prepare_lds_kernels();
 hipError_t launch_build_lut(const double *pts, int n_pts, double vacuum_below, float2 *lut, float *rho,
                             hipStream_t s);
 hipError_t launch_hu_to_index(const int16_t *hu, uint16_t *idx, size_t n, hipStream_t s);
-hipError_t launch_step_aux(const float4 *steps, float4 *aux, unsigned long long n, hipStream_t s);
+hipError_t launch_compact_steps(float4 *steps, unsigned long long n, hipStream_t s);
 hipError_t launch_track_energy(const float4 *steps, const unsigned long long *off, long long *T,
                                uint32_t n_tracks, hipStream_t s);
 hipError_t launch_dose(const uint16_t *idx, const unsigned long long *E, const unsigned long long *E2,
                        const float2 *lut, const float *rho_lut, size_t nvox, double voxel_volume_cm3,
                        const unsigned long long *n_hist, double *dose, double *var, hipStream_t s);
+// processing order of a run's histories by start position (order.hip)
+size_t source_order_temp_bytes(unsigned long long n_total, uint32_t n_items);
+hipError_t launch_source_order(const WorkItem *items, uint32_t n_items,
+                               unsigned long long n_total, unsigned long long n_units, const DevSpot *spots,
+                               const unsigned long long *hnext, uint32_t seed_lo, uint32_t seed_hi,
+                               unsigned long long *keys_a, unsigned long long *keys_b, uint32_t *vals_a,
+                               uint32_t *vals_b, void *temp, size_t temp_bytes, uint32_t *order, hipStream_t s);
 hipError_t launch_advance(const WorkItem *items, uint32_t n_items, unsigned long long *hnext, const DevSpot *spots,
                           const DevPlan *plans, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long *p, size_t n, unsigned long long value, hipStream_t s);

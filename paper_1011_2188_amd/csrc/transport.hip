@@ -60,6 +60,25 @@ __host__ __device__ inline void set_direction_terms(const float d[3], const floa
     }
 }
 
+// A stored step as the walk reads it (16 bytes, converted once when the
+// database is loaded): (dx, the step's energy loss in fixed point as the bits
+// of an int32, theta * cos(phi), theta * sin(phi)).
+__host__ __device__ inline long long step_energy(float4 r)
+{
+    return (long long)__builtin_bit_cast(int, r.y);
+}
+
+// theta and the azimuth's cosine and sine from (theta cos phi, theta sin phi);
+// a step without deflection gets azimuth 0
+__host__ __device__ inline void polar_terms(float4 r, float &th, float &c, float &s)
+{
+    const float t2 = r.z * r.z + r.w * r.w;
+    const float ir = fast_rsq(t2 > 0.f ? t2 : 1.f);
+    th = t2 > 0.f ? t2 * ir : 0.f;
+    c = t2 > 0.f ? r.z * ir : 1.f;
+    s = t2 > 0.f ? r.w * ir : 0.f;
+}
+
 // Where a voxel visit's deposit goes.  Every sink adds the integer deposit
 // `acc` to E[v] and, with the squared-energy tally, q^2 to E2[v] with
 // q = (acc + 2^11) >> 12 (the deposit rounded to 2^-12 MeV).
@@ -264,7 +283,7 @@ __host__ __device__ void replay_history(const TransportArgs &a, const DevSpot &s
     long long cum = 0;
     long long e = 0;
     for (; k < kend; ++k) {
-        e = to_fp(a.steps[k].y);
+        e = step_energy(a.steps[k]);
         if (cum + e > skip) break;
         cum += e;
     }
@@ -355,21 +374,25 @@ __host__ __device__ void replay_history(const TransportArgs &a, const DevSpot &s
     bool escaped = false;
     // the partial first step (its remaining energy e_first of the stored e):
     // length f * dx, angle sqrt(f) * theta, azimuth rotated by phi0
-    float4 rec = a.steps[k], aux = a.step_aux[k];
-    e = to_fp(rec.y);
+    float4 rec = a.steps[k];
+    e = step_energy(rec);
     const long long e_first = cum + e - skip;
     const float f = ll_to_f(e_first) / ll_to_f(e);
     int e32 = (int)e_first;                         // a step's energy fits 32 bits (checked at load)
     float w_tot = f * rec.x;
-    float th = rec.z * sqrtf(f);
-    float cph = aux.x, sph = aux.y;                 // cos, sin of the azimuth
+    float th, cph, sph;                             // polar angle, cos and sin of the azimuth
+    polar_terms(rec, th, cph, sph);
+    th *= sqrtf(f);
     float inv_w = 1.f / w_tot;
-    if (phi0 != 0.f) sincosf(rec.w + phi0, &sph, &cph);
-    float4 next_rec = rec, next_aux = aux;
-    if (k + 1 < kend) {
-        next_rec = a.steps[k + 1];
-        next_aux = a.step_aux[k + 1];
+    if (phi0 != 0.f) {                              // the track rotated rigidly about the beam axis
+        float s0, c0;
+        sincosf(phi0, &s0, &c0);
+        const float c = cph * c0 - sph * s0;
+        sph = sph * c0 + cph * s0;
+        cph = c;
     }
+    float4 next_rec = rec;
+    if (k + 1 < kend) next_rec = a.steps[k + 1];
     for (;;) {
         const float ef = (float)e32;
         float tau = 0.f, g2 = 0.f;
@@ -462,17 +485,11 @@ __host__ __device__ void replay_history(const TransportArgs &a, const DevSpot &s
         // next stored step (its record and terms were loaded one step ahead)
         if (++k >= kend) break;
         rec = next_rec;
-        aux = next_aux;
-        if (k + 1 < kend) {
-            next_rec = a.steps[k + 1];
-            next_aux = a.step_aux[k + 1];
-        }
+        if (k + 1 < kend) next_rec = a.steps[k + 1];
         w_tot = rec.x;
-        th = rec.z;
-        cph = aux.x;
-        sph = aux.y;
-        inv_w = aux.z;
-        e32 = (int)to_fp(rec.y);
+        polar_terms(rec, th, cph, sph);
+        inv_w = fast_rcp(rec.x);
+        e32 = (int)step_energy(rec);
     }
     if (!escaped && acc != 0) sink.add(L.v, (uint32_t)L.i[0], acc);
     esc = escaped ? I_h - hdep : 0;
@@ -505,15 +522,25 @@ __device__ void process_unit(const TransportArgs &a, const float2 *lut, float *w
     const DevSpot &sp = a.spots[it.gspot];
     const DevPlan &pl = a.plans[sp.plan];
     const unsigned long long h0 = it.h0 + (a.hnext ? a.hnext[it.gspot] : 0ull);
-    const unsigned long long h = (h0 / kWave + (unit - it.unit0)) * kWave + lane;
+    // the lane's history: consecutive (a 64-aligned chunk sharing a track), or
+    // the run's order by start position
+    unsigned long long h;
+    bool valid;
+    if (a.order) {
+        const uint32_t off = a.order[unit * kWave + lane];
+        h = h0 + off;
+        valid = off != 0xFFFFFFFFu;
+    } else {
+        h = (h0 / kWave + (unit - it.unit0)) * kWave + lane;
+        valid = h >= h0 && h < h0 + it.n;
+    }
     long long inc = 0, esc = 0;
     // the wave's constants, one per lane 0..11 whether or not the lane has a
     // history (one wave's LDS accesses execute in order, so its later reads
     // see them)
     if (lane < 9) wc[lane] = sp.m[lane];
     else if (lane < 12) wc[lane] = pl.inv_vox[lane - 9];
-    if (h >= h0 && h < h0 + it.n)
-        replay_history<EP>(a, sp, pl, lut, wc, h, (uint32_t)(h - h0), inc, esc, sink);
+    if (valid) replay_history<EP>(a, sp, pl, lut, wc, h, (uint32_t)(h - h0), inc, esc, sink);
     if (!EP) {
         inc = wave_sum(inc);
         esc = wave_sum(esc);

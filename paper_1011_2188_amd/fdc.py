@@ -36,7 +36,7 @@ EXPORTS = ["fdc_create", "fdc_destroy", "fdc_last_error", "fdc_set_allocator", "
            "fdc_unet_num_params", "fdc_unet_create", "fdc_unet_destroy", "fdc_unet_last_error",
            "fdc_unet_set_params", "fdc_unet_get_params", "fdc_unet_get_grads", "fdc_unet_forward",
            "fdc_unet_backward", "fdc_unet_adam", "fdc_unet_debug_buffer", "fdc_density", "fdc_denoise_input",
-           "fdc_unet_init_params"]
+           "fdc_unet_init_params", "fdc_set_timing", "fdc_transport_times"]
 FDC_GRAPH_RESET_TALLIES = 1
 FDC_GRAPH_DOSE = 2
 
@@ -49,7 +49,8 @@ class fdc_summary(C.Structure):
 class fdc_launch_config(C.Structure):
     _fields_ = [("waves_per_block", C.c_uint32), ("blocks_per_cu", C.c_uint32),
                 ("tally_slots", C.c_uint32), ("units_per_wave", C.c_uint32),
-                ("tally_mode", C.c_uint32), ("reserved", C.c_uint32 * 3)]
+                ("tally_mode", C.c_uint32), ("source_order", C.c_uint32),
+                ("reserved", C.c_uint32 * 2)]
 
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
@@ -93,6 +94,8 @@ def lib():
         "fdc_debug_material": (C.c_int, [_P, _P, _P, _P, _P]),
         "fdc_set_launch_config": (C.c_int, [_P, C.POINTER(fdc_launch_config)]),
         "fdc_device_cus": (C.c_int, [_P, C.POINTER(C.c_int)]),
+        "fdc_set_timing": (C.c_int, [_P, C.c_int]),
+        "fdc_transport_times": (C.c_int, [_P, C.POINTER(C.c_float), C.c_uint32]),
         "fdc_mean_uncertainty": (C.c_int, [_P, C.c_int32, _P, _P, C.c_double, C.POINTER(C.c_double),
                                            C.POINTER(C.c_uint64), C.POINTER(C.c_double), _P]),
         "fdc_batch_uncertainty": (C.c_int, [_P, _P, C.c_uint32, C.c_uint64, _P, _P, _P]),
@@ -323,8 +326,9 @@ class Context:
                                                 _stream(stream)))
         return rsp, g, rho
 
-    def set_launch_config(self, waves_per_block=4, blocks_per_cu=0, tally_slots=0, units_per_wave=0, tally_mode=0):
-        cfg = fdc_launch_config(waves_per_block, blocks_per_cu, tally_slots, units_per_wave, tally_mode)
+    def set_launch_config(self, waves_per_block=4, blocks_per_cu=0, tally_slots=0, units_per_wave=0, tally_mode=0,
+                          source_order=0):
+        cfg = fdc_launch_config(waves_per_block, blocks_per_cu, tally_slots, units_per_wave, tally_mode, source_order)
         _check(self.h, lib().fdc_set_launch_config(self.h, C.byref(cfg)))
 
     # -- graphs
@@ -373,6 +377,16 @@ class Context:
         n = C.c_int()
         _check(self.h, lib().fdc_device_cus(self.h, C.byref(n)))
         return n.value
+
+    def set_timing(self, on=True):
+        """Time the transport kernel of every following run (HIP events)."""
+        _check(self.h, lib().fdc_set_timing(self.h, int(bool(on))))
+
+    def transport_times(self, n):
+        """Kernel milliseconds of the last n timed runs, oldest first."""
+        out = np.zeros(n, np.float32)
+        _check(self.h, lib().fdc_transport_times(self.h, out.ctypes.data_as(C.POINTER(C.c_float)), n))
+        return out
 
 
 UNET_BUFFERS = ["x", "e1a", "c1", "p1", "e2a", "c2", "p2", "ma", "m", "d2a", "d2", "d1a", "d1",

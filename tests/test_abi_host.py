@@ -151,7 +151,20 @@ def test_launch_config_validation(ctx):
     _expect(F.FDC_E_ARG, ctx.set_launch_config, 16, 1, 4096, 2, 3)
     _expect(F.FDC_E_ARG, ctx.set_launch_config, 16, 1, 8100, 1, 2)
     _expect(F.FDC_E_ARG, ctx.set_launch_config, 4, 0, 0, 65)
+    ctx.set_launch_config(16, 1, 8064, 1, 1, source_order=1)
+    _expect(F.FDC_E_ARG, ctx.set_launch_config, 16, 1, 8064, 1, 1, 2)
     assert ctx.device_cus() > 0
+
+
+def test_timing_rules(ctx):
+    lib = F.lib()
+    assert lib.fdc_set_timing(ctx.h, 1) == F.FDC_E_STATE          # no device here
+    assert lib.fdc_set_timing(ctx.h, 0) == F.FDC_OK
+    assert lib.fdc_transport_times(ctx.h, None, 0) == F.FDC_OK
+    assert lib.fdc_transport_times(ctx.h, None, 1) == F.FDC_E_ARG
+    with pytest.raises(F.FdcError):
+        ctx.transport_times(1)                                    # nothing timed
+    assert lib.fdc_set_timing(None, 1) == F.FDC_E_ARG
 
 
 def test_allocator_hooks_rules(ctx):

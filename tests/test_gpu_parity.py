@@ -84,6 +84,31 @@ def test_device_philox_bitwise():
     assert np.array_equal(g, o)
 
 
+def test_transport_timing_events():
+    """The library's events bracket the transport kernel of each timed run:
+    positive durations, the last n runs, and no more than were timed."""
+    db = W.multi_bin_db(2000)
+    c = ctx_for(db, waves_per_block=16, blocks_per_cu=1, tally_slots=8064, units_per_wave=1, tally_mode=1,
+                source_order=1)
+    ph = I.slab_phantom(64, 0.2)
+    p = c.load_phantom(ph)
+    c.add_beam_spots(p, W.slab_spots(2000))
+    c.run_histories([p])                       # untimed
+    c.set_timing(True)
+    for _ in range(3):
+        c.run_histories([p])
+    ms = c.transport_times(3)
+    assert ms.shape == (3,) and np.all(ms > 0) and np.all(ms < 1000)
+    with pytest.raises(F.FdcError):
+        c.transport_times(4)
+    for _ in range(70):                        # the ring keeps the last 64
+        c.run_histories([p], 0)
+    assert c.transport_times(64).shape == (64,)
+    with pytest.raises(F.FdcError):
+        c.transport_times(65)
+    c.set_timing(False)
+
+
 def test_device_material_table():
     c = F.Context(device=0, table=I.HU_TABLE_DEFAULT)
     rsp, g, rho = c.debug_material()
@@ -209,7 +234,14 @@ def test_launch_configs_bitwise():
                 dict(waves_per_block=16, blocks_per_cu=1, tally_slots=8064, units_per_wave=1, tally_mode=2),
                 dict(waves_per_block=4, blocks_per_cu=2, tally_slots=256, units_per_wave=2, tally_mode=2),
                 dict(waves_per_block=5, blocks_per_cu=1, tally_slots=512, units_per_wave=3, tally_mode=2),
-                dict(waves_per_block=1, blocks_per_cu=4, tally_slots=256, units_per_wave=1, tally_mode=2)]:
+                dict(waves_per_block=1, blocks_per_cu=4, tally_slots=256, units_per_wave=1, tally_mode=2),
+                # histories in start-position order, every launch kind
+                dict(waves_per_block=4, source_order=1), dict(waves_per_block=8, blocks_per_cu=2, source_order=1),
+                dict(waves_per_block=8, blocks_per_cu=1, tally_slots=1024, units_per_wave=2, source_order=1),
+                dict(waves_per_block=16, blocks_per_cu=1, tally_slots=8064, units_per_wave=1, tally_mode=1,
+                     source_order=1),
+                dict(waves_per_block=16, blocks_per_cu=1, tally_slots=8064, units_per_wave=1, tally_mode=2,
+                     source_order=1)]:
         got = _tallies(db, ph, sp, **cfg)
         assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1]) and got[2] == ref[2], cfg
 
@@ -243,7 +275,9 @@ def test_autotuner_candidates_bitwise_and_tuning_leaves_no_trace(tmp_path):
 @pytest.mark.parametrize("cfg", [{}, dict(waves_per_block=8, blocks_per_cu=1, tally_slots=2048, units_per_wave=2),
                                  dict(waves_per_block=8, blocks_per_cu=1, tally_slots=512, units_per_wave=3,
                                       tally_mode=1),
-                                 dict(waves_per_block=8, blocks_per_cu=1, tally_slots=512, tally_mode=2)])
+                                 dict(waves_per_block=8, blocks_per_cu=1, tally_slots=512, tally_mode=2),
+                                 dict(waves_per_block=8, blocks_per_cu=1, tally_slots=512, tally_mode=1,
+                                      source_order=1)])
 def test_split_runs_and_batching_bitwise(cfg):
     """run(n) twice == run(2n) (history counters continue, unaligned h0), and
     plans launched together == plans launched one by one (also with the LDS
@@ -416,7 +450,9 @@ def test_batched_graph_full_size():
 @pytest.mark.parametrize("cfg", [{}, dict(waves_per_block=16, blocks_per_cu=1, tally_slots=4096, units_per_wave=2),
                                  dict(waves_per_block=16, blocks_per_cu=1, tally_slots=8064, units_per_wave=2,
                                       tally_mode=1),
-                                 dict(waves_per_block=16, blocks_per_cu=1, tally_slots=8064, tally_mode=2)])
+                                 dict(waves_per_block=16, blocks_per_cu=1, tally_slots=8064, tally_mode=2),
+                                 dict(waves_per_block=16, blocks_per_cu=1, tally_slots=8064, tally_mode=1,
+                                      source_order=1)])
 def test_graph_replays_match_eager(cfg):
     """A captured run (clear tallies -> transport -> advance counters -> dose)
     replayed four times, with eager work and synchronisation in between,
