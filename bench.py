@@ -268,7 +268,8 @@ def main():
         v = [int(x) for x in args.launch.split(",")]
         launch = dict(zip(LAUNCH_KEYS, v))
         c.set_launch_config(**launch)
-    kernel = "transport_lds_kernel" if launch.get("tally_slots", 0) else "transport_kernel"
+    kernel = ("transport_kernel" if not launch.get("tally_slots", 0) else
+              "transport_cache_kernel" if launch.get("tally_mode", 0) == 2 else "transport_lds_kernel")
     nvox = ph.hu.size
     hist_per_step = int(sp["n_histories"].sum())
     dose = torch.empty(nvox, dtype=torch.float64, device=dev)
