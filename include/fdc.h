@@ -126,8 +126,9 @@ typedef struct {
     uint32_t source_order;      /* 0 = a wave unit takes 64 consecutive histories of a
                                    spot, which share one database track; 1 = the
                                    histories of each spot are processed in an order
-                                   sorted by start position (a Morton code on a 0.2 mm
-                                   grid of the lateral offset), each lane on its own
+                                   sorted by start position (a Morton code of the
+                                   lateral offset, 256 x 256 cells over the spot's
+                                   width), each lane on its own
                                    track: lanes of a wave start close together, which
                                    lets the LDS cache merge deposits of broad fields.
                                    Costs a sort per run (device memory about 24 B per

@@ -13,9 +13,12 @@
 // the tallies are integer sums, so the order cannot change a result bit.
 //
 // Three steps per run: keys (one thread per history), a device radix sort of
-// (item << 32 | morton, offset) pairs, and a scatter into the per-unit table
+// (item << 16 | morton, offset) pairs (32-bit keys while the run has fewer
+// than 2^16 work items, else 64-bit), and a scatter into the per-unit table
 // order[unit * 64 + lane] = offset of the lane's history in its item
-// (0xFFFFFFFF for the lanes past the item's end).
+// (0xFFFFFFFF for the lanes past the item's end).  The Morton code covers the
+// spot's lateral offset in units of its width: 256 cells over +-4 sigma for a
+// Gaussian spot, over the diameter for a disk field.
 #include <hipcub/hipcub.hpp>
 
 #include "fdc_device.h"
@@ -23,8 +26,6 @@
 namespace fdc {
 
 namespace {
-
-constexpr double kOrderCellCm = 0.02;   // grid of the start-position key
 
 __device__ inline uint32_t spread16(uint32_t x)     // bits 0..15 -> even bits
 {
@@ -46,9 +47,10 @@ __device__ inline uint32_t item_of(const WorkItem *items, uint32_t n_items, unsi
     return lo;
 }
 
+template <class Key>
 __global__ void order_keys_kernel(const WorkItem *items, uint32_t n_items,
                                   unsigned long long n_total, const DevSpot *spots, const unsigned long long *hnext,
-                                  uint32_t seed_lo, uint32_t seed_hi, unsigned long long *keys, uint32_t *vals)
+                                  uint32_t seed_lo, uint32_t seed_hi, Key *keys, uint32_t *vals)
 {
     const unsigned long long g = blockIdx.x * (unsigned long long)blockDim.x + threadIdx.x;
     if (g >= n_total) return;
@@ -63,11 +65,11 @@ __global__ void order_keys_kernel(const WorkItem *items, uint32_t n_items,
     const double r = sp.sigma >= 0.f ? sqrt(-2.0 * log(u01(xs.x))) : sqrt(u01(xs.x));
     double sa, ca;
     sincos(2.0 * M_PI * u01(xs.y), &sa, &ca);
-    const double s = fabs((double)sp.sigma) / kOrderCellCm;
-    const double qx = fmin(fmax(floor(r * ca * s) + 32768.0, 0.0), 65535.0);
-    const double qy = fmin(fmax(floor(r * sa * s) + 32768.0, 0.0), 65535.0);
+    const double cells = sp.sigma >= 0.f ? 32.0 : 128.0;          // per unit of the offset
+    const double qx = fmin(fmax(floor(r * ca * cells) + 128.0, 0.0), 255.0);
+    const double qy = fmin(fmax(floor(r * sa * cells) + 128.0, 0.0), 255.0);
     const uint32_t morton = spread16((uint32_t)qx) | (spread16((uint32_t)qy) << 1);
-    keys[g] = ((unsigned long long)i << 32) | morton;
+    keys[g] = ((Key)i << 16) | (Key)morton;
     vals[g] = (uint32_t)j;
 }
 
@@ -89,16 +91,40 @@ __global__ void order_scatter_kernel(const WorkItem *items, uint32_t n_items,
 
 } // namespace
 
+static bool narrow_keys(uint32_t n_items) { return n_items < (1u << 16); }
+
+static int key_bits(uint32_t n_items) { return 16 + (32 - __builtin_clz(n_items | 1u)); }
+
 size_t source_order_temp_bytes(unsigned long long n_total, uint32_t n_items)
 {
     size_t bytes = 0;
-    const int end_bit = 32 + (32 - __builtin_clz(n_items | 1u));
-    hipcub::DeviceRadixSort::SortPairs(nullptr, bytes, (const unsigned long long *)nullptr,
-                                       (unsigned long long *)nullptr, (const uint32_t *)nullptr, (uint32_t *)nullptr,
-                                       (int)n_total, 0, end_bit);
+    if (narrow_keys(n_items))
+        hipcub::DeviceRadixSort::SortPairs(nullptr, bytes, (const uint32_t *)nullptr, (uint32_t *)nullptr,
+                                           (const uint32_t *)nullptr, (uint32_t *)nullptr, (int)n_total, 0,
+                                           key_bits(n_items));
+    else
+        hipcub::DeviceRadixSort::SortPairs(nullptr, bytes, (const unsigned long long *)nullptr,
+                                           (unsigned long long *)nullptr, (const uint32_t *)nullptr,
+                                           (uint32_t *)nullptr, (int)n_total, 0, key_bits(n_items));
     return bytes;
 }
 
+template <class Key>
+static hipError_t keys_and_sort(const WorkItem *items, uint32_t n_items, unsigned long long n_total,
+                                const DevSpot *spots, const unsigned long long *hnext, uint32_t seed_lo,
+                                uint32_t seed_hi, Key *keys_a, Key *keys_b, uint32_t *vals_a, uint32_t *vals_b,
+                                void *temp, size_t temp_bytes, hipStream_t s)
+{
+    const unsigned int tb = 256;
+    hipLaunchKernelGGL(order_keys_kernel<Key>, dim3((unsigned)((n_total + tb - 1) / tb)), dim3(tb), 0, s, items,
+                       n_items, n_total, spots, hnext, seed_lo, seed_hi, keys_a, vals_a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return hipcub::DeviceRadixSort::SortPairs(temp, temp_bytes, keys_a, keys_b, vals_a, vals_b, (int)n_total, 0,
+                                              key_bits(n_items), s);
+}
+
+// keys_a and keys_b hold n_total 64-bit keys each (the 32-bit form uses their first halves)
 hipError_t launch_source_order(const WorkItem *items, uint32_t n_items,
                                unsigned long long n_total, unsigned long long n_units, const DevSpot *spots,
                                const unsigned long long *hnext, uint32_t seed_lo, uint32_t seed_hi,
@@ -106,14 +132,14 @@ hipError_t launch_source_order(const WorkItem *items, uint32_t n_items,
                                uint32_t *vals_b, void *temp, size_t temp_bytes, uint32_t *order, hipStream_t s)
 {
     if (n_total == 0) return hipSuccess;
+    const hipError_t e =
+        narrow_keys(n_items)
+            ? keys_and_sort<uint32_t>(items, n_items, n_total, spots, hnext, seed_lo, seed_hi, (uint32_t *)keys_a,
+                                      (uint32_t *)keys_b, vals_a, vals_b, temp, temp_bytes, s)
+            : keys_and_sort<unsigned long long>(items, n_items, n_total, spots, hnext, seed_lo, seed_hi, keys_a,
+                                                keys_b, vals_a, vals_b, temp, temp_bytes, s);
+    if (e != hipSuccess) return e;
     const unsigned int tb = 256;
-    hipLaunchKernelGGL(order_keys_kernel, dim3((unsigned)((n_total + tb - 1) / tb)), dim3(tb), 0, s, items, n_items,
-                       n_total, spots, hnext, seed_lo, seed_hi, keys_a, vals_a);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    const int end_bit = 32 + (32 - __builtin_clz(n_items | 1u));
-    e = hipcub::DeviceRadixSort::SortPairs(temp, temp_bytes, keys_a, keys_b, vals_a, vals_b, (int)n_total, 0, end_bit, s);
-    if (e != hipSuccess) return e;
     const unsigned long long n_slots = n_units * kWave;
     hipLaunchKernelGGL(order_scatter_kernel, dim3((unsigned)((n_slots + tb - 1) / tb)), dim3(tb), 0, s, items, n_items,
                        n_slots, vals_b, order);
