@@ -347,12 +347,14 @@ def test_edge_cases():
 
 
 # ------------------------------------------------------ full-size checks ----
-BENCH_LAUNCH = dict(waves_per_block=16, blocks_per_cu=1, tally_slots=8064, units_per_wave=1, tally_mode=1)
+# the configuration the benchmark's autotuner picks for the slab workload
+BENCH_LAUNCH = dict(waves_per_block=16, blocks_per_cu=1, tally_slots=8064, units_per_wave=1, tally_mode=2,
+                    source_order=1)
 
 
 def test_full_size_slab_dose_vs_oracle():
     """The 1e7-history slab workload in the benchmark's launch configuration
-    (LDS write-back cache): dose and Eq. (2) variance against the oracle run
+    (whole-launch LDS cache, start-position order): dose and Eq. (2) variance against the oracle run
     on the same 1e7 histories, energy identity exactly, incident energy equal
     to the oracle's, the tallies bitwise equal to the plain global-atomic
     launch, and sampled end points."""
