@@ -96,8 +96,10 @@ def extras(c, plan, nvox, hist_per_step, launch, log):
     nb = 6
     doses = torch.empty((nb, nvox), dtype=torch.float64, device="cuda")
     # the energy-tally-only runs get their own launch configuration (untimed tuning)
-    cache_cands = [dict(waves_per_block=16, blocks_per_cu=1, tally_slots=8064, units_per_wave=1, tally_mode=m,
-                        source_order=o) for m in (1, 2) for o in (0, 1)]
+    cache_cands = ([dict(waves_per_block=16, blocks_per_cu=1, tally_slots=8064, units_per_wave=1, tally_mode=m,
+                         source_order=0) for m in (1, 2)]
+                   + [dict(waves_per_block=16, blocks_per_cu=1, tally_slots=8064, units_per_wave=u, tally_mode=2,
+                           source_order=1) for u in (1, 2, 4, 8)])
     eq1_launch, _ = A.tune(c, [plan], 0, use_cache=False, candidates=cache_cands, reps=1)
     torch.cuda.synchronize()
     t = time.perf_counter()
