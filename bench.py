@@ -48,21 +48,29 @@ def slab_bytes_per_history(variance: bool, source_order: int = 0) -> float:
 
 def measured_traffic(launch):
     """HBM bytes per launch of the transport kernel from the committed rocprofv3
-    FETCH_SIZE / WRITE_SIZE summary, if it was taken for this launch
+    FETCH_SIZE / WRITE_SIZE summary, if it holds an entry for this launch
     configuration and the kernel sources are unchanged since; else None."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "transport_slab_1e7_pmc.md")
     try:
-        fields = dict(line.strip().split(": ", 1) for line in open(path) if line.startswith("    ") and ": " in line
-                      and line.strip().split(": ", 1)[0] in ("launch", "traffic_bytes_per_launch", "kernel_source_sha1"))
+        lines = [line.strip().split(": ", 1) for line in open(path) if line.startswith("    ") and ": " in line]
         src = b"".join(open(os.path.join(ROOT, "paper_1011_2188_amd", "csrc", f), "rb").read()
                        for f in ("transport.hip", "fdc_device.h"))
     except (OSError, ValueError):
         return None
-    want = ",".join(str(launch.get(k, 0)) for k in LAUNCH_KEYS)
-    if fields.get("kernel_source_sha1") != hashlib.sha1(src).hexdigest() or fields.get("launch") != want:
+    sha = dict(kv for kv in lines if len(kv) == 2).get("kernel_source_sha1")
+    if sha != hashlib.sha1(src).hexdigest():
         return None
-    return float(fields["traffic_bytes_per_launch"])
+    want = ",".join(str(launch.get(k, 0)) for k in LAUNCH_KEYS)
+    cur = None
+    for kv in lines:
+        if len(kv) != 2:
+            continue
+        if kv[0] == "launch":
+            cur = kv[1]
+        elif kv[0] == "traffic_bytes_per_launch" and cur == want:
+            return float(kv[1])
+    return None
 
 
 def extras(c, plan, nvox, hist_per_step, launch, log):
