@@ -138,7 +138,30 @@ __global__ void __launch_bounds__(256) igemm_kernel(const u16 *__restrict__ src,
             for (int m = 0; m < MT; ++m) acc[m][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[m], b, acc[m][t], 0, 0, 0);
         }
     }
-    // epilogue: lane holds D[4*lg + e][li] of every (m, t) tile
+    // epilogue: lane holds D[4*lg + e][li] of every (m, t) tile.  The bias
+    // (one value per column) and the masks are loaded before any use, so their
+    // round trips overlap instead of queueing one per element.
+    float bv[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        const int n = n_base + 16 * t + li;
+        const int co = EM == E_STORE ? n : n - (n / d2s_cout) * d2s_cout;
+        bv[t] = (bias && n < n_cols) ? bias[co] : 0.f;
+    }
+    u16 mk[MT][NT][4];
+    if (EM == E_STORE && mask) {
+#pragma unroll
+        for (int m = 0; m < MT; ++m)
+#pragma unroll
+            for (int t = 0; t < NT; ++t)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const long r = row0 + 16 * m + 4 * lg + e;
+                    const int n = n_base + 16 * t + li;
+                    const bool in = r < n_rows && n < n_cols;
+                    mk[m][t][e] = mask[(in ? r : 0) * mask_pitch + (in ? n : 0)];
+                }
+    }
 #pragma unroll
     for (int m = 0; m < MT; ++m)
 #pragma unroll
@@ -149,15 +172,13 @@ __global__ void __launch_bounds__(256) igemm_kernel(const u16 *__restrict__ src,
             for (int e = 0; e < 4; ++e) {
                 const long r = row0 + 16 * m + 4 * lg + e;
                 if (r >= n_rows) continue;
-                float v = acc[m][t][e];
+                float v = acc[m][t][e] + bv[t];
                 if (EM == E_STORE) {
-                    if (bias) v += bias[n];
                     if (relu) v = fmaxf(v, 0.f);
-                    if (mask && !(bf2f(mask[r * mask_pitch + n]) > 0.f)) v = 0.f;
+                    if (mask && !(bf2f(mk[m][t][e]) > 0.f)) v = 0.f;
                     dst[r * dst_pitch + n] = f2bf(v);
                 } else {
                     const int a8 = n / d2s_cout, co = n - a8 * d2s_cout;
-                    if (bias) v += bias[co];
                     const int x = (int)(r % g.nx), y = (int)((r / g.nx) % g.ny), z = (int)(r / ((long)g.nx * g.ny));
                     const long fv = ((long)(2 * z + (a8 >> 2)) * fy + (2 * y + ((a8 >> 1) & 1))) * fx + 2 * x + (a8 & 1);
                     dst[fv * dst_pitch + co] = f2bf(v);
@@ -199,93 +220,114 @@ __device__ inline void stage16(int total, Src src, Dst dst)
     }
 }
 
-template <int NT, int TY>
-__global__ void __launch_bounds__(256) conv3_kernel(const u16 *__restrict__ src, int src_pitch, int cpad, int cshift,
-                                                    Grid g, const u16 *__restrict__ wpk, int kpad, int n_cols,
+template <int NT, int TY, int CP>
+__global__ void __launch_bounds__(256) conv3_kernel(const u16 *__restrict__ src, int src_pitch, Grid g,
+                                                    const u16 *__restrict__ wpk, int kpad, int n_cols,
                                                     const float *__restrict__ bias, int relu,
                                                     const u16 *__restrict__ mask, int mask_pitch,
                                                     u16 *__restrict__ dst, int dst_pitch)
 {
     constexpr int TX = 16, TZ = 4, HX = TX + 2, HY = TY + 2, HZ = TZ + 2;
+    constexpr int HP = CP + 8;                             // LDS channel pitch (16-byte rows, skewed banks)
+    constexpr int GSHIFT = CP == 8 ? 0 : CP == 16 ? 1 : CP == 32 ? 2 : 3;   // CP / 8 = 1 << GSHIFT
+    constexpr int KVALID = 27 * CP;
+    constexpr int STEPS = (KVALID + 31) / 32;              // K steps of 32
+    constexpr int D0 = NT == 1 ? 8 : NT == 2 ? 4 : 2;
+    constexpr int D = D0 < STEPS ? D0 : STEPS;             // weight look-ahead, in K steps
     extern __shared__ __attribute__((aligned(16))) u16 sh[];
-    __shared__ int s_tap[27];                              // halo-row offset of each tap
-    const int hp = cpad + 8;                               // LDS channel pitch (16-byte rows, skewed banks)
     const int tiles_x = (g.nx + TX - 1) / TX, tiles_y = (g.ny + TY - 1) / TY;
     const int bx = blockIdx.x % tiles_x, by = (blockIdx.x / tiles_x) % tiles_y, bz = blockIdx.x / (tiles_x * tiles_y);
     const int x0 = bx * TX, y0 = by * TY, z0 = bz * TZ;
     const int n_base = blockIdx.y * 16 * NT;
-    const int gshift = cshift - 3;                         // cpad / 8 = 1 << gshift channel groups
-    if (threadIdx.x < 27) {
-        const int o = threadIdx.x;
-        s_tap[o] = ((o / 9) * HY + (o / 3) % 3) * HX + o % 3;
-    }
-    stage16<8>((HZ * HY * HX) << gshift,
+    stage16<8>((HZ * HY * HX) << GSHIFT,
             [&](int t) -> const u16 * {
-                const int h = t >> gshift, cg = t & ((1 << gshift) - 1);
+                const int h = t >> GSHIFT, cg = t & ((1 << GSHIFT) - 1);
                 const int x = x0 - 1 + h % HX, y = y0 - 1 + (h / HX) % HY, z = z0 - 1 + h / (HX * HY);
                 if (x < 0 || x >= g.nx || y < 0 || y >= g.ny || z < 0 || z >= g.nz) return nullptr;
                 return src + (((long)z * g.ny + y) * g.nx + x) * src_pitch + 8 * cg;
             },
-            [&](int t) { return sh + (t >> gshift) * hp + 8 * (t & ((1 << gshift) - 1)); });
+            [&](int t) { return sh + (t >> GSHIFT) * HP + 8 * (t & ((1 << GSHIFT) - 1)); });
     __syncthreads();
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int li = lane & 15, lg = lane >> 4;
-    const int kvalid = 27 * cpad;
     // element offset of this lane's row in each m tile at tap 0
     int base[TY];
 #pragma unroll
-    for (int m = 0; m < TY; ++m) base[m] = ((w * HY + m) * HX + li) * hp;
+    for (int m = 0; m < TY; ++m) base[m] = ((w * HY + m) * HX + li) * HP;
     f32x4 acc[TY][NT];
 #pragma unroll
     for (int m = 0; m < TY; ++m)
 #pragma unroll
         for (int t = 0; t < NT; ++t) acc[m][t] = f32x4{0.f, 0.f, 0.f, 0.f};
     const u16 *wrow[NT];
-    bool wok[NT];
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
         const int n = n_base + 16 * t + li;
-        wok[t] = n < n_cols;
-        wrow[t] = wpk + (long)(wok[t] ? n : 0) * kpad;
+        wrow[t] = wpk + (long)(n < n_cols ? n : 0) * kpad;
     }
-    // weight fragments of K step k (zero past the valid K or columns); loads are
-    // unconditional from a clamped address so that they issue together
-    auto load_w = [&](bf16x8 *b, int k) {
+    // weight fragments of K step st: plain loads (no select on the loaded
+    // value, which would make the wave wait for it at once).  The packed table
+    // is zero from KVALID to kpad, and columns past n_cols are never stored.
+    auto load_w = [&](bf16x8 *b, int st) {
 #pragma unroll
-        for (int t = 0; t < NT; ++t) {
-            const bf16x8 v = load8(wrow[t] + min(k, kpad - 8));
-            b[t] = (wok[t] && k < kvalid) ? v : zero8();
-        }
+        for (int t = 0; t < NT; ++t) b[t] = load8(wrow[t] + 32 * st + 8 * lg);
     };
-    // one K step: all A reads first, then the MFMAs
-    auto kstep = [&](const bf16x8 *b, int k) {
-        const bool kv = k < kvalid;
-        const int o = kv ? k >> cshift : 0;
-        const int off = s_tap[o] * hp + (kv ? k - (o << cshift) : 0);
+    // LDS element offset of the lane's A fragment in step st: tap
+    // o = (32 st + 8 lg) / CP at halo offset ((o/9) HY + (o/3)%3) HX + o%3,
+    // channel (32 st + 8 lg) % CP.  For CP >= 32 the tap does not depend on the
+    // lane; for smaller CP the lane group picks one of 32/CP taps of the step.
+    auto a_off = [&](int st) {
+        const int k = 32 * st + 8 * lg;
+        const int o = k / CP, c = k % CP;
+        return (((o / 9) * HY + (o / 3) % 3) * HX + o % 3) * HP + c;
+    };
+    bf16x8 ring[D][NT];
+#pragma unroll
+    for (int j = 0; j < D; ++j) load_w(ring[j], j);
+#pragma unroll
+    for (int st = 0; st < STEPS; ++st) {
+        const bool kv = 32 * st + 8 * lg < KVALID;        // false only in a last, partial step
+        const int off = kv ? a_off(st) : 0;
         bf16x8 a[TY];
 #pragma unroll
         for (int m = 0; m < TY; ++m) a[m] = load8(sh + base[m] + off);
 #pragma unroll
         for (int m = 0; m < TY; ++m) {
-            const bf16x8 am = kv ? a[m] : zero8();
+            const bf16x8 am = (32 * st + 32 <= KVALID || kv) ? a[m] : zero8();
 #pragma unroll
-            for (int t = 0; t < NT; ++t) acc[m][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am, b[t], acc[m][t], 0, 0, 0);
+            for (int t = 0; t < NT; ++t)
+                acc[m][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am, ring[st % D][t], acc[m][t], 0, 0, 0);
         }
-    };
-    // K loop, two steps per turn with two weight buffers (the next step's
-    // weights load while this step computes)
-    bf16x8 b0[NT], b1[NT];
-    load_w(b0, 8 * lg);
-    for (int k0 = 0; k0 < kpad; k0 += 64) {
-        load_w(b1, k0 + 32 + 8 * lg);
-        kstep(b0, k0 + 8 * lg);
-        if (k0 + 32 >= kpad) break;
-        load_w(b0, k0 + 64 + 8 * lg);
-        kstep(b1, k0 + 32 + 8 * lg);
+        if (st + D < STEPS) load_w(ring[st % D], st + D);
+        // keep each step's loads in their step: the scheduler would otherwise
+        // sink the look-ahead loads next to their use
+        __builtin_amdgcn_sched_barrier(0);
     }
-    // epilogue: lane holds D[4 lg + e][li] of every (m, t) tile: voxel x = x0 + 4 lg + e
+    // epilogue: lane holds D[4 lg + e][li] of every (m, t) tile: voxel x = x0 + 4 lg + e.
+    // The bias (one value per column) and the masks are loaded before any use,
+    // so their round trips overlap instead of queueing one per element.
     const int z = z0 + w;
     if (z >= g.nz) return;
+    float bv[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        const int n = n_base + 16 * t + li;
+        bv[t] = (bias && n < n_cols) ? bias[n] : 0.f;
+    }
+    u16 mk[TY][NT][4];
+    if (mask) {
+#pragma unroll
+        for (int m = 0; m < TY; ++m)
+#pragma unroll
+            for (int t = 0; t < NT; ++t)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int y = y0 + m, x = x0 + 4 * lg + e, n = n_base + 16 * t + li;
+                    const bool in = y < g.ny && x < g.nx && n < n_cols;
+                    const long r = ((long)z * g.ny + (in ? y : 0)) * g.nx + (in ? x : 0);
+                    mk[m][t][e] = mask[r * mask_pitch + (in ? n : 0)];
+                }
+    }
 #pragma unroll
     for (int m = 0; m < TY; ++m) {
         const int y = y0 + m;
@@ -299,10 +341,9 @@ __global__ void __launch_bounds__(256) conv3_kernel(const u16 *__restrict__ src,
                 const int x = x0 + 4 * lg + e;
                 if (x >= g.nx) continue;
                 const long r = ((long)z * g.ny + y) * g.nx + x;
-                float v = acc[m][t][e];
-                if (bias) v += bias[n];
+                float v = acc[m][t][e] + bv[t];
                 if (relu) v = fmaxf(v, 0.f);
-                if (mask && !(bf2f(mask[r * mask_pitch + n]) > 0.f)) v = 0.f;
+                if (mask && !(bf2f(mk[m][t][e]) > 0.f)) v = 0.f;
                 dst[r * dst_pitch + n] = f2bf(v);
             }
         }
@@ -863,20 +904,22 @@ hipError_t igemm(int am, int em, const View &src, int cpad, const Grid &g, const
         IGN(A_CONV1, E_D2S);
     } else if (am == A_CONV3) {
         // LDS-tiled kernel: 16 x TY x 4 output voxels per block (TY = 2 for 64
-        // input channels, so the tile and its halo stay under 64 KB of LDS)
+        // input channels, so the tile and its halo stay under 64 KB of LDS),
+        // compiled per padded channel count so that the K loop unrolls
         const int ty = cpad >= 64 ? 2 : 4;
-        const int cshift = __builtin_ctz((unsigned)cpad);
-        if ((cpad & (cpad - 1)) || cpad < 8 || cpad > 64) return hipErrorInvalidValue;
+        if (cpad != 8 && cpad != 16 && cpad != 32 && cpad != 64) return hipErrorInvalidValue;
+        if (kpad < (27 * cpad + 31) / 32 * 32) return hipErrorInvalidValue;   // the K loop reads 32-wide steps
         const uint32_t tiles = (uint32_t)(((g.nx + 15) / 16) * ((g.ny + ty - 1) / ty) * ((g.nz + 3) / 4));
         const dim3 cgrid(tiles, (uint32_t)((n_cols + 16 * nt - 1) / (16 * nt)));
         const size_t lds = (size_t)6 * (ty + 2) * 18 * (cpad + 8) * sizeof(u16);
-#define CV(NT_, TY_) hipLaunchKernelGGL((conv3_kernel<NT_, TY_>), cgrid, dim3(256), lds, s, src.p, src.pitch, cpad, \
-                                        cshift, g, wpk, kpad, n_cols, bias, (int)relu, mp, mpitch, dst.p, dst.pitch)
-        if (ty == 2) {
-            if (nt == 4) CV(4, 2); else if (nt == 2) CV(2, 2); else CV(1, 2);
-        } else {
-            if (nt == 4) CV(4, 4); else if (nt == 2) CV(2, 4); else CV(1, 4);
-        }
+#define CV(NT_, TY_, CP_) hipLaunchKernelGGL((conv3_kernel<NT_, TY_, CP_>), cgrid, dim3(256), lds, s, src.p, src.pitch, \
+                                             g, wpk, kpad, n_cols, bias, (int)relu, mp, mpitch, dst.p, dst.pitch)
+#define CVN(TY_, CP_) do { if (nt == 4) CV(4, TY_, CP_); else if (nt == 2) CV(2, TY_, CP_); else CV(1, TY_, CP_); } while (0)
+        if (cpad == 8) CVN(4, 8);
+        else if (cpad == 16) CVN(4, 16);
+        else if (cpad == 32) CVN(4, 32);
+        else CVN(2, 64);
+#undef CVN
 #undef CV
     } else if (am == A_S2D) {
         IGN(A_S2D, E_STORE);
