@@ -171,33 +171,15 @@ def extras(c, plan, nvox, hist_per_step, launch, log):
                                           "both tallies"}
     log(f"paper field: {n2 / t2:.4g} histories/s, {u2:.4%} at 1e7")
     c.set_launch_config(**launch)
-    g = torch.Generator(device="cuda").manual_seed(0)
-    vol = (128, 256, 256)
-    net = F.UNet(vol)
-    net.init_params(1)
-    x = torch.rand((2,) + vol, device="cuda", generator=g)
-    y = torch.empty(vol, device="cuda")
-    tf = best(lambda: net.forward(x, y))
-    net.close()
-    crop = (128, 128, 128)
-    net = F.UNet(crop)
-    net.init_params(1)
-    xc = torch.rand((2,) + crop, device="cuda", generator=g)
-    tc = xc[0].clone()
-
-    def step():
-        net.backward(xc, tc, want_loss=False)
-        net.adam(1e-3)
-    ts = best(step)
-    net.close()
-    vox_f, vox_c = float(np.prod(vol)), float(np.prod(crop))
-    out["denoiser"] = {"forward_ms_256x256x128": tf * 1e3, "forward_tflops": 94_880 * vox_f / tf / 1e12,
-                       "train_step_ms_128cube": ts * 1e3, "train_tflops": 3 * 94_880 * vox_c / ts / 1e12,
-                       "peak_tflops_bf16": 2500.0,
+    from paper_1011_2188_amd import experiments as X
+    den = X.denoiser_rate(3)
+    out["denoiser"] = {"forward_ms_256x256x128": den["forward_ms"], "forward_tflops": den["forward_tflops"],
+                       "train_step_ms_128cube": den["train_step_ms"], "train_tflops": den["train_tflops"],
+                       "peak_tflops_bf16": den["peak_tflops_bf16"],
                        "seconds_to_2pct_denoised": None,
                        "note": "denoised time to 2% at equal gamma pass rate: not reached (the plain method is "
                                "faster on thorax-like plans; see profiles/denoiser_study_thorax.md)"}
-    log(f"denoiser: forward {tf * 1e3:.2f} ms, training step {ts * 1e3:.2f} ms")
+    log(f"denoiser: forward {den['forward_ms']:.2f} ms, training step {den['train_step_ms']:.2f} ms")
     return out
 
 

@@ -148,8 +148,45 @@ __global__ void __launch_bounds__(256) igemm_kernel(const u16 *__restrict__ src,
         const int co = EM == E_STORE ? n : n - (n / d2s_cout) * d2s_cout;
         bv[t] = (bias && n < n_cols) ? bias[co] : 0.f;
     }
+    if constexpr (EM == E_D2S) {
+        // The columns of a row are (sub-voxel a8, channel co) of 8 fine voxels.
+        // Per-element stores would write 2 bytes per lane, scattered over 8
+        // fine voxels; the wave instead places its tile in LDS (bf16, rows of
+        // 16 NT columns) and then writes 16-byte runs of 8 channels of one
+        // fine voxel per lane.  Needs d2s_cout, dst_pitch and dst 8-element
+        // aligned (checked by the host).  The tile is private to the wave.
+        constexpr int TP = 16 * NT + 8;                     // row pitch (16-byte rows, skewed banks)
+        __shared__ __attribute__((aligned(16))) u16 stile[4][16 * MT * TP];
+        u16 *tl = stile[threadIdx.x >> 6];
+#pragma unroll
+        for (int m = 0; m < MT; ++m)
+#pragma unroll
+            for (int t = 0; t < NT; ++t)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    float v = acc[m][t][e] + bv[t];
+                    if (relu) v = fmaxf(v, 0.f);
+                    tl[(16 * m + 4 * lg + e) * TP + 16 * t + li] = f2bf(v);
+                }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        constexpr int CH = 2 * NT;                          // 16-byte chunks per row
+#pragma unroll
+        for (int q0 = 0; q0 < 16 * MT * CH; q0 += 64) {
+            const int q = q0 + lane, rl = q / CH, cc = q % CH;
+            const long r = row0 + rl;
+            const int n = n_base + 8 * cc;
+            if (r >= n_rows || n >= n_cols) continue;
+            const int a8 = n / d2s_cout, co = n - a8 * d2s_cout;
+            const int x = (int)(r % g.nx), y = (int)((r / g.nx) % g.ny), z = (int)(r / ((long)g.nx * g.ny));
+            const long fv = ((long)(2 * z + (a8 >> 2)) * fy + (2 * y + ((a8 >> 1) & 1))) * fx + 2 * x + (a8 & 1);
+            *(uint4 *)(dst + fv * dst_pitch + co) = *(const uint4 *)(tl + rl * TP + 8 * cc);
+        }
+        return;
+    }
     u16 mk[MT][NT][4];
-    if (EM == E_STORE && mask) {
+    if (mask) {
 #pragma unroll
         for (int m = 0; m < MT; ++m)
 #pragma unroll
@@ -173,16 +210,9 @@ __global__ void __launch_bounds__(256) igemm_kernel(const u16 *__restrict__ src,
                 const long r = row0 + 16 * m + 4 * lg + e;
                 if (r >= n_rows) continue;
                 float v = acc[m][t][e] + bv[t];
-                if (EM == E_STORE) {
-                    if (relu) v = fmaxf(v, 0.f);
-                    if (mask && !(bf2f(mk[m][t][e]) > 0.f)) v = 0.f;
-                    dst[r * dst_pitch + n] = f2bf(v);
-                } else {
-                    const int a8 = n / d2s_cout, co = n - a8 * d2s_cout;
-                    const int x = (int)(r % g.nx), y = (int)((r / g.nx) % g.ny), z = (int)(r / ((long)g.nx * g.ny));
-                    const long fv = ((long)(2 * z + (a8 >> 2)) * fy + (2 * y + ((a8 >> 1) & 1))) * fx + 2 * x + (a8 & 1);
-                    dst[fv * dst_pitch + co] = f2bf(v);
-                }
+                if (relu) v = fmaxf(v, 0.f);
+                if (mask && !(bf2f(mk[m][t][e]) > 0.f)) v = 0.f;
+                dst[r * dst_pitch + n] = f2bf(v);
             }
         }
 }
@@ -900,7 +930,8 @@ hipError_t igemm(int am, int em, const View &src, int cpad, const Grid &g, const
                                              cpad, g, wpk, kpad, n_cols, bias, (int)relu, mp, mpitch, dst.p, dst.pitch, d2s_cout)
 #define IGN(AM_, EM_) do { if (nt == 4) IG(AM_, EM_, 4); else if (nt == 2) IG(AM_, EM_, 2); else IG(AM_, EM_, 1); } while (0)
     if (em == E_D2S) {
-        if (am != A_CONV1) return hipErrorInvalidValue;
+        // the staged epilogue writes 8 channels of one fine voxel as 16 bytes
+        if (am != A_CONV1 || d2s_cout % 8 || dst.pitch % 8 || ((uintptr_t)dst.p & 15)) return hipErrorInvalidValue;
         IGN(A_CONV1, E_D2S);
     } else if (am == A_CONV3) {
         // LDS-tiled kernel: 16 x TY x 4 output voxels per block (TY = 2 for 64

@@ -10,7 +10,12 @@
   recycling_study   the database-recycling test of Section 3: mean uncertainty
                     against N with the history-by-history estimator (Eq. 2)
                     and with fully independent batches (Eq. 1), for several
-                    track reuse factors R.
+                    track reuse factors R;
+  denoiser_rate     the denoiser's forward pass over a 256x256x128 volume and
+                    its training step on a 128^3 crop.
+
+`python -m paper_1011_2188_amd.experiments denoiser [--reps K]` prints the
+denoiser timings, one line per call, then a JSON summary.
 """
 from __future__ import annotations
 
@@ -216,6 +221,56 @@ def denoiser_study(db, n_train=128, n_test=6, shape=(256, 256, 128), voxel_cm=0.
     return out
 
 
+# multiply-adds of one voxel through the network (all layers, forward), times 2
+UNET_FLOP_PER_VOXEL = 94_880
+
+
+def denoiser_rate(reps=3, vol=(128, 256, 256), crop=(128, 128, 128), log=None):
+    """Best-of-`reps` (after a warm-up) wall time of the denoiser's forward pass
+    over `vol` and of one training step (forward, backward, Adam) on `crop`,
+    random inputs and He-initialised weights; sizes are (z, y, x)."""
+    import torch
+
+    def best(f):
+        f()
+        _sync()
+        ts = []
+        for _ in range(reps):
+            t = time.perf_counter()
+            f()
+            _sync()
+            ts.append(time.perf_counter() - t)
+            if log:
+                log(f"{f.__name__}: {ts[-1] * 1e3:.2f} ms")
+        return min(ts)
+
+    g = torch.Generator(device="cuda").manual_seed(0)
+    net = F.UNet(vol)
+    net.init_params(1)
+    x = torch.rand((2,) + tuple(vol), device="cuda", generator=g)
+    y = torch.empty(vol, device="cuda")
+
+    def forward():
+        net.forward(x, y)
+    tf = best(forward)
+    net.close()
+    net = F.UNet(crop)
+    net.init_params(1)
+    xc = torch.rand((2,) + tuple(crop), device="cuda", generator=g)
+    tc = xc[0].clone()
+
+    def train_step():
+        net.backward(xc, tc, want_loss=False)
+        net.adam(1e-3)
+    ts = best(train_step)
+    net.close()
+    vox_f, vox_c = float(np.prod(vol)), float(np.prod(crop))
+    return {"forward_ms": tf * 1e3, "forward_volume_zyx": list(vol),
+            "forward_tflops": UNET_FLOP_PER_VOXEL * vox_f / tf / 1e12,
+            "train_step_ms": ts * 1e3, "train_crop_zyx": list(crop),
+            "train_tflops": 3 * UNET_FLOP_PER_VOXEL * vox_c / ts / 1e12, "peak_tflops_bf16": 2500.0}
+
+
 def _c_over_sqrt(ns, us):
     """The line C / sqrt(N) through the point of lowest N (as in the paper's
     recycling figure) and the largest relative deviation of the points from it."""
@@ -328,3 +383,22 @@ def recycling_study(R_values=(1, 64, 320), db_seeds=(101, 102, 103, 104, 105, 10
             f"({rec['seconds']:.1f} s)")
         del indep, shared, hb
     return result
+
+
+def _main():
+    import argparse
+    import json
+    ap = argparse.ArgumentParser(prog="python -m paper_1011_2188_amd.experiments")
+    ap.add_argument("what", choices=["denoiser"])
+    ap.add_argument("--reps", type=int, default=3)
+    args = ap.parse_args()
+    import torch
+    assert torch.cuda.is_available(), "the experiments need a GPU"
+    torch.cuda.init()
+    if args.what == "denoiser":
+        out = denoiser_rate(args.reps, log=lambda m: print(m, flush=True))
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    _main()
