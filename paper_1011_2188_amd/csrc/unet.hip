@@ -59,6 +59,20 @@ __device__ inline bf16x8 load8(const u16 *p)
     return __builtin_bit_cast(bf16x8, q);
 }
 
+// zero the bf16 elements of v whose mask element is not > 0 (8 at a time)
+__device__ inline uint4 mask8(uint4 v, uint4 m)
+{
+    uint32_t vv[4] = {v.x, v.y, v.z, v.w};
+    const uint32_t mm[4] = {m.x, m.y, m.z, m.w};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const uint32_t keep = (bf2f((u16)(mm[i] & 0xFFFFu)) > 0.f ? 0x0000FFFFu : 0u) |
+                              (bf2f((u16)(mm[i] >> 16)) > 0.f ? 0xFFFF0000u : 0u);
+        vv[i] &= keep;
+    }
+    return make_uint4(vv[0], vv[1], vv[2], vv[3]);
+}
+
 __device__ inline bf16x8 zero8() { return __builtin_bit_cast(bf16x8, make_uint4(0, 0, 0, 0)); }
 
 // ---------------------------------------------------------------------------
@@ -255,7 +269,7 @@ __global__ void __launch_bounds__(256) conv3_kernel(const u16 *__restrict__ src,
                                                     const u16 *__restrict__ wpk, int kpad, int n_cols,
                                                     const float *__restrict__ bias, int relu,
                                                     const u16 *__restrict__ mask, int mask_pitch,
-                                                    u16 *__restrict__ dst, int dst_pitch)
+                                                    u16 *__restrict__ dst, int dst_pitch, int vec)
 {
     constexpr int TX = 16, TZ = 4, HX = TX + 2, HY = TY + 2, HZ = TZ + 2;
     constexpr int HP = CP + 8;                             // LDS channel pitch (16-byte rows, skewed banks)
@@ -269,26 +283,9 @@ __global__ void __launch_bounds__(256) conv3_kernel(const u16 *__restrict__ src,
     const int bx = blockIdx.x % tiles_x, by = (blockIdx.x / tiles_x) % tiles_y, bz = blockIdx.x / (tiles_x * tiles_y);
     const int x0 = bx * TX, y0 = by * TY, z0 = bz * TZ;
     const int n_base = blockIdx.y * 16 * NT;
-    stage16<8>((HZ * HY * HX) << GSHIFT,
-            [&](int t) -> const u16 * {
-                const int h = t >> GSHIFT, cg = t & ((1 << GSHIFT) - 1);
-                const int x = x0 - 1 + h % HX, y = y0 - 1 + (h / HX) % HY, z = z0 - 1 + h / (HX * HY);
-                if (x < 0 || x >= g.nx || y < 0 || y >= g.ny || z < 0 || z >= g.nz) return nullptr;
-                return src + (((long)z * g.ny + y) * g.nx + x) * src_pitch + 8 * cg;
-            },
-            [&](int t) { return sh + (t >> GSHIFT) * HP + 8 * (t & ((1 << GSHIFT) - 1)); });
-    __syncthreads();
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int li = lane & 15, lg = lane >> 4;
-    // element offset of this lane's row in each m tile at tap 0
-    int base[TY];
-#pragma unroll
-    for (int m = 0; m < TY; ++m) base[m] = ((w * HY + m) * HX + li) * HP;
-    f32x4 acc[TY][NT];
-#pragma unroll
-    for (int m = 0; m < TY; ++m)
-#pragma unroll
-        for (int t = 0; t < NT; ++t) acc[m][t] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const int z = z0 + w;                                  // the wave's output slice
     const u16 *wrow[NT];
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
@@ -302,6 +299,55 @@ __global__ void __launch_bounds__(256) conv3_kernel(const u16 *__restrict__ src,
 #pragma unroll
         for (int t = 0; t < NT; ++t) b[t] = load8(wrow[t] + 32 * st + 8 * lg);
     };
+    // Staged output (see the epilogue): 16 TY voxels x 16 NT channels per wave
+    // in the input tile's LDS, 16-byte chunks of 8 channels of one voxel.
+    constexpr int TP = 16 * NT + 8;                        // voxel pitch (16-byte rows, skewed banks)
+    constexpr bool STAGE = 4 * 16 * TY * TP <= HZ * HY * HX * HP;   // the output tiles fit
+    constexpr int CH = 2 * NT;                             // chunks per voxel
+    constexpr int NQ = STAGE ? 16 * TY * CH / 64 : 1;      // chunks per lane
+    static_assert(!STAGE || (16 * TY * CH) % 64 == 0, "whole chunk rounds");
+    // Everything the block reads from global memory besides the input tile
+    // (the first D weight steps, the bias, the mask chunks) is requested
+    // before the tile, so the block waits for one round trip, not four.
+    bf16x8 ring[D][NT];
+#pragma unroll
+    for (int j = 0; j < D; ++j) load_w(ring[j], j);
+    float bv[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        const int n = n_base + 16 * t + li;
+        bv[t] = (bias && n < n_cols) ? bias[n] : 0.f;
+    }
+    uint4 mq[NQ];
+    if (STAGE && vec && mask) {
+#pragma unroll
+        for (int i = 0; i < NQ; ++i) {
+            const int q = 64 * i + lane, vl = q / CH, cc = q % CH;
+            const int x = x0 + (vl & 15), y = y0 + (vl >> 4), n = n_base + 8 * cc;
+            const bool in = x < g.nx && y < g.ny && z < g.nz && n < n_cols;
+            const long r = in ? ((long)z * g.ny + y) * g.nx + x : 0;
+            mq[i] = *(const uint4 *)(mask + r * mask_pitch + (in ? n : 0));
+        }
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    stage16<8>((HZ * HY * HX) << GSHIFT,
+            [&](int t) -> const u16 * {
+                const int h = t >> GSHIFT, cg = t & ((1 << GSHIFT) - 1);
+                const int x = x0 - 1 + h % HX, y = y0 - 1 + (h / HX) % HY, z = z0 - 1 + h / (HX * HY);
+                if (x < 0 || x >= g.nx || y < 0 || y >= g.ny || z < 0 || z >= g.nz) return nullptr;
+                return src + (((long)z * g.ny + y) * g.nx + x) * src_pitch + 8 * cg;
+            },
+            [&](int t) { return sh + (t >> GSHIFT) * HP + 8 * (t & ((1 << GSHIFT) - 1)); });
+    __syncthreads();
+    // element offset of this lane's row in each m tile at tap 0
+    int base[TY];
+#pragma unroll
+    for (int m = 0; m < TY; ++m) base[m] = ((w * HY + m) * HX + li) * HP;
+    f32x4 acc[TY][NT];
+#pragma unroll
+    for (int m = 0; m < TY; ++m)
+#pragma unroll
+        for (int t = 0; t < NT; ++t) acc[m][t] = f32x4{0.f, 0.f, 0.f, 0.f};
     // LDS element offset of the lane's A fragment in step st: tap
     // o = (32 st + 8 lg) / CP at halo offset ((o/9) HY + (o/3)%3) HX + o%3,
     // channel (32 st + 8 lg) % CP.  For CP >= 32 the tap does not depend on the
@@ -311,9 +357,6 @@ __global__ void __launch_bounds__(256) conv3_kernel(const u16 *__restrict__ src,
         const int o = k / CP, c = k % CP;
         return (((o / 9) * HY + (o / 3) % 3) * HX + o % 3) * HP + c;
     };
-    bf16x8 ring[D][NT];
-#pragma unroll
-    for (int j = 0; j < D; ++j) load_w(ring[j], j);
 #pragma unroll
     for (int st = 0; st < STEPS; ++st) {
         const bool kv = 32 * st + 8 * lg < KVALID;        // false only in a last, partial step
@@ -334,16 +377,45 @@ __global__ void __launch_bounds__(256) conv3_kernel(const u16 *__restrict__ src,
         __builtin_amdgcn_sched_barrier(0);
     }
     // epilogue: lane holds D[4 lg + e][li] of every (m, t) tile: voxel x = x0 + 4 lg + e.
-    // The bias (one value per column) and the masks are loaded before any use,
-    // so their round trips overlap instead of queueing one per element.
-    const int z = z0 + w;
-    if (z >= g.nz) return;
-    float bv[NT];
+    if (STAGE && vec) {
+        // Staged output: each wave writes its 16 TY voxels x 16 NT channels
+        // (bias, ReLU applied, bf16) into the LDS the input tile used, then
+        // stores 16-byte runs of 8 channels of one voxel per lane, the mask
+        // applied 8 channels at a time.  Per-element stores would write
+        // 2 bytes per lane in 32-byte pieces of 4 voxels.  vec needs n_cols,
+        // the pitches and the dst and mask pointers 8-element aligned (the
+        // host checks).
+        __syncthreads();                                   // every wave is done with the input tile
+        u16 *tl = sh + w * (16 * TY * TP);
 #pragma unroll
-    for (int t = 0; t < NT; ++t) {
-        const int n = n_base + 16 * t + li;
-        bv[t] = (bias && n < n_cols) ? bias[n] : 0.f;
+        for (int m = 0; m < TY; ++m)
+#pragma unroll
+            for (int t = 0; t < NT; ++t)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    float v = acc[m][t][e] + bv[t];
+                    if (relu) v = fmaxf(v, 0.f);
+                    tl[(16 * m + 4 * lg + e) * TP + 16 * t + li] = f2bf(v);
+                }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (z >= g.nz) return;
+#pragma unroll
+        for (int i = 0; i < NQ; ++i) {
+            const int q = 64 * i + lane, vl = q / CH, cc = q % CH;
+            const int x = x0 + (vl & 15), y = y0 + (vl >> 4), n = n_base + 8 * cc;
+            if (x >= g.nx || y >= g.ny || n >= n_cols) continue;
+            const long r = ((long)z * g.ny + y) * g.nx + x;
+            uint4 o = *(const uint4 *)(tl + vl * TP + 8 * cc);
+            if (mask) o = mask8(o, mq[i]);
+            *(uint4 *)(dst + r * dst_pitch + n) = o;
+        }
+        return;
     }
+    // per-element path.  The masks are loaded before any use, so their round
+    // trips overlap instead of queueing one per element.
+    if (z >= g.nz) return;
     u16 mk[TY][NT][4];
     if (mask) {
 #pragma unroll
@@ -943,8 +1015,11 @@ hipError_t igemm(int am, int em, const View &src, int cpad, const Grid &g, const
         const uint32_t tiles = (uint32_t)(((g.nx + 15) / 16) * ((g.ny + ty - 1) / ty) * ((g.nz + 3) / 4));
         const dim3 cgrid(tiles, (uint32_t)((n_cols + 16 * nt - 1) / (16 * nt)));
         const size_t lds = (size_t)6 * (ty + 2) * 18 * (cpad + 8) * sizeof(u16);
+        // 16-byte output stores (and mask loads) need 8-element alignment throughout
+        const auto al = [](const void *p) { return ((uintptr_t)p & 15) == 0; };
+        const int vec = n_cols % 8 == 0 && dst.pitch % 8 == 0 && al(dst.p) && (!mp || (mpitch % 8 == 0 && al(mp)));
 #define CV(NT_, TY_, CP_) hipLaunchKernelGGL((conv3_kernel<NT_, TY_, CP_>), cgrid, dim3(256), lds, s, src.p, src.pitch, \
-                                             g, wpk, kpad, n_cols, bias, (int)relu, mp, mpitch, dst.p, dst.pitch)
+                                             g, wpk, kpad, n_cols, bias, (int)relu, mp, mpitch, dst.p, dst.pitch, vec)
 #define CVN(TY_, CP_) do { if (nt == 4) CV(4, TY_, CP_); else if (nt == 2) CV(2, TY_, CP_); else CV(1, TY_, CP_); } while (0)
         if (cpad == 8) CVN(4, 8);
         else if (cpad == 16) CVN(4, 16);
