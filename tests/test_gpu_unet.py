@@ -113,3 +113,48 @@ def test_unet_overfits_one_crop():
         net.adam(3e-3)
     last = net.backward(xin, tt)
     assert last < 0.2 * first
+
+
+def _wgrad3_fp64(gout, inp, shape):
+    """dW[co, ci, dz, dy, dx] = sum over voxels v of gout[v, co] * inp[v + (dz, dy, dx) - 1, ci]
+    (zero outside), in FP64 from the bf16 values the kernels contracted."""
+    nz, ny, nx = shape
+    co, ci = gout.shape[1], inp.shape[1]
+    g = gout.astype(np.float64)
+    xp = np.pad(inp.astype(np.float64).reshape(nz, ny, nx, ci), ((1, 1), (1, 1), (1, 1), (0, 0)))
+    dw = np.zeros((co, ci, 3, 3, 3))
+    for dz in range(3):
+        for dy in range(3):
+            for dx in range(3):
+                dw[:, :, dz, dy, dx] = g.T @ xp[dz:dz + nz, dy:dy + ny, dx:dx + nx].reshape(-1, ci)
+    return dw
+
+
+def test_unet_weight_gradients_multi_tile():
+    """Weight gradients of one layer per weight-gradient kernel shape (16, 32
+    and 64 channels) on a 64 x 128 x 128 crop, where every workgroup walks
+    several tiles (the next tile is prefetched while the current one is
+    contracted), against an FP64 contraction of the same bf16 operands."""
+    shape = (64, 128, 128)
+    rng = np.random.default_rng(7)
+    P = U.init_params(7)
+    flat = U.flatten(P).astype(np.float32)
+    x = np.stack([rng.random(shape) * 2.0, 0.5 + rng.random(shape)]).astype(np.float32)
+    t = (x[0] + 0.1 * rng.standard_normal(shape)).astype(np.float32)
+    net = F.UNet(shape)
+    net.set_params(flat)
+    net.backward(torch.tensor(x, device="cuda"), torch.tensor(t, device="cuda"), want_loss=False)
+    gg = net.get_grads()
+    offs, off = {}, 0
+    for name, kind, ci, co in U.LAYERS:
+        offs[name] = off
+        off += int(np.prod(U.weight_shape(kind, ci, co))) + co
+    levels = [shape, tuple(s // 2 for s in shape), tuple(s // 4 for s in shape)]
+    for layer, gname, iname, lvl, ci, co in [("enc1b", "ge1", "e1a", 0, 16, 16), ("enc2b", "ge2", "e2a", 1, 32, 32),
+                                             ("midb", "gm", "ma", 2, 64, 64)]:
+        want = _wgrad3_fp64(net.debug_buffer(gname)[:, :co], net.debug_buffer(iname)[:, :ci], levels[lvl])
+        got = gg[offs[layer]:offs[layer] + want.size].reshape(want.shape)
+        err = float(np.max(np.abs(got - want))) / _rms(want)
+        print(f"{layer}: max |GPU - FP64| = {err:.2e} of the RMS gradient")
+        assert err <= 1e-4, layer
+    net.close()
