@@ -584,9 +584,11 @@ __global__ void __launch_bounds__(256) wgrad3t_kernel(const u16 *__restrict__ P,
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int lg = lane >> 4;
     const int tiles_j = qc / 16, n_ct = (pc / 16) * tiles_j;   // channel tiles
-    const int n_acc = G * n_ct;                                // <= 48 (the host picks G)
+    const int n_acc = G * n_ct;                                // <= 4 kMaxAcc (the host picks G)
     const int pcg = pc / 8, qcg = qc / 8;
-    constexpr int kMaxAcc = 12;
+    // accumulator tiles per wave: 14 for the 16 x 4 x 2 tiles (16 x 32 channel layers keep all 27
+    // taps in one block), 12 elsewhere (more registers slow the other shapes down)
+    constexpr int kMaxAcc = (TY == 4 && TZ == 2) ? 14 : 12;
     f32x4 acc[kMaxAcc];
 #pragma unroll
     for (int q = 0; q < kMaxAcc; ++q) acc[q] = f32x4{0.f, 0.f, 0.f, 0.f};
@@ -1055,11 +1057,13 @@ hipError_t wgrad(int am, const View &P, int p_ch, const View &Q, int q_ch, const
     if (am == A_CONV3) {
         // 3D tiles: 16 x 4 x 4 voxels for 16-channel operands, 16 x 4 x 2 for 32,
         // 16 x 2 x 2 for 64 (tile and halo under 64 KB of LDS); taps per block G
-        // so that G x channel tiles <= 48 accumulators
+        // so that G x channel tiles fit the kernel's accumulators (4 waves x 14
+        // for 16 x 4 x 2 tiles, 4 x 12 otherwise)
         const int cmax = std::max(pc, qc);
         const int ty = cmax <= 32 ? 4 : 2, tz = cmax <= 16 ? 4 : 2;
         const int n_ct = (pc / 16) * (qc / 16);
-        const int G = 27 * n_ct <= 48 ? 27 : (9 * n_ct <= 48 ? 9 : 3);
+        const int amax = (ty == 4 && tz == 2) ? 56 : 48;
+        const int G = 27 * n_ct <= amax ? 27 : (9 * n_ct <= amax ? 9 : 3);
         const long tiles = ((g.nx + 15) / 16) * (long)((g.ny + ty - 1) / ty) * ((g.nz + tz - 1) / tz);
         const long cap = (long)(u->wpart_n / ((size_t)27 * pc * qc));
         slabs = std::max<long>(1, std::min<long>({tiles, cap, 2048L / (27 / G)}));

@@ -131,8 +131,8 @@ def _wgrad3_fp64(gout, inp, shape):
 
 
 def test_unet_weight_gradients_multi_tile():
-    """Weight gradients of one layer per weight-gradient kernel shape (16, 32
-    and 64 channels) on a 64 x 128 x 128 crop, where every workgroup walks
+    """Weight gradients of one layer per weight-gradient kernel shape (16, 16 x 32,
+    32 and 64 channels) on a 64 x 128 x 128 crop, where every workgroup walks
     several tiles (the next tile is prefetched while the current one is
     contracted), against an FP64 contraction of the same bf16 operands."""
     shape = (64, 128, 128)
@@ -150,8 +150,8 @@ def test_unet_weight_gradients_multi_tile():
         offs[name] = off
         off += int(np.prod(U.weight_shape(kind, ci, co))) + co
     levels = [shape, tuple(s // 2 for s in shape), tuple(s // 4 for s in shape)]
-    for layer, gname, iname, lvl, ci, co in [("enc1b", "ge1", "e1a", 0, 16, 16), ("enc2b", "ge2", "e2a", 1, 32, 32),
-                                             ("midb", "gm", "ma", 2, 64, 64)]:
+    for layer, gname, iname, lvl, ci, co in [("enc1b", "ge1", "e1a", 0, 16, 16), ("dec1a", "gd1a", "c1", 0, 32, 16),
+                                             ("enc2b", "ge2", "e2a", 1, 32, 32), ("midb", "gm", "ma", 2, 64, 64)]:
         want = _wgrad3_fp64(net.debug_buffer(gname)[:, :co], net.debug_buffer(iname)[:, :ci], levels[lvl])
         got = gg[offs[layer]:offs[layer] + want.size].reshape(want.shape)
         err = float(np.max(np.abs(got - want))) / _rms(want)
