@@ -559,9 +559,11 @@ __device__ inline bf16x8 tr_frag(const u16 *tile, int pitch, int row, int col)
 
 // Weight gradient of a 3x3x3 convolution over 3D tiles.  A block loops over
 // tiles of 16 (x) x TY x TZ voxels (tile t = blockIdx.x + k * gridDim.x) and
-// owns the taps og * G .. og * G + G - 1 (og = blockIdx.y).  Per tile it stages
-// the output gradient P of the tile and the input Q of the tile plus a
-// one-voxel halo (row-major, 16-byte copies); the contraction runs over the
+// owns the taps og * G .. og * G + G - 1 and the Q channels
+// 16 qs oq .. 16 qs (oq + 1) - 1 (blockIdx.y = og * (qc / 16 / qs) + oq).  Per
+// tile it stages the output gradient P of the tile (all its channels) and the
+// block's channels of the input Q over the tile plus a one-voxel halo
+// (row-major, 16-byte copies); the contraction runs over the
 // tile's voxels in x-fastest order, 32 at a time.  Eight consecutive
 // contraction voxels are 8 consecutive x of one row, and for every tap their
 // shifted neighbours are 8 consecutive halo rows, so both MFMA operands come
@@ -571,21 +573,22 @@ __device__ inline bf16x8 tr_frag(const u16 *tile, int pitch, int row, int col)
 template <int TY, int TZ>
 __global__ void __launch_bounds__(256) wgrad3t_kernel(const u16 *__restrict__ P, int p_pitch, int p_ch,
                                                       const u16 *__restrict__ Q, int q_pitch, int q_ch, Grid g,
-                                                      float *__restrict__ part, int pc, int qc, int G)
+                                                      float *__restrict__ part, int pc, int qc, int G, int qs)
 {
     constexpr int TX = 16, HX = TX + 2, HY = TY + 2, HZ = TZ + 2, TV = TX * TY * TZ;
     extern __shared__ __attribute__((aligned(16))) u16 lds[];
-    const int sp_pitch = pc + 8, sq_pitch = qc + 8;
+    const int nq = qc / (16 * qs);                             // Q channel slices
+    const int o0 = (blockIdx.y / nq) * G, q_off = 16 * qs * (blockIdx.y % nq);
+    const int sp_pitch = pc + 8, sq_pitch = 16 * qs + 8;
     u16 *sP = lds;
     u16 *sQ = lds + TV * sp_pitch;
     const int tiles_x = (g.nx + TX - 1) / TX, tiles_y = (g.ny + TY - 1) / TY, tiles_z = (g.nz + TZ - 1) / TZ;
     const int n_tiles_grid = tiles_x * tiles_y * tiles_z;
-    const int o0 = blockIdx.y * G;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int lg = lane >> 4;
-    const int tiles_j = qc / 16, n_ct = (pc / 16) * tiles_j;   // channel tiles
-    const int n_acc = G * n_ct;                                // <= 4 kMaxAcc (the host picks G)
-    const int pcg = pc / 8, qcg = qc / 8;
+    const int tiles_j = qs, n_ct = (pc / 16) * tiles_j;        // the block's channel tiles
+    const int n_acc = G * n_ct;                                // <= 4 kMaxAcc (the host picks G, qs)
+    const int pcg = pc / 8, qcg = 2 * qs;
     // accumulator tiles per wave: 14 for the 16 x 4 x 2 tiles (16 x 32 channel layers keep all 27
     // taps in one block), 12 elsewhere (more registers slow the other shapes down)
     constexpr int kMaxAcc = (TY == 4 && TZ == 2) ? 14 : 12;
@@ -608,8 +611,9 @@ __global__ void __launch_bounds__(256) wgrad3t_kernel(const u16 *__restrict__ P,
                 [&](int u) -> const u16 * {
                     const int h = u / qcg, cg = u - h * qcg;
                     const int x = x0 - 1 + h % HX, y = y0 - 1 + (h / HX) % HY, z = z0 - 1 + h / (HX * HY);
-                    if (x < 0 || x >= g.nx || y < 0 || y >= g.ny || z < 0 || z >= g.nz || 8 * cg >= q_ch) return nullptr;
-                    return Q + (((long)z * g.ny + y) * g.nx + x) * q_pitch + 8 * cg;
+                    if (x < 0 || x >= g.nx || y < 0 || y >= g.ny || z < 0 || z >= g.nz || q_off + 8 * cg >= q_ch)
+                        return nullptr;
+                    return Q + (((long)z * g.ny + y) * g.nx + x) * q_pitch + q_off + 8 * cg;
                 },
                 [&](int u) { return sQ + (u / qcg) * sq_pitch + 8 * (u % qcg); });
         __syncthreads();
@@ -643,7 +647,7 @@ __global__ void __launch_bounds__(256) wgrad3t_kernel(const u16 *__restrict__ P,
         const int ti = ct / tiles_j, tj = ct % tiles_j;
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-            const int i = 16 * ti + 4 * lg + e, j = 16 * tj + li;
+            const int i = 16 * ti + 4 * lg + e, j = q_off + 16 * tj + li;
             part[(((long)blockIdx.x * 27 + o) * pc + i) * qc + j] = acc[q][e];
         }
     }
@@ -1055,22 +1059,35 @@ hipError_t wgrad(int am, const View &P, int p_ch, const View &Q, int q_ch, const
     const size_t need = (size_t)slabs * n_off * pc * qc;
     if (need > u->wpart_n) return hipErrorInvalidValue;
     if (am == A_CONV3) {
-        // 3D tiles: 16 x 4 x 4 voxels for 16-channel operands, 16 x 4 x 2 for 32,
-        // 16 x 2 x 2 for 64 (tile and halo under 64 KB of LDS); taps per block G
-        // so that G x channel tiles fit the kernel's accumulators (4 waves x 14
-        // for 16 x 4 x 2 tiles, 4 x 12 otherwise)
-        const int cmax = std::max(pc, qc);
-        const int ty = cmax <= 32 ? 4 : 2, tz = cmax <= 16 ? 4 : 2;
-        const int n_ct = (pc / 16) * (qc / 16);
-        const int amax = (ty == 4 && tz == 2) ? 56 : 48;
-        const int G = 27 * n_ct <= amax ? 27 : (9 * n_ct <= amax ? 9 : 3);
+        // Tile shape (16 x 4 x 4, 16 x 4 x 2 or 16 x 2 x 2 voxels), taps per block G
+        // and Q channel tiles per block qs: the feasible choice (accumulator
+        // tiles G x pc/16 x qs within the kernel's 4 waves x 14 for 16 x 4 x 2
+        // tiles, 4 x 12 otherwise; P tile and Q halo slice within 64 KB of LDS)
+        // that stages the fewest elements per voxel of the layer,
+        // (27 / G) (qc / 16 / qs) (TV pc + HV 16 qs) / TV; ties go to the larger tile.
+        const int shapes[3][2] = {{4, 4}, {4, 2}, {2, 2}};
+        int ty = 0, tz = 0, G = 0, qs = 0;
+        double best = 0.0;
+        for (const auto &sh : shapes) {
+            const int tv = 16 * sh[0] * sh[1], hv = 18 * (sh[0] + 2) * (sh[1] + 2);
+            const int amax = (sh[0] == 4 && sh[1] == 2) ? 56 : 48;
+            for (int gg : {27, 9, 3})
+                for (int q = qc / 16; q >= 1; q /= 2) {
+                    if ((qc / 16) % q || gg * (pc / 16) * q > amax) continue;
+                    if (((size_t)tv * (pc + 8) + (size_t)hv * (16 * q + 8)) * sizeof(u16) > 65536) continue;
+                    const double cost = (double)(27 / gg) * (qc / 16 / q) * ((double)tv * pc + (double)hv * 16 * q) / tv;
+                    if (!G || cost < best) { best = cost; ty = sh[0]; tz = sh[1]; G = gg; qs = q; }
+                }
+        }
+        if (!G) return hipErrorInvalidValue;
+        const int ny_blocks = (27 / G) * (qc / (16 * qs));
         const long tiles = ((g.nx + 15) / 16) * (long)((g.ny + ty - 1) / ty) * ((g.nz + tz - 1) / tz);
         const long cap = (long)(u->wpart_n / ((size_t)27 * pc * qc));
-        slabs = std::max<long>(1, std::min<long>({tiles, cap, 2048L / (27 / G)}));
-        const size_t lds = ((size_t)16 * ty * tz * (pc + 8) + (size_t)18 * (ty + 2) * (tz + 2) * (qc + 8)) * sizeof(u16);
-        const dim3 grid((uint32_t)slabs, (uint32_t)(27 / G));
+        slabs = std::max<long>(1, std::min<long>({tiles, cap, std::max(1L, 2048L / ny_blocks)}));
+        const size_t lds = ((size_t)16 * ty * tz * (pc + 8) + (size_t)18 * (ty + 2) * (tz + 2) * (16 * qs + 8)) * sizeof(u16);
+        const dim3 grid((uint32_t)slabs, (uint32_t)ny_blocks);
 #define WT(TY_, TZ_) hipLaunchKernelGGL((wgrad3t_kernel<TY_, TZ_>), grid, dim3(256), lds, s, P.p, P.pitch, p_ch, \
-                                        Q.p, Q.pitch, q_ch, g, u->wpart, pc, qc, G)
+                                        Q.p, Q.pitch, q_ch, g, u->wpart, pc, qc, G, qs)
         if (ty == 4 && tz == 4) WT(4, 4); else if (ty == 4) WT(4, 2); else WT(2, 2);
 #undef WT
     } else
