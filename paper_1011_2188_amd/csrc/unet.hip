@@ -264,7 +264,9 @@ __device__ inline void stage16(int total, Src src, Dst dst)
     }
 }
 
-template <int NT, int TY, int CP>
+// CS < CP: the input channels are staged CS at a time (phases of all 27 taps
+// over CS channels), so the tile fits LDS with room for more blocks per CU.
+template <int NT, int TY, int CP, int CS = CP>
 __global__ void __launch_bounds__(256) conv3_kernel(const u16 *__restrict__ src, int src_pitch, Grid g,
                                                     const u16 *__restrict__ wpk, int kpad, int n_cols,
                                                     const float *__restrict__ bias, int relu,
@@ -272,12 +274,15 @@ __global__ void __launch_bounds__(256) conv3_kernel(const u16 *__restrict__ src,
                                                     u16 *__restrict__ dst, int dst_pitch, int vec)
 {
     constexpr int TX = 16, TZ = 4, HX = TX + 2, HY = TY + 2, HZ = TZ + 2;
-    constexpr int HP = CP + 8;                             // LDS channel pitch (16-byte rows, skewed banks)
-    constexpr int GSHIFT = CP == 8 ? 0 : CP == 16 ? 1 : CP == 32 ? 2 : 3;   // CP / 8 = 1 << GSHIFT
-    constexpr int KVALID = 27 * CP;
-    constexpr int STEPS = (KVALID + 31) / 32;              // K steps of 32
+    static_assert(CP % CS == 0 && (CS == CP || CS % 32 == 0), "phases of whole K steps");
+    constexpr int HP = CS + 8;                             // LDS channel pitch (16-byte rows, skewed banks)
+    constexpr int GSHIFT = CS == 8 ? 0 : CS == 16 ? 1 : CS == 32 ? 2 : 3;   // CS / 8 = 1 << GSHIFT
+    constexpr int KVALID = 27 * CS;                        // K of one phase
+    constexpr int STEPS = (KVALID + 31) / 32;              // K steps of 32 per phase
+    constexpr int PH = CP / CS;                            // phases
+    constexpr int TOTAL = PH * STEPS;
     constexpr int D0 = NT == 1 ? 8 : NT == 2 ? 4 : 2;
-    constexpr int D = D0 < STEPS ? D0 : STEPS;             // weight look-ahead, in K steps
+    constexpr int D = D0 < TOTAL ? D0 : TOTAL;             // weight look-ahead, in K steps
     extern __shared__ __attribute__((aligned(16))) u16 sh[];
     const int tiles_x = (g.nx + TX - 1) / TX, tiles_y = (g.ny + TY - 1) / TY;
     const int bx = blockIdx.x % tiles_x, by = (blockIdx.x / tiles_x) % tiles_y, bz = blockIdx.x / (tiles_x * tiles_y);
@@ -292,12 +297,16 @@ __global__ void __launch_bounds__(256) conv3_kernel(const u16 *__restrict__ src,
         const int n = n_base + 16 * t + li;
         wrow[t] = wpk + (long)(n < n_cols ? n : 0) * kpad;
     }
-    // weight fragments of K step st: plain loads (no select on the loaded
-    // value, which would make the wave wait for it at once).  The packed table
-    // is zero from KVALID to kpad, and columns past n_cols are never stored.
-    auto load_w = [&](bf16x8 *b, int st) {
+    // weight fragments of K step gs (phase gs / STEPS): the lane group's 8
+    // channels c of tap o sit at k = o CP + CS phase + c of the packed table.
+    // Plain loads (no select on the loaded value, which would make the wave
+    // wait for it at once).  The packed table is zero from 27 CP to kpad, and
+    // columns past n_cols are never stored.
+    auto load_w = [&](bf16x8 *b, int gs) {
+        const int kl = 32 * (gs % STEPS) + 8 * lg;
+        const int k = (kl / CS) * CP + (gs / STEPS) * CS + kl % CS;
 #pragma unroll
-        for (int t = 0; t < NT; ++t) b[t] = load8(wrow[t] + 32 * st + 8 * lg);
+        for (int t = 0; t < NT; ++t) b[t] = load8(wrow[t] + k);
     };
     // Staged output (see the epilogue): 16 TY voxels x 16 NT channels per wave
     // in the input tile's LDS, 16-byte chunks of 8 channels of one voxel.
@@ -330,14 +339,18 @@ __global__ void __launch_bounds__(256) conv3_kernel(const u16 *__restrict__ src,
         }
     }
     __builtin_amdgcn_sched_barrier(0);
-    stage16<8>((HZ * HY * HX) << GSHIFT,
-            [&](int t) -> const u16 * {
-                const int h = t >> GSHIFT, cg = t & ((1 << GSHIFT) - 1);
-                const int x = x0 - 1 + h % HX, y = y0 - 1 + (h / HX) % HY, z = z0 - 1 + h / (HX * HY);
-                if (x < 0 || x >= g.nx || y < 0 || y >= g.ny || z < 0 || z >= g.nz) return nullptr;
-                return src + (((long)z * g.ny + y) * g.nx + x) * src_pitch + 8 * cg;
-            },
-            [&](int t) { return sh + (t >> GSHIFT) * HP + 8 * (t & ((1 << GSHIFT) - 1)); });
+    // channels CS ph .. CS ph + CS - 1 of the tile and its halo into LDS
+    auto stage = [&](int ph) {
+        stage16<8>((HZ * HY * HX) << GSHIFT,
+                [&](int t) -> const u16 * {
+                    const int h = t >> GSHIFT, cg = t & ((1 << GSHIFT) - 1);
+                    const int x = x0 - 1 + h % HX, y = y0 - 1 + (h / HX) % HY, z = z0 - 1 + h / (HX * HY);
+                    if (x < 0 || x >= g.nx || y < 0 || y >= g.ny || z < 0 || z >= g.nz) return nullptr;
+                    return src + (((long)z * g.ny + y) * g.nx + x) * src_pitch + CS * ph + 8 * cg;
+                },
+                [&](int t) { return sh + (t >> GSHIFT) * HP + 8 * (t & ((1 << GSHIFT) - 1)); });
+    };
+    stage(0);
     __syncthreads();
     // element offset of this lane's row in each m tile at tap 0
     int base[TY];
@@ -348,33 +361,42 @@ __global__ void __launch_bounds__(256) conv3_kernel(const u16 *__restrict__ src,
     for (int m = 0; m < TY; ++m)
 #pragma unroll
         for (int t = 0; t < NT; ++t) acc[m][t] = f32x4{0.f, 0.f, 0.f, 0.f};
-    // LDS element offset of the lane's A fragment in step st: tap
-    // o = (32 st + 8 lg) / CP at halo offset ((o/9) HY + (o/3)%3) HX + o%3,
-    // channel (32 st + 8 lg) % CP.  For CP >= 32 the tap does not depend on the
-    // lane; for smaller CP the lane group picks one of 32/CP taps of the step.
+    // LDS element offset of the lane's A fragment in step st of a phase: tap
+    // o = (32 st + 8 lg) / CS at halo offset ((o/9) HY + (o/3)%3) HX + o%3,
+    // channel (32 st + 8 lg) % CS.  For CS >= 32 the tap does not depend on the
+    // lane; for smaller CS the lane group picks one of 32/CS taps of the step.
     auto a_off = [&](int st) {
         const int k = 32 * st + 8 * lg;
-        const int o = k / CP, c = k % CP;
+        const int o = k / CS, c = k % CS;
         return (((o / 9) * HY + (o / 3) % 3) * HX + o % 3) * HP + c;
     };
 #pragma unroll
-    for (int st = 0; st < STEPS; ++st) {
-        const bool kv = 32 * st + 8 * lg < KVALID;        // false only in a last, partial step
-        const int off = kv ? a_off(st) : 0;
-        bf16x8 a[TY];
-#pragma unroll
-        for (int m = 0; m < TY; ++m) a[m] = load8(sh + base[m] + off);
-#pragma unroll
-        for (int m = 0; m < TY; ++m) {
-            const bf16x8 am = (32 * st + 32 <= KVALID || kv) ? a[m] : zero8();
-#pragma unroll
-            for (int t = 0; t < NT; ++t)
-                acc[m][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am, ring[st % D][t], acc[m][t], 0, 0, 0);
+    for (int ph = 0; ph < PH; ++ph) {
+        if (ph > 0) {                                      // every wave is done with the previous channels
+            __syncthreads();
+            stage(ph);
+            __syncthreads();
         }
-        if (st + D < STEPS) load_w(ring[st % D], st + D);
-        // keep each step's loads in their step: the scheduler would otherwise
-        // sink the look-ahead loads next to their use
-        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int st = 0; st < STEPS; ++st) {
+            const int gs = ph * STEPS + st;
+            const bool kv = 32 * st + 8 * lg < KVALID;    // false only in a last, partial step
+            const int off = kv ? a_off(st) : 0;
+            bf16x8 a[TY];
+#pragma unroll
+            for (int m = 0; m < TY; ++m) a[m] = load8(sh + base[m] + off);
+#pragma unroll
+            for (int m = 0; m < TY; ++m) {
+                const bf16x8 am = (32 * st + 32 <= KVALID || kv) ? a[m] : zero8();
+#pragma unroll
+                for (int t = 0; t < NT; ++t)
+                    acc[m][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am, ring[gs % D][t], acc[m][t], 0, 0, 0);
+            }
+            if (gs + D < TOTAL) load_w(ring[gs % D], gs + D);
+            // keep each step's loads in their step: the scheduler would otherwise
+            // sink the look-ahead loads next to their use
+            __builtin_amdgcn_sched_barrier(0);
+        }
     }
     // epilogue: lane holds D[4 lg + e][li] of every (m, t) tile: voxel x = x0 + 4 lg + e.
     if (STAGE && vec) {
@@ -1012,25 +1034,27 @@ hipError_t igemm(int am, int em, const View &src, int cpad, const Grid &g, const
         if (am != A_CONV1 || d2s_cout % 8 || dst.pitch % 8 || ((uintptr_t)dst.p & 15)) return hipErrorInvalidValue;
         IGN(A_CONV1, E_D2S);
     } else if (am == A_CONV3) {
-        // LDS-tiled kernel: 16 x TY x 4 output voxels per block (TY = 2 for 64
-        // input channels, so the tile and its halo stay under 64 KB of LDS),
-        // compiled per padded channel count so that the K loop unrolls
-        const int ty = cpad >= 64 ? 2 : 4;
+        // LDS-tiled kernel: 16 x 4 x 4 output voxels per block, compiled per
+        // padded channel count so that the K loop unrolls; 64 input channels
+        // are staged 32 at a time, so the tile and its halo take 52 KB of LDS
+        const int ty = 4, cs = std::min(cpad, 32);
         if (cpad != 8 && cpad != 16 && cpad != 32 && cpad != 64) return hipErrorInvalidValue;
         if (kpad < (27 * cpad + 31) / 32 * 32) return hipErrorInvalidValue;   // the K loop reads 32-wide steps
         const uint32_t tiles = (uint32_t)(((g.nx + 15) / 16) * ((g.ny + ty - 1) / ty) * ((g.nz + 3) / 4));
         const dim3 cgrid(tiles, (uint32_t)((n_cols + 16 * nt - 1) / (16 * nt)));
-        const size_t lds = (size_t)6 * (ty + 2) * 18 * (cpad + 8) * sizeof(u16);
+        const size_t lds = (size_t)6 * (ty + 2) * 18 * (cs + 8) * sizeof(u16);
         // 16-byte output stores (and mask loads) need 8-element alignment throughout
         const auto al = [](const void *p) { return ((uintptr_t)p & 15) == 0; };
         const int vec = n_cols % 8 == 0 && dst.pitch % 8 == 0 && al(dst.p) && (!mp || (mpitch % 8 == 0 && al(mp)));
-#define CV(NT_, TY_, CP_) hipLaunchKernelGGL((conv3_kernel<NT_, TY_, CP_>), cgrid, dim3(256), lds, s, src.p, src.pitch, \
-                                             g, wpk, kpad, n_cols, bias, (int)relu, mp, mpitch, dst.p, dst.pitch, vec)
-#define CVN(TY_, CP_) do { if (nt == 4) CV(4, TY_, CP_); else if (nt == 2) CV(2, TY_, CP_); else CV(1, TY_, CP_); } while (0)
-        if (cpad == 8) CVN(4, 8);
-        else if (cpad == 16) CVN(4, 16);
-        else if (cpad == 32) CVN(4, 32);
-        else CVN(2, 64);
+#define CV(NT_, TY_, CP_, CS_) hipLaunchKernelGGL((conv3_kernel<NT_, TY_, CP_, CS_>), cgrid, dim3(256), lds, s, src.p, \
+                                                  src.pitch, g, wpk, kpad, n_cols, bias, (int)relu, mp, mpitch, dst.p, \
+                                                  dst.pitch, vec)
+#define CVN(TY_, CP_, CS_) do { if (nt == 4) CV(4, TY_, CP_, CS_); else if (nt == 2) CV(2, TY_, CP_, CS_); \
+                                else CV(1, TY_, CP_, CS_); } while (0)
+        if (cpad == 8) CVN(4, 8, 8);
+        else if (cpad == 16) CVN(4, 16, 16);
+        else if (cpad == 32) CVN(4, 32, 32);
+        else CVN(4, 64, 32);
 #undef CVN
 #undef CV
     } else if (am == A_S2D) {
