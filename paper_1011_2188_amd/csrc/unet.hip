@@ -685,8 +685,10 @@ __global__ void __launch_bounds__(512) slab_sum_kernel(const float *__restrict__
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const long x = blockIdx.x * 64L + lane;
     float s = 0.f;
-    if (x < per_slab)
+    if (x < per_slab) {
+#pragma unroll 8
         for (int k = w; k < slabs; k += 8) s += part[k * per_slab + x];
+    }
     red[w][lane] = s;
     __syncthreads();
     if (w == 0 && x < per_slab) {
@@ -710,6 +712,7 @@ __global__ void __launch_bounds__(256) bias_part_kernel(const u16 *__restrict__ 
     const long v0 = blockIdx.x * per_block, v1 = std::min<long>(n, v0 + per_block);
     float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     if (vo < per_step) {
+#pragma unroll 4
         for (long v = v0 + vo; v < v1; v += per_step) {
             const uint4 q = *(const uint4 *)(G + v * pitch + 8 * cg);
             const u16 *h = (const u16 *)&q;
@@ -832,13 +835,16 @@ __global__ void head_finish_kernel(const double *__restrict__ loss_part, const f
                                    double *__restrict__ loss, float *__restrict__ grad_head)
 {
     const int c = threadIdx.x;
+    // sequential sums (a fixed order), unrolled so that several loads are in flight
     if (c < 17) {
         float s = 0.f;
+#pragma unroll 8
         for (int b = 0; b < nb; ++b) s += gw_part[b * 17 + c];
         grad_head[c] = s;
     }
     if (c == 0) {
         double l = 0.0;
+#pragma unroll 8
         for (int b = 0; b < nb; ++b) l += loss_part[b];
         *loss = l;
     }
@@ -918,8 +924,10 @@ __global__ void __launch_bounds__(256) bias_finish_kernel(const float *__restric
     __shared__ float red[256];
     const int groups = 256 / C, c = threadIdx.x % C, j = threadIdx.x / C;
     float s = 0.f;
-    if (j < groups)
+    if (j < groups) {
+#pragma unroll 8
         for (int b = j; b < nb; b += groups) s += part[(long)b * C + c];
+    }
     red[threadIdx.x] = s;
     __syncthreads();
     if ((int)threadIdx.x < C) {
@@ -1131,7 +1139,11 @@ hipError_t wgrad(int am, const View &P, int p_ch, const View &Q, int q_ch, const
 hipError_t bias_grad(const View &G, int C, long n, fdc_unet *u, float *gb, hipStream_t s)
 {
     if (C % 8 || C > 64) return hipErrorInvalidValue;
-    const long per = 4096;
+    // at most 512 blocks (the partials buffer), each a whole number of rounds
+    // of its 256 threads over C/8 channel groups, at least one round
+    const long per_step = 256 / (C / 8);
+    long per = (n + 511) / 512;
+    per = std::max(per_step, (per + per_step - 1) / per_step * per_step);
     const int nb = (int)((n + per - 1) / per);
     hipLaunchKernelGGL(bias_part_kernel, dim3(nb), dim3(256), 0, s, G.p, G.pitch, C, n, per, u->bpart);
     hipLaunchKernelGGL(bias_finish_kernel, dim3(1), dim3(256), 0, s, u->bpart, nb, C, gb);
@@ -1407,7 +1419,7 @@ int fdc_unet_create(fdc_unet **out, int hip_device, int nx, int ny, int nz)
     u->wpart_n = (size_t)64 * 27 * 64 * 64;
     u->wpart = ualloc<float>(u, u->wpart_n);
     u->wsum = ualloc<float>(u, 27 * 64 * 64 + 256);
-    u->bpart = ualloc<float>(u, (size_t)((n0 + 4095) / 4096) * 64);
+    u->bpart = ualloc<float>(u, (size_t)512 * 64);
     u->hpart = ualloc<float>(u, (size_t)((n0 + 8191) / 8192) * 17);
     u->lpart = ualloc<double>(u, (size_t)((n0 + 8191) / 8192));
     u->loss = ualloc<double>(u, 1);
