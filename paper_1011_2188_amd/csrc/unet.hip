@@ -1084,13 +1084,17 @@ hipError_t wgrad(int am, const View &P, int p_ch, const View &Q, int q_ch, const
 {
     const long rows = (long)g.nx * g.ny * g.nz;
     const int pc = pad16(p_ch), qc = pad16(q_ch);
-    long slabs = std::min<long>(64, std::max<long>(1, rows / 2048));
-    long per = (rows + slabs - 1) / slabs;
-    per = (per + 31) & ~31L;
-    slabs = (rows + per - 1) / per;
-    const size_t need = (size_t)slabs * n_off * pc * qc;
-    if (need > u->wpart_n) return hipErrorInvalidValue;
-    if (am == A_CONV3) {
+    long slabs = 1, per = rows;
+    if (am != A_CONV3) {
+        // slabs of at least 256 rows (8 rounds of 32), at most 1024 of them and
+        // as many as the partials buffer holds: enough blocks to fill the chip
+        const long cap = (long)(u->wpart_n / ((size_t)n_off * pc * qc));
+        if (cap < 1) return hipErrorInvalidValue;
+        slabs = std::min<long>({1024L, cap, std::max<long>(1, rows / 256)});
+        per = (rows + slabs - 1) / slabs;
+        per = (per + 31) & ~31L;
+        slabs = (rows + per - 1) / per;
+    } else {
         // Tile shape (16 x 4 x 4, 16 x 4 x 2 or 16 x 2 x 2 voxels), taps per block G
         // and Q channel tiles per block qs: the feasible choice (accumulator
         // tiles G x pc/16 x qs within the kernel's 4 waves x 14 for 16 x 4 x 2
@@ -1122,7 +1126,8 @@ hipError_t wgrad(int am, const View &P, int p_ch, const View &Q, int q_ch, const
                                         Q.p, Q.pitch, q_ch, g, u->wpart, pc, qc, G, qs)
         if (ty == 4 && tz == 4) WT(4, 4); else if (ty == 4) WT(4, 2); else WT(2, 2);
 #undef WT
-    } else
+    }
+    if (am != A_CONV3)
         hipLaunchKernelGGL((wgrad_kernel<A_S2D>), dim3(n_off, (uint32_t)slabs), dim3(256), 0, s, P.p, P.pitch, p_ch,
                            Q.p, Q.pitch, q_ch, g, per, u->wpart, pc, qc);
     hipError_t e = hipGetLastError();

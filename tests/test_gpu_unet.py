@@ -131,10 +131,10 @@ def _wgrad3_fp64(gout, inp, shape):
 
 
 def test_unet_weight_gradients_multi_tile():
-    """Weight gradients of one layer per weight-gradient kernel shape (16, 16 x 32,
-    32 and 64 channels) on a 64 x 128 x 128 crop, where every workgroup walks
-    several tiles (the next tile is prefetched while the current one is
-    contracted), against an FP64 contraction of the same bf16 operands."""
+    """Weight gradients of one 3x3x3 layer per kernel shape (16, 16 x 32, 32 and
+    64 channels) and of both transposed convolutions on a 64 x 128 x 128 crop,
+    where every workgroup walks several tiles or row slabs, against an FP64
+    contraction of the same bf16 operands."""
     shape = (64, 128, 128)
     rng = np.random.default_rng(7)
     P = U.init_params(7)
@@ -153,6 +153,22 @@ def test_unet_weight_gradients_multi_tile():
     for layer, gname, iname, lvl, ci, co in [("enc1b", "ge1", "e1a", 0, 16, 16), ("dec1a", "gd1a", "c1", 0, 32, 16),
                                              ("enc2b", "ge2", "e2a", 1, 32, 32), ("midb", "gm", "ma", 2, 64, 64)]:
         want = _wgrad3_fp64(net.debug_buffer(gname)[:, :co], net.debug_buffer(iname)[:, :ci], levels[lvl])
+        got = gg[offs[layer]:offs[layer] + want.size].reshape(want.shape)
+        err = float(np.max(np.abs(got - want))) / _rms(want)
+        print(f"{layer}: max |GPU - FP64| = {err:.2e} of the RMS gradient")
+        assert err <= 1e-4, layer
+    # transposed convolutions (2x2x2, stride 2): dW[ci, co, a, b, c] = sum over coarse
+    # voxels v of input[v, ci] * output gradient[2 v + (a, b, c), co]; the gradient of
+    # up1 (up2) is the first 16 (32) channels of the level-0 (level-1) concatenation's
+    for layer, iname, gname, lvl, ci, co in [("up1", "d2", "gc1", 1, 32, 16), ("up2", "m", "gc2", 2, 64, 32)]:
+        cz, cy, cx = levels[lvl]
+        x_in = net.debug_buffer(iname)[:, :ci].astype(np.float64)
+        g_f = net.debug_buffer(gname)[:, :co].astype(np.float64).reshape(2 * cz, 2 * cy, 2 * cx, co)
+        want = np.zeros((ci, co, 2, 2, 2))
+        for a in range(2):
+            for b in range(2):
+                for c in range(2):
+                    want[:, :, a, b, c] = x_in.T @ g_f[a::2, b::2, c::2].reshape(-1, co)
         got = gg[offs[layer]:offs[layer] + want.size].reshape(want.shape)
         err = float(np.max(np.abs(got - want))) / _rms(want)
         print(f"{layer}: max |GPU - FP64| = {err:.2e} of the RMS gradient")
