@@ -1100,9 +1100,11 @@ hipError_t wgrad(int am, const View &P, int p_ch, const View &Q, int q_ch, const
         // tiles G x pc/16 x qs within the kernel's 4 waves x 14 for 16 x 4 x 2
         // tiles, 4 x 12 otherwise; P tile and Q halo slice within 64 KB of LDS)
         // that stages the fewest elements per voxel of the layer,
-        // (27 / G) (qc / 16 / qs) (TV pc + HV 16 qs) / TV; ties go to the larger tile.
+        // (27 / G) (qc / 16 / qs) (TV pc + HV 16 qs) / TV; within 15% the choice
+        // with fewer blocks per tile wins (more MFMA work per staged tile), and
+        // exact ties go to the larger tile.
         const int shapes[3][2] = {{4, 4}, {4, 2}, {2, 2}};
-        int ty = 0, tz = 0, G = 0, qs = 0;
+        int ty = 0, tz = 0, G = 0, qs = 0, best_ny = 0;
         double best = 0.0;
         for (const auto &sh : shapes) {
             const int tv = 16 * sh[0] * sh[1], hv = 18 * (sh[0] + 2) * (sh[1] + 2);
@@ -1111,8 +1113,11 @@ hipError_t wgrad(int am, const View &P, int p_ch, const View &Q, int q_ch, const
                 for (int q = qc / 16; q >= 1; q /= 2) {
                     if ((qc / 16) % q || gg * (pc / 16) * q > amax) continue;
                     if (((size_t)tv * (pc + 8) + (size_t)hv * (16 * q + 8)) * sizeof(u16) > 65536) continue;
-                    const double cost = (double)(27 / gg) * (qc / 16 / q) * ((double)tv * pc + (double)hv * 16 * q) / tv;
-                    if (!G || cost < best) { best = cost; ty = sh[0]; tz = sh[1]; G = gg; qs = q; }
+                    const int nyb = (27 / gg) * (qc / 16 / q);
+                    const double cost = (double)nyb * ((double)tv * pc + (double)hv * 16 * q) / tv;
+                    if (!G || cost < 0.85 * best || (cost < 1.15 * best && nyb < best_ny)) {
+                        best = cost; best_ny = nyb; ty = sh[0]; tz = sh[1]; G = gg; qs = q;
+                    }
                 }
         }
         if (!G) return hipErrorInvalidValue;
