@@ -763,20 +763,32 @@ __global__ void pool_kernel(const u16 *__restrict__ src, int s_pitch, int C, Gri
 
 // adjoint of the pool plus the skip-connection gradient, masked by ReLU:
 // ge[fine v][c] = bf16( (bf16(gp[coarse(v)][c] / 8) + skip[v][c]) * (e[v][c] > 0) )
+// 8 channels (16 bytes of every operand) per thread: C, the pitches and the
+// pointers are 8-element aligned (the host checks).
 __global__ void pool_back_kernel(const u16 *__restrict__ gp, int gp_pitch, const u16 *__restrict__ skip,
                                  int skip_pitch, const u16 *__restrict__ e, int e_pitch, int C, Grid fine,
                                  u16 *__restrict__ ge, int ge_pitch)
 {
     const long n = (long)fine.nx * fine.ny * fine.nz;
-    const int cx = fine.nx / 2, cy = fine.ny / 2;
-    for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < n * C; t += (long)gridDim.x * blockDim.x) {
-        const long v = t / C;
-        const int c = (int)(t - v * C);
+    const int cx = fine.nx / 2, cy = fine.ny / 2, cgs = C / 8;
+    for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < n * cgs; t += (long)gridDim.x * blockDim.x) {
+        const long v = t / cgs;
+        const int c = 8 * (int)(t - v * cgs);
         const int x = (int)(v % fine.nx), y = (int)((v / fine.nx) % fine.ny), z = (int)(v / ((long)fine.nx * fine.ny));
         const long cv = ((long)(z / 2) * cy + y / 2) * cx + x / 2;
-        const float up = bf2f(f2bf(bf2f(gp[cv * gp_pitch + c]) * 0.125f));
-        const float s = bf2f(skip[v * skip_pitch + c]) + up;
-        ge[v * ge_pitch + c] = f2bf(bf2f(e[v * e_pitch + c]) > 0.f ? s : 0.f);
+        const uint4 g4 = *(const uint4 *)(gp + cv * gp_pitch + c);
+        const uint4 s4 = *(const uint4 *)(skip + v * skip_pitch + c);
+        const uint4 e4 = *(const uint4 *)(e + v * e_pitch + c);
+        const u16 *gh = (const u16 *)&g4, *sh = (const u16 *)&s4, *eh = (const u16 *)&e4;
+        uint4 o4;
+        u16 *oh = (u16 *)&o4;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const float up = bf2f(f2bf(bf2f(gh[k]) * 0.125f));
+            const float sum = bf2f(sh[k]) + up;
+            oh[k] = f2bf(bf2f(eh[k]) > 0.f ? sum : 0.f);
+        }
+        *(uint4 *)(ge + v * ge_pitch + c) = o4;
     }
 }
 
@@ -1268,6 +1280,18 @@ hipError_t forward_pass(fdc_unet *u, const float *in, hipStream_t s)
     return e;
 }
 
+// pool adjoint + skip gradient + ReLU mask on the fine grid g (16-byte accesses)
+hipError_t pool_back(const View &gp, const View &skip, const View &e, int C, const Grid &g, const View &ge,
+                     hipStream_t s)
+{
+    const auto al = [](const View &v) { return v.pitch % 8 == 0 && ((uintptr_t)v.p & 15) == 0; };
+    if (C % 8 || !al(gp) || !al(skip) || !al(e) || !al(ge)) return hipErrorInvalidValue;
+    const long n = (long)g.nx * g.ny * g.nz;
+    hipLaunchKernelGGL(pool_back_kernel, dim3(blocks_for(n * (C / 8))), dim3(256), 0, s, gp.p, gp.pitch, skip.p,
+                       skip.pitch, e.p, e.pitch, C, g, ge.p, ge.pitch);
+    return hipGetLastError();
+}
+
 hipError_t backward_pass(fdc_unet *u, const float *in, hipStream_t s)
 {
     const Views v = views(u);
@@ -1315,9 +1339,7 @@ hipError_t backward_pass(fdc_unet *u, const float *in, hipStream_t s)
     if (!e) e = wg3(L_MA, v.gma, v.p2, g[2]);
     // pool 2 adjoint + skip, enc2
     if (!e) {
-        hipLaunchKernelGGL(pool_back_kernel, dim3(blocks_for(u->nv[1] * 32)), dim3(256), 0, s, v.gp2.p, v.gp2.pitch,
-                           v.ge2s.p, v.ge2s.pitch, v.e2.p, v.e2.pitch, 32, g[1], v.ge2.p, v.ge2.pitch);
-        e = hipGetLastError();
+        e = pool_back(v.gp2, v.ge2s, v.e2, 32, g[1], v.ge2, s);
     }
     if (!e) e = bwd(L_E2B, v.ge2, g[1], &v.e2a, v.ge2a);
     if (!e) e = wg3(L_E2B, v.ge2, v.e2a, g[1]);
@@ -1325,9 +1347,7 @@ hipError_t backward_pass(fdc_unet *u, const float *in, hipStream_t s)
     if (!e) e = wg3(L_E2A, v.ge2a, v.p1, g[1]);
     // pool 1 adjoint + skip, enc1
     if (!e) {
-        hipLaunchKernelGGL(pool_back_kernel, dim3(blocks_for(u->nv[0] * 16)), dim3(256), 0, s, v.gp1.p, v.gp1.pitch,
-                           v.ge1s.p, v.ge1s.pitch, v.e1.p, v.e1.pitch, 16, g[0], v.ge1.p, v.ge1.pitch);
-        e = hipGetLastError();
+        e = pool_back(v.gp1, v.ge1s, v.e1, 16, g[0], v.ge1, s);
     }
     if (!e) e = bwd(L_E1B, v.ge1, g[0], &v.e1a, v.ge1a);
     if (!e) e = wg3(L_E1B, v.ge1, v.e1a, g[0]);
