@@ -881,27 +881,43 @@ __global__ void adam_kernel(float *__restrict__ p, const float *__restrict__ g, 
 //   mode 1: conv3 backward  n = ci,            k = o * cpad_out + co,  w[co][ci][26 - o]
 //   mode 2: tconv forward   n = a * cout + co, k = ci,                 w[ci][co][a]
 //   mode 3: tconv backward  n = ci,            k = a * cpad_out + co,  w[ci][co][a]
-__global__ void pack_kernel(const float *__restrict__ w, int mode, int cin, int cout, int cpad, int n_cols, int kpad,
-                            u16 *__restrict__ wpk)
+// One packing job per (layer, direction); all of them run in one launch, each
+// job on its own contiguous range of blocks starting at b0.
+struct PackJob {
+    const float *w;
+    u16 *wpk;
+    int mode, cin, cout, cpad, n_cols, kpad, b0;
+};
+constexpr int kMaxPackJobs = 32;
+struct PackJobs {
+    PackJob j[kMaxPackJobs];
+    int n;
+};
+
+__global__ void pack_kernel(PackJobs jobs)
 {
-    const long total = (long)n_cols * kpad;
-    for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < total; t += (long)gridDim.x * blockDim.x) {
-        const int n = (int)(t / kpad), k = (int)(t - (long)n * kpad);
+    int jb = 0;
+    while (jb + 1 < jobs.n && (int)blockIdx.x >= jobs.j[jb + 1].b0) ++jb;
+    const PackJob J = jobs.j[jb];
+    const int nb = (jb + 1 < jobs.n ? jobs.j[jb + 1].b0 : (int)gridDim.x) - J.b0;
+    const long total = (long)J.n_cols * J.kpad;
+    for (long t = (blockIdx.x - J.b0) * (long)blockDim.x + threadIdx.x; t < total; t += (long)nb * blockDim.x) {
+        const int n = (int)(t / J.kpad), k = (int)(t - (long)n * J.kpad);
         float v = 0.f;
-        if (mode == 0) {
-            const int o = k / cpad, ci = k % cpad;
-            if (o < 27 && ci < cin) v = w[((long)n * cin + ci) * 27 + o];
-        } else if (mode == 1) {
-            const int o = k / cpad, co = k % cpad;
-            if (o < 27 && co < cout) v = w[((long)co * cin + n) * 27 + (26 - o)];
-        } else if (mode == 2) {
-            const int a = n / cout, co = n % cout;
-            if (k < cin) v = w[((long)k * cout + co) * 8 + a];
+        if (J.mode == 0) {
+            const int o = k / J.cpad, ci = k % J.cpad;
+            if (o < 27 && ci < J.cin) v = J.w[((long)n * J.cin + ci) * 27 + o];
+        } else if (J.mode == 1) {
+            const int o = k / J.cpad, co = k % J.cpad;
+            if (o < 27 && co < J.cout) v = J.w[((long)co * J.cin + n) * 27 + (26 - o)];
+        } else if (J.mode == 2) {
+            const int a = n / J.cout, co = n % J.cout;
+            if (k < J.cin) v = J.w[((long)k * J.cout + co) * 8 + a];
         } else {
-            const int a = k / cpad, co = k % cpad;
-            if (a < 8 && co < cout) v = w[((long)n * cout + co) * 8 + a];
+            const int a = k / J.cpad, co = k % J.cpad;
+            if (a < 8 && co < J.cout) v = J.w[((long)n * J.cout + co) * 8 + a];
         }
-        wpk[t] = f2bf(v);
+        J.wpk[t] = f2bf(v);
     }
 }
 
@@ -964,6 +980,7 @@ const LayerDesc kLayers[] = {
     {"dec2b", K_CONV3, 32, 32}, {"up1", K_TCONV, 32, 16},  {"dec1a", K_CONV3, 32, 16}, {"dec1b", K_CONV3, 16, 16},
     {"head", K_CONV1, 16, 1}};
 constexpr int kNumLayers = 13;
+static_assert(2 * kNumLayers <= kMaxPackJobs, "one forward and one backward packing job per layer");
 enum { L_E1A, L_E1B, L_E2A, L_E2B, L_MA, L_MB, L_UP2, L_D2A, L_D2B, L_UP1, L_D1A, L_D1B, L_HEAD };
 
 inline int pad8(int c) { return (c + 7) & ~7; }
@@ -1174,22 +1191,25 @@ hipError_t bias_grad(const View &G, int C, long n, fdc_unet *u, float *gb, hipSt
 
 hipError_t pack_all(fdc_unet *u, hipStream_t s)
 {
+    PackJobs jobs{};
+    int blocks = 0;
+    auto add = [&](const float *w, u16 *wpk, int mode, int cin, int cout, int cpad, int n_cols, int kpad) {
+        PackJob &J = jobs.j[jobs.n++];
+        J = PackJob{w, wpk, mode, cin, cout, cpad, n_cols, kpad, blocks};
+        blocks += (int)blocks_for((long)n_cols * kpad, 256, 1024);
+    };
     for (int l = 0; l < kNumLayers; ++l) {
         const LayerDesc &L = kLayers[l];
         const float *w = u->params + u->w_off[l];
         if (L.kind == K_CONV3) {
-            hipLaunchKernelGGL(pack_kernel, dim3(blocks_for((long)u->ncol_f[l] * u->kpad_f[l])), dim3(256), 0, s, w, 0,
-                               L.cin, L.cout, pad8(L.cin), u->ncol_f[l], u->kpad_f[l], u->wpk_f[l]);
-            if (u->wpk_b[l])
-                hipLaunchKernelGGL(pack_kernel, dim3(blocks_for((long)u->ncol_b[l] * u->kpad_b[l])), dim3(256), 0, s, w,
-                                   1, L.cin, L.cout, pad8(L.cout), u->ncol_b[l], u->kpad_b[l], u->wpk_b[l]);
+            add(w, u->wpk_f[l], 0, L.cin, L.cout, pad8(L.cin), u->ncol_f[l], u->kpad_f[l]);
+            if (u->wpk_b[l]) add(w, u->wpk_b[l], 1, L.cin, L.cout, pad8(L.cout), u->ncol_b[l], u->kpad_b[l]);
         } else if (L.kind == K_TCONV) {
-            hipLaunchKernelGGL(pack_kernel, dim3(blocks_for((long)u->ncol_f[l] * u->kpad_f[l])), dim3(256), 0, s, w, 2,
-                               L.cin, L.cout, pad8(L.cin), u->ncol_f[l], u->kpad_f[l], u->wpk_f[l]);
-            hipLaunchKernelGGL(pack_kernel, dim3(blocks_for((long)u->ncol_b[l] * u->kpad_b[l])), dim3(256), 0, s, w, 3,
-                               L.cin, L.cout, pad8(L.cout), u->ncol_b[l], u->kpad_b[l], u->wpk_b[l]);
+            add(w, u->wpk_f[l], 2, L.cin, L.cout, pad8(L.cin), u->ncol_f[l], u->kpad_f[l]);
+            add(w, u->wpk_b[l], 3, L.cin, L.cout, pad8(L.cout), u->ncol_b[l], u->kpad_b[l]);
         }
     }
+    hipLaunchKernelGGL(pack_kernel, dim3((uint32_t)blocks), dim3(256), 0, s, jobs);
     return hipGetLastError();
 }
 
