@@ -675,11 +675,13 @@ __global__ void __launch_bounds__(256) wgrad3t_kernel(const u16 *__restrict__ P,
     }
 }
 
-// sum the slabs in a fixed order: out[(o, i, j)] = sum_s part[s][o][i][j].
+// sum the slabs in a fixed order, sum_s part[s][o][i][j] for element x = (o pc + i) qc + j,
+// and store it as the canonical weight gradient (i < ni, j < nj; padding dropped):
+//   conv3: i = co, j = ci  -> gw[co][ci][o];   tconv: i = ci, j = co -> gw[ci][co][o]
 // Block = 64 elements x 8 waves: wave w adds slabs w, w + 8, ... (coalesced rows),
 // then the 8 partial sums are added in wave order (reproducible).
 __global__ void __launch_bounds__(512) slab_sum_kernel(const float *__restrict__ part, int slabs, long per_slab,
-                                                       float *__restrict__ out)
+                                                       int pc, int qc, int ni, int nj, float *__restrict__ gw)
 {
     __shared__ float red[8][64];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -695,7 +697,9 @@ __global__ void __launch_bounds__(512) slab_sum_kernel(const float *__restrict__
         float t = 0.f;
 #pragma unroll
         for (int k = 0; k < 8; ++k) t += red[k][lane];
-        out[x] = t;
+        const int j = (int)(x % qc), i = (int)((x / qc) % pc), o = (int)(x / ((long)pc * qc));
+        const int n_off = (int)(per_slab / ((long)pc * qc));
+        if (i < ni && j < nj) gw[((long)i * nj + j) * n_off + o] = t;
     }
 }
 
@@ -921,20 +925,6 @@ __global__ void pack_kernel(PackJobs jobs)
     }
 }
 
-// canonical weight gradient from the summed wgrad output s[o][i][j]
-//   conv3: i = co, j = ci  -> g[co][ci][o];   tconv: i = ci, j = co -> g[ci][co][o]
-__global__ void scatter_wgrad_kernel(const float *__restrict__ s, int n_off, int pc, int qc, int ni, int nj,
-                                     float *__restrict__ gw)
-{
-    const long total = (long)n_off * ni * nj;
-    for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < total; t += (long)gridDim.x * blockDim.x) {
-        const int o = (int)(t % n_off);
-        const long ij = t / n_off;
-        const int j = (int)(ij % nj), i = (int)(ij / nj);
-        gw[((long)i * nj + j) * n_off + o] = s[((long)o * pc + i) * qc + j];
-    }
-}
-
 // head parameters as the head kernel reads them: bf16-rounded weights, FP32 bias
 __global__ void head_weights_kernel(const float *__restrict__ p, float *__restrict__ out)
 {
@@ -1027,7 +1017,7 @@ struct fdc_unet {
     u16 *x, *e1a, *c1, *p1, *e2a, *c2, *p2, *ma, *m, *d2a, *d2, *d1a, *d1;
     // activation gradients
     u16 *gd1, *gd1a, *gc1, *gd2, *gd2a, *gc2, *gm, *gma, *gp2, *ge2, *ge2a, *gp1, *ge1, *ge1a;
-    float *wpart = nullptr, *wsum = nullptr, *bpart = nullptr, *hpart = nullptr, *hw = nullptr;
+    float *wpart = nullptr, *bpart = nullptr, *hpart = nullptr, *hw = nullptr;
     double *lpart = nullptr, *loss = nullptr;
     size_t wpart_n = 0;
 };
@@ -1168,9 +1158,7 @@ hipError_t wgrad(int am, const View &P, int p_ch, const View &Q, int q_ch, const
     if (e != hipSuccess) return e;
     const long per_slab = (long)n_off * pc * qc;
     hipLaunchKernelGGL(slab_sum_kernel, dim3((uint32_t)((per_slab + 63) / 64)), dim3(512), 0, s, u->wpart, (int)slabs,
-                       per_slab, u->wsum);
-    hipLaunchKernelGGL(scatter_wgrad_kernel, dim3(blocks_for((long)n_off * ni * nj)), dim3(256), 0, s, u->wsum, n_off,
-                       pc, qc, ni, nj, gw_out);
+                       per_slab, pc, qc, ni, nj, gw_out);
     (void)transposed_layer;
     return hipGetLastError();
 }
@@ -1468,13 +1456,12 @@ int fdc_unet_create(fdc_unet **out, int hip_device, int nx, int ny, int nz)
     u->ge1 = A16(n0 * 16); u->ge1a = A16(n0 * 16);
     u->wpart_n = (size_t)64 * 27 * 64 * 64;
     u->wpart = ualloc<float>(u, u->wpart_n);
-    u->wsum = ualloc<float>(u, 27 * 64 * 64 + 256);
     u->bpart = ualloc<float>(u, (size_t)512 * 64);
     u->hpart = ualloc<float>(u, (size_t)((n0 + 8191) / 8192) * 17);
     u->lpart = ualloc<double>(u, (size_t)((n0 + 8191) / 8192));
     u->loss = ualloc<double>(u, 1);
     u->hw = ualloc<float>(u, 32);
-    ok = ok && u->hw && u->wpart && u->wsum && u->bpart && u->hpart && u->lpart && u->loss;
+    ok = ok && u->hw && u->wpart && u->bpart && u->hpart && u->lpart && u->loss;
     if (!ok) { fdc_unet_destroy(u); return FDC_E_NOMEM; }
     if (hipMemset(u->params, 0, o * 4) != hipSuccess || hipMemset(u->grads, 0, o * 4) != hipSuccess ||
         hipMemset(u->adam_m, 0, o * 4) != hipSuccess || hipMemset(u->adam_s, 0, o * 4) != hipSuccess) {
