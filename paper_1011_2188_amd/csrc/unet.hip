@@ -703,22 +703,41 @@ __global__ void __launch_bounds__(512) slab_sum_kernel(const float *__restrict__
     }
 }
 
-// bias gradient partials: part[block][c] = sum over the block's voxels of G[v][c].
+// Bias gradients of all layers, two launches for the whole backward pass.
+// Job = one layer's output gradient G (n voxels x C channels, C a multiple of
+// 8 up to 64, 16-byte aligned rows) and its bias gradient gb; its blocks are
+// b0 .. b0 + nb - 1, per voxels each.
+struct BiasJob {
+    const u16 *G;
+    float *gb;
+    long n, per;
+    int pitch, C, b0, nb;
+};
+constexpr int kMaxBiasJobs = 16;
+constexpr int kMaxBiasBlocks = 512;                    // per job
+struct BiasJobs {
+    BiasJob j[kMaxBiasJobs];
+    int n;
+};
+
+// partials: part[block][c] (stride 64) = sum over the block's voxels of G[v][c].
 // Thread t reads 8 channels (16 bytes) of voxel v0 + t / (C/8) + k * (256 / (C/8)),
 // so consecutive threads read consecutive bytes; the per-thread sums are then
-// added per channel in a fixed order (reproducible).  C: multiple of 8, <= 64.
-__global__ void __launch_bounds__(256) bias_part_kernel(const u16 *__restrict__ G, int pitch, int C, long n,
-                                                        long per_block, float *__restrict__ part)
+// added per channel in a fixed order (reproducible).
+__global__ void __launch_bounds__(256) bias_part_kernel(BiasJobs jobs, float *__restrict__ part)
 {
     __shared__ float red[256][8];
-    const int cgs = C / 8, per_step = 256 / cgs;
+    int jb = 0;
+    while (jb + 1 < jobs.n && (int)blockIdx.x >= jobs.j[jb + 1].b0) ++jb;
+    const BiasJob J = jobs.j[jb];
+    const int C = J.C, cgs = C / 8, per_step = 256 / cgs;
     const int cg = threadIdx.x % cgs, vo = threadIdx.x / cgs;
-    const long v0 = blockIdx.x * per_block, v1 = std::min<long>(n, v0 + per_block);
+    const long v0 = (long)((int)blockIdx.x - J.b0) * J.per, v1 = std::min<long>(J.n, v0 + J.per);
     float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     if (vo < per_step) {
 #pragma unroll 4
         for (long v = v0 + vo; v < v1; v += per_step) {
-            const uint4 q = *(const uint4 *)(G + v * pitch + 8 * cg);
+            const uint4 q = *(const uint4 *)(J.G + v * J.pitch + 8 * cg);
             const u16 *h = (const u16 *)&q;
 #pragma unroll
             for (int e = 0; e < 8; ++e) acc[e] += bf2f(h[e]);
@@ -731,7 +750,7 @@ __global__ void __launch_bounds__(256) bias_part_kernel(const u16 *__restrict__ 
         const int c = threadIdx.x, g8 = c / 8, e = c % 8;
         float sum = 0.f;
         for (int k = 0; k < per_step; ++k) sum += red[k * cgs + g8][e];
-        part[(long)blockIdx.x * C + c] = sum;
+        part[(long)blockIdx.x * 64 + c] = sum;
     }
 }
 
@@ -933,25 +952,25 @@ __global__ void head_weights_kernel(const float *__restrict__ p, float *__restri
     if (c == 16) out[16] = p[16];
 }
 
-// gb[c] = sum over the nb partials; 256 threads: thread t sums channel t % C over
-// partials b = t / C, t / C + 256 / C, ... and the groups are added in a fixed
-// order (reproducible)
-__global__ void __launch_bounds__(256) bias_finish_kernel(const float *__restrict__ part, int nb, int C,
-                                                          float *__restrict__ gb)
+// gb[c] = sum over the job's nb partials, one block per job; 256 threads: thread t
+// sums channel t % C over partials b = t / C, t / C + 256 / C, ... and the groups
+// are added in a fixed order (reproducible)
+__global__ void __launch_bounds__(256) bias_finish_kernel(BiasJobs jobs, const float *__restrict__ part)
 {
     __shared__ float red[256];
-    const int groups = 256 / C, c = threadIdx.x % C, j = threadIdx.x / C;
+    const BiasJob J = jobs.j[blockIdx.x];
+    const int C = J.C, groups = 256 / C, c = threadIdx.x % C, j = threadIdx.x / C;
     float s = 0.f;
     if (j < groups) {
 #pragma unroll 8
-        for (int b = j; b < nb; b += groups) s += part[(long)b * C + c];
+        for (int b = j; b < J.nb; b += groups) s += part[(long)(J.b0 + b) * 64 + c];
     }
     red[threadIdx.x] = s;
     __syncthreads();
     if ((int)threadIdx.x < C) {
         float t = 0.f;
         for (int k = 0; k < groups; ++k) t += red[k * C + threadIdx.x];
-        gb[threadIdx.x] = t;
+        J.gb[threadIdx.x] = t;
     }
 }
 
@@ -1163,17 +1182,26 @@ hipError_t wgrad(int am, const View &P, int p_ch, const View &Q, int q_ch, const
     return hipGetLastError();
 }
 
-hipError_t bias_grad(const View &G, int C, long n, fdc_unet *u, float *gb, hipStream_t s)
+// queue the bias gradient of one layer (computed by bias_grad_all)
+hipError_t add_bias_job(BiasJobs &bj, int &blocks, const View &G, int C, long n, float *gb)
 {
-    if (C % 8 || C > 64) return hipErrorInvalidValue;
-    // at most 512 blocks (the partials buffer), each a whole number of rounds
-    // of its 256 threads over C/8 channel groups, at least one round
+    if (C % 8 || C > 64 || G.pitch % 8 || ((uintptr_t)G.p & 15) || bj.n >= kMaxBiasJobs) return hipErrorInvalidValue;
+    // at most kMaxBiasBlocks blocks, each a whole number of rounds of its 256
+    // threads over C/8 channel groups, at least one round
     const long per_step = 256 / (C / 8);
-    long per = (n + 511) / 512;
+    long per = (n + kMaxBiasBlocks - 1) / kMaxBiasBlocks;
     per = std::max(per_step, (per + per_step - 1) / per_step * per_step);
     const int nb = (int)((n + per - 1) / per);
-    hipLaunchKernelGGL(bias_part_kernel, dim3(nb), dim3(256), 0, s, G.p, G.pitch, C, n, per, u->bpart);
-    hipLaunchKernelGGL(bias_finish_kernel, dim3(1), dim3(256), 0, s, u->bpart, nb, C, gb);
+    bj.j[bj.n++] = BiasJob{G.p, gb, n, per, G.pitch, C, blocks, nb};
+    blocks += nb;
+    return hipSuccess;
+}
+
+hipError_t bias_grad_all(const BiasJobs &bj, int blocks, fdc_unet *u, hipStream_t s)
+{
+    if (!bj.n) return hipSuccess;
+    hipLaunchKernelGGL(bias_part_kernel, dim3((uint32_t)blocks), dim3(256), 0, s, bj, u->bpart);
+    hipLaunchKernelGGL(bias_finish_kernel, dim3((uint32_t)bj.n), dim3(256), 0, s, bj, u->bpart);
     return hipGetLastError();
 }
 
@@ -1312,10 +1340,14 @@ hipError_t backward_pass(fdc_unet *u, const float *in, hipStream_t s)
         return igemm(A_CONV3, E_STORE, gout, pad8(L.cout), gr, u->wpk_b[l], u->kpad_b[l], L.cin, nullptr, false, mask,
                      gin, 0, s);
     };
+    // bias gradients are queued and computed together at the end (every output
+    // gradient buffer is written once per backward pass)
+    BiasJobs bj{};
+    int bias_blocks = 0;
     auto wg3 = [&](int l, const View &gout, const View &in_v, const Grid &gr) {
         const LayerDesc &L = kLayers[l];
         hipError_t e = wgrad(A_CONV3, gout, L.cout, in_v, L.cin, gr, 27, u, false, L.cout, L.cin, gw(l), s);
-        if (!e) e = bias_grad(gout, L.cout, (long)gr.nx * gr.ny * gr.nz, u, gb(l), s);
+        if (!e) e = add_bias_job(bj, bias_blocks, gout, L.cout, (long)gr.nx * gr.ny * gr.nz, gb(l));
         return e;
     };
     (void)in;
@@ -1329,7 +1361,7 @@ hipError_t backward_pass(fdc_unet *u, const float *in, hipStream_t s)
     if (!e) e = igemm(A_S2D, E_STORE, v.gu1, 16, g[1], u->wpk_b[L_UP1], u->kpad_b[L_UP1], 32, nullptr, false, &v.d2,
                       v.gd2, 0, s);
     if (!e) e = wgrad(A_S2D, v.d2, 32, v.gu1, 16, g[1], 8, u, true, 32, 16, gw(L_UP1), s);
-    if (!e) e = bias_grad(v.gu1, 16, u->nv[0], u, gb(L_UP1), s);
+    if (!e) e = add_bias_job(bj, bias_blocks, v.gu1, 16, u->nv[0], gb(L_UP1));
     // dec2b, dec2a
     if (!e) e = bwd(L_D2B, v.gd2, g[1], &v.d2a, v.gd2a);
     if (!e) e = wg3(L_D2B, v.gd2, v.d2a, g[1]);
@@ -1339,7 +1371,7 @@ hipError_t backward_pass(fdc_unet *u, const float *in, hipStream_t s)
     if (!e) e = igemm(A_S2D, E_STORE, v.gu2, 32, g[2], u->wpk_b[L_UP2], u->kpad_b[L_UP2], 64, nullptr, false, &v.m,
                       v.gm, 0, s);
     if (!e) e = wgrad(A_S2D, v.m, 64, v.gu2, 32, g[2], 8, u, true, 64, 32, gw(L_UP2), s);
-    if (!e) e = bias_grad(v.gu2, 32, u->nv[1], u, gb(L_UP2), s);
+    if (!e) e = add_bias_job(bj, bias_blocks, v.gu2, 32, u->nv[1], gb(L_UP2));
     // mid
     if (!e) e = bwd(L_MB, v.gm, g[2], &v.ma, v.gma);
     if (!e) e = wg3(L_MB, v.gm, v.ma, g[2]);
@@ -1360,6 +1392,7 @@ hipError_t backward_pass(fdc_unet *u, const float *in, hipStream_t s)
     if (!e) e = bwd(L_E1B, v.ge1, g[0], &v.e1a, v.ge1a);
     if (!e) e = wg3(L_E1B, v.ge1, v.e1a, g[0]);
     if (!e) e = wg3(L_E1A, v.ge1a, v.x, g[0]);
+    if (!e) e = bias_grad_all(bj, bias_blocks, u, s);
     return e;
 }
 
@@ -1456,7 +1489,7 @@ int fdc_unet_create(fdc_unet **out, int hip_device, int nx, int ny, int nz)
     u->ge1 = A16(n0 * 16); u->ge1a = A16(n0 * 16);
     u->wpart_n = (size_t)64 * 27 * 64 * 64;
     u->wpart = ualloc<float>(u, u->wpart_n);
-    u->bpart = ualloc<float>(u, (size_t)512 * 64);
+    u->bpart = ualloc<float>(u, (size_t)kMaxBiasJobs * kMaxBiasBlocks * 64);
     u->hpart = ualloc<float>(u, (size_t)((n0 + 8191) / 8192) * 17);
     u->lpart = ualloc<double>(u, (size_t)((n0 + 8191) / 8192));
     u->loss = ualloc<double>(u, 1);
