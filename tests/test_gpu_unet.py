@@ -174,3 +174,50 @@ def test_unet_weight_gradients_multi_tile():
         print(f"{layer}: max |GPU - FP64| = {err:.2e} of the RMS gradient")
         assert err <= 1e-4, layer
     net.close()
+
+
+def test_unet_forward_full_volume_sampled():
+    """The full 128 x 256 x 256 (z, y, x) volume the denoiser is timed on: three
+    3x3x3 layers (2 -> 16, 16 -> 16, and 64 -> 32 at half resolution, whose 64
+    input channels are staged 32 at a time) recomputed in FP64 at sampled voxels
+    (random, corners and tile edges) from the kernels' own bf16 inputs and the
+    bf16-rounded weights; the GPU output is bf16, so each value must agree within
+    2^-7 of itself plus 1e-3 of the layer's RMS."""
+    shape = (128, 256, 256)
+    rng = np.random.default_rng(11)
+    flat = U.flatten(U.init_params(11)).astype(np.float32)
+    W = U.unflatten(flat.astype(np.float64))
+    net = F.UNet(shape)
+    net.set_params(flat)
+    g = torch.Generator(device="cuda").manual_seed(11)
+    x = torch.rand((2,) + shape, device="cuda", generator=g)
+    y = torch.empty(shape, device="cuda")
+    net.forward(x, y)
+    torch.cuda.synchronize()
+    for layer, src, s_ch, dst, d_off, d_ch, div in [("enc1a", "x", 2, "e1a", 0, 16, 1),
+                                                    ("enc1b", "e1a", 16, "c1", 16, 16, 1),
+                                                    ("dec2a", "c2", 64, "d2a", 0, 32, 2)]:
+        nz, ny, nx = (s // div for s in shape)
+        xin = net.debug_buffer(src)[:, :s_ch].reshape(nz, ny, nx, s_ch).astype(np.float64)
+        out = net.debug_buffer(dst)[:, d_off:d_off + d_ch].reshape(nz, ny, nx, d_ch).astype(np.float64)
+        w = U.bf16_round(W[layer][0])                      # [co, ci, dz, dy, dx]
+        b = W[layer][1]
+        pts = [tuple(int(rng.integers(0, n)) for n in (nz, ny, nx)) for _ in range(240)]
+        pts += [(0, 0, 0), (nz - 1, ny - 1, nx - 1), (3, 3, 15), (4, 4, 16), (nz - 1, 0, nx - 1), (7, ny - 1, 31)]
+        ref, got = [], []
+        for z, yy, xx in pts:
+            acc = b.copy()
+            for dz in range(3):
+                for dy in range(3):
+                    for dx in range(3):
+                        zz, y2, x2 = z + dz - 1, yy + dy - 1, xx + dx - 1
+                        if 0 <= zz < nz and 0 <= y2 < ny and 0 <= x2 < nx:
+                            acc += w[:, :, dz, dy, dx] @ xin[zz, y2, x2]
+            ref.append(np.maximum(acc, 0.0))
+            got.append(out[z, yy, xx])
+        ref, got = np.array(ref), np.array(got)
+        bound = 2.0 ** -7 * np.abs(ref) + 1e-3 * _rms(ref)
+        worst = float(np.max(np.abs(got - ref) / bound))
+        print(f"{layer}: {len(pts)} voxels x {d_ch} channels, worst |GPU - FP64| at {worst:.2f} of the bound")
+        assert worst <= 1.0, layer
+    net.close()
