@@ -592,7 +592,7 @@ __device__ inline bf16x8 tr_frag(const u16 *tile, int pitch, int row, int col)
 // straight from ds_read_b64_tr_b16 with no boundary masks (the halo holds the
 // zeros).  Accumulators stay in registers across the block's tiles;
 // part[blockIdx.x][o][i][j] receives the block's sums.
-template <int TY, int TZ>
+template <int TY, int TZ, bool P16>
 __global__ void __launch_bounds__(256) wgrad3t_kernel(const u16 *__restrict__ P, int p_pitch, int p_ch,
                                                       const u16 *__restrict__ Q, int q_pitch, int q_ch, Grid g,
                                                       float *__restrict__ part, int pc, int qc, int G, int qs)
@@ -644,6 +644,9 @@ __global__ void __launch_bounds__(256) wgrad3t_kernel(const u16 *__restrict__ P,
             // the lane group's 8 contraction voxels: x = 8 (lg % 2) .. +7 of tile row (y, z)
             const int k0 = 32 * kb + 8 * lg;
             const int xr = k0 % TX, yr = (k0 / TX) % TY, zr = k0 / (TX * TY);
+            // P16 (one P channel tile, pc = 16): the P fragment is the same for
+            // every tap of the step and is read once (LDS reads per MFMA 4 -> 2 + 2 / taps)
+            const bf16x8 a16 = P16 ? tr_frag(sP, sp_pitch, k0, 0) : zero8();
 #pragma unroll
             for (int q = 0; q < kMaxAcc; ++q) {
                 const int T = wave + 4 * q;
@@ -651,7 +654,7 @@ __global__ void __launch_bounds__(256) wgrad3t_kernel(const u16 *__restrict__ P,
                     const int o = o0 + T / n_ct, ct = T % n_ct;
                     const int ti = ct / tiles_j, tj = ct % tiles_j;
                     const int dz = o / 9, dy = (o / 3) % 3, dx = o % 3;     // halo shift = tap
-                    const bf16x8 a = tr_frag(sP, sp_pitch, k0, 16 * ti);
+                    const bf16x8 a = P16 ? a16 : tr_frag(sP, sp_pitch, k0, 16 * ti);
                     const int hrow = ((zr + dz) * HY + (yr + dy)) * HX + (xr + dx);
                     const bf16x8 b = tr_frag(sQ, sq_pitch, hrow, 16 * tj);
                     acc[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[q], 0, 0, 0);
@@ -1165,8 +1168,12 @@ hipError_t wgrad(int am, const View &P, int p_ch, const View &Q, int q_ch, const
         slabs = std::max<long>(1, std::min<long>({tiles, cap, std::max(1L, 2048L / ny_blocks)}));
         const size_t lds = ((size_t)16 * ty * tz * (pc + 8) + (size_t)18 * (ty + 2) * (tz + 2) * (16 * qs + 8)) * sizeof(u16);
         const dim3 grid((uint32_t)slabs, (uint32_t)ny_blocks);
-#define WT(TY_, TZ_) hipLaunchKernelGGL((wgrad3t_kernel<TY_, TZ_>), grid, dim3(256), lds, s, P.p, P.pitch, p_ch, \
-                                        Q.p, Q.pitch, q_ch, g, u->wpart, pc, qc, G, qs)
+#define WT(TY_, TZ_) do { if (pc == 16) hipLaunchKernelGGL((wgrad3t_kernel<TY_, TZ_, true>), grid, dim3(256), lds, s, \
+                                                             P.p, P.pitch, p_ch, Q.p, Q.pitch, q_ch, g, u->wpart, pc, qc, \
+                                                             G, qs); \
+                             else hipLaunchKernelGGL((wgrad3t_kernel<TY_, TZ_, false>), grid, dim3(256), lds, s, P.p, \
+                                                     P.pitch, p_ch, Q.p, Q.pitch, q_ch, g, u->wpart, pc, qc, G, qs); \
+                        } while (0)
         if (ty == 4 && tz == 4) WT(4, 4); else if (ty == 4) WT(4, 2); else WT(2, 2);
 #undef WT
     }
