@@ -592,7 +592,7 @@ __device__ inline bf16x8 tr_frag(const u16 *tile, int pitch, int row, int col)
 // straight from ds_read_b64_tr_b16 with no boundary masks (the halo holds the
 // zeros).  Accumulators stay in registers across the block's tiles;
 // part[blockIdx.x][o][i][j] receives the block's sums.
-template <int TY, int TZ, bool P16>
+template <int TY, int TZ, int PT>
 __global__ void __launch_bounds__(256) wgrad3t_kernel(const u16 *__restrict__ P, int p_pitch, int p_ch,
                                                       const u16 *__restrict__ Q, int q_pitch, int q_ch, Grid g,
                                                       float *__restrict__ part, int pc, int qc, int G, int qs)
@@ -608,15 +608,19 @@ __global__ void __launch_bounds__(256) wgrad3t_kernel(const u16 *__restrict__ P,
     const int n_tiles_grid = tiles_x * tiles_y * tiles_z;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int lg = lane >> 4;
-    const int tiles_j = qs, n_ct = (pc / 16) * tiles_j;        // the block's channel tiles
-    const int n_acc = G * n_ct;                                // <= 4 kMaxAcc (the host picks G, qs)
+    // Accumulators: PT = pc / 16 P channel tiles.  The block's work is G qs
+    // groups (tap, Q channel tile); wave w owns groups w, w + 4, ... and, for
+    // each, the PT tiles (ti, tj): one Q fragment read serves PT MFMAs, and the
+    // PT P fragments of a K step are read once for all groups.
+    const int n_grp = G * qs;                                  // <= 4 kMaxAcc / PT (the host picks G, qs)
     const int pcg = pc / 8, qcg = 2 * qs;
     // accumulator tiles per wave: 14 for the 16 x 4 x 2 tiles (16 x 32 channel layers keep all 27
     // taps in one block), 12 elsewhere (more registers slow the other shapes down)
     constexpr int kMaxAcc = (TY == 4 && TZ == 2) ? 14 : 12;
-    f32x4 acc[kMaxAcc];
+    constexpr int RMAX = kMaxAcc / PT;                         // groups per wave
+    f32x4 acc[RMAX * PT];
 #pragma unroll
-    for (int q = 0; q < kMaxAcc; ++q) acc[q] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int q = 0; q < RMAX * PT; ++q) acc[q] = f32x4{0.f, 0.f, 0.f, 0.f};
 
     for (int t = blockIdx.x; t < n_tiles_grid; t += gridDim.x) {
         const int bx = t % tiles_x, by = (t / tiles_x) % tiles_y, bz = t / (tiles_x * tiles_y);
@@ -644,20 +648,20 @@ __global__ void __launch_bounds__(256) wgrad3t_kernel(const u16 *__restrict__ P,
             // the lane group's 8 contraction voxels: x = 8 (lg % 2) .. +7 of tile row (y, z)
             const int k0 = 32 * kb + 8 * lg;
             const int xr = k0 % TX, yr = (k0 / TX) % TY, zr = k0 / (TX * TY);
-            // P16 (one P channel tile, pc = 16): the P fragment is the same for
-            // every tap of the step and is read once (LDS reads per MFMA 4 -> 2 + 2 / taps)
-            const bf16x8 a16 = P16 ? tr_frag(sP, sp_pitch, k0, 0) : zero8();
+            bf16x8 a[PT];                                      // the step's P fragments
 #pragma unroll
-            for (int q = 0; q < kMaxAcc; ++q) {
-                const int T = wave + 4 * q;
-                if (T < n_acc) {
-                    const int o = o0 + T / n_ct, ct = T % n_ct;
-                    const int ti = ct / tiles_j, tj = ct % tiles_j;
+            for (int ti = 0; ti < PT; ++ti) a[ti] = tr_frag(sP, sp_pitch, k0, 16 * ti);
+#pragma unroll
+            for (int r = 0; r < RMAX; ++r) {
+                const int gi = wave + 4 * r;
+                if (gi < n_grp) {
+                    const int o = o0 + gi / qs, tj = gi % qs;
                     const int dz = o / 9, dy = (o / 3) % 3, dx = o % 3;     // halo shift = tap
-                    const bf16x8 a = P16 ? a16 : tr_frag(sP, sp_pitch, k0, 16 * ti);
                     const int hrow = ((zr + dz) * HY + (yr + dy)) * HX + (xr + dx);
                     const bf16x8 b = tr_frag(sQ, sq_pitch, hrow, 16 * tj);
-                    acc[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[q], 0, 0, 0);
+#pragma unroll
+                    for (int ti = 0; ti < PT; ++ti)
+                        acc[r * PT + ti] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[ti], b, acc[r * PT + ti], 0, 0, 0);
                 }
             }
         }
@@ -665,16 +669,17 @@ __global__ void __launch_bounds__(256) wgrad3t_kernel(const u16 *__restrict__ P,
     }
     const int li = lane & 15;
 #pragma unroll
-    for (int q = 0; q < kMaxAcc; ++q) {
-        const int T = wave + 4 * q;
-        if (T >= n_acc) continue;
-        const int o = o0 + T / n_ct, ct = T % n_ct;
-        const int ti = ct / tiles_j, tj = ct % tiles_j;
+    for (int r = 0; r < RMAX; ++r) {
+        const int gi = wave + 4 * r;
+        if (gi >= n_grp) continue;
+        const int o = o0 + gi / qs, tj = gi % qs;
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const int i = 16 * ti + 4 * lg + e, j = q_off + 16 * tj + li;
-            part[(((long)blockIdx.x * 27 + o) * pc + i) * qc + j] = acc[q][e];
-        }
+        for (int ti = 0; ti < PT; ++ti)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int i = 16 * ti + 4 * lg + e, j = q_off + 16 * tj + li;
+                part[(((long)blockIdx.x * 27 + o) * pc + i) * qc + j] = acc[r * PT + ti][e];
+            }
     }
 }
 
@@ -1137,22 +1142,23 @@ hipError_t wgrad(int am, const View &P, int p_ch, const View &Q, int q_ch, const
         slabs = (rows + per - 1) / per;
     } else {
         // Tile shape (16 x 4 x 4, 16 x 4 x 2 or 16 x 2 x 2 voxels), taps per block G
-        // and Q channel tiles per block qs: the feasible choice (accumulator
-        // tiles G x pc/16 x qs within the kernel's 4 waves x 14 for 16 x 4 x 2
-        // tiles, 4 x 12 otherwise; P tile and Q halo slice within 64 KB of LDS)
+        // and Q channel tiles per block qs: the feasible choice (G qs groups of
+        // pc/16 accumulator tiles over 4 waves, at most 14 tiles per wave for
+        // 16 x 4 x 2 tiles, 12 otherwise; P tile and Q halo slice within 64 KB of LDS)
         // that stages the fewest elements per voxel of the layer,
         // (27 / G) (qc / 16 / qs) (TV pc + HV 16 qs) / TV; within 15% the choice
         // with fewer blocks per tile wins (more MFMA work per staged tile), and
         // exact ties go to the larger tile.
+        if (pc != 16 && pc != 32 && pc != 64) return hipErrorInvalidValue;   // the kernel's PT = pc / 16
         const int shapes[3][2] = {{4, 4}, {4, 2}, {2, 2}};
         int ty = 0, tz = 0, G = 0, qs = 0, best_ny = 0;
         double best = 0.0;
         for (const auto &sh : shapes) {
             const int tv = 16 * sh[0] * sh[1], hv = 18 * (sh[0] + 2) * (sh[1] + 2);
-            const int amax = (sh[0] == 4 && sh[1] == 2) ? 56 : 48;
+            const int rmax = ((sh[0] == 4 && sh[1] == 2) ? 14 : 12) / (pc / 16);   // groups per wave
             for (int gg : {27, 9, 3})
                 for (int q = qc / 16; q >= 1; q /= 2) {
-                    if ((qc / 16) % q || gg * (pc / 16) * q > amax) continue;
+                    if ((qc / 16) % q || (gg * q + 3) / 4 > rmax) continue;
                     if (((size_t)tv * (pc + 8) + (size_t)hv * (16 * q + 8)) * sizeof(u16) > 65536) continue;
                     const int nyb = (27 / gg) * (qc / 16 / q);
                     const double cost = (double)nyb * ((double)tv * pc + (double)hv * 16 * q) / tv;
@@ -1168,14 +1174,12 @@ hipError_t wgrad(int am, const View &P, int p_ch, const View &Q, int q_ch, const
         slabs = std::max<long>(1, std::min<long>({tiles, cap, std::max(1L, 2048L / ny_blocks)}));
         const size_t lds = ((size_t)16 * ty * tz * (pc + 8) + (size_t)18 * (ty + 2) * (tz + 2) * (16 * qs + 8)) * sizeof(u16);
         const dim3 grid((uint32_t)slabs, (uint32_t)ny_blocks);
-#define WT(TY_, TZ_) do { if (pc == 16) hipLaunchKernelGGL((wgrad3t_kernel<TY_, TZ_, true>), grid, dim3(256), lds, s, \
-                                                             P.p, P.pitch, p_ch, Q.p, Q.pitch, q_ch, g, u->wpart, pc, qc, \
-                                                             G, qs); \
-                             else hipLaunchKernelGGL((wgrad3t_kernel<TY_, TZ_, false>), grid, dim3(256), lds, s, P.p, \
-                                                     P.pitch, p_ch, Q.p, Q.pitch, q_ch, g, u->wpart, pc, qc, G, qs); \
-                        } while (0)
+#define WTP(TY_, TZ_, PT_) hipLaunchKernelGGL((wgrad3t_kernel<TY_, TZ_, PT_>), grid, dim3(256), lds, s, P.p, P.pitch, \
+                                              p_ch, Q.p, Q.pitch, q_ch, g, u->wpart, pc, qc, G, qs)
+#define WT(TY_, TZ_) do { if (pc == 16) WTP(TY_, TZ_, 1); else if (pc == 32) WTP(TY_, TZ_, 2); else WTP(TY_, TZ_, 4); } while (0)
         if (ty == 4 && tz == 4) WT(4, 4); else if (ty == 4) WT(4, 2); else WT(2, 2);
 #undef WT
+#undef WTP
     }
     if (am != A_CONV3)
         hipLaunchKernelGGL((wgrad_kernel<A_S2D>), dim3(n_off, (uint32_t)slabs), dim3(256), 0, s, P.p, P.pitch, p_ch,
