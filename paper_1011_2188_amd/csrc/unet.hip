@@ -837,11 +837,16 @@ __global__ void head_kernel(const u16 *__restrict__ d1, int pitch, const float *
     float gwl[17];
     for (int c = 0; c < 17; ++c) gwl[c] = 0.f;
     const double inv_n = 1.0 / (double)n;
+    // a voxel's 16 channels are read and written as two 16-byte halves (pitch
+    // and buffers 8-element aligned: the head runs on the pitch-16 d1 buffers)
     for (long v = v0 + threadIdx.x; v < v1; v += blockDim.x) {
+        const uint4 q[2] = {*(const uint4 *)(d1 + v * pitch), *(const uint4 *)(d1 + v * pitch + 8)};
+        const u16 *hq = (const u16 *)q;
         float h[16];
         float y = w[16];
+#pragma unroll
         for (int c = 0; c < 16; ++c) {
-            h[c] = bf2f(d1[v * pitch + c]);
+            h[c] = bf2f(hq[c]);
             y += w[c] * h[c];
         }
         y += in[v];
@@ -850,10 +855,15 @@ __global__ void head_kernel(const u16 *__restrict__ d1, int pitch, const float *
             const float d = y - target[v];
             l += (double)d * d;
             const float gy = (float)(2.0 * d * inv_n);
+            uint4 o[2];
+            u16 *oh = (u16 *)o;
+#pragma unroll
             for (int c = 0; c < 16; ++c) {
                 gwl[c] += gy * h[c];
-                gd1[v * pitch + c] = f2bf(h[c] > 0.f ? w[c] * gy : 0.f);
+                oh[c] = f2bf(h[c] > 0.f ? w[c] * gy : 0.f);
             }
+            *(uint4 *)(gd1 + v * pitch) = o[0];
+            *(uint4 *)(gd1 + v * pitch + 8) = o[1];
             gwl[16] += gy;
         }
     }
