@@ -17,8 +17,9 @@
 //            a depth-to-space store (transposed convolution).
 //   wgrad    weight gradient sum_v P[v][i] * Q[map(v, o)][j] over voxels, tiles
 //            transposed through LDS, per-slab partials summed in a fixed order.
-//   small kernels: input packing, 2x2x2 average pool and its adjoint, the 1x1
-//            head with residual and MSE loss, bias gradients, Adam.
+//   small kernels: input packing, the adjoint of the 2x2x2 average pool (the
+//            pool itself runs in the epilogue of the convolution before it), the
+//            1x1 head with residual and MSE loss, bias gradients, Adam.
 #include "fdc.h"
 #include "fdc_device.h"
 
@@ -271,7 +272,8 @@ __global__ void __launch_bounds__(256) conv3_kernel(const u16 *__restrict__ src,
                                                     const u16 *__restrict__ wpk, int kpad, int n_cols,
                                                     const float *__restrict__ bias, int relu,
                                                     const u16 *__restrict__ mask, int mask_pitch,
-                                                    u16 *__restrict__ dst, int dst_pitch, int vec)
+                                                    u16 *__restrict__ dst, int dst_pitch, int vec,
+                                                    u16 *__restrict__ pool_dst, int pool_pitch)
 {
     constexpr int TX = 16, TZ = 4, HX = TX + 2, HY = TY + 2, HZ = TZ + 2;
     static_assert(CP % CS == 0 && (CS == CP || CS % 32 == 0), "phases of whole K steps");
@@ -422,6 +424,32 @@ __global__ void __launch_bounds__(256) conv3_kernel(const u16 *__restrict__ src,
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (pool_dst) {
+            // fused 2x2x2 average pool of the block's (pool-aligned) output tile:
+            // pool_dst[coarse v][c] = bf16(0.125 * sum of the 8 stored bf16 values),
+            // summed in FP32 over a = 4 dz + 2 dy + dx = 0 .. 7
+            __syncthreads();                               // every wave's slice is in LDS
+            const int ch = (int)threadIdx.x, cq = ch % CH, cv = ch / CH;   // chunk of 8 channels, coarse voxel
+            const int cx = cv % (TX / 2), cy = (cv / (TX / 2)) % (TY / 2), cz = cv / ((TX / 2) * (TY / 2));
+            const int gx = x0 / 2 + cx, gy = y0 / 2 + cy, gz = z0 / 2 + cz, n = n_base + 8 * cq;
+            if (cz < TZ / 2 && gx < g.nx / 2 && gy < g.ny / 2 && gz < g.nz / 2 && n < n_cols) {
+                float acc8[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int a = 0; a < 8; ++a) {
+                    const int wz = 2 * cz + (a >> 2), vy = 2 * cy + ((a >> 1) & 1), vx = 2 * cx + (a & 1);
+                    const uint4 q = *(const uint4 *)(sh + wz * (16 * TY * TP) + (vy * 16 + vx) * TP + 8 * cq);
+                    const u16 *hq = (const u16 *)&q;
+#pragma unroll
+                    for (int k = 0; k < 8; ++k) acc8[k] += bf2f(hq[k]);
+                }
+                uint4 o;
+                u16 *oh = (u16 *)&o;
+#pragma unroll
+                for (int k = 0; k < 8; ++k) oh[k] = f2bf(acc8[k] * 0.125f);
+                const long cvox = ((long)gz * (g.ny / 2) + gy) * (g.nx / 2) + gx;
+                *(uint4 *)(pool_dst + cvox * pool_pitch + n) = o;
+            }
+        }
         if (z >= g.nz) return;
 #pragma unroll
         for (int i = 0; i < NQ; ++i) {
@@ -774,24 +802,6 @@ __global__ void pack_input_kernel(const float *__restrict__ in, long n, u16 *__r
     }
 }
 
-// 2x2x2 average pool: coarse grid g, fine grid 2g
-__global__ void pool_kernel(const u16 *__restrict__ src, int s_pitch, int C, Grid g, u16 *__restrict__ dst, int d_pitch)
-{
-    const long n = (long)g.nx * g.ny * g.nz;
-    const int fx = 2 * g.nx, fy = 2 * g.ny;
-    for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < n * C; t += (long)gridDim.x * blockDim.x) {
-        const long v = t / C;
-        const int c = (int)(t - v * C);
-        const int x = (int)(v % g.nx), y = (int)((v / g.nx) % g.ny), z = (int)(v / ((long)g.nx * g.ny));
-        float s = 0.f;
-        for (int a = 0; a < 8; ++a) {
-            const long fv = ((long)(2 * z + (a >> 2)) * fy + (2 * y + ((a >> 1) & 1))) * fx + 2 * x + (a & 1);
-            s += bf2f(src[fv * s_pitch + c]);
-        }
-        dst[v * d_pitch + c] = f2bf(s * 0.125f);
-    }
-}
-
 // adjoint of the pool plus the skip-connection gradient, masked by ReLU:
 // ge[fine v][c] = bf16( (bf16(gp[coarse(v)][c] / 8) + skip[v][c]) * (e[v][c] > 0) )
 // 8 channels (16 bytes of every operand) per thread: C, the pitches and the
@@ -1082,7 +1092,8 @@ uint32_t blocks_for(long n, int per = 256, long cap = 16384) { return (uint32_t)
 
 // one implicit-GEMM launch: rows on grid g, n_cols output columns
 hipError_t igemm(int am, int em, const View &src, int cpad, const Grid &g, const u16 *wpk, int kpad, int n_cols,
-                 const float *bias, bool relu, const View *mask, const View &dst, int d2s_cout, hipStream_t s)
+                 const float *bias, bool relu, const View *mask, const View &dst, int d2s_cout, hipStream_t s,
+                 const View *pool = nullptr)
 {
     const long rows = (long)g.nx * g.ny * g.nz;
     const long waves = (rows + 31) / 32;                  // MT = 2: 32 rows per wave
@@ -1110,9 +1121,16 @@ hipError_t igemm(int am, int em, const View &src, int cpad, const Grid &g, const
         // 16-byte output stores (and mask loads) need 8-element alignment throughout
         const auto al = [](const void *p) { return ((uintptr_t)p & 15) == 0; };
         const int vec = n_cols % 8 == 0 && dst.pitch % 8 == 0 && al(dst.p) && (!mp || (mpitch % 8 == 0 && al(mp)));
+        // the fused pool needs the staged epilogue, a grid divisible by 2 and one
+        // thread per (coarse voxel, 8 channels) of the block: 32 coarse voxels x 2 nt
+        if (pool && (!vec || pool->pitch % 8 || !al(pool->p) || g.nx % 2 || g.ny % 2 || g.nz % 2 || nt > 4 ||
+                     16 * ty * (16 * nt + 8) * 4 > 6 * (ty + 2) * 18 * (cs + 8)))
+            return hipErrorInvalidValue;
+        u16 *pp = pool ? pool->p : nullptr;
+        const int ppitch = pool ? pool->pitch : 0;
 #define CV(NT_, TY_, CP_, CS_) hipLaunchKernelGGL((conv3_kernel<NT_, TY_, CP_, CS_>), cgrid, dim3(256), lds, s, src.p, \
                                                   src.pitch, g, wpk, kpad, n_cols, bias, (int)relu, mp, mpitch, dst.p, \
-                                                  dst.pitch, vec)
+                                                  dst.pitch, vec, pp, ppitch)
 #define CVN(TY_, CP_, CS_) do { if (nt == 4) CV(4, TY_, CP_, CS_); else if (nt == 2) CV(2, TY_, CP_, CS_); \
                                 else CV(1, TY_, CP_, CS_); } while (0)
         if (cpad == 8) CVN(4, 8, 8);
@@ -1297,11 +1315,12 @@ Views views(const fdc_unet *u)
     return v;
 }
 
-hipError_t conv_fwd(fdc_unet *u, int l, const View &src, const Grid &g, const View &dst, hipStream_t s)
+hipError_t conv_fwd(fdc_unet *u, int l, const View &src, const Grid &g, const View &dst, hipStream_t s,
+                    const View *pool = nullptr)
 {
     const LayerDesc &L = kLayers[l];
     return igemm(A_CONV3, E_STORE, src, pad8(L.cin), g, u->wpk_f[l], u->kpad_f[l], L.cout, u->params + u->b_off[l],
-                 true, nullptr, dst, 0, s);
+                 true, nullptr, dst, 0, s, pool);
 }
 
 hipError_t forward_pass(fdc_unet *u, const float *in, hipStream_t s)
@@ -1311,19 +1330,9 @@ hipError_t forward_pass(fdc_unet *u, const float *in, hipStream_t s)
     hipLaunchKernelGGL(pack_input_kernel, dim3(blocks_for(u->nv[0])), dim3(256), 0, s, in, u->nv[0], u->x);
     hipError_t e = hipGetLastError();
     if (!e) e = conv_fwd(u, L_E1A, v.x, g[0], v.e1a, s);
-    if (!e) e = conv_fwd(u, L_E1B, v.e1a, g[0], v.e1, s);
-    if (!e) {
-        hipLaunchKernelGGL(pool_kernel, dim3(blocks_for(u->nv[1] * 16)), dim3(256), 0, s, v.e1.p, v.e1.pitch, 16, g[1],
-                           v.p1.p, v.p1.pitch);
-        e = hipGetLastError();
-    }
+    if (!e) e = conv_fwd(u, L_E1B, v.e1a, g[0], v.e1, s, &v.p1);    // pool 1 fused into the epilogue
     if (!e) e = conv_fwd(u, L_E2A, v.p1, g[1], v.e2a, s);
-    if (!e) e = conv_fwd(u, L_E2B, v.e2a, g[1], v.e2, s);
-    if (!e) {
-        hipLaunchKernelGGL(pool_kernel, dim3(blocks_for(u->nv[2] * 32)), dim3(256), 0, s, v.e2.p, v.e2.pitch, 32, g[2],
-                           v.p2.p, v.p2.pitch);
-        e = hipGetLastError();
-    }
+    if (!e) e = conv_fwd(u, L_E2B, v.e2a, g[1], v.e2, s, &v.p2);    // pool 2 fused into the epilogue
     if (!e) e = conv_fwd(u, L_MA, v.p2, g[2], v.ma, s);
     if (!e) e = conv_fwd(u, L_MB, v.ma, g[2], v.m, s);
     if (!e) e = igemm(A_CONV1, E_D2S, v.m, 64, g[2], u->wpk_f[L_UP2], u->kpad_f[L_UP2], u->ncol_f[L_UP2],
