@@ -188,11 +188,22 @@ int fdc_load_track_db(fdc_ctx *ctx, const fdc_step *steps, uint64_t n_steps,
                       const uint64_t *track_off, uint32_t n_tracks, const float *bin_E_MeV,
                       const uint32_t *bin_first, uint32_t n_bins, void *hip_stream);
 
+/* The same load from a track-database file (Section 2.2: the stored water
+ * histories).  Layout, all little-endian: a 104-byte header {char magic[8] =
+ * "FDCTRKDB"; uint32 version = 1; uint32 n_bins, n_tracks, reserved; uint64
+ * n_steps; uint64 db_seed; double physics[8] (the generator's constants, not
+ * read)}, then bin_E (float x n_bins), bin_first (uint32 x n_bins+1),
+ * track_off (uint64 x n_tracks+1) and the steps (fdc_step x n_steps), packed.
+ * The file is read on the host and closed before the call returns.  Errors:
+ * FDC_E_ARG (NULL path, file cannot be opened), FDC_E_FORMAT (bad magic or
+ * version, a size that does not match the header, a short read, and every
+ * check of fdc_load_track_db), FDC_E_NOMEM, FDC_E_HIP. */
+int fdc_load_track_db_file(fdc_ctx *ctx, const char *path, void *hip_stream);
+
 /* Add a plan: a phantom of nx*ny*nz voxels of size voxel_cm (x, y, z) whose
  * voxel (0,0,0) starts at origin_cm, with CT numbers hu[] (host, x-fastest;
- * Section 2.3: a three-dimensional array with a material index per voxel).
- * Allocates its energy and squared-energy tallies (Section 2.3: a tally grid
- * with the phantom's voxel count, stored as a one-dimensional array), zeroed.
+ * Section 2.3: the per-voxel material grid).  Allocates its energy and
+ * squared-energy tallies (Section 2.3: the tally grid), zeroed.
  * *plan_out receives the plan id.  Errors: FDC_E_ARG (NULL, non-positive or
  * non-finite sizes, more than 2^31 voxels), FDC_E_NOMEM, FDC_E_HIP. */
 int fdc_load_phantom(fdc_ctx *ctx, int32_t *plan_out, const int16_t *hu, int nx, int ny, int nz,

@@ -136,6 +136,29 @@ void oracle_material(const double *hu_pts, const double *rho, const double *rsp,
 }
 
 /* ---------------------------------------------------------------------- */
+/* Optional record of one history's walk (test aid): one event per voxel
+ * visit and per step end, in the order they happen. */
+typedef struct {
+    int64_t *ev;  /* per event: kind, voxel index, deposited piece (fp), exit axis (-1: none) */
+    double *evd;  /* per event: WEL consumed, geometric length moved */
+    int cap, n;
+} oracle_trace;
+
+enum { EV_VOXEL = 0, EV_VACUUM = 1, EV_STEP_END = 2, EV_ESCAPE = 3 };
+
+static void trace_push(oracle_trace *tr, int64_t kind, int64_t v, int64_t piece, int64_t axis, double w,
+                       double move)
+{
+    if (!tr) return;
+    if (tr->n < tr->cap) {
+        int64_t *e = tr->ev + 4 * tr->n;
+        e[0] = kind; e[1] = v; e[2] = piece; e[3] = axis;
+        tr->evd[2 * tr->n] = w;
+        tr->evd[2 * tr->n + 1] = move;
+    }
+    tr->n++;
+}
+
 typedef struct {
     /* track database */
     const float *steps; /* 4 floats per step: dx (WEL cm), dE (MeV), theta, phi */
@@ -156,6 +179,7 @@ typedef struct {
     uint64_t seed;
     uint32_t R;
     uint32_t flags;
+    oracle_trace *trace; /* NULL unless a test asks for the walk */
 } oracle_problem;
 
 typedef struct {
@@ -163,6 +187,14 @@ typedef struct {
     uint64_t *E2;
     int64_t incident, escaped;
     uint64_t steps, visits, vacuum_visits, flushes;
+    /* optional: the squared-energy tally of Eq. (2) taken literally - the
+     * square of a history's whole deposit in a voxel, summed over every visit
+     * of that history (E2 squares each visit on its own) */
+    uint64_t *E2x;
+    int64_t *hsum;      /* per voxel: this history's deposit so far */
+    size_t *touched;    /* voxels with a non-zero hsum */
+    size_t n_touched, cap_touched;
+    int overflow;
 } oracle_tally;
 
 static int64_t fp_energy(double e) { return (int64_t)nearbyint(e * FP_SCALE); }
@@ -207,6 +239,13 @@ void oracle_rotate(double dir[3], double theta, double phi) { rotate(dir, theta,
 static void flush(const oracle_problem *P, oracle_tally *T, size_t v, int64_t *acc)
 {
     if (*acc == 0) return;
+    if (T->E2x) {
+        if (T->hsum[v] == 0) {
+            if (T->n_touched < T->cap_touched) T->touched[T->n_touched++] = v;
+            else T->overflow = 1;
+        }
+        T->hsum[v] += *acc;
+    }
     T->E[v] += *acc;
     if ((P->flags & FLAG_VARIANCE) && T->E2) {
         uint64_t q = (uint64_t)((*acc + 2048) >> 12);
@@ -354,6 +393,8 @@ static int replay_history(const oracle_problem *P, uint32_t s, uint64_t h, oracl
             }
             int cross = 1;
             double move = lexit;
+            double w_trace = 0.0;
+            int64_t piece_trace = 0;
             if (vac) {
                 if (T) T->vacuum_visits++;
             } else {
@@ -378,13 +419,18 @@ static int replay_history(const oracle_problem *P, uint32_t s, uint64_t h, oracl
                 hist_dep += piece;
                 g2 += w_v * g;
                 tau = tau_n;
+                w_trace = w_v;
+                piece_trace = piece;
             }
+            trace_push(P->trace, vac ? EV_VACUUM : EV_VOXEL, (int64_t)v, piece_trace, cross ? ax : -1, w_trace,
+                       move);
             if (cross) {
                 for (int a = 0; a < 3; ++a) pos[a] += move * d[a];
                 pos[ax] = P->org[ax] + (iv[ax] + (d[ax] > 0.0 ? 1 : 0)) * P->vox[ax];
                 if (T) flush(P, T, v, &acc);
                 iv[ax] += d[ax] > 0.0 ? 1 : -1;
                 if (iv[ax] < 0 || iv[ax] >= P->n[ax]) {
+                    trace_push(P->trace, EV_ESCAPE, -1, I_h - hist_dep, ax, 0.0, 0.0);
                     if (T) T->escaped += I_h - hist_dep;
                     reason = END_ESCAPE;
                     alive = 0;
@@ -397,6 +443,7 @@ static int replay_history(const oracle_problem *P, uint32_t s, uint64_t h, oracl
         if (!alive) break;
         /* deflection at the end of the step, scaled by the traversed material */
         double th = theta * sqrt(g2 / w_tot);
+        trace_push(P->trace, EV_STEP_END, (int64_t)k, 0, -1, g2, th);
         rotate(db, th, phi);
         for (int a = 0; a < 3; ++a) d[a] = M[a][0] * db[0] + M[a][1] * db[1] + M[a][2] * db[2];
     }
@@ -431,6 +478,7 @@ static void setup(oracle_problem *P, const float *steps, const uint64_t *track_o
     P->tab.n = n_pts; P->tab.vacuum_below_hu = vacuum_below_hu;
     P->spot_pos = spot_pos; P->spot_dir = spot_dir; P->spot_E = spot_E; P->spot_sigma = spot_sigma;
     P->plan = plan; P->seed = seed; P->R = R; P->flags = flags;
+    P->trace = NULL;
 }
 
 /*
@@ -441,6 +489,17 @@ static void setup(oracle_problem *P, const float *steps, const uint64_t *track_o
  * each thread tallies privately and the integer sums are added at the end,
  * which is exact.  Returns 0, or -1 if a history failed to conserve energy.
  */
+int oracle_replay_e2x(const float *steps, const uint64_t *track_off, uint32_t n_tracks,
+                      const float *bin_E, const uint32_t *bin_first, uint32_t n_bins,
+                      const int16_t *hu, const int dims[3], const double vox[3], const double org[3],
+                      const double *hu_pts, const double *rho, const double *rsp, const double *rscp,
+                      int n_pts, double vacuum_below_hu,
+                      const float *spot_pos, const float *spot_dir, const float *spot_E,
+                      const float *spot_sigma, uint32_t n_spots,
+                      const uint64_t *h_begin, const uint64_t *h_count,
+                      uint32_t plan, uint64_t seed, uint32_t R, uint32_t flags, int n_threads,
+                      int64_t *E, uint64_t *E2, int64_t *stats, uint64_t *E2x);
+
 int oracle_replay(const float *steps, const uint64_t *track_off, uint32_t n_tracks,
                   const float *bin_E, const uint32_t *bin_first, uint32_t n_bins,
                   const int16_t *hu, const int dims[3], const double vox[3], const double org[3],
@@ -451,6 +510,25 @@ int oracle_replay(const float *steps, const uint64_t *track_off, uint32_t n_trac
                   const uint64_t *h_begin, const uint64_t *h_count,
                   uint32_t plan, uint64_t seed, uint32_t R, uint32_t flags, int n_threads,
                   int64_t *E, uint64_t *E2, int64_t *stats)
+{
+    return oracle_replay_e2x(steps, track_off, n_tracks, bin_E, bin_first, n_bins, hu, dims, vox, org, hu_pts, rho,
+                             rsp, rscp, n_pts, vacuum_below_hu, spot_pos, spot_dir, spot_E, spot_sigma, n_spots,
+                             h_begin, h_count, plan, seed, R, flags, n_threads, E, E2, stats, NULL);
+}
+
+/* As oracle_replay; with E2x non-NULL also the per-history squared tally
+ * (each history's total deposit in a voxel, rounded to 2^-12 MeV like the
+ * per-visit tally, squared once). */
+int oracle_replay_e2x(const float *steps, const uint64_t *track_off, uint32_t n_tracks,
+                      const float *bin_E, const uint32_t *bin_first, uint32_t n_bins,
+                      const int16_t *hu, const int dims[3], const double vox[3], const double org[3],
+                      const double *hu_pts, const double *rho, const double *rsp, const double *rscp,
+                      int n_pts, double vacuum_below_hu,
+                      const float *spot_pos, const float *spot_dir, const float *spot_E,
+                      const float *spot_sigma, uint32_t n_spots,
+                      const uint64_t *h_begin, const uint64_t *h_count,
+                      uint32_t plan, uint64_t seed, uint32_t R, uint32_t flags, int n_threads,
+                      int64_t *E, uint64_t *E2, int64_t *stats, uint64_t *E2x)
 {
     oracle_problem P;
     setup(&P, steps, track_off, n_tracks, bin_E, bin_first, n_bins, hu, dims, vox, org,
@@ -476,6 +554,12 @@ int oracle_replay(const float *steps, const uint64_t *track_off, uint32_t n_trac
         memset(&T, 0, sizeof T);
         T.E = (int64_t *)calloc(nvox, sizeof(int64_t));
         T.E2 = E2 ? (uint64_t *)calloc(nvox, sizeof(uint64_t)) : NULL;
+        if (E2x) {
+            T.E2x = (uint64_t *)calloc(nvox, sizeof(uint64_t));
+            T.hsum = (int64_t *)calloc(nvox, sizeof(int64_t));
+            T.cap_touched = 1u << 20;
+            T.touched = (size_t *)malloc(sizeof(size_t) * T.cap_touched);
+        }
         uint64_t lo = total * (uint64_t)tid / (uint64_t)nth;
         uint64_t hi = total * (uint64_t)(tid + 1) / (uint64_t)nth;
         uint32_t s = 0;
@@ -483,6 +567,16 @@ int oracle_replay(const float *steps, const uint64_t *track_off, uint32_t n_trac
             while (prefix[s + 1] <= g) ++s;
             double ep[3];
             if (replay_history(&P, s, h_begin[s] + (g - prefix[s]), &T, ep) < 0) err |= 1;
+            if (E2x) { /* this history's whole deposit per voxel, squared once */
+                for (size_t i = 0; i < T.n_touched; ++i) {
+                    size_t v = T.touched[i];
+                    uint64_t q = (uint64_t)((T.hsum[v] + 2048) >> 12);
+                    T.E2x[v] += q * q;
+                    T.hsum[v] = 0;
+                }
+                T.n_touched = 0;
+                if (T.overflow) err |= 1;
+            }
         }
 #ifdef _OPENMP
         #pragma omp critical
@@ -491,6 +585,8 @@ int oracle_replay(const float *steps, const uint64_t *track_off, uint32_t n_trac
             for (size_t v = 0; v < nvox; ++v) E[v] += T.E[v];
             if (E2)
                 for (size_t v = 0; v < nvox; ++v) E2[v] += T.E2[v];
+            if (E2x)
+                for (size_t v = 0; v < nvox; ++v) E2x[v] += T.E2x[v];
             stats[0] += T.incident;
             stats[1] += T.escaped;
             stats[2] += (int64_t)T.steps;
@@ -500,6 +596,9 @@ int oracle_replay(const float *steps, const uint64_t *track_off, uint32_t n_trac
         }
         free(T.E);
         free(T.E2);
+        free(T.E2x);
+        free(T.hsum);
+        free(T.touched);
     }
     free(prefix);
     return err ? -1 : 0;
@@ -524,4 +623,32 @@ int oracle_endpoints(const float *steps, const uint64_t *track_off, uint32_t n_t
     for (uint32_t i = 0; i < n; ++i)
         reason[i] = replay_history(&P, s, h0 + i, NULL, xyz + 3 * i);
     return 0;
+}
+
+/* The walk of one history (spot s, index h) as a list of events (test aid):
+ * ev[4*i..] = (kind: 0 voxel visit, 1 vacuum voxel, 2 step end, 3 escape;
+ * voxel index (step index for a step end); deposited piece in fixed point
+ * (escaped remainder for an escape); exit axis of the visit or -1 if the step
+ * ended inside the voxel), evd[2*i..] = (WEL consumed in the voxel, or the
+ * step's accumulated sum(w*G) at a step end; geometric length moved, or the
+ * deflection angle at a step end).  Returns the number of events (which may
+ * exceed cap: only the first cap are written); *reason gets the end reason. */
+int oracle_trace_history(const float *steps, const uint64_t *track_off, uint32_t n_tracks,
+                         const float *bin_E, const uint32_t *bin_first, uint32_t n_bins,
+                         const int16_t *hu, const int dims[3], const double vox[3], const double org[3],
+                         const double *hu_pts, const double *rho, const double *rsp, const double *rscp,
+                         int n_pts, double vacuum_below_hu,
+                         const float *spot_pos, const float *spot_dir, const float *spot_E,
+                         const float *spot_sigma, uint32_t s, uint64_t h,
+                         uint32_t plan, uint64_t seed, uint32_t R, uint32_t flags,
+                         int64_t *ev, double *evd, int cap, int32_t *reason, double endpoint[3])
+{
+    oracle_problem P;
+    setup(&P, steps, track_off, n_tracks, bin_E, bin_first, n_bins, hu, dims, vox, org,
+          hu_pts, rho, rsp, rscp, n_pts, vacuum_below_hu, spot_pos, spot_dir, spot_E, spot_sigma,
+          plan, seed, R, flags);
+    oracle_trace tr = {ev, evd, cap, 0};
+    P.trace = &tr;
+    *reason = replay_history(&P, s, h, NULL, endpoint);
+    return tr.n;
 }

@@ -58,9 +58,22 @@ def _p(a, t):
     return a.ctypes.data_as(C.POINTER(t))
 
 
+# The material table the oracle uses unless a test passes its own: synthetic
+# piecewise-linear constants (Section 2.5 leaves the HU conversion to other
+# work).  Breakpoints at HU -1000 / 0 / 1000 / 3071; water (HU 0) is exactly
+# (1, 1, 1); RScP = rho * k with k = 1 up to HU 0, rising linearly to 1.35 at
+# HU 1000 and flat above; HU below -990 is vacuum.
+ORACLE_HU_TABLE = {
+    "hu": np.array([-1000.0, 0.0, 1000.0, 3071.0]),
+    "rho": np.array([0.0012, 1.0, 1.6, 2.84]),
+    "rsp": np.array([0.0011, 1.0, 1.5, 2.64]),
+    "rscp": np.array([0.0012 * 1.0, 1.0 * 1.0, 1.6 * 1.35, 2.84 * 1.35]),
+    "vacuum_below_hu": -990.0,
+}
+
+
 def default_table():
-    from paper_1011_2188_amd.inputs import HU_TABLE_DEFAULT
-    return HU_TABLE_DEFAULT
+    return ORACLE_HU_TABLE
 
 
 # --------------------------------------------------------------------------
@@ -141,12 +154,14 @@ def _common(db, ph, sp, table):
 
 
 def replay(db, ph, sp, h_begin=None, h_count=None, plan=0, seed=1, R=64, flags=FLAG_VARIANCE,
-           threads=None, table=None):
+           threads=None, table=None, exact_e2=False):
     """Replay histories h_begin[i] .. h_begin[i]+h_count[i]-1 of every spot i.
 
     Returns a dict with the int64 energy tally E, the uint64 sum-of-squares tally
     E2 (x-fastest, shape [nz,ny,nx]), incident/escaped energy (fixed point) and
-    the work counters (steps, visits, vacuum_visits, flushes)."""
+    the work counters (steps, visits, vacuum_visits, flushes).  With exact_e2
+    also E2x: each history's whole deposit in a voxel squared once (Eq. (2)
+    taken literally; E2 squares every visit on its own)."""
     arrs, args = _common(db, ph, sp, table)
     ns = len(sp)
     hb = np.zeros(ns, np.uint64) if h_begin is None else np.ascontiguousarray(h_begin, np.uint64)
@@ -156,14 +171,16 @@ def replay(db, ph, sp, h_begin=None, h_count=None, plan=0, seed=1, R=64, flags=F
     E = np.zeros(nx * ny * nz, np.int64)
     E2 = np.zeros(nx * ny * nz, np.uint64)
     stats = np.zeros(6, np.int64)
+    E2x = np.zeros(nx * ny * nz, np.uint64) if exact_e2 else None
     nthreads = threads or int(os.environ.get("ORACLE_THREADS", min(os.cpu_count() or 1, 16)))
-    rc = lib().oracle_replay(*args, C.c_uint32(ns), _p(hb, C.c_uint64), _p(hc, C.c_uint64),
-                             C.c_uint32(plan), C.c_uint64(seed), C.c_uint32(R), C.c_uint32(flags),
-                             C.c_int(nthreads), _p(E, C.c_int64), _p(E2, C.c_uint64),
-                             _p(stats, C.c_int64))
+    rc = lib().oracle_replay_e2x(*args, C.c_uint32(ns), _p(hb, C.c_uint64), _p(hc, C.c_uint64),
+                                 C.c_uint32(plan), C.c_uint64(seed), C.c_uint32(R), C.c_uint32(flags),
+                                 C.c_int(nthreads), _p(E, C.c_int64), _p(E2, C.c_uint64),
+                                 _p(stats, C.c_int64), _p(E2x, C.c_uint64) if exact_e2 else None)
     if rc != 0:
         raise RuntimeError("oracle replay failed to conserve energy")
-    return dict(E=E.reshape(nz, ny, nx), E2=E2.reshape(nz, ny, nx), incident=int(stats[0]),
+    extra = dict(E2x=E2x.reshape(nz, ny, nx)) if exact_e2 else {}
+    return dict(**extra, E=E.reshape(nz, ny, nx), E2=E2.reshape(nz, ny, nx), incident=int(stats[0]),
                 escaped=int(stats[1]), steps=int(stats[2]), visits=int(stats[3]),
                 vacuum_visits=int(stats[4]), flushes=int(stats[5]),
                 n_histories=int(hc.sum()), threads=nthreads)
@@ -180,6 +197,26 @@ def endpoints(db, ph, sp, spot, h0, n, plan=0, seed=1, R=64, flags=0, table=None
     if np.any(reason < 0):
         raise RuntimeError("oracle replay failed to conserve energy")
     return xyz, reason
+
+
+EV_VOXEL, EV_VACUUM, EV_STEP_END, EV_ESCAPE = 0, 1, 2, 3
+
+
+def trace(db, ph, sp, spot, h, plan=0, seed=1, R=64, flags=0, table=None, cap=100_000):
+    """The walk of one history as a list of events (kind, voxel, piece, axis,
+    wel, move); see oracle_trace_history.  Returns (events, reason, end point)."""
+    arrs, args = _common(db, ph, sp, table)
+    ev = np.zeros((cap, 4), np.int64)
+    evd = np.zeros((cap, 2), np.float64)
+    reason = C.c_int32()
+    ep = np.zeros(3, np.float64)
+    n = lib().oracle_trace_history(*args, C.c_uint32(spot), C.c_uint64(h), C.c_uint32(plan), C.c_uint64(seed),
+                                   C.c_uint32(R), C.c_uint32(flags), _p(ev, C.c_int64), _p(evd, C.c_double),
+                                   C.c_int(cap), C.byref(reason), _p(ep, C.c_double))
+    if n > cap:
+        raise RuntimeError("trace longer than its buffer")
+    out = [(int(a), int(b), int(c), int(d), float(w), float(m)) for (a, b, c, d), (w, m) in zip(ev[:n], evd[:n])]
+    return out, int(reason.value), ep
 
 
 # --------------------------------------------------------------------------

@@ -603,6 +603,69 @@ int fdc_load_track_db(fdc_ctx *ctx, const fdc_step *steps, uint64_t n_steps, con
     return FDC_OK;
 }
 
+// Track-database file: the header below (little-endian), then bin_E
+// (f32 x n_bins), bin_first (u32 x n_bins+1), track_off (u64 x n_tracks+1)
+// and the steps (4 x f32 each), packed in that order.
+namespace {
+struct DbFileHeader {
+    char magic[8];                   // "FDCTRKDB"
+    uint32_t version;                // 1
+    uint32_t n_bins, n_tracks, reserved;
+    uint64_t n_steps;
+    uint64_t db_seed;
+    double physics[8];               // generator constants, informational
+};
+static_assert(sizeof(DbFileHeader) == 104, "track database header layout");
+} // namespace
+
+int fdc_load_track_db_file(fdc_ctx *ctx, const char *path, void *hip_stream)
+{
+    if (!ctx) return FDC_E_ARG;
+    if (!path) return fail(ctx, FDC_E_ARG, "track database file: NULL path");
+    FILE *f = std::fopen(path, "rb");
+    if (!f) return fail(ctx, FDC_E_ARG, "track database file: cannot open %s", path);
+    DbFileHeader h;
+    long long size = -1;
+    if (std::fseek(f, 0, SEEK_END) == 0) size = std::ftell(f);
+    std::rewind(f);
+    if (std::fread(&h, sizeof h, 1, f) != 1) { std::fclose(f); return fail(ctx, FDC_E_FORMAT, "track database file: short header"); }
+    if (std::memcmp(h.magic, "FDCTRKDB", 8) != 0 || h.version != 1) {
+        std::fclose(f);
+        return fail(ctx, FDC_E_FORMAT, "track database file: bad magic or version %u", h.version);
+    }
+    if (h.n_bins == 0 || h.n_tracks == 0 || h.n_steps == 0 || h.n_steps > (1ull << 40)) {
+        std::fclose(f);
+        return fail(ctx, FDC_E_FORMAT, "track database file: empty or implausible counts");
+    }
+    const unsigned long long want = sizeof h + 4ull * h.n_bins + 4ull * (h.n_bins + 1ull) +
+                                    8ull * (h.n_tracks + 1ull) + 16ull * h.n_steps;
+    if (size < 0 || (unsigned long long)size != want) {
+        std::fclose(f);
+        return fail(ctx, FDC_E_FORMAT, "track database file: %lld bytes, the header implies %llu", size, want);
+    }
+    std::vector<float> bin_E;
+    std::vector<uint32_t> bin_first;
+    std::vector<uint64_t> off;
+    std::vector<fdc_step> steps;
+    try {
+        bin_E.resize(h.n_bins);
+        bin_first.resize(h.n_bins + 1ull);
+        off.resize(h.n_tracks + 1ull);
+        steps.resize(h.n_steps);
+    } catch (const std::bad_alloc &) {
+        std::fclose(f);
+        return fail(ctx, FDC_E_NOMEM, "track database file: host buffers");
+    }
+    const bool ok = std::fread(bin_E.data(), 4, bin_E.size(), f) == bin_E.size() &&
+                    std::fread(bin_first.data(), 4, bin_first.size(), f) == bin_first.size() &&
+                    std::fread(off.data(), 8, off.size(), f) == off.size() &&
+                    std::fread(steps.data(), sizeof(fdc_step), steps.size(), f) == steps.size();
+    std::fclose(f);
+    if (!ok) return fail(ctx, FDC_E_FORMAT, "track database file: short read");
+    return fdc_load_track_db(ctx, steps.data(), h.n_steps, off.data(), h.n_tracks, bin_E.data(), bin_first.data(),
+                             h.n_bins, hip_stream);
+}
+
 int fdc_load_phantom(fdc_ctx *ctx, int32_t *plan_out, const int16_t *hu, int nx, int ny, int nz,
                      const float voxel_cm[3], const float origin_cm[3], void *hip_stream)
 {

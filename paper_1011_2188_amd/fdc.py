@@ -28,7 +28,7 @@ ERROR_NAMES = {0: "FDC_OK", -1: "FDC_E_ARG", -2: "FDC_E_STATE", -3: "FDC_E_NOMEM
 
 # every entry point declared in include/fdc.h
 EXPORTS = ["fdc_create", "fdc_destroy", "fdc_last_error", "fdc_set_allocator", "fdc_set_hu_table",
-           "fdc_load_track_db", "fdc_load_phantom", "fdc_add_beam_spots", "fdc_run_histories",
+           "fdc_load_track_db", "fdc_load_track_db_file", "fdc_load_phantom", "fdc_add_beam_spots", "fdc_run_histories",
            "fdc_reset_plan", "fdc_compute_dose", "fdc_read_dose_and_variance", "fdc_debug_endpoints",
            "fdc_debug_philox", "fdc_debug_material", "fdc_set_launch_config", "fdc_device_cus",
            "fdc_mean_uncertainty", "fdc_batch_uncertainty", "fdc_gamma_index",
@@ -82,6 +82,7 @@ def lib():
         "fdc_set_allocator": (C.c_int, [_P, ALLOC_FN, FREE_FN, _P]),
         "fdc_set_hu_table": (C.c_int, [_P, _P, _P, _P, _P, C.c_int, C.c_float]),
         "fdc_load_track_db": (C.c_int, [_P, _P, C.c_uint64, _P, C.c_uint32, _P, _P, C.c_uint32, _P]),
+        "fdc_load_track_db_file": (C.c_int, [_P, C.c_char_p, _P]),
         "fdc_load_phantom": (C.c_int, [_P, C.POINTER(C.c_int32), _P, C.c_int, C.c_int, C.c_int, _P, _P, _P]),
         "fdc_add_beam_spots": (C.c_int, [_P, C.c_int32, _P, C.c_uint32]),
         "fdc_run_histories": (C.c_int, [_P, _P, C.c_uint32, C.c_uint32, _P]),
@@ -263,6 +264,9 @@ class Context:
         _check(self.h, lib().fdc_load_track_db(self.h, steps.ctypes.data, steps.shape[0], off.ctypes.data,
                                                off.size - 1, be.ctypes.data, bf.ctypes.data, be.size,
                                                _stream(stream)))
+
+    def load_track_db_file(self, path, stream=None):
+        _check(self.h, lib().fdc_load_track_db_file(self.h, os.fsencode(path), _stream(stream)))
 
     def load_phantom(self, ph, stream=None):
         hu = np.ascontiguousarray(ph.hu, np.int16)

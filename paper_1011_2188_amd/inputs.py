@@ -172,6 +172,50 @@ def make_water_track_db(bin_energies_MeV, n_tracks_per_bin, seed, step_cm=STEP_C
                    track_off, bins, bin_first)
 
 
+DB_FILE_MAGIC = b"FDCTRKDB"
+_DB_HEADER = np.dtype([("magic", "S8"), ("version", "<u4"), ("n_bins", "<u4"), ("n_tracks", "<u4"),
+                       ("reserved", "<u4"), ("n_steps", "<u8"), ("db_seed", "<u8"), ("physics", "<f8", (8,))])
+assert _DB_HEADER.itemsize == 104
+
+
+def write_track_db_file(path, db, db_seed=0):
+    """Write a track database in the library's file layout: a 104-byte
+    little-endian header, then bin_E, bin_first, track_off and the step
+    records, packed."""
+    h = np.zeros(1, _DB_HEADER)
+    h["magic"] = DB_FILE_MAGIC
+    h["version"] = 1
+    h["n_bins"] = db.n_bins
+    h["n_tracks"] = db.n_tracks
+    h["n_steps"] = db.steps.shape[0]
+    h["db_seed"] = int(db_seed)
+    h["physics"] = [ALPHA, P_BK, K_BOHR, Z_OVER_A_WATER, X0_WATER, M_PROTON, STEP_CM, 0.0]
+    with open(path, "wb") as f:
+        f.write(h.tobytes())
+        f.write(np.ascontiguousarray(db.bin_E, "<f4").tobytes())
+        f.write(np.ascontiguousarray(db.bin_first, "<u4").tobytes())
+        f.write(np.ascontiguousarray(db.track_off, "<u8").tobytes())
+        f.write(np.ascontiguousarray(db.steps, "<f4").tobytes())
+
+
+def read_track_db_file(path):
+    """Read a file written by write_track_db_file back into a TrackDB."""
+    raw = np.fromfile(path, np.uint8)
+    h = raw[:_DB_HEADER.itemsize].view(_DB_HEADER)[0]
+    if bytes(h["magic"]) != DB_FILE_MAGIC or int(h["version"]) != 1:
+        raise ValueError("not a track database file")
+    nb, nt, ns = int(h["n_bins"]), int(h["n_tracks"]), int(h["n_steps"])
+    o = _DB_HEADER.itemsize
+    parts = []
+    for dt, n in (("<f4", nb), ("<u4", nb + 1), ("<u8", nt + 1), ("<f4", 4 * ns)):
+        size = np.dtype(dt).itemsize * n
+        parts.append(raw[o:o + size].view(dt).copy())
+        o += size
+    if o != raw.size:
+        raise ValueError("track database file size does not match its header")
+    return TrackDB(parts[3].reshape(ns, 4), parts[2], parts[0], parts[1])
+
+
 # --------------------------------------------------------------------------
 # phantoms
 # --------------------------------------------------------------------------

@@ -171,3 +171,33 @@ def test_allocator_hooks_rules(ctx):
     lib = F.lib()
     keep = F.ALLOC_FN(lambda n, u: None)
     assert lib.fdc_set_allocator(ctx.h, keep, F.FREE_FN(), None) == F.FDC_E_ARG
+
+
+def test_track_db_file_round_trip(ctx, tmp_path):
+    """The database file layout: written by inputs, read back bit for bit,
+    accepted by the library's file loader; damaged files are refused."""
+    db = _db(5)
+    path = tmp_path / "db.bin"
+    I.write_track_db_file(path, db, db_seed=1)
+    back = I.read_track_db_file(path)
+    for a in ("steps", "track_off", "bin_E", "bin_first"):
+        assert np.array_equal(getattr(back, a), getattr(db, a)) and getattr(back, a).dtype == getattr(db, a).dtype
+    raw = path.read_bytes()
+    assert len(raw) == 104 + 4 * 2 + 4 * 3 + 8 * 11 + 16 * db.steps.shape[0]
+    ctx.load_track_db_file(path)
+    p = ctx.load_phantom(I.water_phantom((4, 4, 4), 0.5))
+    ctx.add_beam_spots(p, I.spots([[0, 0, -1]], [[0, 0, 1]], [101.0], 0.3, 10))   # bins came from the file
+    _expect(F.FDC_E_RANGE, ctx.add_beam_spots, p, I.spots([[0, 0, -1]], [[0, 0, 1]], [106.0], 0.3, 1))
+    bad = tmp_path / "bad.bin"
+    bad.write_bytes(b"XXXXXXXX" + raw[8:])
+    assert "magic" in _expect(F.FDC_E_FORMAT, ctx.load_track_db_file, bad)
+    bad.write_bytes(raw[:-16])
+    _expect(F.FDC_E_FORMAT, ctx.load_track_db_file, bad)
+    bad.write_bytes(raw[:50])
+    _expect(F.FDC_E_FORMAT, ctx.load_track_db_file, bad)
+    steps = np.frombuffer(raw, np.uint8).copy()
+    steps[104 + 8 + 12 + 88 + 16 * 3: 104 + 8 + 12 + 88 + 16 * 3 + 4] = np.frombuffer(np.float32(0.0).tobytes(), np.uint8)
+    bad.write_bytes(steps.tobytes())                    # step 3 with dx = 0: the array checks apply
+    _expect(F.FDC_E_FORMAT, ctx.load_track_db_file, bad)
+    _expect(F.FDC_E_ARG, ctx.load_track_db_file, tmp_path / "missing.bin")
+    assert F.lib().fdc_load_track_db_file(ctx.h, None, None) == F.FDC_E_ARG

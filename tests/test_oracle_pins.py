@@ -12,6 +12,7 @@ from scipy import stats
 
 from oracle import oracle as O
 from paper_1011_2188_amd import inputs as I
+from paper_1011_2188_amd import workloads as W
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 FP = 2.0 ** 24
@@ -420,3 +421,170 @@ def test_sum_of_squares_rounding_several_energies():
     assert len({(i % 4096) >= 2048 for i in Ih}) == 2       # both rounding directions occur
     assert r["E"].ravel()[0] == 100 * sum(Ih)
     assert int(r["E2"].ravel()[0]) == 100 * sum(((i + 2048) >> 12) ** 2 for i in Ih)
+
+
+# ------------------------------------------------- voxel-walk tie-breaks ----
+# Hand-computed walks in a 4 x 4 x 4 water phantom of 1 cm voxels (origin at
+# 0): straight tracks (theta = 0) of 1 MeV steps, a spot of zero width.  Each
+# event is (kind, voxel, piece, exit axis); a step of WEL 1.5 cm crossing a
+# face after 1 cm deposits rint(2^24 * 1 / 1.5) = 11184811 before the face and
+# the remaining 5592405 after it.  Voxel index v = (k * 4 + j) * 4 + i.
+E1 = 16777216
+P23, P13 = 11184811, 5592405
+
+
+def _tie_db(dx, n_steps, dE=1.0):
+    steps = np.zeros((n_steps, 4), np.float32)
+    steps[:, 0] = dx
+    steps[:, 1] = dE
+    E = np.float32(dE * n_steps)
+    return I.TrackDB(steps, np.array([0, n_steps], np.uint64), np.array([E], np.float32),
+                     np.array([0, 1], np.uint32)), float(E)
+
+
+def _tie_run(pos, d, dx=1.5, n_steps=3):
+    db, E = _tie_db(dx, n_steps)
+    ph = I.Phantom(np.zeros((4, 4, 4), np.int16), np.ones(3, np.float32), np.zeros(3, np.float32))
+    sp = I.spots([pos], [d], [E], 0.0, 1)
+    ev, reason, ep = O.trace(db, ph, sp, 0, 0)
+    return ev, reason, ep, (db, ph, sp)
+
+
+def test_walk_ray_along_a_face_takes_the_upper_voxel():
+    """A ray along +x in the plane y = 1 (a voxel boundary, no y motion) walks
+    the voxels with y index 1; a step that ends exactly on a face crosses it in
+    that step (the next step starts in the entered voxel)."""
+    ev, reason, ep, _ = _tie_run([-1.0, 1.0, 2.5], [1.0, 0.0, 0.0])
+    got = [e[:4] for e in ev]
+    assert got == [(0, 36, P23, 0), (0, 37, P13, -1), (2, 0, 0, -1),
+                   (0, 37, P13, 0), (0, 38, P23, 0), (2, 1, 0, -1),       # step 2 ends on the x = 3 face
+                   (0, 39, P23, 0), (3, -1, 3 * E1 - (3 * P23 + 2 * P13), 0)]
+    assert [e[4] for e in ev if e[0] == 0] == [1.0, 0.5, 0.5, 1.0, 1.0]
+    assert reason == O.END_ESCAPE and ep.tolist() == [4.0, 1.0, 2.5]
+
+
+def test_walk_entry_on_the_far_face_moving_down():
+    """Entering through the x = 4 face moving -x starts in voxel i = 3 (a point
+    on a face belongs to the voxel entered); y = 2 and z = 0 are boundaries
+    with no motion along them: j = 2, k = 0."""
+    ev, reason, ep, _ = _tie_run([5.0, 2.0, 0.0], [-1.0, 0.0, 0.0])
+    got = [e[:4] for e in ev]
+    assert got == [(0, 11, P23, 0), (0, 10, P13, -1), (2, 0, 0, -1),
+                   (0, 10, P13, 0), (0, 9, P23, 0), (2, 1, 0, -1),
+                   (0, 8, P23, 0), (3, -1, P13, 0)]
+    assert reason == O.END_ESCAPE and ep.tolist() == [0.0, 2.0, 0.0]
+
+
+def test_walk_rays_along_an_axis_on_box_faces():
+    """On the low face of the box (x = 0, moving along y) the ray is inside;
+    on the high face (x = 4) it misses: the box is [o, o + n * voxel)."""
+    ev, reason, _, _ = _tie_run([0.0, -1.0, 0.5], [0.0, 1.0, 0.0])
+    assert [e[1] for e in ev if e[0] == 0][:2] == [0, 4] and reason == O.END_ESCAPE
+    ev, reason, _, _ = _tie_run([4.0, -1.0, 0.5], [0.0, 1.0, 0.0])
+    assert ev == [] and reason == O.END_MISS
+
+
+@pytest.mark.parametrize("d,seq", [
+    ((1.0, 1.0, 0.0), [32, 33, 37]),          # x before y
+    ((1.0, 0.0, 1.0), [32, 33, 49]),          # x before z
+    ((0.0, 1.0, 1.0), [32, 36, 52]),          # y before z
+    ((1.0, 1.0, 1.0), [32, 33, 37, 53]),      # x, then y, then z
+])
+def test_walk_simultaneous_crossings_go_x_then_y_then_z(d, seq):
+    """From the centre of voxel (0, 0, 2) along a diagonal the exit distances
+    tie: the faces are crossed in the order x, y, z, through intermediate voxels
+    that get a zero-length piece (no WEL, no deposit)."""
+    ev, _, _, _ = _tie_run([0.5, 0.5, 2.5], list(d), dx=3.0, n_steps=1)
+    vox = [e for e in ev if e[0] == 0]
+    assert [e[1] for e in vox[:len(seq)]] == seq
+    for e in vox[1:len(seq) - 1]:
+        assert e[4] <= 1e-12 and e[2] == 0                 # the intermediate voxels: zero length
+    assert vox[0][4] > 0.5 and vox[len(seq) - 1][4] > 0.5
+
+
+def test_walk_trace_agrees_with_the_tallies():
+    """The walk record is the replay itself: its pieces per voxel sum to the
+    energy tally of the same history, and zero pieces do not flush."""
+    ev, _, _, (db, ph, sp) = _tie_run([0.5, 0.5, 2.5], [1.0, 1.0, 1.0], dx=3.0, n_steps=1)
+    r = O.replay(db, ph, sp)
+    E = np.zeros(64, np.int64)
+    for k, v, piece, *_ in ev:
+        if k == 0:
+            E[v] += piece
+    assert np.array_equal(E, r["E"].ravel())
+    runs = [v for i, (k, v, piece, *_) in enumerate(ev) if k == 0 and piece]
+    assert r["flushes"] == len(runs)
+
+
+# -------------------------------------------- database physics, low energy ----
+@pytest.mark.parametrize("E,theta0_mrad,bohr_mev,stop_mev_cm", [
+    (150.0, 2.12, 0.101, 5.42),
+    (70.0, 4.52, 0.097, 9.75),
+    (20.0, 16.2, 0.094, 25.6),
+])
+def test_db_physics_closed_forms(E, theta0_mrad, bohr_mev, stop_mev_cm):
+    """Highland width, Bohr straggling and Bragg-Kleeman stopping power per
+    1 mm of water at 150, 70 and 20 MeV against values worked out by hand from
+    the textbook formulas (beta from the kinetic energy and the proton mass;
+    stopping power = 1 / (alpha p E^(p-1))).  At 20 MeV beta^2 = 0.0413, where a
+    wrong beta or momentum term moves every value by more than the tolerance."""
+    assert abs(I.highland_theta0(E, 0.1) * 1e3 - theta0_mrad) <= 0.006 * theta0_mrad
+    assert abs(I.bohr_sigma(E, 0.1) - bohr_mev) <= 0.006 * bohr_mev
+    s = 1.0 / (0.0022 * 1.77 * E ** 0.77)
+    assert abs(s - stop_mev_cm) <= 0.003 * stop_mev_cm
+    # the generator's mean loss over a 1 mm step (the range difference) lies
+    # between the stopping powers at the step's two ends times its length
+    E_end = I.energy_at_range(I.csda_range(E) - 0.1)
+    s_end = 1.0 / (0.0022 * 1.77 * E_end ** 0.77)
+    assert s * 0.1 < E - E_end < s_end * 0.1
+
+
+@pytest.mark.parametrize("Eb", [20.0, 70.0])
+def test_db_first_step_distributions_low_energy(Eb):
+    """The first step of 2000 tracks at 70 and 20 MeV: energy loss normal
+    around the Bragg-Kleeman mean with Bohr's width at the mid-step energy, and
+    the polar angle Rayleigh with Highland's width there."""
+    db = I.make_water_track_db([Eb], 2000, seed=11)
+    first = db.steps[db.track_off[:-1].astype(np.int64)]
+    R = I.csda_range(Eb)
+    Emid = I.energy_at_range(R - 0.05)
+    mean = Eb - I.energy_at_range(R - 0.1)
+    sig = I.bohr_sigma(Emid, 0.1)
+    z = (first[:, 1].astype(np.float64) - mean) / sig
+    assert stats.kstest(z, "norm").pvalue > 1e-3
+    th0 = I.highland_theta0(Emid, 0.1)
+    assert stats.kstest(first[:, 2] / th0, "rayleigh").pvalue > 1e-3
+    assert stats.kstest(first[:, 3] / np.pi, "uniform", args=(-1, 2)).pvalue > 1e-3
+    # the whole track: range and energy sum
+    L = np.add.reduceat(db.steps[:, 0].astype(np.float64), db.track_off[:-1].astype(np.int64))
+    S = np.add.reduceat(db.steps[:, 1].astype(np.float64), db.track_off[:-1].astype(np.int64))
+    assert abs(L.mean() / R - 1) < 5e-3
+    assert np.max(np.abs(S - Eb)) < 1e-4 * Eb
+
+
+def test_per_visit_squares_against_eq2_taken_literally():
+    """The squared-energy tally squares each voxel visit; Eq. (2) squares a
+    history's whole dose in a voxel.  The oracle computes both (the literal
+    one with a per-history voxel map): on the water pencil beam and the slab
+    the mean uncertainty differs by less than 0.05%, and the literal sum of
+    squares is not smaller overall (squares of sums exceed sums of squares up
+    to the 2^-12 MeV rounding of each term)."""
+    for (ph, sp, db), per in ((W.water_pencil(), 20_000), (W.slab(n_tracks=500), 800)):
+        r = O.replay(db, ph, sp, h_count=np.full(len(sp), per, np.uint64), exact_e2=True, table=O.ORACLE_HU_TABLE)
+        n = r["n_histories"]
+        _, _, _, vac = O.material(ph.hu)
+        vac = vac.reshape(ph.hu.shape)
+        d, v = O.dose_and_variance(r["E"], r["E2"], n, ph)
+        _, vx = O.dose_and_variance(r["E"], r["E2x"], n, ph)
+        u = O.mean_uncertainty(d, np.sqrt(np.maximum(v, 0)), vac)
+        ux = O.mean_uncertainty(d, np.sqrt(np.maximum(vx, 0)), vac)
+        assert 0.9999 <= ux / u <= 1.0005, (ux, u)
+        ratio = float(r["E2x"].sum()) / float(r["E2"].sum())
+        assert 0.99999 <= ratio <= 1.001
+    # one voxel holding every track: one visit per history, the two agree bit for bit
+    db = W.water_db(200)
+    ph = I.Phantom(np.zeros((1, 1, 1), np.int16), np.array([40.0, 40.0, 40.0], np.float32),
+                   np.array([-20.0, -20.0, 0.0], np.float32))
+    sp = I.spots([[0.0, 0.0, -1.0]], [[0.0, 0.0, 1.0]], [150.0], 0.3, 3000)
+    r = O.replay(db, ph, sp, exact_e2=True)
+    assert np.array_equal(r["E2"], r["E2x"]) and r["escaped"] == 0
