@@ -90,6 +90,16 @@ typedef struct {
     uint64_t n_histories; /* histories per fdc_run_histories call */
 } fdc_spot;
 
+/* One incident proton of a phase space (Section 2.3: the incident protons'
+ * positions, directions and energies may be read from a file): start point,
+ * direction (any length > 0) and kinetic energy.  32 bytes. */
+typedef struct {
+    float pos_cm[3];
+    float dir[3];
+    float energy_MeV;
+    float reserved;       /* 0 */
+} fdc_particle;
+
 typedef struct {
     uint64_t n_histories;  /* histories run on the plan since its last reset          */
     int64_t incident_fp;   /* sum of incident energies, 2^-24 MeV                      */
@@ -126,13 +136,14 @@ typedef struct {
     uint32_t source_order;      /* 0 = a wave unit takes 64 consecutive histories of a
                                    spot, which share one database track; 1 = the
                                    histories of each spot are processed in an order
-                                   sorted by start position (a Morton code of the
-                                   lateral offset, 256 x 256 cells over the spot's
-                                   width), each lane on its own
-                                   track: lanes of a wave start close together, which
-                                   lets the LDS cache merge deposits of broad fields.
-                                   Costs a sort per run (device memory about 24 B per
-                                   history); ignored by captured graphs.             */
+                                   sorted by start position (chunks of 16384 of a
+                                   spot's histories, each binned on up to 64 x 64
+                                   cells over the spot's width in Morton order), each
+                                   lane on its own track: lanes of a wave start close
+                                   together, which lets the LDS cache merge deposits
+                                   of broad fields.  Costs one ordering kernel per run
+                                   (a lane table of 4 B per history); captured graphs
+                                   capture it too.                                   */
     uint32_t reserved[2];
 } fdc_launch_config;
 
@@ -217,6 +228,35 @@ int fdc_load_phantom(fdc_ctx *ctx, int32_t *plan_out, const int16_t *hu, int nx,
  * (energy below the first or above the last bin energy), FDC_E_STATE (no
  * database loaded). */
 int fdc_add_beam_spots(fdc_ctx *ctx, int32_t plan, const fdc_spot *spots, uint32_t n);
+
+/* Append a phase space of n protons to a plan (Section 2.3: incident protons
+ * read from a file).  The protons are grouped by energy bin (the smallest bin
+ * energy >= the proton's energy), bins in increasing order, list order kept
+ * within a bin; each non-empty group becomes one source of the plan, numbered
+ * after the plan's sources so far (spots and earlier groups), whose histories
+ * per fdc_run_histories call are its protons, one pass: history h of a group
+ * of m protons is its proton h mod m, so later runs re-use the protons on new
+ * tracks.  Each proton starts at its own position (no lateral spread) along
+ * its own direction (the beam frame of its deflections is that direction's
+ * frame, as for a spot) and skips from its bin energy down to its own energy
+ * on the chosen track (Section 2.3, task 1); 64 consecutive histories of a
+ * group share one track.  The protons are copied to the device before the call
+ * returns.  Returns the number of sources added in *n_sources_out (may be
+ * NULL).  Errors: FDC_E_ARG (bad plan, NULL with n > 0, non-finite values,
+ * zero direction, reserved != 0), FDC_E_RANGE (an energy outside the bin
+ * energies), FDC_E_STATE (no database loaded), FDC_E_NOMEM, FDC_E_HIP. */
+int fdc_add_phase_space(fdc_ctx *ctx, int32_t plan, const fdc_particle *particles, uint64_t n,
+                        uint32_t *n_sources_out, void *hip_stream);
+
+/* The same from a phase-space file: a 32-byte little-endian header {char
+ * magic[8] = "FDCPHSP1"; uint32 version = 1; uint32 record_bytes = 32; uint64
+ * n; uint64 reserved = 0} followed by n fdc_particle records.  The file is
+ * read on the host and closed before the call returns.  Errors: as
+ * fdc_add_phase_space, plus FDC_E_ARG (NULL path, file cannot be opened) and
+ * FDC_E_FORMAT (bad magic, version or record size, a size that does not match
+ * the header, a short read). */
+int fdc_add_phase_space_file(fdc_ctx *ctx, int32_t plan, const char *path, uint32_t *n_sources_out,
+                             void *hip_stream);
 
 /* One pass of the method over n_plans plans in a single launch (Section 2.3:
  * every incident proton is an independent thread re-tracing a stored

@@ -174,6 +174,14 @@ typedef struct {
     hu_table tab;
     /* spots */
     const float *spot_pos, *spot_dir, *spot_E, *spot_sigma;
+    /* sources read from a phase-space list instead (Section 2.3: incident
+     * protons read from a file): source s with ps_count[s] > 0 is the protons
+     * ps_first[s] .. ps_first[s] + ps_count[s] - 1, each with its own position,
+     * direction and energy; history h of it is proton ps_first[s] + h mod
+     * ps_count[s] (a new pass over the list re-uses it with new tracks).
+     * NULL: every source is a spot. */
+    const uint64_t *ps_first, *ps_count;
+    const float *ps_pos, *ps_dir, *ps_E;
     /* run */
     uint32_t plan;
     uint64_t seed;
@@ -265,7 +273,9 @@ static int replay_history(const oracle_problem *P, uint32_t s, uint64_t h, oracl
     const uint32_t key[2] = {(uint32_t)P->seed, (uint32_t)(P->seed >> 32)};
 
     /* ---- task 1: database history, trajectory and start step ---------- */
-    double E_spot = P->spot_E[s];
+    const int listed = P->ps_count && P->ps_count[s] > 0; /* a proton from the phase-space list */
+    const uint64_t pi = listed ? P->ps_first[s] + h % P->ps_count[s] : 0;
+    double E_spot = listed ? P->ps_E[pi] : P->spot_E[s];
     uint32_t b = 0;
     while (b < P->n_bins && (double)P->bin_E[b] < E_spot) ++b;
     uint32_t n_b = P->bin_first[b + 1] - P->bin_first[b];
@@ -298,14 +308,17 @@ static int replay_history(const oracle_problem *P, uint32_t s, uint64_t h, oracl
     ctr[0] = (uint32_t)h; ctr[1] = (uint32_t)(h >> 32); ctr[2] = s;
     ctr[3] = (P->plan << 4) | TAG_SRC;
     oracle_philox4x32_10(ctr, key, x);
-    double sig = P->spot_sigma[s];
+    /* a listed proton has no lateral spread: its own position and direction */
+    double sig = listed ? 0.0 : P->spot_sigma[s];
     /* Gaussian: Box-Muller radius; disk: the radius whose square is uniform */
     double r = sig >= 0.0 ? sqrt(-2.0 * log(oracle_uniform(x[0]))) : sqrt(oracle_uniform(x[0]));
     double ang = 2.0 * M_PI * oracle_uniform(x[1]);
     double n1 = r * cos(ang), n2 = r * sin(ang);
     double phi0 = (P->flags & FLAG_ROTATE) ? 2.0 * M_PI * oracle_uniform(x[2]) : 0.0;
 
-    double d[3] = {P->spot_dir[3 * s], P->spot_dir[3 * s + 1], P->spot_dir[3 * s + 2]};
+    const float *src_dir = listed ? P->ps_dir + 3 * pi : P->spot_dir + 3 * s;
+    const float *src_pos = listed ? P->ps_pos + 3 * pi : P->spot_pos + 3 * s;
+    double d[3] = {src_dir[0], src_dir[1], src_dir[2]};
     double dl = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
     d[0] /= dl; d[1] /= dl; d[2] /= dl;
     double e1[3], e2[3];
@@ -314,7 +327,7 @@ static int replay_history(const oracle_problem *P, uint32_t s, uint64_t h, oracl
     for (int a = 0; a < 3; ++a) { M[a][0] = e1[a]; M[a][1] = e2[a]; M[a][2] = d[a]; }
     double pos[3];
     for (int a = 0; a < 3; ++a)
-        pos[a] = (double)P->spot_pos[3 * s + a] + fabs(sig) * (n1 * e1[a] + n2 * e2[a]);
+        pos[a] = (double)src_pos[a] + fabs(sig) * (n1 * e1[a] + n2 * e2[a]);
 
     if (T) T->incident += I_h;
 
@@ -479,6 +492,29 @@ static void setup(oracle_problem *P, const float *steps, const uint64_t *track_o
     P->spot_pos = spot_pos; P->spot_dir = spot_dir; P->spot_E = spot_E; P->spot_sigma = spot_sigma;
     P->plan = plan; P->seed = seed; P->R = R; P->flags = flags;
     P->trace = NULL;
+    P->ps_first = P->ps_count = NULL;
+    P->ps_pos = P->ps_dir = P->ps_E = NULL;
+}
+
+/* Phase-space sources for the next oracle_replay_e2x / oracle_endpoints /
+ * oracle_trace_history call on this thread (see oracle_problem); NULL arrays
+ * clear them.  The arrays must stay valid until that call returns. */
+static _Thread_local struct {
+    const uint64_t *first, *count;
+    const float *pos, *dir, *E;
+} g_ps;
+
+void oracle_set_phase_space(const uint64_t *first, const uint64_t *count, const float *pos, const float *dir,
+                            const float *E)
+{
+    g_ps.first = first; g_ps.count = count; g_ps.pos = pos; g_ps.dir = dir; g_ps.E = E;
+}
+
+static void use_phase_space(oracle_problem *P)
+{
+    if (!g_ps.count) return;
+    P->ps_first = g_ps.first; P->ps_count = g_ps.count;
+    P->ps_pos = g_ps.pos; P->ps_dir = g_ps.dir; P->ps_E = g_ps.E;
 }
 
 /*
@@ -534,6 +570,7 @@ int oracle_replay_e2x(const float *steps, const uint64_t *track_off, uint32_t n_
     setup(&P, steps, track_off, n_tracks, bin_E, bin_first, n_bins, hu, dims, vox, org,
           hu_pts, rho, rsp, rscp, n_pts, vacuum_below_hu, spot_pos, spot_dir, spot_E, spot_sigma,
           plan, seed, R, flags);
+    use_phase_space(&P);
     size_t nvox = (size_t)dims[0] * dims[1] * dims[2];
     uint64_t *prefix = (uint64_t *)malloc(sizeof(uint64_t) * (n_spots + 1));
     prefix[0] = 0;
@@ -620,6 +657,7 @@ int oracle_endpoints(const float *steps, const uint64_t *track_off, uint32_t n_t
     setup(&P, steps, track_off, n_tracks, bin_E, bin_first, n_bins, hu, dims, vox, org,
           hu_pts, rho, rsp, rscp, n_pts, vacuum_below_hu, spot_pos, spot_dir, spot_E, spot_sigma,
           plan, seed, R, flags);
+    use_phase_space(&P);
     for (uint32_t i = 0; i < n; ++i)
         reason[i] = replay_history(&P, s, h0 + i, NULL, xyz + 3 * i);
     return 0;
@@ -647,6 +685,7 @@ int oracle_trace_history(const float *steps, const uint64_t *track_off, uint32_t
     setup(&P, steps, track_off, n_tracks, bin_E, bin_first, n_bins, hu, dims, vox, org,
           hu_pts, rho, rsp, rscp, n_pts, vacuum_below_hu, spot_pos, spot_dir, spot_E, spot_sigma,
           plan, seed, R, flags);
+    use_phase_space(&P);
     oracle_trace tr = {ev, evd, cap, 0};
     P.trace = &tr;
     *reason = replay_history(&P, s, h, NULL, endpoint);

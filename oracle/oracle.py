@@ -153,15 +153,65 @@ def _common(db, ph, sp, table):
     return arrs, args
 
 
+def phase_space_sources(pos, dirs, energies, bin_E, first_source):
+    """The sources a list of incident protons (Section 2.3: the phase space
+    read from a file) becomes: the protons grouped by energy bin (the smallest
+    bin energy >= the proton's), bins in increasing order, protons in list order
+    within a bin.  Returns a dict for replay(..., phase_space=...): per source
+    index (first_source onward, after the plan's spots) the first proton and
+    count in the regrouped arrays pos, dir, E."""
+    pos = np.asarray(pos, np.float32).reshape(-1, 3)
+    dirs = np.asarray(dirs, np.float32).reshape(-1, 3)
+    E = np.asarray(energies, np.float32).ravel()
+    bins = np.asarray(bin_E, np.float32)
+    b = np.array([int(np.searchsorted(bins, e, side="left")) for e in E], np.int64)   # first bin >= E
+    order = np.argsort(b, kind="stable")
+    groups = [(int(v), int(np.count_nonzero(b == v))) for v in np.unique(b)]
+    first = np.zeros(first_source + len(groups), np.uint64)
+    count = np.zeros(first_source + len(groups), np.uint64)
+    o = 0
+    for k, (_, n) in enumerate(groups):
+        first[first_source + k] = o
+        count[first_source + k] = n
+        o += n
+    return dict(first=first, count=count, pos=np.ascontiguousarray(pos[order]),
+                dir=np.ascontiguousarray(dirs[order]), E=np.ascontiguousarray(E[order]),
+                bins=[g for g, _ in groups])
+
+
+class _PhaseSpace:
+    """Installs phase-space sources for the oracle calls inside the block."""
+
+    def __init__(self, ps):
+        self.ps = ps
+
+    def __enter__(self):
+        if self.ps is not None:
+            ps = self.ps
+            self.keep = [np.ascontiguousarray(ps["first"], np.uint64), np.ascontiguousarray(ps["count"], np.uint64),
+                         np.ascontiguousarray(ps["pos"], np.float32), np.ascontiguousarray(ps["dir"], np.float32),
+                         np.ascontiguousarray(ps["E"], np.float32)]
+            f, c, p, d, e = self.keep
+            lib().oracle_set_phase_space(_p(f, C.c_uint64), _p(c, C.c_uint64), _p(p, C.c_float),
+                                         _p(d, C.c_float), _p(e, C.c_float))
+
+    def __exit__(self, *a):
+        if self.ps is not None:
+            lib().oracle_set_phase_space(None, None, None, None, None)
+
+
 def replay(db, ph, sp, h_begin=None, h_count=None, plan=0, seed=1, R=64, flags=FLAG_VARIANCE,
-           threads=None, table=None, exact_e2=False):
+           threads=None, table=None, exact_e2=False, phase_space=None):
     """Replay histories h_begin[i] .. h_begin[i]+h_count[i]-1 of every spot i.
 
     Returns a dict with the int64 energy tally E, the uint64 sum-of-squares tally
     E2 (x-fastest, shape [nz,ny,nx]), incident/escaped energy (fixed point) and
     the work counters (steps, visits, vacuum_visits, flushes).  With exact_e2
     also E2x: each history's whole deposit in a voxel squared once (Eq. (2)
-    taken literally; E2 squares every visit on its own)."""
+    taken literally; E2 squares every visit on its own).  phase_space (from
+    phase_space_sources): sources past the spots are listed protons; sp must
+    then hold one (placeholder) row per source and h_count give each source's
+    histories."""
     arrs, args = _common(db, ph, sp, table)
     ns = len(sp)
     hb = np.zeros(ns, np.uint64) if h_begin is None else np.ascontiguousarray(h_begin, np.uint64)
@@ -173,10 +223,11 @@ def replay(db, ph, sp, h_begin=None, h_count=None, plan=0, seed=1, R=64, flags=F
     stats = np.zeros(6, np.int64)
     E2x = np.zeros(nx * ny * nz, np.uint64) if exact_e2 else None
     nthreads = threads or int(os.environ.get("ORACLE_THREADS", min(os.cpu_count() or 1, 16)))
-    rc = lib().oracle_replay_e2x(*args, C.c_uint32(ns), _p(hb, C.c_uint64), _p(hc, C.c_uint64),
-                                 C.c_uint32(plan), C.c_uint64(seed), C.c_uint32(R), C.c_uint32(flags),
-                                 C.c_int(nthreads), _p(E, C.c_int64), _p(E2, C.c_uint64),
-                                 _p(stats, C.c_int64), _p(E2x, C.c_uint64) if exact_e2 else None)
+    with _PhaseSpace(phase_space):
+        rc = lib().oracle_replay_e2x(*args, C.c_uint32(ns), _p(hb, C.c_uint64), _p(hc, C.c_uint64),
+                                     C.c_uint32(plan), C.c_uint64(seed), C.c_uint32(R), C.c_uint32(flags),
+                                     C.c_int(nthreads), _p(E, C.c_int64), _p(E2, C.c_uint64),
+                                     _p(stats, C.c_int64), _p(E2x, C.c_uint64) if exact_e2 else None)
     if rc != 0:
         raise RuntimeError("oracle replay failed to conserve energy")
     extra = dict(E2x=E2x.reshape(nz, ny, nx)) if exact_e2 else {}
@@ -186,14 +237,15 @@ def replay(db, ph, sp, h_begin=None, h_count=None, plan=0, seed=1, R=64, flags=F
                 n_histories=int(hc.sum()), threads=nthreads)
 
 
-def endpoints(db, ph, sp, spot, h0, n, plan=0, seed=1, R=64, flags=0, table=None):
+def endpoints(db, ph, sp, spot, h0, n, plan=0, seed=1, R=64, flags=0, table=None, phase_space=None):
     """End point (cm, float64 [n,3]) and end reason of histories h0..h0+n-1 of a spot."""
     arrs, args = _common(db, ph, sp, table)
     xyz = np.zeros((n, 3), np.float64)
     reason = np.zeros(n, np.int32)
-    lib().oracle_endpoints(*args, C.c_uint32(spot), C.c_uint64(h0), C.c_uint32(n), C.c_uint32(plan),
-                           C.c_uint64(seed), C.c_uint32(R), C.c_uint32(flags),
-                           _p(xyz, C.c_double), _p(reason, C.c_int32))
+    with _PhaseSpace(phase_space):
+        lib().oracle_endpoints(*args, C.c_uint32(spot), C.c_uint64(h0), C.c_uint32(n), C.c_uint32(plan),
+                               C.c_uint64(seed), C.c_uint32(R), C.c_uint32(flags),
+                               _p(xyz, C.c_double), _p(reason, C.c_int32))
     if np.any(reason < 0):
         raise RuntimeError("oracle replay failed to conserve energy")
     return xyz, reason

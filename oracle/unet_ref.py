@@ -185,9 +185,10 @@ def forward(P, x, bf16=False):
     return y, c
 
 
-def backward(c, gy, bf16=False):
+def backward(c, gy, bf16=False, acts=None):
     """Gradients (dict name -> (gw, gb)) of a scalar whose gradient wrt the
-    output y is gy."""
+    output y is gy.  With a dict `acts`, it also receives the activation
+    gradients (gd1 ... ge1a, as stored: masked by the ReLU, rounded)."""
     r = bf16_round if bf16 else (lambda a: a)
     W_ = c["W"]
     G = {}
@@ -219,6 +220,9 @@ def backward(c, gy, bf16=False):
     ge1a, *G["enc1b"] = conv3_backward(c["e1a"], W_["enc1b"][0], ge1)
     ge1a = r(ge1a * (c["e1a"] > 0))
     _, *G["enc1a"] = conv3_backward(c["x"], W_["enc1a"][0], ge1a)
+    if acts is not None:
+        acts.update(gd1=gd1, gd1a=gd1a, gc1=gc1, gd2=gd2, gd2a=gd2a, gc2=gc2, gm=gm, gma=gma, gp2=r(gp2),
+                    ge2=ge2, ge2a=ge2a, gp1=r(gp1), ge1=ge1, ge1a=ge1a)
     return {k: (gw, gb) for k, (gw, gb) in G.items()}
 
 

@@ -34,6 +34,18 @@ struct PlanHost {
     std::vector<uint64_t> h_next;
     uint64_t n_hist = 0;
     bool var_complete = true;
+    // per source (parallel to spots): a spot, or a group of listed protons of
+    // one energy bin (fdc_add_phase_space); its spots entry then carries the
+    // bin energy, the first proton's start and direction, and the group size
+    struct Source {
+        uint32_t kind = 0;            // 0 spot, 1 listed protons
+        uint32_t bin = 0;
+        uint64_t first = 0, count = 0;
+        uint64_t db_serial = 0;       // the database the grouping was made for
+    };
+    std::vector<Source> src;
+    float4 *ps = nullptr;             // listed protons of the plan, two float4 each
+    uint64_t ps_n = 0;
 };
 
 // the default material table: synthetic piecewise-linear constants
@@ -68,6 +80,7 @@ struct fdc_ctx {
     std::vector<float> bin_E;
     std::vector<uint32_t> bin_first_h;
     uint32_t n_tracks = 0, n_bins = 0;
+    uint64_t db_serial = 0;           // counts database loads
 
     // material table
     std::vector<double> table;   // rows of (hu, rho, rsp, rscp)
@@ -96,14 +109,8 @@ struct fdc_ctx {
     unsigned long long *d_queue = nullptr;
 
     // processing order by start position (launch config source_order = 1)
-    unsigned long long *d_keys = nullptr;    // 2 x histories
-    size_t keys_cap = 0;
-    uint32_t *d_vals = nullptr;              // 2 x histories
-    size_t vals_cap = 0;
     uint32_t *d_order = nullptr;             // units x 64
     size_t order_cap = 0;
-    unsigned char *d_sort_tmp = nullptr;
-    size_t sort_tmp_cap = 0;
 
     // read-back scratch
     double *d_dose = nullptr, *d_var = nullptr;
@@ -125,6 +132,7 @@ struct fdc_graph {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     WorkItem *d_items = nullptr;
+    uint32_t *d_order = nullptr;             // start-position order table (source_order 1)
     std::vector<int32_t> plans;
     uint32_t flags = 0;
     bool reset = false;
@@ -184,6 +192,11 @@ int rebuild_lut(fdc_ctx *ctx)
     if (!dt) return fail(ctx, FDC_E_NOMEM, "material table: device allocation failed");
     hipError_t e = hipMemcpy(dt, ctx->table.data(), ctx->table.size() * sizeof(double), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = launch_build_lut(dt, n, ctx->vacuum_below, ctx->lut, ctx->rho_lut, nullptr);
+    // which voxels are vacuum may have changed: every plan's vacuum-skip bits follow the table
+    for (size_t p = 0; p < ctx->plans.size() && e == hipSuccess; ++p) {
+        const PlanHost &P = ctx->plans[p];
+        if (P.idx) e = launch_vacuum_skip(P.idx, ctx->lut, P.n[0], P.n[1], P.n[2], nullptr);
+    }
     if (e == hipSuccess) e = hipDeviceSynchronize();
     dfree(ctx, dt);
     if (e != hipSuccess) return fail(ctx, FDC_E_HIP, "material table: %s", hipGetErrorString(e));
@@ -249,6 +262,7 @@ DevSpot make_dev_spot(const fdc_ctx *ctx, const fdc_spot &s, uint32_t plan, uint
     d.plan = plan;
     d.spot = idx;
     d.skip = to_fp(ctx->bin_E[b]) - to_fp(s.energy_MeV);
+    d.n_hist = s.n_histories;
     return d;
 }
 
@@ -263,7 +277,20 @@ int ensure_spots(fdc_ctx *ctx)
             const fdc_spot &s = ctx->plans[p].spots[j];
             int rc = check_spot(ctx, s);
             if (rc) return rc;
-            all.push_back(make_dev_spot(ctx, s, (uint32_t)p, (uint32_t)j));
+            DevSpot d = make_dev_spot(ctx, s, (uint32_t)p, (uint32_t)j);
+            const PlanHost::Source &src = ctx->plans[p].src[j];
+            d.bin_fp = to_fp(ctx->bin_E[d.bin]);
+            if (src.kind) {
+                if (src.db_serial != ctx->db_serial || src.bin >= ctx->n_bins)
+                    return fail(ctx, FDC_E_STATE, "plan %zu: a phase space was grouped for another track database; "
+                                "add it again", p);
+                d.kind = 1;
+                d.bin = src.bin;
+                d.bin_fp = to_fp(ctx->bin_E[src.bin]);
+                d.ps_first = src.first;
+                d.ps_count = src.count;
+            }
+            all.push_back(d);
         }
     }
     ctx->spot_base[ctx->plans.size()] = (uint32_t)all.size();
@@ -304,6 +331,7 @@ int ensure_plans(fdc_ctx *ctx)
         d.E = P.E;
         d.E2 = P.E2;
         d.acc = P.acc;
+        d.ps = P.ps;
         for (int q = 0; q < 3; ++q) {
             d.n[q] = P.n[q];
             d.vox[q] = P.vox[q];
@@ -429,7 +457,12 @@ int fdc_create(fdc_ctx **out, int hip_device, uint64_t seed, uint32_t reuse_R)
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, hip_device) == hipSuccess) ctx->cus = prop.multiProcessorCount;
     if (hipEventCreateWithFlags(&ctx->items_ev, hipEventDisableTiming) != hipSuccess) { delete ctx; return FDC_E_HIP; }
-    if (prepare_lds_kernels() != hipSuccess) { (void)hipEventDestroy(ctx->items_ev); delete ctx; return FDC_E_HIP; }
+    if (prepare_lds_kernels() != hipSuccess) {
+        (void)hipGetLastError();
+        (void)hipEventDestroy(ctx->items_ev);
+        delete ctx;
+        return FDC_E_HIP;
+    }
     *out = ctx;
     return FDC_OK;
 }
@@ -441,13 +474,13 @@ int fdc_destroy(fdc_ctx *ctx)
     (void)hipSetDevice(ctx->device);
     (void)hipDeviceSynchronize();
     for (PlanHost &P : ctx->plans) {
-        dfree(ctx, P.idx); dfree(ctx, P.E); dfree(ctx, P.E2); dfree(ctx, P.acc);
+        dfree(ctx, P.idx); dfree(ctx, P.E); dfree(ctx, P.E2); dfree(ctx, P.acc); dfree(ctx, P.ps);
     }
     dfree(ctx, ctx->steps); dfree(ctx, ctx->track_off); dfree(ctx, ctx->track_T);
     dfree(ctx, ctx->bin_first);
     dfree(ctx, ctx->lut); dfree(ctx, ctx->rho_lut);
     dfree(ctx, ctx->d_plans); dfree(ctx, ctx->d_spots); dfree(ctx, ctx->d_items); dfree(ctx, ctx->d_queue);
-    dfree(ctx, ctx->d_keys); dfree(ctx, ctx->d_vals); dfree(ctx, ctx->d_order); dfree(ctx, ctx->d_sort_tmp);
+    dfree(ctx, ctx->d_order);
     dfree(ctx, ctx->d_hnext);
     if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
     dfree(ctx, ctx->d_dose); dfree(ctx, ctx->d_var);
@@ -561,6 +594,7 @@ int fdc_load_track_db(fdc_ctx *ctx, const fdc_step *steps, uint64_t n_steps, con
         ctx->bin_first_h.assign(bin_first, bin_first + n_bins + 1);
         ctx->n_tracks = n_tracks;
         ctx->n_bins = n_bins;
+        ctx->db_serial++;
         ctx->spots_dirty = true;
         return FDC_OK;
     }
@@ -598,6 +632,7 @@ int fdc_load_track_db(fdc_ctx *ctx, const fdc_step *steps, uint64_t n_steps, con
     ctx->bin_first_h.assign(bin_first, bin_first + n_bins + 1);
     ctx->n_tracks = n_tracks;
     ctx->n_bins = n_bins;
+    ctx->db_serial++;
     ctx->spots_dirty = true;
     ctx->gen++;
     return FDC_OK;
@@ -701,6 +736,7 @@ int fdc_load_phantom(fdc_ctx *ctx, int32_t *plan_out, const int16_t *hu, int nx,
     hipStream_t s = S(hip_stream);
     hipError_t e = hipMemcpyAsync(d_hu, hu, nvox * sizeof(int16_t), hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = launch_hu_to_index(d_hu, P.idx, nvox, s);
+    if (e == hipSuccess) e = launch_vacuum_skip(P.idx, ctx->lut, nx, ny, nz, s);
     if (e == hipSuccess) e = hipMemsetAsync(P.E, 0, nvox * 8, s);
     if (e == hipSuccess) e = hipMemsetAsync(P.E2, 0, nvox * 8, s);
     if (e == hipSuccess) e = hipMemsetAsync(P.acc, 0, 32, s);
@@ -729,9 +765,145 @@ int fdc_add_beam_spots(fdc_ctx *ctx, int32_t plan, const fdc_spot *spots, uint32
     }
     PlanHost &P = ctx->plans[plan];
     P.spots.insert(P.spots.end(), spots, spots + n);
+    P.src.resize(P.spots.size());
     P.h_next.resize(P.spots.size(), 0);
     ctx->spots_dirty = true;
     return FDC_OK;
+}
+
+int fdc_add_phase_space(fdc_ctx *ctx, int32_t plan, const fdc_particle *particles, uint64_t n,
+                        uint32_t *n_sources_out, void *hip_stream)
+{
+    if (!ctx) return FDC_E_ARG;
+    if (n_sources_out) *n_sources_out = 0;
+    if (!valid_plan(ctx, plan)) return fail(ctx, FDC_E_ARG, "phase space: no plan %d", plan);
+    if (n && !particles) return fail(ctx, FDC_E_ARG, "phase space: NULL array");
+    if (ctx->n_bins == 0) return fail(ctx, FDC_E_STATE, "phase space: load a track database first");
+    if (n > (1ull << 40)) return fail(ctx, FDC_E_ARG, "phase space: too many protons");
+    std::vector<uint32_t> bin;
+    try {
+        bin.resize(n);
+    } catch (const std::bad_alloc &) {
+        return fail(ctx, FDC_E_NOMEM, "phase space: host buffers");
+    }
+    for (uint64_t i = 0; i < n; ++i) {
+        const fdc_particle &q = particles[i];
+        if (!finite3(q.pos_cm) || !finite3(q.dir) || !std::isfinite(q.energy_MeV))
+            return fail(ctx, FDC_E_ARG, "phase space: proton %llu has a non-finite field", (unsigned long long)i);
+        if (q.dir[0] == 0.f && q.dir[1] == 0.f && q.dir[2] == 0.f)
+            return fail(ctx, FDC_E_ARG, "phase space: proton %llu has a zero direction", (unsigned long long)i);
+        if (q.reserved != 0.f) return fail(ctx, FDC_E_ARG, "phase space: proton %llu: reserved field not 0",
+                                           (unsigned long long)i);
+        const int b = spot_bin(ctx, q.energy_MeV);
+        if (b < 0 || !(q.energy_MeV >= ctx->bin_E[0]))
+            return fail(ctx, FDC_E_RANGE, "phase space: proton %llu energy %g MeV outside the bins [%g, %g]",
+                        (unsigned long long)i, (double)q.energy_MeV, (double)ctx->bin_E[0],
+                        (double)ctx->bin_E.back());
+        bin[i] = (uint32_t)b;
+    }
+    PlanHost &P = ctx->plans[plan];
+    // protons grouped by bin (bins ascending, list order within a bin)
+    std::vector<uint64_t> order;
+    std::vector<float4> host;
+    try {
+        order.resize(n);
+        host.resize(2 * n);
+    } catch (const std::bad_alloc &) {
+        return fail(ctx, FDC_E_NOMEM, "phase space: host buffers");
+    }
+    for (uint64_t i = 0; i < n; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](uint64_t x, uint64_t y) { return bin[x] < bin[y]; });
+    for (uint64_t k = 0; k < n; ++k) {
+        const fdc_particle &q = particles[order[k]];
+        host[2 * k] = make_float4(q.pos_cm[0], q.pos_cm[1], q.pos_cm[2], q.energy_MeV);
+        host[2 * k + 1] = make_float4(q.dir[0], q.dir[1], q.dir[2], 0.f);
+    }
+    if (!ctx->dry && n) {
+        HIPCHK(hipSetDevice(ctx->device));
+        float4 *d = dalloc_n<float4>(ctx, 2 * (P.ps_n + n));
+        if (!d) return fail(ctx, FDC_E_NOMEM, "phase space: device allocation of %llu protons failed",
+                            (unsigned long long)(P.ps_n + n));
+        hipStream_t s = S(hip_stream);
+        hipError_t e = hipSuccess;
+        if (P.ps_n) e = hipMemcpyAsync(d, P.ps, 2 * P.ps_n * sizeof(float4), hipMemcpyDeviceToDevice, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(d + 2 * P.ps_n, host.data(), 2 * n * sizeof(float4),
+                                                hipMemcpyHostToDevice, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e == hipSuccess) e = hipDeviceSynchronize();     // the old list may be read by earlier work
+        if (e != hipSuccess) {
+            dfree(ctx, d);
+            return fail(ctx, FDC_E_HIP, "phase space upload: %s", hipGetErrorString(e));
+        }
+        dfree(ctx, P.ps);
+        P.ps = d;
+        ctx->plans_dirty = true;
+    }
+    uint32_t added = 0;
+    for (uint64_t k = 0; k < n;) {
+        uint64_t m = k;
+        while (m < n && bin[order[m]] == bin[order[k]]) ++m;
+        const fdc_particle &q = particles[order[k]];
+        fdc_spot sp{};
+        for (int a = 0; a < 3; ++a) { sp.pos_cm[a] = q.pos_cm[a]; sp.dir[a] = q.dir[a]; }
+        sp.energy_MeV = ctx->bin_E[bin[order[k]]];
+        sp.sigma_cm = 0.f;
+        sp.n_histories = m - k;
+        PlanHost::Source src;
+        src.kind = 1;
+        src.bin = bin[order[k]];
+        src.first = P.ps_n + k;
+        src.count = m - k;
+        src.db_serial = ctx->db_serial;
+        P.spots.push_back(sp);
+        P.src.push_back(src);
+        ++added;
+        k = m;
+    }
+    P.ps_n += n;
+    P.h_next.resize(P.spots.size(), 0);
+    ctx->spots_dirty = true;
+    if (n_sources_out) *n_sources_out = added;
+    return FDC_OK;
+}
+
+int fdc_add_phase_space_file(fdc_ctx *ctx, int32_t plan, const char *path, uint32_t *n_sources_out,
+                             void *hip_stream)
+{
+    if (!ctx) return FDC_E_ARG;
+    if (n_sources_out) *n_sources_out = 0;
+    if (!path) return fail(ctx, FDC_E_ARG, "phase space file: NULL path");
+    FILE *f = std::fopen(path, "rb");
+    if (!f) return fail(ctx, FDC_E_ARG, "phase space file: cannot open %s", path);
+    struct {
+        char magic[8];
+        uint32_t version, record_bytes;
+        uint64_t n, reserved;
+    } h;
+    static_assert(sizeof(h) == 32, "phase space header layout");
+    long long size = -1;
+    if (std::fseek(f, 0, SEEK_END) == 0) size = std::ftell(f);
+    std::rewind(f);
+    if (std::fread(&h, sizeof h, 1, f) != 1) { std::fclose(f); return fail(ctx, FDC_E_FORMAT, "phase space file: short header"); }
+    if (std::memcmp(h.magic, "FDCPHSP1", 8) != 0 || h.version != 1 || h.record_bytes != sizeof(fdc_particle)) {
+        std::fclose(f);
+        return fail(ctx, FDC_E_FORMAT, "phase space file: bad magic, version or record size");
+    }
+    if (h.n > (1ull << 40) || size < 0 || (unsigned long long)size != sizeof h + h.n * sizeof(fdc_particle)) {
+        std::fclose(f);
+        return fail(ctx, FDC_E_FORMAT, "phase space file: %lld bytes do not hold the %llu protons of its header",
+                    size, (unsigned long long)h.n);
+    }
+    std::vector<fdc_particle> q;
+    try {
+        q.resize(h.n);
+    } catch (const std::bad_alloc &) {
+        std::fclose(f);
+        return fail(ctx, FDC_E_NOMEM, "phase space file: host buffer");
+    }
+    const bool ok = std::fread(q.data(), sizeof(fdc_particle), q.size(), f) == q.size();
+    std::fclose(f);
+    if (!ok) return fail(ctx, FDC_E_FORMAT, "phase space file: short read");
+    return fdc_add_phase_space(ctx, plan, q.data(), h.n, n_sources_out, hip_stream);
 }
 
 static int validate_run(fdc_ctx *ctx, const int32_t *plans, uint32_t n_plans, uint32_t flags, uint64_t launches)
@@ -773,9 +945,9 @@ static void account_run(fdc_ctx *ctx, const int32_t *plans, uint32_t n_plans, ui
 }
 
 static unsigned long long build_items(const fdc_ctx *ctx, const int32_t *plans, uint32_t n_plans,
-                                      std::vector<WorkItem> &items)
+                                      std::vector<WorkItem> &items, uint32_t *n_chunks = nullptr)
 {
-    unsigned long long units = 0, hist = 0;
+    unsigned long long units = 0, hist = 0, chunks = 0;
     items.clear();
     for (uint32_t i = 0; i < n_plans; ++i) {
         const PlanHost &P = ctx->plans[plans[i]];
@@ -789,31 +961,35 @@ static unsigned long long build_items(const fdc_ctx *ctx, const int32_t *plans, 
             w.first = hist;
             hist += n;
             w.gspot = ctx->spot_base[plans[i]] + (uint32_t)j;
+            w.chunk0 = (uint32_t)chunks;
             items.push_back(w);
             units += units_for(n);
+            chunks += source_order_chunks(n);
         }
     }
+    if (n_chunks) *n_chunks = (uint32_t)std::min<unsigned long long>(chunks, 0xFFFFFFFFull);
     return units;
 }
 
-// the run's processing order by start position: keys, sort, per-unit table
-// (enqueued on s after the work table's upload)
-static int enqueue_source_order(fdc_ctx *ctx, const std::vector<WorkItem> &items, unsigned long long units, hipStream_t s)
+// the run's processing order by start position (enqueued on s after the
+// work table's upload): the per-unit lane table of `units` units, into *order
+// grown to fit
+static int check_source_order(fdc_ctx *ctx, const std::vector<WorkItem> &items)
 {
-    unsigned long long n_total = 0;
+    unsigned long long chunks = 0;
     for (const WorkItem &w : items) {
         if (w.n >= 0xFFFFFFFFull) return fail(ctx, FDC_E_ARG, "run: source_order needs fewer than 2^32 histories per spot");
-        n_total += w.n;
+        chunks += source_order_chunks(w.n);
     }
-    if (n_total >= 0x7FFFFFFFull) return fail(ctx, FDC_E_ARG, "run: source_order needs fewer than 2^31 histories per run");
-    const size_t tmp = source_order_temp_bytes(n_total, (uint32_t)items.size());
-    if (!grow(ctx, ctx->d_keys, ctx->keys_cap, 2 * n_total, s) || !grow(ctx, ctx->d_vals, ctx->vals_cap, 2 * n_total, s) ||
-        !grow(ctx, ctx->d_order, ctx->order_cap, units * kWave, s) ||
-        !grow(ctx, ctx->d_sort_tmp, ctx->sort_tmp_cap, tmp, s))
-        return fail(ctx, FDC_E_NOMEM, "run: source order buffers");
-    HIPCHK(launch_source_order(ctx->d_items, (uint32_t)items.size(), n_total, units, ctx->d_spots, ctx->d_hnext,
-                               (uint32_t)ctx->seed, (uint32_t)(ctx->seed >> 32), ctx->d_keys, ctx->d_keys + n_total,
-                               ctx->d_vals, ctx->d_vals + n_total, ctx->d_sort_tmp, ctx->sort_tmp_cap, ctx->d_order, s));
+    if (chunks > 0x7FFFFFFFull) return fail(ctx, FDC_E_ARG, "run: source_order needs fewer than 2^45 histories per run");
+    return FDC_OK;
+}
+
+static int enqueue_source_order(fdc_ctx *ctx, const WorkItem *d_items, const std::vector<WorkItem> &items,
+                                uint32_t n_chunks, unsigned long long units, uint32_t *order, hipStream_t s)
+{
+    HIPCHK(launch_source_order(d_items, (uint32_t)items.size(), n_chunks, units, ctx->d_spots, ctx->d_hnext,
+                               (uint32_t)ctx->seed, (uint32_t)(ctx->seed >> 32), order, s));
     return FDC_OK;
 }
 
@@ -826,7 +1002,8 @@ static bool one_plan(const int32_t *plans, uint32_t n_plans)
 
 // transport launch for a work table already on the device; the queue counter
 // is cleared with a kernel so that the sequence can be captured in a graph
-static int enqueue_transport_kernel(fdc_ctx *ctx, TransportArgs a, uint32_t flags, hipStream_t s, bool one_plan);
+static int enqueue_transport_kernel(fdc_ctx *ctx, TransportArgs a, uint32_t flags, hipStream_t s, bool one_plan,
+                                    unsigned long long *queue = nullptr);
 
 // the transport kernel, bracketed by the context's timing events when timing
 // is on (eager runs only)
@@ -847,7 +1024,9 @@ static int enqueue_transport(fdc_ctx *ctx, TransportArgs a, uint32_t flags, hipS
     return FDC_OK;
 }
 
-static int enqueue_transport_kernel(fdc_ctx *ctx, TransportArgs a, uint32_t flags, hipStream_t s, bool one_plan)
+// (queue: the persistent launch's counter; null = the context's, allocated on first use)
+static int enqueue_transport_kernel(fdc_ctx *ctx, TransportArgs a, uint32_t flags, hipStream_t s, bool one_plan,
+                                    unsigned long long *queue)
 {
     const uint32_t wpb = ctx->cfg.waves_per_block;
     const bool variance = (flags & FDC_RUN_VARIANCE) != 0;
@@ -858,12 +1037,15 @@ static int enqueue_transport_kernel(fdc_ctx *ctx, TransportArgs a, uint32_t flag
                     ctx->cfg.tally_slots);
     const bool persistent = ctx->cfg.tally_slots || ctx->cfg.blocks_per_cu;
     if (persistent) {
-        if (!ctx->d_queue) {
-            ctx->d_queue = dalloc_n<unsigned long long>(ctx, 1);
-            if (!ctx->d_queue) return fail(ctx, FDC_E_NOMEM, "run: queue allocation failed");
+        if (!queue) {
+            if (!ctx->d_queue) {
+                ctx->d_queue = dalloc_n<unsigned long long>(ctx, 1);
+                if (!ctx->d_queue) return fail(ctx, FDC_E_NOMEM, "run: queue allocation failed");
+            }
+            queue = ctx->d_queue;
         }
-        HIPCHK(launch_fill_u64(ctx->d_queue, 1, 0, s));
-        a.queue = ctx->d_queue;
+        HIPCHK(launch_fill_u64(queue, 1, 0, s));
+        a.queue = queue;
     }
     if (ctx->cfg.tally_slots) {
         const uint32_t grid = std::max<uint32_t>(1, ctx->cfg.blocks_per_cu) * (uint32_t)ctx->cus;
@@ -896,8 +1078,15 @@ int fdc_run_histories(fdc_ctx *ctx, const int32_t *plans, uint32_t n_plans, uint
     if (rc) return rc;
     hipStream_t s = S(hip_stream);
     std::vector<WorkItem> items;
-    const unsigned long long units = build_items(ctx, plans, n_plans, items);
+    uint32_t n_chunks = 0;
+    const unsigned long long units = build_items(ctx, plans, n_plans, items, &n_chunks);
     if (items.empty()) return FDC_OK;
+    if (ctx->cfg.source_order) {
+        rc = check_source_order(ctx, items);
+        if (rc) return rc;
+        if (!grow(ctx, ctx->d_order, ctx->order_cap, units * kWave, s))
+            return fail(ctx, FDC_E_NOMEM, "run: source order table");
+    }
     rc = ensure_items(ctx, items.size(), s);
     if (rc) return rc;
     std::copy(items.begin(), items.end(), ctx->h_items);
@@ -909,7 +1098,7 @@ int fdc_run_histories(fdc_ctx *ctx, const int32_t *plans, uint32_t n_plans, uint
     a.n_units = units;
     a.flags = flags;
     if (ctx->cfg.source_order) {
-        rc = enqueue_source_order(ctx, items, units, s);
+        rc = enqueue_source_order(ctx, ctx->d_items, items, n_chunks, units, ctx->d_order, s);
         if (rc) return rc;
         a.order = ctx->d_order;
     }
@@ -969,7 +1158,13 @@ int fdc_graph_create(fdc_ctx *ctx, const int32_t *plans, uint32_t n_plans, uint3
     if (!rc) rc = ensure_spots(ctx);
     if (rc) return rc;
     std::vector<WorkItem> items;
-    const unsigned long long units = build_items(ctx, plans, n_plans, items);
+    uint32_t n_chunks = 0;
+    const unsigned long long units = build_items(ctx, plans, n_plans, items, &n_chunks);
+    const bool ordered = ctx->cfg.source_order && !items.empty();
+    if (ordered) {
+        rc = check_source_order(ctx, items);
+        if (rc) return rc;
+    }
     fdc_graph *g = new (std::nothrow) fdc_graph();
     if (!g) return fail(ctx, FDC_E_NOMEM, "graph: host allocation failed");
     g->ctx = ctx;
@@ -977,11 +1172,18 @@ int fdc_graph_create(fdc_ctx *ctx, const int32_t *plans, uint32_t n_plans, uint3
     g->flags = flags;
     g->reset = (options & FDC_GRAPH_RESET_TALLIES) != 0;
     g->d_items = dalloc_n<WorkItem>(ctx, std::max<size_t>(items.size(), 1));
-    if (!g->d_items) { delete g; return fail(ctx, FDC_E_NOMEM, "graph: work table allocation failed"); }
+    if (ordered) g->d_order = dalloc_n<uint32_t>(ctx, units * kWave);
+    if (!g->d_items || (ordered && !g->d_order)) {
+        dfree(ctx, g->d_items);
+        dfree(ctx, g->d_order);
+        delete g;
+        return fail(ctx, FDC_E_NOMEM, "graph: work table allocation failed");
+    }
     auto cleanup = [&](int code, const char *what, hipError_t e) {
         if (g->exec) (void)hipGraphExecDestroy(g->exec);
         if (g->graph) (void)hipGraphDestroy(g->graph);
         dfree(ctx, g->d_items);
+        dfree(ctx, g->d_order);
         delete g;
         return fail(ctx, code, "graph: %s: %s", what, hipGetErrorString(e));
     };
@@ -1012,7 +1214,11 @@ int fdc_graph_create(fdc_ctx *ctx, const int32_t *plans, uint32_t n_plans, uint3
         a.n_items = (uint32_t)items.size();
         a.n_units = units;
         a.flags = flags;
-        rc = enqueue_transport(ctx, a, flags, s, one_plan(plans, n_plans));
+        if (ordered) {
+            rc = enqueue_source_order(ctx, g->d_items, items, n_chunks, units, g->d_order, s);
+            a.order = g->d_order;
+        }
+        if (!rc) rc = enqueue_transport(ctx, a, flags, s, one_plan(plans, n_plans));
         if (!rc) e = launch_advance(g->d_items, (uint32_t)items.size(), ctx->d_hnext, ctx->d_spots, ctx->d_plans, s);
     }
     for (uint32_t i = 0; i < n_plans && (options & FDC_GRAPH_DOSE) && e == hipSuccess && !rc; ++i) {
@@ -1055,6 +1261,7 @@ int fdc_graph_destroy(fdc_graph *g)
     if (g->exec) (void)hipGraphExecDestroy(g->exec);
     if (g->graph) (void)hipGraphDestroy(g->graph);
     dfree(ctx, g->d_items);
+    dfree(ctx, g->d_order);
     delete g;
     return FDC_OK;
 }

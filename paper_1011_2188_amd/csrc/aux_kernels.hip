@@ -42,6 +42,47 @@ __global__ void hu_to_index_kernel(const int16_t *__restrict__ hu, uint16_t *__r
     }
 }
 
+// vacuum-skip bits: seed (0 for non-vacuum voxels, the cap for vacuum), then
+// relaxation passes skip(v) = min(skip(v), 1 + min over the 26 neighbours
+// inside the box).  Every value stays an upper bound of the true distance and
+// a voxel at distance d is exact after pass d, so after kMaxSkip passes every
+// voxel holds min(distance, kMaxSkip) whatever order the updates run in (a
+// pass may already see neighbours updated in the same pass).
+__global__ void skip_seed_kernel(uint16_t *__restrict__ idx, const float2 *__restrict__ lut, size_t n)
+{
+    for (size_t v = blockIdx.x * (size_t)blockDim.x + threadIdx.x; v < n; v += (size_t)gridDim.x * blockDim.x) {
+        const uint32_t h = hu_index(idx[v]);
+        idx[v] = (uint16_t)(h | ((lut[h].x == 0.f ? kMaxSkip : 0u) << kHuBits));
+    }
+}
+
+__global__ void skip_relax_kernel(uint16_t *idx, int nx, int ny, int nz)
+{
+    const size_t n = (size_t)nx * ny * nz;
+    for (size_t v = blockIdx.x * (size_t)blockDim.x + threadIdx.x; v < n; v += (size_t)gridDim.x * blockDim.x) {
+        const uint16_t w = idx[v];
+        uint32_t k = vacuum_skip(w);
+        if (k <= 1u) continue;                   // non-vacuum, or already next to material
+        const int x = (int)(v % (size_t)nx), y = (int)((v / (size_t)nx) % (size_t)ny), z = (int)(v / ((size_t)nx * ny));
+        uint32_t best = k;
+        for (int dz = -1; dz <= 1; ++dz) {
+            const int zz = z + dz;
+            if (zz < 0 || zz >= nz) continue;
+            for (int dy = -1; dy <= 1; ++dy) {
+                const int yy = y + dy;
+                if (yy < 0 || yy >= ny) continue;
+                for (int dx = -1; dx <= 1; ++dx) {
+                    const int xx = x + dx;
+                    if (xx < 0 || xx >= nx || (dx | dy | dz) == 0) continue;
+                    const uint32_t kn = vacuum_skip(idx[((size_t)zz * ny + yy) * nx + xx]);
+                    best = min(best, kn + 1u);
+                }
+            }
+        }
+        if (best < k) idx[v] = (uint16_t)(hu_index(w) | (best << kHuBits));
+    }
+}
+
 __global__ void track_energy_kernel(const float4 *__restrict__ steps, const unsigned long long *__restrict__ off,
                                     long long *__restrict__ T, uint32_t n_tracks)
 {
@@ -77,7 +118,7 @@ __global__ void dose_kernel(const uint16_t *__restrict__ idx, const unsigned lon
 {
     const double N = (double)n_hist[0];
     for (size_t v = blockIdx.x * (size_t)blockDim.x + threadIdx.x; v < nvox; v += (size_t)gridDim.x * blockDim.x) {
-        const uint16_t m = idx[v];
+        const uint32_t m = hu_index(idx[v]);
         const bool vac = lut[m].x == 0.f || N <= 0.0;
         const double mass_kg = (double)rho_lut[m] * vol_cm3 * 1e-3;
         const double per = kMeVToJ / mass_kg;                // Gy per MeV in this voxel
@@ -115,7 +156,7 @@ __global__ void density_kernel(const uint16_t *__restrict__ idx, const float *__
                                float *__restrict__ rho)
 {
     for (size_t v = blockIdx.x * (size_t)blockDim.x + threadIdx.x; v < n; v += (size_t)gridDim.x * blockDim.x)
-        rho[v] = rho_lut[idx[v]];
+        rho[v] = rho_lut[hu_index(idx[v])];
 }
 
 // denoiser input: channel 0 = dose * scale, channel 1 = density / 2
@@ -200,6 +241,15 @@ hipError_t launch_advance(const WorkItem *items, uint32_t n_items, unsigned long
 {
     hipLaunchKernelGGL(advance_kernel, dim3((n_items + 255) / 256), dim3(256), 0, s, items, n_items, hnext, spots,
                        plans);
+    return hipGetLastError();
+}
+
+hipError_t launch_vacuum_skip(uint16_t *idx, const float2 *lut, int nx, int ny, int nz, hipStream_t s)
+{
+    const size_t n = (size_t)nx * ny * nz;
+    hipLaunchKernelGGL(skip_seed_kernel, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, idx, lut, n);
+    for (uint32_t pass = 0; pass < kMaxSkip; ++pass)
+        hipLaunchKernelGGL(skip_relax_kernel, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, idx, nx, ny, nz);
     return hipGetLastError();
 }
 

@@ -20,13 +20,23 @@ constexpr size_t kLdsFixedBytes = 64 + 16 * kWaveConst * sizeof(float);   // bes
 constexpr double kMeVToJ = 1.602176634e-13;
 constexpr double kFpMeV = 1.0 / 16777216.0;   // one fixed-point unit in MeV
 
+// A voxel's 16-bit word: the HU index (clamp(HU, -1024, 3071) + 1024) in the
+// low 12 bits; in the high 4 bits, for a vacuum voxel, its Chebyshev distance
+// in voxels to the nearest non-vacuum voxel of the plan, capped at 15 (0 for
+// non-vacuum voxels): every voxel within distance skip - 1 is vacuum too.
+constexpr uint32_t kHuBits = 12;
+constexpr uint32_t kMaxSkip = 15;
+__host__ __device__ inline uint32_t hu_index(uint16_t w) { return w & ((1u << kHuBits) - 1u); }
+__host__ __device__ inline uint32_t vacuum_skip(uint16_t w) { return (uint32_t)w >> kHuBits; }
+
 // one phantom + its tallies, as seen by the kernels
 struct DevPlan {
-    const uint16_t *idx;             // HU index per voxel, x-fastest
+    const uint16_t *idx;             // voxel word (HU index | vacuum skip << 12), x-fastest
     unsigned long long *E;           // int64 energy tally (two's complement in u64 adds)
     unsigned long long *E2;          // uint64 sum of squared per-visit deposits
     unsigned long long *acc;         // [0] incident, [1] escaped (fixed point), [2] scratch,
                                      // [3] histories run since the last reset
+    const float4 *ps;                // listed protons: (x, y, z, E MeV), (dx, dy, dz, 0) each
     int n[3];
     float vox[3];
     float inv_vox[3];                // 1 / vox (FP32)
@@ -45,6 +55,13 @@ struct DevSpot {
     uint32_t plan;                  // plan id (Philox counter word 3)
     uint32_t spot;                  // spot index inside its plan (counter word 2)
     long long skip;                 // fp(E_bin) - fp(E_spot)
+    unsigned long long n_hist;      // histories per run (the device-built work table reads it)
+    // a source of listed protons (kind 1): history h is proton ps_first + h % ps_count
+    // of the plan's list, which brings its own start, direction and energy
+    uint32_t kind;                  // 0 spot, 1 listed protons
+    uint32_t pad;
+    long long bin_fp;               // fp(E_bin)
+    unsigned long long ps_first, ps_count;
 };
 
 // a contiguous range of histories of one spot, cut in wave units of 64
@@ -59,7 +76,7 @@ struct WorkItem {
     unsigned long long unit0;       // index of this item's first wave unit
     unsigned long long first;       // index of this item's first history among the run's
     uint32_t gspot;                 // index into the DevSpot array
-    uint32_t pad;
+    uint32_t chunk0;                // index of this item's first ordering chunk (start-position order)
 };
 
 __host__ __device__ inline unsigned long long units_for(unsigned long long n)
@@ -221,19 +238,21 @@ hipError_t prepare_lds_kernels();
 hipError_t launch_build_lut(const double *pts, int n_pts, double vacuum_below, float2 *lut, float *rho,
                             hipStream_t s);
 hipError_t launch_hu_to_index(const int16_t *hu, uint16_t *idx, size_t n, hipStream_t s);
+// the vacuum-skip bits of every voxel word of a plan, from the material table
+hipError_t launch_vacuum_skip(uint16_t *idx, const float2 *lut, int nx, int ny, int nz, hipStream_t s);
 hipError_t launch_compact_steps(float4 *steps, unsigned long long n, hipStream_t s);
 hipError_t launch_track_energy(const float4 *steps, const unsigned long long *off, long long *T,
                                uint32_t n_tracks, hipStream_t s);
 hipError_t launch_dose(const uint16_t *idx, const unsigned long long *E, const unsigned long long *E2,
                        const float2 *lut, const float *rho_lut, size_t nvox, double voxel_volume_cm3,
                        const unsigned long long *n_hist, double *dose, double *var, hipStream_t s);
-// processing order of a run's histories by start position (order.hip)
-size_t source_order_temp_bytes(unsigned long long n_total, uint32_t n_items);
-hipError_t launch_source_order(const WorkItem *items, uint32_t n_items,
-                               unsigned long long n_total, unsigned long long n_units, const DevSpot *spots,
-                               const unsigned long long *hnext, uint32_t seed_lo, uint32_t seed_hi,
-                               unsigned long long *keys_a, unsigned long long *keys_b, uint32_t *vals_a,
-                               uint32_t *vals_b, void *temp, size_t temp_bytes, uint32_t *order, hipStream_t s);
+// processing order of a run's histories by start position (order.hip):
+// ordering chunks of an item of n histories, and the launch (fill of the
+// per-unit lane table, one workgroup per chunk)
+uint32_t source_order_chunks(unsigned long long n);
+hipError_t launch_source_order(const WorkItem *items, uint32_t n_items, uint32_t n_chunks, unsigned long long n_units,
+                               const DevSpot *spots, const unsigned long long *hnext, uint32_t seed_lo,
+                               uint32_t seed_hi, uint32_t *order, hipStream_t s);
 hipError_t launch_advance(const WorkItem *items, uint32_t n_items, unsigned long long *hnext, const DevSpot *spots,
                           const DevPlan *plans, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long *p, size_t n, unsigned long long value, hipStream_t s);

@@ -13,7 +13,7 @@ constexpr int kRedThreads = 256;
 
 __device__ inline bool is_vacuum(const uint16_t *idx, const float2 *lut, size_t v)
 {
-    return lut[idx[v]].x == 0.f;
+    return lut[hu_index(idx[v])].x == 0.f;
 }
 
 // per-block maximum of non-vacuum doses (doses are >= 0, so the max of their

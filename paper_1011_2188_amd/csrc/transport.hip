@@ -265,12 +265,22 @@ struct CacheSink {
 // matrix (9 floats, row-major) and the plan's 1 / voxel size (3).  They are
 // read where they are used (volatile, so not hoisted into registers that
 // would stay live across the walk).
-template <bool EP, class Sink>
+// LISTED: the source is a list of protons (Section 2.3, a phase space read from
+// a file): history h is the source's proton h mod count, which brings its own
+// start point, direction (and with it the frame of the deflections, kept per
+// lane) and energy.
+template <bool EP, bool LISTED, class Sink>
 __host__ __device__ void replay_history(const TransportArgs &a, const DevSpot &sp, const DevPlan &pl,
                                const float2 *__restrict__ lut, const volatile float *wc, unsigned long long h,
                                uint32_t slot, long long &inc, long long &esc, const Sink &sink)
 {
     // ---- task 1: track, start step, source ---------------------------------
+    float4 q0 = make_float4(0.f, 0.f, 0.f, 0.f), q1 = q0;
+    if (LISTED) {
+        const unsigned long long pi = sp.ps_first + h % sp.ps_count;
+        q0 = pl.ps[2 * pi];
+        q1 = pl.ps[2 * pi + 1];
+    }
     const uint32_t first = a.bin_first[sp.bin];
     const uint32_t nb = a.bin_first[sp.bin + 1] - first;
     const unsigned long long c = h / a.R;
@@ -279,7 +289,7 @@ __host__ __device__ void replay_history(const TransportArgs &a, const DevSpot &s
     const uint32_t t = first + (uint32_t)(((uint64_t)xt.x * nb) >> 32);
     unsigned long long k = a.track_off[t];
     const unsigned long long kend = a.track_off[t + 1];
-    const long long skip = sp.skip;
+    const long long skip = LISTED ? sp.bin_fp - to_fp(q0.w) : sp.skip;
     long long cum = 0;
     long long e = 0;
     for (; k < kend; ++k) {
@@ -301,10 +311,35 @@ __host__ __device__ void replay_history(const TransportArgs &a, const DevSpot &s
     sincos(2.0 * M_PI * u01(xs.y), &sa, &ca);
     const double n1 = r * ca, n2 = r * sa;
     const float phi0 = (a.flags & kFlagRotate) ? (float)(2.0 * M_PI * u01(xs.z)) : 0.f;
-    const double scale = fabs((double)sp.sigma);
-    double p[3];
+    double p[3], dsrc[3];
+    float lm[9];                                    // a listed proton's frame, columns e1 e2 d
+    if (LISTED) {
+        // its own start and direction, no lateral spread; the frame as for a
+        // spot: e2 = normalize(d x a), e1 = e2 x d, a = +x if |d_z| >= 0.9 else +z
+        const double dl = sqrt((double)q1.x * q1.x + (double)q1.y * q1.y + (double)q1.z * q1.z);
+        const double d[3] = {q1.x / dl, q1.y / dl, q1.z / dl};
+        const double ax[3] = {fabs(d[2]) >= 0.9 ? 1.0 : 0.0, 0.0, fabs(d[2]) >= 0.9 ? 0.0 : 1.0};
+        double e2[3] = {d[1] * ax[2] - d[2] * ax[1], d[2] * ax[0] - d[0] * ax[2], d[0] * ax[1] - d[1] * ax[0]};
+        const double l2 = sqrt(e2[0] * e2[0] + e2[1] * e2[1] + e2[2] * e2[2]);
+        e2[0] /= l2; e2[1] /= l2; e2[2] /= l2;
+        const double e1[3] = {e2[1] * d[2] - e2[2] * d[1], e2[2] * d[0] - e2[0] * d[2], e2[0] * d[1] - e2[1] * d[0]};
+        const double q0p[3] = {q0.x, q0.y, q0.z};
 #pragma unroll
-    for (int q = 0; q < 3; ++q) p[q] = sp.pos[q] + scale * (n1 * sp.e1[q] + n2 * sp.e2[q]);
+        for (int q = 0; q < 3; ++q) {
+            p[q] = q0p[q];
+            dsrc[q] = d[q];
+            lm[3 * q + 0] = (float)e1[q];
+            lm[3 * q + 1] = (float)e2[q];
+            lm[3 * q + 2] = (float)d[q];
+        }
+    } else {
+        const double scale = fabs((double)sp.sigma);
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            p[q] = sp.pos[q] + scale * (n1 * sp.e1[q] + n2 * sp.e2[q]);
+            dsrc[q] = sp.d[q];
+        }
+    }
 
     // ray-box entry (FP64); outside the box is vacuum
     double tin = -__builtin_huge_val(), tout = __builtin_huge_val();
@@ -313,10 +348,10 @@ __host__ __device__ void replay_history(const TransportArgs &a, const DevSpot &s
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
         const double lo = pl.org_d[q], hi = pl.org_d[q] + pl.n[q] * pl.vox_d[q];
-        if (sp.d[q] == 0.0) {
+        if (dsrc[q] == 0.0) {
             miss |= (p[q] < lo || p[q] >= hi);
         } else {
-            double t1 = (lo - p[q]) / sp.d[q], t2 = (hi - p[q]) / sp.d[q];
+            double t1 = (lo - p[q]) / dsrc[q], t2 = (hi - p[q]) / dsrc[q];
             if (t1 > t2) { const double tt = t1; t1 = t2; t2 = tt; }
             if (t1 > tin) { tin = t1; ax_in = q; }
             tout = fmin(tout, t2);
@@ -335,20 +370,20 @@ __host__ __device__ void replay_history(const TransportArgs &a, const DevSpot &s
     }
     if (tin > 0.0) {
 #pragma unroll
-        for (int q = 0; q < 3; ++q) p[q] += tin * sp.d[q];
+        for (int q = 0; q < 3; ++q) p[q] += tin * dsrc[q];
     }
     Lane L;
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
         double u = (p[q] - pl.org_d[q]) / pl.vox_d[q];
-        if (tin > 0.0 && q == ax_in) u = sp.d[q] > 0.0 ? 0.0 : (double)pl.n[q];  // on the entry face
+        if (tin > 0.0 && q == ax_in) u = dsrc[q] > 0.0 ? 0.0 : (double)pl.n[q];  // on the entry face
         double fl = floor(u);
         int i = (int)fl;
-        if (u == fl && sp.d[q] < 0.0) i -= 1;     // a boundary point belongs to the voxel entered
+        if (u == fl && dsrc[q] < 0.0) i -= 1;     // a boundary point belongs to the voxel entered
         i = min(max(i, 0), pl.n[q] - 1);
         L.i[q] = i;
         L.f[q] = (float)fmin(fmax(u - (double)i, 0.0), 1.0);
-        L.d[q] = (float)sp.d[q];
+        L.d[q] = (float)dsrc[q];
     }
     L.b[0] = 0.f; L.b[1] = 0.f; L.b[2] = 1.f;
     // what the walk reads of the plan and spot, as values (not re-read from
@@ -369,7 +404,8 @@ __host__ __device__ void replay_history(const TransportArgs &a, const DevSpot &s
     // deposit is flushed, and the next step record one step ahead, so no wait
     // for a load also waits for the tally atomics issued before it.
     const uint16_t *__restrict__ vidx = pl.idx;
-    float2 m = lut[load_global(vidx, L.v)];
+    uint16_t wcur = load_global(vidx, L.v);          // the current voxel's word
+    float2 m = lut[hu_index(wcur)];
     long long acc = 0, hdep = 0;
     bool escaped = false;
     // the partial first step (its remaining energy e_first of the stored e):
@@ -398,6 +434,50 @@ __host__ __device__ void replay_history(const TransportArgs &a, const DevSpot &s
         float tau = 0.f, g2 = 0.f;
         int dep = 0;
         while (tau < w_tot) {
+            const uint32_t kskip = vacuum_skip(wcur);
+            if (kskip >= 2u) {
+                // Free flight through vacuum: every voxel within kskip - 1 of this
+                // one (per axis, and inside the box) is vacuum, so the proton
+                // crosses that cube in one move - no WEL, no deposit, no
+                // scattering, as voxel by voxel - to the face it reaches first
+                // (ties x -> y -> z); past the box it escapes.
+                const int n3[3] = {nx, ny, nz};
+                int ext[3];
+                float tj = kInf;
+                int axj = 0;
+#pragma unroll
+                for (int q = 0; q < 3; ++q) {
+                    const int room = L.d[q] > 0.f ? n3[q] - 1 - L.i[q] : L.i[q];
+                    ext[q] = min((int)kskip - 1, room);
+                    const float t = fmaf(ta[q], L.f[q], tb[q]) + (float)ext[q] * fabsf(ta[q]);
+                    if (t < tj) { tj = t; axj = q; }
+                }
+                bool out = false;
+#pragma unroll
+                for (int q = 0; q < 3; ++q) {
+                    if (q == axj) {
+                        const int up = L.d[q] > 0.f ? 1 : -1;
+                        const int ni = L.i[q] + up * (ext[q] + 1);
+                        out = (unsigned)ni >= (unsigned)n3[q];
+                        L.i[q] = out ? L.i[q] + up * ext[q] : ni;             // out: stays on the last voxel's
+                        L.f[q] = (up > 0) == out ? 1.f : 0.f;                  // exit face, else the entry face
+                    } else if (L.d[q] != 0.f) {
+                        const float u = fmaf(tj, dv[q], L.f[q]);
+                        float fl = floorf(u);
+                        fl = L.d[q] > 0.f ? fminf(fmaxf(fl, 0.f), (float)ext[q]) : fmaxf(fminf(fl, 0.f), -(float)ext[q]);
+                        L.i[q] += (int)fl;
+                        L.f[q] = fminf(fmaxf(u - fl, 0.f), 1.f);
+                    }
+                }
+                if (out) {
+                    escaped = true;
+                    break;
+                }
+                L.v = ((uint32_t)L.i[2] * (uint32_t)ny + (uint32_t)L.i[1]) * (uint32_t)nx + (uint32_t)L.i[0];
+                wcur = load_global(vidx, L.v);
+                m = lut[hu_index(wcur)];
+                continue;
+            }
             // distance (cm) to the exit face along each axis; ties go x -> y -> z
             const float tx = fmaf(ta[0], L.f[0], tb[0]);
             const float ty = fmaf(ta[1], L.f[1], tb[1]);
@@ -452,7 +532,8 @@ __host__ __device__ void replay_history(const TransportArgs &a, const DevSpot &s
                     break;
                 }
                 L.v = vn;
-                m = lut[idx_n];
+                wcur = idx_n;
+                m = lut[hu_index(idx_n)];
             }
         }
         if (escaped) break;
@@ -477,7 +558,8 @@ __host__ __device__ void replay_history(const TransportArgs &a, const DevSpot &s
         L.b[0] = nu * nrm; L.b[1] = nv * nrm; L.b[2] = nw * nrm;
 #pragma unroll
         for (int q = 0; q < 3; ++q)
-            L.d[q] = wc[3 * q + 0] * L.b[0] + wc[3 * q + 1] * L.b[1] + wc[3 * q + 2] * L.b[2];
+            L.d[q] = LISTED ? lm[3 * q + 0] * L.b[0] + lm[3 * q + 1] * L.b[1] + lm[3 * q + 2] * L.b[2]
+                            : wc[3 * q + 0] * L.b[0] + wc[3 * q + 1] * L.b[1] + wc[3 * q + 2] * L.b[2];
         {
             const float iv[3] = {wc[9], wc[10], wc[11]};
             set_direction_terms(L.d, iv, ta, tb, dv);
@@ -540,7 +622,12 @@ __device__ void process_unit(const TransportArgs &a, const float2 *lut, float *w
     // see them)
     if (lane < 9) wc[lane] = sp.m[lane];
     else if (lane < 12) wc[lane] = pl.inv_vox[lane - 9];
-    if (valid) replay_history<EP>(a, sp, pl, lut, wc, h, (uint32_t)(h - h0), inc, esc, sink);
+    if (valid) {
+        if (sp.kind)                                  // (wave-uniform: a unit is one source's)
+            replay_history<EP, true>(a, sp, pl, lut, wc, h, (uint32_t)(h - h0), inc, esc, sink);
+        else
+            replay_history<EP, false>(a, sp, pl, lut, wc, h, (uint32_t)(h - h0), inc, esc, sink);
+    }
     if (!EP) {
         inc = wave_sum(inc);
         esc = wave_sum(esc);

@@ -28,7 +28,8 @@ ERROR_NAMES = {0: "FDC_OK", -1: "FDC_E_ARG", -2: "FDC_E_STATE", -3: "FDC_E_NOMEM
 
 # every entry point declared in include/fdc.h
 EXPORTS = ["fdc_create", "fdc_destroy", "fdc_last_error", "fdc_set_allocator", "fdc_set_hu_table",
-           "fdc_load_track_db", "fdc_load_track_db_file", "fdc_load_phantom", "fdc_add_beam_spots", "fdc_run_histories",
+           "fdc_load_track_db", "fdc_load_track_db_file", "fdc_load_phantom", "fdc_add_beam_spots", "fdc_add_phase_space",
+           "fdc_add_phase_space_file", "fdc_run_histories",
            "fdc_reset_plan", "fdc_compute_dose", "fdc_read_dose_and_variance", "fdc_debug_endpoints",
            "fdc_debug_philox", "fdc_debug_material", "fdc_set_launch_config", "fdc_device_cus",
            "fdc_mean_uncertainty", "fdc_batch_uncertainty", "fdc_gamma_index",
@@ -85,6 +86,8 @@ def lib():
         "fdc_load_track_db_file": (C.c_int, [_P, C.c_char_p, _P]),
         "fdc_load_phantom": (C.c_int, [_P, C.POINTER(C.c_int32), _P, C.c_int, C.c_int, C.c_int, _P, _P, _P]),
         "fdc_add_beam_spots": (C.c_int, [_P, C.c_int32, _P, C.c_uint32]),
+        "fdc_add_phase_space": (C.c_int, [_P, C.c_int32, _P, C.c_uint64, C.POINTER(C.c_uint32), _P]),
+        "fdc_add_phase_space_file": (C.c_int, [_P, C.c_int32, C.c_char_p, C.POINTER(C.c_uint32), _P]),
         "fdc_run_histories": (C.c_int, [_P, _P, C.c_uint32, C.c_uint32, _P]),
         "fdc_reset_plan": (C.c_int, [_P, C.c_int32, C.c_int, _P]),
         "fdc_compute_dose": (C.c_int, [_P, C.c_int32, _P, _P, _P]),
@@ -283,6 +286,20 @@ class Context:
         from .inputs import SPOT_DTYPE
         s = np.ascontiguousarray(spots, SPOT_DTYPE)
         _check(self.h, lib().fdc_add_beam_spots(self.h, plan, s.ctypes.data, s.size))
+
+    def add_phase_space(self, plan, particles, stream=None):
+        """Listed incident protons (inputs.PARTICLE_DTYPE); returns the number of
+        sources (energy-bin groups) added to the plan."""
+        from .inputs import PARTICLE_DTYPE
+        q = np.ascontiguousarray(particles, PARTICLE_DTYPE)
+        n = C.c_uint32()
+        _check(self.h, lib().fdc_add_phase_space(self.h, plan, q.ctypes.data, q.size, C.byref(n), _stream(stream)))
+        return n.value
+
+    def add_phase_space_file(self, plan, path, stream=None):
+        n = C.c_uint32()
+        _check(self.h, lib().fdc_add_phase_space_file(self.h, plan, os.fsencode(path), C.byref(n), _stream(stream)))
+        return n.value
 
     # -- the method
     def run_histories(self, plans, flags=FDC_RUN_VARIANCE, stream=None):

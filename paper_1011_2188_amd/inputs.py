@@ -41,6 +41,12 @@ SPOT_DTYPE = np.dtype([("pos_cm", "<f4", (3,)), ("dir", "<f4", (3,)),
                        ("n_histories", "<u8")])
 assert SPOT_DTYPE.itemsize == 40
 
+# one listed incident proton (the C struct fdc_particle, 32 bytes)
+PARTICLE_DTYPE = np.dtype([("pos_cm", "<f4", (3,)), ("dir", "<f4", (3,)), ("energy_MeV", "<f4"),
+                           ("reserved", "<f4")])
+assert PARTICLE_DTYPE.itemsize == 32
+PHASE_SPACE_MAGIC = b"FDCPHSP1"
+
 # Default HU -> (density, relative stopping power, relative scattering power)
 # table: synthetic constants (not clinical data), piecewise linear.
 HU_TABLE_DEFAULT = {
@@ -214,6 +220,62 @@ def read_track_db_file(path):
     if o != raw.size:
         raise ValueError("track database file size does not match its header")
     return TrackDB(parts[3].reshape(ns, 4), parts[2], parts[0], parts[1])
+
+
+def write_phase_space_file(path, particles):
+    """A phase-space file: 32-byte header (magic, version 1, record size 32,
+    count, 0) then the fdc_particle records."""
+    q = np.ascontiguousarray(particles, PARTICLE_DTYPE)
+    h = np.zeros(1, np.dtype([("magic", "S8"), ("version", "<u4"), ("rec", "<u4"), ("n", "<u8"), ("res", "<u8")]))
+    h["magic"] = PHASE_SPACE_MAGIC
+    h["version"] = 1
+    h["rec"] = PARTICLE_DTYPE.itemsize
+    h["n"] = q.size
+    with open(path, "wb") as f:
+        f.write(h.tobytes())
+        f.write(q.tobytes())
+
+
+def read_phase_space_file(path):
+    raw = np.fromfile(path, np.uint8)
+    if raw[:8].tobytes() != PHASE_SPACE_MAGIC:
+        raise ValueError("not a phase-space file")
+    n = int(raw[16:24].view("<u8")[0])
+    q = raw[32:].view(PARTICLE_DTYPE)
+    if q.size != n:
+        raise ValueError("phase-space file size does not match its header")
+    return q.copy()
+
+
+def synthetic_phase_space(n, seed, e_mean=121.0, e_sigma=0.8, tail_fraction=0.05, tail_min=100.0,
+                          radius_cm=4.0, source_cm=(7.0, -31.0, 0.0), direction=(0.0, 1.0, 0.0),
+                          sad_cm=200.0, divergence_rad=0.002):
+    """A stand-in for a phase-space file scored at the exit of a beam line: a
+    field of circular cross-section (start points uniform over a disk of
+    radius_cm in the plane through source_cm perpendicular to `direction`),
+    directions diverging from a virtual source sad_cm upstream plus a small
+    Gaussian angular spread, energies Gaussian around e_mean with a
+    low-energy tail (protons that lost energy in the beam line), uniform from
+    tail_min to e_mean.  Deterministic in seed."""
+    rng = np.random.default_rng([int(seed), 31])
+    d = np.asarray(direction, np.float64)
+    d /= np.linalg.norm(d)
+    e1, e2 = field_frame(d)
+    r = radius_cm * np.sqrt(rng.random(n))
+    a = 2.0 * np.pi * rng.random(n)
+    off = (r * np.cos(a))[:, None] * e1 + (r * np.sin(a))[:, None] * e2
+    pos = np.asarray(source_cm, np.float64) + off
+    dirs = d * sad_cm + off + divergence_rad * sad_cm * (rng.standard_normal((n, 1)) * e1
+                                                          + rng.standard_normal((n, 1)) * e2)
+    dirs /= np.linalg.norm(dirs, axis=1, keepdims=True)
+    E = rng.normal(e_mean, e_sigma, n)
+    tail = rng.random(n) < tail_fraction
+    E[tail] = rng.uniform(tail_min, e_mean, int(tail.sum()))
+    q = np.zeros(n, PARTICLE_DTYPE)
+    q["pos_cm"] = pos
+    q["dir"] = dirs
+    q["energy_MeV"] = E
+    return q
 
 
 # --------------------------------------------------------------------------

@@ -201,3 +201,45 @@ def test_track_db_file_round_trip(ctx, tmp_path):
     _expect(F.FDC_E_FORMAT, ctx.load_track_db_file, bad)
     _expect(F.FDC_E_ARG, ctx.load_track_db_file, tmp_path / "missing.bin")
     assert F.lib().fdc_load_track_db_file(ctx.h, None, None) == F.FDC_E_ARG
+
+
+def test_phase_space_validation_and_grouping(ctx, tmp_path):
+    """Listed protons become one source per energy bin, numbered after the
+    plan's spots; bad records and energies outside the bins are refused; the
+    file loader checks its header."""
+    ctx.load_track_db(I.make_water_track_db([100.0, 105.0, 110.0], 3, seed=1))
+    p = ctx.load_phantom(I.water_phantom((4, 4, 4), 0.5))
+    ctx.add_beam_spots(p, I.spots([[0, 0, -1]], [[0, 0, 1]], [101.0], 0.3, 10))
+    q = np.zeros(6, I.PARTICLE_DTYPE)
+    q["dir"] = (0.0, 0.0, 1.0)
+    q["energy_MeV"] = [101.0, 108.0, 103.0, 110.0, 100.0, 104.9]     # bins 105, 110, 105, 110, 100, 105
+    assert ctx.add_phase_space(p, q) == 3
+    assert ctx.add_phase_space(p, q[:1]) == 1
+    bad = q.copy()
+    bad["energy_MeV"][2] = 110.5
+    _expect(F.FDC_E_RANGE, ctx.add_phase_space, p, bad)
+    bad = q.copy()
+    bad["dir"][1] = 0.0
+    _expect(F.FDC_E_ARG, ctx.add_phase_space, p, bad)
+    bad = q.copy()
+    bad["pos_cm"][3, 0] = np.nan
+    _expect(F.FDC_E_ARG, ctx.add_phase_space, p, bad)
+    bad = q.copy()
+    bad["reserved"][0] = 1.0
+    _expect(F.FDC_E_ARG, ctx.add_phase_space, p, bad)
+    _expect(F.FDC_E_ARG, ctx.add_phase_space, p + 5, q)
+    ctx.run_histories([p], 0)                                   # 10 + 6 + 1 histories of bookkeeping
+    path = tmp_path / "ps.bin"
+    I.write_phase_space_file(path, q)
+    assert np.array_equal(I.read_phase_space_file(path), q)
+    assert ctx.add_phase_space_file(p, path) == 3
+    raw = path.read_bytes()
+    path.write_bytes(raw[:-4])
+    _expect(F.FDC_E_FORMAT, ctx.add_phase_space_file, p, path)
+    path.write_bytes(b"FDCPHSP2" + raw[8:])
+    _expect(F.FDC_E_FORMAT, ctx.add_phase_space_file, p, path)
+    _expect(F.FDC_E_ARG, ctx.add_phase_space_file, p, tmp_path / "none.bin")
+    c2 = F.Context(device=F.FDC_NO_DEVICE)
+    c2.load_phantom(I.water_phantom((4, 4, 4), 0.5))
+    _expect(F.FDC_E_STATE, c2.add_phase_space, 0, q)            # no database
+    c2.close()

@@ -58,6 +58,17 @@ def check_dose(g, o, ph, n):
     return dose_o, var_o
 
 
+def check_e2(g, o, ph, n):
+    """The squared-energy tally voxel by voxel: within 0.5% of its maximum in
+    every voxel above 10% of Dmax (the same FP32-vs-FP64 boundary shifts as the
+    energy tally, squared per visit)."""
+    dose_o, _ = O.dose_and_variance(o["E"], o["E2"], n, ph)
+    sel = dose_o > 0.1 * dose_o.max()
+    e2g, e2o = g["E2"].astype(np.float64), o["E2"].astype(np.float64)
+    err = np.abs(e2g - e2o)[sel].max() / e2o[sel].max()
+    assert err <= 0.005, f"squared-energy tally differs by {err:.4%} of its maximum"
+
+
 def check_energy(g, o):
     assert g["deposited"] + g["escaped"] == g["incident"]
     assert int(g["E"].sum()) == g["deposited"]
@@ -129,6 +140,7 @@ def test_water_pencil_full_parity():
     o = O.replay(db, ph, sp, seed=SEED)
     check_energy(g, o)
     _, var_o = check_dose(g, o, ph, 100_000)
+    check_e2(g, o, ph, 100_000)
     assert abs(g["escaped"] - o["escaped"]) <= 1e-6 * o["incident"]
     sel = g["dose"] > 0.5 * g["dose"].max()
     ug = np.mean(np.sqrt(g["var"][sel]) / g["dose"][sel])
@@ -148,6 +160,7 @@ def test_slab_parity():
     o = O.replay(db, ph, sp, seed=SEED)
     check_energy(g, o)
     check_dose(g, o, ph, int(sp["n_histories"].sum()))
+    check_e2(g, o, ph, int(sp["n_histories"].sum()))
     tot = good = 0
     for s in range(25):
         ok, n = check_endpoints(c, g["plan"], db, ph, sp, s, 1000, 200)
@@ -368,6 +381,7 @@ def test_full_size_slab_dose_vs_oracle():
     o = O.replay(db, ph, sp, seed=SEED)
     assert g["incident"] == o["incident"]
     dose_o, var_o = check_dose(g, o, ph, 10_000_000)
+    check_e2(g, o, ph, 10_000_000)
     sel = dose_o > 0.5 * dose_o.max()
     rel = np.abs(np.sqrt(g["var"][sel]) - np.sqrt(var_o[sel])) / np.sqrt(var_o[sel])
     assert np.median(rel) < 0.01
@@ -445,6 +459,45 @@ def test_batched_graph_full_size():
         assert ra["n_histories"] == rb["n_histories"] == int(sp["n_histories"].sum())
         assert ra["deposited"] + ra["escaped"] == ra["incident"] == rb["incident"]
         assert np.array_equal(ra["E"], rb["E"]) and np.array_equal(ra["E2"], rb["E2"])
+    gr.close()
+
+
+def test_batched_graph_plans_vs_oracle():
+    """Four plans of the batched workload's generator (thorax-like phantoms of
+    different sizes, one field each), 1e5 histories each, run as ONE captured
+    graph launch in the benchmark's launch configuration (tallies cleared, dose
+    and variance computed inside the graph): every plan's dose against the
+    oracle replaying that plan, its squared-energy tally, its incident energy
+    exactly, and the energy identity."""
+    plans = W.batched_plans(4, seed=77, hist_scale=1.0)
+    db = W.multi_bin_db(2000)
+    c = ctx_for(db, **BENCH_LAUNCH)
+    ids, doses, vars_ = [], [], []
+    for ph, sp in plans:
+        sp = sp.copy()
+        base, extra = divmod(100_000, len(sp))
+        sp["n_histories"] = base
+        sp["n_histories"][:extra] += 1
+        p = c.load_phantom(ph)
+        c.add_beam_spots(p, sp)
+        ids.append((p, ph, sp))
+        doses.append(torch.empty(ph.hu.size, dtype=torch.float64, device="cuda"))
+        vars_.append(torch.empty(ph.hu.size, dtype=torch.float64, device="cuda"))
+    gr = c.graph_create([p for p, _, _ in ids], F.FDC_RUN_VARIANCE, reset=True, doses=doses, variances=vars_)
+    gr.launch()
+    torch.cuda.synchronize()
+    for (p, ph, sp), d, v in zip(ids, doses, vars_):
+        g = c.read_dose_and_variance(p, dose=False, var=False, raw=True)
+        g["dose"] = d.cpu().numpy().reshape(ph.hu.shape)
+        o = O.replay(db, ph, sp, seed=SEED, plan=p)
+        assert g["n_histories"] == 100_000
+        check_energy(g, o)
+        dose_o, var_o = check_dose(g, o, ph, 100_000)
+        check_e2(g, o, ph, 100_000)
+        sel = dose_o > 0.5 * dose_o.max()
+        ug = np.mean(np.sqrt(v.cpu().numpy().reshape(ph.hu.shape)[sel]) / dose_o[sel])
+        uo = np.mean(np.sqrt(var_o[sel]) / dose_o[sel])
+        assert abs(ug / uo - 1) < 0.01
     gr.close()
 
 

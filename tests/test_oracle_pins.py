@@ -588,3 +588,60 @@ def test_per_visit_squares_against_eq2_taken_literally():
     sp = I.spots([[0.0, 0.0, -1.0]], [[0.0, 0.0, 1.0]], [150.0], 0.3, 3000)
     r = O.replay(db, ph, sp, exact_e2=True)
     assert np.array_equal(r["E2"], r["E2x"]) and r["escaped"] == 0
+
+
+# ------------------------------------------------------------ phase space ----
+def test_phase_space_of_one_point_equals_a_zero_width_spot():
+    """Protons listed at one position, direction and energy replay exactly as a
+    spot of zero width there (same source index, same tracks, same histories):
+    the tallies are bit for bit equal; listing them over two energy bins splits
+    them into two sources whose sum keeps the energy identity."""
+    db = I.make_water_track_db([95.0, 100.0, 105.0], 60, seed=4)
+    ph = I.thorax_phantom((40, 36, 30), 0.4, seed=2)
+    sp = I.spots([[0.3, -0.2, -20.0]], [[0.1, 0.0, 1.0]], [98.5], 0.0, 500)
+    a = O.replay(db, ph, sp)
+    n = 500
+    ps = O.phase_space_sources(np.tile([0.3, -0.2, -20.0], (n, 1)), np.tile([0.1, 0.0, 1.0], (n, 1)),
+                               np.full(n, 98.5), db.bin_E, 0)
+    assert ps["count"].tolist() == [n] and ps["bins"] == [1]
+    b = O.replay(db, ph, sp, phase_space=ps)              # the spot row is a placeholder now
+    assert np.array_equal(a["E"], b["E"]) and np.array_equal(a["E2"], b["E2"])
+    assert a["incident"] == b["incident"] and a["escaped"] == b["escaped"]
+    # two bins: protons at 98.5 and 103 MeV alternate in the list -> two sources
+    E = np.where(np.arange(n) % 2 == 0, 98.5, 103.0)
+    ps2 = O.phase_space_sources(np.tile([0.3, -0.2, -20.0], (n, 1)), np.tile([0.1, 0.0, 1.0], (n, 1)), E,
+                                db.bin_E, 0)
+    assert ps2["count"].tolist() == [250, 250] and ps2["bins"] == [1, 2]
+    assert np.all(ps2["E"][:250] == np.float32(98.5)) and np.all(ps2["E"][250:] == np.float32(103.0))
+    sp2 = np.concatenate([sp, sp])
+    c = O.replay(db, ph, sp2, h_count=ps2["count"], phase_space=ps2)
+    assert int(c["E"].sum()) + c["escaped"] == c["incident"]
+    # the 98.5 MeV source is the first 250 histories of the single-bin run
+    d = O.replay(db, ph, sp, h_count=np.array([250], np.uint64), phase_space=ps)
+    e = O.replay(db, ph, sp2, h_count=np.array([250, 0], np.uint64), phase_space=ps2)
+    assert np.array_equal(d["E"], e["E"])
+
+
+def test_phase_space_recycles_protons_with_new_tracks():
+    """History h of a listed source is proton h mod count: a second pass over
+    the list re-uses each proton (same start, same energy) on another track, so
+    its incident energies follow the protons while the tallies differ."""
+    db = I.make_water_track_db([100.0, 105.0], 400, seed=8)
+    ph = I.water_phantom((24, 24, 60), 0.25, origin=(-3.0, -3.0, 0.0))
+    rng = np.random.default_rng(3)
+    n = 64
+    pos = np.column_stack([rng.uniform(-1, 1, n), rng.uniform(-1, 1, n), np.full(n, -5.0)])
+    dirs = np.column_stack([rng.normal(0, 0.01, n), rng.normal(0, 0.01, n), np.ones(n)])
+    E = rng.uniform(100.5, 104.5, n)
+    ps = O.phase_space_sources(pos, dirs, E, db.bin_E, 0)
+    sp = I.spots([[0, 0, -5.0]], [[0, 0, 1.0]], [101.0], 0.0, n)
+    one = O.replay(db, ph, sp, h_count=np.array([n], np.uint64), phase_space=ps)
+    two = O.replay(db, ph, sp, h_count=np.array([2 * n], np.uint64), phase_space=ps)
+    second = O.replay(db, ph, sp, h_begin=np.array([n], np.uint64), h_count=np.array([n], np.uint64),
+                      phase_space=ps)
+    assert np.array_equal(two["E"], one["E"] + second["E"])
+    assert not np.array_equal(one["E"], second["E"])
+    xo, ro = O.endpoints(db, ph, sp, 0, 0, n, phase_space=ps)
+    x2, r2 = O.endpoints(db, ph, sp, 0, n, n, phase_space=ps)
+    assert np.all(ro == 0) and np.all(r2 == 0)                  # all stop inside (range < 15 cm of water)
+    assert not np.allclose(xo, x2)
