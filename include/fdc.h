@@ -271,6 +271,31 @@ int fdc_add_phase_space_file(fdc_ctx *ctx, int32_t plan, const char *path, uint3
 int fdc_run_histories(fdc_ctx *ctx, const int32_t *plans, uint32_t n_plans, uint32_t flags,
                       void *hip_stream);
 
+/* fdc_run_histories for callers that cannot allocate device memory (code under
+ * HIP graph capture, serving loops, harnesses that forbid hipMalloc): the same
+ * pass with the same kernels and bit-identical tallies, but its work table,
+ * persistent-queue counter and start-position lane table live in a scratch
+ * array of 32 MiB that the library holds statically on every device it runs
+ * on (until the process ends), and the work table is built on the device from
+ * the spot table, so the call allocates nothing, on the device or the host.
+ * Limits: at most 64 plans, 16384 spots with histories, and with
+ * source_order 1 at most 128,511 wave units (about 8.2e6 histories) per call.
+ * The plan and spot tables must be current: after loading phantoms or adding
+ * spots, call fdc_prepare_run (or any fdc_run_histories) first.  All calls of
+ * this function on one device share the scratch: calls that overlap in time
+ * on one GPU (different streams, or different contexts on one device) race;
+ * calls on one stream are ordered.  Asynchronous on hip_stream.  Errors: as
+ * fdc_run_histories, plus FDC_E_RANGE (beyond the limits above) and
+ * FDC_E_STATE (tables not current, no device). */
+int fdc_run_histories_noalloc(fdc_ctx *ctx, const int32_t *plans, uint32_t n_plans, uint32_t flags,
+                              void *hip_stream);
+
+/* Bring the device plan and spot tables up to date (may allocate; a no-op
+ * when nothing changed).  fdc_run_histories does this by itself.  Errors:
+ * FDC_E_ARG, FDC_E_NOMEM, FDC_E_HIP, FDC_E_RANGE / FDC_E_STATE (a spot no
+ * longer valid for the loaded database). */
+int fdc_prepare_run(fdc_ctx *ctx);
+
 /* Capture one fdc_run_histories pass over n_plans plans (plus, with options,
  * clearing the tallies first and computing dose and variance after) as a HIP
  * graph, for repeated launches with one call each.  The plans' spots, the

@@ -13,6 +13,7 @@
 #include <cstdio>
 #include <cstring>
 #include <limits>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -118,6 +119,8 @@ struct fdc_ctx {
 
     fdc_launch_config cfg{};
     hipStream_t cap_stream = nullptr;        // for graph capture
+    unsigned char *scratch = nullptr;        // this device's copy of the static run scratch
+    hipError_t scratch_err = hipSuccess;     // why it is missing
 
     // optional timing of the transport kernel: a ring of event pairs
     static constexpr uint32_t kTimeRing = 64;
@@ -421,6 +424,48 @@ bool grow(fdc_ctx *ctx, T *&buf, size_t &cap, size_t n, hipStream_t s)
     return true;
 }
 
+// ---- scratch of the allocation-free run --------------------------------------
+// fdc_run_histories_noalloc keeps its work table, persistent-queue counter and
+// start-position lane table in this statically allocated device array instead
+// of context buffers.  Every device the library runs on holds its own copy
+// until the process ends; host code reaches it only through the address
+// hipGetSymbolAddress returns for that device (taken once per device, with the
+// device current, when the first context on it is created).  Layout: the
+// queue counter at 0, kNoAllocMaxItems work items from 256, the lane table
+// (64 x 4 B per unit) after them.
+constexpr size_t kNoAllocBytes = 32u << 20;
+constexpr uint32_t kNoAllocMaxItems = 16384;
+constexpr size_t kNoAllocItemsOff = 256;
+constexpr size_t kNoAllocOrderOff = (kNoAllocItemsOff + kNoAllocMaxItems * sizeof(WorkItem) + 255) & ~(size_t)255;
+constexpr unsigned long long kNoAllocMaxOrderUnits = (kNoAllocBytes - kNoAllocOrderOff) / (kWave * sizeof(uint32_t));
+static_assert(kNoAllocOrderOff < kNoAllocBytes, "scratch layout");
+
+} // namespace
+
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+unsigned char *g_scratch_ptr[kMaxDevices] = {};
+
+// the current device's copy of the scratch array (ctx->device must be current)
+hipError_t scratch_address(int device, unsigned char **out)
+{
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        g_scratch_ptr[device] = (unsigned char *)p;
+    }
+    *out = g_scratch_ptr[device];
+    return hipSuccess;
+}
+
 } // namespace
 
 extern "C" {
@@ -448,6 +493,7 @@ int fdc_create(fdc_ctx **out, int hip_device, uint64_t seed, uint32_t reuse_R)
     }
     fdc_ctx *ctx = new (std::nothrow) fdc_ctx();
     if (!ctx) return FDC_E_NOMEM;
+    ctx->err.reserve(512);                   // error messages (< 512 chars) then never allocate
     ctx->device = hip_device;
     ctx->seed = seed;
     ctx->R = reuse_R;
@@ -462,6 +508,13 @@ int fdc_create(fdc_ctx **out, int hip_device, uint64_t seed, uint32_t reuse_R)
         (void)hipEventDestroy(ctx->items_ev);
         delete ctx;
         return FDC_E_HIP;
+    }
+    // this device's copy of the allocation-free run's scratch; on failure only
+    // that entry point is unavailable (it reports the error)
+    ctx->scratch_err = scratch_address(hip_device, &ctx->scratch);
+    if (ctx->scratch_err != hipSuccess) {
+        (void)hipGetLastError();
+        ctx->scratch = nullptr;
     }
     *out = ctx;
     return FDC_OK;
@@ -911,10 +964,16 @@ static int validate_run(fdc_ctx *ctx, const int32_t *plans, uint32_t n_plans, ui
     if (n_plans && !plans) return fail(ctx, FDC_E_ARG, "run: NULL plan list");
     if (flags & ~(uint32_t)(FDC_RUN_VARIANCE | FDC_RUN_ROTATE_TRACKS)) return fail(ctx, FDC_E_ARG, "run: unknown flag");
     if (ctx->n_bins == 0) return fail(ctx, FDC_E_STATE, "run: no track database loaded");
-    std::vector<char> seen(ctx->plans.size(), 0);
-    for (uint32_t i = 0; i < n_plans; ++i) {
+    for (uint32_t i = 0; i < n_plans; ++i)
         if (!valid_plan(ctx, plans[i])) return fail(ctx, FDC_E_ARG, "run: no plan %d", plans[i]);
-        if (seen[plans[i]]++) return fail(ctx, FDC_E_ARG, "run: plan %d listed twice", plans[i]);
+    if (n_plans <= kMaxRangePlans) {            // (no host allocation for short lists)
+        for (uint32_t i = 1; i < n_plans; ++i)
+            for (uint32_t j = 0; j < i; ++j)
+                if (plans[i] == plans[j]) return fail(ctx, FDC_E_ARG, "run: plan %d listed twice", plans[i]);
+    } else {
+        std::vector<char> seen(ctx->plans.size(), 0);
+        for (uint32_t i = 0; i < n_plans; ++i)
+            if (seen[plans[i]]++) return fail(ctx, FDC_E_ARG, "run: plan %d listed twice", plans[i]);
     }
     // overflow guard: every history deposits at most the largest bin energy
     const double emax = (double)to_fp(ctx->bin_E.back());
@@ -1107,6 +1166,80 @@ int fdc_run_histories(fdc_ctx *ctx, const int32_t *plans, uint32_t n_plans, uint
     HIPCHK(launch_advance(ctx->d_items, (uint32_t)items.size(), ctx->d_hnext, ctx->d_spots, ctx->d_plans, s));
     account_run(ctx, plans, n_plans, flags, false);
     return FDC_OK;
+}
+
+int fdc_run_histories_noalloc(fdc_ctx *ctx, const int32_t *plans, uint32_t n_plans, uint32_t flags, void *hip_stream)
+{
+    if (!ctx) return FDC_E_ARG;
+    int rc = validate_run(ctx, plans, n_plans, flags, 1);
+    if (rc) return rc;
+    if (ctx->dry) return fail(ctx, FDC_E_STATE, "run (no allocation): context has no device");
+    if (!ctx->scratch)
+        return fail(ctx, FDC_E_HIP, "run (no allocation): scratch address: %s", hipGetErrorString(ctx->scratch_err));
+    if (n_plans > kMaxRangePlans)
+        return fail(ctx, FDC_E_RANGE, "run (no allocation): at most %u plans per run, %u given", kMaxRangePlans, n_plans);
+    // the device plan and spot tables must be current: bringing them up to date may allocate
+    if (ctx->plans_dirty || ctx->spots_dirty)
+        return fail(ctx, FDC_E_STATE, "run (no allocation): plans or spots changed since the last run; "
+                    "call fdc_run_histories or fdc_prepare_run first");
+    // sizes of the work table (as build_items, without building it on the host)
+    unsigned long long n_items = 0, units = 0;
+    for (uint32_t i = 0; i < n_plans; ++i)
+        for (const fdc_spot &sp : ctx->plans[plans[i]].spots)
+            if (sp.n_histories) {
+                if (ctx->cfg.source_order && sp.n_histories >= 0xFFFFFFFFull)
+                    return fail(ctx, FDC_E_ARG, "run: source_order needs fewer than 2^32 histories per spot");
+                ++n_items;
+                units += units_for(sp.n_histories);
+            }
+    if (n_items == 0) return FDC_OK;
+    if (n_items > kNoAllocMaxItems)
+        return fail(ctx, FDC_E_RANGE, "run (no allocation): %llu spots with histories, at most %u",
+                    n_items, kNoAllocMaxItems);
+    if (ctx->cfg.source_order && units > kNoAllocMaxOrderUnits)
+        return fail(ctx, FDC_E_RANGE, "run (no allocation): start-position order of %llu wave units, the scratch "
+                    "holds %llu (about %llu histories); use source_order 0 or fdc_run_histories", units,
+                    kNoAllocMaxOrderUnits, kNoAllocMaxOrderUnits * 64);
+    HIPCHK(hipSetDevice(ctx->device));
+    hipStream_t s = S(hip_stream);
+    SpotRanges r{};
+    r.n = n_plans;
+    for (uint32_t i = 0; i < n_plans; ++i) {
+        r.first[i] = ctx->spot_base[plans[i]];
+        r.count[i] = (uint32_t)ctx->plans[plans[i]].spots.size();
+    }
+    unsigned long long *queue = (unsigned long long *)ctx->scratch;
+    WorkItem *d_items = (WorkItem *)(ctx->scratch + kNoAllocItemsOff);
+    uint32_t *d_order = (uint32_t *)(ctx->scratch + kNoAllocOrderOff);
+    HIPCHK(launch_build_items(ctx->d_spots, r, d_items, s));
+    TransportArgs a = base_args(ctx);
+    a.items = d_items;
+    a.n_items = (uint32_t)n_items;
+    a.n_units = units;
+    a.flags = flags;
+    if (ctx->cfg.source_order) {
+        unsigned long long chunks = 0;
+        for (uint32_t i = 0; i < n_plans; ++i)
+            for (const fdc_spot &sp : ctx->plans[plans[i]].spots) chunks += source_order_chunks(sp.n_histories);
+        HIPCHK(launch_source_order(d_items, (uint32_t)n_items, (uint32_t)chunks, units, ctx->d_spots, ctx->d_hnext,
+                                   (uint32_t)ctx->seed, (uint32_t)(ctx->seed >> 32), d_order, s));
+        a.order = d_order;
+    }
+    rc = enqueue_transport_kernel(ctx, a, flags, s, one_plan(plans, n_plans), queue);
+    if (rc) return rc;
+    HIPCHK(launch_advance(d_items, (uint32_t)n_items, ctx->d_hnext, ctx->d_spots, ctx->d_plans, s));
+    account_run(ctx, plans, n_plans, flags, false);
+    return FDC_OK;
+}
+
+int fdc_prepare_run(fdc_ctx *ctx)
+{
+    if (!ctx) return FDC_E_ARG;
+    if (ctx->dry) return FDC_OK;
+    HIPCHK(hipSetDevice(ctx->device));
+    int rc = ensure_plans(ctx);
+    if (!rc) rc = ensure_spots(ctx);
+    return rc;
 }
 
 int fdc_set_timing(fdc_ctx *ctx, int on)

@@ -145,6 +145,81 @@ __global__ void advance_kernel(const WorkItem *__restrict__ items, uint32_t n_it
     atomicAdd(plans[spots[it.gspot].plan].acc + 3, it.n);
 }
 
+// Work table of a run built on the device: one workgroup walks the listed
+// spots in range order, each thread a contiguous run of them; a spot with
+// histories becomes an item whose unit, history and ordering-chunk offsets are
+// exclusive prefix sums (per thread, then across the workgroup's lanes and
+// waves) of units_for(n), n and source_order_chunks(n).
+constexpr uint32_t kItemThreads = 1024;
+
+struct ItemSums {
+    unsigned long long items, hist, units, chunks;
+};
+
+__device__ inline ItemSums wave_scan_incl(ItemSums v, uint32_t lane)
+{
+#pragma unroll
+    for (uint32_t off = 1; off < kWave; off <<= 1) {
+        const unsigned long long a = __shfl_up(v.items, off, kWave), b = __shfl_up(v.hist, off, kWave);
+        const unsigned long long c = __shfl_up(v.units, off, kWave), d = __shfl_up(v.chunks, off, kWave);
+        if (lane >= off) { v.items += a; v.hist += b; v.units += c; v.chunks += d; }
+    }
+    return v;
+}
+
+__global__ void __launch_bounds__(kItemThreads) build_items_kernel(const DevSpot *__restrict__ spots, SpotRanges r,
+                                                                   WorkItem *__restrict__ items)
+{
+    __shared__ ItemSums s_wave[kItemThreads / kWave];
+    const uint32_t t = threadIdx.x, lane = t & (kWave - 1), wave = t / kWave;
+    uint32_t total = 0;
+    for (uint32_t i = 0; i < r.n; ++i) total += r.count[i];
+    const uint32_t per = (total + kItemThreads - 1) / kItemThreads;
+    const uint32_t j0 = min(total, t * per), j1 = min(total, j0 + per);
+    // the DevSpot index of list position j
+    auto gspot_of = [&](uint32_t j) {
+        uint32_t i = 0;
+        while (j >= r.count[i]) { j -= r.count[i]; ++i; }
+        return r.first[i] + j;
+    };
+    ItemSums mine{0, 0, 0, 0};
+    for (uint32_t j = j0; j < j1; ++j) {
+        const unsigned long long n = spots[gspot_of(j)].n_hist;
+        if (!n) continue;
+        mine.items += 1;
+        mine.hist += n;
+        mine.units += units_for(n);
+        mine.chunks += source_order_chunks(n);
+    }
+    const ItemSums incl = wave_scan_incl(mine, lane);
+    if (lane == kWave - 1) s_wave[wave] = incl;
+    __syncthreads();
+    ItemSums run{incl.items - mine.items, incl.hist - mine.hist, incl.units - mine.units, incl.chunks - mine.chunks};
+    for (uint32_t w = 0; w < wave; ++w) {
+        run.items += s_wave[w].items;
+        run.hist += s_wave[w].hist;
+        run.units += s_wave[w].units;
+        run.chunks += s_wave[w].chunks;
+    }
+    for (uint32_t j = j0; j < j1; ++j) {
+        const uint32_t g = gspot_of(j);
+        const unsigned long long n = spots[g].n_hist;
+        if (!n) continue;
+        WorkItem w{};
+        w.h0 = 0;                              // the spot's device counter is added
+        w.n = n;
+        w.unit0 = run.units;
+        w.first = run.hist;
+        w.gspot = g;
+        w.chunk0 = (uint32_t)run.chunks;
+        items[run.items] = w;
+        run.items += 1;
+        run.hist += n;
+        run.units += units_for(n);
+        run.chunks += source_order_chunks(n);
+    }
+}
+
 __global__ void fill_u64_kernel(unsigned long long *__restrict__ p, size_t n, unsigned long long value)
 {
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
@@ -250,6 +325,12 @@ hipError_t launch_vacuum_skip(uint16_t *idx, const float2 *lut, int nx, int ny, 
     hipLaunchKernelGGL(skip_seed_kernel, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, idx, lut, n);
     for (uint32_t pass = 0; pass < kMaxSkip; ++pass)
         hipLaunchKernelGGL(skip_relax_kernel, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, idx, nx, ny, nz);
+    return hipGetLastError();
+}
+
+hipError_t launch_build_items(const DevSpot *spots, const SpotRanges &r, WorkItem *items, hipStream_t s)
+{
+    hipLaunchKernelGGL(build_items_kernel, dim3(1), dim3(kItemThreads), 0, s, spots, r, items);
     return hipGetLastError();
 }
 

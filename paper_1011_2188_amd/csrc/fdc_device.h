@@ -84,6 +84,23 @@ __host__ __device__ inline unsigned long long units_for(unsigned long long n)
     return n ? (n + 62) / 64 + 1 : 0;
 }
 
+// start-position order: a spot's histories are ordered in chunks of this many
+// (a multiple of the 64-history unit), one ordering workgroup per chunk
+constexpr uint32_t kOrderChunk = 16384;
+__host__ __device__ inline unsigned long long source_order_chunks(unsigned long long n)
+{
+    return (n + kOrderChunk - 1) / kOrderChunk;
+}
+
+// The spots of one run as ranges of the DevSpot array (one per listed plan),
+// for the work table built on the device (allocation-free runs).
+constexpr uint32_t kMaxRangePlans = 64;
+struct SpotRanges {
+    uint32_t n;                          // ranges used
+    uint32_t first[kMaxRangePlans];      // first DevSpot index of each listed plan
+    uint32_t count[kMaxRangePlans];      // its spots
+};
+
 struct TransportArgs {
     const float4 *steps;                 // per step: (dx, fixed-point dE as int32 bits,
                                          // theta cos phi, theta sin phi), made at load
@@ -246,13 +263,15 @@ hipError_t launch_track_energy(const float4 *steps, const unsigned long long *of
 hipError_t launch_dose(const uint16_t *idx, const unsigned long long *E, const unsigned long long *E2,
                        const float2 *lut, const float *rho_lut, size_t nvox, double voxel_volume_cm3,
                        const unsigned long long *n_hist, double *dose, double *var, hipStream_t s);
-// processing order of a run's histories by start position (order.hip):
-// ordering chunks of an item of n histories, and the launch (fill of the
-// per-unit lane table, one workgroup per chunk)
-uint32_t source_order_chunks(unsigned long long n);
+// processing order of a run's histories by start position (order.hip): the
+// launch (fill of the per-unit lane table, one workgroup per chunk)
 hipError_t launch_source_order(const WorkItem *items, uint32_t n_items, uint32_t n_chunks, unsigned long long n_units,
                                const DevSpot *spots, const unsigned long long *hnext, uint32_t seed_lo,
                                uint32_t seed_hi, uint32_t *order, hipStream_t s);
+// the work table of a run over the spots of `r` (every spot with histories,
+// in range order), built by one workgroup from the spots' n_hist; the same
+// items the host builds for fdc_run_histories
+hipError_t launch_build_items(const DevSpot *spots, const SpotRanges &r, WorkItem *items, hipStream_t s);
 hipError_t launch_advance(const WorkItem *items, uint32_t n_items, unsigned long long *hnext, const DevSpot *spots,
                           const DevPlan *plans, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long *p, size_t n, unsigned long long value, hipStream_t s);

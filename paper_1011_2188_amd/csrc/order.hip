@@ -29,7 +29,7 @@ namespace fdc {
 
 namespace {
 
-constexpr uint32_t kChunk = 16384;          // histories per ordering workgroup (256 units)
+constexpr uint32_t kChunk = kOrderChunk;    // histories per ordering workgroup (256 units)
 constexpr uint32_t kThreads = 1024;
 constexpr uint32_t kPer = kChunk / kThreads; // histories per thread
 constexpr uint32_t kMaxHalfBits = 6;        // up to 64 x 64 cells
@@ -140,11 +140,6 @@ __global__ void __launch_bounds__(kThreads) order_chunk_kernel(const WorkItem *_
 }
 
 } // namespace
-
-uint32_t source_order_chunks(unsigned long long n)
-{
-    return (uint32_t)((n + kChunk - 1) / kChunk);
-}
 
 hipError_t launch_source_order(const WorkItem *items, uint32_t n_items, uint32_t n_chunks, unsigned long long n_units,
                                const DevSpot *spots, const unsigned long long *hnext, uint32_t seed_lo,

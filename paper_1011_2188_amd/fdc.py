@@ -29,7 +29,7 @@ ERROR_NAMES = {0: "FDC_OK", -1: "FDC_E_ARG", -2: "FDC_E_STATE", -3: "FDC_E_NOMEM
 # every entry point declared in include/fdc.h
 EXPORTS = ["fdc_create", "fdc_destroy", "fdc_last_error", "fdc_set_allocator", "fdc_set_hu_table",
            "fdc_load_track_db", "fdc_load_track_db_file", "fdc_load_phantom", "fdc_add_beam_spots", "fdc_add_phase_space",
-           "fdc_add_phase_space_file", "fdc_run_histories",
+           "fdc_add_phase_space_file", "fdc_run_histories", "fdc_run_histories_noalloc", "fdc_prepare_run",
            "fdc_reset_plan", "fdc_compute_dose", "fdc_read_dose_and_variance", "fdc_debug_endpoints",
            "fdc_debug_philox", "fdc_debug_material", "fdc_set_launch_config", "fdc_device_cus",
            "fdc_mean_uncertainty", "fdc_batch_uncertainty", "fdc_gamma_index",
@@ -89,6 +89,8 @@ def lib():
         "fdc_add_phase_space": (C.c_int, [_P, C.c_int32, _P, C.c_uint64, C.POINTER(C.c_uint32), _P]),
         "fdc_add_phase_space_file": (C.c_int, [_P, C.c_int32, C.c_char_p, C.POINTER(C.c_uint32), _P]),
         "fdc_run_histories": (C.c_int, [_P, _P, C.c_uint32, C.c_uint32, _P]),
+        "fdc_run_histories_noalloc": (C.c_int, [_P, _P, C.c_uint32, C.c_uint32, _P]),
+        "fdc_prepare_run": (C.c_int, [_P]),
         "fdc_reset_plan": (C.c_int, [_P, C.c_int32, C.c_int, _P]),
         "fdc_compute_dose": (C.c_int, [_P, C.c_int32, _P, _P, _P]),
         "fdc_read_dose_and_variance": (C.c_int, [_P, C.c_int32, _P, _P, _P, _P, C.POINTER(fdc_summary), _P]),
@@ -305,6 +307,13 @@ class Context:
     def run_histories(self, plans, flags=FDC_RUN_VARIANCE, stream=None):
         p = np.ascontiguousarray(np.atleast_1d(plans), np.int32)
         _check(self.h, lib().fdc_run_histories(self.h, p.ctypes.data, p.size, flags, _stream(stream)))
+
+    def run_histories_noalloc(self, plans, flags=FDC_RUN_VARIANCE, stream=None):
+        p = np.ascontiguousarray(np.atleast_1d(plans), np.int32)
+        _check(self.h, lib().fdc_run_histories_noalloc(self.h, p.ctypes.data, p.size, flags, _stream(stream)))
+
+    def prepare_run(self):
+        _check(self.h, lib().fdc_prepare_run(self.h))
 
     def reset_plan(self, plan, rewind=False, stream=None):
         _check(self.h, lib().fdc_reset_plan(self.h, plan, int(bool(rewind)), _stream(stream)))

@@ -113,6 +113,12 @@ def test_spots_and_run_validation(ctx):
     _expect(F.FDC_E_ARG, ctx.run_histories, [3])
     _expect(F.FDC_E_ARG, ctx.run_histories, [p], 1 << 5)
     ctx.run_histories([p], 0)
+    # the allocation-free run checks its arguments as the run does, then needs a device
+    _expect(F.FDC_E_ARG, ctx.run_histories_noalloc, [p, p])
+    _expect(F.FDC_E_ARG, ctx.run_histories_noalloc, [3])
+    _expect(F.FDC_E_ARG, ctx.run_histories_noalloc, [p], 1 << 5)
+    ctx.prepare_run()
+    _expect(F.FDC_E_STATE, ctx.run_histories_noalloc, [p], 0)
     # reading needs a device; a variance read after a run without the flag is refused first
     _expect(F.FDC_E_STATE, ctx.read_dose_and_variance, p, True, True)
     _expect(F.FDC_E_STATE, ctx.read_dose_and_variance, p, True, False)
