@@ -14,10 +14,21 @@ parameter gradient:
     one unit of the last place away after FP32 accumulation in another order),
     parameter gradients within 1e-3 of themselves plus 1e-4 of the RMS;
   * end to end: the oracle's whole forward and backward pass from the same
-    input - 99.9% of the elements within 2^-7 of themselves plus 1e-3 of the
-    buffer's RMS, and every element within 2^-7 of itself plus 1e-2 of the
-    RMS (a bf16 value one unit of the last place apart upstream moves the
-    values computed from it downstream).
+    input.  A bf16 value one unit in the last place apart upstream (FP32
+    accumulation in another order lands on the other side of a rounding
+    boundary) moves every value computed from it downstream, and such flips
+    multiply from layer to layer (an output depends on 27 x C rounded inputs),
+    so after a few layers most values differ by some units in the last place.
+    The tolerance is therefore the oracle's own spread: a second oracle pass in
+    which every stored activation and gradient is perturbed by a relative
+    2^-24 N(0, 1) before its bf16 rounding (FP32's unit roundoff; the spread
+    it produces downstream hardly depends on that size, since the flips
+    saturate) gives the differences its arithmetic admits.  A
+    buffer passes if 99.9% of its elements are within 2^-7 of themselves plus
+    1e-3 of the RMS and all within 2^-7 of themselves plus 1e-2 of the RMS (no
+    cascade), or if its differences from the oracle are no larger than the
+    perturbed pass's: RMS and 99.9th percentile within 2x, largest within 4x
+    (plus 1e-4 of the buffer's RMS).
 The 2 x 2 x 2 average pools are exact: bf16 of the FP32 mean of the eight
 bf16 children."""
 import numpy as np
@@ -77,7 +88,33 @@ def run():
     d = yo - t.astype(np.float64)
     acts = {}
     G = U.backward(cache, 2.0 * d / d.size, bf16=True, acts=acts)
-    return dict(gpu=out, W=cache["W"], cache=cache, yo=yo, G=G, acts=acts, x=xo, t=t.astype(np.float64))
+    pert = _perturbed_pass(Wf, xo, t.astype(np.float64))
+    return dict(gpu=out, W=cache["W"], cache=cache, yo=yo, G=G, acts=acts, x=xo, t=t.astype(np.float64), pert=pert)
+
+
+def _perturbed_pass(Wf, xo, t):
+    """The oracle's forward and backward pass with every value it stores as
+    bf16 first perturbed by a relative 2^-24 N(0, 1) (FP32's unit roundoff).
+    Weights and input are rounded beforehand, so the perturbation (far below
+    half a unit in the last place) leaves them as they are."""
+    rng = np.random.default_rng(77)
+    exact = U.bf16_round
+    Wr = {n: (exact(w), b) for n, (w, b) in Wf.items()}
+    xr = np.stack([exact(xo[0]), exact(xo[1])])
+
+    def noisy(a):
+        a = np.asarray(a, np.float64)
+        return exact(a * (1.0 + 2.0 ** -24 * rng.standard_normal(a.shape)))
+    U.bf16_round = noisy
+    try:
+        yp, cp = U.forward(Wr, xr, bf16=True)
+        yp = yp - xr[0] + xo[0]                        # the residual adds the unrounded input
+        dp = yp - t
+        acts = {}
+        G = U.backward(cp, 2.0 * dp / dp.size, bf16=True, acts=acts)
+    finally:
+        U.bf16_round = exact
+    return dict(cache=cp, yo=yp, acts=acts, G=G)
 
 
 def _cf(buf, lvl, c0, c1):
@@ -93,17 +130,27 @@ def _check(name, got, want, rel, abs_frac):
     assert worst <= 1.0, name
 
 
-def _check_cascade(name, got, want, failures):
-    """End to end: 99.9% of the elements within 2^-7 of themselves plus 1e-3 of
-    the RMS, and every element within 2^-7 of itself plus 1e-2 of the RMS."""
+def _check_cascade(name, got, want, pert, failures):
+    """End to end (see the module notes): within one unit in the last place
+    (99.9% within 2^-7 |x| + 1e-3 RMS, all within 2^-7 |x| + 1e-2 RMS), or no
+    larger than the perturbed oracle pass's differences (`pert`): RMS and
+    99.9th percentile within 2x, largest within 4x, plus 1e-4 RMS."""
     r = np.abs(got - want)
-    tight = 2.0 ** -7 * np.abs(want) + 1e-3 * _rms(want) + 1e-30
-    loose = 2.0 ** -7 * np.abs(want) + 1e-2 * _rms(want) + 1e-30
+    rp = np.abs(pert - want)
+    rms = _rms(want)
+    tight = 2.0 ** -7 * np.abs(want) + 1e-3 * rms + 1e-30
+    loose = 2.0 ** -7 * np.abs(want) + 1e-2 * rms + 1e-30
     frac = float(np.mean(r <= tight))
-    worst_t, worst_l = float(np.max(r / tight)), float(np.max(r / loose))
-    print(f"{name}: {frac:.6f} of elements within the tight bound (worst {worst_t:.2f}), "
-          f"worst at {worst_l:.3f} of the loose bound")
-    if frac < 0.999 or worst_l > 1.0:
+    worst_l = float(np.max(r / loose))
+    stats = [(_rms(r), _rms(rp)), (float(np.quantile(r, 0.999)), float(np.quantile(rp, 0.999))),
+             (float(r.max()), float(rp.max()))]
+    ratios = [a / (b + 1e-4 * rms + 1e-300) for a, b in stats]
+    print(f"{name}: {frac:.6f} within one ulp, worst at {worst_l:.3f} of the loose bound; against the "
+          f"perturbed oracle: rms {stats[0][0]:.3e}/{stats[0][1]:.3e}, q99.9 {stats[1][0]:.3e}/{stats[1][1]:.3e}, "
+          f"max {stats[2][0]:.3e}/{stats[2][1]:.3e}")
+    one_ulp = frac >= 0.999 and worst_l <= 1.0
+    spread = ratios[0] <= 2.0 and ratios[1] <= 2.0 and ratios[2] <= 4.0
+    if not (one_ulp or spread):
         failures.append(name)
 
 
@@ -160,11 +207,12 @@ def test_forward_layer_by_layer(run):
 
 
 def test_forward_end_to_end(run):
-    g, c = run["gpu"], run["cache"]
+    g, c, pc = run["gpu"], run["cache"], run["pert"]["cache"]
     bad = []
     for name in ACT:
-        _check_cascade(f"{name} (end to end)", act(g, name), c[name], bad)
-    _check_cascade("y (end to end)", g["y"] - run["x"][0], run["yo"] - run["x"][0], bad)
+        _check_cascade(f"{name} (end to end)", act(g, name), c[name], pc[name], bad)
+    _check_cascade("y (end to end)", g["y"] - run["x"][0], run["yo"] - run["x"][0],
+                   run["pert"]["yo"] - run["x"][0], bad)
     assert not bad, bad
 
 
@@ -208,7 +256,7 @@ def test_backward_data_end_to_end(run):
     g = run["gpu"]
     bad = []
     for name in GRAD:
-        _check_cascade(f"{name} (end to end)", grad(g, name), run["acts"][name], bad)
+        _check_cascade(f"{name} (end to end)", grad(g, name), run["acts"][name], run["pert"]["acts"][name], bad)
     assert not bad, bad
 
 
@@ -249,7 +297,8 @@ def test_parameter_gradients_end_to_end(run):
     bad = []
     for name, kind, ci, co in U.LAYERS:
         gw, gb = run["G"][name]
+        pw, pb = run["pert"]["G"][name]
         o, nw, _ = offs[name]
-        _check_cascade(f"{name} weights (end to end)", run["gpu"]["grads"][o:o + nw].reshape(gw.shape), gw, bad)
-        _check_cascade(f"{name} biases (end to end)", run["gpu"]["grads"][o + nw:o + nw + co], gb, bad)
+        _check_cascade(f"{name} weights (end to end)", run["gpu"]["grads"][o:o + nw].reshape(gw.shape), gw, pw, bad)
+        _check_cascade(f"{name} biases (end to end)", run["gpu"]["grads"][o + nw:o + nw + co], gb, pb, bad)
     assert not bad, bad
