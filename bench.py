@@ -235,6 +235,31 @@ def extras(c, plan, nvox, hist_per_step, launch, variance):
     return out
 
 
+WEIGHTS = os.path.join(ROOT, "paper_1011_2188_amd", "weights", "denoiser_thorax.npz")
+
+
+def denoised_route(c, ph, sp, plain_plan, plain_dose, n2, rate):
+    """The denoised half of the metric on this workload: G* = gamma pass rate
+    (2%/2 mm) of the plain dose at N_2% (the verification run) against an
+    independent reference of 4e8 histories; the trained denoiser (parameters
+    from the full-scale training study, if present) on doses of N_2% * {1/64,
+    ..., 1} histories; seconds = the first rung reaching G*, at this run's
+    histories/s, plus the measured inference time.  Untimed for `value`."""
+    from paper_1011_2188_amd import denoise as D
+    if not os.path.exists(WEIGHTS):
+        return {"seconds_to_2pct_denoised": None,
+                "denoised": {"note": "no trained denoiser parameters (run the training study first)"}}
+    params, meta = D.load_params(WEIGHTS)
+    t = time.perf_counter()
+    r = D.gamma_ladder(c, ph, sp, params, n2, rate, ref_total=400_000_000, plain=(plain_plan, plain_dose),
+                       log=log)
+    log(f"denoised route: G* {r['G_star']:.5f}, N_d {r['N_denoised']}, t_den {r['t_denoised_s']} "
+        f"({time.perf_counter() - t:.1f} s)")
+    r["weights"] = {k: meta[k] for k in ("train_plans", "input_histories", "target_histories", "steps")
+                    if k in meta}
+    return {"seconds_to_2pct_denoised": r["t_denoised_s"], "denoised": r}
+
+
 def host_cpu():
     model = "unknown"
     try:
@@ -399,6 +424,7 @@ def main():
         out["verify_2pct"] = {"histories": n2_run, "mean_uncertainty": u2, "seconds": min(times),
                               "in_band": bool(0.019 <= u2 <= 0.021)}
         log(f"verification: {n2_run} histories -> {u2:.4%} in {min(times):.4g} s")
+        out.update(denoised_route(c, ph, sp, plan2, dose.clone(), n2_run, value))
 
     so = launch.get("source_order", 0)
     bph = bytes_per_history(COUNTS["thorax"], variance)

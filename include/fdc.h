@@ -100,12 +100,37 @@ typedef struct {
     float reserved;       /* 0 */
 } fdc_particle;
 
+/* A beam-line device upstream of the phantom: an aperture and a range
+ * compensator on one pixel grid (Section 4: the CPU code described them with
+ * a general geometry package, the GPU code handled voxels only).  Its
+ * upstream face is the plane through origin_cm perpendicular to dir (along
+ * the beam, any length > 0); the grid of n[0] x n[1] pixels of pitch_cm is
+ * centred on origin_cm along the lateral axes (e1, e2) of dir, defined as for
+ * a spot.  A history crosses the face where its ray from the start point
+ * meets it; through a closed pixel, off the grid, or if the face is not ahead
+ * of it, the history stops there.  Through an open pixel with compensator
+ * thickness T > 0 its track is replayed through a slab of the compensator's
+ * material until its displacement along dir reaches T - water-equivalent
+ * length consumed at geometric length WEL / rsp, deflections scaled by
+ * sqrt(rscp / rsp), as in a voxel - and goes on towards the phantom from the
+ * slab's exit face, in the middle of a stored step if it leaves there.
+ * Energy deposited in the compensator, and all energy of a history stopped by
+ * the device, is not deposited in the phantom: it counts as escaped. */
+typedef struct {
+    float origin_cm[3];
+    float dir[3];
+    float pitch_cm[2];
+    uint32_t n[2];
+    float rsp, rscp;      /* compensator material, > 0 (used where a pixel has T > 0) */
+} fdc_beam_device;
+
 typedef struct {
     uint64_t n_histories;  /* histories run on the plan since its last reset          */
     int64_t incident_fp;   /* sum of incident energies, 2^-24 MeV                      */
     int64_t deposited_fp;  /* sum of the energy tally                                  */
-    int64_t escaped_fp;    /* energy carried out of the phantom box; deposited+escaped
-                              equals incident exactly                                 */
+    int64_t escaped_fp;    /* energy not deposited in the phantom: carried out of the
+                              box, or stopped or absorbed upstream by a beam-line
+                              device; deposited+escaped equals incident exactly      */
 } fdc_summary;
 
 /* launch knobs; none of them changes any result bit */
@@ -229,6 +254,22 @@ int fdc_load_phantom(fdc_ctx *ctx, int32_t *plan_out, const int16_t *hu, int nx,
  * database loaded). */
 int fdc_add_beam_spots(fdc_ctx *ctx, int32_t plan, const fdc_spot *spots, uint32_t n);
 
+/* Add a beam-line device (see fdc_beam_device) to the context: pixels[n[0] *
+ * n[1]] (host, e1 fastest) hold < 0 for a closed pixel, else the compensator
+ * thickness in cm (0: open, no material).  Copied to the device before the
+ * call returns.  *device_out receives its id (0, 1, ...).  Errors: FDC_E_ARG
+ * (NULL, non-finite values, zero dir, pitch or grid size <= 0, more than 2^26
+ * pixels, rsp or rscp <= 0 where a pixel has material), FDC_E_NOMEM,
+ * FDC_E_HIP. */
+int fdc_add_beam_device(fdc_ctx *ctx, const fdc_beam_device *device, const float *pixels, int32_t *device_out,
+                        void *hip_stream);
+
+/* Spots first_spot .. first_spot+n_spots-1 of a plan pass device `device`
+ * (-1: none, the default) on their way to the phantom.  Applies to later
+ * runs.  Errors: FDC_E_ARG (bad plan, spot range or device id, or a source of
+ * listed protons in the range). */
+int fdc_set_spot_device(fdc_ctx *ctx, int32_t plan, uint32_t first_spot, uint32_t n_spots, int32_t device);
+
 /* Append a phase space of n protons to a plan (Section 2.3: incident protons
  * read from a file).  The protons are grouped by energy bin (the smallest bin
  * energy >= the proton's energy), bins in increasing order, list order kept
@@ -279,7 +320,7 @@ int fdc_run_histories(fdc_ctx *ctx, const int32_t *plans, uint32_t n_plans, uint
  * on (until the process ends), and the work table is built on the device from
  * the spot table, so the call allocates nothing, on the device or the host.
  * Limits: at most 64 plans, 16384 spots with histories, and with
- * source_order 1 at most 128,511 wave units (about 8.2e6 histories) per call.
+ * source_order 1 at most 120,709 wave units (about 7.7e6 histories) per call.
  * The plan and spot tables must be current: after loading phantoms or adding
  * spots, call fdc_prepare_run (or any fdc_run_histories) first.  All calls of
  * this function on one device share the scratch: calls that overlap in time
@@ -344,7 +385,8 @@ int fdc_read_dose_and_variance(fdc_ctx *ctx, int32_t plan, double *dose_gy_per_p
 
 /* Replay histories h0 .. h0+n-1 of spot `spot` of a plan without tallying and
  * return their end points (host xyz_out[3n], cm) and end reasons (host
- * reason_out[n]: 0 stopped, 1 escaped the phantom, 2 missed it).  Uses the
+ * reason_out[n]: 0 stopped, 1 escaped the phantom, 2 missed it, 3 stopped
+ * upstream of it by a beam-line device).  Uses the
  * same kernel code as fdc_run_histories.  Synchronises hip_stream.
  * Errors: FDC_E_ARG, FDC_E_STATE, FDC_E_HIP. */
 int fdc_debug_endpoints(fdc_ctx *ctx, int32_t plan, uint32_t spot, uint64_t h0, uint32_t n,

@@ -182,6 +182,18 @@ typedef struct {
      * NULL: every source is a spot. */
     const uint64_t *ps_first, *ps_count;
     const float *ps_pos, *ps_dir, *ps_E;
+    /* beam-line devices upstream of the phantom (an aperture and a range
+     * compensator on one pixel grid; the GPU code of the paper had none,
+     * Section 4): spot s passes device spot_dev[s] (-1: none).  Device i:
+     * dev_par[16 i ..] = upstream-face centre (3), face normal along the beam
+     * (3), pixel pitch along the normal's lateral axes e1, e2 (2), pixels
+     * along e1, e2 (2), compensator RSP and RScP (2); its pixels (e1 fastest)
+     * are dev_pix[dev_pix_off[i] ..]: < 0 closed, else the compensator
+     * thickness (cm, along the normal).  NULL: no devices. */
+    const int32_t *spot_dev;
+    const double *dev_par;
+    const float *dev_pix;
+    const uint64_t *dev_pix_off;
     /* run */
     uint32_t plan;
     uint64_t seed;
@@ -263,7 +275,138 @@ static void flush(const oracle_problem *P, oracle_tally *T, size_t v, int64_t *a
     *acc = 0;
 }
 
-enum { END_STOP = 0, END_ESCAPE = 1, END_MISS = 2 };
+enum { END_STOP = 0, END_ESCAPE = 1, END_MISS = 2, END_UPSTREAM = 3 };
+
+/* Step k of the track as replayed: water-equivalent length, energy (fixed
+ * point), polar and azimuthal deflection.  The first replayed step k0 is the
+ * part of step k0 left below the spot energy (fraction f of its energy):
+ * length f dx, angle theta sqrt(f) (Highland's sqrt of the length), azimuth
+ * turned by phi0 (track rotation). */
+static void step_params(const float *st, uint64_t k, uint64_t k0, int64_t cum, int64_t skip, double phi0,
+                        double *w_tot, int64_t *e, double *theta, double *phi)
+{
+    *w_tot = st[4 * k + 0];
+    *theta = st[4 * k + 2];
+    *phi = st[4 * k + 3];
+    *e = fp_energy(st[4 * k + 1]);
+    if (k == k0) {
+        int64_t e_first = cum + *e - skip;
+        double f = (double)e_first / (double)*e;
+        *e = e_first;
+        *w_tot *= f;
+        *theta *= sqrt(f);
+        *phi += phi0;
+    }
+}
+
+/* Where a history stands when it reaches the phantom: the step being
+ * replayed and how much of it is done (WEL consumed, energy deposited so far
+ * in fixed point, sum of w G), its beam-frame direction, and the energy
+ * deposited upstream of the phantom. */
+typedef struct {
+    uint64_t k;
+    double tau, g2;
+    int64_t dep;
+    double db[3];
+    int64_t up_dep;
+} replay_state;
+
+/* The beam-line device dv (see oracle_problem) on the history's way: the ray
+ * from pos along d meets the device's upstream face at one pixel; a closed
+ * pixel, a pixel off the grid, or a face not ahead of the start point
+ * (direction not towards it) stops the history there.  An open pixel with a
+ * compensator thickness T > 0: the track is replayed through a slab of the
+ * compensator's material from that point until the displacement along the
+ * normal reaches T - each step's WEL consumed at geometric length WEL / RSP,
+ * its energy split uniformly in WEL with the telescoping rounding, the
+ * deflection at the step end scaled by sqrt(sum w G / WEL) with G = RScP/RSP,
+ * as in a voxel (the slab's thickness is the one of the pixel it was entered
+ * through).  The energy deposited there is absorbed upstream.  Returns 1 if
+ * the history ends on or in the device (blocked, or its track ends in the
+ * compensator), else 0 with pos, d and the state at the exit face. */
+static int device_pass(const oracle_problem *P, int dv, const float *st, uint64_t n_steps, uint64_t k0,
+                       int64_t cum, int64_t skip, double phi0, double M[3][3], double pos[3], double d[3],
+                       replay_state *S)
+{
+    const double *q = P->dev_par + 16 * dv;
+    double o[3] = {q[0], q[1], q[2]}, nrm[3] = {q[3], q[4], q[5]};
+    double nl = sqrt(nrm[0] * nrm[0] + nrm[1] * nrm[1] + nrm[2] * nrm[2]);
+    for (int a = 0; a < 3; ++a) nrm[a] /= nl;
+    double u1[3], u2[3];
+    field_frame(nrm, u1, u2);
+    const long n0 = (long)q[8], n1 = (long)q[9];
+    const double rsp = q[10], g = q[11] / q[10];
+    double dn = d[0] * nrm[0] + d[1] * nrm[1] + d[2] * nrm[2];
+    double t = ((o[0] - pos[0]) * nrm[0] + (o[1] - pos[1]) * nrm[1] + (o[2] - pos[2]) * nrm[2]);
+    if (!(dn > 0.0) || t < 0.0) return 1;
+    t /= dn;
+    for (int a = 0; a < 3; ++a) pos[a] += t * d[a];
+    double ra = 0.0, rb = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        ra += (pos[a] - o[a]) * u1[a];
+        rb += (pos[a] - o[a]) * u2[a];
+    }
+    double fi = floor(ra / q[6] + 0.5 * (double)n0), fj = floor(rb / q[7] + 0.5 * (double)n1);
+    if (fi < 0.0 || fj < 0.0 || fi >= (double)n0 || fj >= (double)n1) return 1;
+    double thick = P->dev_pix[P->dev_pix_off[dv] + (uint64_t)fj * (uint64_t)n0 + (uint64_t)fi];
+    if (thick < 0.0) return 1;
+    if (thick == 0.0) return 0;
+    double z = 0.0; /* displacement along the normal inside the slab */
+    for (uint64_t k = k0; k < n_steps; ++k) {
+        double w_tot, theta, phi;
+        int64_t e;
+        step_params(st, k, k0, cum, skip, phi0, &w_tot, &e, &theta, &phi);
+        double tau = 0.0, g2 = 0.0;
+        int64_t dep = 0;
+        int on_face = 0;            /* the step ended exactly on the exit face */
+        while (tau < w_tot) {
+            dn = d[0] * nrm[0] + d[1] * nrm[1] + d[2] * nrm[2];
+            double lgeo = dn > 0.0 ? (thick - z) / dn : INFINITY;
+            if (lgeo < 0.0) lgeo = 0.0;
+            double rem = w_tot - tau, wb = lgeo * rsp, w_v, tau_n, move;
+            int exits;
+            if (rem <= wb) { /* the step ends in the slab (or on its exit face) */
+                w_v = rem;
+                tau_n = w_tot;
+                move = rem / rsp;
+                exits = (rem == wb);
+            } else {
+                w_v = wb;
+                tau_n = tau + wb;
+                move = lgeo;
+                exits = 1;
+            }
+            int64_t cumk = (int64_t)nearbyint((double)e * (tau_n / w_tot));
+            if (tau_n >= w_tot) cumk = e;
+            S->up_dep += cumk - dep;
+            dep = cumk;
+            g2 += w_v * g;
+            tau = tau_n;
+            for (int a = 0; a < 3; ++a) pos[a] += move * d[a];
+            z += move * dn;
+            if (exits && tau < w_tot) { /* out through the exit face inside the step */
+                S->k = k;
+                S->tau = tau;
+                S->g2 = g2;
+                S->dep = dep;
+                return 0;
+            }
+            on_face = exits;
+        }
+        /* deflection at the end of the step; a step ending exactly on the exit
+         * face ends in the slab and the next one starts beyond it */
+        rotate(S->db, theta * sqrt(g2 / w_tot), phi);
+        for (int a = 0; a < 3; ++a) d[a] = M[a][0] * S->db[0] + M[a][1] * S->db[1] + M[a][2] * S->db[2];
+        if (on_face) {
+            S->k = k + 1;
+            S->tau = 0.0;
+            S->g2 = 0.0;
+            S->dep = 0;
+            return S->k >= n_steps;
+        }
+    }
+    return 1; /* the track ended in the compensator */
+}
 
 /* One history (plan, spot s, index h).  Returns the end reason; the end point
  * is written to endpoint[3].  Tallies go to T (may be NULL for endpoints only). */
@@ -331,6 +474,15 @@ static int replay_history(const oracle_problem *P, uint32_t s, uint64_t h, oracl
 
     if (T) T->incident += I_h;
 
+    /* a beam-line device on the way (aperture, range compensator) */
+    replay_state S = {k0, 0.0, 0.0, 0, {0.0, 0.0, 1.0}, 0};
+    const int dv = P->spot_dev ? P->spot_dev[s] : -1;
+    if (dv >= 0 && I_h > 0 && device_pass(P, dv, st, n_steps, k0, cum, skip, phi0, M, pos, d, &S)) {
+        memcpy(endpoint, pos, sizeof(double) * 3);
+        if (T) T->escaped += I_h;
+        return END_UPSTREAM;
+    }
+
     /* ray-box entry; the region outside the box is vacuum */
     double tin = -INFINITY, tout = INFINITY;
     int ax_in = -1;
@@ -370,25 +522,18 @@ static int replay_history(const oracle_problem *P, uint32_t s, uint64_t h, oracl
     }
 
     /* ---- task 2: re-trace the steps ------------------------------------ */
-    double db[3] = {0.0, 0.0, 1.0}; /* beam-frame direction */
+    double *db = S.db;   /* beam-frame direction */
     int64_t acc = 0, hist_dep = 0;
     int reason = END_STOP;
     int alive = 1;
-    for (uint64_t k = k0; k < n_steps && alive; ++k) {
-        double dx = st[4 * k + 0], theta = st[4 * k + 2], phi = st[4 * k + 3];
-        int64_t e = fp_energy(st[4 * k + 1]);
-        double w_tot = dx;
-        if (k == k0) { /* partial first step */
-            int64_t e_first = cum + e - skip;
-            double f = (double)e_first / (double)e;
-            e = e_first;
-            w_tot = f * dx;
-            theta *= sqrt(f);
-            phi += phi0;
-        }
+    for (uint64_t k = S.k; k < n_steps && alive; ++k) {
+        double w_tot, theta, phi;
+        int64_t e;
+        step_params(st, k, k0, cum, skip, phi0, &w_tot, &e, &theta, &phi);
         if (T) T->steps++;
-        double tau = 0.0, g2 = 0.0;
-        int64_t dep = 0;
+        /* a step begun upstream (in a compensator) continues where it left off */
+        double tau = k == S.k ? S.tau : 0.0, g2 = k == S.k ? S.g2 : 0.0;
+        int64_t dep = k == S.k ? S.dep : 0;
         while (tau < w_tot) {
             size_t v = ((size_t)iv[2] * P->n[1] + iv[1]) * P->n[0] + iv[0];
             double rsp, g;
@@ -463,9 +608,10 @@ static int replay_history(const oracle_problem *P, uint32_t s, uint64_t h, oracl
     if (alive && T) {
         size_t v = ((size_t)iv[2] * P->n[1] + iv[1]) * P->n[0] + iv[0];
         flush(P, T, v, &acc);
+        T->escaped += S.up_dep; /* absorbed upstream: not deposited in the phantom */
     }
     memcpy(endpoint, pos, sizeof(double) * 3);
-    if (alive && hist_dep != I_h) return -1; /* energy not conserved: oracle bug */
+    if (alive && hist_dep + S.up_dep != I_h) return -1; /* energy not conserved: oracle bug */
     return reason;
 }
 
@@ -494,6 +640,10 @@ static void setup(oracle_problem *P, const float *steps, const uint64_t *track_o
     P->trace = NULL;
     P->ps_first = P->ps_count = NULL;
     P->ps_pos = P->ps_dir = P->ps_E = NULL;
+    P->spot_dev = NULL;
+    P->dev_par = NULL;
+    P->dev_pix = NULL;
+    P->dev_pix_off = NULL;
 }
 
 /* Phase-space sources for the next oracle_replay_e2x / oracle_endpoints /
@@ -510,11 +660,30 @@ void oracle_set_phase_space(const uint64_t *first, const uint64_t *count, const 
     g_ps.first = first; g_ps.count = count; g_ps.pos = pos; g_ps.dir = dir; g_ps.E = E;
 }
 
+/* Beam-line devices for the next calls on this thread (see oracle_problem:
+ * spot_dev per spot, 16 parameters per device, pixels and their per-device
+ * offsets); NULL spot_dev clears them. */
+static _Thread_local struct {
+    const int32_t *spot_dev;
+    const double *par;
+    const float *pix;
+    const uint64_t *pix_off;
+} g_dev;
+
+void oracle_set_devices(const int32_t *spot_dev, const double *par, const float *pix, const uint64_t *pix_off)
+{
+    g_dev.spot_dev = spot_dev; g_dev.par = par; g_dev.pix = pix; g_dev.pix_off = pix_off;
+}
+
 static void use_phase_space(oracle_problem *P)
 {
-    if (!g_ps.count) return;
-    P->ps_first = g_ps.first; P->ps_count = g_ps.count;
-    P->ps_pos = g_ps.pos; P->ps_dir = g_ps.dir; P->ps_E = g_ps.E;
+    if (g_ps.count) {
+        P->ps_first = g_ps.first; P->ps_count = g_ps.count;
+        P->ps_pos = g_ps.pos; P->ps_dir = g_ps.dir; P->ps_E = g_ps.E;
+    }
+    if (g_dev.spot_dev) {
+        P->spot_dev = g_dev.spot_dev; P->dev_par = g_dev.par; P->dev_pix = g_dev.pix; P->dev_pix_off = g_dev.pix_off;
+    }
 }
 
 /*
@@ -641,7 +810,8 @@ int oracle_replay_e2x(const float *steps, const uint64_t *track_off, uint32_t n_
     return err ? -1 : 0;
 }
 
-/* End point (cm) and end reason (0 stop, 1 escape, 2 miss) of histories
+/* End point (cm) and end reason (0 stop, 1 escape, 2 miss, 3 stopped upstream of
+ * the phantom by a beam-line device) of histories
  * h0 .. h0+n-1 of spot s.  No tallies are touched. */
 int oracle_endpoints(const float *steps, const uint64_t *track_off, uint32_t n_tracks,
                      const float *bin_E, const uint32_t *bin_first, uint32_t n_bins,

@@ -200,8 +200,47 @@ class _PhaseSpace:
             lib().oracle_set_phase_space(None, None, None, None, None)
 
 
+class _Devices:
+    """Installs beam-line devices for the oracle calls inside the block.
+    devices: (list of device dicts from inputs.beam_device, spot -> device
+    index array with -1 for none), or None."""
+
+    def __init__(self, devices, n_spots):
+        self.devices = devices
+        self.n_spots = n_spots
+
+    def __enter__(self):
+        if self.devices is not None:
+            devs, spot_dev = self.devices
+            par = np.zeros((max(len(devs), 1), 16), np.float64)
+            offs = np.zeros(max(len(devs), 1), np.uint64)
+            pix = []
+            o = 0
+            for i, dv in enumerate(devs):
+                par[i, 0:3] = dv["origin_cm"]
+                par[i, 3:6] = dv["dir"]
+                par[i, 6:8] = dv["pitch_cm"]
+                par[i, 8:10] = dv["n"]
+                par[i, 10] = dv["rsp"]
+                par[i, 11] = dv["rscp"]
+                offs[i] = o
+                p = np.ascontiguousarray(dv["pixels"], np.float32).ravel()
+                pix.append(p)
+                o += p.size
+            sd = np.full(self.n_spots, -1, np.int32)
+            sd[:len(spot_dev)] = np.asarray(spot_dev, np.int32)
+            self.keep = [sd, np.ascontiguousarray(par.ravel()),
+                         np.ascontiguousarray(np.concatenate(pix) if pix else np.zeros(1, np.float32)), offs]
+            a, b, c, d = self.keep
+            lib().oracle_set_devices(_p(a, C.c_int32), _p(b, C.c_double), _p(c, C.c_float), _p(d, C.c_uint64))
+
+    def __exit__(self, *a):
+        if self.devices is not None:
+            lib().oracle_set_devices(None, None, None, None)
+
+
 def replay(db, ph, sp, h_begin=None, h_count=None, plan=0, seed=1, R=64, flags=FLAG_VARIANCE,
-           threads=None, table=None, exact_e2=False, phase_space=None):
+           threads=None, table=None, exact_e2=False, phase_space=None, devices=None):
     """Replay histories h_begin[i] .. h_begin[i]+h_count[i]-1 of every spot i.
 
     Returns a dict with the int64 energy tally E, the uint64 sum-of-squares tally
@@ -211,7 +250,9 @@ def replay(db, ph, sp, h_begin=None, h_count=None, plan=0, seed=1, R=64, flags=F
     taken literally; E2 squares every visit on its own).  phase_space (from
     phase_space_sources): sources past the spots are listed protons; sp must
     then hold one (placeholder) row per source and h_count give each source's
-    histories."""
+    histories.  devices: (device dicts from inputs.beam_device, per spot the
+    index of the device it passes or -1): an aperture and range compensator
+    upstream of the phantom, whose absorbed energy counts as escaped."""
     arrs, args = _common(db, ph, sp, table)
     ns = len(sp)
     hb = np.zeros(ns, np.uint64) if h_begin is None else np.ascontiguousarray(h_begin, np.uint64)
@@ -223,7 +264,7 @@ def replay(db, ph, sp, h_begin=None, h_count=None, plan=0, seed=1, R=64, flags=F
     stats = np.zeros(6, np.int64)
     E2x = np.zeros(nx * ny * nz, np.uint64) if exact_e2 else None
     nthreads = threads or int(os.environ.get("ORACLE_THREADS", min(os.cpu_count() or 1, 16)))
-    with _PhaseSpace(phase_space):
+    with _PhaseSpace(phase_space), _Devices(devices, ns):
         rc = lib().oracle_replay_e2x(*args, C.c_uint32(ns), _p(hb, C.c_uint64), _p(hc, C.c_uint64),
                                      C.c_uint32(plan), C.c_uint64(seed), C.c_uint32(R), C.c_uint32(flags),
                                      C.c_int(nthreads), _p(E, C.c_int64), _p(E2, C.c_uint64),
@@ -237,12 +278,15 @@ def replay(db, ph, sp, h_begin=None, h_count=None, plan=0, seed=1, R=64, flags=F
                 n_histories=int(hc.sum()), threads=nthreads)
 
 
-def endpoints(db, ph, sp, spot, h0, n, plan=0, seed=1, R=64, flags=0, table=None, phase_space=None):
-    """End point (cm, float64 [n,3]) and end reason of histories h0..h0+n-1 of a spot."""
+def endpoints(db, ph, sp, spot, h0, n, plan=0, seed=1, R=64, flags=0, table=None, phase_space=None,
+              devices=None):
+    """End point (cm, float64 [n,3]) and end reason of histories h0..h0+n-1 of a
+    spot (0 stopped, 1 escaped, 2 missed the phantom, 3 stopped upstream by a
+    beam-line device)."""
     arrs, args = _common(db, ph, sp, table)
     xyz = np.zeros((n, 3), np.float64)
     reason = np.zeros(n, np.int32)
-    with _PhaseSpace(phase_space):
+    with _PhaseSpace(phase_space), _Devices(devices, len(sp)):
         lib().oracle_endpoints(*args, C.c_uint32(spot), C.c_uint64(h0), C.c_uint32(n), C.c_uint32(plan),
                                C.c_uint64(seed), C.c_uint32(R), C.c_uint32(flags),
                                _p(xyz, C.c_double), _p(reason, C.c_int32))

@@ -43,6 +43,7 @@ struct PlanHost {
         uint32_t bin = 0;
         uint64_t first = 0, count = 0;
         uint64_t db_serial = 0;       // the database the grouping was made for
+        int32_t dev = -1;             // beam-line device its histories pass (-1 none)
     };
     std::vector<Source> src;
     float4 *ps = nullptr;             // listed protons of the plan, two float4 each
@@ -112,6 +113,15 @@ struct fdc_ctx {
     // processing order by start position (launch config source_order = 1)
     uint32_t *d_order = nullptr;             // units x 64
     size_t order_cap = 0;
+    uint32_t *d_hist = nullptr;              // whole-item histograms of spots of more than one chunk
+    size_t hist_cap = 0;
+
+    // beam-line devices (fdc_add_beam_device): parameters on the host, pixel
+    // arrays and the parameter table on the device
+    std::vector<DevDevice> devices;
+    DevDevice *d_devices = nullptr;
+    size_t d_devices_cap = 0;
+    bool devices_dirty = false;
 
     // read-back scratch
     double *d_dose = nullptr, *d_var = nullptr;
@@ -136,6 +146,7 @@ struct fdc_graph {
     hipGraphExec_t exec = nullptr;
     WorkItem *d_items = nullptr;
     uint32_t *d_order = nullptr;             // start-position order table (source_order 1)
+    uint32_t *d_hist = nullptr;              // and its whole-item histograms
     std::vector<int32_t> plans;
     uint32_t flags = 0;
     bool reset = false;
@@ -264,6 +275,7 @@ DevSpot make_dev_spot(const fdc_ctx *ctx, const fdc_spot &s, uint32_t plan, uint
     d.bin = (uint32_t)b;
     d.plan = plan;
     d.spot = idx;
+    d.dev = -1;
     d.skip = to_fp(ctx->bin_E[b]) - to_fp(s.energy_MeV);
     d.n_hist = s.n_histories;
     return d;
@@ -283,6 +295,7 @@ int ensure_spots(fdc_ctx *ctx)
             DevSpot d = make_dev_spot(ctx, s, (uint32_t)p, (uint32_t)j);
             const PlanHost::Source &src = ctx->plans[p].src[j];
             d.bin_fp = to_fp(ctx->bin_E[d.bin]);
+            d.dev = src.dev;
             if (src.kind) {
                 if (src.db_serial != ctx->db_serial || src.bin >= ctx->n_bins)
                     return fail(ctx, FDC_E_STATE, "plan %zu: a phase space was grouped for another track database; "
@@ -360,6 +373,27 @@ int ensure_plans(fdc_ctx *ctx)
     return FDC_OK;
 }
 
+// the device table of the beam-line devices (rebuilt when devices were added)
+int ensure_devices(fdc_ctx *ctx)
+{
+    if (!ctx->devices_dirty) return FDC_OK;
+    if (ctx->devices.size() > ctx->d_devices_cap) {
+        const size_t cap = std::max<size_t>(ctx->devices.size(), 2 * ctx->d_devices_cap);
+        DevDevice *n = dalloc_n<DevDevice>(ctx, cap);
+        if (!n) return fail(ctx, FDC_E_NOMEM, "device table: device allocation failed");
+        HIPCHK(hipDeviceSynchronize());
+        dfree(ctx, ctx->d_devices);
+        ctx->d_devices = n;
+        ctx->d_devices_cap = cap;
+        ctx->gen++;                              // captured graphs hold the old table
+    }
+    HIPCHK(hipDeviceSynchronize());
+    HIPCHK(hipMemcpy(ctx->d_devices, ctx->devices.data(), ctx->devices.size() * sizeof(DevDevice),
+                     hipMemcpyHostToDevice));
+    ctx->devices_dirty = false;
+    return FDC_OK;
+}
+
 int ensure_items(fdc_ctx *ctx, size_t n, hipStream_t s)
 {
     if (ctx->items_ev_pending) {
@@ -402,6 +436,7 @@ TransportArgs base_args(const fdc_ctx *ctx)
     a.seed_lo = (uint32_t)ctx->seed;
     a.seed_hi = (uint32_t)(ctx->seed >> 32);
     a.R = ctx->R;
+    a.devices = ctx->d_devices;
     return a;
 }
 
@@ -431,14 +466,20 @@ bool grow(fdc_ctx *ctx, T *&buf, size_t &cap, size_t n, hipStream_t s)
 // until the process ends; host code reaches it only through the address
 // hipGetSymbolAddress returns for that device (taken once per device, with the
 // device current, when the first context on it is created).  Layout: the
-// queue counter at 0, kNoAllocMaxItems work items from 256, the lane table
-// (64 x 4 B per unit) after them.
+// queue counter at 0, kNoAllocMaxItems work items from 256, then the lane
+// table (64 x 4 B per unit) of up to kNoAllocMaxOrderUnits units, then the
+// whole-item histograms (4 B per 16 histories of the lane table, plus one
+// counter per item and one).
 constexpr size_t kNoAllocBytes = 32u << 20;
 constexpr uint32_t kNoAllocMaxItems = 16384;
 constexpr size_t kNoAllocItemsOff = 256;
 constexpr size_t kNoAllocOrderOff = (kNoAllocItemsOff + kNoAllocMaxItems * sizeof(WorkItem) + 255) & ~(size_t)255;
-constexpr unsigned long long kNoAllocMaxOrderUnits = (kNoAllocBytes - kNoAllocOrderOff) / (kWave * sizeof(uint32_t));
-static_assert(kNoAllocOrderOff < kNoAllocBytes, "scratch layout");
+// per unit: 64 lane words and 64 / 16 histogram counters; and the per-item counters
+constexpr unsigned long long kNoAllocMaxOrderUnits =
+    (kNoAllocBytes - kNoAllocOrderOff - 4 * (kNoAllocMaxItems + 2) - 256) / (4 * (kWave + kWave / 16));
+constexpr size_t kNoAllocHistOff = (kNoAllocOrderOff + kNoAllocMaxOrderUnits * kWave * 4 + 255) & ~(size_t)255;
+static_assert(kNoAllocHistOff + 4 * (kNoAllocMaxOrderUnits * kWave / 16 + kNoAllocMaxItems + 2) <= kNoAllocBytes,
+              "scratch layout");
 
 } // namespace
 
@@ -533,7 +574,10 @@ int fdc_destroy(fdc_ctx *ctx)
     dfree(ctx, ctx->bin_first);
     dfree(ctx, ctx->lut); dfree(ctx, ctx->rho_lut);
     dfree(ctx, ctx->d_plans); dfree(ctx, ctx->d_spots); dfree(ctx, ctx->d_items); dfree(ctx, ctx->d_queue);
+    for (DevDevice &d : ctx->devices) dfree(ctx, (void *)d.pix);
+    dfree(ctx, ctx->d_devices);
     dfree(ctx, ctx->d_order);
+    dfree(ctx, ctx->d_hist);
     dfree(ctx, ctx->d_hnext);
     if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
     dfree(ctx, ctx->d_dose); dfree(ctx, ctx->d_var);
@@ -824,6 +868,83 @@ int fdc_add_beam_spots(fdc_ctx *ctx, int32_t plan, const fdc_spot *spots, uint32
     return FDC_OK;
 }
 
+int fdc_add_beam_device(fdc_ctx *ctx, const fdc_beam_device *dev, const float *pixels, int32_t *device_out,
+                        void *hip_stream)
+{
+    if (!ctx) return FDC_E_ARG;
+    if (!dev || !pixels || !device_out) return fail(ctx, FDC_E_ARG, "beam device: NULL argument");
+    if (!finite3(dev->origin_cm) || !finite3(dev->dir) || !std::isfinite(dev->pitch_cm[0]) ||
+        !std::isfinite(dev->pitch_cm[1]) || !(dev->pitch_cm[0] > 0.f) || !(dev->pitch_cm[1] > 0.f))
+        return fail(ctx, FDC_E_ARG, "beam device: non-finite position or direction, or pitch <= 0");
+    const double l = std::sqrt((double)dev->dir[0] * dev->dir[0] + (double)dev->dir[1] * dev->dir[1] +
+                               (double)dev->dir[2] * dev->dir[2]);
+    if (!(l > 1e-6)) return fail(ctx, FDC_E_ARG, "beam device: direction is zero");
+    const uint64_t np = (uint64_t)dev->n[0] * dev->n[1];
+    if (dev->n[0] == 0 || dev->n[1] == 0 || np > (1ull << 26) || dev->n[0] > 0x7FFFFFFFu || dev->n[1] > 0x7FFFFFFFu)
+        return fail(ctx, FDC_E_ARG, "beam device: grid must have 1 .. 2^26 pixels");
+    bool material = false;
+    for (uint64_t i = 0; i < np; ++i) {
+        if (!std::isfinite(pixels[i])) return fail(ctx, FDC_E_ARG, "beam device: non-finite pixel %llu",
+                                                   (unsigned long long)i);
+        material |= pixels[i] > 0.f;
+    }
+    if (material && (!(dev->rsp > 0.f) || !(dev->rscp > 0.f) || !std::isfinite(dev->rsp) || !std::isfinite(dev->rscp)))
+        return fail(ctx, FDC_E_ARG, "beam device: compensator rsp and rscp must be finite and > 0");
+    if (ctx->dry) {
+        DevDevice d{};
+        ctx->devices.push_back(d);
+        *device_out = (int32_t)ctx->devices.size() - 1;
+        return FDC_OK;
+    }
+    HIPCHK(hipSetDevice(ctx->device));
+    float *pix = dalloc_n<float>(ctx, np);
+    if (!pix) return fail(ctx, FDC_E_NOMEM, "beam device: pixel allocation failed");
+    hipError_t e = hipMemcpyAsync(pix, pixels, np * sizeof(float), hipMemcpyHostToDevice, S(hip_stream));
+    if (e == hipSuccess) e = hipStreamSynchronize(S(hip_stream));
+    if (e != hipSuccess) {
+        dfree(ctx, pix);
+        return fail(ctx, FDC_E_HIP, "beam device: %s", hipGetErrorString(e));
+    }
+    DevDevice d{};
+    double nrm[3] = {dev->dir[0] / l, dev->dir[1] / l, dev->dir[2] / l};
+    double u1[3], u2[3];
+    field_frame(nrm, u1, u2);
+    for (int q = 0; q < 3; ++q) {
+        d.o[q] = dev->origin_cm[q];
+        d.nrm[q] = nrm[q];
+        d.u1[q] = u1[q];
+        d.u2[q] = u2[q];
+    }
+    d.pitch[0] = dev->pitch_cm[0];
+    d.pitch[1] = dev->pitch_cm[1];
+    d.npix[0] = (int)dev->n[0];
+    d.npix[1] = (int)dev->n[1];
+    d.rsp = material ? dev->rsp : 1.0;
+    d.g = material ? (double)dev->rscp / (double)dev->rsp : 1.0;
+    d.pix = pix;
+    ctx->devices.push_back(d);
+    ctx->devices_dirty = true;
+    *device_out = (int32_t)ctx->devices.size() - 1;
+    return FDC_OK;
+}
+
+int fdc_set_spot_device(fdc_ctx *ctx, int32_t plan, uint32_t first_spot, uint32_t n_spots, int32_t device)
+{
+    if (!ctx) return FDC_E_ARG;
+    if (!valid_plan(ctx, plan)) return fail(ctx, FDC_E_ARG, "spot device: no plan %d", plan);
+    PlanHost &P = ctx->plans[plan];
+    if ((uint64_t)first_spot + n_spots > P.spots.size())
+        return fail(ctx, FDC_E_ARG, "spot device: spots %u .. %u beyond the plan's %zu", first_spot,
+                    first_spot + n_spots, P.spots.size());
+    if (device < -1 || device >= (int64_t)ctx->devices.size())
+        return fail(ctx, FDC_E_ARG, "spot device: no device %d", device);
+    for (uint32_t j = first_spot; j < first_spot + n_spots; ++j)
+        if (P.src[j].kind) return fail(ctx, FDC_E_ARG, "spot device: source %u lists protons", j);
+    for (uint32_t j = first_spot; j < first_spot + n_spots; ++j) P.src[j].dev = device;
+    ctx->spots_dirty = true;
+    return FDC_OK;
+}
+
 int fdc_add_phase_space(fdc_ctx *ctx, int32_t plan, const fdc_particle *particles, uint64_t n,
                         uint32_t *n_sources_out, void *hip_stream)
 {
@@ -1044,11 +1165,28 @@ static int check_source_order(fdc_ctx *ctx, const std::vector<WorkItem> &items)
     return FDC_OK;
 }
 
-static int enqueue_source_order(fdc_ctx *ctx, const WorkItem *d_items, const std::vector<WorkItem> &items,
-                                uint32_t n_chunks, unsigned long long units, uint32_t *order, hipStream_t s)
+// does the run have spots of more than one ordering chunk (whole-item histograms),
+// and how many histogram counters do they need
+static bool large_items(const std::vector<WorkItem> &items, unsigned long long *hist_words)
 {
+    unsigned long long n = 0;
+    bool large = false;
+    for (const WorkItem &w : items) {
+        n += w.n;
+        large |= w.n > kOrderChunk;
+    }
+    *hist_words = order_hist_words(n, items.size());
+    return large;
+}
+
+static int enqueue_source_order(fdc_ctx *ctx, const WorkItem *d_items, const std::vector<WorkItem> &items,
+                                uint32_t n_chunks, unsigned long long units, uint32_t *order, uint32_t *hist,
+                                hipStream_t s)
+{
+    unsigned long long hw = 0;
+    const bool large = large_items(items, &hw);
     HIPCHK(launch_source_order(d_items, (uint32_t)items.size(), n_chunks, units, ctx->d_spots, ctx->d_hnext,
-                               (uint32_t)ctx->seed, (uint32_t)(ctx->seed >> 32), order, s));
+                               (uint32_t)ctx->seed, (uint32_t)(ctx->seed >> 32), order, hist, hw, large, s));
     return FDC_OK;
 }
 
@@ -1134,6 +1272,7 @@ int fdc_run_histories(fdc_ctx *ctx, const int32_t *plans, uint32_t n_plans, uint
     HIPCHK(hipSetDevice(ctx->device));
     rc = ensure_plans(ctx);
     if (!rc) rc = ensure_spots(ctx);
+    if (!rc) rc = ensure_devices(ctx);
     if (rc) return rc;
     hipStream_t s = S(hip_stream);
     std::vector<WorkItem> items;
@@ -1143,7 +1282,10 @@ int fdc_run_histories(fdc_ctx *ctx, const int32_t *plans, uint32_t n_plans, uint
     if (ctx->cfg.source_order) {
         rc = check_source_order(ctx, items);
         if (rc) return rc;
-        if (!grow(ctx, ctx->d_order, ctx->order_cap, units * kWave, s))
+        unsigned long long hw = 0;
+        const bool large = large_items(items, &hw);
+        if (!grow(ctx, ctx->d_order, ctx->order_cap, units * kWave, s) ||
+            (large && !grow(ctx, ctx->d_hist, ctx->hist_cap, hw + 1, s)))
             return fail(ctx, FDC_E_NOMEM, "run: source order table");
     }
     rc = ensure_items(ctx, items.size(), s);
@@ -1157,7 +1299,7 @@ int fdc_run_histories(fdc_ctx *ctx, const int32_t *plans, uint32_t n_plans, uint
     a.n_units = units;
     a.flags = flags;
     if (ctx->cfg.source_order) {
-        rc = enqueue_source_order(ctx, ctx->d_items, items, n_chunks, units, ctx->d_order, s);
+        rc = enqueue_source_order(ctx, ctx->d_items, items, n_chunks, units, ctx->d_order, ctx->d_hist, s);
         if (rc) return rc;
         a.order = ctx->d_order;
     }
@@ -1179,7 +1321,7 @@ int fdc_run_histories_noalloc(fdc_ctx *ctx, const int32_t *plans, uint32_t n_pla
     if (n_plans > kMaxRangePlans)
         return fail(ctx, FDC_E_RANGE, "run (no allocation): at most %u plans per run, %u given", kMaxRangePlans, n_plans);
     // the device plan and spot tables must be current: bringing them up to date may allocate
-    if (ctx->plans_dirty || ctx->spots_dirty)
+    if (ctx->plans_dirty || ctx->spots_dirty || ctx->devices_dirty)
         return fail(ctx, FDC_E_STATE, "run (no allocation): plans or spots changed since the last run; "
                     "call fdc_run_histories or fdc_prepare_run first");
     // sizes of the work table (as build_items, without building it on the host)
@@ -1211,6 +1353,7 @@ int fdc_run_histories_noalloc(fdc_ctx *ctx, const int32_t *plans, uint32_t n_pla
     unsigned long long *queue = (unsigned long long *)ctx->scratch;
     WorkItem *d_items = (WorkItem *)(ctx->scratch + kNoAllocItemsOff);
     uint32_t *d_order = (uint32_t *)(ctx->scratch + kNoAllocOrderOff);
+    uint32_t *d_hist = (uint32_t *)(ctx->scratch + kNoAllocHistOff);
     HIPCHK(launch_build_items(ctx->d_spots, r, d_items, s));
     TransportArgs a = base_args(ctx);
     a.items = d_items;
@@ -1218,11 +1361,18 @@ int fdc_run_histories_noalloc(fdc_ctx *ctx, const int32_t *plans, uint32_t n_pla
     a.n_units = units;
     a.flags = flags;
     if (ctx->cfg.source_order) {
-        unsigned long long chunks = 0;
+        unsigned long long chunks = 0, hist = 0;
+        bool large = false;
         for (uint32_t i = 0; i < n_plans; ++i)
-            for (const fdc_spot &sp : ctx->plans[plans[i]].spots) chunks += source_order_chunks(sp.n_histories);
+            for (const fdc_spot &sp : ctx->plans[plans[i]].spots) {
+                chunks += source_order_chunks(sp.n_histories);
+                hist += sp.n_histories;
+                large |= sp.n_histories > kOrderChunk;
+            }
+        // (n histories <= 64 units: the histograms fit their region)
         HIPCHK(launch_source_order(d_items, (uint32_t)n_items, (uint32_t)chunks, units, ctx->d_spots, ctx->d_hnext,
-                                   (uint32_t)ctx->seed, (uint32_t)(ctx->seed >> 32), d_order, s));
+                                   (uint32_t)ctx->seed, (uint32_t)(ctx->seed >> 32), d_order, d_hist,
+                                   order_hist_words(hist, n_items), large, s));
         a.order = d_order;
     }
     rc = enqueue_transport_kernel(ctx, a, flags, s, one_plan(plans, n_plans), queue);
@@ -1239,6 +1389,7 @@ int fdc_prepare_run(fdc_ctx *ctx)
     HIPCHK(hipSetDevice(ctx->device));
     int rc = ensure_plans(ctx);
     if (!rc) rc = ensure_spots(ctx);
+    if (!rc) rc = ensure_devices(ctx);
     return rc;
 }
 
@@ -1289,6 +1440,7 @@ int fdc_graph_create(fdc_ctx *ctx, const int32_t *plans, uint32_t n_plans, uint3
     HIPCHK(hipSetDevice(ctx->device));
     rc = ensure_plans(ctx);
     if (!rc) rc = ensure_spots(ctx);
+    if (!rc) rc = ensure_devices(ctx);
     if (rc) return rc;
     std::vector<WorkItem> items;
     uint32_t n_chunks = 0;
@@ -1305,10 +1457,14 @@ int fdc_graph_create(fdc_ctx *ctx, const int32_t *plans, uint32_t n_plans, uint3
     g->flags = flags;
     g->reset = (options & FDC_GRAPH_RESET_TALLIES) != 0;
     g->d_items = dalloc_n<WorkItem>(ctx, std::max<size_t>(items.size(), 1));
+    unsigned long long hw = 0;
+    const bool large = ordered && large_items(items, &hw);
     if (ordered) g->d_order = dalloc_n<uint32_t>(ctx, units * kWave);
-    if (!g->d_items || (ordered && !g->d_order)) {
+    if (large) g->d_hist = dalloc_n<uint32_t>(ctx, hw + 1);
+    if (!g->d_items || (ordered && !g->d_order) || (large && !g->d_hist)) {
         dfree(ctx, g->d_items);
         dfree(ctx, g->d_order);
+        dfree(ctx, g->d_hist);
         delete g;
         return fail(ctx, FDC_E_NOMEM, "graph: work table allocation failed");
     }
@@ -1317,6 +1473,7 @@ int fdc_graph_create(fdc_ctx *ctx, const int32_t *plans, uint32_t n_plans, uint3
         if (g->graph) (void)hipGraphDestroy(g->graph);
         dfree(ctx, g->d_items);
         dfree(ctx, g->d_order);
+        dfree(ctx, g->d_hist);
         delete g;
         return fail(ctx, code, "graph: %s: %s", what, hipGetErrorString(e));
     };
@@ -1348,7 +1505,7 @@ int fdc_graph_create(fdc_ctx *ctx, const int32_t *plans, uint32_t n_plans, uint3
         a.n_units = units;
         a.flags = flags;
         if (ordered) {
-            rc = enqueue_source_order(ctx, g->d_items, items, n_chunks, units, g->d_order, s);
+            rc = enqueue_source_order(ctx, g->d_items, items, n_chunks, units, g->d_order, g->d_hist, s);
             a.order = g->d_order;
         }
         if (!rc) rc = enqueue_transport(ctx, a, flags, s, one_plan(plans, n_plans));
@@ -1375,7 +1532,7 @@ int fdc_graph_launch(fdc_graph *g, void *hip_stream)
 {
     if (!g) return FDC_E_ARG;
     fdc_ctx *ctx = g->ctx;
-    if (g->gen != ctx->gen || ctx->spots_dirty || ctx->plans_dirty)
+    if (g->gen != ctx->gen || ctx->spots_dirty || ctx->plans_dirty || ctx->devices_dirty)
         return fail(ctx, FDC_E_STATE, "graph: plans, spots or database changed since capture; capture again");
     int rc = validate_run(ctx, g->plans.data(), (uint32_t)g->plans.size(), g->flags, 1);
     if (rc && !(rc == FDC_E_OVERFLOW && g->reset)) return rc;
@@ -1395,6 +1552,7 @@ int fdc_graph_destroy(fdc_graph *g)
     if (g->graph) (void)hipGraphDestroy(g->graph);
     dfree(ctx, g->d_items);
     dfree(ctx, g->d_order);
+    dfree(ctx, g->d_hist);
     delete g;
     return FDC_OK;
 }
@@ -1493,6 +1651,7 @@ int fdc_debug_endpoints(fdc_ctx *ctx, int32_t plan, uint32_t spot, uint64_t h0, 
     HIPCHK(hipSetDevice(ctx->device));
     int rc = ensure_plans(ctx);
     if (!rc) rc = ensure_spots(ctx);
+    if (!rc) rc = ensure_devices(ctx);
     if (rc) return rc;
     hipStream_t s = S(hip_stream);
     float *d_xyz = dalloc_n<float>(ctx, 3 * (size_t)n);
@@ -1579,6 +1738,21 @@ int fdc_set_launch_config(fdc_ctx *ctx, const fdc_launch_config *cfg)
             return fail(ctx, FDC_E_ARG, "launch config: LDS sub-tally of %u slots does not fit", t);
     }
     if (cfg->units_per_wave > 64) return fail(ctx, FDC_E_ARG, "launch config: units_per_wave must be 0..64");
+    if (cfg->tally_slots && cfg->tally_mode == 2 && !ctx->dry) {
+        // the whole-launch cache kernel's waves wait for a sibling wave of their
+        // workgroup: the workgroup must fit one CU (then its waves are resident together)
+        HIPCHK(hipSetDevice(ctx->device));
+        for (int var = 0; var < 2; ++var) {
+            if (kLutSize * sizeof(float2) + kLdsFixedBytes + lds_tally_bytes(cfg->tally_slots, var, 2) > kMaxLdsBytes)
+                continue;                        // (refused at run time for the squared-energy tally)
+            int blocks = 0;
+            HIPCHK(cache_kernel_occupancy(std::max<uint32_t>(1, cfg->waves_per_block), cfg->tally_slots, var != 0,
+                                          &blocks));
+            if (blocks < 1)
+                return fail(ctx, FDC_E_ARG, "launch config: a workgroup of the whole-launch cache kernel does not fit "
+                            "one CU");
+        }
+    }
     if (cfg->source_order > 1) return fail(ctx, FDC_E_ARG, "launch config: source_order must be 0 or 1");
     ctx->cfg = *cfg;
     return FDC_OK;

@@ -59,9 +59,19 @@ struct DevSpot {
     // a source of listed protons (kind 1): history h is proton ps_first + h % ps_count
     // of the plan's list, which brings its own start, direction and energy
     uint32_t kind;                  // 0 spot, 1 listed protons
-    uint32_t pad;
+    int32_t dev;                    // beam-line device the spot's histories pass, -1 none
     long long bin_fp;               // fp(E_bin)
     unsigned long long ps_first, ps_count;
+};
+
+// a beam-line device upstream of the phantom (fdc_beam_device): its face
+// plane, lateral axes and pixel grid, in FP64 like the source
+struct DevDevice {
+    double o[3], nrm[3], u1[3], u2[3];
+    double pitch[2];
+    int npix[2];
+    double rsp, g;                  // compensator RSP and RScP / RSP
+    const float *pix;               // < 0 closed, else thickness (cm) along nrm
 };
 
 // a contiguous range of histories of one spot, cut in wave units of 64
@@ -122,6 +132,7 @@ struct TransportArgs {
     int *ep_reason;
     const uint32_t *order;               // per unit and lane: offset of the lane's history in its
                                          // item, 0xFFFFFFFF = none (null: consecutive histories)
+    const DevDevice *devices;            // beam-line devices (DevSpot::dev indexes them)
 };
 
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two 32x32
@@ -251,6 +262,7 @@ hipError_t launch_transport(const TransportArgs &a, uint32_t waves_per_block, ui
 hipError_t launch_transport_lds(const TransportArgs &a, uint32_t waves_per_block, uint32_t grid_blocks,
                                 uint32_t slots, uint32_t units_per_wave, bool variance, uint32_t mode, hipStream_t s);
 size_t lds_tally_bytes(uint32_t slots, bool variance, uint32_t mode);
+hipError_t cache_kernel_occupancy(uint32_t waves_per_block, uint32_t slots, bool variance, int *blocks);
 hipError_t prepare_lds_kernels();
 hipError_t launch_build_lut(const double *pts, int n_pts, double vacuum_below, float2 *lut, float *rho,
                             hipStream_t s);
@@ -264,10 +276,18 @@ hipError_t launch_dose(const uint16_t *idx, const unsigned long long *E, const u
                        const float2 *lut, const float *rho_lut, size_t nvox, double voxel_volume_cm3,
                        const unsigned long long *n_hist, double *dose, double *var, hipStream_t s);
 // processing order of a run's histories by start position (order.hip): the
-// launch (fill of the per-unit lane table, one workgroup per chunk)
+// launches (fill of the per-unit lane table, one workgroup per chunk; with
+// `large`, the whole-item histograms of the items of more than one chunk, in
+// hist: hist_words = order_hist_words(...) counters)
 hipError_t launch_source_order(const WorkItem *items, uint32_t n_items, uint32_t n_chunks, unsigned long long n_units,
                                const DevSpot *spots, const unsigned long long *hnext, uint32_t seed_lo,
-                               uint32_t seed_hi, uint32_t *order, hipStream_t s);
+                               uint32_t seed_hi, uint32_t *order, uint32_t *hist, unsigned long long hist_words,
+                               bool large, hipStream_t s);
+// counters the whole-item histograms of a run of n histories in n_items items need
+__host__ __device__ inline unsigned long long order_hist_words(unsigned long long n, unsigned long long n_items)
+{
+    return (n >> 4) + n_items + 1;
+}
 // the work table of a run over the spots of `r` (every spot with histories,
 // in range order), built by one workgroup from the spots' n_hist; the same
 // items the host builds for fdc_run_histories

@@ -11,18 +11,25 @@
 // stays keyed by the history's identity and the tallies are integer sums, so
 // the order cannot change a result bit.
 //
-// Each work item's histories are cut in chunks of 16384 (a multiple of the
-// 64-history unit, so a chunk fills whole units); one workgroup orders one
-// chunk: it draws every history's lateral start offset exactly as the walk
-// draws it, bins it on a square grid over the spot (+-4 sigma for a Gaussian
-// spot, the diameter for a disk field) in Morton order, counts the bins in
-// LDS, scans them and writes each history's offset at its place in the
-// per-unit lane table order[unit * 64 + lane] (0xFFFFFFFF for the lanes past
-// the item's end, filled beforehand).  The grid has about four histories per
-// cell (at most 64 x 64 cells).  Chunks are ordered independently: no global
-// histogram or scan, no scratch memory, and a fixed number of launches, so
-// the sequence can be captured in a graph.  Within a cell the order follows
-// the LDS atomics and may differ between runs; tallies cannot.
+// Every history's lateral start offset is drawn exactly as the walk draws it
+// and binned on a square grid over the spot (+-4 sigma for a Gaussian spot,
+// the diameter for a disk field) in Morton order; each history's offset is
+// written at its place in the per-unit lane table order[unit * 64 + lane]
+// (0xFFFFFFFF for the lanes past the item's end, filled beforehand).
+//  - An item of at most 16384 histories (one chunk, 256 units) is ordered by
+//    one workgroup: it counts the bins in LDS, scans them and places the
+//    histories (about four per cell, at most 64 x 64 cells).
+//  - A larger item is ordered as a whole, so that neighbouring units start
+//    next to each other across the entire spot: a histogram of about 16
+//    histories per cell (at most 256 x 256 cells) in device memory, counted
+//    by one workgroup per chunk of histories with device atomics, scanned by
+//    one workgroup per item, and the histories placed by a second pass over
+//    the chunks.  The histogram of item i starts at first_i / 16 + i (first_i:
+//    the item's first history among the run's), so a run needs at most
+//    n / 16 + items + 1 counters.
+// A fixed number of launches, so the sequence can be captured in a graph.
+// Within a cell the order follows the atomics and may differ between runs;
+// tallies cannot.
 #include "fdc_device.h"
 
 namespace fdc {
@@ -60,6 +67,88 @@ __device__ inline uint32_t start_cell(const DevSpot &sp, unsigned long long h, u
     return spread((uint32_t)qx) | (spread((uint32_t)qy) << 1);
 }
 
+// the item holding chunk c: largest i with items[i].chunk0 <= c
+__device__ inline uint32_t item_of_chunk(const WorkItem *items, uint32_t n_items, uint32_t c)
+{
+    uint32_t lo = 0, hi = n_items;
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (items[mid].chunk0 <= c) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+// half the bits of a large item's cell count: 4^hb <= n / 16, at most 256 x 256 cells
+__device__ inline uint32_t large_half_bits(unsigned long long n)
+{
+    uint32_t hb = 0;
+    while (hb < 8 && (16ull << (2 * (hb + 1))) <= n) ++hb;
+    return hb;
+}
+
+// count (PLACE false) or place (PLACE true) the histories of one chunk of a large item
+template <bool PLACE>
+__global__ void __launch_bounds__(kThreads) order_large_kernel(const WorkItem *__restrict__ items, uint32_t n_items,
+                                                               const DevSpot *__restrict__ spots,
+                                                               const unsigned long long *__restrict__ hnext,
+                                                               uint32_t seed_lo, uint32_t seed_hi,
+                                                               uint32_t *__restrict__ hist, uint32_t *__restrict__ order)
+{
+    const uint32_t i = item_of_chunk(items, n_items, blockIdx.x);
+    const WorkItem it = items[i];
+    if (it.n <= kChunk) return;                                      // (uniform: the whole block)
+    const unsigned long long j0 = (unsigned long long)(blockIdx.x - it.chunk0) * kChunk;
+    if (j0 >= it.n) return;
+    const uint32_t len = (uint32_t)min((unsigned long long)kChunk, it.n - j0);
+    const DevSpot &sp = spots[it.gspot];
+    const uint32_t hb = large_half_bits(it.n);
+    uint32_t *h = hist + (it.first >> 4) + i;
+    const unsigned long long hbase = it.h0 + (hnext ? hnext[it.gspot] : 0ull) + j0;
+    for (uint32_t e = threadIdx.x; e < len; e += kThreads) {
+        const uint32_t cell = start_cell(sp, hbase + e, hb, seed_lo, seed_hi);
+        if (PLACE) {
+            const unsigned long long p = atomicAdd(h + cell, 1u);
+            order[(it.unit0 + p / kWave) * kWave + (p % kWave)] = (uint32_t)(j0 + e);
+        } else {
+            atomicAdd(h + cell, 1u);
+        }
+    }
+}
+
+// exclusive scan of each large item's histogram, one workgroup per item
+__global__ void __launch_bounds__(kThreads) order_scan_kernel(const WorkItem *__restrict__ items,
+                                                              uint32_t *__restrict__ hist)
+{
+    __shared__ uint32_t s_wave[kThreads / kWave];
+    const WorkItem it = items[blockIdx.x];
+    if (it.n <= kChunk) return;
+    const uint32_t ncell = 1u << (2 * large_half_bits(it.n));
+    uint32_t *h = hist + (it.first >> 4) + blockIdx.x;
+    const uint32_t per = (ncell + kThreads - 1) / kThreads;         // 1 .. 64 consecutive cells per thread
+    const uint32_t t = threadIdx.x, lane = t & (kWave - 1), wave = t / kWave;
+    const uint32_t c0 = t * per;
+    uint32_t mine = 0;
+    for (uint32_t k = 0; k < per; ++k)
+        if (c0 + k < ncell) mine += h[c0 + k];
+    uint32_t incl = mine;
+#pragma unroll
+    for (uint32_t off = 1; off < kWave; off <<= 1) {
+        const uint32_t v = __shfl_up(incl, off, kWave);
+        if (lane >= off) incl += v;
+    }
+    if (lane == kWave - 1) s_wave[wave] = incl;
+    __syncthreads();
+    uint32_t run = incl - mine;
+    for (uint32_t w = 0; w < wave; ++w) run += s_wave[w];
+    for (uint32_t k = 0; k < per; ++k) {
+        if (c0 + k < ncell) {
+            const uint32_t c = h[c0 + k];
+            h[c0 + k] = run;
+            run += c;
+        }
+    }
+}
+
 __global__ void __launch_bounds__(kThreads) order_chunk_kernel(const WorkItem *__restrict__ items, uint32_t n_items,
                                                                const DevSpot *__restrict__ spots,
                                                                const unsigned long long *__restrict__ hnext,
@@ -69,16 +158,11 @@ __global__ void __launch_bounds__(kThreads) order_chunk_kernel(const WorkItem *_
     __shared__ uint32_t s_cnt[1u << (2 * kMaxHalfBits)];
     __shared__ uint32_t s_wave[kThreads / kWave];
     const uint32_t t = threadIdx.x;
-    // the item holding this chunk: largest i with items[i].chunk0 <= blockIdx.x
-    uint32_t lo = 0, hi = n_items;
-    while (hi - lo > 1) {
-        const uint32_t mid = (lo + hi) >> 1;
-        if (items[mid].chunk0 <= blockIdx.x) lo = mid; else hi = mid;
-    }
-    const WorkItem it = items[lo];
+    const WorkItem it = items[item_of_chunk(items, n_items, blockIdx.x)];
     const DevSpot &sp = spots[it.gspot];
+    if (it.n > kChunk) return;                                       // a large item (uniform: the whole block)
     const unsigned long long j0 = (unsigned long long)(blockIdx.x - it.chunk0) * kChunk;
-    if (j0 >= it.n) return;                                          // (uniform: the whole block)
+    if (j0 >= it.n) return;
     const uint32_t len = (uint32_t)min((unsigned long long)kChunk, it.n - j0);
     // about four histories per cell: 4^hb <= len / 4
     uint32_t hb = 0;
@@ -143,12 +227,22 @@ __global__ void __launch_bounds__(kThreads) order_chunk_kernel(const WorkItem *_
 
 hipError_t launch_source_order(const WorkItem *items, uint32_t n_items, uint32_t n_chunks, unsigned long long n_units,
                                const DevSpot *spots, const unsigned long long *hnext, uint32_t seed_lo,
-                               uint32_t seed_hi, uint32_t *order, hipStream_t s)
+                               uint32_t seed_hi, uint32_t *order, uint32_t *hist, unsigned long long hist_words,
+                               bool large, hipStream_t s)
 {
     if (n_units == 0) return hipSuccess;
     // lanes past an item's end: none (the table is 64 x n_units words, an even count)
     hipError_t e = launch_fill_u64((unsigned long long *)order, n_units * kWave / 2, ~0ull, s);
     if (e != hipSuccess || n_chunks == 0) return e;
+    if (large) {                                         // items of more than one chunk: whole-item histograms
+        e = launch_fill_u64((unsigned long long *)hist, (hist_words + 1) / 2, 0ull, s);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(order_large_kernel<false>, dim3(n_chunks), dim3(kThreads), 0, s, items, n_items, spots,
+                           hnext, seed_lo, seed_hi, hist, order);
+        hipLaunchKernelGGL(order_scan_kernel, dim3(n_items), dim3(kThreads), 0, s, items, hist);
+        hipLaunchKernelGGL(order_large_kernel<true>, dim3(n_chunks), dim3(kThreads), 0, s, items, n_items, spots,
+                           hnext, seed_lo, seed_hi, hist, order);
+    }
     hipLaunchKernelGGL(order_chunk_kernel, dim3(n_chunks), dim3(kThreads), 0, s, items, n_items, spots, hnext,
                        seed_lo, seed_hi, order);
     return hipGetLastError();

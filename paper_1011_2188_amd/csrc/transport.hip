@@ -261,6 +261,135 @@ struct CacheSink {
     }
 };
 
+// A beam-line device on a spot's way to the phantom (fdc_beam_device), in
+// FP64 like the source: the ray from p along d meets the device's upstream
+// face at one pixel; a closed pixel, a pixel off the grid, or a face not ahead
+// of p stops the history there (returns true).  Through an open pixel with
+// compensator thickness T > 0 the track is replayed from step k in a slab of
+// the compensator's material until the displacement along the face normal
+// reaches T: each piece consumes water-equivalent length at geometric length
+// WEL / RSP, the step's energy split uniformly in WEL with the telescoping
+// rounding, the deflection at a step end scaled by sqrt(sum w G / WEL) as in a
+// voxel.  On return (false) p, d and b (the beam-frame direction) are at the
+// exit face, k is the step being replayed there with tau (WEL consumed), dep
+// (its energy deposited so far) and g2 (sum w G) of it done, and up holds the
+// energy deposited in the compensator (lost to the phantom).  A track that
+// ends inside the compensator stops there (true).
+__host__ __device__ inline bool beam_device_pass(const TransportArgs &a, const DevDevice &dv, const DevSpot &sp,
+                                                 unsigned long long k0, unsigned long long kend, long long cum,
+                                                 long long skip, double phi0, double p[3], double d[3], double b[3],
+                                                 unsigned long long &k_out, double &tau_out, int &dep_out,
+                                                 double &g2_out, long long &up)
+{
+    double dn = d[0] * dv.nrm[0] + d[1] * dv.nrm[1] + d[2] * dv.nrm[2];
+    double t = (dv.o[0] - p[0]) * dv.nrm[0] + (dv.o[1] - p[1]) * dv.nrm[1] + (dv.o[2] - p[2]) * dv.nrm[2];
+    if (!(dn > 0.0) || t < 0.0) return true;
+    t /= dn;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) p[q] += t * d[q];
+    double ra = 0.0, rb = 0.0;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        ra += (p[q] - dv.o[q]) * dv.u1[q];
+        rb += (p[q] - dv.o[q]) * dv.u2[q];
+    }
+    const double fi = floor(ra / dv.pitch[0] + 0.5 * (double)dv.npix[0]);
+    const double fj = floor(rb / dv.pitch[1] + 0.5 * (double)dv.npix[1]);
+    if (fi < 0.0 || fj < 0.0 || fi >= (double)dv.npix[0] || fj >= (double)dv.npix[1]) return true;
+    const double thick = dv.pix[(long)fj * dv.npix[0] + (long)fi];
+    if (thick < 0.0) return true;
+    k_out = k0;
+    if (thick == 0.0) return false;
+    double z = 0.0;                                     // displacement along the normal in the slab
+    for (unsigned long long k = k0; k < kend; ++k) {
+        // the step as replayed (the first one cut to the energy left below the spot energy)
+        const float4 r = a.steps[k];
+        long long e = step_energy(r);
+        double w_tot = r.x;
+        const double t2 = (double)r.z * r.z + (double)r.w * r.w;
+        double th = t2 > 0.0 ? sqrt(t2) : 0.0;
+        double cp = t2 > 0.0 ? r.z / th : 1.0, spp = t2 > 0.0 ? r.w / th : 0.0;
+        if (k == k0) {
+            const long long e_first = cum + e - skip;
+            const double f = (double)e_first / (double)e;
+            e = e_first;
+            w_tot *= f;
+            th *= sqrt(f);
+            double s0, c0;
+            sincos(phi0, &s0, &c0);
+            const double c = cp * c0 - spp * s0;
+            spp = spp * c0 + cp * s0;
+            cp = c;
+        }
+        double tau = 0.0, g2 = 0.0;
+        long long dep = 0;
+        bool on_face = false;                           // the step ended exactly on the exit face
+        while (tau < w_tot) {
+            dn = d[0] * dv.nrm[0] + d[1] * dv.nrm[1] + d[2] * dv.nrm[2];
+            double lgeo = dn > 0.0 ? (thick - z) / dn : __builtin_huge_val();
+            if (lgeo < 0.0) lgeo = 0.0;
+            const double rem = w_tot - tau, wb = lgeo * dv.rsp;
+            double w_v, tau_n, move;
+            bool exits;
+            if (rem <= wb) {
+                w_v = rem;
+                tau_n = w_tot;
+                move = rem / dv.rsp;
+                exits = rem == wb;
+            } else {
+                w_v = wb;
+                tau_n = tau + wb;
+                move = lgeo;
+                exits = true;
+            }
+            long long cumk = (long long)rint((double)e * (tau_n / w_tot));
+            if (tau_n >= w_tot) cumk = e;
+            up += cumk - dep;
+            dep = cumk;
+            g2 += w_v * dv.g;
+            tau = tau_n;
+#pragma unroll
+            for (int q = 0; q < 3; ++q) p[q] += move * d[q];
+            z += move * dn;
+            if (exits && tau < w_tot) {                 // out through the exit face inside the step
+                k_out = k;
+                tau_out = tau;
+                dep_out = (int)dep;
+                g2_out = g2;
+                return false;
+            }
+            on_face = exits;
+        }
+        // deflection at the end of the step (textbook polar/azimuth rotation)
+        const double th2 = th * sqrt(g2 / w_tot);
+        const double st = sin(th2), ct = cos(th2);
+        const double u = b[0], v = b[1], w = b[2];
+        const double rho = sqrt(u * u + v * v);
+        double nu, nv, nw;
+        if (rho < 1e-20) {
+            nu = st * cp;
+            nv = st * spp;
+            nw = w < 0.0 ? -ct : ct;
+        } else {
+            nu = u * ct + st * (u * w * cp - v * spp) / rho;
+            nv = v * ct + st * (v * w * cp + u * spp) / rho;
+            nw = w * ct - rho * st * cp;
+        }
+        const double l = sqrt(nu * nu + nv * nv + nw * nw);
+        b[0] = nu / l; b[1] = nv / l; b[2] = nw / l;
+#pragma unroll
+        for (int q = 0; q < 3; ++q) d[q] = sp.e1[q] * b[0] + sp.e2[q] * b[1] + sp.d[q] * b[2];
+        if (on_face) {                                  // a step ending on the exit face: the next starts beyond it
+            k_out = k + 1;
+            tau_out = 0.0;
+            dep_out = 0;
+            g2_out = 0.0;
+            return k + 1 >= kend;
+        }
+    }
+    return true;                                        // the track ended in the compensator
+}
+
 // wc: the wave's constants in LDS, written by process_unit: the spot's field
 // matrix (9 floats, row-major) and the plan's 1 / voxel size (3).  They are
 // read where they are used (volatile, so not hoisted into registers that
@@ -341,6 +470,29 @@ __host__ __device__ void replay_history(const TransportArgs &a, const DevSpot &s
         }
     }
 
+    // a beam-line device on the way (aperture, range compensator): the walk
+    // then begins where the history leaves it, possibly inside a step
+    const unsigned long long k_first = k;
+    double bb[3] = {0.0, 0.0, 1.0};                 // beam-frame direction
+    double tau0 = 0.0, g20 = 0.0;
+    int dep0 = 0;                                   // (the pass's own split of the step; the walk restates it)
+    long long up = 0;                               // energy deposited upstream of the phantom
+    if (!LISTED && sp.dev >= 0 && a.devices && I_h > 0 && k < kend) {
+        unsigned long long kw = k;
+        if (beam_device_pass(a, a.devices[sp.dev], sp, k, kend, cum, skip, (double)phi0, p, dsrc, bb, kw, tau0, dep0,
+                             g20, up)) {
+            esc = I_h;
+            if (EP) {
+                a.ep_xyz[3 * slot + 0] = (float)p[0];
+                a.ep_xyz[3 * slot + 1] = (float)p[1];
+                a.ep_xyz[3 * slot + 2] = (float)p[2];
+                a.ep_reason[slot] = 3;
+            }
+            return;
+        }
+        k = kw;
+    }
+
     // ray-box entry (FP64); outside the box is vacuum
     double tin = -__builtin_huge_val(), tout = __builtin_huge_val();
     int ax_in = 0;
@@ -385,7 +537,7 @@ __host__ __device__ void replay_history(const TransportArgs &a, const DevSpot &s
         L.f[q] = (float)fmin(fmax(u - (double)i, 0.0), 1.0);
         L.d[q] = (float)dsrc[q];
     }
-    L.b[0] = 0.f; L.b[1] = 0.f; L.b[2] = 1.f;
+    L.b[0] = (float)bb[0]; L.b[1] = (float)bb[1]; L.b[2] = (float)bb[2];
     // what the walk reads of the plan and spot, as values (not re-read from
     // memory inside the loops, where the tally atomics could alias them)
     const int nx = pl.n[0], ny = pl.n[1], nz = pl.n[2];
@@ -409,30 +561,42 @@ __host__ __device__ void replay_history(const TransportArgs &a, const DevSpot &s
     long long acc = 0, hdep = 0;
     bool escaped = false;
     // the partial first step (its remaining energy e_first of the stored e):
-    // length f * dx, angle sqrt(f) * theta, azimuth rotated by phi0
+    // length f * dx, angle sqrt(f) * theta, azimuth rotated by phi0; a later
+    // step (the walk begins behind a compensator) is replayed whole
     float4 rec = a.steps[k];
     e = step_energy(rec);
-    const long long e_first = cum + e - skip;
-    const float f = ll_to_f(e_first) / ll_to_f(e);
-    int e32 = (int)e_first;                         // a step's energy fits 32 bits (checked at load)
-    float w_tot = f * rec.x;
+    int e32 = (int)e;                               // a step's energy fits 32 bits (checked at load)
+    float w_tot = rec.x;
     float th, cph, sph;                             // polar angle, cos and sin of the azimuth
     polar_terms(rec, th, cph, sph);
-    th *= sqrtf(f);
-    float inv_w = 1.f / w_tot;
-    if (phi0 != 0.f) {                              // the track rotated rigidly about the beam axis
-        float s0, c0;
-        sincosf(phi0, &s0, &c0);
-        const float c = cph * c0 - sph * s0;
-        sph = sph * c0 + cph * s0;
-        cph = c;
+    float inv_w;
+    if (k == k_first) {
+        const long long e_first = cum + e - skip;
+        const float f = ll_to_f(e_first) / ll_to_f(e);
+        e32 = (int)e_first;
+        w_tot = f * rec.x;
+        th *= sqrtf(f);
+        inv_w = 1.f / w_tot;
+        if (phi0 != 0.f) {                          // the track rotated rigidly about the beam axis
+            float s0, c0;
+            sincosf(phi0, &s0, &c0);
+            const float c = cph * c0 - sph * s0;
+            sph = sph * c0 + cph * s0;
+            cph = c;
+        }
+    } else {
+        inv_w = fast_rcp(rec.x);
     }
+    // a step begun in a compensator continues with what was done of it there;
+    // its energy deposited so far is restated in the walk's own arithmetic
+    // (the FP32 split the walk applies to the WEL consumed), so that the
+    // walk's pieces, which continue that split, are never negative
+    float tau = (float)tau0, g2 = (float)g20;
+    int dep = tau0 > 0.0 ? min(e32, (int)rintf((float)e32 * (tau * inv_w))) : 0;
     float4 next_rec = rec;
     if (k + 1 < kend) next_rec = a.steps[k + 1];
     for (;;) {
         const float ef = (float)e32;
-        float tau = 0.f, g2 = 0.f;
-        int dep = 0;
         while (tau < w_tot) {
             const uint32_t kskip = vacuum_skip(wcur);
             if (kskip >= 2u) {
@@ -572,9 +736,12 @@ __host__ __device__ void replay_history(const TransportArgs &a, const DevSpot &s
         polar_terms(rec, th, cph, sph);
         inv_w = fast_rcp(rec.x);
         e32 = (int)step_energy(rec);
+        tau = 0.f;
+        g2 = 0.f;
+        dep = 0;
     }
     if (!escaped && acc != 0) sink.add(L.v, (uint32_t)L.i[0], acc);
-    esc = escaped ? I_h - hdep : 0;
+    esc = I_h - hdep;                               // escaped, or deposited upstream (up), or 0
     if (EP) {
 #pragma unroll
         for (int q = 0; q < 3; ++q)
@@ -875,6 +1042,18 @@ hipError_t prepare_lds_kernels()
     for (int i = 0; i < 6 && e == hipSuccess; ++i)
         e = hipFuncSetAttribute(k[i], hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
     return e;
+}
+
+// Workgroups of the whole-launch cache kernel (waves_per_block waves, `slots`
+// LDS slots per tally) that fit one CU at once.  The kernel's waves wait on an
+// LDS word that a sibling wave of the same workgroup writes; a workgroup is
+// dispatched whole, so its waves are resident together whenever it runs at
+// all, and this is at least 1 exactly when the launch can run.
+hipError_t cache_kernel_occupancy(uint32_t waves_per_block, uint32_t slots, bool variance, int *blocks)
+{
+    const void *k = variance ? (const void *)transport_cache_kernel<true> : (const void *)transport_cache_kernel<false>;
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, k, (int)(waves_per_block * kWave),
+                                                        lds_tally_bytes(slots, variance, 2));
 }
 
 hipError_t launch_transport_lds(const TransportArgs &a, uint32_t waves_per_block, uint32_t grid_blocks,

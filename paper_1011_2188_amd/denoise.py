@@ -23,10 +23,12 @@ from . import fdc as F
 from . import inputs as I
 
 
-def denoise_plan(seed, shape=(128, 128, 64), voxel_cm=0.4, e_range=(70.0, 200.0), spots=(200, 2000)):
-    """A thorax-like plan: C3 anatomy scaled to the box, +-15% jitter of the
-    body, lung and spine, 1-3 coplanar fields of spots on a square at the
-    right-lung centre.  Returns (phantom, spots) with n_histories = 1 per spot."""
+def denoise_plan(seed, shape=(128, 128, 64), voxel_cm=0.4, e_range=(70.0, 200.0), spots=(200, 2000),
+                 half_width_cm=3.0):
+    """A thorax-like plan: the thorax anatomy scaled to the box, +-15% jitter of
+    the body, lung and spine, 1-3 coplanar fields of spots on a square of half
+    width half_width_cm at the right-lung centre.  Returns (phantom, spots)
+    with n_histories = 1 per spot."""
     rng = np.random.default_rng([int(seed), 55])
     nx, ny, nz = shape
     sc = (nx * voxel_cm / 51.2, ny * voxel_cm / 51.2, nz * voxel_cm / 25.6)
@@ -40,7 +42,7 @@ def denoise_plan(seed, shape=(128, 128, 64), voxel_cm=0.4, e_range=(70.0, 200.0)
     n_spots = int(rng.integers(spots[0], spots[1] + 1))
     iso = (7.0 * sc[0], -1.0 * sc[1], 0.0)
     per = np.diff(np.linspace(0, n_spots, n_fields + 1).astype(int))
-    sp = np.concatenate([I.field_spots(iso, g, int(k), rng, half_width_cm=3.0 * sc[0], e_range=e_range,
+    sp = np.concatenate([I.field_spots(iso, g, int(k), rng, half_width_cm=half_width_cm * sc[0], e_range=e_range,
                                        histories=np.ones(int(k), np.uint64)) for g, k in zip(gantries, per)])
     return ph, sp
 
@@ -187,3 +189,108 @@ def infer(params, x):
     net.forward(x, y)
     net.close()
     return y
+
+
+# ---- the denoised route to the plain method's gamma pass rate -----------------
+
+def with_total(sp, total):
+    """The spots with `total` histories per run, split evenly (the first spots
+    take the remainder)."""
+    sp = sp.copy()
+    base, extra = divmod(int(total), len(sp))
+    sp["n_histories"] = base
+    sp["n_histories"][:extra] += 1
+    return sp
+
+
+def plan_dose(ctx, ph, sp, total, flags=0):
+    """A new plan of phantom ph with spots sp at `total` histories, run once;
+    (plan id, dose, variance or None) as float64 device tensors.  A new plan id
+    keys new random numbers, so doses of different plans are independent."""
+    import torch
+    p = ctx.load_phantom(ph)
+    ctx.add_beam_spots(p, with_total(sp, total))
+    ctx.run_histories([p], flags)
+    n = ph.hu.size
+    d = torch.empty(n, dtype=torch.float64, device="cuda")
+    v = torch.empty(n, dtype=torch.float64, device="cuda") if flags & F.FDC_RUN_VARIANCE else None
+    ctx.compute_dose(p, d, v)
+    return p, d, v
+
+
+def normalised(ctx, plan, dose, rho, scale):
+    """(dose * scale, rho / 2) as a [2, nz, ny, nx] float32 tensor (the network
+    input, and with channel 0 alone a dose on the same normalisation)."""
+    import torch
+    shape = ctx.plans[plan]                          # (nz, ny, nx)
+    out = torch.empty((2,) + tuple(shape), dtype=torch.float32, device="cuda")
+    ctx.denoise_input(plan, dose, rho, scale, out)
+    return out
+
+
+def gamma_ladder(ctx, ph, sp, params, n2, rate, ref_total=400_000_000, rungs=7, plain=None, ref=None,
+                 flags=F.FDC_RUN_ROTATE_TRACKS, log=None):
+    """Seconds to the plain method's gamma pass rate, plain vs denoised.
+
+    G* = gamma pass rate (2%/2 mm, global, 10% cutoff) of the plain dose of
+    n2 histories (the histories to 2% mean uncertainty; `plain` = (plan, dose)
+    if already run) against an independent reference of ref_total histories.
+    The denoised dose is evaluated at N = n2 / 2^(rungs-1) ... n2 / 2, n2 (the
+    ladder n2 * {1/64, ..., 1} for 7 rungs); N_d = the smallest N whose
+    denoised dose reaches G*.  Times: histories / rate (the measured transport
+    rate), plus the measured inference time for the denoised route.  Every rung
+    is a new plan (independent histories); the plain dose of each rung is
+    scored too."""
+    import torch
+    if ref is None:
+        pr, dref, _ = plan_dose(ctx, ph, sp, ref_total, flags)
+    else:
+        pr, dref = ref
+    if plain is None:
+        pp, dplain, _ = plan_dose(ctx, ph, sp, int(round(n2)), flags)
+    else:
+        pp, dplain = plain
+    rho = torch.empty(ph.hu.size, dtype=torch.float32, device="cuda")
+    ctx.density(pp, rho)
+    g_star = ctx.gamma_index(pp, dref, dplain)[0]
+    net = F.UNet(tuple(ph.hu.shape))
+    net.set_params(params)
+    y = torch.empty(tuple(ph.hu.shape), dtype=torch.float32, device="cuda")
+    rows, n_d, t_inf_best = [], None, None
+    for j in range(rungs):
+        n = max(1, int(round(n2 / 2 ** (rungs - 1 - j))))
+        p, d, _ = plan_dose(ctx, ph, sp, n, flags)
+        _, _, dmax = ctx.mean_uncertainty(p, d, d, 0.5)
+        scale = 1.0 / dmax if dmax > 0 else 1.0
+        x = normalised(ctx, p, d, rho, scale)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        net.forward(x, y)
+        torch.cuda.synchronize()
+        t_inf = time.perf_counter() - t0
+        t_inf_best = t_inf if t_inf_best is None else min(t_inf_best, t_inf)
+        r = normalised(ctx, p, dref, rho, scale)[0].reshape(-1).double()
+        g_den = ctx.gamma_index(p, r, y.reshape(-1).double())[0]
+        g_plain = ctx.gamma_index(p, r, x[0].reshape(-1).double())[0]
+        rows.append({"histories": n, "gamma_denoised": g_den, "gamma_plain": g_plain, "inference_s": t_inf})
+        if log:
+            log(f"  rung {j}: {n} histories, gamma denoised {g_den:.5f} plain {g_plain:.5f} (G* {g_star:.5f})")
+        if n_d is None and g_den >= g_star:
+            n_d = (n, t_inf)
+    net.close()
+    return {"N_2pct": n2, "G_star": g_star, "reference_histories": ref_total, "t_plain_s": n2 / rate,
+            "ladder": rows, "N_denoised": n_d[0] if n_d else None,
+            "t_denoised_s": (n_d[0] / rate + n_d[1]) if n_d else None, "inference_s": t_inf_best}
+
+
+def save_params(path, params, meta):
+    """Network parameters (float32) and a JSON description, as an .npz (no pickles)."""
+    import json
+    np.savez(path, params=np.asarray(params, np.float32), meta=np.frombuffer(json.dumps(meta).encode(), np.uint8))
+
+
+def load_params(path):
+    """(params float32, meta dict) from save_params' file."""
+    import json
+    with np.load(path, allow_pickle=False) as z:
+        return z["params"].astype(np.float32), json.loads(bytes(z["meta"]).decode())

@@ -221,6 +221,173 @@ def denoiser_study(db, n_train=128, n_test=6, shape=(256, 256, 128), voxel_cm=0.
     return out
 
 
+C5_LAUNCH = dict(waves_per_block=16, blocks_per_cu=1, tally_slots=8064, units_per_wave=2, tally_mode=2,
+                 source_order=1)
+
+
+def c5_pairs(db, seeds, shape, voxel_cm, base, levels, high, launch, log, e_range=(70.0, 230.0), t_high=None):
+    """Training samples of the given plan seeds: per plan the density / 2
+    (bf16) and the high-history target divided by its own Dmax (float32); per
+    input level k the dose of k * base histories divided by its own Dmax (bf16)
+    and the ratio of the two Dmax values (the target on the input's
+    normalisation is target * ratio).  Plans run in contexts of 25 plans
+    (closed afterwards); track rotation on; every dose is a new plan id, so
+    inputs and targets never share a history."""
+    import concurrent.futures as cf
+
+    import torch
+    out = []
+    t_high = [] if t_high is None else t_high          # wall time of each target run (load, run, dose)
+    # the phantoms are generated on the host two plans ahead of the GPU work
+    pool = cf.ThreadPoolExecutor(2)
+    make = lambda sd: D.denoise_plan(sd, shape, voxel_cm, e_range=e_range, half_width_cm=4.0)
+    futs = {sd: pool.submit(make, sd) for sd in seeds[:2]}
+    for c0 in range(0, len(seeds), 25):
+        ctx = F.Context(0, 7, table=I.HU_TABLE_DEFAULT)
+        ctx.load_track_db(db)
+        ctx.set_launch_config(**launch)
+        for i, sd in enumerate(seeds[c0:c0 + 25]):
+            for nxt in seeds[c0 + i + 1:c0 + i + 3]:
+                if nxt not in futs:
+                    futs[nxt] = pool.submit(make, nxt)
+            ph, sp = futs.pop(sd).result()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ph_, hd, _ = D.plan_dose(ctx, ph, sp, high, F.FDC_RUN_ROTATE_TRACKS)
+            torch.cuda.synchronize()
+            t_high.append(time.perf_counter() - t0)
+            rho = torch.empty(ph.hu.size, dtype=torch.float32, device="cuda")
+            ctx.density(ph_, rho)
+            _, _, dmax_h = ctx.mean_uncertainty(ph_, hd, hd, 0.5)
+            th = D.normalised(ctx, ph_, hd, rho, 1.0 / dmax_h)
+            sample = {"rho": th[1].to(torch.bfloat16), "target": th[0].clone(), "levels": []}
+            del th, hd
+            for k in levels:
+                pl, ld, _ = D.plan_dose(ctx, ph, sp, k * base, F.FDC_RUN_ROTATE_TRACKS)
+                _, _, dmax_l = ctx.mean_uncertainty(pl, ld, ld, 0.5)
+                xl = D.normalised(ctx, pl, ld, rho, 1.0 / dmax_l)
+                sample["levels"].append((xl[0].to(torch.bfloat16), dmax_h / dmax_l))
+                del xl, ld
+            out.append(sample)
+        torch.cuda.synchronize()
+        ctx.close()
+        log(f"c5 pairs: {min(c0 + 25, len(seeds))}/{len(seeds)} plans")
+    pool.shutdown()
+    return out
+
+
+def train_samples(samples, crop, steps, lr=1e-3, seed=0, log=None, log_every=500, focus=0.9, lr_final=0.1):
+    """D.train on c5_pairs samples: a step picks a plan and an input level,
+    crops (x = (input, density), target * ratio) around the dose region with
+    probability focus, and mirrors the crop along random axes."""
+    import torch
+    net = F.UNet(crop)
+    net.init_params(seed)
+    rng = np.random.default_rng(seed)
+    hot = [D._dose_voxels(s["target"]) for s in samples]
+    losses = []
+    cz, cy, cx = crop
+    t0 = time.perf_counter()
+    for it in range(steps):
+        k = int(rng.integers(len(samples)))
+        s = samples[k]
+        low, ratio = s["levels"][int(rng.integers(len(s["levels"])))]
+        nz, ny, nx = s["target"].shape
+        if hot[k].size and rng.random() < focus:
+            c = int(hot[k][int(rng.integers(hot[k].size))])
+            centre = (c // (ny * nx), (c // nx) % ny, c % nx)
+            z0, y0, x0 = (min(max(int(q) - w // 2 + int(rng.integers(-w // 4, w // 4 + 1)), 0), n - w)
+                          for q, w, n in zip(centre, crop, (nz, ny, nx)))
+        else:
+            z0, y0, x0 = (int(rng.integers(0, n - w + 1)) for n, w in zip((nz, ny, nx), crop))
+        sl = (slice(z0, z0 + cz), slice(y0, y0 + cy), slice(x0, x0 + cx))
+        xc = torch.stack([low[sl], s["rho"][sl]]).float()
+        tc = s["target"][sl] * float(ratio)
+        axes = [a for a in (0, 1, 2) if rng.random() < 0.5]
+        if axes:
+            xc = torch.flip(xc, [a + 1 for a in axes])
+            tc = torch.flip(tc, axes)
+        want = (it % log_every == 0) or it == steps - 1
+        loss = net.backward(xc.contiguous(), tc.contiguous(), want_loss=want)
+        rate = lr * (lr_final + (1 - lr_final) * 0.5 * (1 + math.cos(math.pi * it / max(steps - 1, 1))))
+        net.adam(rate)
+        if want:
+            losses.append((it, loss))
+            if log:
+                log(f"step {it} loss {loss:.4g} lr {rate:.3g} ({time.perf_counter() - t0:.1f} s)")
+    torch.cuda.synchronize()
+    params = net.get_params()
+    net.close()
+    return params, losses, time.perf_counter() - t0
+
+
+def c5_study(db, n_train=500, n_val=50, shape=(256, 256, 128), voxel_cm=0.2, base=250_000, levels=(1, 2, 4, 8),
+             high=100_000_000, ref_total=400_000_000, crop=(128, 128, 128), steps=16000, lr=1e-3,
+             launch=C5_LAUNCH, weights_out=None, json_out=None, log=print):
+    """The learned denoiser at full scale: n_train thorax-like training plans
+    (seeds 10000..) and n_val validation plans (seeds 20000..), 256x256x128 of
+    2 mm, 1-3 fields of 200-2000 spots, 70-230 MeV, over 8x8 cm at the right
+    lung.  Inputs: doses of k * base histories (k in levels: 2.5e5 .. 2e6, the
+    1e6-history input among them); targets 1e8 histories; 128^3 crops, MSE,
+    Adam (lr 1e-3, cosine to 1e-4).  Each validation plan: N_2% from the Eq.
+    (2) mean uncertainty of 1e6 histories, G* of the plain dose at N_2% against
+    an independent 4e8-history reference, the denoised ladder N_2% * {1/64 ..
+    1} (gamma_ladder).  Times use the transport rate measured on the pairs.
+    With json_out, the result so far is written after every validation plan."""
+    import torch
+    t = time.perf_counter()
+    t_high = []
+    samples = c5_pairs(db, [10_000 + k for k in range(n_train)], shape, voxel_cm, base, levels, high, launch, log,
+                       t_high=t_high)
+    torch.cuda.synchronize()
+    t_pairs = time.perf_counter() - t
+    n_hist = n_train * (high + sum(levels) * base)
+    rate = high / float(np.median(t_high))              # a target run: load, 1e8 histories, dose
+    log(f"c5 pairs: {n_train} plans, {n_hist:.3g} histories in {t_pairs:.1f} s; target runs at {rate:.3g} "
+        f"histories/s (median, loading and dose included)")
+    params, losses, t_train = train_samples(samples, crop, steps, lr, seed=0, log=log)
+    del samples
+    torch.cuda.empty_cache()
+    meta = {"train_plans": n_train, "seeds": [10_000, 10_000 + n_train - 1], "shape_xyz": list(shape),
+            "voxel_cm": voxel_cm, "input_histories": [k * base for k in levels], "target_histories": high,
+            "crop_zyx": list(crop), "steps": steps, "lr": lr, "n_params": int(params.size)}
+    if weights_out:
+        D.save_params(weights_out, params, meta)
+        log(f"weights written to {weights_out}")
+    rows = []
+    ctx = None
+    for j in range(n_val):
+        if ctx is not None:
+            ctx.close()
+        ctx = F.Context(0, 11, table=I.HU_TABLE_DEFAULT)
+        ctx.load_track_db(db)
+        ctx.set_launch_config(**launch)
+        ph, sp = D.denoise_plan(20_000 + j, shape, voxel_cm, e_range=(70.0, 230.0), half_width_cm=4.0)
+        p1, d1, v1 = D.plan_dose(ctx, ph, sp, 1_000_000, F.FDC_RUN_VARIANCE | F.FDC_RUN_ROTATE_TRACKS)
+        u1, _, _ = ctx.mean_uncertainty(p1, d1, v1, 0.5)
+        n2 = 1_000_000 * (u1 / 0.02) ** 2
+        row = D.gamma_ladder(ctx, ph, sp, params, n2, rate, ref_total=ref_total)
+        row.update(plan_seed=20_000 + j, u_1e6=u1)
+        rows.append(row)
+        lad = " ".join(f"{r['histories']:.3g}:{r['gamma_denoised']:.4f}/{r['gamma_plain']:.4f}" for r in row["ladder"])
+        log(f"c5 val {j}: N_2% {n2:.3g}, G* {row['G_star']:.5f}, N_d {row['N_denoised']}, ladder {lad}")
+        del d1, v1
+        if json_out:
+            import json
+            with open(json_out, "w") as f:
+                json.dump({**meta, "rate_histories_per_s": rate, "pair_seconds": t_pairs, "train_seconds": t_train,
+                           "final_losses": losses[-5:], "rows": rows}, f, default=float)
+    if ctx is not None:
+        ctx.close()
+    reached = [r for r in rows if r["N_denoised"] is not None]
+    out = {**meta, "val_plans": n_val, "pair_seconds": t_pairs, "train_seconds": t_train,
+           "rate_histories_per_s": rate, "final_losses": losses[-5:], "reached": len(reached),
+           "t_plain_mean_s": float(np.mean([r["t_plain_s"] for r in rows])),
+           "t_denoised_mean_s_reached": float(np.mean([r["t_denoised_s"] for r in reached])) if reached else None,
+           "rows": rows}
+    return out
+
+
 # multiply-adds of one voxel through the network (all layers, forward), times 2
 UNET_FLOP_PER_VOXEL = 94_880
 
@@ -389,15 +556,27 @@ def _main():
     import argparse
     import json
     ap = argparse.ArgumentParser(prog="python -m paper_1011_2188_amd.experiments")
-    ap.add_argument("what", choices=["denoiser"])
+    ap.add_argument("what", choices=["denoiser", "c5"])
     ap.add_argument("--reps", type=int, default=3)
+    ap.add_argument("--train", type=int, default=500, help="c5: training plans")
+    ap.add_argument("--val", type=int, default=50, help="c5: validation plans")
+    ap.add_argument("--steps", type=int, default=16000, help="c5: training steps")
+    ap.add_argument("--weights", default=None, help="c5: write the trained parameters here (.npz)")
+    ap.add_argument("--json", default=None, help="c5: write the result here")
     args = ap.parse_args()
     import torch
     assert torch.cuda.is_available(), "the experiments need a GPU"
     torch.cuda.init()
+    log = lambda m: print(m, flush=True)
     if args.what == "denoiser":
-        out = denoiser_rate(args.reps, log=lambda m: print(m, flush=True))
-    print(json.dumps(out), flush=True)
+        out = denoiser_rate(args.reps, log=log)
+    else:
+        out = c5_study(W.multi_bin_db(), n_train=args.train, n_val=args.val, steps=args.steps,
+                       weights_out=args.weights, json_out=args.json, log=log)
+        if args.json:
+            with open(args.json, "w") as f:
+                json.dump(out, f, default=float)
+    print(json.dumps(out, default=float), flush=True)
 
 
 if __name__ == "__main__":

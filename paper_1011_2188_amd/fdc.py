@@ -29,7 +29,8 @@ ERROR_NAMES = {0: "FDC_OK", -1: "FDC_E_ARG", -2: "FDC_E_STATE", -3: "FDC_E_NOMEM
 # every entry point declared in include/fdc.h
 EXPORTS = ["fdc_create", "fdc_destroy", "fdc_last_error", "fdc_set_allocator", "fdc_set_hu_table",
            "fdc_load_track_db", "fdc_load_track_db_file", "fdc_load_phantom", "fdc_add_beam_spots", "fdc_add_phase_space",
-           "fdc_add_phase_space_file", "fdc_run_histories", "fdc_run_histories_noalloc", "fdc_prepare_run",
+           "fdc_add_phase_space_file", "fdc_add_beam_device", "fdc_set_spot_device", "fdc_run_histories",
+           "fdc_run_histories_noalloc", "fdc_prepare_run",
            "fdc_reset_plan", "fdc_compute_dose", "fdc_read_dose_and_variance", "fdc_debug_endpoints",
            "fdc_debug_philox", "fdc_debug_material", "fdc_set_launch_config", "fdc_device_cus",
            "fdc_mean_uncertainty", "fdc_batch_uncertainty", "fdc_gamma_index",
@@ -45,6 +46,11 @@ FDC_GRAPH_DOSE = 2
 class fdc_summary(C.Structure):
     _fields_ = [("n_histories", C.c_uint64), ("incident_fp", C.c_int64),
                 ("deposited_fp", C.c_int64), ("escaped_fp", C.c_int64)]
+
+
+class fdc_beam_device(C.Structure):
+    _fields_ = [("origin_cm", C.c_float * 3), ("dir", C.c_float * 3), ("pitch_cm", C.c_float * 2),
+                ("n", C.c_uint32 * 2), ("rsp", C.c_float), ("rscp", C.c_float)]
 
 
 class fdc_launch_config(C.Structure):
@@ -88,6 +94,8 @@ def lib():
         "fdc_add_beam_spots": (C.c_int, [_P, C.c_int32, _P, C.c_uint32]),
         "fdc_add_phase_space": (C.c_int, [_P, C.c_int32, _P, C.c_uint64, C.POINTER(C.c_uint32), _P]),
         "fdc_add_phase_space_file": (C.c_int, [_P, C.c_int32, C.c_char_p, C.POINTER(C.c_uint32), _P]),
+        "fdc_add_beam_device": (C.c_int, [_P, C.POINTER(fdc_beam_device), _P, C.POINTER(C.c_int32), _P]),
+        "fdc_set_spot_device": (C.c_int, [_P, C.c_int32, C.c_uint32, C.c_uint32, C.c_int32]),
         "fdc_run_histories": (C.c_int, [_P, _P, C.c_uint32, C.c_uint32, _P]),
         "fdc_run_histories_noalloc": (C.c_int, [_P, _P, C.c_uint32, C.c_uint32, _P]),
         "fdc_prepare_run": (C.c_int, [_P]),
@@ -288,6 +296,22 @@ class Context:
         from .inputs import SPOT_DTYPE
         s = np.ascontiguousarray(spots, SPOT_DTYPE)
         _check(self.h, lib().fdc_add_beam_spots(self.h, plan, s.ctypes.data, s.size))
+
+    def add_beam_device(self, dev, stream=None):
+        """A beam-line device (a dict from inputs.beam_device); returns its id."""
+        d = fdc_beam_device()
+        d.origin_cm[:] = [float(x) for x in dev["origin_cm"]]
+        d.dir[:] = [float(x) for x in dev["dir"]]
+        d.pitch_cm[:] = [float(x) for x in dev["pitch_cm"]]
+        d.n[:] = [int(x) for x in dev["n"]]
+        d.rsp, d.rscp = float(dev["rsp"]), float(dev["rscp"])
+        pix = np.ascontiguousarray(dev["pixels"], np.float32)
+        out = C.c_int32()
+        _check(self.h, lib().fdc_add_beam_device(self.h, C.byref(d), pix.ctypes.data, C.byref(out), _stream(stream)))
+        return out.value
+
+    def set_spot_device(self, plan, first_spot, n_spots, device):
+        _check(self.h, lib().fdc_set_spot_device(self.h, plan, first_spot, n_spots, device))
 
     def add_phase_space(self, plan, particles, stream=None):
         """Listed incident protons (inputs.PARTICLE_DTYPE); returns the number of

@@ -354,6 +354,37 @@ def disk_field(pos, direction, energy_MeV, radius_cm, n_histories):
     return spots([pos], [direction], [energy_MeV], -float(radius_cm), n_histories)
 
 
+def beam_device(origin_cm, direction, pitch_cm, pixels, rsp=1.0, rscp=1.0):
+    """A beam-line device upstream of the phantom: an aperture and a range
+    compensator on one pixel grid in the plane through origin_cm (the centre
+    of its upstream face) perpendicular to direction (along the beam).
+    pixels[j][i] (i along e1, fastest; j along e2; (e1, e2) the lateral axes of
+    direction as for a spot, the grid centred on origin_cm, pitch_cm per
+    axis): < 0 closed, else the compensator thickness in cm along direction
+    (0: open, no material).  rsp, rscp: the compensator material's relative
+    stopping and scattering powers."""
+    pix = np.ascontiguousarray(np.asarray(pixels, np.float32))
+    assert pix.ndim == 2
+    return dict(origin_cm=np.asarray(origin_cm, np.float32).reshape(3), dir=np.asarray(direction, np.float32).reshape(3),
+                pitch_cm=np.asarray(pitch_cm, np.float32).reshape(2), n=np.array([pix.shape[1], pix.shape[0]], np.uint32),
+                rsp=float(rsp), rscp=float(rscp), pixels=pix)
+
+
+def aperture_compensator(origin_cm, direction, radius_cm, ramp_cm=(0.0, 0.0), pitch_cm=0.1, half_width_cm=None,
+                         rsp=1.19, rscp=1.35):
+    """A circular aperture of radius radius_cm with a wedge-shaped compensator
+    behind it (thickness ramp_cm[0] at e1 = -radius rising linearly to
+    ramp_cm[1] at e1 = +radius), on a square grid of pitch pitch_cm; the
+    default material resembles PMMA (RSP 1.19)."""
+    hw = radius_cm * 1.25 if half_width_cm is None else half_width_cm
+    n = int(math.ceil(2 * hw / pitch_cm))
+    c = (np.arange(n) + 0.5 - n / 2) * pitch_cm
+    a, b = np.meshgrid(c, c)                                    # a along e1 (columns), b along e2 (rows)
+    t = ramp_cm[0] + (ramp_cm[1] - ramp_cm[0]) * (a + radius_cm) / (2 * radius_cm)
+    pix = np.where(a * a + b * b <= radius_cm * radius_cm, np.maximum(t, 0.0), -1.0)
+    return beam_device(origin_cm, direction, (pitch_cm, pitch_cm), pix, rsp, rscp)
+
+
 def gantry_direction(gantry_deg):
     """Beam direction in the x-y plane for a coplanar gantry angle:
     0 deg points along -y, 90 deg along -x, 180 deg along +y."""

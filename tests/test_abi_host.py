@@ -249,3 +249,30 @@ def test_phase_space_validation_and_grouping(ctx, tmp_path):
     c2.load_phantom(I.water_phantom((4, 4, 4), 0.5))
     _expect(F.FDC_E_STATE, c2.add_phase_space, 0, q)            # no database
     c2.close()
+
+
+def test_beam_device_validation(ctx):
+    ctx.load_track_db(_db())
+    p = ctx.load_phantom(I.water_phantom((4, 4, 4), 0.5))
+    ctx.add_beam_spots(p, I.spots([[0, 0, -5]] * 3, [[0, 0, 1]] * 3, [101.0] * 3, 0.3, 10))
+    good = I.beam_device([0, 0, -2], [0, 0, 1], [0.1, 0.1], np.zeros((8, 8)))
+    assert ctx.add_beam_device(good) == 0
+    bad = dict(good, pitch_cm=np.array([0.0, 0.1], np.float32))
+    _expect(F.FDC_E_ARG, ctx.add_beam_device, bad)
+    bad = dict(good, dir=np.zeros(3, np.float32))
+    _expect(F.FDC_E_ARG, ctx.add_beam_device, bad)
+    bad = dict(good, pixels=np.full((8, 8), np.nan, np.float32))
+    _expect(F.FDC_E_ARG, ctx.add_beam_device, bad)
+    bad = dict(good, pixels=np.ones((8, 8), np.float32), rsp=0.0)          # material needs rsp > 0
+    _expect(F.FDC_E_ARG, ctx.add_beam_device, bad)
+    assert ctx.add_beam_device(dict(good, pixels=-np.ones((8, 8), np.float32), rsp=0.0)) == 1   # aperture only
+    ctx.set_spot_device(p, 0, 2, 1)
+    ctx.set_spot_device(p, 2, 1, -1)
+    _expect(F.FDC_E_ARG, ctx.set_spot_device, p, 2, 2, 0)                  # past the plan's spots
+    _expect(F.FDC_E_ARG, ctx.set_spot_device, p, 0, 1, 2)                  # no device 2
+    _expect(F.FDC_E_ARG, ctx.set_spot_device, 5, 0, 1, 0)
+    q = ctx.load_phantom(I.water_phantom((4, 4, 4), 0.5))
+    ps = I.synthetic_phase_space(20, seed=3, e_mean=102.0, e_sigma=0.5, tail_fraction=0.0)
+    ctx.add_phase_space(q, ps)
+    _expect(F.FDC_E_ARG, ctx.set_spot_device, q, 0, 1, 0)                  # listed protons take no device
+    ctx.run_histories([p], 0)

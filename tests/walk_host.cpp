@@ -175,6 +175,7 @@ int main(int argc, char **argv)
     std::vector<int> ep_reason;
     for (uint32_t s = 0; s < n_spots; ++s) {
         DevSpot sp{};
+        sp.dev = -1;                                   // no beam-line device
         double d[3] = {dir[3 * s], dir[3 * s + 1], dir[3 * s + 2]};
         const double l = std::sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
         for (double &x : d) x /= l;
