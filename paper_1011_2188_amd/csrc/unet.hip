@@ -106,16 +106,19 @@ __global__ void __launch_bounds__(256) igemm_kernel(const u16 *__restrict__ src,
     const int kvalid = n_off * cpad;
     const int fx = 2 * g.nx, fy = 2 * g.ny;     // fine grid (A_S2D sources)
 
+    // (grids hold fewer than 2^31 rows, checked by the host: 32-bit divisions)
+    const uint32_t unx = (uint32_t)g.nx, uny = (uint32_t)g.ny;
     int rz[MT], ry[MT], rx[MT];
     bool rok[MT];
 #pragma unroll
     for (int m = 0; m < MT; ++m) {
         const long r = row0 + 16 * m + li;
         rok[m] = r < n_rows;
-        const long rr = rok[m] ? r : 0;
-        rx[m] = (int)(rr % g.nx);
-        ry[m] = (int)((rr / g.nx) % g.ny);
-        rz[m] = (int)(rr / ((long)g.nx * g.ny));
+        const uint32_t rr = rok[m] ? (uint32_t)r : 0u;
+        const uint32_t q = rr / unx;
+        rx[m] = (int)(rr - q * unx);
+        ry[m] = (int)(q % uny);
+        rz[m] = (int)(q / uny);
     }
     f32x4 acc[MT][NT];
 #pragma unroll
@@ -194,7 +197,8 @@ __global__ void __launch_bounds__(256) igemm_kernel(const u16 *__restrict__ src,
             const int n = n_base + 8 * cc;
             if (r >= n_rows || n >= n_cols) continue;
             const int a8 = n / d2s_cout, co = n - a8 * d2s_cout;
-            const int x = (int)(r % g.nx), y = (int)((r / g.nx) % g.ny), z = (int)(r / ((long)g.nx * g.ny));
+            const uint32_t r32 = (uint32_t)r, qy = r32 / unx;
+            const int x = (int)(r32 - qy * unx), y = (int)(qy % uny), z = (int)(qy / uny);
             const long fv = ((long)(2 * z + (a8 >> 2)) * fy + (2 * y + ((a8 >> 1) & 1))) * fx + 2 * x + (a8 & 1);
             *(uint4 *)(dst + fv * dst_pitch + co) = *(const uint4 *)(tl + rl * TP + 8 * cc);
         }
@@ -539,7 +543,10 @@ __global__ void __launch_bounds__(256) wgrad_kernel(const u16 *__restrict__ P, i
             if (r < r_end) {
                 if (8 * cg < p_ch) vp = *(const uint4 *)(P + r * p_pitch + 8 * cg);
                 if (8 * cg < q_ch) {
-                    const int x = (int)(r % g.nx), y = (int)((r / g.nx) % g.ny), z = (int)(r / ((long)g.nx * g.ny));
+                    // (grids hold fewer than 2^31 rows: 32-bit divisions)
+                    const uint32_t r32 = (uint32_t)r, qy = r32 / (uint32_t)g.nx;
+                    const int x = (int)(r32 - qy * (uint32_t)g.nx), y = (int)(qy % (uint32_t)g.ny),
+                              z = (int)(qy / (uint32_t)g.ny);
                     long sv = -1;
                     if (AM == A_CONV3) {
                         const int zz = z + o / 9 - 1, yy = y + (o / 3) % 3 - 1, xx = x + o % 3 - 1;

@@ -229,7 +229,7 @@ def normalised(ctx, plan, dose, rho, scale):
 
 
 def gamma_ladder(ctx, ph, sp, params, n2, rate, ref_total=400_000_000, rungs=7, plain=None, ref=None,
-                 flags=F.FDC_RUN_ROTATE_TRACKS, log=None):
+                 flags=F.FDC_RUN_ROTATE_TRACKS, log=None, above=0):
     """Seconds to the plain method's gamma pass rate, plain vs denoised.
 
     G* = gamma pass rate (2%/2 mm, global, 10% cutoff) of the plain dose of
@@ -240,7 +240,8 @@ def gamma_ladder(ctx, ph, sp, params, n2, rate, ref_total=400_000_000, rungs=7, 
     denoised dose reaches G*.  Times: histories / rate (the measured transport
     rate), plus the measured inference time for the denoised route.  Every rung
     is a new plan (independent histories); the plain dose of each rung is
-    scored too."""
+    scored too.  `above` further rungs go past n2 (2 n2, 4 n2, ...): where the
+    denoised route needs more histories than the plain one."""
     import torch
     if ref is None:
         pr, dref, _ = plan_dose(ctx, ph, sp, ref_total, flags)
@@ -257,8 +258,8 @@ def gamma_ladder(ctx, ph, sp, params, n2, rate, ref_total=400_000_000, rungs=7, 
     net.set_params(params)
     y = torch.empty(tuple(ph.hu.shape), dtype=torch.float32, device="cuda")
     rows, n_d, t_inf_best = [], None, None
-    for j in range(rungs):
-        n = max(1, int(round(n2 / 2 ** (rungs - 1 - j))))
+    for j in range(rungs + above):
+        n = max(1, int(round(n2 * 2.0 ** (j - (rungs - 1)))))
         p, d, _ = plan_dose(ctx, ph, sp, n, flags)
         _, _, dmax = ctx.mean_uncertainty(p, d, d, 0.5)
         scale = 1.0 / dmax if dmax > 0 else 1.0
