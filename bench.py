@@ -129,7 +129,7 @@ def mean_unc(c, plan, dose, var):
     return u
 
 
-def extras(c, plan, nvox, hist_per_step, launch, variance):
+def extras(c, plan, nvox, hist_per_step, launch, variance, ph_thorax, sp_thorax):
     """Other rows of the path, timed live: the batch estimator of Eq. (1) on the
     thorax (six batches of new histories, energy tally only, as the paper's batch
     method; the batches share the database, whose own variance the recycling
@@ -226,6 +226,36 @@ def extras(c, plan, nvox, hist_per_step, launch, variance):
     log(f"paper field: {n2 / t2:.4g} histories/s, {u2:.4%} at 1e7")
     del d2, v2
 
+    # the thorax with secondary trajectories in its database (protons from
+    # non-elastic nuclear interactions, about 1%/cm above 20 MeV), the
+    # headline's launch configuration
+    t = time.perf_counter()
+    db_s = W.multi_bin_db(secondaries=True)
+    log(f"database with secondaries: {db_s.sec.n} secondaries, {db_s.sec.steps.shape[0]} steps "
+        f"({time.perf_counter() - t:.1f} s)")
+    c3 = F.Context(0, 1, table=I.HU_TABLE_DEFAULT)
+    c3.load_track_db(db_s)
+    c3.set_launch_config(**launch)
+    p3 = c3.load_phantom(ph_thorax)
+    c3.add_beam_spots(p3, sp_thorax)
+    flags3 = F.FDC_RUN_VARIANCE if variance else 0
+
+    def sec_run():
+        c3.reset_plan(p3)
+        c3.run_histories([p3], flags3)
+    t3 = best_of(sec_run)
+    k3 = timed_kernel_ms(c3, sec_run)
+    r3 = c3.read_dose_and_variance(p3, raw=True)
+    c3.close()
+    out["thorax_1e8_secondaries"] = {
+        "seconds": t3, "histories_per_s": hist_per_step / t3, "kernel_ms": k3, "launch": launch,
+        "secondaries": db_s.sec.n, "secondary_steps": int(db_s.sec.steps.shape[0]),
+        "escaped_fraction": r3["escaped"] / max(r3["incident"], 1),
+        "workload": "the headline thorax workload with a database of 33 bins x 1e4 tracks carrying "
+                    "secondary proton trajectories (nuclear interactions 1.2%/cm above 20 MeV)"}
+    log(f"thorax with secondaries: {hist_per_step / t3:.4g} histories/s, kernel {k3:.3f} ms")
+    del db_s
+
     from paper_1011_2188_amd import experiments as X
     den = X.denoiser_rate(3)
     out["denoiser"] = {"forward_ms_256x256x128": den["forward_ms"], "forward_tflops": den["forward_tflops"],
@@ -243,8 +273,10 @@ def denoised_route(c, ph, sp, plain_plan, plain_dose, n2, rate):
     (2%/2 mm) of the plain dose at N_2% (the verification run) against an
     independent reference of 4e8 histories; the trained denoiser (parameters
     from the full-scale training study, if present) on doses of N_2% * {1/64,
-    ..., 1} histories; seconds = the first rung reaching G*, at this run's
-    histories/s, plus the measured inference time.  Untimed for `value`."""
+    ..., 1, 2, 4} histories; seconds = the first rung reaching G*, at this
+    run's histories/s, plus the measured inference time (null when no rung
+    reaches it; the ladder, the denoised pass rate at N_2% and the best one are
+    reported either way).  Untimed for `value`."""
     from paper_1011_2188_amd import denoise as D
     if not os.path.exists(WEIGHTS):
         return {"seconds_to_2pct_denoised": None,
@@ -252,7 +284,11 @@ def denoised_route(c, ph, sp, plain_plan, plain_dose, n2, rate):
     params, meta = D.load_params(WEIGHTS)
     t = time.perf_counter()
     r = D.gamma_ladder(c, ph, sp, params, n2, rate, ref_total=400_000_000, plain=(plain_plan, plain_dose),
-                       log=log)
+                       log=log, above=2)
+    at_n2 = next(row for row in r["ladder"] if row["histories"] == max(1, int(round(n2))))
+    r["gamma_denoised_at_N_2pct"] = at_n2["gamma_denoised"]
+    r["best_gamma_denoised"] = max(row["gamma_denoised"] for row in r["ladder"])
+    r["reached_G_star"] = r["N_denoised"] is not None
     log(f"denoised route: G* {r['G_star']:.5f}, N_d {r['N_denoised']}, t_den {r['t_denoised_s']} "
         f"({time.perf_counter() - t:.1f} s)")
     r["weights"] = {k: meta[k] for k in ("train_plans", "input_histories", "target_histories", "steps")
@@ -448,7 +484,7 @@ def main():
         **out,
     }
     if not args.no_extras:
-        result["extras"] = extras(c, plan, nvox, hist_per_step, launch, variance)
+        result["extras"] = extras(c, plan, nvox, hist_per_step, launch, variance, ph, sp)
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample ...")
         result["cpu_baseline"] = cpu_baseline(ph, sp, db)

@@ -224,12 +224,43 @@ int fdc_load_track_db(fdc_ctx *ctx, const fdc_step *steps, uint64_t n_steps,
                       const uint64_t *track_off, uint32_t n_tracks, const float *bin_E_MeV,
                       const uint32_t *bin_first, uint32_t n_bins, void *hip_stream);
 
+/* Secondary trajectories of the loaded track database (Section 2.2: a stored
+ * history is the set of its particles' trajectories, each broken into steps).
+ * Secondary j of track t (sec_first[t] <= j < sec_first[t+1], at most 4 per
+ * track) starts at the end of the track's primary step branch[j] (counted from
+ * the track's first step, in order within a track), leaves at polar angle
+ * emit[2j] in [0, pi] and azimuth emit[2j+1] (radians) from the primary's
+ * direction there, and replays steps[sec_off[j] .. sec_off[j+1]) like a
+ * primary's steps (whole, deflected at their ends, no secondaries of their
+ * own).  A history replays its primary, then its secondaries from the points
+ * the primary reached; their energy is part of the track's (incident energy),
+ * after their branch step's in the track's order: a spot's energy skip that
+ * ends inside a secondary's energy drops it and starts the primary at the next
+ * step whole.  A secondary whose branch step ends inside a beam-line device is
+ * absorbed there.  End-point replays (fdc_debug_endpoints) follow the primary.
+ * sec_first has n_tracks + 1 entries (the database's), sec_off n_sec + 1; the
+ * arrays are host memory, copied before the call returns.  Replaces previously
+ * loaded secondaries; loading a track database removes them.
+ * Errors: FDC_E_STATE (no track database), FDC_E_ARG (NULL arrays),
+ * FDC_E_FORMAT (offsets not monotone or not ending at the counts, an empty
+ * secondary, more than 4 on a track, a branch past its track's last step or
+ * out of order, an angle out of range, and the step checks of
+ * fdc_load_track_db), FDC_E_NOMEM, FDC_E_HIP. */
+int fdc_load_secondaries(fdc_ctx *ctx, const uint32_t *sec_first, const uint64_t *sec_off, uint32_t n_sec,
+                         const fdc_step *steps, uint64_t n_sec_steps, const uint32_t *branch,
+                         const float *emit, void *hip_stream);
+
 /* The same load from a track-database file (Section 2.2: the stored water
  * histories).  Layout, all little-endian: a 104-byte header {char magic[8] =
- * "FDCTRKDB"; uint32 version = 1; uint32 n_bins, n_tracks, reserved; uint64
+ * "FDCTRKDB"; uint32 version = 1 or 2; uint32 n_bins, n_tracks, reserved; uint64
  * n_steps; uint64 db_seed; double physics[8] (the generator's constants, not
  * read)}, then bin_E (float x n_bins), bin_first (uint32 x n_bins+1),
  * track_off (uint64 x n_tracks+1) and the steps (fdc_step x n_steps), packed.
+ * Version 2 adds secondary trajectories (fdc_load_secondaries): the header's
+ * reserved word is n_sec, and after the primary steps come n_sec_steps
+ * (uint64), sec_first (uint32 x n_tracks+1), sec_off (uint64 x n_sec+1),
+ * branch (uint32 x n_sec), emit (float x 2 n_sec) and the secondaries' steps
+ * (fdc_step x n_sec_steps), packed.
  * The file is read on the host and closed before the call returns.  Errors:
  * FDC_E_ARG (NULL path, file cannot be opened), FDC_E_FORMAT (bad magic or
  * version, a size that does not match the header, a short read, and every

@@ -194,6 +194,15 @@ typedef struct {
     const double *dev_par;
     const float *dev_pix;
     const uint64_t *dev_pix_off;
+    /* secondary trajectories of the database (NULL sec_first: none): track t
+     * has secondaries sec_first[t] .. sec_first[t+1]-1; secondary j starts at
+     * the end of the track's primary step sec_branch[j] (counted from its first
+     * step), leaves at polar angle sec_emit[2j] and azimuth sec_emit[2j+1]
+     * from the primary's direction there, and has steps sec_steps[4 sec_off[j]
+     * ..] up to sec_off[j+1] (4 floats each, as the primary's). */
+    const uint32_t *sec_first, *sec_branch;
+    const uint64_t *sec_off;
+    const float *sec_steps, *sec_emit;
     /* run */
     uint32_t plan;
     uint64_t seed;
@@ -408,8 +417,146 @@ static int device_pass(const oracle_problem *P, int dv, const float *st, uint64_
     return 1; /* the track ended in the compensator */
 }
 
-/* One history (plan, spot s, index h).  Returns the end reason; the end point
- * is written to endpoint[3].  Tallies go to T (may be NULL for endpoints only). */
+/* Branch points of a track's secondary trajectories met by the primary's
+ * walk (position, voxel, beam-frame direction at the end of the branch step). */
+#define MAX_BRANCH 16
+typedef struct {
+    const uint32_t *branch;   /* branch step of each secondary of the track */
+    uint32_t j, end;          /* next secondary to meet, one past the track's last */
+    int n;
+    uint32_t sec[MAX_BRANCH];
+    double pos[MAX_BRANCH][3], db[MAX_BRANCH][3];
+    int iv[MAX_BRANCH][3];
+} branch_log;
+
+/* Re-trace a trajectory's steps from k (its state: position, voxel, direction
+ * d = M db, and for the first step replayed the part of it already done, tau0
+ * WEL, dep0 energy, g20 sum w G) to n_steps: each step's WEL consumed voxel by
+ * voxel at geometric length WEL / RSP, its energy split uniformly in WEL with
+ * a telescoping round to nearest, the deflection at the step end scaled by
+ * sqrt(sum w G / WEL) (Section 2.2); deposits flushed per voxel visit.
+ * Steps k0 and beyond follow step_params (k0 the primary's partial first step;
+ * a secondary passes k0 = UINT64_MAX).  With a branch log, the secondaries
+ * starting at the end of a step are recorded there.  Adds the deposited
+ * energy to *dep; returns END_STOP or END_ESCAPE (the remaining energy,
+ * e_left minus what was deposited, goes to the trace's escape event). */
+static int walk_trajectory(const oracle_problem *P, oracle_tally *T, const float *st, uint64_t k, uint64_t n_steps,
+                           uint64_t k0, int64_t cum, int64_t skip, double phi0, double pos[3], int iv[3],
+                           double d[3], double db[3], double M[3][3], double tau0, double g20, int64_t dep0,
+                           branch_log *br, int64_t e_left, int64_t *hist_dep_out)
+{
+    int64_t acc = 0, hist_dep = 0;
+    int reason = END_STOP;
+    int alive = 1;
+    const uint64_t k_begin = k;
+    for (; k < n_steps && alive; ++k) {
+        double w_tot, theta, phi;
+        int64_t e;
+        step_params(st, k, k0, cum, skip, phi0, &w_tot, &e, &theta, &phi);
+        if (T) T->steps++;
+        /* a step begun upstream (in a compensator) continues where it left off */
+        double tau = k == k_begin ? tau0 : 0.0, g2 = k == k_begin ? g20 : 0.0;
+        int64_t dep = k == k_begin ? dep0 : 0;
+        while (tau < w_tot) {
+            size_t v = ((size_t)iv[2] * P->n[1] + iv[1]) * P->n[0] + iv[0];
+            double rsp, g;
+            int vac = material(&P->tab, P->hu[v], &rsp, &g);
+            /* distance to the voxel exit, ties resolved x -> y -> z */
+            double lexit = INFINITY;
+            int ax = -1;
+            for (int a = 0; a < 3; ++a) {
+                double ta;
+                if (d[a] > 0.0) ta = (P->org[a] + (iv[a] + 1) * P->vox[a] - pos[a]) / d[a];
+                else if (d[a] < 0.0) ta = (P->org[a] + iv[a] * P->vox[a] - pos[a]) / d[a];
+                else continue;
+                if (ta < 0.0) ta = 0.0;
+                if (ta < lexit) { lexit = ta; ax = a; }
+            }
+            int cross = 1;
+            double move = lexit;
+            double w_trace = 0.0;
+            int64_t piece_trace = 0;
+            if (vac) {
+                if (T) T->vacuum_visits++;
+            } else {
+                if (T) T->visits++;
+                double rem = w_tot - tau;
+                double wb = lexit * rsp;
+                double w_v, tau_n;
+                if (rem <= wb) { /* the step ends in this voxel (or on its exit face) */
+                    w_v = rem;
+                    tau_n = w_tot;
+                    move = rem / rsp;
+                    cross = (rem == wb);
+                } else {
+                    w_v = wb;
+                    tau_n = tau + wb;
+                }
+                int64_t cumk = (int64_t)nearbyint((double)e * (tau_n / w_tot));
+                if (tau_n >= w_tot) cumk = e;
+                int64_t piece = cumk - dep;
+                dep = cumk;
+                acc += piece;
+                hist_dep += piece;
+                g2 += w_v * g;
+                tau = tau_n;
+                w_trace = w_v;
+                piece_trace = piece;
+            }
+            trace_push(P->trace, vac ? EV_VACUUM : EV_VOXEL, (int64_t)v, piece_trace, cross ? ax : -1, w_trace,
+                       move);
+            if (cross) {
+                for (int a = 0; a < 3; ++a) pos[a] += move * d[a];
+                pos[ax] = P->org[ax] + (iv[ax] + (d[ax] > 0.0 ? 1 : 0)) * P->vox[ax];
+                if (T) flush(P, T, v, &acc);
+                iv[ax] += d[ax] > 0.0 ? 1 : -1;
+                if (iv[ax] < 0 || iv[ax] >= P->n[ax]) {
+                    trace_push(P->trace, EV_ESCAPE, -1, e_left - hist_dep, ax, 0.0, 0.0);
+                    reason = END_ESCAPE;
+                    alive = 0;
+                    break;
+                }
+            } else {
+                for (int a = 0; a < 3; ++a) pos[a] += move * d[a];
+            }
+        }
+        if (!alive) break;
+        /* deflection at the end of the step, scaled by the traversed material */
+        double th = theta * sqrt(g2 / w_tot);
+        trace_push(P->trace, EV_STEP_END, (int64_t)k, 0, -1, g2, th);
+        rotate(db, th, phi);
+        for (int a = 0; a < 3; ++a) d[a] = M[a][0] * db[0] + M[a][1] * db[1] + M[a][2] * db[2];
+        /* secondary trajectories that start here */
+        while (br && br->j < br->end && br->branch[br->j] == k) {
+            if (br->n < MAX_BRANCH) {
+                br->sec[br->n] = br->j;
+                memcpy(br->pos[br->n], pos, sizeof(double) * 3);
+                memcpy(br->db[br->n], db, sizeof(double) * 3);
+                memcpy(br->iv[br->n], iv, sizeof(int) * 3);
+                br->n++;
+            }
+            br->j++;
+        }
+    }
+    if (alive && T) {
+        size_t v = ((size_t)iv[2] * P->n[1] + iv[1]) * P->n[0] + iv[0];
+        flush(P, T, v, &acc);
+    }
+    *hist_dep_out += hist_dep;
+    return reason;
+}
+
+/* total energy of a secondary trajectory, fixed point */
+static int64_t sec_energy(const oracle_problem *P, uint32_t j)
+{
+    int64_t e = 0;
+    for (uint64_t k = P->sec_off[j]; k < P->sec_off[j + 1]; ++k) e += fp_energy(P->sec_steps[4 * k + 1]);
+    return e;
+}
+
+/* One history (plan, spot s, index h).  Returns the end reason of its primary
+ * trajectory; the end point is written to endpoint[3].  Tallies go to T (may
+ * be NULL for endpoints only). */
 static int replay_history(const oracle_problem *P, uint32_t s, uint64_t h, oracle_tally *T,
                           double endpoint[3])
 {
@@ -421,6 +568,10 @@ static int replay_history(const oracle_problem *P, uint32_t s, uint64_t h, oracl
     double E_spot = listed ? P->ps_E[pi] : P->spot_E[s];
     uint32_t b = 0;
     while (b < P->n_bins && (double)P->bin_E[b] < E_spot) ++b;
+    if (b >= P->n_bins) { /* above the database's top bin: not a valid source */
+        for (int a = 0; a < 3; ++a) endpoint[a] = 0.0;
+        return -1;
+    }
     uint32_t n_b = P->bin_first[b + 1] - P->bin_first[b];
 
     uint64_t c = h / P->R; /* chunk of R histories sharing one track */
@@ -431,19 +582,38 @@ static int replay_history(const oracle_problem *P, uint32_t s, uint64_t h, oracl
 
     const float *st = P->steps + 4 * P->track_off[t];
     uint64_t n_steps = P->track_off[t + 1] - P->track_off[t];
+    /* the track's secondary trajectories (Section 2.2), each starting at the
+     * end of a primary step; their energy is part of the track's */
+    const uint32_t j_begin = P->sec_first ? P->sec_first[t] : 0, j_end = P->sec_first ? P->sec_first[t + 1] : 0;
 
-    /* energy skip of a spot below its bin energy, and the start step */
+    /* energy skip of a spot below its bin energy, and the start step
+     * (Section 2.3, task 1): the energy below the bin's goes in the order the
+     * track spends it - each primary step's loss, then the secondaries that
+     * start at its end.  A skip that ends inside a secondary's energy drops
+     * that secondary and starts at the next primary step whole (the incident
+     * energy is then the track's after it). */
     int64_t skip = fp_energy(P->bin_E[b]) - fp_energy(E_spot);
     int64_t T_fp = 0;
     for (uint64_t k = 0; k < n_steps; ++k) T_fp += fp_energy(st[4 * k + 1]);
+    for (uint32_t j = j_begin; j < j_end; ++j) T_fp += sec_energy(P, j);
     uint64_t k0 = 0;
     int64_t cum = 0;
-    while (k0 < n_steps && cum + fp_energy(st[4 * k0 + 1]) <= skip) {
-        cum += fp_energy(st[4 * k0 + 1]);
+    uint32_t j_first = j_begin;
+    while (k0 < n_steps) {
+        int64_t e = fp_energy(st[4 * k0 + 1]);
+        if (cum + e > skip) break;
+        cum += e;
+        while (j_first < j_end && P->sec_branch[j_first] == k0) cum += sec_energy(P, j_first++);
         ++k0;
+        if (cum > skip) {
+            skip = cum;
+            break;
+        }
     }
     int64_t I_h = T_fp - skip;
     if (I_h < 0) I_h = 0;
+    int64_t E_sec = 0; /* energy of the secondaries still ahead */
+    for (uint32_t j = j_first; j < j_end; ++j) E_sec += sec_energy(P, j);
 
     /* source: lateral position (Gaussian of standard deviation sigma, or for
      * sigma < 0 uniform over a disk of radius -sigma: the circular field of
@@ -521,97 +691,36 @@ static int replay_history(const oracle_problem *P, uint32_t s, uint64_t h, oracl
         iv[a] = i;
     }
 
-    /* ---- task 2: re-trace the steps ------------------------------------ */
-    double *db = S.db;   /* beam-frame direction */
-    int64_t acc = 0, hist_dep = 0;
-    int reason = END_STOP;
-    int alive = 1;
-    for (uint64_t k = S.k; k < n_steps && alive; ++k) {
-        double w_tot, theta, phi;
-        int64_t e;
-        step_params(st, k, k0, cum, skip, phi0, &w_tot, &e, &theta, &phi);
-        if (T) T->steps++;
-        /* a step begun upstream (in a compensator) continues where it left off */
-        double tau = k == S.k ? S.tau : 0.0, g2 = k == S.k ? S.g2 : 0.0;
-        int64_t dep = k == S.k ? S.dep : 0;
-        while (tau < w_tot) {
-            size_t v = ((size_t)iv[2] * P->n[1] + iv[1]) * P->n[0] + iv[0];
-            double rsp, g;
-            int vac = material(&P->tab, P->hu[v], &rsp, &g);
-            /* distance to the voxel exit, ties resolved x -> y -> z */
-            double lexit = INFINITY;
-            int ax = -1;
-            for (int a = 0; a < 3; ++a) {
-                double ta;
-                if (d[a] > 0.0) ta = (P->org[a] + (iv[a] + 1) * P->vox[a] - pos[a]) / d[a];
-                else if (d[a] < 0.0) ta = (P->org[a] + iv[a] * P->vox[a] - pos[a]) / d[a];
-                else continue;
-                if (ta < 0.0) ta = 0.0;
-                if (ta < lexit) { lexit = ta; ax = a; }
-            }
-            int cross = 1;
-            double move = lexit;
-            double w_trace = 0.0;
-            int64_t piece_trace = 0;
-            if (vac) {
-                if (T) T->vacuum_visits++;
-            } else {
-                if (T) T->visits++;
-                double rem = w_tot - tau;
-                double wb = lexit * rsp;
-                double w_v, tau_n;
-                if (rem <= wb) { /* the step ends in this voxel (or on its exit face) */
-                    w_v = rem;
-                    tau_n = w_tot;
-                    move = rem / rsp;
-                    cross = (rem == wb);
-                } else {
-                    w_v = wb;
-                    tau_n = tau + wb;
-                }
-                int64_t cumk = (int64_t)nearbyint((double)e * (tau_n / w_tot));
-                if (tau_n >= w_tot) cumk = e;
-                int64_t piece = cumk - dep;
-                dep = cumk;
-                acc += piece;
-                hist_dep += piece;
-                g2 += w_v * g;
-                tau = tau_n;
-                w_trace = w_v;
-                piece_trace = piece;
-            }
-            trace_push(P->trace, vac ? EV_VACUUM : EV_VOXEL, (int64_t)v, piece_trace, cross ? ax : -1, w_trace,
-                       move);
-            if (cross) {
-                for (int a = 0; a < 3; ++a) pos[a] += move * d[a];
-                pos[ax] = P->org[ax] + (iv[ax] + (d[ax] > 0.0 ? 1 : 0)) * P->vox[ax];
-                if (T) flush(P, T, v, &acc);
-                iv[ax] += d[ax] > 0.0 ? 1 : -1;
-                if (iv[ax] < 0 || iv[ax] >= P->n[ax]) {
-                    trace_push(P->trace, EV_ESCAPE, -1, I_h - hist_dep, ax, 0.0, 0.0);
-                    if (T) T->escaped += I_h - hist_dep;
-                    reason = END_ESCAPE;
-                    alive = 0;
-                    break;
-                }
-            } else {
-                for (int a = 0; a < 3; ++a) pos[a] += move * d[a];
-            }
-        }
-        if (!alive) break;
-        /* deflection at the end of the step, scaled by the traversed material */
-        double th = theta * sqrt(g2 / w_tot);
-        trace_push(P->trace, EV_STEP_END, (int64_t)k, 0, -1, g2, th);
-        rotate(db, th, phi);
-        for (int a = 0; a < 3; ++a) d[a] = M[a][0] * db[0] + M[a][1] * db[1] + M[a][2] * db[2];
-    }
-    if (alive && T) {
-        size_t v = ((size_t)iv[2] * P->n[1] + iv[1]) * P->n[0] + iv[0];
-        flush(P, T, v, &acc);
-        T->escaped += S.up_dep; /* absorbed upstream: not deposited in the phantom */
-    }
+    /* ---- task 2: re-trace the primary, then its secondaries --------------- */
+    branch_log br = {P->sec_branch, j_first, j_end, 0, {0}, {{0}}, {{0}}, {{0}}};
+    /* secondaries that start at the end of a step completed in a beam-line
+     * device stay there (their energy counts as absorbed upstream) */
+    while (br.j < br.end && P->sec_branch[br.j] < S.k) br.j++;
+    int64_t dep_prim = 0, dep_all = 0;
+    int reason = walk_trajectory(P, T, st, S.k, n_steps, k0, cum, skip, phi0, pos, iv, d, S.db, M, S.tau, S.g2, S.dep,
+                                 j_first < j_end ? &br : NULL, I_h - E_sec, &dep_prim);
     memcpy(endpoint, pos, sizeof(double) * 3);
-    if (alive && hist_dep + S.up_dep != I_h) return -1; /* energy not conserved: oracle bug */
+    dep_all = dep_prim;
+    int bad = reason == END_STOP && dep_prim + S.up_dep != I_h - E_sec;
+    if (br.n >= MAX_BRANCH) bad = 1;
+    for (int q = 0; q < br.n; ++q) {
+        /* a secondary leaves its branch point at (theta, phi) from the primary's direction */
+        uint32_t j = br.sec[q];
+        double sdb[3] = {br.db[q][0], br.db[q][1], br.db[q][2]};
+        rotate(sdb, P->sec_emit[2 * j], P->sec_emit[2 * j + 1]);
+        double sd[3], sp[3] = {br.pos[q][0], br.pos[q][1], br.pos[q][2]};
+        for (int a = 0; a < 3; ++a) sd[a] = M[a][0] * sdb[0] + M[a][1] * sdb[1] + M[a][2] * sdb[2];
+        int siv[3] = {br.iv[q][0], br.iv[q][1], br.iv[q][2]};
+        const float *sst = P->sec_steps + 4 * P->sec_off[j];
+        uint64_t sn = P->sec_off[j + 1] - P->sec_off[j];
+        int64_t dep_s = 0;
+        int sr = walk_trajectory(P, T, sst, 0, sn, UINT64_MAX, 0, 0, 0.0, sp, siv, sd, sdb, M, 0.0, 0.0, 0, NULL,
+                                 sec_energy(P, j), &dep_s);
+        if (sr == END_STOP && dep_s != sec_energy(P, j)) bad = 1;
+        dep_all += dep_s;
+    }
+    if (T) T->escaped += I_h - dep_all; /* carried out of the box, absorbed upstream, or never started */
+    if (bad) return -1; /* energy not conserved: oracle bug */
     return reason;
 }
 
@@ -644,6 +753,9 @@ static void setup(oracle_problem *P, const float *steps, const uint64_t *track_o
     P->dev_par = NULL;
     P->dev_pix = NULL;
     P->dev_pix_off = NULL;
+    P->sec_first = P->sec_branch = NULL;
+    P->sec_off = NULL;
+    P->sec_steps = P->sec_emit = NULL;
 }
 
 /* Phase-space sources for the next oracle_replay_e2x / oracle_endpoints /
@@ -675,6 +787,20 @@ void oracle_set_devices(const int32_t *spot_dev, const double *par, const float 
     g_dev.spot_dev = spot_dev; g_dev.par = par; g_dev.pix = pix; g_dev.pix_off = pix_off;
 }
 
+/* The database's secondary trajectories for the next calls on this thread
+ * (see oracle_problem); NULL first clears them. */
+static _Thread_local struct {
+    const uint32_t *first, *branch;
+    const uint64_t *off;
+    const float *steps, *emit;
+} g_sec;
+
+void oracle_set_secondaries(const uint32_t *first, const uint64_t *off, const float *steps, const uint32_t *branch,
+                            const float *emit)
+{
+    g_sec.first = first; g_sec.off = off; g_sec.steps = steps; g_sec.branch = branch; g_sec.emit = emit;
+}
+
 static void use_phase_space(oracle_problem *P)
 {
     if (g_ps.count) {
@@ -683,6 +809,10 @@ static void use_phase_space(oracle_problem *P)
     }
     if (g_dev.spot_dev) {
         P->spot_dev = g_dev.spot_dev; P->dev_par = g_dev.par; P->dev_pix = g_dev.pix; P->dev_pix_off = g_dev.pix_off;
+    }
+    if (g_sec.first) {
+        P->sec_first = g_sec.first; P->sec_branch = g_sec.branch; P->sec_off = g_sec.off;
+        P->sec_steps = g_sec.steps; P->sec_emit = g_sec.emit;
     }
 }
 

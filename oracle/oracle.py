@@ -239,6 +239,30 @@ class _Devices:
             lib().oracle_set_devices(None, None, None, None)
 
 
+class _Secondaries:
+    """Installs a database's secondary trajectories (db.sec) for the oracle
+    calls inside the block; a database without them installs nothing."""
+
+    def __init__(self, db):
+        self.sec = getattr(db, "sec", None)
+
+    def __enter__(self):
+        if self.sec is not None:
+            s = self.sec
+            self.keep = [np.ascontiguousarray(s.sec_first, np.uint32), np.ascontiguousarray(s.off, np.uint64),
+                         np.ascontiguousarray(s.steps, np.float32).reshape(-1),
+                         np.ascontiguousarray(s.branch, np.uint32), np.ascontiguousarray(s.emit, np.float32)]
+            if self.keep[2].size == 0:
+                self.keep[2] = np.zeros(4, np.float32)
+            f, o, st, b, e = self.keep
+            lib().oracle_set_secondaries(_p(f, C.c_uint32), _p(o, C.c_uint64), _p(st, C.c_float),
+                                         _p(b, C.c_uint32), _p(e, C.c_float))
+
+    def __exit__(self, *a):
+        if self.sec is not None:
+            lib().oracle_set_secondaries(None, None, None, None, None)
+
+
 def replay(db, ph, sp, h_begin=None, h_count=None, plan=0, seed=1, R=64, flags=FLAG_VARIANCE,
            threads=None, table=None, exact_e2=False, phase_space=None, devices=None):
     """Replay histories h_begin[i] .. h_begin[i]+h_count[i]-1 of every spot i.
@@ -252,7 +276,8 @@ def replay(db, ph, sp, h_begin=None, h_count=None, plan=0, seed=1, R=64, flags=F
     then hold one (placeholder) row per source and h_count give each source's
     histories.  devices: (device dicts from inputs.beam_device, per spot the
     index of the device it passes or -1): an aperture and range compensator
-    upstream of the phantom, whose absorbed energy counts as escaped."""
+    upstream of the phantom, whose absorbed energy counts as escaped.  A
+    database with secondary trajectories (db.sec) replays them too."""
     arrs, args = _common(db, ph, sp, table)
     ns = len(sp)
     hb = np.zeros(ns, np.uint64) if h_begin is None else np.ascontiguousarray(h_begin, np.uint64)
@@ -264,13 +289,13 @@ def replay(db, ph, sp, h_begin=None, h_count=None, plan=0, seed=1, R=64, flags=F
     stats = np.zeros(6, np.int64)
     E2x = np.zeros(nx * ny * nz, np.uint64) if exact_e2 else None
     nthreads = threads or int(os.environ.get("ORACLE_THREADS", min(os.cpu_count() or 1, 16)))
-    with _PhaseSpace(phase_space), _Devices(devices, ns):
+    with _PhaseSpace(phase_space), _Devices(devices, ns), _Secondaries(db):
         rc = lib().oracle_replay_e2x(*args, C.c_uint32(ns), _p(hb, C.c_uint64), _p(hc, C.c_uint64),
                                      C.c_uint32(plan), C.c_uint64(seed), C.c_uint32(R), C.c_uint32(flags),
                                      C.c_int(nthreads), _p(E, C.c_int64), _p(E2, C.c_uint64),
                                      _p(stats, C.c_int64), _p(E2x, C.c_uint64) if exact_e2 else None)
     if rc != 0:
-        raise RuntimeError("oracle replay failed to conserve energy")
+        raise RuntimeError("oracle replay failed: energy not conserved, or a source above the top energy bin")
     extra = dict(E2x=E2x.reshape(nz, ny, nx)) if exact_e2 else {}
     return dict(**extra, E=E.reshape(nz, ny, nx), E2=E2.reshape(nz, ny, nx), incident=int(stats[0]),
                 escaped=int(stats[1]), steps=int(stats[2]), visits=int(stats[3]),
@@ -286,12 +311,12 @@ def endpoints(db, ph, sp, spot, h0, n, plan=0, seed=1, R=64, flags=0, table=None
     arrs, args = _common(db, ph, sp, table)
     xyz = np.zeros((n, 3), np.float64)
     reason = np.zeros(n, np.int32)
-    with _PhaseSpace(phase_space), _Devices(devices, len(sp)):
+    with _PhaseSpace(phase_space), _Devices(devices, len(sp)), _Secondaries(db):
         lib().oracle_endpoints(*args, C.c_uint32(spot), C.c_uint64(h0), C.c_uint32(n), C.c_uint32(plan),
                                C.c_uint64(seed), C.c_uint32(R), C.c_uint32(flags),
                                _p(xyz, C.c_double), _p(reason, C.c_int32))
     if np.any(reason < 0):
-        raise RuntimeError("oracle replay failed to conserve energy")
+        raise RuntimeError("oracle replay failed: energy not conserved, or a source above the top energy bin")
     return xyz, reason
 
 
@@ -306,9 +331,10 @@ def trace(db, ph, sp, spot, h, plan=0, seed=1, R=64, flags=0, table=None, cap=10
     evd = np.zeros((cap, 2), np.float64)
     reason = C.c_int32()
     ep = np.zeros(3, np.float64)
-    n = lib().oracle_trace_history(*args, C.c_uint32(spot), C.c_uint64(h), C.c_uint32(plan), C.c_uint64(seed),
-                                   C.c_uint32(R), C.c_uint32(flags), _p(ev, C.c_int64), _p(evd, C.c_double),
-                                   C.c_int(cap), C.byref(reason), _p(ep, C.c_double))
+    with _Secondaries(db):
+        n = lib().oracle_trace_history(*args, C.c_uint32(spot), C.c_uint64(h), C.c_uint32(plan), C.c_uint64(seed),
+                                       C.c_uint32(R), C.c_uint32(flags), _p(ev, C.c_int64), _p(evd, C.c_double),
+                                       C.c_int(cap), C.byref(reason), _p(ep, C.c_double))
     if n > cap:
         raise RuntimeError("trace longer than its buffer")
     out = [(int(a), int(b), int(c), int(d), float(w), float(m)) for (a, b, c, d), (w, m) in zip(ev[:n], evd[:n])]

@@ -83,6 +83,14 @@ struct fdc_ctx {
     std::vector<uint32_t> bin_first_h;
     uint32_t n_tracks = 0, n_bins = 0;
     uint64_t db_serial = 0;           // counts database loads
+    std::vector<uint64_t> track_off_h;
+    uint64_t n_steps_prim = 0;        // primary steps (the secondaries' follow them in `steps`)
+    // secondary trajectories (fdc_load_secondaries): per track its first, the
+    // table with its end marker, and what they add to each track's energy
+    uint32_t *sec_first = nullptr;
+    DevSec *secs = nullptr;
+    uint32_t n_sec = 0;
+    std::vector<long long> sec_T_track;
 
     // material table
     std::vector<double> table;   // rows of (hu, rho, rsp, rscp)
@@ -437,6 +445,8 @@ TransportArgs base_args(const fdc_ctx *ctx)
     a.seed_hi = (uint32_t)(ctx->seed >> 32);
     a.R = ctx->R;
     a.devices = ctx->d_devices;
+    a.sec_first = ctx->n_sec ? ctx->sec_first : nullptr;
+    a.secs = ctx->n_sec ? ctx->secs : nullptr;
     return a;
 }
 
@@ -572,6 +582,7 @@ int fdc_destroy(fdc_ctx *ctx)
     }
     dfree(ctx, ctx->steps); dfree(ctx, ctx->track_off); dfree(ctx, ctx->track_T);
     dfree(ctx, ctx->bin_first);
+    dfree(ctx, ctx->sec_first); dfree(ctx, ctx->secs);
     dfree(ctx, ctx->lut); dfree(ctx, ctx->rho_lut);
     dfree(ctx, ctx->d_plans); dfree(ctx, ctx->d_spots); dfree(ctx, ctx->d_items); dfree(ctx, ctx->d_queue);
     for (DevDevice &d : ctx->devices) dfree(ctx, (void *)d.pix);
@@ -689,6 +700,10 @@ int fdc_load_track_db(fdc_ctx *ctx, const fdc_step *steps, uint64_t n_steps, con
     if (ctx->dry) {
         ctx->bin_E.assign(bin_E, bin_E + n_bins);
         ctx->bin_first_h.assign(bin_first, bin_first + n_bins + 1);
+        ctx->track_off_h.assign(track_off, track_off + (size_t)n_tracks + 1);
+        ctx->n_steps_prim = n_steps;
+        ctx->n_sec = 0;
+        ctx->sec_T_track.clear();
         ctx->n_tracks = n_tracks;
         ctx->n_bins = n_bins;
         ctx->db_serial++;
@@ -721,16 +736,127 @@ int fdc_load_track_db(fdc_ctx *ctx, const fdc_step *steps, uint64_t n_steps, con
     HIPCHK(hipDeviceSynchronize());
     dfree(ctx, ctx->steps); dfree(ctx, ctx->track_off); dfree(ctx, ctx->track_T);
     dfree(ctx, ctx->bin_first);
+    dfree(ctx, ctx->sec_first); dfree(ctx, ctx->secs);
+    ctx->sec_first = nullptr;
+    ctx->secs = nullptr;
+    ctx->n_sec = 0;
+    ctx->sec_T_track.clear();
     ctx->steps = d_steps;
     ctx->track_off = d_off;
     ctx->track_T = d_T;
     ctx->bin_first = d_bf;
     ctx->bin_E.assign(bin_E, bin_E + n_bins);
     ctx->bin_first_h.assign(bin_first, bin_first + n_bins + 1);
+    ctx->track_off_h.assign(track_off, track_off + (size_t)n_tracks + 1);
+    ctx->n_steps_prim = n_steps;
     ctx->n_tracks = n_tracks;
     ctx->n_bins = n_bins;
     ctx->db_serial++;
     ctx->spots_dirty = true;
+    ctx->gen++;
+    return FDC_OK;
+}
+
+int fdc_load_secondaries(fdc_ctx *ctx, const uint32_t *sec_first, const uint64_t *sec_off, uint32_t n_sec,
+                         const fdc_step *steps, uint64_t n_sec_steps, const uint32_t *branch, const float *emit,
+                         void *hip_stream)
+{
+    if (!ctx) return FDC_E_ARG;
+    if (ctx->n_bins == 0) return fail(ctx, FDC_E_STATE, "secondaries: load a track database first");
+    if (!sec_first || !sec_off) return fail(ctx, FDC_E_ARG, "secondaries: NULL array");
+    if (n_sec && (!steps || !branch || !emit)) return fail(ctx, FDC_E_ARG, "secondaries: NULL array");
+    const uint32_t nt = ctx->n_tracks;
+    if (sec_first[0] != 0 || sec_first[nt] != n_sec)
+        return fail(ctx, FDC_E_FORMAT, "secondaries: sec_first must start at 0 and end at n_sec");
+    if (sec_off[0] != 0 || sec_off[n_sec] != n_sec_steps)
+        return fail(ctx, FDC_E_FORMAT, "secondaries: offsets must start at 0 and end at n_sec_steps");
+    for (uint32_t t = 0; t < nt; ++t) {
+        if (sec_first[t + 1] < sec_first[t]) return fail(ctx, FDC_E_FORMAT, "secondaries: sec_first decreases at track %u", t);
+        if (sec_first[t + 1] - sec_first[t] > kMaxSecPerTrack)
+            return fail(ctx, FDC_E_FORMAT, "secondaries: track %u has %u (at most %u)", t, sec_first[t + 1] - sec_first[t],
+                        kMaxSecPerTrack);
+        const uint64_t ns = ctx->track_off_h[t + 1] - ctx->track_off_h[t];
+        for (uint32_t j = sec_first[t]; j < sec_first[t + 1]; ++j) {
+            if (branch[j] >= ns) return fail(ctx, FDC_E_FORMAT, "secondaries: %u branches past its track's last step", j);
+            if (j > sec_first[t] && branch[j] < branch[j - 1])
+                return fail(ctx, FDC_E_FORMAT, "secondaries: branch steps of track %u not in order", t);
+        }
+    }
+    for (uint32_t j = 0; j < n_sec; ++j) {
+        if (!(sec_off[j + 1] > sec_off[j])) return fail(ctx, FDC_E_FORMAT, "secondaries: %u empty or offsets not increasing", j);
+        const float th = emit[2 * j], ph = emit[2 * j + 1];
+        if (!std::isfinite(th) || !std::isfinite(ph) || th < 0.f || th > 3.14159274f)
+            return fail(ctx, FDC_E_FORMAT, "secondaries: %u needs a finite azimuth and a polar angle in [0, pi]", j);
+    }
+    for (uint64_t k = 0; k < n_sec_steps; ++k) {
+        const fdc_step &st = steps[k];
+        if (!std::isfinite(st.dx_cm) || !std::isfinite(st.dE_MeV) || !std::isfinite(st.theta_rad) ||
+            !std::isfinite(st.phi_rad) || !(st.dx_cm > 0.f) || st.dE_MeV < 0.f || st.theta_rad < 0.f ||
+            !(st.dE_MeV < 128.f))
+            return fail(ctx, FDC_E_FORMAT, "secondaries: step %llu needs finite values, dx > 0, 0 <= dE < 128 MeV, "
+                        "theta >= 0", (unsigned long long)k);
+    }
+    // the table: each secondary's steps behind the primary steps, its branch
+    // step in the same numbering, its energy, and the end marker
+    std::vector<DevSec> tab((size_t)n_sec + 1);
+    std::vector<long long> add(nt, 0);
+    for (uint32_t t = 0; t < nt; ++t) {
+        for (uint32_t j = sec_first[t]; j < sec_first[t + 1]; ++j) {
+            DevSec &d = tab[j];
+            d.k0 = ctx->n_steps_prim + sec_off[j];
+            d.k1 = ctx->n_steps_prim + sec_off[j + 1];
+            d.kb = ctx->track_off_h[t] + branch[j];
+            long long T = 0;
+            for (uint64_t k = sec_off[j]; k < sec_off[j + 1]; ++k) T += to_fp(steps[k].dE_MeV);
+            d.T = T;
+            const double th = emit[2 * j], ph = emit[2 * j + 1];
+            d.ct = (float)cos(th);
+            d.st = (float)sin(th);
+            d.cph = (float)cos(ph);
+            d.sph = (float)sin(ph);
+            add[t] += T;
+        }
+    }
+    tab[n_sec] = DevSec{~0ull, ~0ull, ~0ull, 0, 1.f, 0.f, 1.f, 0.f};
+    if (ctx->dry) {
+        ctx->n_sec = n_sec;
+        ctx->sec_T_track = add;
+        return FDC_OK;
+    }
+    HIPCHK(hipSetDevice(ctx->device));
+    const uint64_t np = ctx->n_steps_prim;
+    float4 *d_steps = dalloc_n<float4>(ctx, np + n_sec_steps);
+    uint32_t *d_first = dalloc_n<uint32_t>(ctx, (size_t)nt + 1);
+    DevSec *d_tab = dalloc_n<DevSec>(ctx, (size_t)n_sec + 1);
+    if (!d_steps || !d_first || !d_tab) {
+        dfree(ctx, d_steps); dfree(ctx, d_first); dfree(ctx, d_tab);
+        return fail(ctx, FDC_E_NOMEM, "secondaries: device allocation failed");
+    }
+    // the tracks' energies with the new secondaries in place of the old
+    std::vector<long long> T(nt);
+    hipStream_t s = S(hip_stream);
+    hipError_t e = hipMemcpyAsync(T.data(), ctx->track_T, (size_t)nt * 8, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    for (uint32_t t = 0; t < nt && e == hipSuccess; ++t)
+        T[t] += add[t] - (ctx->sec_T_track.empty() ? 0 : ctx->sec_T_track[t]);
+    if (e == hipSuccess) e = hipMemcpyAsync(d_steps, ctx->steps, np * sizeof(float4), hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess && n_sec_steps)
+        e = hipMemcpyAsync(d_steps + np, steps, n_sec_steps * sizeof(float4), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && n_sec_steps) e = launch_compact_steps(d_steps + np, n_sec_steps, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(d_first, sec_first, ((size_t)nt + 1) * 4, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(d_tab, tab.data(), tab.size() * sizeof(DevSec), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(ctx->track_T, T.data(), (size_t)nt * 8, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        dfree(ctx, d_steps); dfree(ctx, d_first); dfree(ctx, d_tab);
+        return fail(ctx, FDC_E_HIP, "secondaries upload: %s", hipGetErrorString(e));
+    }
+    dfree(ctx, ctx->steps); dfree(ctx, ctx->sec_first); dfree(ctx, ctx->secs);
+    ctx->steps = d_steps;
+    ctx->sec_first = d_first;
+    ctx->secs = d_tab;
+    ctx->n_sec = n_sec;
+    ctx->sec_T_track = add;
     ctx->gen++;
     return FDC_OK;
 }
@@ -741,8 +867,8 @@ int fdc_load_track_db(fdc_ctx *ctx, const fdc_step *steps, uint64_t n_steps, con
 namespace {
 struct DbFileHeader {
     char magic[8];                   // "FDCTRKDB"
-    uint32_t version;                // 1
-    uint32_t n_bins, n_tracks, reserved;
+    uint32_t version;                // 1, or 2 with secondary trajectories
+    uint32_t n_bins, n_tracks, n_sec;   // (n_sec: version 2 only)
     uint64_t n_steps;
     uint64_t db_seed;
     double physics[8];               // generator constants, informational
@@ -761,7 +887,7 @@ int fdc_load_track_db_file(fdc_ctx *ctx, const char *path, void *hip_stream)
     if (std::fseek(f, 0, SEEK_END) == 0) size = std::ftell(f);
     std::rewind(f);
     if (std::fread(&h, sizeof h, 1, f) != 1) { std::fclose(f); return fail(ctx, FDC_E_FORMAT, "track database file: short header"); }
-    if (std::memcmp(h.magic, "FDCTRKDB", 8) != 0 || h.version != 1) {
+    if (std::memcmp(h.magic, "FDCTRKDB", 8) != 0 || (h.version != 1 && h.version != 2)) {
         std::fclose(f);
         return fail(ctx, FDC_E_FORMAT, "track database file: bad magic or version %u", h.version);
     }
@@ -769,33 +895,69 @@ int fdc_load_track_db_file(fdc_ctx *ctx, const char *path, void *hip_stream)
         std::fclose(f);
         return fail(ctx, FDC_E_FORMAT, "track database file: empty or implausible counts");
     }
-    const unsigned long long want = sizeof h + 4ull * h.n_bins + 4ull * (h.n_bins + 1ull) +
+    const bool v2 = h.version == 2;
+    const uint64_t n_sec = v2 ? h.n_sec : 0;
+    const unsigned long long body = sizeof h + 4ull * h.n_bins + 4ull * (h.n_bins + 1ull) +
                                     8ull * (h.n_tracks + 1ull) + 16ull * h.n_steps;
+    uint64_t n_sec_steps = 0;
+    if (v2) {
+        // the secondaries' section: its step count, then sec_first, sec_off,
+        // branch, emit and the steps
+        if (std::fseek(f, (long)body, SEEK_SET) != 0 || std::fread(&n_sec_steps, 8, 1, f) != 1 ||
+            n_sec_steps > (1ull << 40)) {
+            std::fclose(f);
+            return fail(ctx, FDC_E_FORMAT, "track database file: missing or implausible secondaries section");
+        }
+        std::fseek(f, (long)sizeof h, SEEK_SET);
+    }
+    const unsigned long long want = body + (v2 ? 8ull + 4ull * (h.n_tracks + 1ull) + 8ull * (n_sec + 1ull) +
+                                                     4ull * n_sec + 8ull * n_sec + 16ull * n_sec_steps
+                                               : 0ull);
     if (size < 0 || (unsigned long long)size != want) {
         std::fclose(f);
         return fail(ctx, FDC_E_FORMAT, "track database file: %lld bytes, the header implies %llu", size, want);
     }
-    std::vector<float> bin_E;
-    std::vector<uint32_t> bin_first;
-    std::vector<uint64_t> off;
-    std::vector<fdc_step> steps;
+    std::vector<float> bin_E, emit;
+    std::vector<uint32_t> bin_first, sec_first, branch;
+    std::vector<uint64_t> off, sec_off;
+    std::vector<fdc_step> steps, sec_steps;
     try {
         bin_E.resize(h.n_bins);
         bin_first.resize(h.n_bins + 1ull);
         off.resize(h.n_tracks + 1ull);
         steps.resize(h.n_steps);
+        if (v2) {
+            sec_first.resize(h.n_tracks + 1ull);
+            sec_off.resize(n_sec + 1ull);
+            branch.resize(n_sec);
+            emit.resize(2 * n_sec);
+            sec_steps.resize(n_sec_steps);
+        }
     } catch (const std::bad_alloc &) {
         std::fclose(f);
         return fail(ctx, FDC_E_NOMEM, "track database file: host buffers");
     }
-    const bool ok = std::fread(bin_E.data(), 4, bin_E.size(), f) == bin_E.size() &&
-                    std::fread(bin_first.data(), 4, bin_first.size(), f) == bin_first.size() &&
-                    std::fread(off.data(), 8, off.size(), f) == off.size() &&
-                    std::fread(steps.data(), sizeof(fdc_step), steps.size(), f) == steps.size();
+    bool ok = std::fread(bin_E.data(), 4, bin_E.size(), f) == bin_E.size() &&
+              std::fread(bin_first.data(), 4, bin_first.size(), f) == bin_first.size() &&
+              std::fread(off.data(), 8, off.size(), f) == off.size() &&
+              std::fread(steps.data(), sizeof(fdc_step), steps.size(), f) == steps.size();
+    if (ok && v2) {
+        uint64_t again = 0;
+        ok = std::fread(&again, 8, 1, f) == 1 &&
+             std::fread(sec_first.data(), 4, sec_first.size(), f) == sec_first.size() &&
+             std::fread(sec_off.data(), 8, sec_off.size(), f) == sec_off.size() &&
+             std::fread(branch.data(), 4, branch.size(), f) == branch.size() &&
+             std::fread(emit.data(), 4, emit.size(), f) == emit.size() &&
+             std::fread(sec_steps.data(), sizeof(fdc_step), sec_steps.size(), f) == sec_steps.size();
+    }
     std::fclose(f);
     if (!ok) return fail(ctx, FDC_E_FORMAT, "track database file: short read");
-    return fdc_load_track_db(ctx, steps.data(), h.n_steps, off.data(), h.n_tracks, bin_E.data(), bin_first.data(),
-                             h.n_bins, hip_stream);
+    int rc = fdc_load_track_db(ctx, steps.data(), h.n_steps, off.data(), h.n_tracks, bin_E.data(), bin_first.data(),
+                               h.n_bins, hip_stream);
+    if (rc == FDC_OK && v2)
+        rc = fdc_load_secondaries(ctx, sec_first.data(), sec_off.data(), (uint32_t)n_sec, sec_steps.data(),
+                                  n_sec_steps, branch.data(), emit.data(), hip_stream);
+    return rc;
 }
 
 int fdc_load_phantom(fdc_ctx *ctx, int32_t *plan_out, const int16_t *hu, int nx, int ny, int nz,
@@ -1173,7 +1335,7 @@ static bool large_items(const std::vector<WorkItem> &items, unsigned long long *
     bool large = false;
     for (const WorkItem &w : items) {
         n += w.n;
-        large |= w.n > kOrderChunk;
+        large |= w.n > kOrderWholeSpot;
     }
     *hist_words = order_hist_words(n, items.size());
     return large;
@@ -1367,7 +1529,7 @@ int fdc_run_histories_noalloc(fdc_ctx *ctx, const int32_t *plans, uint32_t n_pla
             for (const fdc_spot &sp : ctx->plans[plans[i]].spots) {
                 chunks += source_order_chunks(sp.n_histories);
                 hist += sp.n_histories;
-                large |= sp.n_histories > kOrderChunk;
+                large |= sp.n_histories > kOrderWholeSpot;
             }
         // (n histories <= 64 units: the histograms fit their region)
         HIPCHK(launch_source_order(d_items, (uint32_t)n_items, (uint32_t)chunks, units, ctx->d_spots, ctx->d_hnext,

@@ -74,6 +74,17 @@ struct DevDevice {
     const float *pix;               // < 0 closed, else thickness (cm) along nrm
 };
 
+// a secondary trajectory of the track database: a particle that starts at
+// the end of one of its track's primary steps and replays steps of its own,
+// kept behind the primary steps in the same step array
+constexpr uint32_t kMaxSecPerTrack = 4;
+struct DevSec {
+    unsigned long long k0, k1;      // its steps: steps[k0 .. k1)
+    unsigned long long kb;          // the primary step at whose end it starts (~0: the end marker)
+    long long T;                    // its energy, fixed point
+    float ct, st, cph, sph;         // cos and sin of its polar and azimuthal emission angles
+};
+
 // a contiguous range of histories of one spot, cut in wave units of 64
 // histories aligned to multiples of 64.  The range starts at h0, plus the
 // spot's device history counter hnext[gspot] when the launch has one (runs;
@@ -97,6 +108,9 @@ __host__ __device__ inline unsigned long long units_for(unsigned long long n)
 // start-position order: a spot's histories are ordered in chunks of this many
 // (a multiple of the 64-history unit), one ordering workgroup per chunk
 constexpr uint32_t kOrderChunk = 16384;
+// spots of more histories than this are ordered as a whole (a device-memory
+// histogram); smaller ones chunk by chunk in LDS (at most four chunks)
+constexpr unsigned long long kOrderWholeSpot = 4ull * kOrderChunk;
 __host__ __device__ inline unsigned long long source_order_chunks(unsigned long long n)
 {
     return (n + kOrderChunk - 1) / kOrderChunk;
@@ -133,6 +147,8 @@ struct TransportArgs {
     const uint32_t *order;               // per unit and lane: offset of the lane's history in its
                                          // item, 0xFFFFFFFF = none (null: consecutive histories)
     const DevDevice *devices;            // beam-line devices (DevSpot::dev indexes them)
+    const uint32_t *sec_first;           // per track: its first secondary (null: none loaded)
+    const DevSec *secs;                  // secondaries by track and branch step, then an end marker
 };
 
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two 32x32

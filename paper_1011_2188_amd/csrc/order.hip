@@ -16,9 +16,10 @@
 // the diameter for a disk field) in Morton order; each history's offset is
 // written at its place in the per-unit lane table order[unit * 64 + lane]
 // (0xFFFFFFFF for the lanes past the item's end, filled beforehand).
-//  - An item of at most 16384 histories (one chunk, 256 units) is ordered by
-//    one workgroup: it counts the bins in LDS, scans them and places the
-//    histories (about four per cell, at most 64 x 64 cells).
+//  - An item of at most 65536 histories is ordered chunk by chunk (16384
+//    histories, 256 units each): one workgroup per chunk counts the bins in
+//    LDS, scans them and places the histories (about four per cell, at most
+//    64 x 64 cells).
 //  - A larger item is ordered as a whole, so that neighbouring units start
 //    next to each other across the entire spot: a histogram of about 16
 //    histories per cell (at most 256 x 256 cells) in device memory, counted
@@ -96,7 +97,7 @@ __global__ void __launch_bounds__(kThreads) order_large_kernel(const WorkItem *_
 {
     const uint32_t i = item_of_chunk(items, n_items, blockIdx.x);
     const WorkItem it = items[i];
-    if (it.n <= kChunk) return;                                      // (uniform: the whole block)
+    if (it.n <= kOrderWholeSpot) return;                             // (uniform: the whole block)
     const unsigned long long j0 = (unsigned long long)(blockIdx.x - it.chunk0) * kChunk;
     if (j0 >= it.n) return;
     const uint32_t len = (uint32_t)min((unsigned long long)kChunk, it.n - j0);
@@ -121,7 +122,7 @@ __global__ void __launch_bounds__(kThreads) order_scan_kernel(const WorkItem *__
 {
     __shared__ uint32_t s_wave[kThreads / kWave];
     const WorkItem it = items[blockIdx.x];
-    if (it.n <= kChunk) return;
+    if (it.n <= kOrderWholeSpot) return;
     const uint32_t ncell = 1u << (2 * large_half_bits(it.n));
     uint32_t *h = hist + (it.first >> 4) + blockIdx.x;
     const uint32_t per = (ncell + kThreads - 1) / kThreads;         // 1 .. 64 consecutive cells per thread
@@ -160,7 +161,7 @@ __global__ void __launch_bounds__(kThreads) order_chunk_kernel(const WorkItem *_
     const uint32_t t = threadIdx.x;
     const WorkItem it = items[item_of_chunk(items, n_items, blockIdx.x)];
     const DevSpot &sp = spots[it.gspot];
-    if (it.n > kChunk) return;                                       // a large item (uniform: the whole block)
+    if (it.n > kOrderWholeSpot) return;                              // ordered as a whole (uniform: the whole block)
     const unsigned long long j0 = (unsigned long long)(blockIdx.x - it.chunk0) * kChunk;
     if (j0 >= it.n) return;
     const uint32_t len = (uint32_t)min((unsigned long long)kChunk, it.n - j0);

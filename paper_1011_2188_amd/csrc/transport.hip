@@ -79,6 +79,29 @@ __host__ __device__ inline void polar_terms(float4 r, float &th, float &c, float
     s = t2 > 0.f ? r.w * ir : 0.f;
 }
 
+// Turn a unit direction b by polar angle (st = sin, ct = cos) and azimuth
+// (cph, sph) about itself, in the frame fixed by b and the beam axis (a
+// direction along the axis takes the azimuth from the beam frame's x axis),
+// and renormalise.
+__host__ __device__ inline void turn_direction(float b[3], float st, float ct, float cph, float sph)
+{
+    const float u = b[0], vv = b[1], w = b[2];
+    const float rho = fast_sqrt(u * u + vv * vv);     // |u|, |v| <= 1: no overflow
+    float nu, nv, nw;
+    if (rho < 1e-20f) {
+        nu = st * cph;
+        nv = st * sph;
+        nw = (w < 0.f ? -ct : ct);
+    } else {
+        const float ir = fast_rcp(rho);
+        nu = u * ct + st * (u * w * cph - vv * sph) * ir;
+        nv = vv * ct + st * (vv * w * cph + u * sph) * ir;
+        nw = w * ct - rho * st * cph;
+    }
+    const float nrm = fast_rsq(nu * nu + nv * nv + nw * nw);
+    b[0] = nu * nrm; b[1] = nv * nrm; b[2] = nw * nrm;
+}
+
 // Where a voxel visit's deposit goes.  Every sink adds the integer deposit
 // `acc` to E[v] and, with the squared-energy tally, q^2 to E2[v] with
 // q = (acc + 2^11) >> 12 (the deposit rounded to 2^-12 MeV).
@@ -398,7 +421,14 @@ __host__ __device__ inline bool beam_device_pass(const TransportArgs &a, const D
 // a file): history h is the source's proton h mod count, which brings its own
 // start point, direction (and with it the frame of the deflections, kept per
 // lane) and energy.
-template <bool EP, bool LISTED, class Sink>
+// SEC: the database has secondary trajectories (Section 2.2: a stored
+// history is the set of its particles' trajectories): a secondary starts at
+// the end of one of its track's primary steps, from the point the primary
+// reached and its direction there turned by the secondary's emission angles,
+// and is replayed after the primary (an end-point replay follows the primary
+// only).  Its energy follows that step's in the track's order, so a skip that
+// ends inside it drops it and starts at the next primary step whole.
+template <bool EP, bool LISTED, bool SEC, class Sink>
 __host__ __device__ void replay_history(const TransportArgs &a, const DevSpot &sp, const DevPlan &pl,
                                const float2 *__restrict__ lut, const volatile float *wc, unsigned long long h,
                                uint32_t slot, long long &inc, long long &esc, const Sink &sink)
@@ -417,14 +447,24 @@ __host__ __device__ void replay_history(const TransportArgs &a, const DevSpot &s
                                               (sp.plan << 4) | kTagTrack), a.seed_lo, a.seed_hi);
     const uint32_t t = first + (uint32_t)(((uint64_t)xt.x * nb) >> 32);
     unsigned long long k = a.track_off[t];
-    const unsigned long long kend = a.track_off[t + 1];
-    const long long skip = LISTED ? sp.bin_fp - to_fp(q0.w) : sp.skip;
+    unsigned long long kend = a.track_off[t + 1];
+    long long skip = LISTED ? sp.bin_fp - to_fp(q0.w) : sp.skip;
     long long cum = 0;
     long long e = 0;
+    uint32_t j = SEC ? a.sec_first[t] : 0u;          // the track's next secondary
     for (; k < kend; ++k) {
         e = step_energy(a.steps[k]);
         if (cum + e > skip) break;
         cum += e;
+        if (SEC) {
+            // (a later track's secondaries, and the end marker, never match k)
+            while (a.secs[j].kb == k) cum += a.secs[j++].T;
+            if (cum > skip) {
+                skip = cum;
+                ++k;
+                break;
+            }
+        }
     }
     long long I_h = a.track_T[t] - skip;
     if (I_h < 0) I_h = 0;
@@ -491,6 +531,9 @@ __host__ __device__ void replay_history(const TransportArgs &a, const DevSpot &s
             return;
         }
         k = kw;
+        // secondaries emitted at step ends inside the device stay there
+        if (SEC)
+            while (a.secs[j].kb < k) ++j;
     }
 
     // ray-box entry (FP64); outside the box is vacuum
@@ -556,198 +599,240 @@ __host__ __device__ void replay_history(const TransportArgs &a, const DevSpot &s
     // deposit is flushed, and the next step record one step ahead, so no wait
     // for a load also waits for the tally atomics issued before it.
     const uint16_t *__restrict__ vidx = pl.idx;
-    uint16_t wcur = load_global(vidx, L.v);          // the current voxel's word
-    float2 m = lut[hu_index(wcur)];
     long long acc = 0, hdep = 0;
-    bool escaped = false;
-    // the partial first step (its remaining energy e_first of the stored e):
-    // length f * dx, angle sqrt(f) * theta, azimuth rotated by phi0; a later
-    // step (the walk begins behind a compensator) is replayed whole
-    float4 rec = a.steps[k];
-    e = step_energy(rec);
-    int e32 = (int)e;                               // a step's energy fits 32 bits (checked at load)
-    float w_tot = rec.x;
-    float th, cph, sph;                             // polar angle, cos and sin of the azimuth
-    polar_terms(rec, th, cph, sph);
-    float inv_w;
-    if (k == k_first) {
-        const long long e_first = cum + e - skip;
-        const float f = ll_to_f(e_first) / ll_to_f(e);
-        e32 = (int)e_first;
-        w_tot = f * rec.x;
-        th *= sqrtf(f);
-        inv_w = 1.f / w_tot;
-        if (phi0 != 0.f) {                          // the track rotated rigidly about the beam axis
-            float s0, c0;
-            sincosf(phi0, &s0, &c0);
-            const float c = cph * c0 - sph * s0;
-            sph = sph * c0 + cph * s0;
-            cph = c;
-        }
-    } else {
-        inv_w = fast_rcp(rec.x);
-    }
-    // a step begun in a compensator continues with what was done of it there;
-    // its energy deposited so far is restated in the walk's own arithmetic
-    // (the FP32 split the walk applies to the WEL consumed), so that the
-    // walk's pieces, which continue that split, are never negative
-    float tau = (float)tau0, g2 = (float)g20;
-    int dep = tau0 > 0.0 ? min(e32, (int)rintf((float)e32 * (tau * inv_w))) : 0;
-    float4 next_rec = rec;
-    if (k + 1 < kend) next_rec = a.steps[k + 1];
-    for (;;) {
-        const float ef = (float)e32;
-        while (tau < w_tot) {
-            const uint32_t kskip = vacuum_skip(wcur);
-            if (kskip >= 2u) {
-                // Free flight through vacuum: every voxel within kskip - 1 of this
-                // one (per axis, and inside the box) is vacuum, so the proton
-                // crosses that cube in one move - no WEL, no deposit, no
-                // scattering, as voxel by voxel - to the face it reaches first
-                // (ties x -> y -> z); past the box it escapes.
-                const int n3[3] = {nx, ny, nz};
-                int ext[3];
-                float tj = kInf;
-                int axj = 0;
-#pragma unroll
-                for (int q = 0; q < 3; ++q) {
-                    const int room = L.d[q] > 0.f ? n3[q] - 1 - L.i[q] : L.i[q];
-                    ext[q] = min((int)kskip - 1, room);
-                    const float t = fmaf(ta[q], L.f[q], tb[q]) + (float)ext[q] * fabsf(ta[q]);
-                    if (t < tj) { tj = t; axj = q; }
-                }
-                bool out = false;
-#pragma unroll
-                for (int q = 0; q < 3; ++q) {
-                    if (q == axj) {
-                        const int up = L.d[q] > 0.f ? 1 : -1;
-                        const int ni = L.i[q] + up * (ext[q] + 1);
-                        out = (unsigned)ni >= (unsigned)n3[q];
-                        L.i[q] = out ? L.i[q] + up * ext[q] : ni;             // out: stays on the last voxel's
-                        L.f[q] = (up > 0) == out ? 1.f : 0.f;                  // exit face, else the entry face
-                    } else if (L.d[q] != 0.f) {
-                        const float u = fmaf(tj, dv[q], L.f[q]);
-                        float fl = floorf(u);
-                        fl = L.d[q] > 0.f ? fminf(fmaxf(fl, 0.f), (float)ext[q]) : fmaxf(fminf(fl, 0.f), -(float)ext[q]);
-                        L.i[q] += (int)fl;
-                        L.f[q] = fminf(fmaxf(u - fl, 0.f), 1.f);
-                    }
-                }
-                if (out) {
-                    escaped = true;
-                    break;
-                }
-                L.v = ((uint32_t)L.i[2] * (uint32_t)ny + (uint32_t)L.i[1]) * (uint32_t)nx + (uint32_t)L.i[0];
-                wcur = load_global(vidx, L.v);
-                m = lut[hu_index(wcur)];
-                continue;
-            }
-            // distance (cm) to the exit face along each axis; ties go x -> y -> z
-            const float tx = fmaf(ta[0], L.f[0], tb[0]);
-            const float ty = fmaf(ta[1], L.f[1], tb[1]);
-            const float tz = fmaf(ta[2], L.f[2], tb[2]);
-            float tmin = tx;
-            int ax = 0;
-            if (ty < tmin) { tmin = ty; ax = 1; }
-            if (tz < tmin) { tmin = tz; ax = 2; }
-            // the voxel across that face, and its material index (prefetch)
-            const float d_ax = ax == 0 ? L.d[0] : (ax == 1 ? L.d[1] : L.d[2]);
-            const int i_ax = ax == 0 ? L.i[0] : (ax == 1 ? L.i[1] : L.i[2]);
-            const int n_ax = ax == 0 ? nx : (ax == 1 ? ny : nz);
-            const uint32_t st_ax = ax == 0 ? stride[0] : (ax == 1 ? stride[1] : stride[2]);
-            const int ni = i_ax + (d_ax > 0.f ? 1 : -1);
-            const bool out = (unsigned)ni >= (unsigned)n_ax;
-            const uint32_t vn = d_ax > 0.f ? L.v + st_ax : L.v - st_ax;
-            const uint16_t idx_n = load_global(vidx, out ? L.v : vn);
-            // consume WEL in this voxel: up to the face (wb) or the step's end
-            // (rem), whichever comes first.  Written without branches; a vacuum
-            // voxel (RSP 0) gives wb = 0: no WEL, no deposit, a full crossing.
-            const float rem = w_tot - tau;
-            const float wb = tmin * m.x;
-            const bool ends = rem <= wb;                 // the step ends in this voxel
-            const float w_v = ends ? rem : wb;
-            const float tau_n = ends ? w_tot : tau + wb;
-            const float move = ends ? rem * fast_rcp(m.x) : tmin;
-            const bool cross = ends ? (rem == wb) : true;
-            const int cumk = tau_n < w_tot ? min(e32, (int)rintf(ef * (tau_n * inv_w))) : e32;
-            const int piece = cumk - dep;
-            dep = cumk;
-            acc += piece;
-            hdep += piece;
-            g2 += w_v * m.y;
-            tau = tau_n;
-#pragma unroll
-            for (int q = 0; q < 3; ++q) L.f[q] = fminf(fmaxf(L.f[q] + move * dv[q], 0.f), 1.f);
-            if (cross) {
-                if (acc != 0) {
-                    sink.add(L.v, (uint32_t)L.i[0], acc);
-                    acc = 0;
-                }
-                const float f_new = (d_ax > 0.f) == out ? 1.f : 0.f;   // exit face when out, else entry face
-#pragma unroll
-                for (int q = 0; q < 3; ++q) {
-                    if (q == ax) {
-                        L.f[q] = f_new;
-                        if (!out) L.i[q] = ni;
-                    }
-                }
-                if (out) {
-                    escaped = true;
-                    break;
-                }
-                L.v = vn;
-                wcur = idx_n;
-                m = lut[hu_index(idx_n)];
-            }
-        }
-        if (escaped) break;
-        // deflection at the end of the step, scaled by the traversed material
-        const float th2 = th * fast_sqrt(g2 * inv_w);
-        float st, ct;
-        small_sincos(th2, &st, &ct);
-        const float u = L.b[0], vv = L.b[1], w = L.b[2];
-        const float rho = fast_sqrt(u * u + vv * vv);     // |u|, |v| <= 1: no overflow
-        float nu, nv, nw;
-        if (rho < 1e-20f) {
-            nu = st * cph;
-            nv = st * sph;
-            nw = (w < 0.f ? -ct : ct);
-        } else {
-            const float ir = fast_rcp(rho);
-            nu = u * ct + st * (u * w * cph - vv * sph) * ir;
-            nv = vv * ct + st * (vv * w * cph + u * sph) * ir;
-            nw = w * ct - rho * st * cph;
-        }
-        const float nrm = fast_rsq(nu * nu + nv * nv + nw * nw);
-        L.b[0] = nu * nrm; L.b[1] = nv * nrm; L.b[2] = nw * nrm;
-#pragma unroll
-        for (int q = 0; q < 3; ++q)
-            L.d[q] = LISTED ? lm[3 * q + 0] * L.b[0] + lm[3 * q + 1] * L.b[1] + lm[3 * q + 2] * L.b[2]
-                            : wc[3 * q + 0] * L.b[0] + wc[3 * q + 1] * L.b[1] + wc[3 * q + 2] * L.b[2];
-        {
-            const float iv[3] = {wc[9], wc[10], wc[11]};
-            set_direction_terms(L.d, iv, ta, tb, dv);
-        }
-        // next stored step (its record and terms were loaded one step ahead)
-        if (++k >= kend) break;
-        rec = next_rec;
-        if (k + 1 < kend) next_rec = a.steps[k + 1];
-        w_tot = rec.x;
+    // secondaries met by the primary (SEC): kb is the step at whose end the
+    // next one starts
+    struct Branch {
+        int i[3];
+        float f[3], b[3];
+        uint32_t j;
+    };
+    Branch br[SEC ? kMaxSecPerTrack : 1];
+    int nbr = 0, traj = 0;
+    unsigned long long kb = SEC ? a.secs[j].kb : 0ull;
+    for (;;) {                                      // the primary, then its secondaries
+        uint16_t wcur = load_global(vidx, L.v);          // the current voxel's word
+        float2 m = lut[hu_index(wcur)];
+        bool escaped = false;
+        // the partial first step (its remaining energy e_first of the stored e):
+        // length f * dx, angle sqrt(f) * theta, azimuth rotated by phi0; a later
+        // step (the walk begins behind a compensator) is replayed whole
+        float4 rec = a.steps[k];
+        e = step_energy(rec);
+        int e32 = (int)e;                               // a step's energy fits 32 bits (checked at load)
+        float w_tot = rec.x;
+        float th, cph, sph;                             // polar angle, cos and sin of the azimuth
         polar_terms(rec, th, cph, sph);
-        inv_w = fast_rcp(rec.x);
-        e32 = (int)step_energy(rec);
-        tau = 0.f;
-        g2 = 0.f;
-        dep = 0;
-    }
-    if (!escaped && acc != 0) sink.add(L.v, (uint32_t)L.i[0], acc);
-    esc = I_h - hdep;                               // escaped, or deposited upstream (up), or 0
-    if (EP) {
+        float inv_w;
+        if (k == k_first) {
+            const long long e_first = cum + e - skip;
+            const float f = ll_to_f(e_first) / ll_to_f(e);
+            e32 = (int)e_first;
+            w_tot = f * rec.x;
+            th *= sqrtf(f);
+            inv_w = 1.f / w_tot;
+            if (phi0 != 0.f) {                          // the track rotated rigidly about the beam axis
+                float s0, c0;
+                sincosf(phi0, &s0, &c0);
+                const float c = cph * c0 - sph * s0;
+                sph = sph * c0 + cph * s0;
+                cph = c;
+            }
+        } else {
+            inv_w = fast_rcp(rec.x);
+        }
+        // a step begun in a compensator continues with what was done of it there;
+        // its energy deposited so far is restated in the walk's own arithmetic
+        // (the FP32 split the walk applies to the WEL consumed), so that the
+        // walk's pieces, which continue that split, are never negative
+        float tau = (float)tau0, g2 = (float)g20;
+        int dep = tau0 > 0.0 ? min(e32, (int)rintf((float)e32 * (tau * inv_w))) : 0;
+        float4 next_rec = rec;
+        if (k + 1 < kend) next_rec = a.steps[k + 1];
+        for (;;) {
+            const float ef = (float)e32;
+            while (tau < w_tot) {
+                const uint32_t kskip = vacuum_skip(wcur);
+                if (kskip >= 2u) {
+                    // Free flight through vacuum: every voxel within kskip - 1 of this
+                    // one (per axis, and inside the box) is vacuum, so the proton
+                    // crosses that cube in one move - no WEL, no deposit, no
+                    // scattering, as voxel by voxel - to the face it reaches first
+                    // (ties x -> y -> z); past the box it escapes.
+                    const int n3[3] = {nx, ny, nz};
+                    int ext[3];
+                    float tj = kInf;
+                    int axj = 0;
 #pragma unroll
-        for (int q = 0; q < 3; ++q)
-            a.ep_xyz[3 * slot + q] = (float)(pl.org_d[q] + ((double)L.i[q] + (double)L.f[q]) * pl.vox_d[q]);
-        a.ep_reason[slot] = escaped ? 1 : 0;
+                    for (int q = 0; q < 3; ++q) {
+                        const int room = L.d[q] > 0.f ? n3[q] - 1 - L.i[q] : L.i[q];
+                        ext[q] = min((int)kskip - 1, room);
+                        const float t = fmaf(ta[q], L.f[q], tb[q]) + (float)ext[q] * fabsf(ta[q]);
+                        if (t < tj) { tj = t; axj = q; }
+                    }
+                    bool out = false;
+#pragma unroll
+                    for (int q = 0; q < 3; ++q) {
+                        if (q == axj) {
+                            const int up = L.d[q] > 0.f ? 1 : -1;
+                            const int ni = L.i[q] + up * (ext[q] + 1);
+                            out = (unsigned)ni >= (unsigned)n3[q];
+                            L.i[q] = out ? L.i[q] + up * ext[q] : ni;             // out: stays on the last voxel's
+                            L.f[q] = (up > 0) == out ? 1.f : 0.f;                  // exit face, else the entry face
+                        } else if (L.d[q] != 0.f) {
+                            const float u = fmaf(tj, dv[q], L.f[q]);
+                            float fl = floorf(u);
+                            fl = L.d[q] > 0.f ? fminf(fmaxf(fl, 0.f), (float)ext[q]) : fmaxf(fminf(fl, 0.f), -(float)ext[q]);
+                            L.i[q] += (int)fl;
+                            L.f[q] = fminf(fmaxf(u - fl, 0.f), 1.f);
+                        }
+                    }
+                    if (out) {
+                        escaped = true;
+                        break;
+                    }
+                    L.v = ((uint32_t)L.i[2] * (uint32_t)ny + (uint32_t)L.i[1]) * (uint32_t)nx + (uint32_t)L.i[0];
+                    wcur = load_global(vidx, L.v);
+                    m = lut[hu_index(wcur)];
+                    continue;
+                }
+                // distance (cm) to the exit face along each axis; ties go x -> y -> z
+                const float tx = fmaf(ta[0], L.f[0], tb[0]);
+                const float ty = fmaf(ta[1], L.f[1], tb[1]);
+                const float tz = fmaf(ta[2], L.f[2], tb[2]);
+                float tmin = tx;
+                int ax = 0;
+                if (ty < tmin) { tmin = ty; ax = 1; }
+                if (tz < tmin) { tmin = tz; ax = 2; }
+                // the voxel across that face, and its material index (prefetch)
+                const float d_ax = ax == 0 ? L.d[0] : (ax == 1 ? L.d[1] : L.d[2]);
+                const int i_ax = ax == 0 ? L.i[0] : (ax == 1 ? L.i[1] : L.i[2]);
+                const int n_ax = ax == 0 ? nx : (ax == 1 ? ny : nz);
+                const uint32_t st_ax = ax == 0 ? stride[0] : (ax == 1 ? stride[1] : stride[2]);
+                const int ni = i_ax + (d_ax > 0.f ? 1 : -1);
+                const bool out = (unsigned)ni >= (unsigned)n_ax;
+                const uint32_t vn = d_ax > 0.f ? L.v + st_ax : L.v - st_ax;
+                const uint16_t idx_n = load_global(vidx, out ? L.v : vn);
+                // consume WEL in this voxel: up to the face (wb) or the step's end
+                // (rem), whichever comes first.  Written without branches; a vacuum
+                // voxel (RSP 0) gives wb = 0: no WEL, no deposit, a full crossing.
+                const float rem = w_tot - tau;
+                const float wb = tmin * m.x;
+                const bool ends = rem <= wb;                 // the step ends in this voxel
+                const float w_v = ends ? rem : wb;
+                const float tau_n = ends ? w_tot : tau + wb;
+                const float move = ends ? rem * fast_rcp(m.x) : tmin;
+                const bool cross = ends ? (rem == wb) : true;
+                const int cumk = tau_n < w_tot ? min(e32, (int)rintf(ef * (tau_n * inv_w))) : e32;
+                const int piece = cumk - dep;
+                dep = cumk;
+                acc += piece;
+                hdep += piece;
+                g2 += w_v * m.y;
+                tau = tau_n;
+#pragma unroll
+                for (int q = 0; q < 3; ++q) L.f[q] = fminf(fmaxf(L.f[q] + move * dv[q], 0.f), 1.f);
+                if (cross) {
+                    if (acc != 0) {
+                        sink.add(L.v, (uint32_t)L.i[0], acc);
+                        acc = 0;
+                    }
+                    const float f_new = (d_ax > 0.f) == out ? 1.f : 0.f;   // exit face when out, else entry face
+#pragma unroll
+                    for (int q = 0; q < 3; ++q) {
+                        if (q == ax) {
+                            L.f[q] = f_new;
+                            if (!out) L.i[q] = ni;
+                        }
+                    }
+                    if (out) {
+                        escaped = true;
+                        break;
+                    }
+                    L.v = vn;
+                    wcur = idx_n;
+                    m = lut[hu_index(idx_n)];
+                }
+            }
+            if (escaped) break;
+            // deflection at the end of the step, scaled by the traversed material
+            const float th2 = th * fast_sqrt(g2 * inv_w);
+            float st, ct;
+            small_sincos(th2, &st, &ct);
+            turn_direction(L.b, st, ct, cph, sph);
+#pragma unroll
+            for (int q = 0; q < 3; ++q)
+                L.d[q] = LISTED ? lm[3 * q + 0] * L.b[0] + lm[3 * q + 1] * L.b[1] + lm[3 * q + 2] * L.b[2]
+                                : wc[3 * q + 0] * L.b[0] + wc[3 * q + 1] * L.b[1] + wc[3 * q + 2] * L.b[2];
+            {
+                const float iv[3] = {wc[9], wc[10], wc[11]};
+                set_direction_terms(L.d, iv, ta, tb, dv);
+            }
+            // secondaries that start here: the point and the direction after the
+            // deflection, kept until the primary is done
+            if (SEC && k == kb) {
+                do {
+                    Branch &B = br[nbr++];              // at most kMaxSecPerTrack per track (checked at load)
+#pragma unroll
+                    for (int q = 0; q < 3; ++q) {
+                        B.i[q] = L.i[q];
+                        B.f[q] = L.f[q];
+                        B.b[q] = L.b[q];
+                    }
+                    B.j = j;
+                    kb = a.secs[++j].kb;
+                } while (kb == k);
+            }
+            // next stored step (its record and terms were loaded one step ahead)
+            if (++k >= kend) break;
+            rec = next_rec;
+            if (k + 1 < kend) next_rec = a.steps[k + 1];
+            w_tot = rec.x;
+            polar_terms(rec, th, cph, sph);
+            inv_w = fast_rcp(rec.x);
+            e32 = (int)step_energy(rec);
+            tau = 0.f;
+            g2 = 0.f;
+            dep = 0;
+        }
+        if (!escaped && acc != 0) sink.add(L.v, (uint32_t)L.i[0], acc);
+        acc = 0;
+        if (EP) {                                       // the primary's end
+#pragma unroll
+            for (int q = 0; q < 3; ++q)
+                a.ep_xyz[3 * slot + q] = (float)(pl.org_d[q] + ((double)L.i[q] + (double)L.f[q]) * pl.vox_d[q]);
+            a.ep_reason[slot] = escaped ? 1 : 0;
+            break;
+        }
+        if (!SEC || traj >= nbr) break;
+        // the next secondary: from its branch point, turned by its emission angles,
+        // all of its steps whole
+        {
+            const Branch B = br[traj++];
+            const DevSec sc = a.secs[B.j];
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                L.i[q] = B.i[q];
+                L.f[q] = B.f[q];
+                L.b[q] = B.b[q];
+            }
+            turn_direction(L.b, sc.st, sc.ct, sc.cph, sc.sph);
+#pragma unroll
+            for (int q = 0; q < 3; ++q)
+                L.d[q] = LISTED ? lm[3 * q + 0] * L.b[0] + lm[3 * q + 1] * L.b[1] + lm[3 * q + 2] * L.b[2]
+                                : wc[3 * q + 0] * L.b[0] + wc[3 * q + 1] * L.b[1] + wc[3 * q + 2] * L.b[2];
+            {
+                const float iv[3] = {wc[9], wc[10], wc[11]};
+                set_direction_terms(L.d, iv, ta, tb, dv);
+            }
+            L.v = ((uint32_t)L.i[2] * (uint32_t)ny + (uint32_t)L.i[1]) * (uint32_t)nx + (uint32_t)L.i[0];
+            k = sc.k0;
+            kend = sc.k1;
+            tau0 = 0.0;
+            g20 = 0.0;
+        }
     }
+    esc = I_h - hdep;                               // escaped, or deposited upstream (up), or 0
 }
 
 __device__ inline long long wave_sum(long long x)
@@ -757,7 +842,7 @@ __device__ inline long long wave_sum(long long x)
     return x;
 }
 
-template <bool EP, class Sink>
+template <bool EP, bool SEC, class Sink>
 __device__ void process_unit(const TransportArgs &a, const float2 *lut, float *wc, unsigned long long unit,
                              uint32_t lane, const Sink &sink)
 {
@@ -791,9 +876,9 @@ __device__ void process_unit(const TransportArgs &a, const float2 *lut, float *w
     else if (lane < 12) wc[lane] = pl.inv_vox[lane - 9];
     if (valid) {
         if (sp.kind)                                  // (wave-uniform: a unit is one source's)
-            replay_history<EP, true>(a, sp, pl, lut, wc, h, (uint32_t)(h - h0), inc, esc, sink);
+            replay_history<EP, true, SEC>(a, sp, pl, lut, wc, h, (uint32_t)(h - h0), inc, esc, sink);
         else
-            replay_history<EP, false>(a, sp, pl, lut, wc, h, (uint32_t)(h - h0), inc, esc, sink);
+            replay_history<EP, false, SEC>(a, sp, pl, lut, wc, h, (uint32_t)(h - h0), inc, esc, sink);
     }
     if (!EP) {
         inc = wave_sum(inc);
@@ -824,7 +909,7 @@ __device__ inline unsigned long long scalar_u64(unsigned long long x)
     return ((unsigned long long)hi << 32) | lo;
 }
 
-template <bool VAR, bool EP>
+template <bool VAR, bool EP, bool SEC>
 __global__ void __launch_bounds__(1024) transport_kernel(TransportArgs a)
 {
     __shared__ float2 s_lut[kLutSize];
@@ -837,10 +922,10 @@ __global__ void __launch_bounds__(1024) transport_kernel(TransportArgs a)
     if (a.queue == nullptr) {
         const unsigned long long unit = (unsigned long long)blockIdx.x * wpb + wave;
         if (unit < a.n_units) {
-            if (EP) process_unit<EP>(a, s_lut, s_wc[wave], unit, lane, NullSink{});
+            if (EP) process_unit<EP, SEC>(a, s_lut, s_wc[wave], unit, lane, NullSink{});
             else {
                 const DevPlan *pl = plan_of_unit(a, unit);
-                process_unit<EP>(a, s_lut, s_wc[wave], unit, lane, GlobalSink<VAR>{pl->E, pl->E2});
+                process_unit<EP, SEC>(a, s_lut, s_wc[wave], unit, lane, GlobalSink<VAR>{pl->E, pl->E2});
             }
         }
         return;
@@ -853,10 +938,10 @@ __global__ void __launch_bounds__(1024) transport_kernel(TransportArgs a)
     for (;;) {
         const unsigned long long unit = scalar_u64(atomicAdd(a.queue, lane == 0 ? 1ull : 0ull));
         if (unit >= a.n_units) break;
-        if (EP) process_unit<EP>(a, s_lut, s_wc[wave], unit, lane, NullSink{});
+        if (EP) process_unit<EP, SEC>(a, s_lut, s_wc[wave], unit, lane, NullSink{});
         else {
             const DevPlan *pl = plan_of_unit(a, unit);
-            process_unit<EP>(a, s_lut, s_wc[wave], unit, lane, GlobalSink<VAR>{pl->E, pl->E2});
+            process_unit<EP, SEC>(a, s_lut, s_wc[wave], unit, lane, GlobalSink<VAR>{pl->E, pl->E2});
         }
     }
 }
@@ -869,7 +954,7 @@ __global__ void __launch_bounds__(1024) transport_kernel(TransportArgs a)
 // whose histories overlap in space, so most visits of a round merge in LDS.
 // CACHE selects the sub-tally: the hash table with global fallback (LdsSink)
 // or the write-back cache (CacheSink).
-template <bool VAR, bool CACHE>
+template <bool VAR, bool CACHE, bool SEC>
 __global__ void __launch_bounds__(1024) transport_lds_kernel(TransportArgs a, uint32_t slots, uint32_t upw)
 {
     __shared__ float2 s_lut[kLutSize];
@@ -906,11 +991,11 @@ __global__ void __launch_bounds__(1024) transport_lds_kernel(TransportArgs a, ui
             if (unit >= a.n_units) break;
             const DevPlan *pl = plan_of_unit(a, unit);
             if (CACHE)
-                process_unit<false>(a, s_lut, s_wc[wave], unit, lane,
-                                    CacheSink<VAR>{pl->E, pl->E2, pl == tab_pl, s_e, s_e2, slots, vbits, nvox});
+                process_unit<false, SEC>(a, s_lut, s_wc[wave], unit, lane,
+                                         CacheSink<VAR>{pl->E, pl->E2, pl == tab_pl, s_e, s_e2, slots, vbits, nvox});
             else
-                process_unit<false>(a, s_lut, s_wc[wave], unit, lane,
-                                    LdsSink<VAR>{pl->E, pl->E2, pl == tab_pl, s_key, s_e, s_e2, slots - 1});
+                process_unit<false, SEC>(a, s_lut, s_wc[wave], unit, lane,
+                                         LdsSink<VAR>{pl->E, pl->E2, pl == tab_pl, s_key, s_e, s_e2, slots - 1});
         }
         __syncthreads();
         // flush: one atomic per occupied slot; consecutive slots often hold
@@ -960,7 +1045,7 @@ __global__ void __launch_bounds__(1024) transport_lds_kernel(TransportArgs a, ui
 // (first unit << 16 | units handed out); the wave that draws index `chunk`
 // fetches the next chunk, waves that draw past it wait until the word holds
 // a new chunk (that wave's fetch never waits on anything).
-template <bool VAR>
+template <bool VAR, bool SEC>
 __global__ void __launch_bounds__(1024) transport_cache_kernel(TransportArgs a, uint32_t slots, uint32_t chunk)
 {
     __shared__ float2 s_lut[kLutSize];
@@ -995,7 +1080,7 @@ __global__ void __launch_bounds__(1024) transport_cache_kernel(TransportArgs a, 
         if (base >= n_units) break;
         if (idx < chunk) {
             const unsigned long long unit = base + idx;
-            if (unit < n_units) process_unit<false>(a, s_lut, s_wc[wave], unit, lane, cs);
+            if (unit < n_units) process_unit<false, SEC>(a, s_lut, s_wc[wave], unit, lane, cs);
         } else if (idx == chunk) {
             const unsigned long long nb = scalar_u64(atomicAdd(a.queue, lane == 0 ? (unsigned long long)chunk : 0ull));
             if (lane == 0) atomicExch(&s_chunk, (nb < n_units ? nb : n_units) << 16);
@@ -1011,6 +1096,39 @@ __global__ void __launch_bounds__(1024) transport_cache_kernel(TransportArgs a, 
     }
 }
 
+template <bool SEC>
+hipError_t launch_transport_t(const TransportArgs &a, dim3 grid, dim3 block, bool variance, bool endpoints,
+                              hipStream_t s)
+{
+    if (endpoints)
+        hipLaunchKernelGGL((transport_kernel<false, true, SEC>), grid, block, 0, s, a);
+    else if (variance)
+        hipLaunchKernelGGL((transport_kernel<true, false, SEC>), grid, block, 0, s, a);
+    else
+        hipLaunchKernelGGL((transport_kernel<false, false, SEC>), grid, block, 0, s, a);
+    return hipGetLastError();
+}
+
+template <bool SEC>
+hipError_t launch_transport_lds_t(const TransportArgs &a, dim3 grid, dim3 block, size_t dyn, uint32_t slots,
+                                  uint32_t units_per_wave, uint32_t waves_per_block, bool variance, uint32_t mode,
+                                  hipStream_t s)
+{
+    if (mode == 2 && variance)
+        hipLaunchKernelGGL((transport_cache_kernel<true, SEC>), grid, block, dyn, s, a, slots, waves_per_block * units_per_wave);
+    else if (mode == 2)
+        hipLaunchKernelGGL((transport_cache_kernel<false, SEC>), grid, block, dyn, s, a, slots, waves_per_block * units_per_wave);
+    else if (mode && variance)
+        hipLaunchKernelGGL((transport_lds_kernel<true, true, SEC>), grid, block, dyn, s, a, slots, units_per_wave);
+    else if (mode)
+        hipLaunchKernelGGL((transport_lds_kernel<false, true, SEC>), grid, block, dyn, s, a, slots, units_per_wave);
+    else if (variance)
+        hipLaunchKernelGGL((transport_lds_kernel<true, false, SEC>), grid, block, dyn, s, a, slots, units_per_wave);
+    else
+        hipLaunchKernelGGL((transport_lds_kernel<false, false, SEC>), grid, block, dyn, s, a, slots, units_per_wave);
+    return hipGetLastError();
+}
+
 } // namespace
 
 hipError_t launch_transport(const TransportArgs &a, uint32_t waves_per_block, uint32_t grid_blocks,
@@ -1018,13 +1136,8 @@ hipError_t launch_transport(const TransportArgs &a, uint32_t waves_per_block, ui
 {
     const dim3 block(waves_per_block * kWave);
     const dim3 grid(grid_blocks);
-    if (endpoints)
-        hipLaunchKernelGGL((transport_kernel<false, true>), grid, block, 0, s, a);
-    else if (variance)
-        hipLaunchKernelGGL((transport_kernel<true, false>), grid, block, 0, s, a);
-    else
-        hipLaunchKernelGGL((transport_kernel<false, false>), grid, block, 0, s, a);
-    return hipGetLastError();
+    return a.secs ? launch_transport_t<true>(a, grid, block, variance, endpoints, s)
+                  : launch_transport_t<false>(a, grid, block, variance, endpoints, s);
 }
 
 size_t lds_tally_bytes(uint32_t slots, bool variance, uint32_t mode)
@@ -1035,11 +1148,18 @@ size_t lds_tally_bytes(uint32_t slots, bool variance, uint32_t mode)
 hipError_t prepare_lds_kernels()
 {
     const int dyn = (int)(kMaxLdsBytes - kLutSize * sizeof(float2) - kLdsFixedBytes);
-    const void *k[6] = {(const void *)transport_lds_kernel<true, false>, (const void *)transport_lds_kernel<false, false>,
-                        (const void *)transport_lds_kernel<true, true>, (const void *)transport_lds_kernel<false, true>,
-                        (const void *)transport_cache_kernel<true>, (const void *)transport_cache_kernel<false>};
+    const void *k[12] = {(const void *)transport_lds_kernel<true, false, false>,
+                         (const void *)transport_lds_kernel<false, false, false>,
+                         (const void *)transport_lds_kernel<true, true, false>,
+                         (const void *)transport_lds_kernel<false, true, false>,
+                         (const void *)transport_cache_kernel<true, false>, (const void *)transport_cache_kernel<false, false>,
+                         (const void *)transport_lds_kernel<true, false, true>,
+                         (const void *)transport_lds_kernel<false, false, true>,
+                         (const void *)transport_lds_kernel<true, true, true>,
+                         (const void *)transport_lds_kernel<false, true, true>,
+                         (const void *)transport_cache_kernel<true, true>, (const void *)transport_cache_kernel<false, true>};
     hipError_t e = hipSuccess;
-    for (int i = 0; i < 6 && e == hipSuccess; ++i)
+    for (int i = 0; i < 12 && e == hipSuccess; ++i)
         e = hipFuncSetAttribute(k[i], hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
     return e;
 }
@@ -1051,9 +1171,19 @@ hipError_t prepare_lds_kernels()
 // all, and this is at least 1 exactly when the launch can run.
 hipError_t cache_kernel_occupancy(uint32_t waves_per_block, uint32_t slots, bool variance, int *blocks)
 {
-    const void *k = variance ? (const void *)transport_cache_kernel<true> : (const void *)transport_cache_kernel<false>;
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, k, (int)(waves_per_block * kWave),
-                                                        lds_tally_bytes(slots, variance, 2));
+    // (the kernels with and without secondaries: the launch may use either)
+    const void *k[2] = {variance ? (const void *)transport_cache_kernel<true, false>
+                                 : (const void *)transport_cache_kernel<false, false>,
+                        variance ? (const void *)transport_cache_kernel<true, true>
+                                 : (const void *)transport_cache_kernel<false, true>};
+    int b[2] = {0, 0};
+    for (int i = 0; i < 2; ++i) {
+        const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(b + i, k[i], (int)(waves_per_block * kWave),
+                                                                          lds_tally_bytes(slots, variance, 2));
+        if (e != hipSuccess) return e;
+    }
+    *blocks = b[0] < b[1] ? b[0] : b[1];
+    return hipSuccess;
 }
 
 hipError_t launch_transport_lds(const TransportArgs &a, uint32_t waves_per_block, uint32_t grid_blocks,
@@ -1062,19 +1192,10 @@ hipError_t launch_transport_lds(const TransportArgs &a, uint32_t waves_per_block
     const dim3 block(waves_per_block * kWave);
     const dim3 grid(grid_blocks);
     const size_t dyn = lds_tally_bytes(slots, variance, mode);
-    if (mode == 2 && variance)
-        hipLaunchKernelGGL((transport_cache_kernel<true>), grid, block, dyn, s, a, slots, waves_per_block * units_per_wave);
-    else if (mode == 2)
-        hipLaunchKernelGGL((transport_cache_kernel<false>), grid, block, dyn, s, a, slots, waves_per_block * units_per_wave);
-    else if (mode && variance)
-        hipLaunchKernelGGL((transport_lds_kernel<true, true>), grid, block, dyn, s, a, slots, units_per_wave);
-    else if (mode)
-        hipLaunchKernelGGL((transport_lds_kernel<false, true>), grid, block, dyn, s, a, slots, units_per_wave);
-    else if (variance)
-        hipLaunchKernelGGL((transport_lds_kernel<true, false>), grid, block, dyn, s, a, slots, units_per_wave);
-    else
-        hipLaunchKernelGGL((transport_lds_kernel<false, false>), grid, block, dyn, s, a, slots, units_per_wave);
-    return hipGetLastError();
+    return a.secs ? launch_transport_lds_t<true>(a, grid, block, dyn, slots, units_per_wave, waves_per_block, variance,
+                                                 mode, s)
+                  : launch_transport_lds_t<false>(a, grid, block, dyn, slots, units_per_wave, waves_per_block, variance,
+                                                  mode, s);
 }
 
 } // namespace fdc

@@ -28,7 +28,7 @@ ERROR_NAMES = {0: "FDC_OK", -1: "FDC_E_ARG", -2: "FDC_E_STATE", -3: "FDC_E_NOMEM
 
 # every entry point declared in include/fdc.h
 EXPORTS = ["fdc_create", "fdc_destroy", "fdc_last_error", "fdc_set_allocator", "fdc_set_hu_table",
-           "fdc_load_track_db", "fdc_load_track_db_file", "fdc_load_phantom", "fdc_add_beam_spots", "fdc_add_phase_space",
+           "fdc_load_track_db", "fdc_load_secondaries", "fdc_load_track_db_file", "fdc_load_phantom", "fdc_add_beam_spots", "fdc_add_phase_space",
            "fdc_add_phase_space_file", "fdc_add_beam_device", "fdc_set_spot_device", "fdc_run_histories",
            "fdc_run_histories_noalloc", "fdc_prepare_run",
            "fdc_reset_plan", "fdc_compute_dose", "fdc_read_dose_and_variance", "fdc_debug_endpoints",
@@ -89,6 +89,7 @@ def lib():
         "fdc_set_allocator": (C.c_int, [_P, ALLOC_FN, FREE_FN, _P]),
         "fdc_set_hu_table": (C.c_int, [_P, _P, _P, _P, _P, C.c_int, C.c_float]),
         "fdc_load_track_db": (C.c_int, [_P, _P, C.c_uint64, _P, C.c_uint32, _P, _P, C.c_uint32, _P]),
+        "fdc_load_secondaries": (C.c_int, [_P, _P, _P, C.c_uint32, _P, C.c_uint64, _P, _P, _P]),
         "fdc_load_track_db_file": (C.c_int, [_P, C.c_char_p, _P]),
         "fdc_load_phantom": (C.c_int, [_P, C.POINTER(C.c_int32), _P, C.c_int, C.c_int, C.c_int, _P, _P, _P]),
         "fdc_add_beam_spots": (C.c_int, [_P, C.c_int32, _P, C.c_uint32]),
@@ -277,6 +278,19 @@ class Context:
         _check(self.h, lib().fdc_load_track_db(self.h, steps.ctypes.data, steps.shape[0], off.ctypes.data,
                                                off.size - 1, be.ctypes.data, bf.ctypes.data, be.size,
                                                _stream(stream)))
+        if getattr(db, "sec", None) is not None:
+            self.load_secondaries(db.sec, stream)
+
+    def load_secondaries(self, sec, stream=None):
+        """The database's secondary trajectories (inputs.Secondaries)."""
+        first = np.ascontiguousarray(sec.sec_first, np.uint32)
+        off = np.ascontiguousarray(sec.off, np.uint64)
+        st = np.ascontiguousarray(sec.steps, np.float32).reshape(-1, 4)
+        br = np.ascontiguousarray(sec.branch, np.uint32)
+        em = np.ascontiguousarray(sec.emit, np.float32).reshape(-1, 2)
+        _check(self.h, lib().fdc_load_secondaries(self.h, first.ctypes.data, off.ctypes.data, br.size,
+                                                  st.ctypes.data, st.shape[0], br.ctypes.data, em.ctypes.data,
+                                                  _stream(stream)))
 
     def load_track_db_file(self, path, stream=None):
         _check(self.h, lib().fdc_load_track_db_file(self.h, os.fsencode(path), _stream(stream)))

@@ -71,11 +71,32 @@ class Phantom:
 
 
 @dataclasses.dataclass
+class Secondaries:
+    """Secondary trajectories of a track database (Section 2.2: each particle
+    trajectory of a stored history is broken into steps): trajectory j of
+    track t (sec_first[t] <= j < sec_first[t+1]) starts at the end of the
+    track's primary step `branch[j]` (counted from the track's first step),
+    leaving at polar angle emit[j, 0] and azimuth emit[j, 1] from the
+    primary's direction there, and replays its own steps
+    steps[off[j] : off[j+1]] = (dx, dE, theta, phi)."""
+    sec_first: np.ndarray     # uint32 [n_tracks + 1]
+    off: np.ndarray           # uint64 [n_sec + 1]
+    steps: np.ndarray         # float32 [n_sec_steps, 4]
+    branch: np.ndarray        # uint32 [n_sec]
+    emit: np.ndarray          # float32 [n_sec, 2]
+
+    @property
+    def n(self):
+        return int(self.branch.size)
+
+
+@dataclasses.dataclass
 class TrackDB:
     steps: np.ndarray         # float32 [n_steps, 4] = (dx, dE, theta, phi)
     track_off: np.ndarray     # uint64 [n_tracks + 1]
     bin_E: np.ndarray         # float32 [n_bins]
     bin_first: np.ndarray     # uint32 [n_bins + 1]
+    sec: Secondaries = None   # secondary trajectories, if any
 
     @property
     def n_tracks(self):
@@ -117,10 +138,18 @@ def energy_at_range(R):
     return np.power(np.maximum(R, 0.0) / ALPHA, 1.0 / P_BK)
 
 
-def _gen_bin(Eb, n_tracks, rng, step_cm):
-    """All tracks of one energy bin; returns (records [n_steps,4] f32, steps per track)."""
-    E = np.full(n_tracks, float(Eb))
+def _gen_bin(Eb, n_tracks, rng, step_cm, nuc=None):
+    """All tracks of one energy bin (Eb a scalar, or one start energy per
+    track); returns (records [n_steps,4] f32, steps per track).  With nuc =
+    (rng, rate per cm, max per track, list), a regular step of a track with
+    more than NUC_MIN_MEV left ends with a nuclear interaction with probability
+    rate * step length: a secondary proton takes a fraction U(0.2, 0.5) of the
+    energy left after the step, leaving at polar angle U(0.05, 0.4) rad and a
+    uniform azimuth, and the primary goes on with the rest; each interaction
+    is appended to the list as (track, step, energy, theta, phi)."""
+    E = np.broadcast_to(np.asarray(Eb, np.float64), (n_tracks,)).copy()
     alive = np.ones(n_tracks, bool)
+    n_sec = np.zeros(n_tracks, np.int64)
     cols = []     # per step: (n_tracks, 4) float32, valid where mask
     masks = []
     while alive.any():
@@ -151,48 +180,100 @@ def _gen_bin(Eb, n_tracks, rng, step_cm):
         cols.append(rec.astype(np.float32))
         masks.append(alive.copy())
         E = np.where(alive, E - dE, E)
+        if nuc is not None:
+            nrng, rate, max_sec, out = nuc
+            u = nrng.random((n_tracks, 4))
+            hit = normal & (E > NUC_MIN_MEV) & (n_sec < max_sec) & (u[:, 0] < rate * step_cm)
+            for t in np.flatnonzero(hit):
+                Es = float(np.float32(E[t] * (0.2 + 0.3 * u[t, 1])))
+                out.append((int(t), len(cols) - 1, Es, 0.05 + 0.35 * u[t, 2], 2.0 * math.pi * u[t, 3]))
+                E[t] -= Es
+                n_sec[t] += 1
         alive = normal & (E > 0.0)
     recs = np.stack(cols, axis=1)            # [n_tracks, n_steps_max, 4]
     mask = np.stack(masks, axis=1)           # [n_tracks, n_steps_max]
     return recs[mask], mask.sum(axis=1)
 
 
-def make_water_track_db(bin_energies_MeV, n_tracks_per_bin, seed, step_cm=STEP_CM):
+NUC_PER_CM = 0.012        # non-elastic nuclear interactions of protons in water, per cm (about 1%/cm)
+NUC_MIN_MEV = 20.0        # no interaction below this energy left
+NUC_MAX_PER_TRACK = 2
+
+
+def make_water_track_db(bin_energies_MeV, n_tracks_per_bin, seed, step_cm=STEP_CM, secondaries=False,
+                        nuc_per_cm=NUC_PER_CM):
     """Synthetic water track database: `n_tracks_per_bin` tracks at each bin energy.
 
-    Deterministic in (seed, bin index).  Bins must be strictly increasing."""
+    Deterministic in (seed, bin index).  Bins must be strictly increasing.
+    With secondaries, nuclear interactions along the primary (see _gen_bin)
+    each start a secondary proton trajectory generated the same way (from its
+    own energy, no interactions of its own); interactions and secondaries draw
+    from streams of their own, so a track without an interaction is the same
+    as in the database without secondaries."""
     bins = np.asarray(bin_energies_MeV, np.float32)
     if bins.ndim != 1 or bins.size == 0 or np.any(np.diff(bins) <= 0):
         raise ValueError("bin energies must be a non-empty increasing list")
     recs, counts = [], []
+    sec_recs, sec_counts, sec_branch, sec_emit, sec_per_track = [], [], [], [], []
     for b, Eb in enumerate(bins):
         rng = np.random.default_rng([int(seed), b])
-        r, c = _gen_bin(float(Eb), int(n_tracks_per_bin), rng, step_cm)
+        inter = []
+        nuc = (np.random.default_rng([int(seed), b, 7]), nuc_per_cm, NUC_MAX_PER_TRACK, inter) if secondaries else None
+        r, c = _gen_bin(float(Eb), int(n_tracks_per_bin), rng, step_cm, nuc)
         recs.append(r)
         counts.append(c)
+        if secondaries:
+            inter.sort(key=lambda x: (x[0], x[1]))
+            per = np.zeros(int(n_tracks_per_bin), np.int64)
+            for t, *_ in inter:
+                per[t] += 1
+            sec_per_track.append(per)
+            if inter:
+                srng = np.random.default_rng([int(seed), b, 8])
+                sr, sc = _gen_bin(np.array([x[2] for x in inter]), len(inter), srng, step_cm)
+                sec_recs.append(sr)
+                sec_counts.append(sc)
+                sec_branch.append(np.array([x[1] for x in inter], np.uint32))
+                sec_emit.append(np.array([[x[3], x[4]] for x in inter], np.float32))
     counts = np.concatenate(counts).astype(np.uint64)
     track_off = np.zeros(counts.size + 1, np.uint64)
     np.cumsum(counts, out=track_off[1:])
     bin_first = (np.arange(bins.size + 1, dtype=np.uint64) * int(n_tracks_per_bin)).astype(np.uint32)
+    sec = None
+    if secondaries:
+        per = np.concatenate(sec_per_track)
+        sec_first = np.zeros(per.size + 1, np.uint32)
+        np.cumsum(per, out=sec_first[1:])
+        sc = np.concatenate(sec_counts).astype(np.uint64) if sec_counts else np.zeros(0, np.uint64)
+        off = np.zeros(sc.size + 1, np.uint64)
+        np.cumsum(sc, out=off[1:])
+        sec = Secondaries(sec_first, off,
+                          np.ascontiguousarray(np.concatenate(sec_recs, axis=0) if sec_recs else np.zeros((0, 4)),
+                                               np.float32),
+                          np.concatenate(sec_branch) if sec_branch else np.zeros(0, np.uint32),
+                          np.concatenate(sec_emit) if sec_emit else np.zeros((0, 2), np.float32))
     return TrackDB(np.ascontiguousarray(np.concatenate(recs, axis=0), np.float32),
-                   track_off, bins, bin_first)
+                   track_off, bins, bin_first, sec)
 
 
 DB_FILE_MAGIC = b"FDCTRKDB"
 _DB_HEADER = np.dtype([("magic", "S8"), ("version", "<u4"), ("n_bins", "<u4"), ("n_tracks", "<u4"),
-                       ("reserved", "<u4"), ("n_steps", "<u8"), ("db_seed", "<u8"), ("physics", "<f8", (8,))])
+                       ("n_sec", "<u4"), ("n_steps", "<u8"), ("db_seed", "<u8"), ("physics", "<f8", (8,))])
 assert _DB_HEADER.itemsize == 104
 
 
 def write_track_db_file(path, db, db_seed=0):
     """Write a track database in the library's file layout: a 104-byte
     little-endian header, then bin_E, bin_first, track_off and the step
-    records, packed."""
+    records, packed.  A database with secondary trajectories is version 2:
+    the header's n_sec, and after the primary steps the secondaries' step
+    count (u64), sec_first, sec_off, branch, emit and their steps."""
     h = np.zeros(1, _DB_HEADER)
     h["magic"] = DB_FILE_MAGIC
-    h["version"] = 1
+    h["version"] = 1 if db.sec is None else 2
     h["n_bins"] = db.n_bins
     h["n_tracks"] = db.n_tracks
+    h["n_sec"] = 0 if db.sec is None else db.sec.n
     h["n_steps"] = db.steps.shape[0]
     h["db_seed"] = int(db_seed)
     h["physics"] = [ALPHA, P_BK, K_BOHR, Z_OVER_A_WATER, X0_WATER, M_PROTON, STEP_CM, 0.0]
@@ -202,24 +283,43 @@ def write_track_db_file(path, db, db_seed=0):
         f.write(np.ascontiguousarray(db.bin_first, "<u4").tobytes())
         f.write(np.ascontiguousarray(db.track_off, "<u8").tobytes())
         f.write(np.ascontiguousarray(db.steps, "<f4").tobytes())
+        if db.sec is not None:
+            s = db.sec
+            st = np.ascontiguousarray(s.steps, "<f4").reshape(-1, 4)
+            f.write(np.array([st.shape[0]], "<u8").tobytes())
+            f.write(np.ascontiguousarray(s.sec_first, "<u4").tobytes())
+            f.write(np.ascontiguousarray(s.off, "<u8").tobytes())
+            f.write(np.ascontiguousarray(s.branch, "<u4").tobytes())
+            f.write(np.ascontiguousarray(s.emit, "<f4").tobytes())
+            f.write(st.tobytes())
 
 
 def read_track_db_file(path):
     """Read a file written by write_track_db_file back into a TrackDB."""
     raw = np.fromfile(path, np.uint8)
     h = raw[:_DB_HEADER.itemsize].view(_DB_HEADER)[0]
-    if bytes(h["magic"]) != DB_FILE_MAGIC or int(h["version"]) != 1:
+    if bytes(h["magic"]) != DB_FILE_MAGIC or int(h["version"]) not in (1, 2):
         raise ValueError("not a track database file")
     nb, nt, ns = int(h["n_bins"]), int(h["n_tracks"]), int(h["n_steps"])
     o = _DB_HEADER.itemsize
-    parts = []
-    for dt, n in (("<f4", nb), ("<u4", nb + 1), ("<u8", nt + 1), ("<f4", 4 * ns)):
+
+    def take(dt, n):
+        nonlocal o
         size = np.dtype(dt).itemsize * n
-        parts.append(raw[o:o + size].view(dt).copy())
+        a = raw[o:o + size].view(dt).copy()
         o += size
+        return a
+    parts = [take(dt, n) for dt, n in (("<f4", nb), ("<u4", nb + 1), ("<u8", nt + 1), ("<f4", 4 * ns))]
+    sec = None
+    if int(h["version"]) == 2:
+        n_sec = int(h["n_sec"])
+        nss = int(take("<u8", 1)[0])
+        first, off, branch = take("<u4", nt + 1), take("<u8", n_sec + 1), take("<u4", n_sec)
+        emit = take("<f4", 2 * n_sec).reshape(n_sec, 2)
+        sec = Secondaries(first, off, take("<f4", 4 * nss).reshape(nss, 4), branch, emit)
     if o != raw.size:
         raise ValueError("track database file size does not match its header")
-    return TrackDB(parts[3].reshape(ns, 4), parts[2], parts[0], parts[1])
+    return TrackDB(parts[3].reshape(ns, 4), parts[2], parts[0], parts[1], sec)
 
 
 def write_phase_space_file(path, particles):

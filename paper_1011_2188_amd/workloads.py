@@ -30,8 +30,8 @@ def water_db(n_tracks=10_000, seed=1011, energy=150.0):
 
 
 @functools.lru_cache(maxsize=4)
-def multi_bin_db(n_tracks=10_000, seed=2188, bins=tuple(DB_BINS_FULL)):
-    return I.make_water_track_db(list(bins), n_tracks, seed)
+def multi_bin_db(n_tracks=10_000, seed=2188, bins=tuple(DB_BINS_FULL), secondaries=False):
+    return I.make_water_track_db(list(bins), n_tracks, seed, secondaries=secondaries)
 
 
 def water_pencil(n_histories=100_000, n_tracks=10_000, depth_vox=64):

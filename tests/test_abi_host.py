@@ -209,6 +209,37 @@ def test_track_db_file_round_trip(ctx, tmp_path):
     assert F.lib().fdc_load_track_db_file(ctx.h, None, None) == F.FDC_E_ARG
 
 
+def test_track_db_file_with_secondaries(ctx, tmp_path):
+    """Version 2 of the file layout carries the secondary trajectories: read
+    back bit for bit, accepted by the library, its secondaries checked like
+    fdc_load_secondaries' arrays; a version-1 file of the same primaries is
+    the same file up to the header's version word and the added section."""
+    db = I.make_water_track_db([100.0, 105.0], 30, seed=4, secondaries=True)
+    s = db.sec
+    path = tmp_path / "db2.bin"
+    I.write_track_db_file(path, db)
+    back = I.read_track_db_file(path)
+    for a in ("sec_first", "off", "steps", "branch", "emit"):
+        assert np.array_equal(getattr(back.sec, a), getattr(s, a)), a
+    assert np.array_equal(back.steps, db.steps)
+    raw = path.read_bytes()
+    v1 = tmp_path / "db1.bin"
+    I.write_track_db_file(v1, I.TrackDB(db.steps, db.track_off, db.bin_E, db.bin_first))
+    r1 = v1.read_bytes()
+    n_tr = db.n_tracks
+    assert len(raw) == len(r1) + 8 + 4 * (n_tr + 1) + 8 * (s.n + 1) + 4 * s.n + 8 * s.n + 16 * s.steps.shape[0]
+    assert raw[:8] == r1[:8] and raw[16:20] == r1[16:20] and raw[24:len(r1)] == r1[24:]
+    ctx.load_track_db_file(path)
+    ctx.load_track_db_file(v1)
+    bad = np.frombuffer(raw, np.uint8).copy()
+    o = len(r1) + 8 + 4 * (n_tr + 1) + 8 * (s.n + 1)            # the branch array
+    bad[o:o + 4] = np.frombuffer(np.uint32(10_000).tobytes(), np.uint8)
+    (tmp_path / "bad2.bin").write_bytes(bad.tobytes())
+    assert "branches past" in _expect(F.FDC_E_FORMAT, ctx.load_track_db_file, tmp_path / "bad2.bin")
+    (tmp_path / "short2.bin").write_bytes(raw[:-16])
+    _expect(F.FDC_E_FORMAT, ctx.load_track_db_file, tmp_path / "short2.bin")
+
+
 def test_phase_space_validation_and_grouping(ctx, tmp_path):
     """Listed protons become one source per energy bin, numbered after the
     plan's spots; bad records and energies outside the bins are refused; the
@@ -276,3 +307,41 @@ def test_beam_device_validation(ctx):
     ctx.add_phase_space(q, ps)
     _expect(F.FDC_E_ARG, ctx.set_spot_device, q, 0, 1, 0)                  # listed protons take no device
     ctx.run_histories([p], 0)
+
+
+def test_secondaries_validation(ctx):
+    db = I.make_water_track_db([100.0, 105.0], 40, seed=2, secondaries=True)
+    s = db.sec
+    assert s.n > 0
+    _expect(F.FDC_E_STATE, ctx.load_secondaries, s)                      # no database yet
+    ctx.load_track_db(db)                                                 # loads its secondaries too
+
+    def bad(**kw):
+        d = dict(sec_first=s.sec_first.copy(), off=s.off.copy(), steps=s.steps.copy(), branch=s.branch.copy(),
+                 emit=s.emit.copy())
+        d.update(kw)
+        return I.Secondaries(**d)
+    j = int(np.flatnonzero(np.diff(s.sec_first.astype(np.int64)))[0])   # a track with a secondary
+    j0 = int(s.sec_first[j])
+    n_steps_j = int(db.track_off[j + 1] - db.track_off[j])
+    br = s.branch.copy(); br[j0] = n_steps_j                              # past the track's last step
+    _expect(F.FDC_E_FORMAT, ctx.load_secondaries, bad(branch=br))
+    em = s.emit.copy(); em[0, 0] = 3.5                                    # polar angle beyond pi
+    _expect(F.FDC_E_FORMAT, ctx.load_secondaries, bad(emit=em))
+    st = s.steps.copy(); st[0, 1] = 200.0                                 # 32-bit split
+    _expect(F.FDC_E_FORMAT, ctx.load_secondaries, bad(steps=st))
+    off = s.off.copy(); off[1] = 0                                        # an empty secondary
+    _expect(F.FDC_E_FORMAT, ctx.load_secondaries, bad(off=off))
+    sf = s.sec_first.copy(); sf[-1] -= 1
+    _expect(F.FDC_E_FORMAT, ctx.load_secondaries, bad(sec_first=sf))
+    # five on one track: more than the walk keeps
+    five = I.Secondaries(np.array([0] + [5] * db.n_tracks, np.uint32), np.arange(6, dtype=np.uint64),
+                         np.tile(np.array([[0.1, 1.0, 0.0, 0.0]], np.float32), (5, 1)), np.zeros(5, np.uint32),
+                         np.zeros((5, 2), np.float32))
+    msg = _expect(F.FDC_E_FORMAT, ctx.load_secondaries, five)
+    assert "at most 4" in msg
+    two = I.Secondaries(np.array([0, 2, 2] + [2] * (db.n_tracks - 2), np.uint32), np.arange(3, dtype=np.uint64),
+                        np.tile(np.array([[0.1, 1.0, 0.0, 0.0]], np.float32), (2, 1)), np.array([3, 1], np.uint32),
+                        np.zeros((2, 2), np.float32))
+    _expect(F.FDC_E_FORMAT, ctx.load_secondaries, two)                   # branch steps out of order
+    ctx.load_secondaries(s)

@@ -57,7 +57,7 @@ def _first_call_inputs():
     ph_b = I.thorax_phantom((40, 56, 32), 0.35, seed=12)
     sp_a = I.spots([[0.3, -0.2, -20.0], [-0.5, 0.4, 20.0], [1.0, 0.0, -20.0]], [[0, 0, 1.0], [0, 0, -1.0], [0, 0, 1.0]],
                    [97.5, 110.0, 102.0], 0.4, 7000)
-    sp_a["n_histories"][2] = 40_000       # more than one ordering chunk: the whole-spot histogram order
+    sp_a["n_histories"][2] = 70_000       # more than four ordering chunks: the whole-spot histogram order
     sp_b = I.spots([[0.0, -20.0, 0.5], [20.0, 0.0, -0.5]], [[0, 1.0, 0], [-1.0, 0, 0]], [100.0, 108.5], 0.3, 5001)
     return (ph_a, sp_a), (ph_b, sp_b)
 

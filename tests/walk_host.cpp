@@ -209,14 +209,14 @@ int main(int argc, char **argv)
         int reason = 0;
         for (uint64_t h = 0; h < cnt[s]; ++h) {
             long long inc = 0, esc = 0;
-            replay_history<false, false>(a, sp, pl, lut.data(), wc, h, 0, inc, esc, sink);
+            replay_history<false, false, false>(a, sp, pl, lut.data(), wc, h, 0, inc, esc, sink);
             incident += inc;
             escaped += esc;
             // the same history once more for its end point
             a.ep_xyz = xyz;
             a.ep_reason = &reason;
             long long i2 = 0, e2_ = 0;
-            replay_history<true, false>(a, sp, pl, lut.data(), wc, h, 0, i2, e2_, NullSink{});
+            replay_history<true, false, false>(a, sp, pl, lut.data(), wc, h, 0, i2, e2_, NullSink{});
             a.ep_xyz = nullptr;
             a.ep_reason = nullptr;
             ep_xyz.insert(ep_xyz.end(), xyz, xyz + 3);
