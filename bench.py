@@ -332,6 +332,9 @@ def cpu_baseline(ph, sp, db, target_s=12.0):
     probe, _, _ = rate(threads, 4)
     per_all = int(max(4, min(int(sp["n_histories"].max()), probe * target_s / len(sp))))
     v_all, n_all, dt_all = rate(threads, per_all)
+    if dt_all < 0.5 * target_s:               # the short probe underestimated the threaded rate
+        per_all = int(max(4, min(int(sp["n_histories"].max()), v_all * target_s / len(sp))))
+        v_all, n_all, dt_all = rate(threads, per_all)
     per_one = int(max(1, min(per_all, v_all / threads * target_s / len(sp))))
     v_one, n_one, dt_one = rate(1, per_one)
     return {"value": v_all, "unit": "histories/s", "cores": threads, "kind": "oracle",
@@ -425,8 +428,21 @@ def main():
 
     # seconds to 2% mean uncertainty (Eq. (2), voxels above Dmax/2), from the last step
     out = {}
+    # the work of one launch counted on the device (untimed, its own run): steps
+    # S, non-vacuum voxel pieces C and flushes G per history, against the
+    # oracle's counts on a sample that the roofline's byte figure uses
     if variance:
-        u0, _, _ = c.mean_uncertainty(plan, dose, var, 0.5, stream=stream)
+        u_step, _, _ = c.mean_uncertainty(plan, dose, var, 0.5, stream=stream)
+    c.reset_plan(plan, stream=stream)
+    c.run_histories([plan], flags | F.FDC_RUN_COUNT_WORK, stream=stream)
+    wk = c.read_work_counts(plan, stream=stream)
+    live = {"S": wk["steps"] / hist_per_step, "C": wk["visits"] / hist_per_step, "G": wk["flushes"] / hist_per_step}
+    out["work_per_history"] = {"device": live, "oracle_sample": COUNTS["thorax"],
+                               "bytes_per_history_device": bytes_per_history(live, variance)}
+    log(f"work per history on the device: S {live['S']:.2f}, C {live['C']:.2f}, G {live['G']:.2f} "
+        f"(oracle sample {COUNTS['thorax']['S']}, {COUNTS['thorax']['C']}, {COUNTS['thorax']['G']})")
+    if variance:
+        u0 = u_step
         n2 = hist_per_step * (u0 / 0.02) ** 2
         out["mean_uncertainty_at_step"] = u0
         out["histories_to_2pct"] = n2

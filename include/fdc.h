@@ -67,7 +67,8 @@ enum {
 /* run flags */
 enum {
     FDC_RUN_VARIANCE = 1u,      /* also tally squared per-visit deposits (Section 2.3)  */
-    FDC_RUN_ROTATE_TRACKS = 2u  /* rotate each re-traced track by a random azimuth      */
+    FDC_RUN_ROTATE_TRACKS = 2u, /* rotate each re-traced track by a random azimuth      */
+    FDC_RUN_COUNT_WORK = 4u     /* debug: count the run's work into the plan's counters */
 };
 
 /* One stored water step (Section 2.2: direction change, length and energy loss
@@ -392,7 +393,19 @@ int fdc_graph_launch(fdc_graph *graph, void *hip_stream);
 /* Wait for the device, then free the graph and its work table. */
 int fdc_graph_destroy(fdc_graph *graph);
 
-/* Zero a plan's tallies and summary (asynchronous).  The history counters keep
+/* The work counters of a plan (a debug aid for the roofline's per-history byte
+ * counts): counts[0] = steps started in the phantom, counts[1] = non-vacuum
+ * voxel pieces (Section 2.3 task 2: a step consumed voxel by voxel), counts[2]
+ * = deposits flushed to the tallies, summed over the plan's runs with
+ * FDC_RUN_COUNT_WORK since it was loaded or last reset.  Such a run takes the
+ * global-atomic kernel (one wave per 64-history unit) whatever the launch
+ * configuration, with tallies bitwise equal to any other run's.  Vacuum
+ * voxels crossed in free flight are not pieces.  Synchronous on hip_stream;
+ * a context without a device reports zeros.  Errors: FDC_E_ARG (NULL, no
+ * such plan), FDC_E_HIP. */
+int fdc_read_work_counts(fdc_ctx *ctx, int32_t plan, uint64_t counts[3], void *hip_stream);
+
+/* Zero a plan's tallies, summary and work counters (asynchronous).  The history counters keep
  * running unless rewind is non-zero, in which case the next run repeats the
  * same histories from h = 0.  Errors: FDC_E_ARG. */
 int fdc_reset_plan(fdc_ctx *ctx, int32_t plan, int rewind, void *hip_stream);

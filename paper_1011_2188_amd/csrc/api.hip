@@ -987,7 +987,7 @@ int fdc_load_phantom(fdc_ctx *ctx, int32_t *plan_out, const int16_t *hu, int nx,
     P.idx = dalloc_n<uint16_t>(ctx, nvox);
     P.E = dalloc_n<unsigned long long>(ctx, nvox);
     P.E2 = dalloc_n<unsigned long long>(ctx, nvox);
-    P.acc = dalloc_n<unsigned long long>(ctx, 4);
+    P.acc = dalloc_n<unsigned long long>(ctx, 8);
     if (!d_hu || !P.idx || !P.E || !P.E2 || !P.acc) {
         dfree(ctx, d_hu); dfree(ctx, P.idx); dfree(ctx, P.E); dfree(ctx, P.E2); dfree(ctx, P.acc);
         return fail(ctx, FDC_E_NOMEM, "phantom: device allocation failed (%zu voxels)", nvox);
@@ -998,7 +998,7 @@ int fdc_load_phantom(fdc_ctx *ctx, int32_t *plan_out, const int16_t *hu, int nx,
     if (e == hipSuccess) e = launch_vacuum_skip(P.idx, ctx->lut, nx, ny, nz, s);
     if (e == hipSuccess) e = hipMemsetAsync(P.E, 0, nvox * 8, s);
     if (e == hipSuccess) e = hipMemsetAsync(P.E2, 0, nvox * 8, s);
-    if (e == hipSuccess) e = hipMemsetAsync(P.acc, 0, 32, s);
+    if (e == hipSuccess) e = hipMemsetAsync(P.acc, 0, 64, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     dfree(ctx, d_hu);
     if (e != hipSuccess) {
@@ -1245,7 +1245,8 @@ int fdc_add_phase_space_file(fdc_ctx *ctx, int32_t plan, const char *path, uint3
 static int validate_run(fdc_ctx *ctx, const int32_t *plans, uint32_t n_plans, uint32_t flags, uint64_t launches)
 {
     if (n_plans && !plans) return fail(ctx, FDC_E_ARG, "run: NULL plan list");
-    if (flags & ~(uint32_t)(FDC_RUN_VARIANCE | FDC_RUN_ROTATE_TRACKS)) return fail(ctx, FDC_E_ARG, "run: unknown flag");
+    if (flags & ~(uint32_t)(FDC_RUN_VARIANCE | FDC_RUN_ROTATE_TRACKS | FDC_RUN_COUNT_WORK))
+        return fail(ctx, FDC_E_ARG, "run: unknown flag");
     if (ctx->n_bins == 0) return fail(ctx, FDC_E_STATE, "run: no track database loaded");
     for (uint32_t i = 0; i < n_plans; ++i)
         if (!valid_plan(ctx, plans[i])) return fail(ctx, FDC_E_ARG, "run: no plan %d", plans[i]);
@@ -1394,6 +1395,14 @@ static int enqueue_transport_kernel(fdc_ctx *ctx, TransportArgs a, uint32_t flag
             kMaxLdsBytes)
         return fail(ctx, FDC_E_ARG, "run: LDS sub-tally of %u slots with the squared-energy tally does not fit",
                     ctx->cfg.tally_slots);
+    if (flags & FDC_RUN_COUNT_WORK) {
+        // the counting kernel: global atomics, one wave per unit, whatever the configuration
+        const unsigned long long g = (a.n_units + wpb - 1) / wpb;
+        if (g > 0x7fffffffull) return fail(ctx, FDC_E_ARG, "run: too many work units for one launch");
+        a.queue = nullptr;
+        HIPCHK(launch_transport(a, wpb, (uint32_t)g, variance, false, s, true));
+        return FDC_OK;
+    }
     const bool persistent = ctx->cfg.tally_slots || ctx->cfg.blocks_per_cu;
     if (persistent) {
         if (!queue) {
@@ -1658,7 +1667,7 @@ int fdc_graph_create(fdc_ctx *ctx, const int32_t *plans, uint32_t n_plans, uint3
         PlanHost &P = ctx->plans[plans[i]];
         e = launch_fill_u64(P.E, P.nvox, 0, s);
         if (e == hipSuccess) e = launch_fill_u64(P.E2, P.nvox, 0, s);
-        if (e == hipSuccess) e = launch_fill_u64(P.acc, 4, 0, s);
+        if (e == hipSuccess) e = launch_fill_u64(P.acc, 8, 0, s);
     }
     if (e == hipSuccess && !items.empty()) {
         TransportArgs a = base_args(ctx);
@@ -1719,6 +1728,21 @@ int fdc_graph_destroy(fdc_graph *g)
     return FDC_OK;
 }
 
+int fdc_read_work_counts(fdc_ctx *ctx, int32_t plan, uint64_t counts[3], void *hip_stream)
+{
+    if (!ctx || !counts) return FDC_E_ARG;
+    if (!valid_plan(ctx, plan)) return fail(ctx, FDC_E_ARG, "work counts: no plan %d", plan);
+    if (ctx->dry) {
+        counts[0] = counts[1] = counts[2] = 0;
+        return FDC_OK;
+    }
+    HIPCHK(hipSetDevice(ctx->device));
+    hipStream_t s = S(hip_stream);
+    HIPCHK(hipMemcpyAsync(counts, ctx->plans[plan].acc + 4, 3 * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return FDC_OK;
+}
+
 int fdc_reset_plan(fdc_ctx *ctx, int32_t plan, int rewind, void *hip_stream)
 {
     if (!ctx) return FDC_E_ARG;
@@ -1729,7 +1753,7 @@ int fdc_reset_plan(fdc_ctx *ctx, int32_t plan, int rewind, void *hip_stream)
         hipStream_t s = S(hip_stream);
         HIPCHK(launch_fill_u64(P.E, P.nvox, 0, s));
         HIPCHK(launch_fill_u64(P.E2, P.nvox, 0, s));
-        HIPCHK(launch_fill_u64(P.acc, 4, 0, s));
+        HIPCHK(launch_fill_u64(P.acc, 8, 0, s));
         if (rewind && !ctx->spots_dirty && !P.spots.empty())
             HIPCHK(launch_fill_u64(ctx->d_hnext + ctx->spot_base[plan], P.spots.size(), 0, s));
     }

@@ -35,7 +35,8 @@ struct DevPlan {
     unsigned long long *E;           // int64 energy tally (two's complement in u64 adds)
     unsigned long long *E2;          // uint64 sum of squared per-visit deposits
     unsigned long long *acc;         // [0] incident, [1] escaped (fixed point), [2] scratch,
-                                     // [3] histories run since the last reset
+                                     // [3] histories run since the last reset, [4..6] work
+                                     // counters (steps, voxel visits, flushes), [7] unused
     const float4 *ps;                // listed protons: (x, y, z, E MeV), (dx, dy, dz, 0) each
     int n[3];
     float vox[3];
@@ -274,7 +275,7 @@ __host__ __device__ inline long long to_fp(float mev)
 
 // kernels' host-side launchers (implemented next to their kernels)
 hipError_t launch_transport(const TransportArgs &a, uint32_t waves_per_block, uint32_t grid_blocks,
-                            bool variance, bool endpoints, hipStream_t s);
+                            bool variance, bool endpoints, hipStream_t s, bool count = false);
 hipError_t launch_transport_lds(const TransportArgs &a, uint32_t waves_per_block, uint32_t grid_blocks,
                                 uint32_t slots, uint32_t units_per_wave, bool variance, uint32_t mode, hipStream_t s);
 size_t lds_tally_bytes(uint32_t slots, bool variance, uint32_t mode);

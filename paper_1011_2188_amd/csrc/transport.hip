@@ -35,6 +35,12 @@ namespace {
 
 constexpr float kInf = __builtin_huge_valf();
 
+// Work of one history (counted with CNT, a debug option): steps started in
+// the phantom, non-vacuum voxel pieces, and deposits flushed to a sink.
+struct WorkCount {
+    uint32_t steps, visits, flushes;
+};
+
 struct Lane {
     int i[3];           // voxel
     float f[3];         // position inside the voxel, voxel units, [0, 1]
@@ -428,10 +434,10 @@ __host__ __device__ inline bool beam_device_pass(const TransportArgs &a, const D
 // and is replayed after the primary (an end-point replay follows the primary
 // only).  Its energy follows that step's in the track's order, so a skip that
 // ends inside it drops it and starts at the next primary step whole.
-template <bool EP, bool LISTED, bool SEC, class Sink>
+template <bool EP, bool LISTED, bool SEC, bool CNT, class Sink>
 __host__ __device__ void replay_history(const TransportArgs &a, const DevSpot &sp, const DevPlan &pl,
                                const float2 *__restrict__ lut, const volatile float *wc, unsigned long long h,
-                               uint32_t slot, long long &inc, long long &esc, const Sink &sink)
+                               uint32_t slot, long long &inc, long long &esc, const Sink &sink, WorkCount &wk)
 {
     // ---- task 1: track, start step, source ---------------------------------
     float4 q0 = make_float4(0.f, 0.f, 0.f, 0.f), q1 = q0;
@@ -649,6 +655,7 @@ __host__ __device__ void replay_history(const TransportArgs &a, const DevSpot &s
         int dep = tau0 > 0.0 ? min(e32, (int)rintf((float)e32 * (tau * inv_w))) : 0;
         float4 next_rec = rec;
         if (k + 1 < kend) next_rec = a.steps[k + 1];
+        if (CNT) ++wk.steps;
         for (;;) {
             const float ef = (float)e32;
             while (tau < w_tot) {
@@ -723,6 +730,7 @@ __host__ __device__ void replay_history(const TransportArgs &a, const DevSpot &s
                 const float tau_n = ends ? w_tot : tau + wb;
                 const float move = ends ? rem * fast_rcp(m.x) : tmin;
                 const bool cross = ends ? (rem == wb) : true;
+                if (CNT) wk.visits += m.x > 0.f ? 1u : 0u;
                 const int cumk = tau_n < w_tot ? min(e32, (int)rintf(ef * (tau_n * inv_w))) : e32;
                 const int piece = cumk - dep;
                 dep = cumk;
@@ -735,6 +743,7 @@ __host__ __device__ void replay_history(const TransportArgs &a, const DevSpot &s
                 if (cross) {
                     if (acc != 0) {
                         sink.add(L.v, (uint32_t)L.i[0], acc);
+                        if (CNT) ++wk.flushes;
                         acc = 0;
                     }
                     const float f_new = (d_ax > 0.f) == out ? 1.f : 0.f;   // exit face when out, else entry face
@@ -785,6 +794,7 @@ __host__ __device__ void replay_history(const TransportArgs &a, const DevSpot &s
             }
             // next stored step (its record and terms were loaded one step ahead)
             if (++k >= kend) break;
+            if (CNT) ++wk.steps;
             rec = next_rec;
             if (k + 1 < kend) next_rec = a.steps[k + 1];
             w_tot = rec.x;
@@ -795,7 +805,10 @@ __host__ __device__ void replay_history(const TransportArgs &a, const DevSpot &s
             g2 = 0.f;
             dep = 0;
         }
-        if (!escaped && acc != 0) sink.add(L.v, (uint32_t)L.i[0], acc);
+        if (!escaped && acc != 0) {
+            sink.add(L.v, (uint32_t)L.i[0], acc);
+            if (CNT) ++wk.flushes;
+        }
         acc = 0;
         if (EP) {                                       // the primary's end
 #pragma unroll
@@ -842,7 +855,7 @@ __device__ inline long long wave_sum(long long x)
     return x;
 }
 
-template <bool EP, bool SEC, class Sink>
+template <bool EP, bool SEC, bool CNT, class Sink>
 __device__ void process_unit(const TransportArgs &a, const float2 *lut, float *wc, unsigned long long unit,
                              uint32_t lane, const Sink &sink)
 {
@@ -869,6 +882,7 @@ __device__ void process_unit(const TransportArgs &a, const float2 *lut, float *w
         valid = h >= h0 && h < h0 + it.n;
     }
     long long inc = 0, esc = 0;
+    WorkCount wk{0u, 0u, 0u};
     // the wave's constants, one per lane 0..11 whether or not the lane has a
     // history (one wave's LDS accesses execute in order, so its later reads
     // see them)
@@ -876,9 +890,9 @@ __device__ void process_unit(const TransportArgs &a, const float2 *lut, float *w
     else if (lane < 12) wc[lane] = pl.inv_vox[lane - 9];
     if (valid) {
         if (sp.kind)                                  // (wave-uniform: a unit is one source's)
-            replay_history<EP, true, SEC>(a, sp, pl, lut, wc, h, (uint32_t)(h - h0), inc, esc, sink);
+            replay_history<EP, true, SEC, CNT>(a, sp, pl, lut, wc, h, (uint32_t)(h - h0), inc, esc, sink, wk);
         else
-            replay_history<EP, false, SEC>(a, sp, pl, lut, wc, h, (uint32_t)(h - h0), inc, esc, sink);
+            replay_history<EP, false, SEC, CNT>(a, sp, pl, lut, wc, h, (uint32_t)(h - h0), inc, esc, sink, wk);
     }
     if (!EP) {
         inc = wave_sum(inc);
@@ -886,6 +900,15 @@ __device__ void process_unit(const TransportArgs &a, const float2 *lut, float *w
         if (lane == 0) {
             if (inc) add_global(pl.acc + 0, (unsigned long long)inc);
             if (esc) add_global(pl.acc + 1, (unsigned long long)esc);
+        }
+        if (CNT) {                                    // the plan's work counters
+            const long long ws = wave_sum((long long)wk.steps), wv = wave_sum((long long)wk.visits),
+                            wf = wave_sum((long long)wk.flushes);
+            if (lane == 0) {
+                add_global(pl.acc + 4, (unsigned long long)ws);
+                add_global(pl.acc + 5, (unsigned long long)wv);
+                add_global(pl.acc + 6, (unsigned long long)wf);
+            }
         }
     }
 }
@@ -909,7 +932,7 @@ __device__ inline unsigned long long scalar_u64(unsigned long long x)
     return ((unsigned long long)hi << 32) | lo;
 }
 
-template <bool VAR, bool EP, bool SEC>
+template <bool VAR, bool EP, bool SEC, bool CNT = false>
 __global__ void __launch_bounds__(1024) transport_kernel(TransportArgs a)
 {
     __shared__ float2 s_lut[kLutSize];
@@ -922,10 +945,10 @@ __global__ void __launch_bounds__(1024) transport_kernel(TransportArgs a)
     if (a.queue == nullptr) {
         const unsigned long long unit = (unsigned long long)blockIdx.x * wpb + wave;
         if (unit < a.n_units) {
-            if (EP) process_unit<EP, SEC>(a, s_lut, s_wc[wave], unit, lane, NullSink{});
+            if (EP) process_unit<EP, SEC, CNT>(a, s_lut, s_wc[wave], unit, lane, NullSink{});
             else {
                 const DevPlan *pl = plan_of_unit(a, unit);
-                process_unit<EP, SEC>(a, s_lut, s_wc[wave], unit, lane, GlobalSink<VAR>{pl->E, pl->E2});
+                process_unit<EP, SEC, CNT>(a, s_lut, s_wc[wave], unit, lane, GlobalSink<VAR>{pl->E, pl->E2});
             }
         }
         return;
@@ -938,10 +961,10 @@ __global__ void __launch_bounds__(1024) transport_kernel(TransportArgs a)
     for (;;) {
         const unsigned long long unit = scalar_u64(atomicAdd(a.queue, lane == 0 ? 1ull : 0ull));
         if (unit >= a.n_units) break;
-        if (EP) process_unit<EP, SEC>(a, s_lut, s_wc[wave], unit, lane, NullSink{});
+        if (EP) process_unit<EP, SEC, CNT>(a, s_lut, s_wc[wave], unit, lane, NullSink{});
         else {
             const DevPlan *pl = plan_of_unit(a, unit);
-            process_unit<EP, SEC>(a, s_lut, s_wc[wave], unit, lane, GlobalSink<VAR>{pl->E, pl->E2});
+            process_unit<EP, SEC, CNT>(a, s_lut, s_wc[wave], unit, lane, GlobalSink<VAR>{pl->E, pl->E2});
         }
     }
 }
@@ -991,10 +1014,10 @@ __global__ void __launch_bounds__(1024) transport_lds_kernel(TransportArgs a, ui
             if (unit >= a.n_units) break;
             const DevPlan *pl = plan_of_unit(a, unit);
             if (CACHE)
-                process_unit<false, SEC>(a, s_lut, s_wc[wave], unit, lane,
+                process_unit<false, SEC, false>(a, s_lut, s_wc[wave], unit, lane,
                                          CacheSink<VAR>{pl->E, pl->E2, pl == tab_pl, s_e, s_e2, slots, vbits, nvox});
             else
-                process_unit<false, SEC>(a, s_lut, s_wc[wave], unit, lane,
+                process_unit<false, SEC, false>(a, s_lut, s_wc[wave], unit, lane,
                                          LdsSink<VAR>{pl->E, pl->E2, pl == tab_pl, s_key, s_e, s_e2, slots - 1});
         }
         __syncthreads();
@@ -1080,7 +1103,7 @@ __global__ void __launch_bounds__(1024) transport_cache_kernel(TransportArgs a, 
         if (base >= n_units) break;
         if (idx < chunk) {
             const unsigned long long unit = base + idx;
-            if (unit < n_units) process_unit<false, SEC>(a, s_lut, s_wc[wave], unit, lane, cs);
+            if (unit < n_units) process_unit<false, SEC, false>(a, s_lut, s_wc[wave], unit, lane, cs);
         } else if (idx == chunk) {
             const unsigned long long nb = scalar_u64(atomicAdd(a.queue, lane == 0 ? (unsigned long long)chunk : 0ull));
             if (lane == 0) atomicExch(&s_chunk, (nb < n_units ? nb : n_units) << 16);
@@ -1098,9 +1121,13 @@ __global__ void __launch_bounds__(1024) transport_cache_kernel(TransportArgs a, 
 
 template <bool SEC>
 hipError_t launch_transport_t(const TransportArgs &a, dim3 grid, dim3 block, bool variance, bool endpoints,
-                              hipStream_t s)
+                              bool count, hipStream_t s)
 {
-    if (endpoints)
+    if (count && variance)
+        hipLaunchKernelGGL((transport_kernel<true, false, SEC, true>), grid, block, 0, s, a);
+    else if (count)
+        hipLaunchKernelGGL((transport_kernel<false, false, SEC, true>), grid, block, 0, s, a);
+    else if (endpoints)
         hipLaunchKernelGGL((transport_kernel<false, true, SEC>), grid, block, 0, s, a);
     else if (variance)
         hipLaunchKernelGGL((transport_kernel<true, false, SEC>), grid, block, 0, s, a);
@@ -1132,12 +1159,12 @@ hipError_t launch_transport_lds_t(const TransportArgs &a, dim3 grid, dim3 block,
 } // namespace
 
 hipError_t launch_transport(const TransportArgs &a, uint32_t waves_per_block, uint32_t grid_blocks,
-                            bool variance, bool endpoints, hipStream_t s)
+                            bool variance, bool endpoints, hipStream_t s, bool count)
 {
     const dim3 block(waves_per_block * kWave);
     const dim3 grid(grid_blocks);
-    return a.secs ? launch_transport_t<true>(a, grid, block, variance, endpoints, s)
-                  : launch_transport_t<false>(a, grid, block, variance, endpoints, s);
+    return a.secs ? launch_transport_t<true>(a, grid, block, variance, endpoints, count, s)
+                  : launch_transport_t<false>(a, grid, block, variance, endpoints, count, s);
 }
 
 size_t lds_tally_bytes(uint32_t slots, bool variance, uint32_t mode)

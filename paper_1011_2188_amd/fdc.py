@@ -23,6 +23,7 @@ FDC_OK, FDC_E_ARG, FDC_E_STATE, FDC_E_NOMEM, FDC_E_HIP, FDC_E_RANGE, FDC_E_FORMA
 FDC_NO_DEVICE = -1
 FDC_RUN_VARIANCE = 1
 FDC_RUN_ROTATE_TRACKS = 2
+FDC_RUN_COUNT_WORK = 4
 ERROR_NAMES = {0: "FDC_OK", -1: "FDC_E_ARG", -2: "FDC_E_STATE", -3: "FDC_E_NOMEM", -4: "FDC_E_HIP",
                -5: "FDC_E_RANGE", -6: "FDC_E_FORMAT", -7: "FDC_E_OVERFLOW"}
 
@@ -31,7 +32,7 @@ EXPORTS = ["fdc_create", "fdc_destroy", "fdc_last_error", "fdc_set_allocator", "
            "fdc_load_track_db", "fdc_load_secondaries", "fdc_load_track_db_file", "fdc_load_phantom", "fdc_add_beam_spots", "fdc_add_phase_space",
            "fdc_add_phase_space_file", "fdc_add_beam_device", "fdc_set_spot_device", "fdc_run_histories",
            "fdc_run_histories_noalloc", "fdc_prepare_run",
-           "fdc_reset_plan", "fdc_compute_dose", "fdc_read_dose_and_variance", "fdc_debug_endpoints",
+           "fdc_reset_plan", "fdc_read_work_counts", "fdc_compute_dose", "fdc_read_dose_and_variance", "fdc_debug_endpoints",
            "fdc_debug_philox", "fdc_debug_material", "fdc_set_launch_config", "fdc_device_cus",
            "fdc_mean_uncertainty", "fdc_batch_uncertainty", "fdc_gamma_index",
            "fdc_graph_create", "fdc_graph_launch", "fdc_graph_destroy",
@@ -101,6 +102,7 @@ def lib():
         "fdc_run_histories_noalloc": (C.c_int, [_P, _P, C.c_uint32, C.c_uint32, _P]),
         "fdc_prepare_run": (C.c_int, [_P]),
         "fdc_reset_plan": (C.c_int, [_P, C.c_int32, C.c_int, _P]),
+        "fdc_read_work_counts": (C.c_int, [_P, C.c_int32, _P, _P]),
         "fdc_compute_dose": (C.c_int, [_P, C.c_int32, _P, _P, _P]),
         "fdc_read_dose_and_variance": (C.c_int, [_P, C.c_int32, _P, _P, _P, _P, C.POINTER(fdc_summary), _P]),
         "fdc_debug_endpoints": (C.c_int, [_P, C.c_int32, C.c_uint32, C.c_uint64, C.c_uint32, C.c_uint32,
@@ -352,6 +354,13 @@ class Context:
 
     def prepare_run(self):
         _check(self.h, lib().fdc_prepare_run(self.h))
+
+    def read_work_counts(self, plan, stream=None):
+        """Steps, non-vacuum voxel pieces and flushes of the plan's runs with
+        FDC_RUN_COUNT_WORK since its last reset."""
+        out = np.zeros(3, np.uint64)
+        _check(self.h, lib().fdc_read_work_counts(self.h, plan, out.ctypes.data, _stream(stream)))
+        return dict(steps=int(out[0]), visits=int(out[1]), flushes=int(out[2]))
 
     def reset_plan(self, plan, rewind=False, stream=None):
         _check(self.h, lib().fdc_reset_plan(self.h, plan, int(bool(rewind)), _stream(stream)))

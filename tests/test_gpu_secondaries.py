@@ -185,3 +185,63 @@ def test_secondaries_from_a_database_file(tmp_path):
         assert a["incident"] == b["incident"] and a["escaped"] == b["escaped"]
     finally:
         c.close()
+
+
+def test_secondaries_with_a_phase_space():
+    """Listed protons (a phase space, each with its own start, direction,
+    energy and frame) on a database with secondaries, against the oracle."""
+    db, ph, _, _ = _case()
+    q = I.synthetic_phase_space(6000, 5, e_mean=107.5, e_sigma=2.0, tail_fraction=0.1, tail_min=101.0,
+                                radius_cm=1.5, source_cm=(0.0, -20.0, 0.0), direction=(0.0, 1.0, 0.0))
+    c = F.Context(0, 1, table=I.HU_TABLE_DEFAULT)
+    try:
+        c.load_track_db(db)
+        c.set_launch_config(**LAUNCHES[1])
+        p = c.load_phantom(ph)
+        n_src = c.add_phase_space(p, q)
+        c.run_histories([p], F.FDC_RUN_VARIANCE)
+        g = c.read_dose_and_variance(p, raw=True)
+        ps = O.phase_space_sources(q["pos_cm"], q["dir"], q["energy_MeV"], db.bin_E, 0)
+        rows = np.zeros(len(ps["count"]), I.SPOT_DTYPE)
+        rows["dir"] = (0.0, 0.0, 1.0)
+        rows["energy_MeV"] = db.bin_E[-1]
+        assert n_src == len(ps["count"]) >= 2
+        o = O.replay(db, ph, rows, h_count=ps["count"], phase_space=ps)
+        assert g["incident"] == o["incident"] and g["deposited"] + g["escaped"] == g["incident"]
+        dose_o, _ = O.dose_and_variance(o["E"], o["E2"], q.size, ph)
+        dmax = dose_o.max()
+        sel = dose_o > 0.1 * dmax
+        assert np.abs(g["dose"] - dose_o)[sel].max() <= 0.005 * dmax
+    finally:
+        c.close()
+
+
+def test_secondaries_in_a_captured_graph():
+    """A captured run (tallies cleared, transport, counters advanced) replayed
+    three times with eager work between the replays: each replay equals the
+    eager run of the same histories bit for bit."""
+    db, ph, sp, devices = _case()
+    c = F.Context(0, 1, table=I.HU_TABLE_DEFAULT)
+    e = F.Context(0, 1, table=I.HU_TABLE_DEFAULT)
+    try:
+        for x in (c, e):
+            x.load_track_db(db)
+            x.set_launch_config(**LAUNCHES[1])
+        p = c.load_phantom(ph)
+        c.add_beam_spots(p, sp)
+        q = e.load_phantom(ph)
+        e.add_beam_spots(q, sp)
+        gr = c.graph_create([p], F.FDC_RUN_VARIANCE)
+        for rep in range(3):
+            gr.launch()
+            torch.cuda.synchronize()
+            a = c.read_dose_and_variance(p, raw=True)
+            e.reset_plan(q)
+            e.run_histories([q], F.FDC_RUN_VARIANCE)
+            b = e.read_dose_and_variance(q, raw=True)
+            assert np.array_equal(a["E"], b["E"]) and np.array_equal(a["E2"], b["E2"]), rep
+            assert a["incident"] == b["incident"] and a["escaped"] == b["escaped"]
+        gr.close()
+    finally:
+        c.close()
+        e.close()

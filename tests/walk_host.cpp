@@ -171,6 +171,7 @@ int main(int argc, char **argv)
     std::vector<unsigned long long> E2(nvox, 0);
     const HostSink sink{&E, &E2, (flags & kFlagVariance) != 0};
     long long incident = 0, escaped = 0;
+    WorkCount work{0u, 0u, 0u};         // steps, voxel pieces and flushes of every history
     std::vector<float> ep_xyz;
     std::vector<int> ep_reason;
     for (uint32_t s = 0; s < n_spots; ++s) {
@@ -209,14 +210,15 @@ int main(int argc, char **argv)
         int reason = 0;
         for (uint64_t h = 0; h < cnt[s]; ++h) {
             long long inc = 0, esc = 0;
-            replay_history<false, false, false>(a, sp, pl, lut.data(), wc, h, 0, inc, esc, sink);
+            replay_history<false, false, false, true>(a, sp, pl, lut.data(), wc, h, 0, inc, esc, sink, work);
             incident += inc;
             escaped += esc;
             // the same history once more for its end point
             a.ep_xyz = xyz;
             a.ep_reason = &reason;
             long long i2 = 0, e2_ = 0;
-            replay_history<true, false, false>(a, sp, pl, lut.data(), wc, h, 0, i2, e2_, NullSink{});
+            WorkCount none{0u, 0u, 0u};
+            replay_history<true, false, false, false>(a, sp, pl, lut.data(), wc, h, 0, i2, e2_, NullSink{}, none);
             a.ep_xyz = nullptr;
             a.ep_reason = nullptr;
             ep_xyz.insert(ep_xyz.end(), xyz, xyz + 3);
@@ -236,6 +238,6 @@ int main(int argc, char **argv)
         std::fwrite(&ep_reason[i], 4, 1, o);
     }
     std::fclose(o);
-    std::printf("%lld %lld\n", incident, escaped);
+    std::printf("%lld %lld %u %u %u\n", incident, escaped, work.steps, work.visits, work.flushes);
     return 0;
 }
