@@ -15,8 +15,7 @@ constexpr uint32_t kFlagVariance = 1u;
 constexpr uint32_t kFlagRotate = 2u;
 constexpr int kMaxTablePts = 64;
 constexpr size_t kMaxLdsBytes = 160 * 1024;   // LDS per workgroup on gfx950
-constexpr int kWaveConst = 16;                 // floats of per-wave constants in LDS
-constexpr size_t kLdsFixedBytes = 64 + 16 * kWaveConst * sizeof(float);   // besides the material table
+constexpr size_t kLdsFixedBytes = 64;          // besides the material table and the tally: the ticket words
 constexpr double kMeVToJ = 1.602176634e-13;
 constexpr double kFpMeV = 1.0 / 16777216.0;   // one fixed-point unit in MeV
 

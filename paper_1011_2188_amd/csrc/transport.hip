@@ -419,10 +419,10 @@ __host__ __device__ inline bool beam_device_pass(const TransportArgs &a, const D
     return true;                                        // the track ended in the compensator
 }
 
-// wc: the wave's constants in LDS, written by process_unit: the spot's field
-// matrix (9 floats, row-major) and the plan's 1 / voxel size (3).  They are
-// read where they are used (volatile, so not hoisted into registers that
-// would stay live across the walk).
+// wc: the wave's constants, the spot's field matrix (9 floats, row-major) and
+// the plan's 1 / voxel size (3), as values known to be the same in every lane
+// of the wave (they live in scalar registers, read at step ends without a
+// memory access).
 // LISTED: the source is a list of protons (Section 2.3, a phase space read from
 // a file): history h is the source's proton h mod count, which brings its own
 // start point, direction (and with it the frame of the deflections, kept per
@@ -436,7 +436,7 @@ __host__ __device__ inline bool beam_device_pass(const TransportArgs &a, const D
 // ends inside it drops it and starts at the next primary step whole.
 template <bool EP, bool LISTED, bool SEC, bool CNT, class Sink>
 __host__ __device__ void replay_history(const TransportArgs &a, const DevSpot &sp, const DevPlan &pl,
-                               const float2 *__restrict__ lut, const volatile float *wc, unsigned long long h,
+                               const float2 *__restrict__ lut, const float *wc, unsigned long long h,
                                uint32_t slot, long long &inc, long long &esc, const Sink &sink, WorkCount &wk)
 {
     // ---- task 1: track, start step, source ---------------------------------
@@ -848,6 +848,13 @@ __host__ __device__ void replay_history(const TransportArgs &a, const DevSpot &s
     esc = I_h - hdep;                               // escaped, or deposited upstream (up), or 0
 }
 
+// a value the same in every lane, as the first active lane's (so the compiler
+// keeps it in a scalar register)
+__device__ inline float uniform_f(float x)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, x)));
+}
+
 __device__ inline long long wave_sum(long long x)
 {
 #pragma unroll
@@ -856,7 +863,7 @@ __device__ inline long long wave_sum(long long x)
 }
 
 template <bool EP, bool SEC, bool CNT, class Sink>
-__device__ void process_unit(const TransportArgs &a, const float2 *lut, float *wc, unsigned long long unit,
+__device__ void process_unit(const TransportArgs &a, const float2 *lut, unsigned long long unit,
                              uint32_t lane, const Sink &sink)
 {
     // the work item holding this unit: largest i with items[i].unit0 <= unit
@@ -883,11 +890,12 @@ __device__ void process_unit(const TransportArgs &a, const float2 *lut, float *w
     }
     long long inc = 0, esc = 0;
     WorkCount wk{0u, 0u, 0u};
-    // the wave's constants, one per lane 0..11 whether or not the lane has a
-    // history (one wave's LDS accesses execute in order, so its later reads
-    // see them)
-    if (lane < 9) wc[lane] = sp.m[lane];
-    else if (lane < 12) wc[lane] = pl.inv_vox[lane - 9];
+    // the wave's constants (a unit is one source's: the same in every lane)
+    float wc[12];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) wc[q] = uniform_f(sp.m[q]);
+#pragma unroll
+    for (int q = 0; q < 3; ++q) wc[9 + q] = uniform_f(pl.inv_vox[q]);
     if (valid) {
         if (sp.kind)                                  // (wave-uniform: a unit is one source's)
             replay_history<EP, true, SEC, CNT>(a, sp, pl, lut, wc, h, (uint32_t)(h - h0), inc, esc, sink, wk);
@@ -936,7 +944,6 @@ template <bool VAR, bool EP, bool SEC, bool CNT = false>
 __global__ void __launch_bounds__(1024) transport_kernel(TransportArgs a)
 {
     __shared__ float2 s_lut[kLutSize];
-    __shared__ float s_wc[16][kWaveConst];
     for (int i = threadIdx.x; i < kLutSize; i += blockDim.x) s_lut[i] = a.lut[i];
     __syncthreads();
     const uint32_t lane = threadIdx.x & (kWave - 1);
@@ -945,10 +952,10 @@ __global__ void __launch_bounds__(1024) transport_kernel(TransportArgs a)
     if (a.queue == nullptr) {
         const unsigned long long unit = (unsigned long long)blockIdx.x * wpb + wave;
         if (unit < a.n_units) {
-            if (EP) process_unit<EP, SEC, CNT>(a, s_lut, s_wc[wave], unit, lane, NullSink{});
+            if (EP) process_unit<EP, SEC, CNT>(a, s_lut, unit, lane, NullSink{});
             else {
                 const DevPlan *pl = plan_of_unit(a, unit);
-                process_unit<EP, SEC, CNT>(a, s_lut, s_wc[wave], unit, lane, GlobalSink<VAR>{pl->E, pl->E2});
+                process_unit<EP, SEC, CNT>(a, s_lut, unit, lane, GlobalSink<VAR>{pl->E, pl->E2});
             }
         }
         return;
@@ -961,10 +968,10 @@ __global__ void __launch_bounds__(1024) transport_kernel(TransportArgs a)
     for (;;) {
         const unsigned long long unit = scalar_u64(atomicAdd(a.queue, lane == 0 ? 1ull : 0ull));
         if (unit >= a.n_units) break;
-        if (EP) process_unit<EP, SEC, CNT>(a, s_lut, s_wc[wave], unit, lane, NullSink{});
+        if (EP) process_unit<EP, SEC, CNT>(a, s_lut, unit, lane, NullSink{});
         else {
             const DevPlan *pl = plan_of_unit(a, unit);
-            process_unit<EP, SEC, CNT>(a, s_lut, s_wc[wave], unit, lane, GlobalSink<VAR>{pl->E, pl->E2});
+            process_unit<EP, SEC, CNT>(a, s_lut, unit, lane, GlobalSink<VAR>{pl->E, pl->E2});
         }
     }
 }
@@ -981,7 +988,6 @@ template <bool VAR, bool CACHE, bool SEC>
 __global__ void __launch_bounds__(1024) transport_lds_kernel(TransportArgs a, uint32_t slots, uint32_t upw)
 {
     __shared__ float2 s_lut[kLutSize];
-    __shared__ float s_wc[16][kWaveConst];
     __shared__ unsigned long long s_claim;
     extern __shared__ unsigned long long s_dyn[];
     unsigned long long *s_e = s_dyn;
@@ -1014,10 +1020,10 @@ __global__ void __launch_bounds__(1024) transport_lds_kernel(TransportArgs a, ui
             if (unit >= a.n_units) break;
             const DevPlan *pl = plan_of_unit(a, unit);
             if (CACHE)
-                process_unit<false, SEC, false>(a, s_lut, s_wc[wave], unit, lane,
+                process_unit<false, SEC, false>(a, s_lut, unit, lane,
                                          CacheSink<VAR>{pl->E, pl->E2, pl == tab_pl, s_e, s_e2, slots, vbits, nvox});
             else
-                process_unit<false, SEC, false>(a, s_lut, s_wc[wave], unit, lane,
+                process_unit<false, SEC, false>(a, s_lut, unit, lane,
                                          LdsSink<VAR>{pl->E, pl->E2, pl == tab_pl, s_key, s_e, s_e2, slots - 1});
         }
         __syncthreads();
@@ -1072,7 +1078,6 @@ template <bool VAR, bool SEC>
 __global__ void __launch_bounds__(1024) transport_cache_kernel(TransportArgs a, uint32_t slots, uint32_t chunk)
 {
     __shared__ float2 s_lut[kLutSize];
-    __shared__ float s_wc[16][kWaveConst];
     __shared__ unsigned long long s_chunk;
     extern __shared__ unsigned long long s_dyn[];
     unsigned long long *s_e = s_dyn;
@@ -1103,7 +1108,7 @@ __global__ void __launch_bounds__(1024) transport_cache_kernel(TransportArgs a, 
         if (base >= n_units) break;
         if (idx < chunk) {
             const unsigned long long unit = base + idx;
-            if (unit < n_units) process_unit<false, SEC, false>(a, s_lut, s_wc[wave], unit, lane, cs);
+            if (unit < n_units) process_unit<false, SEC, false>(a, s_lut, unit, lane, cs);
         } else if (idx == chunk) {
             const unsigned long long nb = scalar_u64(atomicAdd(a.queue, lane == 0 ? (unsigned long long)chunk : 0ull));
             if (lane == 0) atomicExch(&s_chunk, (nb < n_units ? nb : n_units) << 16);

@@ -150,8 +150,8 @@ def test_launch_config_validation(ctx):
     _expect(F.FDC_E_ARG, ctx.set_launch_config, 16, 1, 3000, 2)
     _expect(F.FDC_E_ARG, ctx.set_launch_config, 16, 1, 128, 2)
     ctx.set_launch_config(16, 1, 8064, 2, 1)
-    ctx.set_launch_config(16, 1, 16192, 2, 1)          # fits with the energy tally alone
-    _expect(F.FDC_E_ARG, ctx.set_launch_config, 16, 1, 16256, 2, 1)
+    ctx.set_launch_config(16, 1, 16320, 2, 1)          # fits with the energy tally alone
+    _expect(F.FDC_E_ARG, ctx.set_launch_config, 16, 1, 16384, 2, 1)
     _expect(F.FDC_E_ARG, ctx.set_launch_config, 16, 1, 8100, 2, 1)
     ctx.set_launch_config(16, 1, 8064, 1, 2)
     _expect(F.FDC_E_ARG, ctx.set_launch_config, 16, 1, 4096, 2, 3)
