@@ -393,6 +393,26 @@ int fdc_graph_launch(fdc_graph *graph, void *hip_stream);
 /* Wait for the device, then free the graph and its work table. */
 int fdc_graph_destroy(fdc_graph *graph);
 
+/* Checkpoint and resume of a plan: its tallies (E, E2), summary (incident,
+ * escaped, histories run) and each source's next-history counter, as one
+ * host buffer of fdc_plan_state_bytes bytes (a 48-byte header {char
+ * magic[8] = "FDCSTATE"; uint32 version = 1, var_complete; uint64 nvox,
+ * n_sources, n_hist, reserved}, the summary words (8 x uint64), the counters
+ * (uint64 per source) and E, E2 (uint64 per voxel), little-endian).  Random
+ * numbers are keyed by counters and the tallies are integers, so a plan
+ * restored into a context with the same database, seed, phantom and sources
+ * continues exactly as the saved run would have: run(N), save, restore
+ * elsewhere, run(N) equals run(2N) bit for bit.  Save and restore are
+ * synchronous on hip_stream (order them after the runs they cover on the same
+ * stream); the caller owns buf.  A context without a device saves zero
+ * tallies and restores the counters only.  Errors: FDC_E_ARG (NULL, no such
+ * plan, a save buffer of the wrong size), FDC_E_FORMAT (restore: bad magic or
+ * version, a voxel or source count other than the plan's, a size that does
+ * not match), FDC_E_HIP. */
+int fdc_plan_state_bytes(fdc_ctx *ctx, int32_t plan, uint64_t *bytes);
+int fdc_save_plan_state(fdc_ctx *ctx, int32_t plan, void *buf, uint64_t bytes, void *hip_stream);
+int fdc_restore_plan_state(fdc_ctx *ctx, int32_t plan, const void *buf, uint64_t bytes, void *hip_stream);
+
 /* The work counters of a plan (a debug aid for the roofline's per-history byte
  * counts): counts[0] = steps started in the phantom, counts[1] = non-vacuum
  * voxel pieces (Section 2.3 task 2: a step consumed voxel by voxel), counts[2]

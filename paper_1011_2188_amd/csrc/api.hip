@@ -1728,6 +1728,105 @@ int fdc_graph_destroy(fdc_graph *g)
     return FDC_OK;
 }
 
+// A plan's saved state: this header, then acc[8] (u64), the next-history
+// counter of each source (u64), E and E2 (u64 per voxel).
+namespace {
+struct PlanStateHeader {
+    char magic[8];                   // "FDCSTATE"
+    uint32_t version;                // 1
+    uint32_t var_complete;           // every history so far tallied its squares
+    uint64_t nvox, n_sources, n_hist, reserved;
+};
+static_assert(sizeof(PlanStateHeader) == 48, "plan state header layout");
+
+uint64_t plan_state_bytes(const PlanHost &P)
+{
+    return sizeof(PlanStateHeader) + 8 * 8 + 8 * (uint64_t)P.spots.size() + 16 * (uint64_t)P.nvox;
+}
+} // namespace
+
+int fdc_plan_state_bytes(fdc_ctx *ctx, int32_t plan, uint64_t *bytes)
+{
+    if (!ctx || !bytes) return FDC_E_ARG;
+    if (!valid_plan(ctx, plan)) return fail(ctx, FDC_E_ARG, "state: no plan %d", plan);
+    *bytes = plan_state_bytes(ctx->plans[plan]);
+    return FDC_OK;
+}
+
+int fdc_save_plan_state(fdc_ctx *ctx, int32_t plan, void *buf, uint64_t bytes, void *hip_stream)
+{
+    if (!ctx || !buf) return FDC_E_ARG;
+    if (!valid_plan(ctx, plan)) return fail(ctx, FDC_E_ARG, "state: no plan %d", plan);
+    PlanHost &P = ctx->plans[plan];
+    if (bytes != plan_state_bytes(P))
+        return fail(ctx, FDC_E_ARG, "state: buffer of %llu bytes, the plan's state takes %llu",
+                    (unsigned long long)bytes, (unsigned long long)plan_state_bytes(P));
+    unsigned char *o = (unsigned char *)buf;
+    PlanStateHeader h{};
+    std::memcpy(h.magic, "FDCSTATE", 8);
+    h.version = 1;
+    h.var_complete = P.var_complete ? 1u : 0u;
+    h.nvox = P.nvox;
+    h.n_sources = P.spots.size();
+    h.n_hist = P.n_hist;
+    std::memcpy(o, &h, sizeof h);
+    o += sizeof h;
+    unsigned char *acc = o;
+    o += 64;
+    std::memcpy(o, P.h_next.data(), 8 * P.h_next.size());
+    o += 8 * P.h_next.size();
+    if (ctx->dry) {                           // no tallies without a device
+        std::memset(acc, 0, 64);
+        std::memset(o, 0, 16 * P.nvox);
+        return FDC_OK;
+    }
+    HIPCHK(hipSetDevice(ctx->device));
+    hipStream_t s = S(hip_stream);
+    HIPCHK(hipMemcpyAsync(acc, P.acc, 64, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(o, P.E, 8 * P.nvox, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(o + 8 * P.nvox, P.E2, 8 * P.nvox, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return FDC_OK;
+}
+
+int fdc_restore_plan_state(fdc_ctx *ctx, int32_t plan, const void *buf, uint64_t bytes, void *hip_stream)
+{
+    if (!ctx || !buf) return FDC_E_ARG;
+    if (!valid_plan(ctx, plan)) return fail(ctx, FDC_E_ARG, "state: no plan %d", plan);
+    PlanHost &P = ctx->plans[plan];
+    PlanStateHeader h;
+    if (bytes < sizeof h) return fail(ctx, FDC_E_FORMAT, "state: short buffer");
+    std::memcpy(&h, buf, sizeof h);
+    if (std::memcmp(h.magic, "FDCSTATE", 8) != 0 || h.version != 1)
+        return fail(ctx, FDC_E_FORMAT, "state: bad magic or version");
+    if (h.nvox != P.nvox || h.n_sources != P.spots.size())
+        return fail(ctx, FDC_E_FORMAT, "state: saved for %llu voxels and %llu sources, the plan has %llu and %llu",
+                    (unsigned long long)h.nvox, (unsigned long long)h.n_sources, (unsigned long long)P.nvox,
+                    (unsigned long long)P.spots.size());
+    if (bytes != plan_state_bytes(P)) return fail(ctx, FDC_E_FORMAT, "state: size does not match its header");
+    const unsigned char *in = (const unsigned char *)buf + sizeof h;
+    const unsigned char *acc = in;
+    in += 64;
+    std::vector<uint64_t> hn(P.spots.size());
+    std::memcpy(hn.data(), in, 8 * hn.size());
+    in += 8 * hn.size();
+    if (!ctx->dry) {
+        HIPCHK(hipSetDevice(ctx->device));
+        hipStream_t s = S(hip_stream);
+        HIPCHK(hipMemcpyAsync(P.acc, acc, 64, hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemcpyAsync(P.E, in, 8 * P.nvox, hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemcpyAsync(P.E2, in + 8 * P.nvox, 8 * P.nvox, hipMemcpyHostToDevice, s));
+        if (!ctx->spots_dirty && !hn.empty())
+            HIPCHK(hipMemcpyAsync(ctx->d_hnext + ctx->spot_base[plan], hn.data(), 8 * hn.size(),
+                                  hipMemcpyHostToDevice, s));
+        HIPCHK(hipStreamSynchronize(s));
+    }
+    P.h_next = hn;
+    P.n_hist = h.n_hist;
+    P.var_complete = h.var_complete != 0;
+    return FDC_OK;
+}
+
 int fdc_read_work_counts(fdc_ctx *ctx, int32_t plan, uint64_t counts[3], void *hip_stream)
 {
     if (!ctx || !counts) return FDC_E_ARG;

@@ -32,7 +32,8 @@ EXPORTS = ["fdc_create", "fdc_destroy", "fdc_last_error", "fdc_set_allocator", "
            "fdc_load_track_db", "fdc_load_secondaries", "fdc_load_track_db_file", "fdc_load_phantom", "fdc_add_beam_spots", "fdc_add_phase_space",
            "fdc_add_phase_space_file", "fdc_add_beam_device", "fdc_set_spot_device", "fdc_run_histories",
            "fdc_run_histories_noalloc", "fdc_prepare_run",
-           "fdc_reset_plan", "fdc_read_work_counts", "fdc_compute_dose", "fdc_read_dose_and_variance", "fdc_debug_endpoints",
+           "fdc_reset_plan", "fdc_read_work_counts", "fdc_plan_state_bytes", "fdc_save_plan_state",
+           "fdc_restore_plan_state", "fdc_compute_dose", "fdc_read_dose_and_variance", "fdc_debug_endpoints",
            "fdc_debug_philox", "fdc_debug_material", "fdc_set_launch_config", "fdc_device_cus",
            "fdc_mean_uncertainty", "fdc_batch_uncertainty", "fdc_gamma_index",
            "fdc_graph_create", "fdc_graph_launch", "fdc_graph_destroy",
@@ -103,6 +104,9 @@ def lib():
         "fdc_prepare_run": (C.c_int, [_P]),
         "fdc_reset_plan": (C.c_int, [_P, C.c_int32, C.c_int, _P]),
         "fdc_read_work_counts": (C.c_int, [_P, C.c_int32, _P, _P]),
+        "fdc_plan_state_bytes": (C.c_int, [_P, C.c_int32, _P]),
+        "fdc_save_plan_state": (C.c_int, [_P, C.c_int32, _P, C.c_uint64, _P]),
+        "fdc_restore_plan_state": (C.c_int, [_P, C.c_int32, _P, C.c_uint64, _P]),
         "fdc_compute_dose": (C.c_int, [_P, C.c_int32, _P, _P, _P]),
         "fdc_read_dose_and_variance": (C.c_int, [_P, C.c_int32, _P, _P, _P, _P, C.POINTER(fdc_summary), _P]),
         "fdc_debug_endpoints": (C.c_int, [_P, C.c_int32, C.c_uint32, C.c_uint64, C.c_uint32, C.c_uint32,
@@ -354,6 +358,18 @@ class Context:
 
     def prepare_run(self):
         _check(self.h, lib().fdc_prepare_run(self.h))
+
+    def save_plan_state(self, plan, stream=None):
+        """The plan's state (tallies, summary, history counters) as bytes."""
+        n = C.c_uint64()
+        _check(self.h, lib().fdc_plan_state_bytes(self.h, plan, C.byref(n)))
+        buf = np.empty(n.value, np.uint8)
+        _check(self.h, lib().fdc_save_plan_state(self.h, plan, buf.ctypes.data, buf.size, _stream(stream)))
+        return buf.tobytes()
+
+    def restore_plan_state(self, plan, state, stream=None):
+        buf = np.frombuffer(state, np.uint8)
+        _check(self.h, lib().fdc_restore_plan_state(self.h, plan, buf.ctypes.data, buf.size, _stream(stream)))
 
     def read_work_counts(self, plan, stream=None):
         """Steps, non-vacuum voxel pieces and flushes of the plan's runs with

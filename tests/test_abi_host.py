@@ -345,3 +345,35 @@ def test_secondaries_validation(ctx):
                         np.zeros((2, 2), np.float32))
     _expect(F.FDC_E_FORMAT, ctx.load_secondaries, two)                   # branch steps out of order
     ctx.load_secondaries(s)
+
+
+def test_plan_state_format_and_checks(ctx):
+    """The checkpoint buffer: header, summary words, counters, tallies; a
+    context without a device saves zero tallies and its counters, and restores
+    the counters; damaged or mismatched buffers are refused."""
+    ctx.load_track_db(_db())
+    p = ctx.load_phantom(I.water_phantom((4, 4, 4), 0.5))
+    ctx.add_beam_spots(p, I.spots([[0, 0, -5]] * 3, [[0, 0, 1]] * 3, [101.0] * 3, 0.3, [10, 20, 30]))
+    ctx.run_histories([p], F.FDC_RUN_VARIANCE)
+    st = ctx.save_plan_state(p)
+    assert len(st) == 48 + 64 + 8 * 3 + 16 * 64
+    assert st[:8] == b"FDCSTATE"
+    hdr = np.frombuffer(st[:48], np.dtype([("m", "S8"), ("v", "<u4"), ("vc", "<u4"), ("nvox", "<u8"),
+                                           ("ns", "<u8"), ("nh", "<u8"), ("r", "<u8")]))[0]
+    assert hdr["v"] == 1 and hdr["vc"] == 1 and hdr["nvox"] == 64 and hdr["ns"] == 3 and hdr["nh"] == 60
+    assert list(np.frombuffer(st[112:136], "<u8")) == [10, 20, 30]
+    q = ctx.load_phantom(I.water_phantom((4, 4, 4), 0.5))
+    ctx.add_beam_spots(q, I.spots([[0, 0, -5]] * 3, [[0, 0, 1]] * 3, [101.0] * 3, 0.3, [10, 20, 30]))
+    ctx.restore_plan_state(q, st)
+    assert ctx.save_plan_state(q) == st                                   # the counters came along
+    bad = bytearray(st)
+    bad[0:8] = b"XXXXXXXX"
+    assert "magic" in _expect(F.FDC_E_FORMAT, ctx.restore_plan_state, q, bytes(bad))
+    _expect(F.FDC_E_FORMAT, ctx.restore_plan_state, q, st[:-8])
+    r = ctx.load_phantom(I.water_phantom((4, 4, 8), 0.5))
+    ctx.add_beam_spots(r, I.spots([[0, 0, -5]] * 3, [[0, 0, 1]] * 3, [101.0] * 3, 0.3, 10))
+    assert "voxels" in _expect(F.FDC_E_FORMAT, ctx.restore_plan_state, r, st)
+    n = F.C.c_uint64()
+    assert F.lib().fdc_plan_state_bytes(ctx.h, p, F.C.byref(n)) == F.FDC_OK and n.value == len(st)
+    buf = np.zeros(len(st) - 1, np.uint8)
+    assert F.lib().fdc_save_plan_state(ctx.h, p, buf.ctypes.data, buf.size, None) == F.FDC_E_ARG
