@@ -1348,8 +1348,9 @@ static int enqueue_source_order(fdc_ctx *ctx, const WorkItem *d_items, const std
 {
     unsigned long long hw = 0;
     const bool large = large_items(items, &hw);
+    const OrderTracks ot{ctx->bin_first, ctx->n_sec ? ctx->sec_first : nullptr, ctx->R};
     HIPCHK(launch_source_order(d_items, (uint32_t)items.size(), n_chunks, units, ctx->d_spots, ctx->d_hnext,
-                               (uint32_t)ctx->seed, (uint32_t)(ctx->seed >> 32), order, hist, hw, large, s));
+                               (uint32_t)ctx->seed, (uint32_t)(ctx->seed >> 32), order, hist, hw, large, ot, s));
     return FDC_OK;
 }
 
@@ -1541,9 +1542,10 @@ int fdc_run_histories_noalloc(fdc_ctx *ctx, const int32_t *plans, uint32_t n_pla
                 large |= sp.n_histories > kOrderWholeSpot;
             }
         // (n histories <= 64 units: the histograms fit their region)
+        const OrderTracks ot{ctx->bin_first, ctx->n_sec ? ctx->sec_first : nullptr, ctx->R};
         HIPCHK(launch_source_order(d_items, (uint32_t)n_items, (uint32_t)chunks, units, ctx->d_spots, ctx->d_hnext,
                                    (uint32_t)ctx->seed, (uint32_t)(ctx->seed >> 32), d_order, d_hist,
-                                   order_hist_words(hist, n_items), large, s));
+                                   order_hist_words(hist, n_items), large, ot, s));
         a.order = d_order;
     }
     rc = enqueue_transport_kernel(ctx, a, flags, s, one_plan(plans, n_plans), queue);

@@ -295,10 +295,17 @@ hipError_t launch_dose(const uint16_t *idx, const unsigned long long *E, const u
 // launches (fill of the per-unit lane table, one workgroup per chunk; with
 // `large`, the whole-item histograms of the items of more than one chunk, in
 // hist: hist_words = order_hist_words(...) counters)
+// what the start-position order needs to tell histories whose track has secondary
+// trajectories (sec_first null: the database has none)
+struct OrderTracks {
+    const uint32_t *bin_first;
+    const uint32_t *sec_first;
+    uint32_t R;
+};
 hipError_t launch_source_order(const WorkItem *items, uint32_t n_items, uint32_t n_chunks, unsigned long long n_units,
                                const DevSpot *spots, const unsigned long long *hnext, uint32_t seed_lo,
                                uint32_t seed_hi, uint32_t *order, uint32_t *hist, unsigned long long hist_words,
-                               bool large, hipStream_t s);
+                               bool large, const OrderTracks &tracks, hipStream_t s);
 // counters the whole-item histograms of a run of n histories in n_items items need
 __host__ __device__ inline unsigned long long order_hist_words(unsigned long long n, unsigned long long n_items)
 {

@@ -28,6 +28,11 @@
 //    the chunks.  The histogram of item i starts at first_i / 16 + i (first_i:
 //    the item's first history among the run's), so a run needs at most
 //    n / 16 + items + 1 counters.
+// With secondary trajectories in the database, the histories whose track has
+// any come after those whose track has none, each group in Morton order at
+// half the spatial resolution (the top bit of the key): a wave replays its
+// primaries and then its secondaries, so a wave of which only some lanes
+// have secondaries would idle the others meanwhile.
 // A fixed number of launches, so the sequence can be captured in a graph.
 // Within a cell the order follows the atomics and may differ between runs;
 // tallies cannot.
@@ -68,6 +73,29 @@ __device__ inline uint32_t start_cell(const DevSpot &sp, unsigned long long h, u
     return spread((uint32_t)qx) | (spread((uint32_t)qy) << 1);
 }
 
+// 1 when the history's track has secondary trajectories (the track drawn as the walk draws it)
+__device__ inline uint32_t has_secondaries(const DevSpot &sp, unsigned long long h, const OrderTracks &ot,
+                                           uint32_t seed_lo, uint32_t seed_hi)
+{
+    const unsigned long long c = h / ot.R;
+    const uint4 xt = philox4x32_10(make_uint4((uint32_t)c, (uint32_t)(c >> 32), sp.spot, (sp.plan << 4) | kTagTrack),
+                                   seed_lo, seed_hi);
+    const uint32_t first = ot.bin_first[sp.bin];
+    const uint32_t nb = ot.bin_first[sp.bin + 1] - first;
+    const uint32_t t = first + (uint32_t)(((uint64_t)xt.x * nb) >> 32);
+    return ot.sec_first[t + 1] > ot.sec_first[t] ? 1u : 0u;
+}
+
+// the sort key of a history among 4^hb bins (at least 2 with secondaries)
+__device__ inline uint32_t order_key(const DevSpot &sp, unsigned long long h, uint32_t hb, const OrderTracks &ot,
+                                     uint32_t seed_lo, uint32_t seed_hi)
+{
+    const uint32_t cell = start_cell(sp, h, hb, seed_lo, seed_hi);
+    if (!ot.sec_first) return cell;
+    const uint32_t sec = has_secondaries(sp, h, ot, seed_lo, seed_hi);
+    return hb ? ((cell >> 1) | (sec << (2 * hb - 1))) : sec;
+}
+
 // the item holding chunk c: largest i with items[i].chunk0 <= c
 __device__ inline uint32_t item_of_chunk(const WorkItem *items, uint32_t n_items, uint32_t c)
 {
@@ -93,7 +121,8 @@ __global__ void __launch_bounds__(kThreads) order_large_kernel(const WorkItem *_
                                                                const DevSpot *__restrict__ spots,
                                                                const unsigned long long *__restrict__ hnext,
                                                                uint32_t seed_lo, uint32_t seed_hi,
-                                                               uint32_t *__restrict__ hist, uint32_t *__restrict__ order)
+                                                               uint32_t *__restrict__ hist, uint32_t *__restrict__ order,
+                                                               OrderTracks ot)
 {
     const uint32_t i = item_of_chunk(items, n_items, blockIdx.x);
     const WorkItem it = items[i];
@@ -106,7 +135,7 @@ __global__ void __launch_bounds__(kThreads) order_large_kernel(const WorkItem *_
     uint32_t *h = hist + (it.first >> 4) + i;
     const unsigned long long hbase = it.h0 + (hnext ? hnext[it.gspot] : 0ull) + j0;
     for (uint32_t e = threadIdx.x; e < len; e += kThreads) {
-        const uint32_t cell = start_cell(sp, hbase + e, hb, seed_lo, seed_hi);
+        const uint32_t cell = order_key(sp, hbase + e, hb, ot, seed_lo, seed_hi);
         if (PLACE) {
             const unsigned long long p = atomicAdd(h + cell, 1u);
             order[(it.unit0 + p / kWave) * kWave + (p % kWave)] = (uint32_t)(j0 + e);
@@ -154,7 +183,7 @@ __global__ void __launch_bounds__(kThreads) order_chunk_kernel(const WorkItem *_
                                                                const DevSpot *__restrict__ spots,
                                                                const unsigned long long *__restrict__ hnext,
                                                                uint32_t seed_lo, uint32_t seed_hi,
-                                                               uint32_t *__restrict__ order)
+                                                               uint32_t *__restrict__ order, OrderTracks ot)
 {
     __shared__ uint32_t s_cnt[1u << (2 * kMaxHalfBits)];
     __shared__ uint32_t s_wave[kThreads / kWave];
@@ -168,7 +197,7 @@ __global__ void __launch_bounds__(kThreads) order_chunk_kernel(const WorkItem *_
     // about four histories per cell: 4^hb <= len / 4
     uint32_t hb = 0;
     while (hb < kMaxHalfBits && (4u << (2 * (hb + 1))) <= len) ++hb;
-    const uint32_t nbins = 1u << (2 * hb);
+    const uint32_t nbins = ot.sec_first && hb == 0 ? 2u : 1u << (2 * hb);
     const unsigned long long hbase = it.h0 + (hnext ? hnext[it.gspot] : 0ull) + j0;
 
     for (uint32_t b = t; b < nbins; b += kThreads) s_cnt[b] = 0;
@@ -179,7 +208,7 @@ __global__ void __launch_bounds__(kThreads) order_chunk_kernel(const WorkItem *_
         const uint32_t e = t + r * kThreads;
         cell[r] = 0;
         if (e < len) {
-            cell[r] = start_cell(sp, hbase + e, hb, seed_lo, seed_hi);
+            cell[r] = order_key(sp, hbase + e, hb, ot, seed_lo, seed_hi);
             atomicAdd(&s_cnt[cell[r]], 1u);
         }
     }
@@ -229,7 +258,7 @@ __global__ void __launch_bounds__(kThreads) order_chunk_kernel(const WorkItem *_
 hipError_t launch_source_order(const WorkItem *items, uint32_t n_items, uint32_t n_chunks, unsigned long long n_units,
                                const DevSpot *spots, const unsigned long long *hnext, uint32_t seed_lo,
                                uint32_t seed_hi, uint32_t *order, uint32_t *hist, unsigned long long hist_words,
-                               bool large, hipStream_t s)
+                               bool large, const OrderTracks &tracks, hipStream_t s)
 {
     if (n_units == 0) return hipSuccess;
     // lanes past an item's end: none (the table is 64 x n_units words, an even count)
@@ -239,13 +268,13 @@ hipError_t launch_source_order(const WorkItem *items, uint32_t n_items, uint32_t
         e = launch_fill_u64((unsigned long long *)hist, (hist_words + 1) / 2, 0ull, s);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(order_large_kernel<false>, dim3(n_chunks), dim3(kThreads), 0, s, items, n_items, spots,
-                           hnext, seed_lo, seed_hi, hist, order);
+                           hnext, seed_lo, seed_hi, hist, order, tracks);
         hipLaunchKernelGGL(order_scan_kernel, dim3(n_items), dim3(kThreads), 0, s, items, hist);
         hipLaunchKernelGGL(order_large_kernel<true>, dim3(n_chunks), dim3(kThreads), 0, s, items, n_items, spots,
-                           hnext, seed_lo, seed_hi, hist, order);
+                           hnext, seed_lo, seed_hi, hist, order, tracks);
     }
     hipLaunchKernelGGL(order_chunk_kernel, dim3(n_chunks), dim3(kThreads), 0, s, items, n_items, spots, hnext,
-                       seed_lo, seed_hi, order);
+                       seed_lo, seed_hi, order, tracks);
     return hipGetLastError();
 }
 
