@@ -29,7 +29,8 @@ CANDIDATES = (
        dict(waves_per_block=8, blocks_per_cu=1, tally_slots=8064, units_per_wave=1, tally_mode=2)]
     + [dict(waves_per_block=8, blocks_per_cu=2, tally_slots=3008, units_per_wave=u, tally_mode=1) for u in (2, 4)]
     # histories in start-position order (lanes of a wave start next to each other)
-    + [dict(waves_per_block=16, blocks_per_cu=1, tally_slots=8064, units_per_wave=1, tally_mode=1, source_order=1)]
+    + [dict(waves_per_block=16, blocks_per_cu=1, tally_slots=8064, units_per_wave=u, tally_mode=1, source_order=1)
+       for u in (1, 2, 4)]
     + [dict(waves_per_block=16, blocks_per_cu=1, tally_slots=8064, units_per_wave=u, tally_mode=2, source_order=1)
        for u in (1, 2, 4, 8)]
 )

@@ -94,10 +94,10 @@ def batched(db, log=print, hist_scale=1.0):
             ids.append(p)
         ctxs.append((c, ids))
     (cg, ids), (ce, ide) = ctxs
-    # launch configurations a captured graph runs as tuned (a graph keeps the
-    # history order: the ordering's sort clears memory with memset nodes)
-    cands = [c for c in A.CANDIDATES if not c.get("source_order")]
-    cfg, _ = A.tune(cg, ids, F.FDC_RUN_VARIANCE, reps=1, candidates=cands, use_cache=False)
+    # the launch configuration both sides run, tuned on the whole batch (a
+    # launch of several plans takes the rounds cache; the start-position order
+    # is captured in the graph like the rest)
+    cfg, _ = A.tune(cg, ids, F.FDC_RUN_VARIANCE, reps=1, candidates=A.CANDIDATES, use_cache=False)
     ce.set_launch_config(**cfg)
     doses = [torch.empty(ph.hu.size, dtype=torch.float64, device="cuda") for ph, _ in plans]
     vars_ = [torch.empty(ph.hu.size, dtype=torch.float64, device="cuda") for ph, _ in plans]
