@@ -271,8 +271,13 @@ __device__ inline void stage16(int total, Src src, Dst dst)
 
 // CS < CP: the input channels are staged CS at a time (phases of all 27 taps
 // over CS channels), so the tile fits LDS with room for more blocks per CU.
+// Input channels from `split` on come from a second buffer (src2, its own
+// pitch, channel c - split): a decoder's input is the concatenation of the
+// up-convolution's output and the skip, kept as two dense buffers so that
+// their producers write whole cache lines.
 template <int NT, int TY, int CP, int CS = CP>
-__global__ void __launch_bounds__(256) conv3_kernel(const u16 *__restrict__ src, int src_pitch, Grid g,
+__global__ void __launch_bounds__(256) conv3_kernel(const u16 *__restrict__ src, int src_pitch,
+                                                    const u16 *__restrict__ src2, int src2_pitch, int split, Grid g,
                                                     const u16 *__restrict__ wpk, int kpad, int n_cols,
                                                     const float *__restrict__ bias, int relu,
                                                     const u16 *__restrict__ mask, int mask_pitch,
@@ -352,7 +357,9 @@ __global__ void __launch_bounds__(256) conv3_kernel(const u16 *__restrict__ src,
                     const int h = t >> GSHIFT, cg = t & ((1 << GSHIFT) - 1);
                     const int x = x0 - 1 + h % HX, y = y0 - 1 + (h / HX) % HY, z = z0 - 1 + h / (HX * HY);
                     if (x < 0 || x >= g.nx || y < 0 || y >= g.ny || z < 0 || z >= g.nz) return nullptr;
-                    return src + (((long)z * g.ny + y) * g.nx + x) * src_pitch + CS * ph + 8 * cg;
+                    const long v = ((long)z * g.ny + y) * g.nx + x;
+                    const int c = CS * ph + 8 * cg;
+                    return c < split ? src + v * src_pitch + c : src2 + v * src2_pitch + (c - split);
                 },
                 [&](int t) { return sh + (t >> GSHIFT) * HP + 8 * (t & ((1 << GSHIFT) - 1)); });
     };
@@ -625,11 +632,13 @@ __device__ inline bf16x8 tr_frag(const u16 *tile, int pitch, int row, int col)
 // contraction voxels are 8 consecutive x of one row, and for every tap their
 // shifted neighbours are 8 consecutive halo rows, so both MFMA operands come
 // straight from ds_read_b64_tr_b16 with no boundary masks (the halo holds the
-// zeros).  Accumulators stay in registers across the block's tiles;
+// zeros).  Q channels from q_split on come from Q2 (a concatenation kept as
+// two buffers, as in conv3_kernel).  Accumulators stay in registers across the block's tiles;
 // part[blockIdx.x][o][i][j] receives the block's sums.
 template <int TY, int TZ, int PT>
 __global__ void __launch_bounds__(256) wgrad3t_kernel(const u16 *__restrict__ P, int p_pitch, int p_ch,
-                                                      const u16 *__restrict__ Q, int q_pitch, int q_ch, Grid g,
+                                                      const u16 *__restrict__ Q, int q_pitch, int q_ch,
+                                                      const u16 *__restrict__ Q2, int q2_pitch, int q_split, Grid g,
                                                       float *__restrict__ part, int pc, int qc, int G, int qs)
 {
     constexpr int TX = 16, HX = TX + 2, HY = TY + 2, HZ = TZ + 2, TV = TX * TY * TZ;
@@ -672,9 +681,10 @@ __global__ void __launch_bounds__(256) wgrad3t_kernel(const u16 *__restrict__ P,
                 [&](int u) -> const u16 * {
                     const int h = u / qcg, cg = u - h * qcg;
                     const int x = x0 - 1 + h % HX, y = y0 - 1 + (h / HX) % HY, z = z0 - 1 + h / (HX * HY);
-                    if (x < 0 || x >= g.nx || y < 0 || y >= g.ny || z < 0 || z >= g.nz || q_off + 8 * cg >= q_ch)
-                        return nullptr;
-                    return Q + (((long)z * g.ny + y) * g.nx + x) * q_pitch + q_off + 8 * cg;
+                    const int c = q_off + 8 * cg;
+                    if (x < 0 || x >= g.nx || y < 0 || y >= g.ny || z < 0 || z >= g.nz || c >= q_ch) return nullptr;
+                    const long v = ((long)z * g.ny + y) * g.nx + x;
+                    return c < q_split ? Q + v * q_pitch + c : Q2 + v * q2_pitch + (c - q_split);
                 },
                 [&](int u) { return sQ + (u / qcg) * sq_pitch + 8 * (u % qcg); });
         __syncthreads();
@@ -1047,6 +1057,11 @@ struct View {
     u16 *p;
     int pitch;
     int ch;
+    // a concatenation held as two dense buffers: channels from `split` on are
+    // channel c - split of p2 (pitch pitch2)
+    u16 *p2 = nullptr;
+    int pitch2 = 0;
+    int split = 0;
 };
 
 } // namespace nn
@@ -1111,6 +1126,7 @@ hipError_t igemm(int am, int em, const View &src, int cpad, const Grid &g, const
 #define IG(AM_, EM_, NT_) hipLaunchKernelGGL((igemm_kernel<AM_, EM_, 2, NT_>), grid, dim3(256), 0, s, src.p, src.pitch, \
                                              cpad, g, wpk, kpad, n_cols, bias, (int)relu, mp, mpitch, dst.p, dst.pitch, d2s_cout)
 #define IGN(AM_, EM_) do { if (nt == 4) IG(AM_, EM_, 4); else if (nt == 2) IG(AM_, EM_, 2); else IG(AM_, EM_, 1); } while (0)
+    if (src.p2 && am != A_CONV3) return hipErrorInvalidValue;          // two-buffer sources: 3x3x3 only
     if (em == E_D2S) {
         // the staged epilogue writes 8 channels of one fine voxel as 16 bytes
         if (am != A_CONV1 || d2s_cout % 8 || dst.pitch % 8 || ((uintptr_t)dst.p & 15)) return hipErrorInvalidValue;
@@ -1135,8 +1151,15 @@ hipError_t igemm(int am, int em, const View &src, int cpad, const Grid &g, const
             return hipErrorInvalidValue;
         u16 *pp = pool ? pool->p : nullptr;
         const int ppitch = pool ? pool->pitch : 0;
+        // a two-buffer source: its parts split at a whole 16-byte channel group
+        if (src.p2 && (src.split % 8 || src.split <= 0 || src.split >= cpad || src.pitch2 % 8 ||
+                       ((uintptr_t)src.p2 & 15)))
+            return hipErrorInvalidValue;
+        const u16 *s2 = src.p2 ? src.p2 : src.p;
+        const int s2pitch = src.p2 ? src.pitch2 : src.pitch, split = src.p2 ? src.split : cpad;
 #define CV(NT_, TY_, CP_, CS_) hipLaunchKernelGGL((conv3_kernel<NT_, TY_, CP_, CS_>), cgrid, dim3(256), lds, s, src.p, \
-                                                  src.pitch, g, wpk, kpad, n_cols, bias, (int)relu, mp, mpitch, dst.p, \
+                                                  src.pitch, s2, s2pitch, split, g, wpk, kpad, n_cols, bias, (int)relu, \
+                                                  mp, mpitch, dst.p, \
                                                   dst.pitch, vec, pp, ppitch)
 #define CVN(TY_, CP_, CS_) do { if (nt == 4) CV(4, TY_, CP_, CS_); else if (nt == 2) CV(2, TY_, CP_, CS_); \
                                 else CV(1, TY_, CP_, CS_); } while (0)
@@ -1165,6 +1188,7 @@ hipError_t wgrad(int am, const View &P, int p_ch, const View &Q, int q_ch, const
 {
     const long rows = (long)g.nx * g.ny * g.nz;
     const int pc = pad16(p_ch), qc = pad16(q_ch);
+    if (P.p2 || (Q.p2 && am != A_CONV3)) return hipErrorInvalidValue;      // two-buffer sources: 3x3x3 Q only
     long slabs = 1, per = rows;
     if (am != A_CONV3) {
         // slabs of at least 256 rows (8 rounds of 32), at most 1024 of them and
@@ -1209,8 +1233,12 @@ hipError_t wgrad(int am, const View &P, int p_ch, const View &Q, int q_ch, const
         slabs = std::max<long>(1, std::min<long>({tiles, cap, std::max(1L, 2048L / ny_blocks)}));
         const size_t lds = ((size_t)16 * ty * tz * (pc + 8) + (size_t)18 * (ty + 2) * (tz + 2) * (16 * qs + 8)) * sizeof(u16);
         const dim3 grid((uint32_t)slabs, (uint32_t)ny_blocks);
+        // a two-buffer Q: its parts split at a whole 16-byte channel group
+        if (Q.p2 && (Q.split % 8 || Q.split <= 0 || Q.pitch2 % 8 || ((uintptr_t)Q.p2 & 15))) return hipErrorInvalidValue;
+        const u16 *q2 = Q.p2 ? Q.p2 : Q.p;
+        const int q2pitch = Q.p2 ? Q.pitch2 : Q.pitch, qsplit = Q.p2 ? Q.split : qc;
 #define WTP(TY_, TZ_, PT_) hipLaunchKernelGGL((wgrad3t_kernel<TY_, TZ_, PT_>), grid, dim3(256), lds, s, P.p, P.pitch, \
-                                              p_ch, Q.p, Q.pitch, q_ch, g, u->wpart, pc, qc, G, qs)
+                                              p_ch, Q.p, Q.pitch, q_ch, q2, q2pitch, qsplit, g, u->wpart, pc, qc, G, qs)
 #define WT(TY_, TZ_) do { if (pc == 16) WTP(TY_, TZ_, 1); else if (pc == 32) WTP(TY_, TZ_, 2); else WTP(TY_, TZ_, 4); } while (0)
         if (ty == 4 && tz == 4) WT(4, 4); else if (ty == 4) WT(4, 2); else WT(2, 2);
 #undef WT
@@ -1286,14 +1314,15 @@ Views views(const fdc_unet *u)
     Views v;
     v.x = {u->x, 8, 2};
     v.e1a = {u->e1a, 16, 16};
-    v.c1 = {u->c1, 32, 32};
-    v.u1 = {u->c1, 32, 16};
-    v.e1 = {u->c1 + 16, 32, 16};
+    // decoder inputs: up-convolution output | skip, each half dense
+    v.u1 = {u->c1, 16, 16};
+    v.e1 = {u->c1 + u->nv[0] * 16, 16, 16};
+    v.c1 = {v.u1.p, 16, 32, v.e1.p, 16, 16};
     v.p1 = {u->p1, 16, 16};
     v.e2a = {u->e2a, 32, 32};
-    v.c2 = {u->c2, 64, 64};
-    v.u2 = {u->c2, 64, 32};
-    v.e2 = {u->c2 + 32, 64, 32};
+    v.u2 = {u->c2, 32, 32};
+    v.e2 = {u->c2 + u->nv[1] * 32, 32, 32};
+    v.c2 = {v.u2.p, 32, 64, v.e2.p, 32, 32};
     v.p2 = {u->p2, 32, 32};
     v.ma = {u->ma, 64, 64};
     v.m = {u->m, 64, 64};
@@ -1635,7 +1664,16 @@ int fdc_unet_debug_buffer(fdc_unet *u, int index, uint16_t *host_out, int64_t *n
     if (!host_out) return FDC_OK;
     hipStream_t s = (hipStream_t)hip_stream;
     hipError_t e = hipSetDevice(u->device);
-    if (!e) e = hipMemcpyAsync(host_out, bufs[index], (size_t)n * pit[index] * 2, hipMemcpyDeviceToHost, s);
+    if (index == 2 || index == 5) {
+        // a concatenation (up-convolution output | skip) is held as two dense
+        // halves; the copy interleaves them into rows of pitch channels
+        const size_t h = (size_t)pit[index] / 2;
+        if (!e) e = hipMemcpy2DAsync(host_out, 2 * h * 2, bufs[index], h * 2, h * 2, (size_t)n, hipMemcpyDeviceToHost, s);
+        if (!e) e = hipMemcpy2DAsync((u16 *)host_out + h, 2 * h * 2, bufs[index] + (size_t)n * h, h * 2, h * 2,
+                                     (size_t)n, hipMemcpyDeviceToHost, s);
+    } else if (!e) {
+        e = hipMemcpyAsync(host_out, bufs[index], (size_t)n * pit[index] * 2, hipMemcpyDeviceToHost, s);
+    }
     if (!e) e = hipStreamSynchronize(s);
     if (e) return ufail(u, FDC_E_HIP, "debug_buffer", e);
     return FDC_OK;
