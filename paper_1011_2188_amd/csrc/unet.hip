@@ -4,8 +4,11 @@
 //
 // Activations are bfloat16, channels-last: element (voxel v, channel c) of a
 // view is p[v * pitch + c], channel counts padded to multiples of 8 so that a
-// lane loads 8 channels (16 bytes) at once.  Concatenations are views into one
-// buffer (no copies).  Weights live as FP32 master copies in the canonical
+// lane loads 8 channels (16 bytes) at once; the network's two input channels
+// are kept unpadded for the first convolution (and padded for its weight
+// gradients).  A decoder's input, the concatenation of the up-convolution's
+// output and the skip, is two dense buffers that the kernels stage as one (no
+// copies).  Weights live as FP32 master copies in the canonical
 // layout of the network description (per layer: weights, then biases) and are
 // packed to bfloat16 GEMM operands after every update.
 //
@@ -286,7 +289,12 @@ __global__ void __launch_bounds__(256) conv3_kernel(const u16 *__restrict__ src,
 {
     constexpr int TX = 16, TZ = 4, HX = TX + 2, HY = TY + 2, HZ = TZ + 2;
     static_assert(CP % CS == 0 && (CS == CP || CS % 32 == 0), "phases of whole K steps");
-    constexpr int HP = CS + 8;                             // LDS channel pitch (16-byte rows, skewed banks)
+    // NARROW (two input channels, the network's input): the tile holds 4 bytes
+    // per voxel, and a lane group's 8 K elements are the two channels of four
+    // consecutive taps, K = 54 in two steps instead of 27 x 8 in seven
+    constexpr bool NARROW = CP == 2;
+    static_assert(!NARROW || CS == 2, "two channels in one phase");
+    constexpr int HP = NARROW ? 2 : CS + 8;                // LDS channel pitch (16-byte rows, skewed banks)
     constexpr int GSHIFT = CS == 8 ? 0 : CS == 16 ? 1 : CS == 32 ? 2 : 3;   // CS / 8 = 1 << GSHIFT
     constexpr int KVALID = 27 * CS;                        // K of one phase
     constexpr int STEPS = (KVALID + 31) / 32;              // K steps of 32 per phase
@@ -322,7 +330,8 @@ __global__ void __launch_bounds__(256) conv3_kernel(const u16 *__restrict__ src,
     // Staged output (see the epilogue): 16 TY voxels x 16 NT channels per wave
     // in the input tile's LDS, 16-byte chunks of 8 channels of one voxel.
     constexpr int TP = 16 * NT + 8;                        // voxel pitch (16-byte rows, skewed banks)
-    constexpr bool STAGE = 4 * 16 * TY * TP <= HZ * HY * HX * HP;   // the output tiles fit
+    // the output tiles fit (a NARROW launch allocates LDS for them)
+    constexpr bool STAGE = NARROW || 4 * 16 * TY * TP <= HZ * HY * HX * HP;
     constexpr int CH = 2 * NT;                             // chunks per voxel
     constexpr int NQ = STAGE ? 16 * TY * CH / 64 : 1;      // chunks per lane
     static_assert(!STAGE || (16 * TY * CH) % 64 == 0, "whole chunk rounds");
@@ -352,6 +361,26 @@ __global__ void __launch_bounds__(256) conv3_kernel(const u16 *__restrict__ src,
     __builtin_amdgcn_sched_barrier(0);
     // channels CS ph .. CS ph + CS - 1 of the tile and its halo into LDS
     auto stage = [&](int ph) {
+        if constexpr (NARROW) {
+            // one 4-byte item per tile voxel, eight loads in flight per thread
+            constexpr int NV = HZ * HY * HX;
+            for (int t0 = threadIdx.x; t0 < NV; t0 += 8 * (int)blockDim.x) {
+                uint32_t q[8];
+#pragma unroll
+                for (int b = 0; b < 8; ++b) {
+                    const int h = t0 + b * (int)blockDim.x;
+                    const int x = x0 - 1 + h % HX, y = y0 - 1 + (h / HX) % HY, z = z0 - 1 + h / (HX * HY);
+                    const bool in = h < NV && x >= 0 && x < g.nx && y >= 0 && y < g.ny && z >= 0 && z < g.nz;
+                    q[b] = in ? *(const uint32_t *)(src + (((long)z * g.ny + y) * g.nx + x) * src_pitch) : 0u;
+                }
+#pragma unroll
+                for (int b = 0; b < 8; ++b) {
+                    const int h = t0 + b * (int)blockDim.x;
+                    if (h < NV) *(uint32_t *)(sh + h * HP) = q[b];
+                }
+            }
+            return;
+        }
         stage16<8>((HZ * HY * HX) << GSHIFT,
                 [&](int t) -> const u16 * {
                     const int h = t >> GSHIFT, cg = t & ((1 << GSHIFT) - 1);
@@ -397,7 +426,26 @@ __global__ void __launch_bounds__(256) conv3_kernel(const u16 *__restrict__ src,
             const int off = kv ? a_off(st) : 0;
             bf16x8 a[TY];
 #pragma unroll
-            for (int m = 0; m < TY; ++m) a[m] = load8(sh + base[m] + off);
+            for (int m = 0; m < TY; ++m) a[m] = NARROW ? zero8() : load8(sh + base[m] + off);
+            if constexpr (NARROW) {
+                // taps 16 st + 4 lg + j, j = 0..3, both channels of each (zero past the 27th)
+                int to[4];
+                bool tv[4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int o = 16 * st + 4 * lg + j;
+                    tv[j] = o < 27;
+                    const int oc = tv[j] ? o : 0;
+                    to[j] = (((oc / 9) * HY + (oc / 3) % 3) * HX + oc % 3) * HP;
+                }
+#pragma unroll
+                for (int m = 0; m < TY; ++m) {
+                    uint32_t q[4];
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) q[j] = tv[j] ? *(const uint32_t *)(sh + base[m] + to[j]) : 0u;
+                    a[m] = __builtin_bit_cast(bf16x8, make_uint4(q[0], q[1], q[2], q[3]));
+                }
+            }
 #pragma unroll
             for (int m = 0; m < TY; ++m) {
                 const bf16x8 am = (32 * st + 32 <= KVALID || kv) ? a[m] : zero8();
@@ -807,15 +855,15 @@ __global__ void __launch_bounds__(256) bias_part_kernel(BiasJobs jobs, float *__
     }
 }
 
-// FP32 [2][n] channels-first input -> bf16 channels-last, pitch 8 (zeros beyond 2)
-__global__ void pack_input_kernel(const float *__restrict__ in, long n, u16 *__restrict__ x)
+// FP32 [2][n] channels-first input -> bf16 channels-last, pitch 2 or 8 (zeros beyond 2)
+__global__ void pack_input_kernel(const float *__restrict__ in, long n, u16 *__restrict__ x, int pitch)
 {
     for (long v = blockIdx.x * (long)blockDim.x + threadIdx.x; v < n; v += (long)gridDim.x * blockDim.x) {
-        uint4 q = make_uint4(0, 0, 0, 0);
-        u16 *h = (u16 *)&q;
-        h[0] = f2bf(in[v]);
-        h[1] = f2bf(in[n + v]);
-        *(uint4 *)(x + v * 8) = q;
+        const uint32_t lo = f2bf(in[v]), hi = f2bf(in[n + v]);
+        if (pitch == 2)
+            *(uint32_t *)(x + v * 2) = lo | (hi << 16);
+        else
+            *(uint4 *)(x + v * 8) = make_uint4(lo | (hi << 16), 0u, 0u, 0u);
     }
 }
 
@@ -1040,6 +1088,9 @@ enum { L_E1A, L_E1B, L_E2A, L_E2B, L_MA, L_MB, L_UP2, L_D2A, L_D2B, L_UP1, L_D1A
 inline int pad8(int c) { return (c + 7) & ~7; }
 inline int pad16(int c) { return (c + 15) & ~15; }
 inline int pad32(int k) { return (k + 31) & ~31; }
+// channels per tap in a 3x3x3 layer's forward K: the network's two input
+// channels unpadded (the two-channel kernel), else padded to 8
+inline int fwd_cpad(int cin) { return cin == 2 ? 2 : pad8(cin); }
 
 long weight_count(const LayerDesc &L)
 {
@@ -1082,8 +1133,9 @@ struct fdc_unet {
     u16 *wpk_f[kNumLayers] = {}, *wpk_b[kNumLayers] = {};
     int kpad_f[kNumLayers] = {}, ncol_f[kNumLayers] = {}, kpad_b[kNumLayers] = {}, ncol_b[kNumLayers] = {};
     std::vector<void *> allocs;
-    // activations (bf16, channels-last)
-    u16 *x, *e1a, *c1, *p1, *e2a, *c2, *p2, *ma, *m, *d2a, *d2, *d1a, *d1;
+    // activations (bf16, channels-last); x2: the input's two channels (the
+    // forward pass), x: the same padded to 8 (weight gradients of the first layer)
+    u16 *x, *x2, *e1a, *c1, *p1, *e2a, *c2, *p2, *ma, *m, *d2a, *d2, *d1a, *d1;
     // activation gradients
     u16 *gd1, *gd1a, *gc1, *gd2, *gd2a, *gc2, *gm, *gma, *gp2, *ge2, *ge2a, *gp1, *ge1, *ge1a;
     float *wpart = nullptr, *bpart = nullptr, *hpart = nullptr, *hw = nullptr;
@@ -1136,11 +1188,14 @@ hipError_t igemm(int am, int em, const View &src, int cpad, const Grid &g, const
         // padded channel count so that the K loop unrolls; 64 input channels
         // are staged 32 at a time, so the tile and its halo take 52 KB of LDS
         const int ty = 4, cs = std::min(cpad, 32);
-        if (cpad != 8 && cpad != 16 && cpad != 32 && cpad != 64) return hipErrorInvalidValue;
+        if (cpad != 2 && cpad != 8 && cpad != 16 && cpad != 32 && cpad != 64) return hipErrorInvalidValue;
+        if (cpad == 2 && (pool || src.p2 || src.pitch < 2 || ((uintptr_t)src.p & 3))) return hipErrorInvalidValue;
         if (kpad < (27 * cpad + 31) / 32 * 32) return hipErrorInvalidValue;   // the K loop reads 32-wide steps
         const uint32_t tiles = (uint32_t)(((g.nx + 15) / 16) * ((g.ny + ty - 1) / ty) * ((g.nz + 3) / 4));
         const dim3 cgrid(tiles, (uint32_t)((n_cols + 16 * nt - 1) / (16 * nt)));
-        const size_t lds = (size_t)6 * (ty + 2) * 18 * (cs + 8) * sizeof(u16);
+        // (two input channels: a 4-byte tile, the LDS sized for the staged output)
+        const size_t lds = cpad == 2 ? (size_t)std::max(6 * (ty + 2) * 18 * 2, 4 * 16 * ty * (16 * nt + 8)) * sizeof(u16)
+                                     : (size_t)6 * (ty + 2) * 18 * (cs + 8) * sizeof(u16);
         // 16-byte output stores (and mask loads) need 8-element alignment throughout
         const auto al = [](const void *p) { return ((uintptr_t)p & 15) == 0; };
         const int vec = n_cols % 8 == 0 && dst.pitch % 8 == 0 && al(dst.p) && (!mp || (mpitch % 8 == 0 && al(mp)));
@@ -1163,7 +1218,8 @@ hipError_t igemm(int am, int em, const View &src, int cpad, const Grid &g, const
                                                   dst.pitch, vec, pp, ppitch)
 #define CVN(TY_, CP_, CS_) do { if (nt == 4) CV(4, TY_, CP_, CS_); else if (nt == 2) CV(2, TY_, CP_, CS_); \
                                 else CV(1, TY_, CP_, CS_); } while (0)
-        if (cpad == 8) CVN(4, 8, 8);
+        if (cpad == 2) CVN(4, 2, 2);
+        else if (cpad == 8) CVN(4, 8, 8);
         else if (cpad == 16) CVN(4, 16, 16);
         else if (cpad == 32) CVN(4, 32, 32);
         else CVN(4, 64, 32);
@@ -1292,7 +1348,7 @@ hipError_t pack_all(fdc_unet *u, hipStream_t s)
         const LayerDesc &L = kLayers[l];
         const float *w = u->params + u->w_off[l];
         if (L.kind == K_CONV3) {
-            add(w, u->wpk_f[l], 0, L.cin, L.cout, pad8(L.cin), u->ncol_f[l], u->kpad_f[l]);
+            add(w, u->wpk_f[l], 0, L.cin, L.cout, fwd_cpad(L.cin), u->ncol_f[l], u->kpad_f[l]);
             if (u->wpk_b[l]) add(w, u->wpk_b[l], 1, L.cin, L.cout, pad8(L.cout), u->ncol_b[l], u->kpad_b[l]);
         } else if (L.kind == K_TCONV) {
             add(w, u->wpk_f[l], 2, L.cin, L.cout, pad8(L.cin), u->ncol_f[l], u->kpad_f[l]);
@@ -1355,7 +1411,7 @@ hipError_t conv_fwd(fdc_unet *u, int l, const View &src, const Grid &g, const Vi
                     const View *pool = nullptr)
 {
     const LayerDesc &L = kLayers[l];
-    return igemm(A_CONV3, E_STORE, src, pad8(L.cin), g, u->wpk_f[l], u->kpad_f[l], L.cout, u->params + u->b_off[l],
+    return igemm(A_CONV3, E_STORE, src, fwd_cpad(L.cin), g, u->wpk_f[l], u->kpad_f[l], L.cout, u->params + u->b_off[l],
                  true, nullptr, dst, 0, s, pool);
 }
 
@@ -1363,9 +1419,9 @@ hipError_t forward_pass(fdc_unet *u, const float *in, hipStream_t s)
 {
     const Views v = views(u);
     const Grid *g = u->g;
-    hipLaunchKernelGGL(pack_input_kernel, dim3(blocks_for(u->nv[0])), dim3(256), 0, s, in, u->nv[0], u->x);
+    hipLaunchKernelGGL(pack_input_kernel, dim3(blocks_for(u->nv[0])), dim3(256), 0, s, in, u->nv[0], u->x2, 2);
     hipError_t e = hipGetLastError();
-    if (!e) e = conv_fwd(u, L_E1A, v.x, g[0], v.e1a, s);
+    if (!e) e = conv_fwd(u, L_E1A, View{u->x2, 2, 2}, g[0], v.e1a, s);
     if (!e) e = conv_fwd(u, L_E1B, v.e1a, g[0], v.e1, s, &v.p1);    // pool 1 fused into the epilogue
     if (!e) e = conv_fwd(u, L_E2A, v.p1, g[1], v.e2a, s);
     if (!e) e = conv_fwd(u, L_E2B, v.e2a, g[1], v.e2, s, &v.p2);    // pool 2 fused into the epilogue
@@ -1416,8 +1472,9 @@ hipError_t backward_pass(fdc_unet *u, const float *in, hipStream_t s)
         if (!e) e = add_bias_job(bj, bias_blocks, gout, L.cout, (long)gr.nx * gr.ny * gr.nz, gb(l));
         return e;
     };
-    (void)in;
-    hipError_t e = hipSuccess;
+    // the input padded to 8 channels, for the first layer's weight gradients
+    hipLaunchKernelGGL(pack_input_kernel, dim3(blocks_for(u->nv[0])), dim3(256), 0, s, in, u->nv[0], u->x, 8);
+    hipError_t e = hipGetLastError();
     // dec1b, dec1a
     if (!e) e = bwd(L_D1B, v.gd1, g[0], &v.d1a, v.gd1a);
     if (!e) e = wg3(L_D1B, v.gd1, v.d1a, g[0]);
@@ -1534,7 +1591,7 @@ int fdc_unet_create(fdc_unet **out, int hip_device, int nx, int ny, int nz)
     for (int l = 0; l < kNumLayers; ++l) {
         const LayerDesc &L = kLayers[l];
         if (L.kind == K_CONV3) {
-            u->ncol_f[l] = L.cout; u->kpad_f[l] = pad32(27 * pad8(L.cin));
+            u->ncol_f[l] = L.cout; u->kpad_f[l] = pad32(27 * fwd_cpad(L.cin));
             u->ncol_b[l] = L.cin;  u->kpad_b[l] = pad32(27 * pad8(L.cout));
             u->wpk_f[l] = A16((long)u->ncol_f[l] * u->kpad_f[l]);
             if (l != L_E1A) u->wpk_b[l] = A16((long)u->ncol_b[l] * u->kpad_b[l]);
@@ -1546,7 +1603,8 @@ int fdc_unet_create(fdc_unet **out, int hip_device, int nx, int ny, int nz)
         }
     }
     const long n0 = u->nv[0], n1 = u->nv[1], n2 = u->nv[2];
-    u->x = A16(n0 * 8); u->e1a = A16(n0 * 16); u->c1 = A16(n0 * 32); u->p1 = A16(n1 * 16); u->e2a = A16(n1 * 32);
+    u->x = A16(n0 * 8); u->x2 = A16(n0 * 2);
+    u->e1a = A16(n0 * 16); u->c1 = A16(n0 * 32); u->p1 = A16(n1 * 16); u->e2a = A16(n1 * 32);
     u->c2 = A16(n1 * 64); u->p2 = A16(n2 * 32); u->ma = A16(n2 * 64); u->m = A16(n2 * 64); u->d2a = A16(n1 * 32);
     u->d2 = A16(n1 * 32); u->d1a = A16(n0 * 16); u->d1 = A16(n0 * 16);
     u->gd1 = A16(n0 * 16); u->gd1a = A16(n0 * 16); u->gc1 = A16(n0 * 32); u->gd2 = A16(n1 * 32);
@@ -1664,7 +1722,11 @@ int fdc_unet_debug_buffer(fdc_unet *u, int index, uint16_t *host_out, int64_t *n
     if (!host_out) return FDC_OK;
     hipStream_t s = (hipStream_t)hip_stream;
     hipError_t e = hipSetDevice(u->device);
-    if (index == 2 || index == 5) {
+    if (index == 0) {
+        // the input as the forward pass read it (two channels), in rows of 8
+        std::memset(host_out, 0, (size_t)n * 8 * 2);
+        if (!e) e = hipMemcpy2DAsync(host_out, 16, u->x2, 4, 4, (size_t)n, hipMemcpyDeviceToHost, s);
+    } else if (index == 2 || index == 5) {
         // a concatenation (up-convolution output | skip) is held as two dense
         // halves; the copy interleaves them into rows of pitch channels
         const size_t h = (size_t)pit[index] / 2;
