@@ -1722,17 +1722,28 @@ int fdc_unet_debug_buffer(fdc_unet *u, int index, uint16_t *host_out, int64_t *n
     if (!host_out) return FDC_OK;
     hipStream_t s = (hipStream_t)hip_stream;
     hipError_t e = hipSetDevice(u->device);
-    if (index == 0) {
-        // the input as the forward pass read it (two channels), in rows of 8
-        std::memset(host_out, 0, (size_t)n * 8 * 2);
-        if (!e) e = hipMemcpy2DAsync(host_out, 16, u->x2, 4, 4, (size_t)n, hipMemcpyDeviceToHost, s);
-    } else if (index == 2 || index == 5) {
-        // a concatenation (up-convolution output | skip) is held as two dense
-        // halves; the copy interleaves them into rows of pitch channels
-        const size_t h = (size_t)pit[index] / 2;
-        if (!e) e = hipMemcpy2DAsync(host_out, 2 * h * 2, bufs[index], h * 2, h * 2, (size_t)n, hipMemcpyDeviceToHost, s);
-        if (!e) e = hipMemcpy2DAsync((u16 *)host_out + h, 2 * h * 2, bufs[index] + (size_t)n * h, h * 2, h * 2,
-                                     (size_t)n, hipMemcpyDeviceToHost, s);
+    if (index == 0 || index == 2 || index == 5) {
+        // the input as the forward pass read it (two channels, returned in rows
+        // of 8), or a concatenation held as two dense halves (returned
+        // interleaved): contiguous copies, rearranged here
+        const size_t h = index == 0 ? 2 : (size_t)pit[index] / 2, parts = index == 0 ? 1 : 2;
+        std::vector<u16> tmp;
+        try {
+            tmp.resize((size_t)n * h * parts);
+        } catch (const std::bad_alloc &) {
+            return ufail(u, FDC_E_NOMEM, "debug_buffer: host staging");
+        }
+        const u16 *src = index == 0 ? u->x2 : bufs[index];
+        if (!e) e = hipMemcpyAsync(tmp.data(), src, tmp.size() * 2, hipMemcpyDeviceToHost, s);
+        if (!e) e = hipStreamSynchronize(s);
+        if (!e) {
+            u16 *o = (u16 *)host_out;
+            const size_t P = (size_t)pit[index];
+            std::memset(o, 0, (size_t)n * P * 2);
+            for (size_t part = 0; part < parts; ++part)
+                for (size_t v = 0; v < (size_t)n; ++v)
+                    std::memcpy(o + v * P + part * h, tmp.data() + (part * (size_t)n + v) * h, h * 2);
+        }
     } else if (!e) {
         e = hipMemcpyAsync(host_out, bufs[index], (size_t)n * pit[index] * 2, hipMemcpyDeviceToHost, s);
     }
