@@ -285,7 +285,9 @@ __global__ void __launch_bounds__(256) conv3_kernel(const u16 *__restrict__ src,
                                                     const float *__restrict__ bias, int relu,
                                                     const u16 *__restrict__ mask, int mask_pitch,
                                                     u16 *__restrict__ dst, int dst_pitch, int vec,
-                                                    u16 *__restrict__ pool_dst, int pool_pitch)
+                                                    u16 *__restrict__ pool_dst, int pool_pitch,
+                                                    const float *__restrict__ head_w,
+                                                    const float *__restrict__ head_in, float *__restrict__ head_out)
 {
     constexpr int TX = 16, TZ = 4, HX = TX + 2, HY = TY + 2, HZ = TZ + 2;
     static_assert(CP % CS == 0 && (CS == CP || CS % 32 == 0), "phases of whole K steps");
@@ -510,6 +512,19 @@ __global__ void __launch_bounds__(256) conv3_kernel(const u16 *__restrict__ src,
             }
         }
         if (z >= g.nz) return;
+        if (NT == 1 && TY == 4 && head_out) {
+            // the network's 1x1 head (16 channels -> 1, bias) and the residual,
+            // fused for inference: lane = voxel of the wave's 16 x 4 slice, its
+            // 16 channels one row of the staged tile (the head kernel's sum order)
+            const int x = x0 + (lane & 15), y = y0 + (lane >> 4);
+            if (x < g.nx && y < g.ny) {
+                const long r = ((long)z * g.ny + y) * g.nx + x;
+                float yv = head_w[16];
+#pragma unroll
+                for (int c = 0; c < 16; ++c) yv += head_w[c] * bf2f(tl[lane * TP + c]);
+                head_out[r] = yv + head_in[r];
+            }
+        }
 #pragma unroll
         for (int i = 0; i < NQ; ++i) {
             const int q = 64 * i + lane, vl = q / CH, cc = q % CH;
@@ -1165,9 +1180,16 @@ template <class T> T *ualloc(fdc_unet *u, size_t n)
 uint32_t blocks_for(long n, int per = 256, long cap = 16384) { return (uint32_t)std::max<long>(1, std::min<long>(cap, (n + per - 1) / per)); }
 
 // one implicit-GEMM launch: rows on grid g, n_cols output columns
+// the network's head fused into the last convolution's epilogue (inference)
+struct HeadFuse {
+    const float *w;     // 16 weights and the bias, as the head kernel reads them
+    const float *in;    // the input's first channel (the residual)
+    float *out;
+};
+
 hipError_t igemm(int am, int em, const View &src, int cpad, const Grid &g, const u16 *wpk, int kpad, int n_cols,
                  const float *bias, bool relu, const View *mask, const View &dst, int d2s_cout, hipStream_t s,
-                 const View *pool = nullptr)
+                 const View *pool = nullptr, const HeadFuse *head = nullptr)
 {
     const long rows = (long)g.nx * g.ny * g.nz;
     const long waves = (rows + 31) / 32;                  // MT = 2: 32 rows per wave
@@ -1206,6 +1228,11 @@ hipError_t igemm(int am, int em, const View &src, int cpad, const Grid &g, const
             return hipErrorInvalidValue;
         u16 *pp = pool ? pool->p : nullptr;
         const int ppitch = pool ? pool->pitch : 0;
+        // the fused head needs one 16-channel tile per block, 16 x 4 voxels per wave, the staged epilogue
+        if (head && (nt != 1 || n_cols != 16 || !vec || pool || mp || !head->w || !head->in || !head->out))
+            return hipErrorInvalidValue;
+        const float *hw = head ? head->w : nullptr, *hin = head ? head->in : nullptr;
+        float *hout = head ? head->out : nullptr;
         // a two-buffer source: its parts split at a whole 16-byte channel group
         if (src.p2 && (src.split % 8 || src.split <= 0 || src.split >= cpad || src.pitch2 % 8 ||
                        ((uintptr_t)src.p2 & 15)))
@@ -1215,7 +1242,7 @@ hipError_t igemm(int am, int em, const View &src, int cpad, const Grid &g, const
 #define CV(NT_, TY_, CP_, CS_) hipLaunchKernelGGL((conv3_kernel<NT_, TY_, CP_, CS_>), cgrid, dim3(256), lds, s, src.p, \
                                                   src.pitch, s2, s2pitch, split, g, wpk, kpad, n_cols, bias, (int)relu, \
                                                   mp, mpitch, dst.p, \
-                                                  dst.pitch, vec, pp, ppitch)
+                                                  dst.pitch, vec, pp, ppitch, hw, hin, hout)
 #define CVN(TY_, CP_, CS_) do { if (nt == 4) CV(4, TY_, CP_, CS_); else if (nt == 2) CV(2, TY_, CP_, CS_); \
                                 else CV(1, TY_, CP_, CS_); } while (0)
         if (cpad == 2) CVN(4, 2, 2);
@@ -1408,14 +1435,16 @@ Views views(const fdc_unet *u)
 }
 
 hipError_t conv_fwd(fdc_unet *u, int l, const View &src, const Grid &g, const View &dst, hipStream_t s,
-                    const View *pool = nullptr)
+                    const View *pool = nullptr, const HeadFuse *head = nullptr)
 {
     const LayerDesc &L = kLayers[l];
     return igemm(A_CONV3, E_STORE, src, fwd_cpad(L.cin), g, u->wpk_f[l], u->kpad_f[l], L.cout, u->params + u->b_off[l],
-                 true, nullptr, dst, 0, s, pool);
+                 true, nullptr, dst, 0, s, pool, head);
 }
 
-hipError_t forward_pass(fdc_unet *u, const float *in, hipStream_t s)
+// out: the network's output (inference: the head runs in dec1b's epilogue),
+// or null (training: the head kernel follows with the loss and its gradient)
+hipError_t forward_pass(fdc_unet *u, const float *in, hipStream_t s, float *out = nullptr)
 {
     const Views v = views(u);
     const Grid *g = u->g;
@@ -1434,7 +1463,15 @@ hipError_t forward_pass(fdc_unet *u, const float *in, hipStream_t s)
     if (!e) e = igemm(A_CONV1, E_D2S, v.d2, 32, g[1], u->wpk_f[L_UP1], u->kpad_f[L_UP1], u->ncol_f[L_UP1],
                       u->params + u->b_off[L_UP1], false, nullptr, v.u1, 16, s);
     if (!e) e = conv_fwd(u, L_D1A, v.c1, g[0], v.d1a, s);
-    if (!e) e = conv_fwd(u, L_D1B, v.d1a, g[0], v.d1, s);
+    if (out) {
+        // the head reads bf16-rounded weights like every other layer (its bias stays FP32)
+        hipLaunchKernelGGL(head_weights_kernel, dim3(1), dim3(64), 0, s, u->params + u->w_off[L_HEAD], u->hw);
+        if (!e) e = hipGetLastError();
+        const HeadFuse hf{u->hw, in, out};
+        if (!e) e = conv_fwd(u, L_D1B, v.d1a, g[0], v.d1, s, nullptr, &hf);
+    } else if (!e) {
+        e = conv_fwd(u, L_D1B, v.d1a, g[0], v.d1, s);
+    }
     return e;
 }
 
@@ -1683,8 +1720,7 @@ int fdc_unet_forward(fdc_unet *u, const float *in_dev, float *out_dev, void *hip
     if (!in_dev || !out_dev) return ufail(u, FDC_E_ARG, "forward: NULL");
     hipStream_t s = (hipStream_t)hip_stream;
     hipError_t e = hipSetDevice(u->device);
-    if (!e) e = forward_pass(u, in_dev, s);
-    if (!e) e = head(u, in_dev, nullptr, out_dev, s);
+    if (!e) e = forward_pass(u, in_dev, s, out_dev);
     if (e) return ufail(u, FDC_E_HIP, "forward", e);
     return FDC_OK;
 }
