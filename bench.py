@@ -289,6 +289,14 @@ def denoised_route(c, ph, sp, plain_plan, plain_dose, n2, rate):
     r["gamma_denoised_at_N_2pct"] = at_n2["gamma_denoised"]
     r["best_gamma_denoised"] = max(row["gamma_denoised"] for row in r["ladder"])
     r["reached_G_star"] = r["N_denoised"] is not None
+    # The ladder's doses use track rotation (as the denoiser's training data did);
+    # G* is the benchmarked plain method's (no rotation).  The same comparison
+    # against the rotated plain dose of N_2% histories, and the histories the
+    # rotated plain dose alone needs to reach G*, both from the ladder's rungs:
+    g_rot = at_n2["gamma_plain"]
+    first = lambda key, g: next((row["histories"] for row in r["ladder"] if row[key] >= g), None)
+    r["rotated_plain"] = {"G_star": g_rot, "N_denoised": first("gamma_denoised", g_rot),
+                          "histories_to_G_star": first("gamma_plain", r["G_star"])}
     log(f"denoised route: G* {r['G_star']:.5f}, N_d {r['N_denoised']}, t_den {r['t_denoised_s']} "
         f"({time.perf_counter() - t:.1f} s)")
     r["weights"] = {k: meta[k] for k in ("train_plans", "input_histories", "target_histories", "steps")
